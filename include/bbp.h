@@ -1,0 +1,170 @@
+/*
+ * bbp.h - C ABI of libbbp: block belief propagation (block BP) for 2D PEPS
+ * on an MI355X (gfx950) GPU.
+ *
+ * Method: Guo, Poletti and Arad, "Block belief propagation algorithm for
+ * two-dimensional tensor networks".  The double-layer network <psi|psi>
+ * (Sec. II, Fig. 1(a,b)) is cut into blocks (Fig. 1(c)); every directed
+ * message between neighbouring blocks is an MPS along their shared edge,
+ * updated by Eq. (1) from the other three incoming messages of the sending
+ * block, with the block contracted column by column as MPO x MPS variational
+ * fits truncated to bond chi (App. A).  Observables use the converged
+ * messages as the block environment (Sec. II; App. A; App. B).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All arithmetic is FP64 unless the "precision" option says otherwise.
+ *  - Site tensor layout: A[site][s][u][l][d][r], C order, doubles.  s is the
+ *    physical index (dimension d, default 2, s=0 <-> sigma_z=+1); u,l,d,r
+ *    the up/left/down/right virtual legs, each stored with dimension D.
+ *    Sites are row-major (y outer, x inner).
+ *  - Finite lattices have open boundaries: a leg pointing off the lattice
+ *    has true dimension 1 and must be zero for indices > 0 (zero padding);
+ *    otherwise BBP_EINVAL.  Infinite lattices take the ucx*ucy tensors of
+ *    the unit cell, every leg of true dimension D.
+ *  - Operators: one-site op[s'][s] (d x d, row-major); two-site
+ *    op[(s0',s1')][(s0,s1)] (d^2 x d^2) with the first site as major index.
+ *    Expectation values are <psi|O|psi>/<psi|psi> for real tensors.
+ *  - Ownership: the caller owns every host buffer; the library copies on
+ *    entry and never keeps a caller pointer.  The context owns the device
+ *    memory it allocates (hipMalloc) and frees it in bbp_destroy.
+ *  - Errors: every call returns a bbp_status; bbp_last_error() gives a
+ *    context-local message.  Arguments are validated before any state
+ *    changes.  A failed sweep leaves the previous messages in place.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef BBP_H
+#define BBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bbp_ctx bbp_ctx;
+
+typedef enum {
+  BBP_OK = 0,
+  BBP_EINVAL = 1,   /* invalid argument or tensor content              */
+  BBP_ENOMEM = 2,   /* device or host allocation failed                */
+  BBP_EDEVICE = 3,  /* HIP runtime error or no usable gfx950 device    */
+  BBP_ESTATE = 4,   /* call not valid in the current state             */
+  BBP_ENUMERIC = 5  /* zero-norm or non-finite message or boundary     */
+} bbp_status;
+
+/*
+ * Create a context.  Finite open lattice: infinite = 0, Lx x Ly sites,
+ * ucx = ucy = 0 (the unit cell is the lattice).  Infinite lattice (Sec. II,
+ * iPEPS paragraph: one block exchanging messages with its own copies):
+ * infinite = 1, Lx = Ly = 0, unit cell ucx x ucy, and the block must be a
+ * multiple of the cell.  Blocks are bx x by sites (Fig. 1(c)); a finite
+ * lattice that is not a multiple of the block is padded with trivial sites,
+ * which leaves <psi|psi> unchanged.  D is the PEPS bond dimension, chi the
+ * message bond cap (chi_m of Sec. II, App. A).
+ * Errors: BBP_EINVAL for non-positive sizes or an incommensurate block,
+ * BBP_EDEVICE if no GPU is usable, BBP_ENOMEM.
+ */
+bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
+                      int32_t ucx, int32_t ucy, int32_t bx, int32_t by,
+                      int32_t D, int32_t chi);
+
+/*
+ * Set an option before bbp_set_tensors (later changes return BBP_ESTATE,
+ * except "n_fit" and "chi_env", which may change at any time):
+ *   "d"        physical dimension (default 2)
+ *   "chi_env"  boundary bond for observables (default 2*D^2+10, Sec. II)
+ *   "n_fit"    full fit sweeps per column absorption (default 2, App. A)
+ *   "seed"     seed of the counter-based fit initial states (default 0)
+ * Unknown keys or out-of-range values: BBP_EINVAL.
+ */
+bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
+
+/* Launch all work of this context on the given hipStream_t (default: the
+ * null stream).  The pointer is a HIP stream handle; NULL selects the null
+ * stream. */
+bbp_status bbp_set_stream(bbp_ctx *c, void *hip_stream);
+
+/*
+ * Upload the site tensors (host FP64, layout above; n = number of doubles =
+ * nsites*d*D^4 with nsites = Lx*Ly or ucx*ucy), form the per-message rotated
+ * copies, and reset the messages to the identity product state (one site
+ * m[(k,k')] = delta_kk'/sqrt(D)) and the fit warm starts.
+ * Errors: BBP_EINVAL for a wrong n, NaN/Inf entries, or nonzero padding on
+ * an open edge.
+ */
+bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n);
+
+/*
+ * Exactly n synchronous sweeps of Eq. (1): every directed message between
+ * neighbouring blocks is recomputed from the previous sweep's messages
+ * (Sec. II: all messages of one iteration are independent).  No early exit.
+ * *residual (may be NULL) receives the last sweep's residual: the mean over
+ * directed messages of max(0, 2 - 2|<m_new, m_old>|) for unit-norm messages
+ * (the squared sign-aligned distance; App. A's mean-square error).
+ * Errors: BBP_ESTATE before bbp_set_tensors, BBP_ENUMERIC for a zero-norm
+ * or non-finite message (messages then stay at their previous values).
+ */
+bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual);
+
+/*
+ * <O> at site (x, y) from the current messages (Sec. II, App. A, App. B):
+ * the site's block with its four incoming messages; boundary MPSs absorbed
+ * from top and bottom at bond chi_env; the site's row contracted exactly.
+ * Infinite lattices: (x, y) in unit-cell coordinates, evaluated at the copy
+ * nearest the centre of the block.  op: d*d doubles.
+ */
+bbp_status bbp_expect_site(bbp_ctx *c, int32_t x, int32_t y,
+                           const double *op, double *out);
+
+/*
+ * <O> on the nearest-neighbour bond (x0,y0)-(x1,y1) with (x1,y1) =
+ * (x0+1,y0) or (x0,y0+1).  A bond inside a block uses that block; a bond
+ * crossing two blocks uses the union of the two blocks with its six
+ * incoming messages.  Vertical bonds are contracted along their column.
+ * op: d^2*d^2 doubles.  Errors: BBP_EINVAL for other site pairs.
+ */
+bbp_status bbp_expect_bond(bbp_ctx *c, int32_t x0, int32_t y0, int32_t x1,
+                           int32_t y1, const double *op, double *out);
+
+/*
+ * Batched forms of the two calls above: n sites (xs[i], ys[i]) with one
+ * shared operator, or n bonds.  out has n entries.
+ */
+bbp_status bbp_expect_sites(bbp_ctx *c, int32_t n, const int32_t *xs,
+                            const int32_t *ys, const double *op, double *out);
+bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
+                            const int32_t *y0, const int32_t *x1,
+                            const int32_t *y1, const double *op, double *out);
+
+/*
+ * log|<psi|psi>| estimated by the block Bethe formula
+ * sum_blocks log|Z_A| - sum_edges log|Z_AB| (Z_A: block A with its four
+ * incoming unit-norm messages; Z_AB = <m_{A->B}, m_{B->A}>).  Exact when
+ * the block graph is a tree.  Infinite lattices: per block.
+ */
+bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign);
+
+/*
+ * Messages as flat FP64: for each directed message in enumeration order
+ * (blocks row-major, directions L,R,U,D, only existing neighbours), an
+ * int-valued header [nsites, b_0..b_nsites] (bond dims as doubles) followed
+ * by each site [b_i][D*D][b_{i+1}] in C order.  bbp_get_messages writes at
+ * most n doubles and reports the size needed in *needed; bbp_set_messages
+ * replaces every message (and clears the fit warm starts).
+ */
+bbp_status bbp_get_messages(bbp_ctx *c, double *buf, size_t n, size_t *needed);
+bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n);
+
+/* Number of directed messages and the floating-point operations of the
+ * last sweep counted on the split-layer schedule (fit contractions only). */
+bbp_status bbp_stats(bbp_ctx *c, int32_t *n_messages, double *sweep_flops);
+
+const char *bbp_last_error(const bbp_ctx *c);
+void bbp_destroy(bbp_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBP_H */

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libbbp (include/bbp.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts NumPy arrays
+to pointers, raises on error status, and unpacks message buffers.  The library
+must be built (``python -m paper_2301_05844_amd.build``); importing this module
+without it raises ``ImportError``.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbp.so")
+
+EXPORTS = (
+    "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_tensors",
+    "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
+    "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
+    "bbp_set_messages", "bbp_stats", "bbp_last_error", "bbp_destroy",
+)
+
+STATUS = {0: "BBP_OK", 1: "BBP_EINVAL", 2: "BBP_ENOMEM", 3: "BBP_EDEVICE",
+          4: "BBP_ESTATE", 5: "BBP_ENUMERIC"}
+
+
+class BBPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libbbp.so not built at {LIB_PATH}; run "
+                          "python -m paper_2301_05844_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_size = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.c_void_p
+    dp = ctypes.POINTER(c_double)
+    ip = ctypes.POINTER(c_int)
+    sig = {
+        "bbp_create": [ctypes.POINTER(P)] + [c_int] * 9,
+        "bbp_set_option": [P, ctypes.c_char_p, c_double],
+        "bbp_set_stream": [P, P],
+        "bbp_set_tensors": [P, dp, c_size],
+        "bbp_sweep": [P, c_int, dp],
+        "bbp_expect_site": [P, c_int, c_int, dp, dp],
+        "bbp_expect_bond": [P, c_int, c_int, c_int, c_int, dp, dp],
+        "bbp_expect_sites": [P, c_int, ip, ip, dp, dp],
+        "bbp_expect_bonds": [P, c_int, ip, ip, ip, ip, dp, dp],
+        "bbp_log_norm": [P, dp, ip],
+        "bbp_get_messages": [P, dp, c_size, ctypes.POINTER(c_size)],
+        "bbp_set_messages": [P, dp, c_size],
+        "bbp_stats": [P, ip, dp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.bbp_last_error.argtypes = [P]
+    lib.bbp_last_error.restype = ctypes.c_char_p
+    lib.bbp_destroy.argtypes = [P]
+    lib.bbp_destroy.restype = None
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class BlockBP:
+    """One libbbp context.  ``finite``: ``BlockBP(Lx=, Ly=, bx=, by=, D=,
+    chi=)``; infinite: ``BlockBP(infinite=True, ucx=, ucy=, bx=, by=, D=,
+    chi=)``.  Options (``chi_env``, ``n_fit``, ``seed``, ``d``) are passed to
+    ``bbp_set_option`` before the tensors."""
+
+    def __init__(self, D, chi, bx, by, Lx=0, Ly=0, infinite=False, ucx=0,
+                 ucy=0, stream=None, **options):
+        self._ctx = ctypes.c_void_p()
+        st = _lib.bbp_create(ctypes.byref(self._ctx), int(bool(infinite)),
+                             Lx, Ly, ucx, ucy, bx, by, D, chi)
+        if st != 0:
+            raise BBPError(st, "bbp_create rejected its arguments")
+        self.D, self.chi = D, chi
+        for k, v in options.items():
+            self._check(_lib.bbp_set_option(self._ctx, k.encode(), float(v)))
+        if stream is not None:
+            self.set_stream(stream)
+
+    def _check(self, st):
+        if st != 0:
+            raise BBPError(st, _lib.bbp_last_error(self._ctx).decode())
+
+    def set_stream(self, stream):
+        """``stream``: a torch.cuda.Stream, an integer handle, or None."""
+        handle = getattr(stream, "cuda_stream", stream)
+        self._check(_lib.bbp_set_stream(self._ctx, ctypes.c_void_p(handle)))
+
+    def set_option(self, key, value):
+        self._check(_lib.bbp_set_option(self._ctx, key.encode(), float(value)))
+
+    def set_tensors(self, A):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        self._check(_lib.bbp_set_tensors(self._ctx, _dptr(A), A.size))
+
+    def sweep(self, n=1):
+        r = ctypes.c_double(0.0)
+        self._check(_lib.bbp_sweep(self._ctx, int(n), ctypes.byref(r)))
+        return r.value
+
+    def expect_site(self, x, y, op):
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = ctypes.c_double()
+        self._check(_lib.bbp_expect_site(self._ctx, x, y, _dptr(op),
+                                         ctypes.byref(out)))
+        return out.value
+
+    def expect_bond(self, x0, y0, x1, y1, op):
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = ctypes.c_double()
+        self._check(_lib.bbp_expect_bond(self._ctx, x0, y0, x1, y1, _dptr(op),
+                                         ctypes.byref(out)))
+        return out.value
+
+    def expect_sites(self, xs, ys, op):
+        xs = np.ascontiguousarray(xs, dtype=np.int32)
+        ys = np.ascontiguousarray(ys, dtype=np.int32)
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = np.zeros(len(xs))
+        self._check(_lib.bbp_expect_sites(self._ctx, len(xs), _iptr(xs),
+                                          _iptr(ys), _dptr(op), _dptr(out)))
+        return out
+
+    def expect_bonds(self, bonds, op):
+        b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 4))
+        cols = [np.ascontiguousarray(b[:, i]) for i in range(4)]
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = np.zeros(len(b))
+        self._check(_lib.bbp_expect_bonds(self._ctx, len(b),
+                                          *[_iptr(c) for c in cols],
+                                          _dptr(op), _dptr(out)))
+        return out
+
+    def log_norm(self):
+        v = ctypes.c_double()
+        s = ctypes.c_int32()
+        self._check(_lib.bbp_log_norm(self._ctx, ctypes.byref(v),
+                                      ctypes.byref(s)))
+        return v.value, s.value
+
+    def get_messages_flat(self):
+        need = ctypes.c_size_t()
+        self._check(_lib.bbp_get_messages(self._ctx, None, 0,
+                                          ctypes.byref(need)))
+        buf = np.zeros(need.value)
+        self._check(_lib.bbp_get_messages(self._ctx, _dptr(buf), buf.size,
+                                          ctypes.byref(need)))
+        return buf
+
+    def get_messages(self):
+        """List of messages in enumeration order, each a list of site arrays
+        ``[b_i, D*D, b_{i+1}]``."""
+        buf = self.get_messages_flat()
+        P = self.D * self.D
+        out, o = [], 0
+        while o < buf.size:
+            n = int(buf[o])
+            o += 1
+            bonds = [int(v) for v in buf[o:o + n + 1]]
+            o += n + 1
+            m = []
+            for s in range(n):
+                size = bonds[s] * P * bonds[s + 1]
+                m.append(buf[o:o + size].reshape(bonds[s], P, bonds[s + 1]))
+                o += size
+            out.append(m)
+        return out
+
+    def set_messages(self, msgs):
+        parts = []
+        for m in msgs:
+            parts.append([float(len(m))])
+            parts.append([1.0] + [float(t.shape[2]) for t in m])
+            for t in m:
+                parts.append(np.asarray(t, dtype=np.float64).reshape(-1))
+        buf = np.ascontiguousarray(np.concatenate(parts))
+        self._check(_lib.bbp_set_messages(self._ctx, _dptr(buf), buf.size))
+
+    def stats(self):
+        n = ctypes.c_int32()
+        f = ctypes.c_double()
+        self._check(_lib.bbp_stats(self._ctx, ctypes.byref(n), ctypes.byref(f)))
+        return n.value, f.value
+
+    def close(self):
+        if self._ctx:
+            _lib.bbp_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,121 @@
+// Internal declarations shared by the host orchestration and the kernels of
+// libbbp.  Not part of the public ABI (include/bbp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace bbp {
+
+// Largest number of sites of a boundary MPS (column height + 2 corners).
+constexpr int NMAX = 68;
+
+// Shapes of the fit result Y for one work item and one absorbed column:
+// site j of Y is (bl[j], p[j], br[j]) with bl[0] = br[N-1] = 1.
+struct FitDims {
+  int32_t bl[NMAX];
+  int32_t br[NMAX];
+  int32_t p[NMAX];
+  int32_t rnd;      // 1: start from the counter-based random state
+  int32_t pad_[3];
+};
+
+// Device buffers of one batch of independent column absorptions ("items"),
+// all with the same boundary length N, width W and bond cap K.  Every MPS
+// site lives in a zero-padded slot of S = K*P*K doubles; end sites use the
+// first K*K doubles of their slot as a [phys][bond] or [bond][phys] matrix.
+struct FitBatch {
+  int items = 0;
+  int K = 0, P = 0, D = 0, d = 0;  // bond cap, D^2, D, physical dim
+  int H = 0, W = 0, N = 0;          // column height, width, N = H + 2
+  size_t S = 0;                     // slot size (doubles)
+  double *store = nullptr;  // [items][W][N][S]  fit result per column
+  double *xin = nullptr;    // [items][N][S]     boundary before column W-1
+  double *mt = nullptr;     // [items][W][S]     top message sites (rotated)
+  double *mb = nullptr;     // [items][W][S]     bottom message sites
+  double *lenv = nullptr;   // [items][N][S]
+  double *renv = nullptr;   // [items][N][S]
+  double *t1 = nullptr;     // [items][K*P*P*K]
+  double *t2 = nullptr;     // [items][d*K*K*P*P]
+  double *t3 = nullptr;     // [items][K*P*K*P]
+  double *tmp = nullptr;    // [items][S]
+  double *acan = nullptr;   // [items][H][W][d*D^4]  rotated site tensors (ket)
+  double *abra = nullptr;   // bra tensors if different from acan (or null)
+  double *rbuf = nullptr;   // [items][K*K]
+  double *nu = nullptr;     // [items] norm of the last fit
+  int32_t *flag = nullptr;  // [items] per-item active flags
+  int32_t *err = nullptr;   // [1] numeric error flag
+  FitDims *dims = nullptr;  // [items][W]
+  uint64_t *slot = nullptr; // [items] random-state slot base
+  uint64_t seed = 0;
+};
+
+// Visit kinds of the fit engine.
+enum VisitMode : int {
+  LR_INNER = 0,  // left-to-right visit of an inner site (QR)
+  RL_INNER = 1,  // right-to-left visit of an inner site (LQ)
+  LR_TOP = 2,    // left-to-right visit of site 0 (top corner/message site)
+  RL_BOT = 3     // right-to-left visit of site N-1 (bottom corner)
+};
+
+// A per-item device pointer: item i uses p + i*stride.
+struct Ptr {
+  double *p = nullptr;
+  size_t stride = 0;
+  __host__ __device__ double *at(int i) const { return p + (size_t)i * stride; }
+};
+
+// Offset of site j of column c inside one item's fit-result store.
+inline size_t slot_store(const FitBatch &f, int c, int j) {
+  return ((size_t)c * f.N + j) * f.S;
+}
+
+// Launchers (bbp_kernels.hip).  All enqueue on `st`.
+// Inner-site chain T1 -> T2 -> T3 (split layers) for site j of column c.
+hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl,
+                              Ptr X, Ptr F, hipStream_t st);
+// Yt = T3 . G  (local update), written into Y.
+hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
+                              hipStream_t st);
+// env' = Y . T3
+hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
+                            hipStream_t st);
+// End-site chain T = Mend . Xe (top corner in LR, bottom corner in RL).
+hipError_t launch_end_chain(const FitBatch &f, bool rl, Ptr Mend, Ptr Xe,
+                            hipStream_t st);
+hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
+                            hipStream_t st);
+hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
+                          hipStream_t st);
+// Householder QR of the site panel (mode: VisitMode); Q replaces the panel.
+hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
+                     bool want_r, bool only_flagged, hipStream_t st);
+// Y_{j-1} <- Y_{j-1} . L with L = R^T from rbuf (flagged items only).
+hipError_t launch_apply_l(const FitBatch &f, bool end_site, Ptr Y,
+                          hipStream_t st);
+// Counter-based random start for all N sites of column c (flagged items).
+hipError_t launch_rand_init(const FitBatch &f, int c, Ptr Ybase,
+                            hipStream_t st);
+// Set slot (per item) to the 1x1x1 unit tensor.
+hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st);
+// Normalise the end slot Y0 to unit norm; nu[item] = its norm.
+hipError_t launch_normalize(const FitBatch &f, Ptr Y0, hipStream_t st);
+
+// Message gathering / extraction / overlap.
+struct GatherSrc {
+  const double *src[3];  // top, right, bottom incoming message (site 0 slot)
+  int32_t rev[3];        // reverse the site order
+  int32_t pad_;
+};
+hipError_t launch_gather(const FitBatch &f, const GatherSrc *srcs,
+                         hipStream_t st);
+// Final boundary of column 0 -> message of H sites at dst[item].
+hipError_t launch_extract(const FitBatch &f, double *const *dst,
+                          const int32_t *rev, hipStream_t st);
+// out[i] = <a_i | b_i> for items i, each an L-site padded MPS.
+hipError_t launch_overlap(int items, int K, int P, int L, const double *const *a,
+                          const double *const *b, double *E, double *U,
+                          double *out, hipStream_t st);
+
+}  // namespace bbp

@@ -1,0 +1,814 @@
+// HIP kernels of libbbp for gfx950 (MI355X): the split-layer fit visit of
+// block BP (App. A of Guo, Poletti, Arad), Householder QR/LQ, and the small
+// gather / extract / normalise / overlap steps around it.
+//
+// Every MPS site lives in a zero-padded slot of S = K*P*K doubles (K the
+// bond cap, P = D^2 the fused double-layer leg), so all contractions of a
+// batch have the same shape; zero padding stays exactly zero through every
+// contraction, and the QR works on the true panel only.
+#include "bbp_internal.h"
+
+namespace bbp {
+namespace {
+
+constexpr int kThreads = 256;
+
+// ---------------------------------------------------------------------------
+// Batched FP64 GEMM engine.  C(it, m, n) = sum_k A(it, m, k) B(it, k, n) for
+// the items of a batch (blockIdx.z).  The operand and result index maps are
+// supplied by an op struct (a(), b(), st()); each workgroup stages BK-deep
+// slices of A and B in LDS and 16 x 16 threads accumulate TM x TN tiles.
+// ---------------------------------------------------------------------------
+template <int BM, int BN, int BK, class Op>
+__global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
+  const int it = blockIdx.z;
+  if (op.flag && !op.flag[it]) return;
+  constexpr int TM = BM / 16, TN = BN / 16;
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  double acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < op.Kd; k0 += BK) {
+    for (int i = tid; i < BM * BK; i += kThreads) {
+      const int kk = i % BK, mm = i / BK;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < op.M && k < op.Kd) ? op.a(it, m, k) : 0.0;
+    }
+    for (int i = tid; i < BK * BN; i += kThreads) {
+      const int nn = i % BN, kk = i / BN;
+      const int n = n0 + nn, k = k0 + kk;
+      Bs[kk][nn] = (n < op.N && k < op.Kd) ? op.b(it, k, n) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (m < op.M && n < op.N) op.st(it, m, n, acc[i][j]);
+    }
+}
+
+template <int BM, int BN, int BK, class Op>
+hipError_t run_gemm(const Op &op, int items, hipStream_t st) {
+  if (items <= 0 || op.M <= 0 || op.N <= 0) return hipSuccess;
+  dim3 grid((op.N + BN - 1) / BN, (op.M + BM - 1) / BM, items);
+  hipLaunchKernelGGL((k_gemm<BM, BN, BK, Op>), grid, dim3(kThreads), 0, st,
+                     op);
+  return hipGetLastError();
+}
+
+// Site tensor A'[s][u][l][d][r] of the rotated block, flat index.
+__device__ __forceinline__ size_t aidx(int D, int s, int u, int l, int dd,
+                                       int r) {
+  return ((((size_t)s * D + u) * D + l) * D + dd) * D + r;
+}
+
+struct Shape {
+  int K, P, D, d;
+};
+
+// ---- inner-site visit ---------------------------------------------------
+// Front view: "front" is the side the sweep comes from (left for LR, right
+// for RL).  X_f[xf][a][xb], A_f[s][wf][l][wb][a] with wf the MPO leg on the
+// front side, F the front environment, G the back environment.
+
+// T1[yf][wfb][ab][xb][wfk][ak] = sum_xf F[yf][wf][xf] X_f[xf][a][xb]
+struct OpK1 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  Ptr X, F;
+  double *t1;
+  size_t t1s;
+  __device__ double a(int it, int m, int k) const {
+    return F.at(it)[(size_t)m * s.K + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    const int a = n / s.K, xb = n - a * s.K;
+    const double *x = X.at(it);
+    return rl ? x[((size_t)xb * s.P + a) * s.K + k]
+              : x[((size_t)k * s.P + a) * s.K + xb];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    const int D = s.D, K = s.K, P = s.P;
+    const int yf = m / P, wf = m - yf * P, wfk = wf / D, wfb = wf - wfk * D;
+    const int a = n / K, xb = n - a * K, ak = a / D, ab = a - ak * D;
+    const size_t idx =
+        (((((size_t)yf * D + wfb) * D + ab) * K + xb) * D + wfk) * D + ak;
+    t1[(size_t)it * t1s + idx] = v;
+  }
+};
+
+// T2[yf][xb][lk][wbk][s][wfb][ab] = sum_{wfk,ak} T1[...][wfk][ak] Aket_f[s][wfk][lk][wbk][ak]
+struct OpK2 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t1;
+  size_t t1s;
+  const double *A;  // item 0, site (j-1, c)
+  size_t as;
+  double *t2;
+  size_t t2s;
+  __device__ double a(int it, int m, int k) const {
+    return t1[(size_t)it * t1s + (size_t)m * s.P + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    const int D = s.D;
+    const int wfk = k / D, ak = k - wfk * D;
+    const int sp = n / s.P, r = n - sp * s.P, lk = r / D, wbk = r - lk * D;
+    const double *A0 = A + (size_t)it * as;
+    return rl ? A0[aidx(D, sp, wbk, lk, wfk, ak)]
+              : A0[aidx(D, sp, wfk, lk, wbk, ak)];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    const int D = s.D, K = s.K;
+    int t = m;
+    const int xb = t % K;
+    t /= K;
+    const int ab = t % D;
+    t /= D;
+    const int wfb = t % D;
+    const int yf = t / D;
+    const int sp = n / s.P, r = n - sp * s.P, lk = r / D, wbk = r - lk * D;
+    const size_t idx =
+        (((((((size_t)yf * K + xb) * D + lk) * D + wbk) * s.d + sp) * D + wfb) *
+             D +
+         ab);
+    t2[(size_t)it * t2s + idx] = v;
+  }
+};
+
+// T3[yf][lk][lb][xb][wbk][wbb] = sum_{s,wfb,ab} T2[...] Abra_f[s][wfb][lb][wbb][ab]
+struct OpK3 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t2;
+  size_t t2s;
+  const double *A;
+  size_t as;
+  double *t3;
+  size_t t3s;
+  __device__ double a(int it, int m, int k) const {
+    return t2[(size_t)it * t2s + (size_t)m * Kd + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    const int D = s.D;
+    const int sp = k / s.P, r = k - sp * s.P, wfb = r / D, ab = r - wfb * D;
+    const int lb = n / D, wbb = n - lb * D;
+    const double *A0 = A + (size_t)it * as;
+    return rl ? A0[aidx(D, sp, wbb, lb, wfb, ab)]
+              : A0[aidx(D, sp, wfb, lb, wbb, ab)];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    const int D = s.D, K = s.K, P = s.P;
+    int t = m;
+    const int wbk = t % D;
+    t /= D;
+    const int lk = t % D;
+    t /= D;
+    const int xb = t % K;
+    const int yf = t / K;
+    const int lb = n / D, wbb = n - lb * D;
+    const size_t idx =
+        (((size_t)yf * P + lk * D + lb) * K + xb) * P + wbk * D + wbb;
+    t3[(size_t)it * t3s + idx] = v;
+  }
+};
+
+// Yt[yf][l][yb] = sum_{xb,wb} T3[yf][l][xb][wb] G[yb][wb][xb]
+struct OpK4 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t3;
+  size_t t3s;
+  Ptr G, Y;
+  __device__ double a(int it, int m, int k) const {
+    return t3[(size_t)it * t3s + (size_t)m * Kd + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    const int xb = k / s.P, wb = k - xb * s.P;
+    return G.at(it)[((size_t)n * s.P + wb) * s.K + xb];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    const int yf = m / s.P, l = m - yf * s.P;
+    const size_t idx = rl ? ((size_t)n * s.P + l) * s.K + yf
+                          : ((size_t)yf * s.P + l) * s.K + n;
+    Y.at(it)[idx] = v;
+  }
+};
+
+// env'[yb][wb][xb] = sum_{yf,l} Y[yf][l][yb] T3[yf][l][xb][wb]
+struct OpK5 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t3;
+  size_t t3s;
+  Ptr Y, E;
+  __device__ double a(int it, int m, int k) const {
+    const int yf = k / s.P, l = k - yf * s.P;
+    const size_t idx = rl ? ((size_t)m * s.P + l) * s.K + yf
+                          : ((size_t)yf * s.P + l) * s.K + m;
+    return Y.at(it)[idx];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return t3[(size_t)it * t3s + (size_t)k * N + n];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    const int xb = n / s.P, wb = n - xb * s.P;
+    E.at(it)[((size_t)m * s.P + wb) * s.K + xb] = v;
+  }
+};
+
+// ---- end-site visit (message site as MPO: Mend[a][q][a']) ----------------
+// T[a][q][xb] = sum_{a'} Mend[a][q][a'] X_e[a'][xb]
+struct OpE1 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  Ptr Mend, Xe;
+  double *t3;
+  size_t t3s;
+  __device__ double a(int it, int m, int k) const {
+    return Mend.at(it)[(size_t)m * s.K + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return rl ? Xe.at(it)[(size_t)n * s.K + k] : Xe.at(it)[(size_t)k * s.K + n];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    t3[(size_t)it * t3s + (size_t)m * s.K + n] = v;
+  }
+};
+
+// Yt_e[a][yb] = sum_{q,xb} T[a][q][xb] G[yb][q][xb]
+struct OpE2 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t3;
+  size_t t3s;
+  Ptr G, Ye;
+  __device__ double a(int it, int m, int k) const {
+    return t3[(size_t)it * t3s + (size_t)m * Kd + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return G.at(it)[(size_t)n * Kd + k];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    Ye.at(it)[rl ? (size_t)n * s.K + m : (size_t)m * s.K + n] = v;
+  }
+};
+
+// env'[yb][q][xb] = sum_a Y_e[a][yb] T[a][q][xb]
+struct OpE3 {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  bool rl;
+  const double *t3;
+  size_t t3s;
+  Ptr Ye, E;
+  __device__ double a(int it, int m, int k) const {
+    return rl ? Ye.at(it)[(size_t)m * s.K + k] : Ye.at(it)[(size_t)k * s.K + m];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return t3[(size_t)it * t3s + (size_t)k * N + n];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    E.at(it)[(size_t)m * N + n] = v;
+  }
+};
+
+// Y <- Y . L with L[k][n] = R[n][k]: rows of the slot times the bond.
+struct OpApplyL {
+  int M, N, Kd;
+  const int32_t *flag;
+  Shape s;
+  Ptr Y;
+  const double *rbuf;
+  double *tmp;
+  size_t S;
+  __device__ double a(int it, int m, int k) const {
+    return Y.at(it)[(size_t)m * s.K + k];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return rbuf[(size_t)it * s.K * s.K + (size_t)n * s.K + k];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    tmp[(size_t)it * S + (size_t)m * s.K + n] = v;
+  }
+};
+
+// Transfer-matrix steps of <a|b>.
+struct OpOv1 {  // U[b'][q][a] = sum_{a'} E[a'][b'] a_i[a'][q][a]
+  int M, N, Kd;
+  const int32_t *flag;
+  int K;
+  const double *E;
+  const double *const *ap;
+  size_t off;
+  double *U;
+  size_t S;
+  __device__ double a(int it, int m, int k) const {
+    return E[(size_t)it * K * K + (size_t)k * K + m];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return ap[it][off + (size_t)k * N + n];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    U[(size_t)it * S + (size_t)m * N + n] = v;
+  }
+};
+struct OpOv2 {  // E'[a][b] = sum_{b',q} U[b'][q][a] b_i[b'][q][b]
+  int M, N, Kd;
+  const int32_t *flag;
+  int K, P;
+  const double *U;
+  size_t S;
+  const double *const *bp;
+  size_t off;
+  double *E;
+  __device__ double a(int it, int m, int k) const {
+    return U[(size_t)it * S + (size_t)k * K + m];
+  }
+  __device__ double b(int it, int k, int n) const {
+    return bp[it][off + (size_t)k * K + n];
+  }
+  __device__ void st(int it, int m, int n, double v) const {
+    E[(size_t)it * K * K + (size_t)m * K + n] = v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Householder QR (LAPACK conventions: dlarfg reflectors, dorg2r formation).
+// One workgroup per item; the true panel (rows r = r1*n2 + r2, columns c at
+// base[r1*s1 + r2*s2 + c*sc]) is copied column-major into LDS (or a global
+// scratch when it does not fit), factorised, and Q written back in place.
+// ---------------------------------------------------------------------------
+struct QrArgs {
+  FitDims *dims;
+  int W, c, j, mode, K, P;
+  Ptr Y;
+  double *rbuf;
+  double *scratch;
+  size_t scratch_stride;
+  const int32_t *flag;
+  int want_r;
+};
+
+constexpr int kQrLds = 19968;  // doubles (156 KB of the 160 KB LDS)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
+  const int it = blockIdx.x;
+  if (q.flag && !q.flag[it]) return;
+  const FitDims &dm = q.dims[(size_t)it * q.W + q.c];
+  const int K = q.K, P = q.P, j = q.j;
+  int n1, n2, ncol;
+  size_t s1, s2, sc;
+  switch (q.mode) {
+    case LR_INNER:
+      n1 = dm.bl[j]; s1 = (size_t)P * K; n2 = P; s2 = K; ncol = dm.br[j]; sc = 1;
+      break;
+    case RL_INNER:
+      n1 = dm.br[j]; s1 = 1; n2 = P; s2 = K; ncol = dm.bl[j]; sc = (size_t)P * K;
+      break;
+    case LR_TOP:
+      n1 = dm.p[j]; s1 = K; n2 = 1; s2 = 0; ncol = dm.br[j]; sc = 1;
+      break;
+    default:  // RL_BOT
+      n1 = dm.p[j]; s1 = 1; n2 = 1; s2 = 0; ncol = dm.bl[j]; sc = K;
+      break;
+  }
+  const int m = n1 * n2, n = ncol;
+  double *base = q.Y.at(it);
+  __shared__ double lds[kLds > 0 ? (kLds ? kQrLds : 1) : 1];
+  __shared__ double red[8];
+  __shared__ double tau_s[128];
+  double *A = kLds ? lds : q.scratch + (size_t)it * q.scratch_stride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int idx = tid; idx < m * n; idx += kThreads) {
+    const int col = idx / m, r = idx - col * m;
+    const int r1 = r / n2, r2 = r - r1 * n2;
+    A[idx] = base[r1 * s1 + r2 * s2 + col * sc];
+  }
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    double *v = A + (size_t)k * m;
+    double part = 0.0;
+    for (int i = k + 1 + tid; i < m; i += kThreads) part += v[i] * v[i];
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (tid == 0) {
+      const double sigma2 = red[0] + red[1] + red[2] + red[3];
+      const double alpha = v[k];
+      double tau = 0.0, scal = 0.0, beta = alpha;
+      if (sigma2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      tau_s[k] = tau;
+      red[4] = scal;
+      v[k] = beta;
+    }
+    __syncthreads();
+    const double scal = red[4], tau = tau_s[k];
+    if (tau != 0.0)
+      for (int i = k + 1 + tid; i < m; i += kThreads) v[i] *= scal;
+    __syncthreads();
+    if (tau != 0.0) {
+      for (int jj = k + 1 + wave; jj < n; jj += kThreads / 64) {
+        double *a = A + (size_t)jj * m;
+        double w = 0.0;
+        for (int i = k + 1 + lane; i < m; i += 64) w += v[i] * a[i];
+        w = wave_sum(w) + a[k];
+        w *= tau;
+        if (lane == 0) a[k] -= w;
+        for (int i = k + 1 + lane; i < m; i += 64) a[i] -= v[i] * w;
+      }
+    }
+    __syncthreads();
+  }
+
+  if (q.want_r) {
+    double *R = q.rbuf + (size_t)it * K * K;
+    for (int idx = tid; idx < K * K; idx += kThreads) {
+      const int r = idx / K, cc = idx - r * K;
+      R[idx] = (r < n && cc < n && r <= cc) ? A[(size_t)cc * m + r] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  // Q = H_0 ... H_{n-1} [I; 0], formed in place from the last reflector.
+  for (int k = n - 1; k >= 0; --k) {
+    double *v = A + (size_t)k * m;
+    const double tau = tau_s[k];
+    if (k < n - 1 && tau != 0.0) {
+      for (int jj = k + 1 + wave; jj < n; jj += kThreads / 64) {
+        double *a = A + (size_t)jj * m;
+        double w = 0.0;
+        for (int i = k + 1 + lane; i < m; i += 64) w += v[i] * a[i];
+        w = wave_sum(w) + a[k];
+        w *= tau;
+        if (lane == 0) a[k] -= w;
+        for (int i = k + 1 + lane; i < m; i += 64) a[i] -= v[i] * w;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kThreads) {
+      if (i > k) v[i] *= -tau;
+      else if (i == k) v[i] = 1.0 - tau;
+      else v[i] = 0.0;
+    }
+    __syncthreads();
+  }
+
+  for (int idx = tid; idx < m * n; idx += kThreads) {
+    const int col = idx / m, r = idx - col * m;
+    const int r1 = r / n2, r2 = r - r1 * n2;
+    base[r1 * s1 + r2 * s2 + col * sc] = A[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based uniform numbers: SplitMix64 (Steele, Lea, Flood 2014).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// One workgroup per (site, item): zero the slot, then fill the true
+// (bl, p, br) tensor with 2*(h >> 11)*2^-52... values indexed by the compact
+// C-order position, exactly as the oracle does.
+__global__ __launch_bounds__(kThreads) void k_rand_init(
+    FitDims *dims, int W, int c, int N, int K, int P, size_t S, Ptr Y,
+    const uint64_t *slot, uint64_t seed, const int32_t *flag) {
+  const int j = blockIdx.x, it = blockIdx.y;
+  if (!flag[it]) return;
+  const FitDims &dm = dims[(size_t)it * W + c];
+  double *y = Y.at(it) + (size_t)j * S;
+  for (size_t i = threadIdx.x; i < S; i += kThreads) y[i] = 0.0;
+  __syncthreads();
+  const int bl = dm.bl[j], p = dm.p[j], br = dm.br[j];
+  const uint64_t h = splitmix(splitmix(splitmix(seed) ^ (slot[it] + c)) ^
+                              (uint64_t)j);
+  const int total = bl * p * br;
+  for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+    const uint64_t v = splitmix(h ^ (uint64_t)idx);
+    const double u = (double)(v >> 11) * 0x1p-52 - 1.0;
+    const int y0 = idx / (p * br), rem = idx - y0 * p * br;
+    const int a = rem / br, y1 = rem - a * br;
+    size_t addr;
+    if (j == 0) addr = (size_t)a * K + y1;               // [p][br]
+    else if (j == N - 1) addr = (size_t)y0 * K + a;      // [bl][p]
+    else addr = ((size_t)y0 * P + a) * K + y1;           // [bl][p][br]
+    y[addr] = u;
+  }
+}
+
+__global__ void k_set_unit(Ptr slot, size_t S) {
+  double *s = slot.at(blockIdx.y);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < S;
+       i += (size_t)gridDim.x * blockDim.x)
+    s[i] = (i == 0) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_flagged(
+    const double *src, size_t sstride, Ptr dst, size_t n, const int32_t *flag) {
+  const int it = blockIdx.y;
+  if (flag && !flag[it]) return;
+  double *d = dst.at(it);
+  const double *s = src + (size_t)it * sstride;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * kThreads)
+    d[i] = s[i];
+}
+
+// Norm of the end slot (K*K doubles) per item; scale to unit norm.
+__global__ __launch_bounds__(kThreads) void k_normalize(Ptr Y0, int K,
+                                                        double *nu,
+                                                        int32_t *err) {
+  const int it = blockIdx.x;
+  double *y = Y0.at(it);
+  const int n = K * K;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) part += y[i] * y[i];
+  part = wave_sum(part);
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  const double nrm = sqrt(red[0] + red[1] + red[2] + red[3]);
+  const bool ok = nrm > 0.0 && isfinite(nrm);
+  if (threadIdx.x == 0) {
+    nu[it] = nrm;
+    if (!ok) atomicOr(err, 1);
+  }
+  if (ok) {
+    const double inv = 1.0 / nrm;
+    for (int i = threadIdx.x; i < n; i += kThreads) y[i] *= inv;
+  }
+}
+
+// Copy one message site slot [a][q][b], optionally transposed to [b][q][a].
+__device__ __forceinline__ void copy_site(const double *src, double *dst,
+                                          int K, int P, bool tr, double scale,
+                                          int tid, int nt) {
+  const size_t S = (size_t)K * P * K;
+  for (size_t i = tid; i < S; i += nt) {
+    if (!tr) {
+      dst[i] = scale * src[i];
+    } else {
+      const int a = (int)(i / ((size_t)P * K));
+      const int rem = (int)(i - (size_t)a * P * K);
+      const int qq = rem / K, b = rem - qq * K;
+      dst[i] = scale * src[((size_t)b * P + qq) * K + a];
+    }
+  }
+}
+
+// blockIdx.x: site (0..W-1 for top/bottom, 0..H+1 for the boundary),
+// blockIdx.y: which (0 top, 1 boundary, 2 bottom), blockIdx.z: item.
+__global__ __launch_bounds__(kThreads) void k_gather(FitBatch f,
+                                                     const GatherSrc *srcs) {
+  const int site = blockIdx.x, which = blockIdx.y, it = blockIdx.z;
+  const GatherSrc g = srcs[it];
+  const int K = f.K, P = f.P;
+  const size_t S = f.S;
+  if (which == 1) {
+    if (site >= f.N) return;
+    double *dst = f.xin + ((size_t)it * f.N + site) * S;
+    if (site == 0 || site == f.N - 1) {
+      for (size_t i = threadIdx.x; i < S; i += kThreads)
+        dst[i] = (i == 0) ? 1.0 : 0.0;
+      return;
+    }
+    const int L = f.H, i = site - 1;
+    const int src_site = g.rev[1] ? L - 1 - i : i;
+    copy_site(g.src[1] + (size_t)src_site * S, dst, K, P, g.rev[1], 1.0,
+              threadIdx.x, kThreads);
+    return;
+  }
+  if (site >= f.W) return;
+  const int k = which == 0 ? 0 : 2;
+  double *dst = (which == 0 ? f.mt : f.mb) + ((size_t)it * f.W + site) * S;
+  const int src_site = g.rev[k] ? f.W - 1 - site : site;
+  copy_site(g.src[k] + (size_t)src_site * S, dst, K, P, g.rev[k], 1.0,
+            threadIdx.x, kThreads);
+}
+
+// Final boundary (column 0) of each item -> message of H sites.
+__global__ __launch_bounds__(kThreads) void k_extract(FitBatch f,
+                                                      double *const *dst,
+                                                      const int32_t *rev) {
+  const int i = blockIdx.x, it = blockIdx.y;
+  const int L = f.H;
+  const double *Y = f.store + ((size_t)it * f.W * f.N) * f.S;  // column 0
+  double scale = 1.0;
+  if (i == 0) scale *= Y[0];                              // site 0 scalar
+  if (i == L - 1) scale *= Y[(size_t)(f.N - 1) * f.S];    // site N-1 scalar
+  const int out = rev[it] ? L - 1 - i : i;
+  copy_site(Y + (size_t)(i + 1) * f.S, dst[it] + (size_t)out * f.S, f.K, f.P,
+            rev[it] != 0, scale, threadIdx.x, kThreads);
+}
+
+__global__ void k_ov_init(double *E, int K, int items) {
+  const int it = blockIdx.x;
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x)
+    E[(size_t)it * K * K + i] = (i == 0) ? 1.0 : 0.0;
+}
+__global__ void k_ov_out(const double *E, int K, int items, double *out) {
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it < items) out[it] = E[(size_t)it * K * K];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static Shape shape_of(const FitBatch &f) { return Shape{f.K, f.P, f.D, f.d}; }
+static size_t t1_stride(const FitBatch &f) { return (size_t)f.K * f.P * f.P * f.K; }
+static size_t t2_stride(const FitBatch &f) {
+  return (size_t)f.d * f.K * f.K * f.P * f.P;
+}
+static size_t a_site(const FitBatch &f) { return (size_t)f.d * f.P * f.P; }
+static size_t a_stride(const FitBatch &f) { return (size_t)f.H * f.W * a_site(f); }
+
+hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl, Ptr X,
+                              Ptr F, hipStream_t st) {
+  const Shape s = shape_of(f);
+  const size_t t1s = t1_stride(f), t2s = t2_stride(f), t3s = t1s;
+  const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
+  const double *Ak = f.acan + site_off;
+  const double *Ab = (f.abra ? f.abra : f.acan) + site_off;
+  OpK1 k1{f.K * f.P, f.P * f.K, f.K, nullptr, s, rl, X, F, f.t1, t1s};
+  hipError_t e = run_gemm<64, 64, 16>(k1, f.items, st);
+  if (e != hipSuccess) return e;
+  OpK2 k2{f.K * f.P * f.K, f.d * f.P, f.P, nullptr, s, rl, f.t1, t1s, Ak,
+          a_stride(f), f.t2, t2s};
+  e = run_gemm<128, 32, 16>(k2, f.items, st);
+  if (e != hipSuccess) return e;
+  OpK3 k3{f.K * f.K * f.P, f.P, f.d * f.P, nullptr, s, rl, f.t2, t2s, Ab,
+          a_stride(f), f.t3, t3s};
+  return run_gemm<256, 16, 16>(k3, f.items, st);
+}
+
+hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
+                              hipStream_t st) {
+  OpK4 k4{f.K * f.P, f.K, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
+          t1_stride(f), G, Y};
+  return run_gemm<64, 32, 16>(k4, f.items, st);
+}
+
+hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
+                            hipStream_t st) {
+  OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
+          t1_stride(f), Y, envOut};
+  return run_gemm<32, 64, 16>(k5, f.items, st);
+}
+
+hipError_t launch_end_chain(const FitBatch &f, bool rl, Ptr Mend, Ptr Xe,
+                            hipStream_t st) {
+  OpE1 e1{f.K * f.P, f.K, f.K, nullptr, shape_of(f), rl, Mend, Xe, f.t3,
+          t1_stride(f)};
+  return run_gemm<64, 32, 16>(e1, f.items, st);
+}
+
+hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
+                            hipStream_t st) {
+  OpE2 e2{f.K, f.K, f.P * f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
+          G, Ye};
+  return run_gemm<32, 32, 16>(e2, f.items, st);
+}
+
+hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
+                          hipStream_t st) {
+  OpE3 e3{f.K, f.P * f.K, f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
+          Ye, envOut};
+  return run_gemm<32, 64, 16>(e3, f.items, st);
+}
+
+hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
+                     bool want_r, bool only_flagged, hipStream_t st) {
+  QrArgs q{f.dims, f.W, c, j, mode, f.K, f.P, Y, f.rbuf, f.t1, t1_stride(f),
+           only_flagged ? f.flag : nullptr, want_r ? 1 : 0};
+  const size_t panel = (size_t)f.K * f.P * f.K;  // upper bound of m*n
+  if (panel <= (size_t)kQrLds)
+    hipLaunchKernelGGL(k_qr<true>, dim3(f.items), dim3(kThreads), 0, st, q);
+  else
+    hipLaunchKernelGGL(k_qr<false>, dim3(f.items), dim3(kThreads), 0, st, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_l(const FitBatch &f, bool end_site, Ptr Y,
+                          hipStream_t st) {
+  const int rows = end_site ? f.K : f.K * f.P;
+  OpApplyL op{rows, f.K, f.K, f.flag, shape_of(f), Y, f.rbuf, f.tmp, f.S};
+  hipError_t e = run_gemm<64, 32, 16>(op, f.items, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_flagged, dim3(64, f.items), dim3(kThreads), 0, st,
+                     (const double *)f.tmp, f.S, Y, f.S, (const int32_t *)f.flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_rand_init(const FitBatch &f, int c, Ptr Ybase,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_rand_init, dim3(f.N, f.items), dim3(kThreads), 0, st,
+                     f.dims, f.W, c, f.N, f.K, f.P, f.S, Ybase,
+                     (const uint64_t *)f.slot, f.seed, (const int32_t *)f.flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_unit, dim3(16, f.items), dim3(kThreads), 0, st,
+                     slot, f.S);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const FitBatch &f, Ptr Y0, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize, dim3(f.items), dim3(kThreads), 0, st, Y0,
+                     f.K, f.nu, f.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const FitBatch &f, const GatherSrc *srcs,
+                         hipStream_t st) {
+  const int nx = f.N > f.W ? f.N : f.W;
+  hipLaunchKernelGGL(k_gather, dim3(nx, 3, f.items), dim3(kThreads), 0, st, f,
+                     srcs);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(const FitBatch &f, double *const *dst,
+                          const int32_t *rev, hipStream_t st) {
+  hipLaunchKernelGGL(k_extract, dim3(f.H, f.items), dim3(kThreads), 0, st, f,
+                     dst, rev);
+  return hipGetLastError();
+}
+
+hipError_t launch_overlap(int items, int K, int P, int L,
+                          const double *const *a, const double *const *b,
+                          double *E, double *U, double *out, hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  const size_t S = (size_t)K * P * K;
+  hipLaunchKernelGGL(k_ov_init, dim3(items), dim3(64), 0, st, E, K, items);
+  for (int i = 0; i < L; ++i) {
+    OpOv1 o1{K, P * K, K, nullptr, K, E, a, (size_t)i * S, U, S};
+    hipError_t e = run_gemm<32, 64, 16>(o1, items, st);
+    if (e != hipSuccess) return e;
+    OpOv2 o2{K, K, K * P, nullptr, K, P, U, S, b, (size_t)i * S, E};
+    e = run_gemm<32, 32, 16>(o2, items, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_ov_out, dim3((items + 63) / 64), dim3(64), 0, st, E, K,
+                     items, out);
+  return hipGetLastError();
+}
+
+}  // namespace bbp
