@@ -5,10 +5,12 @@
 // Nothing here touches the GPU before bbp_set_tensors has validated its
 // input, so argument checking works on machines without a GPU.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <vector>
@@ -81,6 +83,18 @@ struct Group {
   DevBuf flagbuf;              // [W][items]
 };
 
+// Reduced density matrices of one region (block or union of two blocks)
+// computed from its boundary stacks; NaN where not computed.
+struct RegionResult {
+  int H = 0, W = 0;
+  bool has_row = false, has_col = false;
+  std::vector<double> zrow, lsrow;  // per row: line value and log scale
+  std::vector<double> site;         // [H][W][d*d]  unit (s',s) at s'*d+s
+  std::vector<double> hbond;        // [H][W-1][d^2][d^2]
+  std::vector<double> zcol, lscol;  // per column
+  std::vector<double> vbond;        // [W][H-1][d^2][d^2]
+};
+
 }  // namespace
 
 struct bbp_ctx {
@@ -102,6 +116,7 @@ struct bbp_ctx {
   int cur = 0;
   std::vector<std::unique_ptr<Group>> groups;
   double last_flops = 0.0;
+  std::map<std::tuple<int, int, int>, RegionResult> obs;  // (kind, bi, bj)
 
   bbp_status fail(bbp_status s, const std::string &m) {
     err = m;
@@ -263,17 +278,18 @@ static bbp_status ensure_device(bbp_ctx *c) {
   return BBP_OK;
 }
 
-static bbp_status alloc_group(bbp_ctx *c, Group &g) {
+static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
+                              const std::vector<uint64_t> &slots) {
   FitBatch &f = g.fb;
-  f.items = (int)g.ids.size();
-  f.K = c->K;
+  f.items = items;
+  f.K = bond_cap;
   f.P = c->P;
   f.D = c->D;
   f.d = c->d;
   f.H = g.H;
   f.W = g.W;
   f.N = g.H + 2;
-  f.S = c->S;
+  f.S = (size_t)bond_cap * c->P * bond_cap;
   f.seed = c->seed;
   const size_t it = f.items, S = f.S, K = f.K, P = f.P;
   struct Req {
@@ -293,7 +309,7 @@ static bbp_status alloc_group(bbp_ctx *c, Group &g) {
       {&f.tmp, it * S},
       {&f.acan, it * f.H * f.W * (size_t)f.d * P * P},
       {&f.rbuf, it * K * K},
-      {&f.nu, it},
+      {&f.nu, it * f.W},
   };
   g.bufs.resize(reqs.size() + 4);
   for (size_t i = 0; i < reqs.size(); ++i) {
@@ -318,10 +334,6 @@ static bbp_status alloc_group(bbp_ctx *c, Group &g) {
   f.err = (int32_t *)c->errflag.p;
   g.dims.assign(it * f.W, FitDims{});
   g.have.assign(it * f.W, 0);
-  // random-state slot bases: message e, column c -> (1<<40)|(e<<8)|c
-  std::vector<uint64_t> slots(it);
-  for (size_t i = 0; i < it; ++i)
-    slots[i] = (1ull << 40) | ((uint64_t)g.ids[i] << 8);
   hipError_t e = hipMemcpy(f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload slots");
   return BBP_OK;
@@ -409,88 +421,21 @@ static double column_macs(const FitDims &f, const std::vector<int> &xb_bonds,
   return t;
 }
 
-static bbp_status run_sweep(bbp_ctx *c, double *residual) {
+// Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
+// each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
+// for the bond caps and the random-start flags.
+static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo) {
   hipStream_t st = c->stream;
-  const int nxt = 1 - c->cur;
-  const size_t per = (size_t)c->Lmax * c->S;
-  double *cur = c->msgbuf[c->cur].d(), *nb = c->msgbuf[nxt].d();
-  hipError_t e = hipMemsetAsync(c->errflag.p, 0, 4, st);
-  if (e != hipSuccess) return c->hip_fail(e, "memset");
-  std::vector<std::vector<int>> new_bonds(c->msgs.size());
-  double flops = 0.0;
-  for (auto &gp : c->groups) {
-    Group &g = *gp;
-    FitBatch &f = g.fb;
-    const int W = f.W, H = f.H, N = f.N;
-    std::vector<GatherSrc> &gs = g.gs;
-    std::vector<double *> &dsts = g.dsts;
-    std::vector<int32_t> &revs = g.revs;
-    gs.assign(f.items, GatherSrc{});
-    dsts.assign(f.items, nullptr);
-    revs.assign(f.items, 0);
-    std::vector<int> any_rnd(W, 0);
-    std::vector<std::vector<int>> xb0(f.items);
-    for (int i = 0; i < f.items; ++i) {
-      const Message &m = c->msgs[g.ids[i]];
-      char side[3];
-      int rv[3];
-      canon_sources(m.dir, side, rv);
-      std::vector<int> bl[3];
-      for (int k = 0; k < 3; ++k) {
-        Incoming in = c->incoming(m.bi, m.bj, side[k]);
-        if (in.id < 0) {
-          gs[i].src[k] = c->trivial.d();
-          bl[k].assign(in.n + 1, 1);
-        } else {
-          gs[i].src[k] = cur + (size_t)in.id * per;
-          bl[k] = c->msgs[in.id].bonds;
-        }
-        gs[i].rev[k] = rv[k];
-        if (rv[k]) bl[k] = reversed(bl[k]);
-      }
-      dsts[i] = nb + (size_t)g.ids[i] * per;
-      revs[i] = out_reversed(m.dir) ? 1 : 0;
-      std::vector<FitDims> cd;
-      column_dims(W, H, f.K, f.P, bl[0], bl[2], bl[1], cd);
-      std::vector<int> xbonds = bl[1];
-      for (int col = W - 1; col >= 0; --col) {
-        FitDims &nd = cd[col];
-        FitDims &od = g.dims[(size_t)i * W + col];
-        bool same = g.have[(size_t)i * W + col] &&
-                    std::memcmp(nd.bl, od.bl, sizeof(nd.bl)) == 0 &&
-                    std::memcmp(nd.br, od.br, sizeof(nd.br)) == 0 &&
-                    std::memcmp(nd.p, od.p, sizeof(nd.p)) == 0;
-        nd.rnd = same ? 0 : 1;
-        any_rnd[col] |= nd.rnd;
-        od = nd;
-        g.have[(size_t)i * W + col] = 1;
-        const int xp0 = col == W - 1 ? 1 : cd[col + 1].p[0];
-        const int xpN = col == W - 1 ? 1 : cd[col + 1].p[N - 1];
-        flops += 2.0 * column_macs(nd, xbonds, xp0, xpN, N, f.P, f.D, f.d,
-                                   c->n_fit);
-        xbonds.assign(N - 1, 1);
-        for (int j = 0; j < N - 1; ++j) xbonds[j] = nd.br[j];
-      }
-      const FitDims &c0 = cd[0];
-      std::vector<int> cb(H + 1, 1);
-      for (int s = 0; s + 1 < H; ++s) cb[s + 1] = c0.br[s + 1];
-      new_bonds[g.ids[i]] = revs[i] ? reversed(cb) : cb;
-    }
-    e = hipMemcpyAsync(g.gather.p, gs.data(), sizeof(GatherSrc) * f.items,
-                       hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(g.dst.p, dsts.data(), sizeof(double *) * f.items,
-                         hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(g.rev.p, revs.data(), 4 * f.items,
-                         hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
-                         hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return c->hip_fail(e, "upload sweep tables");
-    e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
-    if (e != hipSuccess) return c->hip_fail(e, "gather");
-
+  FitBatch &f = g.fb;
+  const int W = f.W, N = f.N;
+  hipError_t e;
+  std::vector<int> any_rnd(W, 0);
+  for (int i = 0; i < f.items; ++i)
+    for (int col = 0; col < W; ++col)
+      any_rnd[col] |= g.dims[(size_t)i * W + col].rnd;
+  e = hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return c->hip_fail(e, "upload dims");
     const size_t sN = (size_t)N * f.S, sWN = (size_t)W * N * f.S;
     g.flags.assign((size_t)W * f.items, 0);
     for (int col = 0; col < W; ++col)
@@ -499,7 +444,7 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
     e = hipMemcpyAsync(g.flagbuf.p, g.flags.data(), 4 * g.flags.size(),
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return c->hip_fail(e, "upload flags");
-    for (int col = W - 1; col >= 0; --col) {
+    for (int col = W - 1; col >= col_lo; --col) {
       Ptr X = col == W - 1 ? Ptr{f.xin, sN}
                            : Ptr{f.store + slot_store(f, col + 1, 0), sWN};
       auto Xs = [&](int j) { return Ptr{X.p + (size_t)j * f.S, X.stride}; };
@@ -564,9 +509,93 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
       }
       e = launch_end_chain(f, false, MT, Xs(0), st);
       if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
-      if (e == hipSuccess) e = launch_normalize(f, Ys(0), st);
+      if (e == hipSuccess) e = launch_normalize(f, col, Ys(0), st);
       if (e != hipSuccess) return c->hip_fail(e, "final visit");
     }
+  return BBP_OK;
+}
+
+static bbp_status run_sweep(bbp_ctx *c, double *residual) {
+  hipStream_t st = c->stream;
+  const int nxt = 1 - c->cur;
+  const size_t per = (size_t)c->Lmax * c->S;
+  double *cur = c->msgbuf[c->cur].d(), *nb = c->msgbuf[nxt].d();
+  hipError_t e = hipMemsetAsync(c->errflag.p, 0, 4, st);
+  if (e != hipSuccess) return c->hip_fail(e, "memset");
+  std::vector<std::vector<int>> new_bonds(c->msgs.size());
+  double flops = 0.0;
+  for (auto &gp : c->groups) {
+    Group &g = *gp;
+    FitBatch &f = g.fb;
+    const int W = f.W, H = f.H, N = f.N;
+    std::vector<GatherSrc> &gs = g.gs;
+    std::vector<double *> &dsts = g.dsts;
+    std::vector<int32_t> &revs = g.revs;
+    gs.assign(f.items, GatherSrc{});
+    dsts.assign(f.items, nullptr);
+    revs.assign(f.items, 0);
+    std::vector<std::vector<int>> xb0(f.items);
+    for (int i = 0; i < f.items; ++i) {
+      const Message &m = c->msgs[g.ids[i]];
+      char side[3];
+      int rv[3];
+      canon_sources(m.dir, side, rv);
+      std::vector<int> bl[3];
+      gs[i].ksrc = c->K;
+      for (int k = 0; k < 3; ++k) {
+        Incoming in = c->incoming(m.bi, m.bj, side[k]);
+        if (in.id < 0) {
+          gs[i].src[k][0] = c->trivial.d();
+          bl[k].assign(in.n + 1, 1);
+        } else {
+          gs[i].src[k][0] = cur + (size_t)in.id * per;
+          bl[k] = c->msgs[in.id].bonds;
+        }
+        gs[i].n[k][0] = in.n;
+        gs[i].rev[k][0] = rv[k];
+        if (rv[k]) bl[k] = reversed(bl[k]);
+      }
+      dsts[i] = nb + (size_t)g.ids[i] * per;
+      revs[i] = out_reversed(m.dir) ? 1 : 0;
+      std::vector<FitDims> cd;
+      column_dims(W, H, f.K, f.P, bl[0], bl[2], bl[1], cd);
+      std::vector<int> xbonds = bl[1];
+      for (int col = W - 1; col >= 0; --col) {
+        FitDims &nd = cd[col];
+        FitDims &od = g.dims[(size_t)i * W + col];
+        bool same = g.have[(size_t)i * W + col] &&
+                    std::memcmp(nd.bl, od.bl, sizeof(nd.bl)) == 0 &&
+                    std::memcmp(nd.br, od.br, sizeof(nd.br)) == 0 &&
+                    std::memcmp(nd.p, od.p, sizeof(nd.p)) == 0;
+        nd.rnd = same ? 0 : 1;
+        od = nd;
+        g.have[(size_t)i * W + col] = 1;
+        const int xp0 = col == W - 1 ? 1 : cd[col + 1].p[0];
+        const int xpN = col == W - 1 ? 1 : cd[col + 1].p[N - 1];
+        flops += 2.0 * column_macs(nd, xbonds, xp0, xpN, N, f.P, f.D, f.d,
+                                   c->n_fit);
+        xbonds.assign(N - 1, 1);
+        for (int j = 0; j < N - 1; ++j) xbonds[j] = nd.br[j];
+      }
+      const FitDims &c0 = cd[0];
+      std::vector<int> cb(H + 1, 1);
+      for (int s = 0; s + 1 < H; ++s) cb[s + 1] = c0.br[s + 1];
+      new_bonds[g.ids[i]] = revs[i] ? reversed(cb) : cb;
+    }
+    e = hipMemcpyAsync(g.gather.p, gs.data(), sizeof(GatherSrc) * f.items,
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.dst.p, dsts.data(), sizeof(double *) * f.items,
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.rev.p, revs.data(), 4 * f.items,
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return c->hip_fail(e, "upload sweep tables");
+    e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
+    if (e != hipSuccess) return c->hip_fail(e, "gather");
+
+    bbp_status bs = absorb_columns(c, g, 0);
+    if (bs != BBP_OK) return bs;
     e = launch_extract(f, (double *const *)g.dst.p, (const int32_t *)g.rev.p, st);
     if (e != hipSuccess) return c->hip_fail(e, "extract");
   }
@@ -613,8 +642,703 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
   }
   for (int i = 0; i < nm; ++i) c->msgs[i].bonds = new_bonds[i];
   c->cur = nxt;
+  c->obs.clear();
   c->last_flops = flops;
   if (residual) *residual = nm ? sum / nm : 0.0;
+  return BBP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Observables (Sec. II; App. A second paragraph; App. B): a region (a block,
+// or the union of two neighbouring blocks for a bond crossing them) with its
+// incoming messages.  Boundary MPSs are absorbed from each side at bond
+// chi_env (the same fit engine as the messages), then every line of the
+// region is contracted exactly between its two boundaries: left and right
+// environment chains, and environment steps with a matrix unit |s'><s| on
+// one site, whose contractions are the one- and two-site reduced density
+// matrices.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Seg {
+  int id;  // message id, -1 for a trivial message
+  int n;   // sites
+};
+
+struct RegionSpec {
+  int kind, bi, bj;  // 0 block, 1 block + right neighbour, 2 block + lower
+  int H, W;
+  std::vector<Seg> side[4];  // incoming on 'U','D','L','R', natural order
+  bool row, col;             // frames needed
+};
+
+int side_slot(char s) { return s == 'U' ? 0 : s == 'D' ? 1 : s == 'L' ? 2 : 3; }
+
+struct StackItem {
+  int region;
+  char orient;
+  int Wc, Hc;  // canonical width (columns absorbed from) and height
+};
+
+struct LineItem {
+  int region;
+  bool row;     // row frame ('D' stack as X, 'U' stack as Y) or column frame
+  int k;        // row (row frame) or column (column frame) in the region
+  int xs, ys;   // stack item indices of the X and Y boundaries
+  int cx, cy;   // canonical column of the line in the X / Y frames
+  double ls;    // log scale of the two boundaries
+};
+
+struct UnitItem {
+  int line;  // index in the line batch
+  int j;     // canonical site (1..H)
+  int u;     // matrix unit s'*d + s
+};
+
+}  // namespace
+
+static RegionSpec region_spec(const bbp_ctx *c, int kind, int bi, int bj) {
+  RegionSpec r;
+  r.kind = kind;
+  r.bi = bi;
+  r.bj = bj;
+  r.row = r.col = false;
+  auto inc = [&](int i, int j, char sd) {
+    Incoming in = c->incoming(i, j, sd);
+    return Seg{in.id, in.n};
+  };
+  if (kind == 0) {
+    r.H = c->by;
+    r.W = c->bx;
+    for (char sd : {'U', 'D', 'L', 'R'}) r.side[side_slot(sd)] = {inc(bi, bj, sd)};
+  } else if (kind == 1) {
+    int ni, nj;
+    c->neighbour(bi, bj, 'R', &ni, &nj);
+    r.H = c->by;
+    r.W = 2 * c->bx;
+    r.side[0] = {inc(bi, bj, 'U'), inc(ni, nj, 'U')};
+    r.side[1] = {inc(bi, bj, 'D'), inc(ni, nj, 'D')};
+    r.side[2] = {inc(bi, bj, 'L')};
+    r.side[3] = {inc(ni, nj, 'R')};
+  } else {
+    int ni, nj;
+    c->neighbour(bi, bj, 'D', &ni, &nj);
+    r.H = 2 * c->by;
+    r.W = c->bx;
+    r.side[0] = {inc(bi, bj, 'U')};
+    r.side[1] = {inc(ni, nj, 'D')};
+    r.side[2] = {inc(bi, bj, 'L'), inc(ni, nj, 'L')};
+    r.side[3] = {inc(bi, bj, 'R'), inc(ni, nj, 'R')};
+  }
+  return r;
+}
+
+static uint64_t region_slot(int kind, int bi, int bj, char orient) {
+  return (2ull << 40) | ((uint64_t)kind << 36) | ((uint64_t)bj << 24) |
+         ((uint64_t)bi << 12) | ((uint64_t)dir_index(orient) << 8);
+}
+
+// Gather table and bond lists of one rotated side made of message segments.
+static void side_source(const bbp_ctx *c, const std::vector<Seg> &segs,
+                        bool rev, GatherSrc &g, int k, std::vector<int> &bonds) {
+  std::vector<Seg> order = segs;
+  if (rev) std::reverse(order.begin(), order.end());
+  const size_t per = (size_t)c->Lmax * c->S;
+  const double *cur = c->msgbuf[c->cur].d();
+  bonds.assign(1, 1);
+  for (size_t t = 0; t < 2; ++t) {
+    g.src[k][t] = nullptr;
+    g.n[k][t] = 0;
+    g.rev[k][t] = 0;
+  }
+  for (size_t t = 0; t < order.size(); ++t) {
+    const Seg &sg = order[t];
+    g.src[k][t] = sg.id < 0 ? c->trivial.d() : cur + (size_t)sg.id * per;
+    g.n[k][t] = sg.n;
+    g.rev[k][t] = rev ? 1 : 0;
+    std::vector<int> b = sg.id < 0 ? std::vector<int>(sg.n + 1, 1)
+                                   : c->msgs[sg.id].bonds;
+    if (rev) b = reversed(b);
+    bonds.insert(bonds.end(), b.begin() + 1, b.end());
+  }
+}
+
+// Lattice coordinates of region cell (y, x).
+static const double *region_site(const bbp_ctx *c, const RegionSpec &r, int y,
+                                 int x) {
+  return c->site(r.bi * c->bx + x, r.bj * c->by + y);
+}
+
+static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
+  hipStream_t st = c->stream;
+  hipError_t e;
+  const int Kenv = c->chi_env, P = c->P, d = c->d, d2 = d * d;
+  const size_t Senv = (size_t)Kenv * P * Kenv;
+  const size_t asite = (size_t)d * P * P;
+  // ---- 1. boundary stacks, batched by rotated shape -----------------------
+  std::vector<StackItem> stacks;
+  std::vector<std::array<int, 4>> stack_of(regs.size(), {-1, -1, -1, -1});
+  for (size_t r = 0; r < regs.size(); ++r) {
+    const RegionSpec &R = regs[r];
+    std::vector<char> ors;
+    if (R.row) ors.insert(ors.end(), {'D', 'U'});
+    if (R.col) ors.insert(ors.end(), {'L', 'R'});
+    for (char o : ors) {
+      StackItem it{(int)r, o, 0, 0};
+      if (o == 'D' || o == 'U') {
+        it.Wc = R.H;
+        it.Hc = R.W;
+      } else {
+        it.Wc = R.W;
+        it.Hc = R.H;
+      }
+      stack_of[r][dir_index(o)] = (int)stacks.size();
+      stacks.push_back(it);
+    }
+  }
+  std::map<std::pair<int, int>, std::vector<int>> sgroups;
+  for (size_t i = 0; i < stacks.size(); ++i)
+    sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
+  std::vector<std::unique_ptr<Group>> sg;
+  std::vector<std::pair<int, int>> where(stacks.size());  // (group, item)
+  std::vector<std::vector<double>> nus;
+  for (auto &kv : sgroups) {
+    std::unique_ptr<Group> gp(new Group);
+    Group &g = *gp;
+    g.W = kv.first.first;
+    g.H = kv.first.second;
+    const std::vector<int> &ids = kv.second;
+    std::vector<uint64_t> slots(ids.size());
+    for (size_t i = 0; i < ids.size(); ++i) {
+      const StackItem &it = stacks[ids[i]];
+      const RegionSpec &R = regs[it.region];
+      slots[i] = region_slot(R.kind, R.bi, R.bj, it.orient);
+      where[ids[i]] = {(int)sg.size(), (int)i};
+    }
+    bbp_status bs = alloc_batch(c, g, (int)ids.size(), Kenv, slots);
+    if (bs != BBP_OK) return bs;
+    FitBatch &f = g.fb;
+    // rotated tensors, gather tables and bond caps
+    std::vector<double> host((size_t)f.items * f.H * f.W * asite);
+    g.gs.assign(f.items, GatherSrc{});
+    for (int i = 0; i < f.items; ++i) {
+      const StackItem &it = stacks[ids[i]];
+      const RegionSpec &R = regs[it.region];
+      for (int yc = 0; yc < f.H; ++yc)
+        for (int xc = 0; xc < f.W; ++xc) {
+          int y, x;
+          canon_to_region(it.orient, R.H, R.W, yc, xc, &y, &x);
+          rotate_site(c, region_site(c, R, y, x), it.orient,
+                      host.data() + (((size_t)i * f.H + yc) * f.W + xc) * asite);
+        }
+      char side[3];
+      int rv[3];
+      canon_sources(it.orient, side, rv);
+      std::vector<int> bl[3];
+      g.gs[i].ksrc = c->K;
+      for (int k = 0; k < 3; ++k)
+        side_source(c, R.side[side_slot(side[k])], rv[k] != 0, g.gs[i], k, bl[k]);
+      std::vector<FitDims> cd;
+      column_dims(f.W, f.H, Kenv, P, bl[0], bl[2], bl[1], cd);
+      for (int col = 0; col < f.W; ++col) {
+        cd[col].rnd = 1;
+        g.dims[(size_t)i * f.W + col] = cd[col];
+      }
+    }
+    e = hipMemcpyAsync(f.acan, host.data(), host.size() * 8,
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(g.gather.p, g.gs.data(), sizeof(GatherSrc) * f.items,
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging reused
+    if (e != hipSuccess) return c->hip_fail(e, "region setup");
+    if (f.W > 1) {
+      bs = absorb_columns(c, g, 1);
+      if (bs != BBP_OK) return bs;
+    }
+    std::vector<double> nu((size_t)f.items * f.W, 1.0);
+    e = hipMemcpyAsync(nu.data(), f.nu, nu.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return c->hip_fail(e, "region stacks");
+    if (f.W == 1) std::fill(nu.begin(), nu.end(), 1.0);
+    nus.push_back(nu);
+    g.ids = ids;
+    sg.push_back(std::move(gp));
+  }
+  int32_t errv = 0;
+  e = hipMemcpy(&errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return c->hip_fail(e, "error flag");
+  if (errv) return c->fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
+
+  // boundary after absorbing canonical columns W-1..col+1 (col = W-1: none)
+  auto boundary = [&](int sidx, int col, size_t j) -> const double * {
+    const Group &g = *sg[where[sidx].first];
+    const int i = where[sidx].second;
+    const FitBatch &f = g.fb;
+    if (col == f.W - 1) return f.xin + ((size_t)i * f.N + j) * f.S;
+    return f.store + ((size_t)i * f.W * f.N) * f.S + slot_store(f, col + 1, (int)j);
+  };
+  auto logscale = [&](int sidx, int col) {
+    const Group &g = *sg[where[sidx].first];
+    const int i = where[sidx].second;
+    double t = 0.0;
+    for (int cc = col + 1; cc < g.fb.W; ++cc)
+      t += std::log(nus[where[sidx].first][(size_t)i * g.fb.W + cc]);
+    return t;
+  };
+
+  // ---- 2. lines, batched by length ---------------------------------------
+  std::vector<LineItem> lines;
+  for (size_t r = 0; r < regs.size(); ++r) {
+    const RegionSpec &R = regs[r];
+    if (R.row)
+      for (int k = 0; k < R.H; ++k) {
+        LineItem L{(int)r, true, k, stack_of[r][dir_index('D')],
+                   stack_of[r][dir_index('U')], R.H - 1 - k, k, 0.0};
+        L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
+        lines.push_back(L);
+      }
+    if (R.col)
+      for (int k = 0; k < R.W; ++k) {
+        LineItem L{(int)r, false, k, stack_of[r][dir_index('L')],
+                   stack_of[r][dir_index('R')], k, R.W - 1 - k, 0.0};
+        L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
+        lines.push_back(L);
+      }
+  }
+  std::map<int, std::vector<int>> lgroups;
+  for (size_t i = 0; i < lines.size(); ++i) {
+    const int Hc = stacks[lines[i].xs].Hc;
+    lgroups[Hc].push_back((int)i);
+  }
+  // results per line
+  std::vector<double> lz(lines.size(), 0.0);
+  // unit results: (line, j, u) -> LR step value maps keyed in host tables
+  std::map<std::tuple<int, int, int>, double> site_rho;        // (line,j,u)
+  std::map<std::tuple<int, int, int, int>, double> bond_rho;   // (line,j,u,v)
+  for (auto &kv : lgroups) {
+    const int Hc = kv.first;
+    const std::vector<int> &lids = kv.second;
+    Group lg;
+    lg.W = 1;
+    lg.H = Hc;
+    std::vector<uint64_t> slots(lids.size(), 0);
+    bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots);
+    if (bs != BBP_OK) return bs;
+    FitBatch &f = lg.fb;
+    const int N = f.N;
+    std::vector<CopyJob> jobs;
+    for (size_t li = 0; li < lids.size(); ++li) {
+      const LineItem &L = lines[lids[li]];
+      const Group &gx = *sg[where[L.xs].first];
+      const int ix = where[L.xs].second;
+      for (int j = 0; j < N; ++j) {
+        jobs.push_back(CopyJob{boundary(L.xs, L.cx, j),
+                               f.xin + (li * N + j) * f.S, (int64_t)f.S, 0, 0});
+        const bool endsite = (j == 0 || j == N - 1);
+        jobs.push_back(CopyJob{boundary(L.ys, L.cy, N - 1 - j),
+                               f.store + (li * N + j) * f.S, (int64_t)f.S,
+                               endsite ? 2 : 1, 0});
+      }
+      for (int j = 0; j < Hc; ++j)
+        jobs.push_back(CopyJob{
+            gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
+            f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
+      jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                             f.mt + li * f.S, (int64_t)f.S, 0, 0});
+      jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                             f.mb + li * f.S, (int64_t)f.S, 0, 0});
+    }
+    DevBuf djobs;
+    if (djobs.alloc(sizeof(CopyJob) * jobs.size()) != hipSuccess)
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    e = hipMemcpy(djobs.p, jobs.data(), sizeof(CopyJob) * jobs.size(),
+                  hipMemcpyHostToDevice);
+    for (size_t o = 0; e == hipSuccess && o < jobs.size(); o += 60000)
+      e = launch_copy_jobs((const CopyJob *)djobs.p + o,
+                           (int)std::min<size_t>(60000, jobs.size() - o), Kenv,
+                           P, st);
+    if (e != hipSuccess) return c->hip_fail(e, "line setup");
+    const size_t sN = (size_t)N * f.S;
+    auto Xs = [&](int j) { return Ptr{f.xin + (size_t)j * f.S, sN}; };
+    auto Ys = [&](int j) { return Ptr{f.store + (size_t)j * f.S, sN}; };
+    auto Le = [&](int j) { return Ptr{f.lenv + (size_t)j * f.S, sN}; };
+    auto Re = [&](int j) { return Ptr{f.renv + (size_t)j * f.S, sN}; };
+    Ptr MT{f.mt, f.S}, MB{f.mb, f.S};
+    if ((e = launch_set_unit(f, Le(0), st)) != hipSuccess ||
+        (e = launch_set_unit(f, Re(N - 1), st)) != hipSuccess)
+      return c->hip_fail(e, "set_unit");
+    for (int j = 0; j < N - 1; ++j) {
+      if (j == 0) {
+        e = launch_end_chain(f, false, MT, Xs(0), st);
+        if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
+      } else {
+        e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), st);
+        if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+      }
+      if (e != hipSuccess) return c->hip_fail(e, "line left environments");
+    }
+    for (int j = N - 1; j >= 1; --j) {
+      if (j == N - 1) {
+        e = launch_end_chain(f, true, MB, Xs(N - 1), st);
+        if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
+      } else {
+        e = launch_inner_chain(f, 0, j, true, Xs(j), Re(j), st);
+        if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
+      }
+      if (e != hipSuccess) return c->hip_fail(e, "line right environments");
+    }
+    // ---- 3. matrix-unit steps ------------------------------------------
+    // needed (line, j, direction): sites and the first site of a bond take
+    // a left-to-right step; the second site of a bond a right-to-left step.
+    std::vector<UnitItem> units[2];
+    for (size_t li = 0; li < lids.size(); ++li) {
+      const LineItem &L = lines[lids[li]];
+      const RegionSpec &R = regs[L.region];
+      std::vector<int> lr, rl;
+      if (L.row) {
+        if (R.kind == 0) {
+          for (int j = 1; j <= Hc; ++j) lr.push_back(j);
+          for (int j = 2; j <= Hc; ++j) rl.push_back(j);
+        } else {  // union: the bond crossing the two blocks
+          lr.push_back(c->bx);
+          rl.push_back(c->bx + 1);
+        }
+      } else {
+        if (R.kind == 0) {
+          for (int j = 1; j < Hc; ++j) lr.push_back(j);
+          for (int j = 2; j <= Hc; ++j) rl.push_back(j);
+        } else {
+          lr.push_back(c->by);
+          rl.push_back(c->by + 1);
+        }
+      }
+      for (int j : lr)
+        for (int u = 0; u < d2; ++u) units[0].push_back(UnitItem{(int)li, j, u});
+      for (int j : rl)
+        for (int u = 0; u < d2; ++u) units[1].push_back(UnitItem{(int)li, j, u});
+    }
+    const int CH = 256;
+    std::vector<double *> out_ptr[2];
+    DevBuf outbuf[2];
+    for (int dir = 0; dir < 2; ++dir) {
+      const std::vector<UnitItem> &U = units[dir];
+      if (U.empty()) continue;
+      if (outbuf[dir].alloc(U.size() * f.S * 8) != hipSuccess)
+        return c->fail(BBP_ENOMEM, "device allocation failed");
+      out_ptr[dir].resize(U.size());
+      for (size_t i = 0; i < U.size(); ++i)
+        out_ptr[dir][i] = outbuf[dir].d() + i * f.S;
+      for (size_t o = 0; o < U.size(); o += CH) {
+        const int n = (int)std::min<size_t>(CH, U.size() - o);
+        Group ug;
+        ug.W = 1;
+        ug.H = 1;
+        bbp_status bs2 = alloc_batch(c, ug, n, Kenv, std::vector<uint64_t>(n, 0));
+        if (bs2 != BBP_OK) return bs2;
+        FitBatch &fu = ug.fb;
+        DevBuf kets, bras, tabs;
+        if (kets.alloc((size_t)n * asite * 8) != hipSuccess ||
+            bras.alloc((size_t)n * asite * 8) != hipSuccess ||
+            tabs.alloc((size_t)n * 3 * sizeof(double *)) != hipSuccess)
+          return c->fail(BBP_ENOMEM, "device allocation failed");
+        e = hipMemsetAsync(kets.p, 0, kets.bytes, st);
+        std::vector<CopyJob> uj;
+        std::vector<double *> tab(3 * (size_t)n);
+        const size_t slice = asite / d;
+        for (int i = 0; i < n; ++i) {
+          const UnitItem &ui = U[o + i];
+          const double *A = f.acan + ((size_t)ui.line * Hc + (ui.j - 1)) * asite;
+          const int sp = ui.u / d, s0 = ui.u % d;
+          // bra: A; ket: only physical index s' present, equal to A[s]
+          uj.push_back(CopyJob{A, bras.d() + (size_t)i * asite, (int64_t)asite, 0, 0});
+          uj.push_back(CopyJob{A + s0 * slice, kets.d() + (size_t)i * asite + sp * slice,
+                               (int64_t)slice, 0, 0});
+          tab[i] = f.xin + ((size_t)ui.line * N + ui.j) * f.S;
+          tab[n + i] = (dir == 0 ? f.lenv : f.renv) + ((size_t)ui.line * N + ui.j) * f.S;
+          tab[2 * n + i] = f.store + ((size_t)ui.line * N + ui.j) * f.S;
+        }
+        DevBuf ujobs;
+        if (ujobs.alloc(sizeof(CopyJob) * uj.size()) != hipSuccess)
+          return c->fail(BBP_ENOMEM, "device allocation failed");
+        if (e == hipSuccess)
+          e = hipMemcpy(ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
+                        hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(tabs.p, tab.data(), tab.size() * sizeof(double *),
+                        hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = launch_copy_jobs((const CopyJob *)ujobs.p, (int)uj.size(), Kenv, P, st);
+        if (e != hipSuccess) return c->hip_fail(e, "unit setup");
+        fu.acan = kets.d();
+        fu.abra = bras.d();
+        double *const *tp = (double *const *)tabs.p;
+        Ptr X{nullptr, 0, tp}, F{nullptr, 0, tp + n}, Y{nullptr, 0, tp + 2 * n};
+        e = launch_inner_chain(fu, 0, 1, dir == 1, X, F, st);
+        if (e == hipSuccess)
+          e = launch_inner_env(fu, dir == 1, Y, Ptr{outbuf[dir].d() + o * f.S, f.S},
+                               st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return c->hip_fail(e, "unit steps");
+      }
+    }
+    // ---- 4. contractions: line values, site and bond density matrices -----
+    std::vector<const double *> pa, pb;
+    struct Tag {
+      int kind, line, j, u, v;
+    };
+    std::vector<Tag> tags;
+    for (size_t li = 0; li < lids.size(); ++li) {
+      pa.push_back(f.lenv + (li * N + 1) * f.S);
+      pb.push_back(f.renv + (li * N + 0) * f.S);
+      tags.push_back(Tag{0, (int)li, 0, 0, 0});
+    }
+    std::map<std::tuple<int, int, int>, int> lr_index, rl_index;
+    for (size_t i = 0; i < units[0].size(); ++i)
+      lr_index[{units[0][i].line, units[0][i].j, units[0][i].u}] = (int)i;
+    for (size_t i = 0; i < units[1].size(); ++i)
+      rl_index[{units[1][i].line, units[1][i].j, units[1][i].u}] = (int)i;
+    for (auto &kv2 : lr_index) {
+      const int li = std::get<0>(kv2.first), j = std::get<1>(kv2.first),
+                u = std::get<2>(kv2.first);
+      // site: <L^u_{j+1}, R_j>
+      pa.push_back(out_ptr[0][kv2.second]);
+      pb.push_back(f.renv + ((size_t)li * N + j) * f.S);
+      tags.push_back(Tag{1, li, j, u, 0});
+      // bond (j, j+1): <L^u_{j+1}, R^v_j> with R^v_j the step at site j+1
+      for (int v = 0; v < d2; ++v) {
+        auto it = rl_index.find({li, j + 1, v});
+        if (it == rl_index.end()) continue;
+        pa.push_back(out_ptr[0][kv2.second]);
+        pb.push_back(out_ptr[1][it->second]);
+        tags.push_back(Tag{2, li, j, u, v});
+      }
+    }
+    DevBuf da, db, dout;
+    if (da.alloc(pa.size() * 8) != hipSuccess || db.alloc(pb.size() * 8) != hipSuccess ||
+        dout.alloc(pa.size() * 8) != hipSuccess)
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    std::vector<double> vals(pa.size());
+    e = hipMemcpy(da.p, pa.data(), pa.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(db.p, pb.data(), pb.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = launch_dots((int)pa.size(), (const double *const *)da.p,
+                      (const double *const *)db.p, f.S, dout.d(), st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(vals.data(), dout.p, vals.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return c->hip_fail(e, "line contractions");
+    for (size_t t = 0; t < tags.size(); ++t) {
+      const Tag &tg = tags[t];
+      const int line = lids[tg.line];
+      if (tg.kind == 0) lz[line] = vals[t];
+      else if (tg.kind == 1) site_rho[{line, tg.j, tg.u}] = vals[t];
+      else bond_rho[{line, tg.j, tg.u, tg.v}] = vals[t];
+    }
+  }
+  // ---- 5. results per region ----------------------------------------------
+  const double nan = std::nan("");
+  for (size_t r = 0; r < regs.size(); ++r) {
+    const RegionSpec &R = regs[r];
+    RegionResult &res = c->obs[std::make_tuple(R.kind, R.bi, R.bj)];
+    res.H = R.H;
+    res.W = R.W;
+    if (R.row) {
+      res.has_row = true;
+      res.zrow.assign(R.H, nan);
+      res.lsrow.assign(R.H, nan);
+      res.site.assign((size_t)R.H * R.W * d2, nan);
+      res.hbond.assign((size_t)R.H * std::max(R.W - 1, 0) * d2 * d2, nan);
+    }
+    if (R.col) {
+      res.has_col = true;
+      res.zcol.assign(R.W, nan);
+      res.lscol.assign(R.W, nan);
+      res.vbond.assign((size_t)R.W * std::max(R.H - 1, 0) * d2 * d2, nan);
+    }
+  }
+  for (size_t li = 0; li < lines.size(); ++li) {
+    const LineItem &L = lines[li];
+    const RegionSpec &R = regs[L.region];
+    RegionResult &res = c->obs[std::make_tuple(R.kind, R.bi, R.bj)];
+    if (L.row) {
+      res.zrow[L.k] = lz[li];
+      res.lsrow[L.k] = L.ls;
+    } else {
+      res.zcol[L.k] = lz[li];
+      res.lscol[L.k] = L.ls;
+    }
+  }
+  for (auto &kv : site_rho) {
+    const LineItem &L = lines[std::get<0>(kv.first)];
+    const RegionSpec &R = regs[L.region];
+    if (!L.row) continue;
+    RegionResult &res = c->obs[std::make_tuple(R.kind, R.bi, R.bj)];
+    const int x = std::get<1>(kv.first) - 1;
+    res.site[((size_t)L.k * R.W + x) * d2 + std::get<2>(kv.first)] = kv.second;
+  }
+  for (auto &kv : bond_rho) {
+    const LineItem &L = lines[std::get<0>(kv.first)];
+    const RegionSpec &R = regs[L.region];
+    RegionResult &res = c->obs[std::make_tuple(R.kind, R.bi, R.bj)];
+    const int p0 = std::get<1>(kv.first) - 1, u = std::get<2>(kv.first),
+              v = std::get<3>(kv.first);
+    if (L.row)
+      res.hbond[(((size_t)L.k * (R.W - 1) + p0) * d2 + u) * d2 + v] = kv.second;
+    else
+      res.vbond[(((size_t)L.k * (R.H - 1) + p0) * d2 + u) * d2 + v] = kv.second;
+  }
+  return BBP_OK;
+}
+
+// Region-local position of lattice site (x, y): block indices and offsets.
+// Infinite lattices use the unit-cell copy nearest the centre of the block.
+static void locate(const bbp_ctx *c, int x, int y, int *bi, int *bj, int *lx,
+                   int *ly) {
+  if (c->infinite) {
+    const int ox = (c->bx - c->ucx) / 2, oy = (c->by - c->ucy) / 2;
+    x = ox + (((x - ox) % c->ucx) + c->ucx) % c->ucx;
+    y = oy + (((y - oy) % c->ucy) + c->ucy) % c->ucy;
+  }
+  *bi = x / c->bx;
+  *bj = y / c->by;
+  *lx = x % c->bx;
+  *ly = y % c->by;
+}
+
+struct Query {
+  int kind, bi, bj;
+  bool row;   // row frame (sites, horizontal bonds) or column frame
+  int line, pos;
+  bool bond;
+};
+
+static bbp_status make_query(bbp_ctx *c, int x0, int y0, int x1, int y1,
+                             bool bond, Query &q) {
+  if (!c->infinite) {
+    const bool in0 = x0 >= 0 && y0 >= 0 && x0 < c->Lx && y0 < c->Ly;
+    const bool in1 = x1 >= 0 && y1 >= 0 && x1 < c->Lx && y1 < c->Ly;
+    if (!in0 || (bond && !in1)) return c->fail(BBP_EINVAL, "site outside the lattice");
+  }
+  int bi, bj, lx, ly;
+  locate(c, x0, y0, &bi, &bj, &lx, &ly);
+  q.bi = bi;
+  q.bj = bj;
+  q.bond = bond;
+  if (!bond) {
+    q.kind = 0;
+    q.row = true;
+    q.line = ly;
+    q.pos = lx;
+    return BBP_OK;
+  }
+  if (x1 == x0 + 1 && y1 == y0) {
+    q.row = true;
+    q.line = ly;
+    if (lx + 1 < c->bx) {
+      q.kind = 0;
+      q.pos = lx;
+    } else {
+      q.kind = 1;
+      q.pos = c->bx - 1;
+    }
+  } else if (x1 == x0 && y1 == y0 + 1) {
+    q.row = false;
+    q.line = lx;
+    if (ly + 1 < c->by) {
+      q.kind = 0;
+      q.pos = ly;
+    } else {
+      q.kind = 2;
+      q.pos = c->by - 1;
+    }
+  } else {
+    return c->fail(BBP_EINVAL, "bond must join (x,y) to (x+1,y) or (x,y+1)");
+  }
+  return BBP_OK;
+}
+
+static bbp_status ensure_regions(bbp_ctx *c, const std::vector<Query> &qs) {
+  std::map<std::tuple<int, int, int>, std::pair<bool, bool>> need;
+  for (const Query &q : qs) {
+    auto key = std::make_tuple(q.kind, q.bi, q.bj);
+    auto it = c->obs.find(key);
+    const bool have_row = it != c->obs.end() && it->second.has_row;
+    const bool have_col = it != c->obs.end() && it->second.has_col;
+    auto &n = need[key];
+    if (q.row && !have_row) n.first = true;
+    if (!q.row && !have_col) n.second = true;
+    if (q.kind == 0 && q.row && !have_col) n.second = true;  // whole block
+    if (q.kind == 0 && !q.row && !have_row) n.first = true;
+  }
+  std::vector<RegionSpec> regs;
+  for (auto &kv : need) {
+    if (!kv.second.first && !kv.second.second) continue;
+    RegionSpec r = region_spec(c, std::get<0>(kv.first), std::get<1>(kv.first),
+                               std::get<2>(kv.first));
+    r.row = kv.second.first;
+    r.col = kv.second.second;
+    regs.push_back(r);
+    c->obs.erase(kv.first);
+  }
+  if (regs.empty()) return BBP_OK;
+  return compute_regions(c, regs);
+}
+
+static bbp_status answer(bbp_ctx *c, const Query &q, const double *op,
+                         double *out) {
+  const RegionResult &res = c->obs.at(std::make_tuple(q.kind, q.bi, q.bj));
+  const int d = c->d, d2 = d * d;
+  double num = 0.0, den = 0.0;
+  if (!q.bond) {
+    const double *rho = &res.site[((size_t)q.line * res.W + q.pos) * d2];
+    for (int sp = 0; sp < d; ++sp)
+      for (int s = 0; s < d; ++s) num += op[sp * d + s] * rho[sp * d + s];
+    for (int s = 0; s < d; ++s) den += rho[s * d + s];
+  } else {
+    const double *rho =
+        q.row ? &res.hbond[((size_t)q.line * (res.W - 1) + q.pos) * d2 * d2]
+              : &res.vbond[((size_t)q.line * (res.H - 1) + q.pos) * d2 * d2];
+    for (int s0p = 0; s0p < d; ++s0p)
+      for (int s1p = 0; s1p < d; ++s1p)
+        for (int s0 = 0; s0 < d; ++s0)
+          for (int s1 = 0; s1 < d; ++s1) {
+            const double o = op[(s0p * d + s1p) * d2 + s0 * d + s1];
+            num += o * rho[(s0p * d + s0) * d2 + s1p * d + s1];
+          }
+    for (int s0 = 0; s0 < d; ++s0)
+      for (int s1 = 0; s1 < d; ++s1) den += rho[(s0 * d + s0) * d2 + s1 * d + s1];
+  }
+  if (!std::isfinite(num) || !std::isfinite(den) || den == 0.0)
+    return c->fail(BBP_ENUMERIC, "vanishing or non-finite region contraction");
+  *out = num / den;
+  return BBP_OK;
+}
+
+static bbp_status expect_many(bbp_ctx *c, int n, const int32_t *x0,
+                              const int32_t *y0, const int32_t *x1,
+                              const int32_t *y1, bool bond, const double *op,
+                              double *out) {
+  if (!c) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (n < 0 || (n > 0 && (!x0 || !y0 || !op || !out || (bond && (!x1 || !y1)))))
+    return c->fail(BBP_EINVAL, "null argument");
+  if (c->chi_env < c->chi)
+    return c->fail(BBP_EINVAL, "chi_env must be at least chi");
+  const int m = bond ? c->d * c->d : c->d;
+  for (int i = 0; i < m * m; ++i)
+    if (!std::isfinite(op[i])) return c->fail(BBP_EINVAL, "non-finite operator");
+  std::vector<Query> qs(n);
+  for (int i = 0; i < n; ++i) {
+    bbp_status s = make_query(c, x0[i], y0[i], bond ? x1[i] : 0, bond ? y1[i] : 0,
+                              bond, qs[i]);
+    if (s != BBP_OK) return s;
+  }
+  bbp_status s = ensure_regions(c, qs);
+  if (s != BBP_OK) return s;
+  for (int i = 0; i < n; ++i)
+    if ((s = answer(c, qs[i], op, &out[i])) != BBP_OK) return s;
   return BBP_OK;
 }
 
@@ -682,10 +1406,12 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     if (v < 1 || v > 128 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "chi_env must be an integer in [1,128]");
     c->chi_env = (int)v;
+    c->obs.clear();
   } else if (k == "n_fit") {
     if (v < 1 || v > 64 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "n_fit must be an integer in [1,64]");
     c->n_fit = (int)v;
+    c->obs.clear();
   } else if (k == "seed") {
     if (v < 0 || v != std::floor(v) || v > 9007199254740992.0)
       return c->fail(BBP_EINVAL, "seed must be a non-negative integer");
@@ -776,10 +1502,16 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
     c->groups[gid[key]]->ids.push_back((int)i);
   }
   for (auto &g : c->groups) {
-    if ((s = alloc_group(c, *g)) != BBP_OK) return s;
+    // random-state slot bases: message e, column c -> (1<<40)|(e<<8)|c
+    std::vector<uint64_t> slots(g->ids.size());
+    for (size_t i = 0; i < slots.size(); ++i)
+      slots[i] = (1ull << 40) | ((uint64_t)g->ids[i] << 8);
+    if ((s = alloc_batch(c, *g, (int)g->ids.size(), c->K, slots)) != BBP_OK)
+      return s;
     if ((s = upload_rotated(c, *g)) != BBP_OK) return s;
   }
   if ((s = init_messages(c)) != BBP_OK) return s;
+  c->obs.clear();
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return c->hip_fail(e, "set_tensors");
   c->tensors_set = true;
@@ -871,6 +1603,7 @@ bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n) {
   if (e != hipSuccess) return c->hip_fail(e, "upload messages");
   for (size_t i = 0; i < c->msgs.size(); ++i) c->msgs[i].bonds = bonds[i];
   for (auto &g : c->groups) std::fill(g->have.begin(), g->have.end(), 0);
+  c->obs.clear();
   return BBP_OK;
 }
 
@@ -881,25 +1614,93 @@ bbp_status bbp_stats(bbp_ctx *c, int32_t *n_messages, double *sweep_flops) {
   return BBP_OK;
 }
 
-bbp_status bbp_expect_site(bbp_ctx *c, int32_t, int32_t, const double *,
-                           double *) {
-  return c ? c->fail(BBP_ESTATE, "observables not available") : BBP_EINVAL;
+bbp_status bbp_expect_site(bbp_ctx *c, int32_t x, int32_t y, const double *op,
+                           double *out) {
+  return expect_many(c, 1, &x, &y, nullptr, nullptr, false, op, out);
 }
-bbp_status bbp_expect_bond(bbp_ctx *c, int32_t, int32_t, int32_t, int32_t,
-                           const double *, double *) {
-  return c ? c->fail(BBP_ESTATE, "observables not available") : BBP_EINVAL;
+
+bbp_status bbp_expect_bond(bbp_ctx *c, int32_t x0, int32_t y0, int32_t x1,
+                           int32_t y1, const double *op, double *out) {
+  return expect_many(c, 1, &x0, &y0, &x1, &y1, true, op, out);
 }
-bbp_status bbp_expect_sites(bbp_ctx *c, int32_t, const int32_t *,
-                            const int32_t *, const double *, double *) {
-  return c ? c->fail(BBP_ESTATE, "observables not available") : BBP_EINVAL;
+
+bbp_status bbp_expect_sites(bbp_ctx *c, int32_t n, const int32_t *xs,
+                            const int32_t *ys, const double *op, double *out) {
+  return expect_many(c, n, xs, ys, nullptr, nullptr, false, op, out);
 }
-bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t, const int32_t *,
-                            const int32_t *, const int32_t *, const int32_t *,
-                            const double *, double *) {
-  return c ? c->fail(BBP_ESTATE, "observables not available") : BBP_EINVAL;
+
+bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
+                            const int32_t *y0, const int32_t *x1,
+                            const int32_t *y1, const double *op, double *out) {
+  return expect_many(c, n, x0, y0, x1, y1, true, op, out);
 }
-bbp_status bbp_log_norm(bbp_ctx *c, double *, int32_t *) {
-  return c ? c->fail(BBP_ESTATE, "observables not available") : BBP_EINVAL;
+
+bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {
+  if (!c || !log_abs) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (c->chi_env < c->chi)
+    return c->fail(BBP_EINVAL, "chi_env must be at least chi");
+  // Z_A of every block: line 0 of its row frame
+  std::vector<Query> qs;
+  for (int bj = 0; bj < c->gy; ++bj)
+    for (int bi = 0; bi < c->gx; ++bi)
+      qs.push_back(Query{0, bi, bj, true, 0, 0, false});
+  bbp_status s = ensure_regions(c, qs);
+  if (s != BBP_OK) return s;
+  double total = 0.0;
+  int sg = 1;
+  for (const Query &q : qs) {
+    const RegionResult &res = c->obs.at(std::make_tuple(0, q.bi, q.bj));
+    const double z = res.zrow[0];
+    if (!(std::isfinite(z) && z != 0.0))
+      return c->fail(BBP_ENUMERIC, "vanishing block contraction");
+    total += std::log(std::fabs(z)) + res.lsrow[0];
+    if (z < 0) sg = -sg;
+  }
+  // Z_AB = <m_{A->B}, m_{B->A}> over edges (messages to the right / down)
+  std::vector<int> ea, eb;
+  for (size_t i = 0; i < c->msgs.size(); ++i) {
+    const Message &m = c->msgs[i];
+    if (m.dir != 'R' && m.dir != 'D') continue;
+    int ni, nj;
+    c->neighbour(m.bi, m.bj, m.dir, &ni, &nj);
+    ea.push_back((int)i);
+    eb.push_back(c->msg_id(ni, nj, opposite(m.dir)));
+  }
+  const size_t per = (size_t)c->Lmax * c->S;
+  double *cur = c->msgbuf[c->cur].d();
+  std::map<int, std::vector<int>> by_len;
+  for (size_t t = 0; t < ea.size(); ++t) by_len[c->msgs[ea[t]].n].push_back((int)t);
+  for (auto &kv : by_len) {
+    std::vector<const double *> pa, pb;
+    for (int t : kv.second) {
+      pa.push_back(cur + (size_t)ea[t] * per);
+      pb.push_back(cur + (size_t)eb[t] * per);
+    }
+    std::vector<double> ov(pa.size());
+    hipError_t e = hipMemcpy(c->ovA.p, pa.data(), 8 * pa.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->ovB.p, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = launch_overlap((int)pa.size(), c->K, c->P, kv.first,
+                         (const double *const *)c->ovA.p,
+                         (const double *const *)c->ovB.p, c->ovE.d(), c->ovU.d(),
+                         c->ovOut.d(), c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ov.data(), c->ovOut.p, 8 * ov.size(), hipMemcpyDeviceToHost,
+                         c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->hip_fail(e, "edge overlaps");
+    for (double z : ov) {
+      if (!(std::isfinite(z) && z != 0.0))
+        return c->fail(BBP_ENUMERIC, "vanishing edge overlap");
+      total -= std::log(std::fabs(z));
+      if (z < 0) sg = -sg;
+    }
+  }
+  *log_abs = total;
+  if (sign) *sign = sg;
+  return BBP_OK;
 }
 
 const char *bbp_last_error(const bbp_ctx *c) {

@@ -43,7 +43,7 @@ struct FitBatch {
   double *acan = nullptr;   // [items][H][W][d*D^4]  rotated site tensors (ket)
   double *abra = nullptr;   // bra tensors if different from acan (or null)
   double *rbuf = nullptr;   // [items][K*K]
-  double *nu = nullptr;     // [items] norm of the last fit
+  double *nu = nullptr;     // [items][W] norm of each column's fit
   int32_t *flag = nullptr;  // [items] per-item active flags
   int32_t *err = nullptr;   // [1] numeric error flag
   FitDims *dims = nullptr;  // [items][W]
@@ -59,11 +59,15 @@ enum VisitMode : int {
   RL_BOT = 3     // right-to-left visit of site N-1 (bottom corner)
 };
 
-// A per-item device pointer: item i uses p + i*stride.
+// A per-item device pointer: item i uses p + i*stride, or, with a pointer
+// table, tab[i] + stride.
 struct Ptr {
   double *p = nullptr;
   size_t stride = 0;
-  __host__ __device__ double *at(int i) const { return p + (size_t)i * stride; }
+  double *const *tab = nullptr;
+  __host__ __device__ double *at(int i) const {
+    return tab ? tab[i] + stride : p + (size_t)i * stride;
+  }
 };
 
 // Offset of site j of column c inside one item's fit-result store.
@@ -99,13 +103,17 @@ hipError_t launch_rand_init(const FitBatch &f, int c, Ptr Ybase,
                             hipStream_t st);
 // Set slot (per item) to the 1x1x1 unit tensor.
 hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st);
-// Normalise the end slot Y0 to unit norm; nu[item] = its norm.
-hipError_t launch_normalize(const FitBatch &f, Ptr Y0, hipStream_t st);
+// Normalise the end slot Y0 to unit norm; nu[item*W + c] = its norm.
+hipError_t launch_normalize(const FitBatch &f, int c, Ptr Y0, hipStream_t st);
 
-// Message gathering / extraction / overlap.
+// Message gathering / extraction / overlap.  Each rotated incoming side
+// (top, right, bottom) is made of up to two message segments (two for the
+// union of two blocks), already listed in rotated order.
 struct GatherSrc {
-  const double *src[3];  // top, right, bottom incoming message (site 0 slot)
-  int32_t rev[3];        // reverse the site order
+  const double *src[3][2];  // site-0 slot of each segment
+  int32_t n[3][2];          // sites per segment (0: unused)
+  int32_t rev[3][2];        // segment read in reverse site order
+  int32_t ksrc;             // bond cap of the source slots
   int32_t pad_;
 };
 hipError_t launch_gather(const FitBatch &f, const GatherSrc *srcs,
@@ -113,6 +121,22 @@ hipError_t launch_gather(const FitBatch &f, const GatherSrc *srcs,
 // Final boundary of column 0 -> message of H sites at dst[item].
 hipError_t launch_extract(const FitBatch &f, double *const *dst,
                           const int32_t *rev, hipStream_t st);
+// Copy of one slot-shaped tensor: mode 0 copy n doubles, 1 transpose an
+// inner site [a][q][b] -> [b][q][a] (bond cap K, P), 2 transpose a K x K end
+// site.
+struct CopyJob {
+  const double *src;
+  double *dst;
+  int64_t n;
+  int32_t mode;
+  int32_t pad_;
+};
+hipError_t launch_copy_jobs(const CopyJob *jobs, int njobs, int K, int P,
+                            hipStream_t st);
+// out[i] = sum_k a_i[k] b_i[k] over n doubles.
+hipError_t launch_dots(int items, const double *const *a,
+                       const double *const *b, size_t n, double *out,
+                       hipStream_t st);
 // out[i] = <a_i | b_i> for items i, each an L-site padded MPS.
 hipError_t launch_overlap(int items, int K, int P, int L, const double *const *a,
                           const double *const *b, double *E, double *U,

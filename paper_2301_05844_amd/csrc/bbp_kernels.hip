@@ -407,8 +407,8 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
     case LR_INNER:
       n1 = dm.bl[j]; s1 = (size_t)P * K; n2 = P; s2 = K; ncol = dm.br[j]; sc = 1;
       break;
-    case RL_INNER:
-      n1 = dm.br[j]; s1 = 1; n2 = P; s2 = K; ncol = dm.bl[j]; sc = (size_t)P * K;
+    case RL_INNER:  // rows (l, yb), l-major, as in the QR of the transpose
+      n1 = P; s1 = K; n2 = dm.br[j]; s2 = 1; ncol = dm.bl[j]; sc = (size_t)P * K;
       break;
     case LR_TOP:
       n1 = dm.p[j]; s1 = K; n2 = 1; s2 = 0; ncol = dm.br[j]; sc = 1;
@@ -570,8 +570,9 @@ __global__ __launch_bounds__(kThreads) void k_copy_flagged(
 }
 
 // Norm of the end slot (K*K doubles) per item; scale to unit norm.
+// nu[it*W] receives the norm (nu already offset to the column).
 __global__ __launch_bounds__(kThreads) void k_normalize(Ptr Y0, int K,
-                                                        double *nu,
+                                                        double *nu, int W,
                                                         int32_t *err) {
   const int it = blockIdx.x;
   double *y = Y0.at(it);
@@ -586,7 +587,7 @@ __global__ __launch_bounds__(kThreads) void k_normalize(Ptr Y0, int K,
   const double nrm = sqrt(red[0] + red[1] + red[2] + red[3]);
   const bool ok = nrm > 0.0 && isfinite(nrm);
   if (threadIdx.x == 0) {
-    nu[it] = nrm;
+    nu[(size_t)it * W] = nrm;
     if (!ok) atomicOr(err, 1);
   }
   if (ok) {
@@ -595,50 +596,57 @@ __global__ __launch_bounds__(kThreads) void k_normalize(Ptr Y0, int K,
   }
 }
 
-// Copy one message site slot [a][q][b], optionally transposed to [b][q][a].
+// Copy one message site [a][q][b] from a slot with bond cap ks to a slot
+// with bond cap kd (kd >= ks), optionally transposed to [b][q][a].  The
+// destination slot is fully written (zero padding included).
 __device__ __forceinline__ void copy_site(const double *src, double *dst,
-                                          int K, int P, bool tr, double scale,
-                                          int tid, int nt) {
-  const size_t S = (size_t)K * P * K;
+                                          int ks, int kd, int P, bool tr,
+                                          double scale, int tid, int nt) {
+  const size_t S = (size_t)kd * P * kd;
   for (size_t i = tid; i < S; i += nt) {
-    if (!tr) {
-      dst[i] = scale * src[i];
-    } else {
-      const int a = (int)(i / ((size_t)P * K));
-      const int rem = (int)(i - (size_t)a * P * K);
-      const int qq = rem / K, b = rem - qq * K;
-      dst[i] = scale * src[((size_t)b * P + qq) * K + a];
-    }
+    const int a = (int)(i / ((size_t)P * kd));
+    const int rem = (int)(i - (size_t)a * P * kd);
+    const int qq = rem / kd, b = rem - qq * kd;
+    double v = 0.0;
+    if (a < ks && b < ks)
+      v = tr ? src[((size_t)b * P + qq) * ks + a] : src[((size_t)a * P + qq) * ks + b];
+    dst[i] = scale * v;
   }
 }
 
-// blockIdx.x: site (0..W-1 for top/bottom, 0..H+1 for the boundary),
-// blockIdx.y: which (0 top, 1 boundary, 2 bottom), blockIdx.z: item.
+// blockIdx.x: site, blockIdx.y: which (0 top, 1 boundary, 2 bottom),
+// blockIdx.z: item.
 __global__ __launch_bounds__(kThreads) void k_gather(FitBatch f,
                                                      const GatherSrc *srcs) {
   const int site = blockIdx.x, which = blockIdx.y, it = blockIdx.z;
-  const GatherSrc g = srcs[it];
+  const GatherSrc &g = srcs[it];
   const int K = f.K, P = f.P;
   const size_t S = f.S;
+  int k, i;
+  double *dst;
   if (which == 1) {
     if (site >= f.N) return;
-    double *dst = f.xin + ((size_t)it * f.N + site) * S;
+    dst = f.xin + ((size_t)it * f.N + site) * S;
     if (site == 0 || site == f.N - 1) {
-      for (size_t i = threadIdx.x; i < S; i += kThreads)
-        dst[i] = (i == 0) ? 1.0 : 0.0;
+      for (size_t t = threadIdx.x; t < S; t += kThreads)
+        dst[t] = (t == 0) ? 1.0 : 0.0;
       return;
     }
-    const int L = f.H, i = site - 1;
-    const int src_site = g.rev[1] ? L - 1 - i : i;
-    copy_site(g.src[1] + (size_t)src_site * S, dst, K, P, g.rev[1], 1.0,
-              threadIdx.x, kThreads);
-    return;
+    k = 1;
+    i = site - 1;
+  } else {
+    if (site >= f.W) return;
+    k = which == 0 ? 0 : 2;
+    i = site;
+    dst = (which == 0 ? f.mt : f.mb) + ((size_t)it * f.W + site) * S;
   }
-  if (site >= f.W) return;
-  const int k = which == 0 ? 0 : 2;
-  double *dst = (which == 0 ? f.mt : f.mb) + ((size_t)it * f.W + site) * S;
-  const int src_site = g.rev[k] ? f.W - 1 - site : site;
-  copy_site(g.src[k] + (size_t)src_site * S, dst, K, P, g.rev[k], 1.0,
+  const int seg = i < g.n[k][0] ? 0 : 1;
+  const int loc = seg ? i - g.n[k][0] : i;
+  const int n = g.n[k][seg];
+  const bool rev = g.rev[k][seg] != 0;
+  const int src_site = rev ? n - 1 - loc : loc;
+  const size_t Ss = (size_t)g.ksrc * P * g.ksrc;
+  copy_site(g.src[k][seg] + (size_t)src_site * Ss, dst, g.ksrc, K, P, rev, 1.0,
             threadIdx.x, kThreads);
 }
 
@@ -653,8 +661,45 @@ __global__ __launch_bounds__(kThreads) void k_extract(FitBatch f,
   if (i == 0) scale *= Y[0];                              // site 0 scalar
   if (i == L - 1) scale *= Y[(size_t)(f.N - 1) * f.S];    // site N-1 scalar
   const int out = rev[it] ? L - 1 - i : i;
-  copy_site(Y + (size_t)(i + 1) * f.S, dst[it] + (size_t)out * f.S, f.K, f.P,
-            rev[it] != 0, scale, threadIdx.x, kThreads);
+  copy_site(Y + (size_t)(i + 1) * f.S, dst[it] + (size_t)out * f.S, f.K, f.K,
+            f.P, rev[it] != 0, scale, threadIdx.x, kThreads);
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_jobs(const CopyJob *jobs,
+                                                        int K, int P) {
+  const CopyJob j = jobs[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < j.n;
+       i += (int64_t)gridDim.x * kThreads) {
+    int64_t from = i;
+    if (j.mode == 1) {
+      const int64_t a = i / ((int64_t)P * K), rem = i - a * P * K;
+      const int64_t qq = rem / K, b = rem - qq * K;
+      from = (b * P + qq) * K + a;
+    } else if (j.mode == 2) {
+      if (i >= (int64_t)K * K) {
+        j.dst[i] = 0.0;
+        continue;
+      }
+      const int64_t a = i / K, b = i - a * K;
+      from = b * K + a;
+    }
+    j.dst[i] = j.src[from];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dots(const double *const *a,
+                                                   const double *const *b,
+                                                   size_t n, double *out) {
+  const int it = blockIdx.x;
+  const double *x = a[it], *y = b[it];
+  double part = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += kThreads) part += x[i] * y[i];
+  part = wave_sum(part);
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) out[it] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ void k_ov_init(double *E, int K, int items) {
@@ -771,9 +816,9 @@ hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(const FitBatch &f, Ptr Y0, hipStream_t st) {
+hipError_t launch_normalize(const FitBatch &f, int c, Ptr Y0, hipStream_t st) {
   hipLaunchKernelGGL(k_normalize, dim3(f.items), dim3(kThreads), 0, st, Y0,
-                     f.K, f.nu, f.err);
+                     f.K, f.nu + c, f.W, f.err);
   return hipGetLastError();
 }
 
@@ -789,6 +834,22 @@ hipError_t launch_extract(const FitBatch &f, double *const *dst,
                           const int32_t *rev, hipStream_t st) {
   hipLaunchKernelGGL(k_extract, dim3(f.H, f.items), dim3(kThreads), 0, st, f,
                      dst, rev);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_jobs(const CopyJob *jobs, int njobs, int K, int P,
+                            hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_jobs, dim3(8, njobs), dim3(kThreads), 0, st, jobs,
+                     K, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(int items, const double *const *a,
+                       const double *const *b, size_t n, double *out,
+                       hipStream_t st) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dots, dim3(items), dim3(kThreads), 0, st, a, b, n, out);
   return hipGetLastError();
 }
 
