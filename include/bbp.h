@@ -77,6 +77,7 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *   "chi_env"  boundary bond for observables (default 2*D^2+10, Sec. II)
  *   "n_fit"    full fit sweeps per column absorption (default 2, App. A)
  *   "seed"     seed of the counter-based fit initial states (default 0)
+ *   "timing"   1: record per-kernel-class launch times (any time; resets)
  * Unknown keys or out-of-range values: BBP_EINVAL.
  */
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
@@ -160,6 +161,25 @@ bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n);
 /* Number of directed messages and the floating-point operations of the
  * last sweep counted on the split-layer schedule (fit contractions only). */
 bbp_status bbp_stats(bbp_ctx *c, int32_t *n_messages, double *sweep_flops);
+
+/*
+ * Launch statistics of kernel class cls (0 .. 8) collected while the
+ * "timing" option is 1, summed over the process since the last reset: the
+ * class name (static string), number of launches, total duration in ms
+ * measured with HIP events on the stream the kernels were launched on, and
+ * the algorithmic floating-point operations and HBM bytes (operands read
+ * plus results written, once each) of those launches.  Synchronises the
+ * recorded events.  Classes: fit_visit (the fused contractions of one fit
+ * visit, App. A Eq. (update), on MFMA), fit_T1, fit_ket, fit_bra, fit_local
+ * (the same contractions as separate kernels, used when the fused tiles do
+ * not fit in LDS), fit_env (environment recursion of App. A), fit_end
+ * (end-site contractions), qr (Householder QR/LQ), other.  Errors:
+ * BBP_EINVAL for cls out of range.
+ */
+bbp_status bbp_kernel_stats(bbp_ctx *c, int32_t cls, const char **name,
+                            int64_t *launches, double *ms, double *flops,
+                            double *bytes);
+bbp_status bbp_kernel_stats_reset(bbp_ctx *c);
 
 const char *bbp_last_error(const bbp_ctx *c);
 void bbp_destroy(bbp_ctx *c);

@@ -11,6 +11,14 @@ import os
 
 import numpy as np
 
+try:
+    # torch (device memory, streams) ships its own HIP runtime; loading it
+    # before libbbp makes the library bind to that same runtime, so one HIP
+    # runtime serves both in this process.
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbbp.so")
 
@@ -18,7 +26,8 @@ EXPORTS = (
     "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_tensors",
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
     "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
-    "bbp_set_messages", "bbp_stats", "bbp_last_error", "bbp_destroy",
+    "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
+    "bbp_kernel_stats_reset", "bbp_last_error", "bbp_destroy",
 )
 
 STATUS = {0: "BBP_OK", 1: "BBP_EINVAL", 2: "BBP_ENOMEM", 3: "BBP_EDEVICE",
@@ -54,6 +63,9 @@ def _load():
         "bbp_get_messages": [P, dp, c_size, ctypes.POINTER(c_size)],
         "bbp_set_messages": [P, dp, c_size],
         "bbp_stats": [P, ip, dp],
+        "bbp_kernel_stats": [P, c_int, ctypes.POINTER(ctypes.c_char_p),
+                             ctypes.POINTER(ctypes.c_int64), dp, dp, dp],
+        "bbp_kernel_stats_reset": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -204,6 +216,24 @@ class BlockBP:
         f = ctypes.c_double()
         self._check(_lib.bbp_stats(self._ctx, ctypes.byref(n), ctypes.byref(f)))
         return n.value, f.value
+
+    def kernel_stats(self):
+        """Per-kernel-class launch statistics (``timing`` option): list of
+        dicts with name, launches, ms, flops, bytes."""
+        out = []
+        for i in range(9):
+            name = ctypes.c_char_p()
+            n = ctypes.c_int64()
+            ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            self._check(_lib.bbp_kernel_stats(self._ctx, i, ctypes.byref(name),
+                                              ctypes.byref(n), ctypes.byref(ms),
+                                              ctypes.byref(fl), ctypes.byref(by)))
+            out.append(dict(name=name.value.decode(), launches=n.value,
+                            ms=ms.value, flops=fl.value, bytes=by.value))
+        return out
+
+    def kernel_stats_reset(self):
+        self._check(_lib.bbp_kernel_stats_reset(self._ctx))
 
     def close(self):
         if self._ctx:

@@ -485,8 +485,7 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo) {
             if (e == hipSuccess) e = launch_qr(f, col, 0, LR_TOP, Ys(0), false, false, st);
             if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
           } else {
-            e = launch_inner_chain(f, col, j, false, Xs(j), Le(j), st);
-            if (e == hipSuccess) e = launch_inner_local(f, false, Re(j), Ys(j), st);
+            e = launch_inner_visit(f, col, j, false, Xs(j), Le(j), Re(j), Ys(j), st);
             if (e == hipSuccess) e = launch_qr(f, col, j, LR_INNER, Ys(j), false, false, st);
             if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
           }
@@ -499,8 +498,7 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo) {
             if (e == hipSuccess) e = launch_qr(f, col, N - 1, RL_BOT, Ys(N - 1), false, false, st);
             if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
           } else {
-            e = launch_inner_chain(f, col, j, true, Xs(j), Re(j), st);
-            if (e == hipSuccess) e = launch_inner_local(f, true, Le(j), Ys(j), st);
+            e = launch_inner_visit(f, col, j, true, Xs(j), Re(j), Le(j), Ys(j), st);
             if (e == hipSuccess) e = launch_qr(f, col, j, RL_INNER, Ys(j), false, false, st);
             if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
           }
@@ -771,7 +769,8 @@ static const double *region_site(const bbp_ctx *c, const RegionSpec &r, int y,
 
 static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   hipStream_t st = c->stream;
-  hipError_t e;
+  hipError_t e = hipMemsetAsync(c->errflag.p, 0, 4, st);
+  if (e != hipSuccess) return c->hip_fail(e, "memset");
   const int Kenv = c->chi_env, P = c->P, d = c->d, d2 = d * d;
   const size_t Senv = (size_t)Kenv * P * Kenv;
   const size_t asite = (size_t)d * P * P;
@@ -1395,7 +1394,7 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   if (!c || !key) return BBP_EINVAL;
   std::string k(key);
-  const bool late_ok = (k == "n_fit" || k == "chi_env");
+  const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing");
   if (c->tensors_set && !late_ok)
     return c->fail(BBP_ESTATE, "option must be set before bbp_set_tensors");
   if (!std::isfinite(v)) return c->fail(BBP_EINVAL, "non-finite option value");
@@ -1412,6 +1411,9 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
       return c->fail(BBP_EINVAL, "n_fit must be an integer in [1,64]");
     c->n_fit = (int)v;
     c->obs.clear();
+  } else if (k == "timing") {
+    bbp::timing_enable(v != 0.0);
+    bbp::timing_reset();
   } else if (k == "seed") {
     if (v < 0 || v != std::floor(v) || v > 9007199254740992.0)
       return c->fail(BBP_EINVAL, "seed must be a non-negative integer");
@@ -1474,7 +1476,8 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       c->ovOut.alloc(nm * 8) != hipSuccess || c->ovA.alloc(nm * 8) != hipSuccess ||
       c->ovB.alloc(nm * 8) != hipSuccess || c->errflag.alloc(64) != hipSuccess)
     return c->fail(BBP_ENOMEM, "device allocation failed");
-  if (hipMemset(c->msgbuf[0].p, 0, c->msgbuf[0].bytes) != hipSuccess ||
+  if (hipMemset(c->errflag.p, 0, c->errflag.bytes) != hipSuccess ||
+      hipMemset(c->msgbuf[0].p, 0, c->msgbuf[0].bytes) != hipSuccess ||
       hipMemset(c->msgbuf[1].p, 0, c->msgbuf[1].bytes) != hipSuccess)
     return c->fail(BBP_EDEVICE, "clear message buffers");
   {
@@ -1700,6 +1703,25 @@ bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {
   }
   *log_abs = total;
   if (sign) *sign = sg;
+  return BBP_OK;
+}
+
+bbp_status bbp_kernel_stats(bbp_ctx *c, int32_t cls, const char **name,
+                            int64_t *launches, double *ms, double *flops,
+                            double *bytes) {
+  if (!c) return BBP_EINVAL;
+  if (cls < 0 || cls >= bbp::KC_COUNT)
+    return c->fail(BBP_EINVAL, "kernel class out of range");
+  long long n = 0;
+  hipError_t e = bbp::timing_query(cls, name, &n, ms, flops, bytes);
+  if (e != hipSuccess) return c->hip_fail(e, "kernel timing");
+  if (launches) *launches = n;
+  return BBP_OK;
+}
+
+bbp_status bbp_kernel_stats_reset(bbp_ctx *c) {
+  if (!c) return BBP_EINVAL;
+  bbp::timing_reset();
   return BBP_OK;
 }
 

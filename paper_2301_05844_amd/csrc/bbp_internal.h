@@ -76,9 +76,15 @@ inline size_t slot_store(const FitBatch &f, int c, int j) {
 }
 
 // Launchers (bbp_kernels.hip).  All enqueue on `st`.
-// Inner-site chain T1 -> T2 -> T3 (split layers) for site j of column c.
+// Inner-site chain T1 -> T2 -> T3 (split layers) for site j of column c
+// (fused MFMA kernel when its tiles fit in LDS, else the generic chain).
 hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl,
                               Ptr X, Ptr F, hipStream_t st);
+hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
+                                      Ptr X, Ptr F, hipStream_t st);
+// Chain plus the local update Yt = T3 . G written into Y.
+hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
+                              Ptr F, Ptr G, Ptr Y, hipStream_t st);
 // Yt = T3 . G  (local update), written into Y.
 hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
                               hipStream_t st);
@@ -141,5 +147,27 @@ hipError_t launch_dots(int items, const double *const *a,
 hipError_t launch_overlap(int items, int K, int P, int L, const double *const *a,
                           const double *const *b, double *E, double *U,
                           double *out, hipStream_t st);
+
+// Per-kernel-class launch timing (process-wide; enabled by the "timing"
+// option).  Each timed launch records a pair of HIP events on its stream and
+// the algorithmic floating-point operations and bytes it processes.
+enum KernelClass : int {
+  KC_VISIT = 0,  // fused F.X -> ket -> bra (-> local update) on MFMA
+  KC_T1 = 1,     // F . X            (generic chain)
+  KC_KET = 2,    // T1 . A ket layer (generic chain)
+  KC_BRA = 3,    // T2 . A bra layer (generic chain)
+  KC_LOCAL = 4,  // T3 . G  local update (generic chain)
+  KC_ENV = 5,    // Y . T3  environment update
+  KC_END = 6,    // end-site contractions
+  KC_QR = 7,     // Householder QR / LQ
+  KC_OTHER = 8,  // gather, extract, normalise, overlaps, copies
+  KC_COUNT = 9
+};
+void timing_enable(bool on);
+bool timing_enabled();
+void timing_reset();
+// Synchronises the recorded events and returns the totals of one class.
+hipError_t timing_query(int cls, const char **name, long long *launches,
+                        double *ms, double *flops, double *bytes);
 
 }  // namespace bbp

@@ -6,9 +6,109 @@
 // bond cap, P = D^2 the fused double-layer leg), so all contractions of a
 // batch have the same shape; zero padding stays exactly zero through every
 // contraction, and the QR works on the true panel only.
+#include <vector>
+
 #include "bbp_internal.h"
 
 namespace bbp {
+
+// ---------------------------------------------------------------------------
+// Launch timing
+// ---------------------------------------------------------------------------
+namespace {
+struct TimedLaunch {
+  int cls;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+struct TimingState {
+  bool on = false;
+  std::vector<TimedLaunch> done;
+  std::vector<hipEvent_t> pool;
+  long long launches[KC_COUNT] = {};
+  double ms[KC_COUNT] = {}, flops[KC_COUNT] = {}, bytes[KC_COUNT] = {};
+};
+TimingState &timing() {
+  static TimingState t;
+  return t;
+}
+hipEvent_t take_event() {
+  TimingState &t = timing();
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+// Folds completed event pairs into the per-class totals.
+hipError_t drain() {
+  TimingState &t = timing();
+  for (TimedLaunch &l : t.done) {
+    hipError_t e = hipEventSynchronize(l.b);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, l.a, l.b);
+    if (e != hipSuccess) return e;
+    t.launches[l.cls] += 1;
+    t.ms[l.cls] += ms;
+    t.flops[l.cls] += l.flops;
+    t.bytes[l.cls] += l.bytes;
+    t.pool.push_back(l.a);
+    t.pool.push_back(l.b);
+  }
+  t.done.clear();
+  return hipSuccess;
+}
+// Brackets one launch with events when timing is on.
+struct Span {
+  int cls;
+  hipStream_t st;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  Span(int c, hipStream_t s, double f, double b) : cls(c), st(s), flops(f), bytes(b) {
+    if (!timing().on) return;
+    if (timing().done.size() > 4096) (void)drain();
+    a = take_event();
+    if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+  }
+  ~Span() {
+    if (!a) return;
+    hipEvent_t b = take_event();
+    if (b && hipEventRecord(b, st) == hipSuccess)
+      timing().done.push_back(TimedLaunch{cls, a, b, flops, bytes});
+  }
+};
+const char *kClassNames[KC_COUNT] = {"fit_visit", "fit_T1",  "fit_ket",
+                                     "fit_bra",   "fit_local", "fit_env",
+                                     "fit_end",   "qr",       "other"};
+}  // namespace
+
+void timing_enable(bool on) { timing().on = on; }
+bool timing_enabled() { return timing().on; }
+void timing_reset() {
+  (void)drain();
+  TimingState &t = timing();
+  for (int i = 0; i < KC_COUNT; ++i) {
+    t.launches[i] = 0;
+    t.ms[i] = t.flops[i] = t.bytes[i] = 0.0;
+  }
+}
+hipError_t timing_query(int cls, const char **name, long long *launches,
+                        double *ms, double *flops, double *bytes) {
+  hipError_t e = drain();
+  if (e != hipSuccess) return e;
+  TimingState &t = timing();
+  if (name) *name = kClassNames[cls];
+  if (launches) *launches = t.launches[cls];
+  if (ms) *ms = t.ms[cls];
+  if (flops) *flops = t.flops[cls];
+  if (bytes) *bytes = t.bytes[cls];
+  return hipSuccess;
+}
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -371,6 +471,233 @@ struct OpOv2 {  // E'[a][b] = sum_{b',q} U[b'][q][a] b_i[b'][q][b]
 };
 
 // ---------------------------------------------------------------------------
+// Fused fit visit on FP64 MFMA (v_mfma_f64_16x16x4f64).  One workgroup per
+// (item, tile of TY front bonds yf); it walks all tiles of TX back bonds xb
+// and, per tile, runs four LDS-resident contractions:
+//   (a) T1[yf,wf][a,xb]      = sum_xf F[yf][wf][xf] X_f[xf][a][xb]
+//   (b) T2[wfb,ab][s,lk,wbk] = sum_{wfk,ak} T1 Aket_f[s][wfk][lk][wbk][ak]  (per pair)
+//   (c) T3[lk,wbk][lb,wbb]   = sum_{s,wfb,ab} T2 Abra_f[s][wfb][lb][wbb][ab] (per pair)
+//   (e) Yt[yf,l][yb]        += sum_{xb,wb} T3 G[yb][wb][xb]
+// T3 goes to HBM once (the environment update reads it); T1 and T2 never do.
+// MFMA operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator register r holds D[4r + l/16][l%16].
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct VisitArgs {
+  int K, P, D, d, TY, TX;
+  int rl, do_local;
+  Ptr F, X, G, Y;
+  const double *aket;
+  size_t aket_stride;
+  const double *abra;
+  size_t abra_stride;
+  double *t3;
+  size_t t3_stride;
+};
+
+constexpr int kVisitThreads = 512;
+constexpr int kVisitWaves = kVisitThreads / 64;
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One batched LDS GEMM: for batch p < nb, C_p[M][N] = A_p[M][Kd] B_p[Kd][N];
+// 16 x 16 output tiles spread over the waves; afn/bfn read operands (zero
+// outside), sfn stores the result tile element.
+template <class AF, class BF, class SF>
+__device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
+                                         BF bfn, SF sfn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+  const int ntiles = nb * tm * tn;
+  for (int t = wave; t < ntiles; t += kVisitWaves) {
+    const int p = t / (tm * tn), r2 = t - p * tm * tn;
+    const int m0 = (r2 / tn) << 4, n0 = (r2 % tn) << 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int am = m0 + lr, bn = n0 + lr;
+    for (int k0 = 0; k0 < Kd; k0 += 4) {
+      const int k = k0 + lq;
+      const double a = (am < M && k < Kd) ? afn(p, am, k) : 0.0;
+      const double b = (bn < N && k < Kd) ? bfn(p, k, bn) : 0.0;
+      acc = mfma16(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + 4 * r + lq, n = n0 + lr;
+      if (m < M && n < N) sfn(p, m, n, acc[r]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
+  extern __shared__ double sm[];
+  const int K = v.K, P = v.P, D = v.D, d = v.d, TY = v.TY, TX = v.TX;
+  const int dP = d * P, P2 = P * P;
+  const int it = blockIdx.y, y0 = blockIdx.x * TY;
+  const int tid = threadIdx.x;
+  double *Fs = sm;                         // [TY*P][K]
+  double *Xs = Fs + (size_t)TY * P * K;    // [K][P*TX]
+  double *T1s = Xs + (size_t)K * P * TX;   // [TY*TX][P][P]
+  double *T2s = T1s + (size_t)TY * TX * P2;     // [TY*TX][P][dP]
+  double *T3s = T2s + (size_t)TY * TX * P * dP; // [TY*TX][P][P]
+  double *Gs = T3s + (size_t)TY * TX * P2;      // [TX*P][K]
+  double *Ak = Gs + (size_t)TX * P * K;         // [d][D][D][D][D] front view
+  double *Ab = Ak + (size_t)d * P2;
+  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
+  const double *ak = v.aket + (size_t)it * v.aket_stride;
+  const double *ab = v.abra + (size_t)it * v.abra_stride;
+  double *T3g = v.t3 + (size_t)it * v.t3_stride;
+  const bool rl = v.rl != 0;
+
+  // front-view site tensors: A_f[s][wf][l][wb][a]; RL swaps the u/d legs
+  for (int i = tid; i < d * P2; i += kVisitThreads) {
+    int t = i;
+    const int a = t % D; t /= D;
+    const int wb = t % D; t /= D;
+    const int l = t % D; t /= D;
+    const int wf = t % D;
+    const int s = t / D;
+    const int u = rl ? wb : wf, dd = rl ? wf : wb;
+    const size_t src = ((((size_t)s * D + u) * D + l) * D + dd) * D + a;
+    Ak[i] = ak[src];
+    Ab[i] = ab[src];
+  }
+  // F rows of this y tile: F[yf][wf][xf]
+  for (int i = tid; i < TY * P * K; i += kVisitThreads) {
+    const int row = i / K, xf = i - row * K;
+    const int yf = y0 + row / P;
+    Fs[i] = yf < K ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
+  }
+  // Yt accumulators: tiles of [(ty,l)][yb], kept in registers
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int Me = TY * P, tme = (Me + 15) >> 4, tne = (K + 15) >> 4;
+  const int ntile_e = tme * tne;
+  constexpr int kMaxE = 4;  // tiles per wave (host keeps ntile_e <= 4 * waves)
+  v4d accE[kMaxE];
+#pragma unroll
+  for (int q = 0; q < kMaxE; ++q) accE[q] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int x0 = 0; x0 < K; x0 += TX) {
+    __syncthreads();  // previous tile's Xs/Gs/T3s consumers are done
+    // X_f[xf][a][xb] for the tile, as Xs[xf][a*TX + tx]
+    for (int i = tid; i < K * P * TX; i += kVisitThreads) {
+      const int xf = i / (P * TX), r = i - xf * P * TX;
+      const int a = r / TX, tx = r - a * TX, xb = x0 + tx;
+      double val = 0.0;
+      if (xb < K)
+        val = rl ? X[((size_t)xb * P + a) * K + xf] : X[((size_t)xf * P + a) * K + xb];
+      Xs[i] = val;
+    }
+    if (v.do_local)
+      // G[yb][wb][xb] as Gs[(tx*P + wb)][yb]
+      for (int i = tid; i < TX * P * K; i += kVisitThreads) {
+        const int row = i / K, yb = i - row * K;
+        const int tx = row / P, wb = row - tx * P, xb = x0 + tx;
+        Gs[i] = xb < K ? G[((size_t)yb * P + wb) * K + xb] : 0.0;
+      }
+    __syncthreads();
+    // (a) T1: rows (ty, wf), cols (a, tx)
+    lds_gemm(
+        1, TY * P, P * TX, K,
+        [&](int, int m, int k) { return Fs[m * K + k]; },
+        [&](int, int k, int n) { return Xs[k * P * TX + n]; },
+        [&](int, int m, int n, double val) {
+          const int ty = m / P, wf = m - ty * P, a = n / TX, tx = n - a * TX;
+          T1s[(ty * TX + tx) * P2 + wf * P + a] = val;
+        });
+    __syncthreads();
+    // (b) ket: per pair, rows (wfb, ab), k (wfk, ak), cols (s, lk, wbk)
+    lds_gemm(
+        TY * TX, P, dP, P,
+        [&](int p, int m, int k) {
+          const int wfb = m / D, abx = m - wfb * D, wfk = k / D, akx = k - wfk * D;
+          return T1s[p * P2 + (wfk * D + wfb) * P + akx * D + abx];
+        },
+        [&](int, int k, int n) {
+          const int wfk = k / D, akx = k - wfk * D;
+          const int s = n / P, r = n - s * P, lk = r / D, wbk = r - lk * D;
+          return Ak[(((s * D + wfk) * D + lk) * D + wbk) * D + akx];
+        },
+        [&](int p, int m, int n, double val) { T2s[(p * P + m) * dP + n] = val; });
+    __syncthreads();
+    // (c) bra: per pair, rows (lk, wbk), k (s, wfb, ab), cols (lb, wbb)
+    lds_gemm(
+        TY * TX, P, P, dP,
+        [&](int p, int m, int k) {
+          const int lk = m / D, wbk = m - lk * D;
+          const int s = k / P, r = k - s * P, wfb = r / D, abx = r - wfb * D;
+          return T2s[(p * P + wfb * D + abx) * dP + s * P + lk * D + wbk];
+        },
+        [&](int, int k, int n) {
+          const int s = k / P, r = k - s * P, wfb = r / D, abx = r - wfb * D;
+          const int lb = n / D, wbb = n - lb * D;
+          return Ab[(((s * D + wfb) * D + lb) * D + wbb) * D + abx];
+        },
+        [&](int p, int m, int n, double val) { T3s[p * P2 + m * P + n] = val; });
+    __syncthreads();
+    // T3 tile to HBM as T3[yf][l][xb][wb]
+    for (int i = tid; i < TY * TX * P2; i += kVisitThreads) {
+      int t = i;
+      const int wb = t % P; t /= P;
+      const int tx = t % TX; t /= TX;
+      const int l = t % P;
+      const int ty = t / P;
+      const int yf = y0 + ty, xb = x0 + tx;
+      if (yf < K && xb < K) {
+        const int lk = l / D, lb = l - lk * D, wbk = wb / D, wbb = wb - wbk * D;
+        T3g[(((size_t)yf * P + l) * K + xb) * P + wb] =
+            T3s[(ty * TX + tx) * P2 + (lk * D + wbk) * P + lb * D + wbb];
+      }
+    }
+    // (e) local update, accumulated over the xb tiles
+    if (v.do_local) {
+      const int Ke = TX * P;
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wave + q * kVisitWaves;
+        if (t >= ntile_e) break;
+        const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
+        const int am = m0 + lr, bn = n0 + lr;
+        const int ty = am / P, l = am - ty * P;
+        const int lk = l / D, lb = l - lk * D;
+        v4d acc = accE[q];
+        for (int k0 = 0; k0 < Ke; k0 += 4) {
+          const int k = k0 + lq;
+          const int tx = k / P, wb = k - tx * P, wbk = wb / D, wbb = wb - wbk * D;
+          const double a = am < Me ? T3s[(ty * TX + tx) * P2 + (lk * D + wbk) * P + lb * D + wbb] : 0.0;
+          const double b = bn < K ? Gs[k * K + bn] : 0.0;
+          acc = mfma16(a, b, acc);
+        }
+        accE[q] = acc;
+      }
+    }
+  }
+  if (v.do_local) {
+    double *Y = v.Y.at(it);
+#pragma unroll
+    for (int q = 0; q < kMaxE; ++q) {
+      const int t = wave + q * kVisitWaves;
+      if (t >= ntile_e) break;
+      const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 4 * r + lq, yb = n0 + lr;
+        const int ty = m / P, l = m - ty * P, yf = y0 + ty;
+        if (m < Me && yb < K && yf < K) {
+          const size_t idx = rl ? ((size_t)yb * P + l) * K + yf
+                                : ((size_t)yf * P + l) * K + yb;
+          Y[idx] = accE[q][r];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Householder QR (LAPACK conventions: dlarfg reflectors, dorg2r formation).
 // One workgroup per item; the true panel (rows r = r1*n2 + r2, columns c at
 // base[r1*s1 + r2*s2 + c*sc]) is copied column-major into LDS (or a global
@@ -725,22 +1052,112 @@ static size_t t2_stride(const FitBatch &f) {
 static size_t a_site(const FitBatch &f) { return (size_t)f.d * f.P * f.P; }
 static size_t a_stride(const FitBatch &f) { return (size_t)f.H * f.W * a_site(f); }
 
+// Tile shape of the fused visit: the largest TY x TX pair set whose LDS
+// footprint fits, or TY = 0 when none does (generic chain then).
+static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
+  const size_t K = f.K, P = f.P, d = f.d;
+  const int cand[][2] = {{2, 8}, {2, 4}, {4, 2}, {2, 2}, {1, 4}, {1, 2}, {1, 1}};
+  for (auto &c : cand) {
+    const size_t ty = c[0], tx = c[1];
+    if ((int)ty > f.K) continue;
+    const size_t n = ty * P * K + K * P * tx + ty * tx * P * P * (2 + d) +
+                     tx * P * K + 2 * d * P * P;
+    const size_t tiles = ((ty * P + 15) / 16) * ((K + 15) / 16);
+    if (n * 8 <= 150 * 1024 && tiles <= 4 * (size_t)kVisitWaves) {
+      *TY = (int)ty;
+      *TX = (int)tx;
+      *bytes = n * 8;
+      return;
+    }
+  }
+  *TY = 0;
+}
+
+static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
+                               Ptr F, Ptr G, Ptr Y, bool do_local, int TY,
+                               int TX, size_t lds, hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_visit,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
+  VisitArgs v;
+  v.K = f.K; v.P = f.P; v.D = f.D; v.d = f.d; v.TY = TY; v.TX = TX;
+  v.rl = rl ? 1 : 0;
+  v.do_local = do_local ? 1 : 0;
+  v.F = F; v.X = X; v.G = G; v.Y = Y;
+  v.aket = f.acan + site_off;
+  v.aket_stride = a_stride(f);
+  v.abra = (f.abra ? f.abra : f.acan) + site_off;
+  v.abra_stride = a_stride(f);
+  v.t3 = f.t3;
+  v.t3_stride = t1_stride(f);
+  const double it = f.items, K = f.K, P = f.P, d = f.d;
+  double flops = it * (2 * K * K * K * P * P + 4 * d * K * K * P * P * P);
+  double bytes = it * 8 * (2 * K * P * K + K * K * P * P + 2 * d * P * P);
+  if (do_local) {
+    flops += it * 2 * K * K * K * P * P;
+    bytes += it * 8 * 2 * K * P * K;
+  }
+  Span sp(KC_VISIT, st, flops, bytes);
+  hipLaunchKernelGGL(k_visit, dim3((f.K + TY - 1) / TY, f.items),
+                     dim3(kVisitThreads), lds, st, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
+                              Ptr F, Ptr G, Ptr Y, hipStream_t st) {
+  int TY, TX;
+  size_t lds;
+  visit_tiles(f, &TY, &TX, &lds);
+  if (TY > 0) return launch_fused(f, c, j, rl, X, F, G, Y, true, TY, TX, lds, st);
+  hipError_t e = launch_inner_chain_generic(f, c, j, rl, X, F, st);
+  if (e != hipSuccess) return e;
+  return launch_inner_local(f, rl, G, Y, st);
+}
+
 hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl, Ptr X,
                               Ptr F, hipStream_t st) {
+  int TY, TX;
+  size_t lds;
+  visit_tiles(f, &TY, &TX, &lds);
+  if (TY > 0)
+    return launch_fused(f, c, j, rl, X, F, Ptr{}, Ptr{}, false, TY, TX, lds, st);
+  return launch_inner_chain_generic(f, c, j, rl, X, F, st);
+}
+
+hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
+                                      Ptr X, Ptr F, hipStream_t st) {
   const Shape s = shape_of(f);
   const size_t t1s = t1_stride(f), t2s = t2_stride(f), t3s = t1s;
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
   const double *Ak = f.acan + site_off;
   const double *Ab = (f.abra ? f.abra : f.acan) + site_off;
+  const double it = f.items, K = f.K, P = f.P, d = f.d;
   OpK1 k1{f.K * f.P, f.P * f.K, f.K, nullptr, s, rl, X, F, f.t1, t1s};
-  hipError_t e = run_gemm<64, 64, 16>(k1, f.items, st);
+  hipError_t e;
+  {
+    Span sp(KC_T1, st, it * 2 * K * P * P * K * K,
+            it * 8 * (2 * K * P * K + K * K * P * P));
+    e = run_gemm<64, 64, 16>(k1, f.items, st);
+  }
   if (e != hipSuccess) return e;
   OpK2 k2{f.K * f.P * f.K, f.d * f.P, f.P, nullptr, s, rl, f.t1, t1s, Ak,
           a_stride(f), f.t2, t2s};
-  e = run_gemm<128, 32, 16>(k2, f.items, st);
+  {
+    Span sp(KC_KET, st, it * 2 * K * P * K * d * P * P,
+            it * 8 * (K * K * P * P + d * P * P + d * K * K * P * P));
+    e = run_gemm<128, 32, 16>(k2, f.items, st);
+  }
   if (e != hipSuccess) return e;
   OpK3 k3{f.K * f.K * f.P, f.P, f.d * f.P, nullptr, s, rl, f.t2, t2s, Ab,
           a_stride(f), f.t3, t3s};
+  Span sp(KC_BRA, st, it * 2 * K * K * P * P * d * P,
+          it * 8 * (d * K * K * P * P + d * P * P + K * K * P * P));
   return run_gemm<256, 16, 16>(k3, f.items, st);
 }
 
@@ -748,6 +1165,9 @@ hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
                               hipStream_t st) {
   OpK4 k4{f.K * f.P, f.K, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
           t1_stride(f), G, Y};
+  const double it = f.items, K = f.K, P = f.P;
+  Span sp(KC_LOCAL, st, it * 2 * K * P * K * K * P,
+          it * 8 * (K * K * P * P + 2 * K * P * K));
   return run_gemm<64, 32, 16>(k4, f.items, st);
 }
 
@@ -755,6 +1175,9 @@ hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
                             hipStream_t st) {
   OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
           t1_stride(f), Y, envOut};
+  const double it = f.items, K = f.K, P = f.P;
+  Span sp(KC_ENV, st, it * 2 * K * K * P * K * P,
+          it * 8 * (K * K * P * P + 2 * K * P * K));
   return run_gemm<32, 64, 16>(k5, f.items, st);
 }
 
@@ -762,6 +1185,8 @@ hipError_t launch_end_chain(const FitBatch &f, bool rl, Ptr Mend, Ptr Xe,
                             hipStream_t st) {
   OpE1 e1{f.K * f.P, f.K, f.K, nullptr, shape_of(f), rl, Mend, Xe, f.t3,
           t1_stride(f)};
+  const double it = f.items, K = f.K, P = f.P;
+  Span sp(KC_END, st, it * 2 * K * P * K * K, it * 8 * (2 * K * P * K + K * K));
   return run_gemm<64, 32, 16>(e1, f.items, st);
 }
 
@@ -769,6 +1194,8 @@ hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
                             hipStream_t st) {
   OpE2 e2{f.K, f.K, f.P * f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
           G, Ye};
+  const double it = f.items, K = f.K, P = f.P;
+  Span sp(KC_END, st, it * 2 * K * K * P * K, it * 8 * (2 * K * P * K + K * K));
   return run_gemm<32, 32, 16>(e2, f.items, st);
 }
 
@@ -776,6 +1203,8 @@ hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
                           hipStream_t st) {
   OpE3 e3{f.K, f.P * f.K, f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
           Ye, envOut};
+  const double it = f.items, K = f.K, P = f.P;
+  Span sp(KC_END, st, it * 2 * K * P * K * K, it * 8 * (2 * K * P * K + K * K));
   return run_gemm<32, 64, 16>(e3, f.items, st);
 }
 
@@ -784,6 +1213,9 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
   QrArgs q{f.dims, f.W, c, j, mode, f.K, f.P, Y, f.rbuf, f.t1, t1_stride(f),
            only_flagged ? f.flag : nullptr, want_r ? 1 : 0};
   const size_t panel = (size_t)f.K * f.P * f.K;  // upper bound of m*n
+  const double m = (double)f.K * f.P, n = f.K;
+  Span sp(KC_QR, st, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
+          f.items * 16.0 * m * n);
   if (panel <= (size_t)kQrLds)
     hipLaunchKernelGGL(k_qr<true>, dim3(f.items), dim3(kThreads), 0, st, q);
   else

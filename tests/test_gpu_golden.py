@@ -1,0 +1,81 @@
+"""Full-size parity against stored oracle values (tests/golden/*.json,
+written by tests/golden/make_golden.py from the FP64 oracle only).
+
+16x16 open lattice, D=4, 4x4 blocks, chi=32 and the infinite lattice with a
+2x2 unit cell, D=4, 4x4 block, chi=32: the same number of sweeps as the
+oracle needed to bring the residual below 1e-10, then every observable
+within 1e-10 absolute and the log-norm within 1e-10 relative.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from bbp_inputs import (CONFIGS, op_heis, op_sx, op_sz, op_szsz, peps_finite,
+                        peps_infinite)
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-10
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"{name}_seed0.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _check_residuals(gpu, ref):
+    # residual = 2 - 2|<m_new, m_old>| with the overlap near 1: its rounding
+    # floor is ~1e-15 absolute, hence the absolute term
+    for k, (a, b) in enumerate(zip(gpu, ref)):
+        print(f"sweep {k + 1}: gpu {a:.6e} oracle {b:.6e}", flush=True)
+        assert abs(a - b) <= 1e-6 * b + 1e-14, (k, a, b)
+
+
+def test_obc16x16_D4_chi32_matches_oracle():
+    from paper_2301_05844_amd import bbp
+    g = _golden("obc16x16_D4_b4_chi32")
+    cfg = CONFIGS["obc16x16_D4_b4_chi32"]
+    A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=g["seed"])
+    ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
+                      D=cfg["D"], chi=cfg["chi"])
+    ctx.set_tensors(A)
+    res = [ctx.sweep(1) for _ in range(g["sweeps"])]
+    _check_residuals(res, g["residuals"])
+    assert res[-1] < 1e-10
+    sites = np.array(g["sites"], dtype=np.int32)
+    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+    err_sz = np.abs(sz - np.array(g["sz"])).max()
+    ss = ctx.expect_bonds(g["bonds"], op_heis())
+    err_ss = np.abs(ss - np.array(g["ss"])).max()
+    lz, sign = ctx.log_norm()
+    print(f"max |d sz| {err_sz:.2e}  max |d SS| {err_ss:.2e}  "
+          f"log-norm {lz:.12f} vs {g['log_norm']:.12f}", flush=True)
+    assert err_sz < TOL and err_ss < TOL
+    assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
+    assert sign == g["log_norm_sign"]
+
+
+def test_inf2x2_D4_chi32_matches_oracle():
+    from paper_2301_05844_amd import bbp
+    g = _golden("inf2x2_D4_b4_chi32")
+    cfg = CONFIGS["inf2x2_D4_b4_chi32"]
+    A = peps_infinite(cfg["ucx"], cfg["ucy"], cfg["D"], seed=g["seed"])
+    ctx = bbp.BlockBP(D=cfg["D"], chi=cfg["chi"], bx=cfg["bx"], by=cfg["by"],
+                      infinite=True, ucx=cfg["ucx"], ucy=cfg["ucy"])
+    ctx.set_tensors(A)
+    res = [ctx.sweep(1) for _ in range(g["sweeps"])]
+    _check_residuals(res, g["residuals"])
+    assert res[-1] < 1e-10
+    for i, (x, y) in enumerate(g["sites"]):
+        assert abs(ctx.expect_site(x, y, op_sz()) - g["sz"][i]) < TOL
+        assert abs(ctx.expect_site(x, y, op_sx()) - g["sx"][i]) < TOL
+    for i, b in enumerate(g["bonds"]):
+        assert abs(ctx.expect_bond(*b, op_szsz()) - g["szsz"][i]) < TOL
+    lz, _ = ctx.log_norm()
+    assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
