@@ -278,8 +278,15 @@ static bbp_status ensure_device(bbp_ctx *c) {
   return BBP_OK;
 }
 
+// Buffers a batch needs (bit mask for alloc_batch).
+enum : unsigned {
+  NEED_FIT = 1u,      // store, xin, mt, mb, lenv, renv, tmp, acan, rbuf, nu
+  NEED_SCRATCH = 2u,  // t3, and t1/t2 when the generic chain or QR needs them
+};
+
 static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
-                              const std::vector<uint64_t> &slots) {
+                              const std::vector<uint64_t> &slots,
+                              unsigned need = NEED_FIT | NEED_SCRATCH) {
   FitBatch &f = g.fb;
   f.items = items;
   f.K = bond_cap;
@@ -292,32 +299,42 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.S = (size_t)bond_cap * c->P * bond_cap;
   f.seed = c->seed;
   const size_t it = f.items, S = f.S, K = f.K, P = f.P;
+  const bool fused = visit_fused_fits(f);
+  const bool fit = (need & NEED_FIT) != 0, scr = (need & NEED_SCRATCH) != 0;
   struct Req {
     double **dst;
     size_t n;
+    bool zero;  // cleared: zero padding of MPS slots is relied upon
   };
   std::vector<Req> reqs = {
-      {&f.store, it * f.W * f.N * S},
-      {&f.xin, it * f.N * S},
-      {&f.mt, it * f.W * S},
-      {&f.mb, it * f.W * S},
-      {&f.lenv, it * f.N * S},
-      {&f.renv, it * f.N * S},
-      {&f.t1, it * K * P * P * K},
-      {&f.t2, it * (size_t)f.d * K * K * P * P},
-      {&f.t3, it * K * P * P * K},
-      {&f.tmp, it * S},
-      {&f.acan, it * f.H * f.W * (size_t)f.d * P * P},
-      {&f.rbuf, it * K * K},
-      {&f.nu, it * f.W},
+      {&f.store, fit ? it * f.W * f.N * S : 0, true},
+      {&f.xin, fit ? it * f.N * S : 0, true},
+      {&f.mt, fit ? it * f.W * S : 0, true},
+      {&f.mb, fit ? it * f.W * S : 0, true},
+      {&f.lenv, fit ? it * f.N * S : 0, true},
+      {&f.renv, fit ? it * f.N * S : 0, true},
+      {&f.t1, scr && (!fused || qr_needs_scratch(f)) ? it * K * P * P * K : 0,
+       false},
+      {&f.t2, scr && !fused ? it * (size_t)f.d * K * K * P * P : 0, false},
+      {&f.t3, scr ? it * K * P * P * K : 0, false},
+      {&f.tmp, fit ? it * S : 0, false},
+      {&f.acan, fit ? it * f.H * f.W * (size_t)f.d * P * P : 0, true},
+      {&f.rbuf, fit ? it * K * K : 0, false},
+      {&f.nu, fit ? it * f.W : 0, true},
   };
+  g.bufs.clear();
   g.bufs.resize(reqs.size() + 4);
+  hipError_t e;
   for (size_t i = 0; i < reqs.size(); ++i) {
-    hipError_t e = g.bufs[i].alloc(std::max<size_t>(reqs[i].n, 1) * 8);
+    *reqs[i].dst = nullptr;
+    if (reqs[i].n == 0) continue;
+    e = g.bufs[i].alloc(reqs[i].n * 8);
     if (e != hipSuccess) return c->fail(BBP_ENOMEM, "device allocation failed");
     *reqs[i].dst = g.bufs[i].d();
-    e = hipMemsetAsync(g.bufs[i].p, 0, g.bufs[i].bytes, c->stream);
-    if (e != hipSuccess) return c->hip_fail(e, "clear buffers");
+    if (reqs[i].zero) {
+      e = hipMemsetAsync(g.bufs[i].p, 0, g.bufs[i].bytes, c->stream);
+      if (e != hipSuccess) return c->hip_fail(e, "clear buffers");
+    }
   }
   size_t k = reqs.size();
   if (g.bufs[k].alloc(it * 4) != hipSuccess ||
@@ -334,7 +351,7 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.err = (int32_t *)c->errflag.p;
   g.dims.assign(it * f.W, FitDims{});
   g.have.assign(it * f.W, 0);
-  hipError_t e = hipMemcpy(f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
+  e = hipMemcpy(f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload slots");
   return BBP_OK;
 }
@@ -1034,7 +1051,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         Group ug;
         ug.W = 1;
         ug.H = 1;
-        bbp_status bs2 = alloc_batch(c, ug, n, Kenv, std::vector<uint64_t>(n, 0));
+        bbp_status bs2 = alloc_batch(c, ug, n, Kenv, std::vector<uint64_t>(n, 0),
+                                     NEED_SCRATCH);
         if (bs2 != BBP_OK) return bs2;
         FitBatch &fu = ug.fb;
         DevBuf kets, bras, tabs;

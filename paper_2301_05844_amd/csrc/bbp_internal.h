@@ -82,6 +82,11 @@ hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl,
                               Ptr X, Ptr F, hipStream_t st);
 hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
                                       Ptr X, Ptr F, hipStream_t st);
+// Whether the fused visit kernel's tiles fit in LDS for this batch shape
+// (otherwise the generic chain with its T1/T2 scratch runs), and whether the
+// QR panel needs the global scratch (t1).
+bool visit_fused_fits(const FitBatch &f);
+bool qr_needs_scratch(const FitBatch &f);
 // Chain plus the local update Yt = T3 . G written into Y.
 hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
                               Ptr F, Ptr G, Ptr Y, hipStream_t st);

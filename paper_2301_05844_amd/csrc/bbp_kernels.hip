@@ -840,6 +840,214 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
 }
 
 // ---------------------------------------------------------------------------
+// Householder QR with the panel in registers: wave w holds rows
+// [w*R, (w+1)*R) of every column, lane j column j (n <= 64); the first RREG
+// rows of a wave's chunk sit in registers, the rest (at most kQrExt) in a
+// lane-private LDS region.  Same reflector sequence as LAPACK's
+// dgeqr2/dorg2r; the reflector of step k is staged in LDS, dot products over
+// a wave's rows run locally and are summed across waves in LDS in a fixed
+// order.
+// ---------------------------------------------------------------------------
+constexpr int kQr2Threads = 1024;
+constexpr int kQr2Waves = kQr2Threads / 64;
+constexpr int kQrReg = 28;
+constexpr int kQrExt = 16;
+
+__global__ __launch_bounds__(kQr2Threads) void k_qr3(QrArgs q) {
+  const int it = blockIdx.x;
+  if (q.flag && !q.flag[it]) return;
+  const FitDims &dm = q.dims[(size_t)it * q.W + q.c];
+  const int K = q.K, P = q.P, j = q.j;
+  int n1, n2, ncol;
+  size_t s1, s2, sc;
+  switch (q.mode) {
+    case LR_INNER:
+      n1 = dm.bl[j]; s1 = (size_t)P * K; n2 = P; s2 = K; ncol = dm.br[j]; sc = 1;
+      break;
+    case RL_INNER:  // rows (l, yb), l-major, as in the QR of the transpose
+      n1 = P; s1 = K; n2 = dm.br[j]; s2 = 1; ncol = dm.bl[j]; sc = (size_t)P * K;
+      break;
+    case LR_TOP:
+      n1 = dm.p[j]; s1 = K; n2 = 1; s2 = 0; ncol = dm.br[j]; sc = 1;
+      break;
+    default:  // RL_BOT
+      n1 = dm.p[j]; s1 = 1; n2 = 1; s2 = 0; ncol = dm.bl[j]; sc = K;
+      break;
+  }
+  const int m = n1 * n2, n = ncol;
+  double *base = q.Y.at(it);
+  __shared__ double vbuf[(kQrReg + kQrExt) * kQr2Waves];
+  __shared__ double ext[kQr2Waves][kQrExt][64];
+  __shared__ double part[kQr2Waves][64];
+  __shared__ double wv[64];
+  __shared__ double red[kQr2Waves];
+  __shared__ double tau_s[64];
+  __shared__ double alpha_s, scal_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R = (m + kQr2Waves - 1) / kQr2Waves;
+  const int i0 = wave * R, i1 = min(m, i0 + R);
+  const int ie = i0 + kQrReg;  // first row of this wave kept in LDS
+  double reg[kQrReg];
+  double(*xt)[64] = ext[wave];
+  auto addr = [&](int i) {
+    const int r1 = i / n2, r2 = i - r1 * n2;
+    return r1 * s1 + r2 * s2 + lane * sc;
+  };
+#pragma unroll
+  for (int r = 0; r < kQrReg; ++r) {
+    const int i = i0 + r;
+    reg[r] = (i < i1 && lane < n) ? base[addr(i)] : 0.0;
+  }
+  for (int i = ie; i < i1; ++i) xt[i - ie][lane] = lane < n ? base[addr(i)] : 0.0;
+
+  // Apply H_k (v in vbuf, v_k = 1) to the columns held by lanes jj > k.
+  auto apply = [&](int k, double tau) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < kQrReg; ++r) {
+      const int i = i0 + r;
+      if (i < i1) {
+        if (i > k) s += vbuf[i] * reg[r];
+        else if (i == k) s += reg[r];
+      }
+    }
+    for (int i = max(ie, k); i < i1; ++i)
+      s += (i > k ? vbuf[i] : 1.0) * xt[i - ie][lane];
+    if (lane > k && lane < n) part[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && lane > k && lane < n) {
+      double t = 0.0;
+      for (int w = 0; w < kQr2Waves; ++w) t += part[w][lane];
+      wv[lane] = tau * t;
+    }
+    __syncthreads();
+    if (lane > k && lane < n) {
+      const double w = wv[lane];
+#pragma unroll
+      for (int r = 0; r < kQrReg; ++r) {
+        const int i = i0 + r;
+        if (i < i1) {
+          if (i > k) reg[r] -= vbuf[i] * w;
+          else if (i == k) reg[r] -= w;
+        }
+      }
+      for (int i = max(ie, k); i < i1; ++i)
+        xt[i - ie][lane] -= (i > k ? vbuf[i] : 1.0) * w;
+    }
+  };
+
+  for (int k = 0; k < n; ++k) {
+    // column k: sigma^2 over rows > k (lane k of each wave), alpha = A[k][k]
+    if (lane == k) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < kQrReg; ++r) {
+        const int i = i0 + r;
+        if (i < i1 && i > k) s += reg[r] * reg[r];
+        if (i < i1 && i == k) alpha_s = reg[r];
+      }
+      for (int i = ie; i < i1; ++i) {
+        const double x = xt[i - ie][lane];
+        if (i > k) s += x * x;
+        if (i == k) alpha_s = x;
+      }
+      red[wave] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sigma2 = 0.0;
+      for (int w = 0; w < kQr2Waves; ++w) sigma2 += red[w];
+      const double alpha = alpha_s;
+      double tau = 0.0, scal = 0.0;
+      if (sigma2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+        alpha_s = beta;
+      }
+      tau_s[k] = tau;
+      scal_s = scal;
+    }
+    __syncthreads();
+    const double tau = tau_s[k];
+    if (lane == k) {
+      const double scal = scal_s, beta = alpha_s;
+#pragma unroll
+      for (int r = 0; r < kQrReg; ++r) {
+        const int i = i0 + r;
+        if (i < i1) {
+          if (i > k) {
+            if (tau != 0.0) reg[r] *= scal;
+            vbuf[i] = reg[r];
+          } else if (i == k) {
+            reg[r] = beta;
+          }
+        }
+      }
+      for (int i = ie; i < i1; ++i) {
+        if (i > k) {
+          if (tau != 0.0) xt[i - ie][lane] *= scal;
+          vbuf[i] = xt[i - ie][lane];
+        } else if (i == k) {
+          xt[i - ie][lane] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    if (tau != 0.0) apply(k, tau);
+    __syncthreads();
+  }
+
+  if (q.want_r) {  // R rows live in the waves owning rows < n
+    double *Rm = q.rbuf + (size_t)it * K * K;
+#pragma unroll
+    for (int r = 0; r < kQrReg; ++r) {
+      const int i = i0 + r;
+      if (i < i1 && i < n && lane < K)
+        Rm[(size_t)i * K + lane] = (lane >= i && lane < n) ? reg[r] : 0.0;
+    }
+    for (int i = ie; i < min(i1, n); ++i)
+      if (lane < K) Rm[(size_t)i * K + lane] = (lane >= i && lane < n) ? xt[i - ie][lane] : 0.0;
+    for (int idx = tid; idx < K * K; idx += kQr2Threads)
+      if (idx / K >= n) Rm[idx] = 0.0;
+  }
+
+  // Q = H_0 ... H_{n-1} [I; 0] (dorg2r order)
+  for (int k = n - 1; k >= 0; --k) {
+    const double tau = tau_s[k];
+    if (lane == k) {
+#pragma unroll
+      for (int r = 0; r < kQrReg; ++r) {
+        const int i = i0 + r;
+        if (i < i1 && i > k) vbuf[i] = reg[r];
+      }
+      for (int i = max(ie, k + 1); i < i1; ++i) vbuf[i] = xt[i - ie][lane];
+    }
+    __syncthreads();
+    if (k < n - 1 && tau != 0.0) apply(k, tau);
+    if (lane == k) {
+#pragma unroll
+      for (int r = 0; r < kQrReg; ++r) {
+        const int i = i0 + r;
+        if (i < i1) reg[r] = i > k ? -tau * vbuf[i] : (i == k ? 1.0 - tau : 0.0);
+      }
+      for (int i = ie; i < i1; ++i)
+        xt[i - ie][lane] = i > k ? -tau * vbuf[i] : (i == k ? 1.0 - tau : 0.0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int r = 0; r < kQrReg; ++r) {
+    const int i = i0 + r;
+    if (i < i1 && lane < n) base[addr(i)] = reg[r];
+  }
+  for (int i = ie; i < i1; ++i)
+    if (lane < n) base[addr(i)] = xt[i - ie][lane];
+}
+
+// ---------------------------------------------------------------------------
 // Counter-based uniform numbers: SplitMix64 (Steele, Lea, Flood 2014).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t splitmix(uint64_t x) {
@@ -1109,6 +1317,20 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   return hipGetLastError();
 }
 
+bool visit_fused_fits(const FitBatch &f) {
+  int TY, TX;
+  size_t lds;
+  visit_tiles(f, &TY, &TX, &lds);
+  return TY > 0;
+}
+
+bool qr_needs_scratch(const FitBatch &f) {
+  const int rows = (f.K * f.P + kQr2Waves - 1) / kQr2Waves;
+  if ((size_t)f.K * f.P * f.K <= (size_t)kQrLds) return false;
+  if (f.K <= 64 && rows <= kQrReg + kQrExt) return false;  // register panel
+  return true;
+}
+
 hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
                               Ptr F, Ptr G, Ptr Y, hipStream_t st) {
   int TY, TX;
@@ -1216,10 +1438,20 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
   const double m = (double)f.K * f.P, n = f.K;
   Span sp(KC_QR, st, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
           f.items * 16.0 * m * n);
-  if (panel <= (size_t)kQrLds)
+  // Measured fastest per shape: the LDS kernel when the panel fits, the
+  // register-resident kernel for panels up to 704 x 64, else the LDS kernel's
+  // global-memory form.
+  const int rows = (f.K * f.P + kQr2Waves - 1) / kQr2Waves;  // per wave
+  if (panel <= (size_t)kQrLds) {
     hipLaunchKernelGGL(k_qr<true>, dim3(f.items), dim3(kThreads), 0, st, q);
-  else
+  } else if (f.K <= 64 && rows <= kQrReg + kQrExt) {
+    hipLaunchKernelGGL(k_qr3, dim3(f.items), dim3(kQr2Threads), 0, st, q);
+  } else {
+    if (!f.t1 || t1_stride(f) < panel)
+      return hipErrorInvalidValue;  // global panel scratch missing or too small
     hipLaunchKernelGGL(k_qr<false>, dim3(f.items), dim3(kThreads), 0, st, q);
+  }
+  (void)panel;
   return hipGetLastError();
 }
 

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/bbp.h declares, and
+reject bad arguments before touching a device.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from bbp_inputs import peps_finite
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bbp.h")
+
+
+def _bbp():
+    try:
+        from paper_2301_05844_amd import bbp
+    except ImportError as e:
+        pytest.fail(f"libbbp.so missing: {e}")
+    return bbp
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bbp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    bbp = _bbp()
+    assert set(_declared()) == set(bbp.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported():
+    bbp = _bbp()
+    lib = ctypes.CDLL(bbp.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_create_validates_arguments():
+    bbp = _bbp()
+    lib = bbp.lib()
+    ctx = ctypes.c_void_p()
+    bad = [
+        (0, 4, 4, 0, 0, 0, 2, 2, 4),      # bx = 0
+        (0, 4, 4, 0, 0, 2, 2, 0, 4),      # D = 0
+        (0, 0, 4, 0, 0, 2, 2, 2, 4),      # Lx = 0
+        (1, 0, 0, 2, 2, 3, 4, 2, 4),      # block not a multiple of the cell
+        (0, 4, 4, 0, 0, 2, 2, 2, 200),    # chi above the supported cap
+        (0, 80, 80, 0, 0, 40, 40, 2, 4),  # block longer than the boundary cap
+    ]
+    for args in bad:
+        assert lib.bbp_create(ctypes.byref(ctx), *args) == 1, args
+    assert lib.bbp_create(None, 0, 4, 4, 0, 0, 2, 2, 2, 4) == 1
+    assert lib.bbp_create(ctypes.byref(ctx), 0, 4, 4, 0, 0, 2, 2, 2, 4) == 0
+    lib.bbp_destroy(ctx)
+
+
+def test_options_and_state_checks():
+    bbp = _bbp()
+    g = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
+    with pytest.raises(bbp.BBPError) as e:
+        g.set_option("no_such_option", 1)
+    assert e.value.status == 1
+    for key, val in [("n_fit", 0), ("n_fit", 2.5), ("chi_env", 0),
+                     ("chi_env", 500), ("d", 0), ("seed", -1)]:
+        with pytest.raises(bbp.BBPError):
+            g.set_option(key, val)
+    g.set_option("n_fit", 3)
+    g.set_option("chi_env", 20)
+    with pytest.raises(bbp.BBPError) as e:
+        g.sweep(1)
+    assert e.value.status == 4  # BBP_ESTATE before the tensors
+    with pytest.raises(bbp.BBPError) as e:
+        g.expect_site(0, 0, np.eye(2))
+    assert e.value.status == 4
+
+
+def test_set_tensors_validates_before_device():
+    bbp = _bbp()
+    g = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
+    A = peps_finite(4, 4, 2, seed=0)
+    with pytest.raises(bbp.BBPError) as e:
+        g.set_tensors(A[:-1])
+    assert e.value.status == 1
+    B = A.copy()
+    B[0, 0, 1, 0, 0, 0] = 0.5   # up leg of a top-edge site, index 1
+    with pytest.raises(bbp.BBPError) as e:
+        g.set_tensors(B)
+    assert e.value.status == 1 and "open-edge" in str(e.value)
+    B = A.copy()
+    B[7, 1, 0, 1, 0, 1] = np.inf
+    with pytest.raises(bbp.BBPError) as e:
+        g.set_tensors(B)
+    assert e.value.status == 1
+
+
+def test_gpu_absence_is_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    bbp = _bbp()
+    g = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
+    with pytest.raises(bbp.BBPError) as e:
+        g.set_tensors(peps_finite(4, 4, 2, seed=0))
+    assert e.value.status == 3  # BBP_EDEVICE, no silent CPU path
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
