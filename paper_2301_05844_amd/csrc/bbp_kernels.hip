@@ -119,21 +119,24 @@ constexpr int kThreads = 256;
 // supplied by an op struct (a(), b(), st()); each workgroup stages BK-deep
 // slices of A and B in LDS and 16 x 16 threads accumulate TM x TN tiles.
 // ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <int BM, int BN, int BK, class Op>
 __global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
   const int it = blockIdx.z;
   if (op.flag && !op.flag[it]) return;
-  constexpr int TM = BM / 16, TN = BN / 16;
+  // 16 x 16 MFMA tiles of the BM x BN block, spread over the four waves
+  constexpr int TMX = BM / 16, TNX = BN / 16, NT = TMX * TNX;
+  constexpr int TPW = (NT + 3) / 4;
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  double acc[TM][TN];
+  v4d acc[TPW];
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
+  for (int q = 0; q < TPW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < op.Kd; k0 += BK) {
     for (int i = tid; i < BM * BK; i += kThreads) {
       const int kk = i % BK, mm = i / BK;
@@ -147,26 +150,30 @@ __global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[TM], b[TN];
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + 4 * q;
+      if (t < NT) {
+        const int tm = (t / TNX) * 16, tn = (t % TNX) * 16;
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int kk = 0; kk < BK; kk += 4)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              As[kk + lq][tm + lr], Bs[kk + lq][tn + lr], acc[q], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + 4 * q;
+    if (t < NT) {
+      const int tm = (t / TNX) * 16, tn = (t % TNX) * 16;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
-      if (m < op.M && n < op.N) op.st(it, m, n, acc[i][j]);
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + tm + 4 * r + lq, n = n0 + tn + lr;
+        if (m < op.M && n < op.N) op.st(it, m, n, acc[q][r]);
+      }
     }
+  }
 }
 
 template <int BM, int BN, int BK, class Op>
@@ -482,8 +489,6 @@ struct OpOv2 {  // E'[a][b] = sum_{b',q} U[b'][q][a] b_i[b'][q][b]
 // MFMA operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator register r holds D[4r + l/16][l%16].
 // ---------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
-
 struct VisitArgs {
   int K, P, D, d, TY, TX;
   int rl, do_local;
@@ -532,9 +537,14 @@ __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
   }
 }
 
+// DT > 0 fixes D (and P = D^2) at compile time; DT = 0 reads them at run time.
+template <int DT>
 __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   extern __shared__ double sm[];
-  const int K = v.K, P = v.P, D = v.D, d = v.d, TY = v.TY, TX = v.TX;
+  constexpr bool kFixed = DT > 0;
+  const int D = kFixed ? DT : v.D;
+  const int P = kFixed ? DT * DT : v.P;
+  const int K = v.K, d = v.d, TY = v.TY, TX = v.TX;
   const int dP = d * P, P2 = P * P;
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x;
@@ -1281,15 +1291,30 @@ static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   *TY = 0;
 }
 
+using VisitKernel = void (*)(VisitArgs);
+
+static VisitKernel visit_kernel(int D) {
+  switch (D) {
+    case 2: return k_visit<2>;
+    case 3: return k_visit<3>;
+    case 4: return k_visit<4>;
+    case 5: return k_visit<5>;
+    case 6: return k_visit<6>;
+    default: return k_visit<0>;
+  }
+}
+
 static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
                                Ptr F, Ptr G, Ptr Y, bool do_local, int TY,
                                int TX, size_t lds, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_visit,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e != hipSuccess) return e;
+    for (int D : {0, 2, 3, 4, 5, 6}) {
+      hipError_t e = hipFuncSetAttribute(
+          (const void *)visit_kernel(D),
+          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) return e;
+    }
     attr_set = true;
   }
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
@@ -1312,7 +1337,7 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     bytes += it * 8 * 2 * K * P * K;
   }
   Span sp(KC_VISIT, st, flops, bytes);
-  hipLaunchKernelGGL(k_visit, dim3((f.K + TY - 1) / TY, f.items),
+  hipLaunchKernelGGL(visit_kernel(f.D), dim3((f.K + TY - 1) / TY, f.items),
                      dim3(kVisitThreads), lds, st, v);
   return hipGetLastError();
 }
