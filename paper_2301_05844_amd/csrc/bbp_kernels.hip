@@ -850,20 +850,90 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR with the panel in registers: wave w holds rows
-// [w*R, (w+1)*R) of every column, lane j column j (n <= 64); the first RREG
-// rows of a wave's chunk sit in registers, the rest (at most kQrExt) in a
-// lane-private LDS region.  Same reflector sequence as LAPACK's
-// dgeqr2/dorg2r; the reflector of step k is staged in LDS, dot products over
-// a wave's rows run locally and are summed across waves in LDS in a fixed
-// order.
+// Blocked Householder QR on FP64 MFMA tiles, one workgroup of NW waves per
+// item.  The panel stays in registers as 16x16 tiles in the MFMA accumulator
+// layout (register s of lane l holds row 4s + l/16, column l%16 of its tile);
+// wave w owns row tiles w, w + NW, ... of every column tile.  Columns are
+// factorised in blocks of 16 as in dgeqrf.  Inside a block, step k
+// broadcasts column k along each 16-lane row (DPP row_newbcast) and forms,
+// in one pass and one cross-wave sum, x^T a_c for every column c (x = column
+// k below the diagonal) and the row-k entries a_kc; column k's own entries
+// give sigma^2 and alpha for dlarfg, and w_c = a_kc + scal x^T a_c gives the
+// dlarf update of the block's later columns.  The block reflector
+// I - V T V^T (T from dlarft) is then applied to the columns on the right on
+// MFMA (W = V^T A, A -= V T^T W).  Q is formed backwards over the blocks as
+// in dorgqr: the block reflector updates the columns on the right, and the
+// block's own columns are E - V (T V_top^T), E the unit columns, both on
+// MFMA.  The reflectors are those of the unblocked algorithm (dgeqr2); only
+// the rounding order of sums and updates differs.  Cross-wave sums are taken
+// in a fixed order that every wave repeats, so all waves hold the same bits.
 // ---------------------------------------------------------------------------
-constexpr int kQr2Threads = 1024;
-constexpr int kQr2Waves = kQr2Threads / 64;
-constexpr int kQrReg = 28;
-constexpr int kQrExt = 16;
+// Orders one wave's LDS writes before its later LDS reads (other lanes).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__global__ __launch_bounds__(kQr2Threads) void k_qr3(QrArgs q) {
+constexpr int kQmRowCap = 768;        // rows held by one workgroup, at most
+constexpr int kQmVs = kQmRowCap + 4;   // stride of a V column in LDS
+
+__device__ __forceinline__ double join_f64(int lo, int hi) {
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the four 16-lane rows: row pairs (0,1), (2,3) through
+// permlane16_swap, then the two pair sums through permlane32_swap; the same
+// bits land in every row.
+__device__ __forceinline__ double sum_rows4(double x) {
+  long long b = __double_as_longlong(x);
+  auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  x = join_f64(lo[0], hi[0]) + join_f64(lo[1], hi[1]);
+  b = __double_as_longlong(x);
+  lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+  hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  return join_f64(lo[0], hi[0]) + join_f64(lo[1], hi[1]);
+}
+
+__device__ __forceinline__ int cl_index(int i, int j) {  // accumulator slot of (i, j)
+  return (i >> 2) * 64 + (i & 3) * 16 + j;
+}
+
+template <int CTRL, int N>
+__device__ __forceinline__ void newbcast_all(double *d, const double *x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    d[i] = __longlong_as_double(
+        __builtin_amdgcn_mov_dpp(__double_as_longlong(x[i]), CTRL, 0xf, 0xf, true));
+}
+
+// d[i] = x[i] of lane `src` of the same 16-lane row (64-bit row_newbcast)
+template <int N>
+__device__ __forceinline__ void row_bcast(double *d, const double *x, int src) {
+  switch (src) {
+    case 0: newbcast_all<0x150, N>(d, x); break;
+    case 1: newbcast_all<0x151, N>(d, x); break;
+    case 2: newbcast_all<0x152, N>(d, x); break;
+    case 3: newbcast_all<0x153, N>(d, x); break;
+    case 4: newbcast_all<0x154, N>(d, x); break;
+    case 5: newbcast_all<0x155, N>(d, x); break;
+    case 6: newbcast_all<0x156, N>(d, x); break;
+    case 7: newbcast_all<0x157, N>(d, x); break;
+    case 8: newbcast_all<0x158, N>(d, x); break;
+    case 9: newbcast_all<0x159, N>(d, x); break;
+    case 10: newbcast_all<0x15A, N>(d, x); break;
+    case 11: newbcast_all<0x15B, N>(d, x); break;
+    case 12: newbcast_all<0x15C, N>(d, x); break;
+    case 13: newbcast_all<0x15D, N>(d, x); break;
+    case 14: newbcast_all<0x15E, N>(d, x); break;
+    default: newbcast_all<0x15F, N>(d, x); break;
+  }
+}
+
+template <int NW, int RT, int CT>
+__global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
+  static_assert(NW % 4 == 0 && NW >= CT && 16 * NW * RT <= kQmRowCap, "panel shape");
   const int it = blockIdx.x;
   if (q.flag && !q.flag[it]) return;
   const FitDims &dm = q.dims[(size_t)it * q.W + q.c];
@@ -884,178 +954,295 @@ __global__ __launch_bounds__(kQr2Threads) void k_qr3(QrArgs q) {
       n1 = dm.p[j]; s1 = 1; n2 = 1; s2 = 0; ncol = dm.bl[j]; sc = K;
       break;
   }
-  const int m = n1 * n2, n = ncol;
+  const int m = n1 * n2, n = min(ncol, m);
   double *base = q.Y.at(it);
-  __shared__ double vbuf[(kQrReg + kQrExt) * kQr2Waves];
-  __shared__ double ext[kQr2Waves][kQrExt][64];
-  __shared__ double part[kQr2Waves][64];
-  __shared__ double wv[64];
-  __shared__ double red[kQr2Waves];
-  __shared__ double tau_s[64];
-  __shared__ double alpha_s, scal_s;
+  __shared__ double VT[16][kQmVs];  // V of the current block, column-major
+  __shared__ double wred[NW][256];
+  __shared__ double Ws[256], Zs[256];
+  __shared__ double Tm[CT][16][16];
+  __shared__ double wp[2][NW][16], wq[2][NW][16];
+  __shared__ double tau_s[16 * CT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int R = (m + kQr2Waves - 1) / kQr2Waves;
-  const int i0 = wave * R, i1 = min(m, i0 + R);
-  const int ie = i0 + kQrReg;  // first row of this wave kept in LDS
-  double reg[kQrReg];
-  double(*xt)[64] = ext[wave];
-  auto addr = [&](int i) {
-    const int r1 = i / n2, r2 = i - r1 * n2;
-    return r1 * s1 + r2 * s2 + lane * sc;
-  };
-#pragma unroll
-  for (int r = 0; r < kQrReg; ++r) {
-    const int i = i0 + r;
-    reg[r] = (i < i1 && lane < n) ? base[addr(i)] : 0.0;
-  }
-  for (int i = ie; i < i1; ++i) xt[i - ie][lane] = lane < n ? base[addr(i)] : 0.0;
-
-  // Apply H_k (v in vbuf, v_k = 1) to the columns held by lanes jj > k.
-  auto apply = [&](int k, double tau) {
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < kQrReg; ++r) {
-      const int i = i0 + r;
-      if (i < i1) {
-        if (i > k) s += vbuf[i] * reg[r];
-        else if (i == k) s += reg[r];
-      }
-    }
-    for (int i = max(ie, k); i < i1; ++i)
-      s += (i > k ? vbuf[i] : 1.0) * xt[i - ie][lane];
-    if (lane > k && lane < n) part[wave][lane] = s;
-    __syncthreads();
-    if (wave == 0 && lane > k && lane < n) {
-      double t = 0.0;
-      for (int w = 0; w < kQr2Waves; ++w) t += part[w][lane];
-      wv[lane] = tau * t;
-    }
-    __syncthreads();
-    if (lane > k && lane < n) {
-      const double w = wv[lane];
-#pragma unroll
-      for (int r = 0; r < kQrReg; ++r) {
-        const int i = i0 + r;
-        if (i < i1) {
-          if (i > k) reg[r] -= vbuf[i] * w;
-          else if (i == k) reg[r] -= w;
-        }
-      }
-      for (int i = max(ie, k); i < i1; ++i)
-        xt[i - ie][lane] -= (i > k ? vbuf[i] : 1.0) * w;
-    }
+  const int lr = lane >> 4, lc = lane & 15;
+  // Row tiles t > 0 start at row 16 * NW >= n, below every diagonal entry.
+  auto rowof = [&](int t, int s) { return 16 * (wave + NW * t) + 4 * s + lr; };
+  auto gaddr = [&](int row, int col) {
+    const int r1 = row / n2, r2 = row - r1 * n2;
+    return r1 * s1 + r2 * s2 + col * sc;
   };
 
-  for (int k = 0; k < n; ++k) {
-    // column k: sigma^2 over rows > k (lane k of each wave), alpha = A[k][k]
-    if (lane == k) {
-      double s = 0.0;
+  v4d a[RT][CT];
 #pragma unroll
-      for (int r = 0; r < kQrReg; ++r) {
-        const int i = i0 + r;
-        if (i < i1 && i > k) s += reg[r] * reg[r];
-        if (i < i1 && i == k) alpha_s = reg[r];
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = rowof(t, s), col = 16 * ct + lc;
+        a[t][ct][s] = (row < m && col < n) ? base[gaddr(row, col)] : 0.0;
       }
-      for (int i = ie; i < i1; ++i) {
-        const double x = xt[i - ie][lane];
-        if (i > k) s += x * x;
-        if (i == k) alpha_s = x;
+
+  // Column tile b's reflectors to LDS: 0 above the diagonal, 1 on it.
+  auto store_v = [&](int b, int nbb) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = rowof(t, s), pr = 16 * b + lc;
+        VT[lc][row] = lc < nbb ? ((t > 0 || row > pr) ? a[t][b][s] : (row == pr ? 1.0 : 0.0))
+                               : 0.0;
       }
-      red[wave] = s;
+    wave_lds_order();
+  };
+
+  // Sum of the per-wave 16x16 accumulators into Ws (accumulator slots).
+  auto reduce_tiles = [&](const v4d &acc) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) wred[wave][r * 64 + lane] = acc[r];
+    __syncthreads();
+    if (tid < 256) {
+      double x = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) x += wred[w][tid];
+      Ws[tid] = x;
     }
     __syncthreads();
-    if (tid == 0) {
-      double sigma2 = 0.0;
-      for (int w = 0; w < kQr2Waves; ++w) sigma2 += red[w];
-      const double alpha = alpha_s;
-      double tau = 0.0, scal = 0.0;
+  };
+
+  // C += V Zs for column tile ct, Zs = -(16x16 coefficients), K = 16 (MFMA)
+  auto update_tile = [&](v4d (&c)[RT]) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        c[t] = mfma16(VT[4 * kk + lr][16 * (wave + NW * t) + lc],
+                      Zs[(4 * kk + lr) * 16 + lc], c[t]);
+  };
+
+  // C -= V op(T) (V^T C) for the column tiles right of block b.
+  auto apply_block = [&](int b, bool trans) {
+    double xo[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xo[t][s] = VT[lc][16 * (wave + NW * t) + 4 * s + lr];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      if (ct <= b || 16 * ct >= n) continue;
+      v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s & 1] = mfma16(xo[t][s], a[t][ct][s], acc[s & 1]);
+      reduce_tiles(acc[0] + acc[1]);  // W = V^T C
+      if (tid < 256) {
+        const int p = tid >> 4, jj = tid & 15;
+        double z = 0.0;
+#pragma unroll 4
+        for (int qq = 0; qq < 16; ++qq)
+          z += (trans ? Tm[b][qq][p] : Tm[b][p][qq]) * Ws[cl_index(qq, jj)];
+        Zs[tid] = -z;
+      }
+      __syncthreads();
+      v4d c[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) c[t] = a[t][ct];
+      update_tile(c);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t][ct] = c[t];
+    }
+  };
+
+  // ---- factorisation (dgeqrf order) ----
+  int pb = 0;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) {
+    const int b0 = 16 * b;
+    if (b0 >= n) break;
+    const int nbb = min(16, n - b0);
+    double my_scal = 0.0, my_beta = 0.0, my_tau = 0.0;  // of column b0 + lc
+    for (int kc = 0; kc < nbb; ++kc) {
+      const int k = b0 + kc;
+      // x = column k below row k, broadcast along the rows from lane kc
+      double cv[RT * 4], xb[RT * 4];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) cv[t * 4 + s] = a[t][b][s];
+      row_bcast<RT * 4>(xb, cv, kc);
+      double pdot = 0.0, qk = 0.0;  // x^T a_c, and a_kc where this lane holds row k
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = rowof(0, s);
+        if (row <= k) xb[s] = 0.0;
+        if (row == k) qk = a[0][b][s];
+      }
+      double pp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) pp[s] = fma(xb[t * 4 + s], a[t][b][s], pp[s]);
+      pdot = sum_rows4((pp[0] + pp[1]) + (pp[2] + pp[3]));
+      qk = sum_rows4(qk);
+      if (lr == 0) {
+        wp[pb][wave][lc] = pdot;
+        wq[pb][wave][lc] = qk;
+      }
+      __syncthreads();
+      double pc = 0.0, qc = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ww += 4) {
+        pc += wp[pb][ww + lr][lc];
+        qc += wq[pb][ww + lr][lc];
+      }
+      pc = sum_rows4(pc);
+      qc = sum_rows4(qc);
+      pb ^= 1;
+      // dlarfg on column k: sigma^2 = x^T x, alpha = a_kk (lane kc of each row)
+      double sa[2] = {pc, qc}, sb[2];
+      row_bcast<2>(sb, sa, kc);
+      const double sigma2 = sb[0], alpha = sb[1];
+      double tau = 0.0, scal = 0.0, beta = alpha;
       if (sigma2 > 0.0) {
         const double nrm = sqrt(alpha * alpha + sigma2);
-        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        beta = alpha >= 0.0 ? -nrm : nrm;
         tau = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
-        alpha_s = beta;
       }
-      tau_s[k] = tau;
-      scal_s = scal;
-    }
-    __syncthreads();
-    const double tau = tau_s[k];
-    if (lane == k) {
-      const double scal = scal_s, beta = alpha_s;
+      if (tid == 0) tau_s[k] = tau;
+      if (lc == kc) {
+        my_scal = scal;
+        my_beta = beta;
+        my_tau = tau;
+      }
+      // dlarf on the block's columns c > k: w_c = a_kc + scal x^T a_c,
+      // a_c -= tau v w_c with v = (1, scal x)
+      const double wt = (lc > kc && lc < nbb) ? -(tau * (qc + scal * pc)) : 0.0;
+      const double cs = scal * wt;
 #pragma unroll
-      for (int r = 0; r < kQrReg; ++r) {
-        const int i = i0 + r;
-        if (i < i1) {
-          if (i > k) {
-            if (tau != 0.0) reg[r] *= scal;
-            vbuf[i] = reg[r];
-          } else if (i == k) {
-            reg[r] = beta;
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a[t][b][s] = fma(xb[t * 4 + s], cs, a[t][b][s]);
+          if (t == 0 && rowof(0, s) == k) a[0][b][s] += wt;
+        }
+    }
+    // reflectors scaled in place, beta on the diagonal
+    if (lc < nbb) {
+      const int pr = b0 + lc;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int row = rowof(t, s);
+          if (t > 0 || row > pr) {
+            if (my_tau != 0.0) a[t][b][s] *= my_scal;
+          } else if (row == pr) {
+            a[t][b][s] = my_beta;
           }
         }
+    }
+    store_v(b, nbb);
+
+    // Gram matrix V^T V of the block, then T as in dlarft (forward, columnwise)
+    v4d g[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double x = VT[lc][16 * (wave + NW * t) + 4 * s + lr];
+        g[s & 1] = mfma16(x, x, g[s & 1]);
       }
-      for (int i = ie; i < i1; ++i) {
-        if (i > k) {
-          if (tau != 0.0) xt[i - ie][lane] *= scal;
-          vbuf[i] = xt[i - ie][lane];
-        } else if (i == k) {
-          xt[i - ie][lane] = beta;
-        }
+    reduce_tiles(g[0] + g[1]);
+    if (wave == 0) {
+      // lane (lr, lc) keeps T[lc][lr + 4u]; column i of T needs columns < i
+      double tr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double ti = i < nbb ? tau_s[b0 + i] : 0.0;
+        double x = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (4 * u < i && lr + 4 * u < i) x += tr[u] * Ws[cl_index(lr + 4 * u, i)];
+        x = sum_rows4(x);
+        const double t = lc < i ? -ti * x : (lc == i ? ti : 0.0);
+        if (lr == (i & 3)) tr[i >> 2] = t;
+        __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Tm[b][lc][lr + 4 * u] = tr[u];
     }
     __syncthreads();
-    if (tau != 0.0) apply(k, tau);
-    __syncthreads();
+    apply_block(b, true);
   }
 
-  if (q.want_r) {  // R rows live in the waves owning rows < n
+  if (q.want_r) {
     double *Rm = q.rbuf + (size_t)it * K * K;
 #pragma unroll
-    for (int r = 0; r < kQrReg; ++r) {
-      const int i = i0 + r;
-      if (i < i1 && i < n && lane < K)
-        Rm[(size_t)i * K + lane] = (lane >= i && lane < n) ? reg[r] : 0.0;
-    }
-    for (int i = ie; i < min(i1, n); ++i)
-      if (lane < K) Rm[(size_t)i * K + lane] = (lane >= i && lane < n) ? xt[i - ie][lane] : 0.0;
-    for (int idx = tid; idx < K * K; idx += kQr2Threads)
-      if (idx / K >= n) Rm[idx] = 0.0;
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = rowof(0, s), col = 16 * ct + lc;
+        if (row < K && col < K)
+          Rm[(size_t)row * K + col] =
+              (row < n && col < n && col >= row) ? a[0][ct][s] : 0.0;
+      }
+#pragma unroll
+    for (int t = 1; t < RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int row = rowof(t, s), col = 16 * ct + lc;
+          if (row < K && col < K) Rm[(size_t)row * K + col] = 0.0;
+        }
   }
 
-  // Q = H_0 ... H_{n-1} [I; 0] (dorg2r order)
-  for (int k = n - 1; k >= 0; --k) {
-    const double tau = tau_s[k];
-    if (lane == k) {
+  // ---- Q = H_0 ... H_{n-1} [I; 0], backwards over the blocks (dorgqr) ----
 #pragma unroll
-      for (int r = 0; r < kQrReg; ++r) {
-        const int i = i0 + r;
-        if (i < i1 && i > k) vbuf[i] = reg[r];
-      }
-      for (int i = max(ie, k + 1); i < i1; ++i) vbuf[i] = xt[i - ie][lane];
+  for (int b = CT - 1; b >= 0; --b) {
+    const int b0 = 16 * b;
+    if (b0 >= n) continue;
+    const int nbb = min(16, n - b0);
+    store_v(b, nbb);
+    apply_block(b, false);
+    __syncthreads();  // V of every wave visible
+    // the block's own columns: E - V (T V_top^T), E the unit columns at rows b0..
+    if (tid < 256) {
+      const int p = tid >> 4, jj = tid & 15;
+      double z = 0.0;
+#pragma unroll 4
+      for (int qq = 0; qq < 16; ++qq) z += Tm[b][p][qq] * VT[qq][b0 + jj];
+      Zs[tid] = -z;
     }
     __syncthreads();
-    if (k < n - 1 && tau != 0.0) apply(k, tau);
-    if (lane == k) {
+    v4d c[RT];
 #pragma unroll
-      for (int r = 0; r < kQrReg; ++r) {
-        const int i = i0 + r;
-        if (i < i1) reg[r] = i > k ? -tau * vbuf[i] : (i == k ? 1.0 - tau : 0.0);
-      }
-      for (int i = ie; i < i1; ++i)
-        xt[i - ie][lane] = i > k ? -tau * vbuf[i] : (i == k ? 1.0 - tau : 0.0);
-    }
-    __syncthreads();
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        c[t][s] = (t == 0 && rowof(0, s) == b0 + lc && lc < nbb) ? 1.0 : 0.0;
+    update_tile(c);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) a[t][b] = c[t];
   }
 
+  // Recompute the store addresses instead of keeping the load's alive.
+  size_t os1 = s1, os2 = s2, osc = sc;
+  int on2 = n2;
+  asm volatile("" : "+s"(os1), "+s"(os2), "+s"(osc), "+s"(on2));
 #pragma unroll
-  for (int r = 0; r < kQrReg; ++r) {
-    const int i = i0 + r;
-    if (i < i1 && lane < n) base[addr(i)] = reg[r];
-  }
-  for (int i = ie; i < i1; ++i)
-    if (lane < n) base[addr(i)] = xt[i - ie][lane];
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = rowof(t, s), col = 16 * ct + lc;
+        const int r1 = row / on2, r2 = row - r1 * on2;
+        if (row < m && col < n) base[r1 * os1 + r2 * os2 + col * osc] = a[t][ct][s];
+      }
 }
+
 
 // ---------------------------------------------------------------------------
 // Counter-based uniform numbers: SplitMix64 (Steele, Lea, Flood 2014).
@@ -1349,11 +1536,34 @@ bool visit_fused_fits(const FitBatch &f) {
   return TY > 0;
 }
 
+// Blocked MFMA QR (8 waves) for panels up to 768 x 48: row tiles per wave and
+// column tiles from the bond cap K and the physical dimension P.
+constexpr int kQmWavesUsed = 8;
+
+bool qrm_fits(const FitBatch &f) {
+  return f.K <= 48 && f.K * f.P <= 16 * kQmWavesUsed * 6;
+}
+
 bool qr_needs_scratch(const FitBatch &f) {
-  const int rows = (f.K * f.P + kQr2Waves - 1) / kQr2Waves;
-  if ((size_t)f.K * f.P * f.K <= (size_t)kQrLds) return false;
-  if (f.K <= 64 && rows <= kQrReg + kQrExt) return false;  // register panel
-  return true;
+  if (qrm_fits(f)) return false;
+  return (size_t)f.K * f.P * f.K > (size_t)kQrLds;
+}
+
+template <int RT>
+void launch_qrm_rt(int CT, int items, hipStream_t st, const QrArgs &q) {
+  constexpr int NW = kQmWavesUsed;
+  if (CT == 1) hipLaunchKernelGGL((k_qrm<NW, RT, 1>), dim3(items), dim3(NW * 64), 0, st, q);
+  else if (CT == 2) hipLaunchKernelGGL((k_qrm<NW, RT, 2>), dim3(items), dim3(NW * 64), 0, st, q);
+  else hipLaunchKernelGGL((k_qrm<NW, RT, 3>), dim3(items), dim3(NW * 64), 0, st, q);
+}
+
+void launch_qrm(const FitBatch &f, hipStream_t st, const QrArgs &q) {
+  const int rt = (f.K * f.P + 16 * kQmWavesUsed - 1) / (16 * kQmWavesUsed);
+  const int CT = (f.K + 15) / 16;
+  if (rt <= 1) launch_qrm_rt<1>(CT, f.items, st, q);
+  else if (rt <= 2) launch_qrm_rt<2>(CT, f.items, st, q);
+  else if (rt <= 4) launch_qrm_rt<4>(CT, f.items, st, q);
+  else launch_qrm_rt<6>(CT, f.items, st, q);
 }
 
 hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
@@ -1463,14 +1673,12 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
   const double m = (double)f.K * f.P, n = f.K;
   Span sp(KC_QR, st, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
           f.items * 16.0 * m * n);
-  // Measured fastest per shape: the LDS kernel when the panel fits, the
-  // register-resident kernel for panels up to 704 x 64, else the LDS kernel's
-  // global-memory form.
-  const int rows = (f.K * f.P + kQr2Waves - 1) / kQr2Waves;  // per wave
-  if (panel <= (size_t)kQrLds) {
+  // The blocked MFMA kernel for panels up to 768 x 48 (every shape of the
+  // D <= 4 workloads); otherwise the LDS kernel, or its global-memory form.
+  if (qrm_fits(f)) {
+    launch_qrm(f, st, q);
+  } else if (panel <= (size_t)kQrLds) {
     hipLaunchKernelGGL(k_qr<true>, dim3(f.items), dim3(kThreads), 0, st, q);
-  } else if (f.K <= 64 && rows <= kQrReg + kQrExt) {
-    hipLaunchKernelGGL(k_qr3, dim3(f.items), dim3(kQr2Threads), 0, st, q);
   } else {
     if (!f.t1 || t1_stride(f) < panel)
       return hipErrorInvalidValue;  // global panel scratch missing or too small
