@@ -11,6 +11,12 @@ roofline figures (HIP events on its launch stream) and the FP64 CPU oracle
 timed on the host are added to the same JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py --calibrate-copy   (plain 1 GiB device copy, for counters)
+
+The roofline's `traffic` (HBM bytes per launch of the dominant kernel) comes
+from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ and is
+reported only while the HIP sources match the ones the counters were taken
+on; otherwise it is null.
 """
 
 import argparse
@@ -32,6 +38,8 @@ MAX_SWEEPS = 40
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fit_visit_obc16x16_D4_chi32.json")
+COPY_BYTES = 1 << 30
 
 
 def log(msg):
@@ -76,10 +84,36 @@ def roofline(stats):
         achieved = flops / avg_s / 1e12
         r = dict(bound="mfma", achieved=achieved, peak=PEAK_FP64_TFLOPS,
                  unit="TFLOP/s", frac=achieved / PEAK_FP64_TFLOPS)
-    r.update(traffic=None, kernel=dom["name"], launches=dom["launches"],
+    r.update(traffic=measured_traffic(dom["name"]), kernel=dom["name"], launches=dom["launches"],
              avg_us=dom["ms"] / n * 1e3, flops_per_launch=flops,
              bytes_per_launch=bytes_, intensity=intensity)
     return r
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernels (same source hash) for this kernel class."""
+    from paper_2301_05844_amd.profiling import source_sha
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != source_sha() or t.get("kernel_class") != cls:
+        return None
+    return t["bytes_per_launch"]
+
+
+def calibrate_copy():
+    """A plain device copy of COPY_BYTES (read and written once), five times:
+    the reference for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes=COPY_BYTES, kernel="neg (elementwise)")), flush=True)
 
 
 def cpu_baseline(cfg, A):
@@ -110,7 +144,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: every message update of this "
               "workload runs on a single MI355X; --gpus must be 1",

@@ -1,0 +1,155 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_2301_05844_amd.profiling trace DIR --title T --cmd C > out.md
+        kernel table (calls, average and total time) from a
+        ``rocprofv3 --kernel-trace --stats --output-format csv`` run.
+
+    python -m paper_2301_05844_amd.profiling traffic --kernel k_visit \
+        --kernel-class fit_visit --launches N --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \
+        --copy-bytes B --out FILE.json
+        HBM bytes per launch of the kernel: FETCH_SIZE and WRITE_SIZE (KiB per
+        dispatch) of its last N dispatches, each scaled by what the same
+        counter reads for a plain copy of B bytes read and B bytes written.
+
+``source_sha()`` hashes the HIP sources, so a traffic figure can be dropped
+once the kernels have changed since the counters were taken.
+"""
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ("csrc/bbp_kernels.hip", "csrc/bbp_api.hip", "csrc/bbp_internal.h")
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name):
+    """Kernel name without namespaces and argument lists."""
+    name = name.replace("(anonymous namespace)::", "").replace("bbp::", "")
+    name = re.sub(r"^void ", "", name)
+    depth, out = 0, []
+    for ch in name:  # drop the parameter list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _one(pattern):
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise FileNotFoundError(pattern)
+    return files[0]
+
+
+def trace_table(outdir):
+    rows = list(csv.DictReader(open(_one(os.path.join(outdir, "**", "*kernel_stats.csv")))))
+    table = []
+    for r in rows:
+        table.append(dict(name=short_name(r["Name"]), calls=int(r["Calls"]),
+                          avg_us=float(r["AverageNs"]) / 1e3,
+                          total_ms=float(r["TotalDurationNs"]) / 1e6,
+                          pct=float(r["Percentage"])))
+    return sorted(table, key=lambda t: -t["total_ms"])
+
+
+def last_dispatches_us(outdir, kernel, n):
+    """Average duration (us) of the last n dispatches of a kernel in a
+    --kernel-trace run (the timed steps follow the warm-up)."""
+    rows = list(csv.DictReader(open(_one(os.path.join(outdir, "**", "*kernel_trace.csv")))))
+    d = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+         for r in rows if short_name(r["Kernel_Name"]).startswith(kernel)]
+    d.sort()
+    tail = [x[1] for x in d[-n:]]
+    return sum(tail) / len(tail) / 1e3, len(tail)
+
+
+def trace_markdown(outdir, title, cmd, top=16):
+    lines = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "",
+             "```", cmd, "```", "",
+             "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    for t in trace_table(outdir)[:top]:
+        lines.append(f"| `{t['name']}` | {t['calls']} | {t['avg_us']:.1f} | "
+                     f"{t['total_ms']:.1f} | {t['pct']:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
+def counter_values(outdir, counter, kernel):
+    """Per-dispatch values (dispatch order) of one counter for kernels whose
+    short name starts with `kernel`."""
+    rows = list(csv.DictReader(open(_one(os.path.join(outdir, "**", "*counter_collection.csv")))))
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter or not short_name(r["Kernel_Name"]).startswith(kernel):
+            continue
+        key = int(r["Dispatch_Id"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return [per[k] for k in sorted(per)]
+
+
+def traffic(kernel, kernel_class, launches, fetch, write, copy_fetch, copy_write, copy_bytes,
+            copy_kernel):
+    f = counter_values(fetch, "FETCH_SIZE", kernel)[-launches:]
+    w = counter_values(write, "WRITE_SIZE", kernel)[-launches:]
+    cf = max(counter_values(copy_fetch, "FETCH_SIZE", copy_kernel))
+    cw = max(counter_values(copy_write, "WRITE_SIZE", copy_kernel))
+    kib = copy_bytes / 1024.0
+    ff, fw = cf / kib, cw / kib  # counter KiB per KiB actually moved
+    fetch_b = sum(f) / len(f) * 1024.0 / ff
+    write_b = sum(w) / len(w) * 1024.0 / fw
+    return dict(kernel=kernel, kernel_class=kernel_class, launches=len(f), source_sha=source_sha(),
+                fetch_kib_per_dispatch=sum(f) / len(f), write_kib_per_dispatch=sum(w) / len(w),
+                copy_bytes=copy_bytes, copy_fetch_factor=ff, copy_write_factor=fw,
+                fetch_bytes_per_launch=fetch_b, write_bytes_per_launch=write_b,
+                bytes_per_launch=fetch_b + write_b)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="action", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--title", required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--timed-kernel", default="")
+    t.add_argument("--timed-launches", type=int, default=0)
+    c = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "out"):
+        c.add_argument("--" + k.replace("_", "-"), required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--kernel-class", required=True)
+    c.add_argument("--launches", type=int, required=True)
+    c.add_argument("--copy-bytes", type=float, required=True)
+    c.add_argument("--copy-kernel", default="")
+    a = ap.parse_args(argv)
+    if a.action == "trace":
+        sys.stdout.write(trace_markdown(a.dir, a.title, a.cmd))
+        if a.timed_kernel:
+            us, n = last_dispatches_us(a.dir, a.timed_kernel, a.timed_launches)
+            sys.stdout.write(f"\nLast {n} dispatches of `{a.timed_kernel}` (the timed solves): "
+                             f"average {us:.1f} us.\n")
+    else:
+        r = traffic(a.kernel, a.kernel_class, a.launches, a.fetch, a.write, a.copy_fetch, a.copy_write,
+                    a.copy_bytes, a.copy_kernel)
+        with open(a.out, "w") as f:
+            json.dump(r, f, indent=1)
+        print(json.dumps(r))
+
+
+if __name__ == "__main__":
+    main()
