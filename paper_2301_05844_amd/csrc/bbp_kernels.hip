@@ -509,8 +509,10 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 }
 
 // One batched LDS GEMM: for batch p < nb, C_p[M][N] = A_p[M][Kd] B_p[Kd][N];
-// 16 x 16 output tiles spread over the waves; afn/bfn read operands (zero
-// outside), sfn stores the result tile element.
+// 16 x 16 output tiles spread over the waves, two per wave at a time when
+// there are enough; each tile keeps two accumulators (even and odd k-steps)
+// and its operands are read two k-steps ahead of the MFMAs.  afn/bfn read
+// operands (zero outside), sfn stores the result tile element.
 template <class AF, class BF, class SF>
 __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
                                          BF bfn, SF sfn) {
@@ -518,26 +520,74 @@ __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
   const int lr = lane & 15, lq = lane >> 4;
   const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
   const int ntiles = nb * tm * tn;
-  for (int t = wave; t < ntiles; t += kVisitWaves) {
-    const int p = t / (tm * tn), r2 = t - p * tm * tn;
-    const int m0 = (r2 / tn) << 4, n0 = (r2 % tn) << 4;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    const int am = m0 + lr, bn = n0 + lr;
-    for (int k0 = 0; k0 < Kd; k0 += 4) {
-      const int k = k0 + lq;
-      const double a = (am < M && k < Kd) ? afn(p, am, k) : 0.0;
-      const double b = (bn < N && k < Kd) ? bfn(p, k, bn) : 0.0;
-      acc = mfma16(a, b, acc);
+  for (int t0 = wave; t0 < ntiles; t0 += 2 * kVisitWaves) {
+    int p[2], m0[2], n0[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = min(t0 + h * kVisitWaves, ntiles - 1);
+      p[h] = t / (tm * tn);
+      const int r2 = t - p[h] * tm * tn;
+      m0[h] = (r2 / tn) << 4;
+      n0[h] = (r2 % tn) << 4;
+    }
+    const bool two = t0 + kVisitWaves < ntiles;
+    v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
+                     {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
+    for (int k0 = 0; k0 < Kd; k0 += 8) {
+      double av[2][2], bv[2][2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int k = k0 + 4 * u + lq, am = m0[h] + lr, bn = n0[h] + lr;
+          const bool on = h == 0 || two;
+          av[h][u] = (on && am < M && k < Kd) ? afn(p[h], am, k) : 0.0;
+          bv[h][u] = (on && bn < N && k < Kd) ? bfn(p[h], k, bn) : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        acc[0][u] = mfma16(av[0][u], bv[0][u], acc[0][u]);
+        if (two) acc[1][u] = mfma16(av[1][u], bv[1][u], acc[1][u]);
+      }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + 4 * r + lq, n = n0 + lr;
-      if (m < M && n < N) sfn(p, m, n, acc[r]);
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+      const v4d c = acc[h][0] + acc[h][1];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0[h] + 4 * r + lq, n = n0[h] + lr;
+        if (m < M && n < N) sfn(p[h], m, n, c[r]);
+      }
     }
   }
 }
 
+// LDS row strides that keep the MFMA operand reads free of bank conflicts
+// (64-bit words, 32 word pairs per bank row; a read serves 16 lanes along the
+// tile and 2 lane groups along k together): a row that the 16 lanes walk as
+// the A operand gets a stride of 2 (mod 32), a row that 2 lane groups walk as
+// the B operand a stride of 16 (mod 32).
+__host__ __device__ constexpr int pad_a(int x) { return x + (34 - x % 32) % 32; }
+__host__ __device__ constexpr int pad_b(int x) { return x + (48 - x % 32) % 32; }
+
+// Doubles of dynamic LDS for one fused-visit workgroup with tiles TY x TX.
+__host__ __device__ inline size_t visit_lds(int K, int P, int d, int TY, int TX) {
+  const size_t P2 = (size_t)P * P;
+  return (size_t)TY * P * pad_a(K) + (size_t)K * pad_b(P * TX) + (size_t)TY * TX * P2 +
+         (size_t)TY * TX * P * pad_b(d * P) + (size_t)TY * TX * P2 +
+         (size_t)TX * P * pad_b(K) + 2 * (size_t)d * P2;
+}
+
 // DT > 0 fixes D (and P = D^2) at compile time; DT = 0 reads them at run time.
+// LDS layouts (index order, fastest last):
+//   Fs [ty, wf][xf]          stride pad_a(K)
+//   Xs [xf][a, tx]           stride pad_b(P TX)
+//   T1s[pair][wfk, akx][wfb, abx]
+//   T2s[pair][wfb, abx][s, lk, wbk]   stride pad_b(d P)
+//   T3s[pair][wbk, wbb][lk, lb]
+//   Gs [tx, wb][yb]          stride pad_b(K)
+//   Ak, Ab [s][wf][a][l][wb] of the front view (ket and bra roles alike)
 template <int DT>
 __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   extern __shared__ double sm[];
@@ -546,15 +596,16 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   const int P = kFixed ? DT * DT : v.P;
   const int K = v.K, d = v.d, TY = v.TY, TX = v.TX;
   const int dP = d * P, P2 = P * P;
+  const int FS = pad_a(K), XS = pad_b(P * TX), T2S = pad_b(dP), GS = pad_b(K);
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x;
-  double *Fs = sm;                         // [TY*P][K]
-  double *Xs = Fs + (size_t)TY * P * K;    // [K][P*TX]
-  double *T1s = Xs + (size_t)K * P * TX;   // [TY*TX][P][P]
-  double *T2s = T1s + (size_t)TY * TX * P2;     // [TY*TX][P][dP]
-  double *T3s = T2s + (size_t)TY * TX * P * dP; // [TY*TX][P][P]
-  double *Gs = T3s + (size_t)TY * TX * P2;      // [TX*P][K]
-  double *Ak = Gs + (size_t)TX * P * K;         // [d][D][D][D][D] front view
+  double *Fs = sm;
+  double *Xs = Fs + (size_t)TY * P * FS;
+  double *T1s = Xs + (size_t)K * XS;
+  double *T2s = T1s + (size_t)TY * TX * P2;
+  double *T3s = T2s + (size_t)TY * TX * P * T2S;
+  double *Gs = T3s + (size_t)TY * TX * P2;
+  double *Ak = Gs + (size_t)TX * P * GS;
   double *Ab = Ak + (size_t)d * P2;
   const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
   const double *ak = v.aket + (size_t)it * v.aket_stride;
@@ -562,12 +613,13 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   double *T3g = v.t3 + (size_t)it * v.t3_stride;
   const bool rl = v.rl != 0;
 
-  // front-view site tensors: A_f[s][wf][l][wb][a]; RL swaps the u/d legs
+  // front-view site tensors A_f[s][wf][l][wb][a] (RL swaps the u/d legs),
+  // stored as [s][wf][a][l][wb]
   for (int i = tid; i < d * P2; i += kVisitThreads) {
     int t = i;
-    const int a = t % D; t /= D;
     const int wb = t % D; t /= D;
     const int l = t % D; t /= D;
+    const int a = t % D; t /= D;
     const int wf = t % D;
     const int s = t / D;
     const int u = rl ? wb : wf, dd = rl ? wf : wb;
@@ -579,13 +631,16 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   for (int i = tid; i < TY * P * K; i += kVisitThreads) {
     const int row = i / K, xf = i - row * K;
     const int yf = y0 + row / P;
-    Fs[i] = yf < K ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
+    Fs[row * FS + xf] = yf < K ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
   }
-  // Yt accumulators: tiles of [(ty,l)][yb], kept in registers
+  // Yt accumulators: tiles of [(ty,l)][yb], kept in registers.  With at
+  // most half as many tiles as waves, each tile's k range is split over two
+  // waves (kh = 0, 1) and the halves are summed at the end.
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   const int Me = TY * P, tme = (Me + 15) >> 4, tne = (K + 15) >> 4;
   const int ntile_e = tme * tne;
+  const bool split_e = 2 * ntile_e <= kVisitWaves;
   constexpr int kMaxE = 4;  // tiles per wave (host keeps ntile_e <= 4 * waves)
   v4d accE[kMaxE];
 #pragma unroll
@@ -593,61 +648,69 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
 
   for (int x0 = 0; x0 < K; x0 += TX) {
     __syncthreads();  // previous tile's Xs/Gs/T3s consumers are done
-    // X_f[xf][a][xb] for the tile, as Xs[xf][a*TX + tx]
+    // X_f[xf][a][xb] for the tile, as Xs[xf][a*TX + tx]; the loop runs along
+    // the contiguous global index (xb for LR, xf for RL)
     for (int i = tid; i < K * P * TX; i += kVisitThreads) {
-      const int xf = i / (P * TX), r = i - xf * P * TX;
-      const int a = r / TX, tx = r - a * TX, xb = x0 + tx;
+      int xf, a, tx;
+      if (rl) {
+        xf = i % K;
+        const int r = i / K;
+        a = r % P;
+        tx = r / P;
+      } else {
+        tx = i % TX;
+        const int r = i / TX;
+        a = r % P;
+        xf = r / P;
+      }
+      const int xb = x0 + tx;
       double val = 0.0;
       if (xb < K)
         val = rl ? X[((size_t)xb * P + a) * K + xf] : X[((size_t)xf * P + a) * K + xb];
-      Xs[i] = val;
+      Xs[xf * XS + a * TX + tx] = val;
     }
     if (v.do_local)
-      // G[yb][wb][xb] as Gs[(tx*P + wb)][yb]
+      // G[yb][wb][xb] as Gs[(tx*P + wb)][yb], read along xb
       for (int i = tid; i < TX * P * K; i += kVisitThreads) {
-        const int row = i / K, yb = i - row * K;
-        const int tx = row / P, wb = row - tx * P, xb = x0 + tx;
-        Gs[i] = xb < K ? G[((size_t)yb * P + wb) * K + xb] : 0.0;
+        const int tx = i % TX, r = i / TX;
+        const int wb = r % P, yb = r / P, xb = x0 + tx;
+        Gs[(tx * P + wb) * GS + yb] = xb < K ? G[((size_t)yb * P + wb) * K + xb] : 0.0;
       }
     __syncthreads();
-    // (a) T1: rows (ty, wf), cols (a, tx)
+    // (a) T1: rows (ty, wf), cols (a, tx), stored [pair][wfk, akx][wfb, abx]
     lds_gemm(
         1, TY * P, P * TX, K,
-        [&](int, int m, int k) { return Fs[m * K + k]; },
-        [&](int, int k, int n) { return Xs[k * P * TX + n]; },
+        [&](int, int m, int k) { return Fs[m * FS + k]; },
+        [&](int, int k, int n) { return Xs[k * XS + n]; },
         [&](int, int m, int n, double val) {
           const int ty = m / P, wf = m - ty * P, a = n / TX, tx = n - a * TX;
-          T1s[(ty * TX + tx) * P2 + wf * P + a] = val;
+          const int wfk = wf / D, wfb = wf - wfk * D, akx = a / D, abx = a - akx * D;
+          T1s[(ty * TX + tx) * P2 + (wfk * D + akx) * P + wfb * D + abx] = val;
         });
     __syncthreads();
-    // (b) ket: per pair, rows (wfb, ab), k (wfk, ak), cols (s, lk, wbk)
+    // (b) ket: per pair, rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
     lds_gemm(
         TY * TX, P, dP, P,
-        [&](int p, int m, int k) {
-          const int wfb = m / D, abx = m - wfb * D, wfk = k / D, akx = k - wfk * D;
-          return T1s[p * P2 + (wfk * D + wfb) * P + akx * D + abx];
-        },
+        [&](int p, int m, int k) { return T1s[p * P2 + k * P + m]; },
         [&](int, int k, int n) {
-          const int wfk = k / D, akx = k - wfk * D;
-          const int s = n / P, r = n - s * P, lk = r / D, wbk = r - lk * D;
-          return Ak[(((s * D + wfk) * D + lk) * D + wbk) * D + akx];
+          const int s = n / P;
+          return Ak[(s * P + k) * P + (n - s * P)];
         },
-        [&](int p, int m, int n, double val) { T2s[(p * P + m) * dP + n] = val; });
+        [&](int p, int m, int n, double val) { T2s[(p * P + m) * T2S + n] = val; });
     __syncthreads();
-    // (c) bra: per pair, rows (lk, wbk), k (s, wfb, ab), cols (lb, wbb)
+    // (c) bra: per pair, rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb);
+    // stored as T3s[pair][wb][l]
     lds_gemm(
         TY * TX, P, P, dP,
         [&](int p, int m, int k) {
-          const int lk = m / D, wbk = m - lk * D;
-          const int s = k / P, r = k - s * P, wfb = r / D, abx = r - wfb * D;
-          return T2s[(p * P + wfb * D + abx) * dP + s * P + lk * D + wbk];
+          const int s = k / P;
+          return T2s[(p * P + (k - s * P)) * T2S + s * P + m];
         },
-        [&](int, int k, int n) {
-          const int s = k / P, r = k - s * P, wfb = r / D, abx = r - wfb * D;
-          const int lb = n / D, wbb = n - lb * D;
-          return Ab[(((s * D + wfb) * D + lb) * D + wbb) * D + abx];
-        },
-        [&](int p, int m, int n, double val) { T3s[p * P2 + m * P + n] = val; });
+        [&](int, int k, int n) { return Ab[k * P + n]; },
+        [&](int p, int m, int n, double val) {
+          const int lk = m / D, wbk = m - lk * D, lb = n / D, wbb = n - lb * D;
+          T3s[p * P2 + (wbk * D + wbb) * P + lk * D + lb] = val;
+        });
     __syncthreads();
     // T3 tile to HBM as T3[yf][l][xb][wb]
     for (int i = tid; i < TY * TX * P2; i += kVisitThreads) {
@@ -657,40 +720,70 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
       const int l = t % P;
       const int ty = t / P;
       const int yf = y0 + ty, xb = x0 + tx;
-      if (yf < K && xb < K) {
-        const int lk = l / D, lb = l - lk * D, wbk = wb / D, wbb = wb - wbk * D;
-        T3g[(((size_t)yf * P + l) * K + xb) * P + wb] =
-            T3s[(ty * TX + tx) * P2 + (lk * D + wbk) * P + lb * D + wbb];
-      }
+      if (yf < K && xb < K)
+        T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = T3s[(ty * TX + tx) * P2 + wb * P + l];
     }
     // (e) local update, accumulated over the xb tiles
     if (v.do_local) {
       const int Ke = TX * P;
+      const int kh = split_e ? wave / (kVisitWaves / 2) : 0;
+      const int wt = split_e ? wave % (kVisitWaves / 2) : wave;
+      const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
+      const int kb = split_e ? kh * (Ke / 2) : 0, ke = split_e ? kb + Ke / 2 : Ke;
 #pragma unroll
       for (int q = 0; q < kMaxE; ++q) {
-        const int t = wave + q * kVisitWaves;
+        const int t = wt + q * wstep;
         if (t >= ntile_e) break;
         const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
         const int am = m0 + lr, bn = n0 + lr;
         const int ty = am / P, l = am - ty * P;
-        const int lk = l / D, lb = l - lk * D;
-        v4d acc = accE[q];
-        for (int k0 = 0; k0 < Ke; k0 += 4) {
-          const int k = k0 + lq;
-          const int tx = k / P, wb = k - tx * P, wbk = wb / D, wbb = wb - wbk * D;
-          const double a = am < Me ? T3s[(ty * TX + tx) * P2 + (lk * D + wbk) * P + lb * D + wbb] : 0.0;
-          const double b = bn < K ? Gs[k * K + bn] : 0.0;
-          acc = mfma16(a, b, acc);
+        v4d acc[2] = {accE[q], v4d{0.0, 0.0, 0.0, 0.0}};
+        for (int k0 = kb; k0 < ke; k0 += 8) {
+          double av[2], bv[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int k = k0 + 4 * u + lq;
+            const int tx = k / P, wb = k - tx * P;
+            av[u] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : 0.0;
+            bv[u] = (bn < K && k < ke) ? Gs[k * GS + bn] : 0.0;
+          }
+          acc[0] = mfma16(av[0], bv[0], acc[0]);
+          acc[1] = mfma16(av[1], bv[1], acc[1]);
         }
-        accE[q] = acc;
+        accE[q] = acc[0] + acc[1];
       }
     }
   }
-  if (v.do_local) {
+  if (v.do_local && split_e) {  // add the second k half into the first
+    __syncthreads();
+    double *red = sm;  // every LDS buffer is free after the last tile
+    if (wave >= kVisitWaves / 2) {
+      const int wt = wave - kVisitWaves / 2;
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wt + q * (kVisitWaves / 2);
+        if (t >= ntile_e) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(t * 4 + r) * 64 + lane] = accE[q][r];
+      }
+    }
+    __syncthreads();
+    if (wave < kVisitWaves / 2) {
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wave + q * (kVisitWaves / 2);
+        if (t >= ntile_e) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accE[q][r] += red[(t * 4 + r) * 64 + lane];
+      }
+    }
+  }
+  if (v.do_local && (!split_e || wave < kVisitWaves / 2)) {
     double *Y = v.Y.at(it);
+    const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
 #pragma unroll
     for (int q = 0; q < kMaxE; ++q) {
-      const int t = wave + q * kVisitWaves;
+      const int t = wave + q * wstep;
       if (t >= ntile_e) break;
       const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
 #pragma unroll
@@ -700,6 +793,249 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
         if (m < Me && yb < K && yf < K) {
           const size_t idx = rl ? ((size_t)yb * P + l) * K + yf
                                 : ((size_t)yf * P + l) * K + yb;
+          Y[idx] = accE[q][r];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused fit visit specialised for D = 4 (P = 16) and d = 2, tiles TY x TX
+// fixed at compile time.  Same four contractions and layouts as k_visit; every
+// MFMA operand is read through a per-lane pointer with a compile-time step, the
+// k loops are unrolled, and the operand tiles are zero-padded in LDS (rows and
+// columns up to a multiple of 4 in k, of 16 in yb) so that no bounds test sits
+// in an MFMA loop.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int ceil4(int x) { return (x + 3) & ~3; }
+__host__ __device__ inline int ceil16(int x) { return (x + 15) & ~15; }
+
+__host__ __device__ inline size_t visit4_lds(int K, int TY, int TX) {
+  const int K4 = ceil4(K);
+  return (size_t)TY * 16 * pad_a(K4) + (size_t)K4 * pad_b(16 * TX) + (size_t)TY * TX * 256 +
+         (size_t)TY * TX * 16 * pad_b(32) + (size_t)TY * TX * 256 + (size_t)TX * 16 * pad_b(K) +
+         2 * 2 * 256;
+}
+
+// acc[0] / acc[1] += sum over N k-steps (even / odd) of A(pa + i*da) B(pb + i*db)
+template <int N>
+__device__ __forceinline__ void mma_steps(v4d (&acc)[2], const double *pa, int da,
+                                          const double *pb, int db) {
+  double av[N], bv[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    av[i] = pa[i * da];
+    bv[i] = pb[i * db];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) acc[i & 1] = mfma16(av[i], bv[i], acc[i & 1]);
+}
+
+template <int TY, int TX>
+__global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
+  extern __shared__ double sm[];
+  constexpr int D = 4, P = 16, P2 = 256, NP = TY * TX;
+  constexpr int XS = pad_b(16 * TX), T2S = pad_b(32);
+  const int K = v.K, K4 = ceil4(K), FS = pad_a(K4), GS = pad_b(K), KY = ceil16(K);
+  const int it = blockIdx.y, y0 = blockIdx.x * TY;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  double *Fs = sm;
+  double *Xs = Fs + TY * 16 * FS;
+  double *T1s = Xs + K4 * XS;
+  double *T2s = T1s + NP * P2;
+  double *T3s = T2s + NP * 16 * T2S;
+  double *Gs = T3s + NP * P2;
+  double *Ak = Gs + TX * 16 * GS;
+  double *Ab = Ak + 2 * P2;
+  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
+  const double *ak = v.aket + (size_t)it * v.aket_stride;
+  const double *ab = v.abra + (size_t)it * v.abra_stride;
+  double *T3g = v.t3 + (size_t)it * v.t3_stride;
+  const bool rl = v.rl != 0;
+
+  // site tensors as [s][wf][a][l][wb] of the front view (RL swaps u and d)
+  for (int i = tid; i < 2 * P2; i += kVisitThreads) {
+    const int wb = i & 3, l = (i >> 2) & 3, a = (i >> 4) & 3, wf = (i >> 6) & 3, s = i >> 8;
+    const int u = rl ? wb : wf, dd = rl ? wf : wb;
+    const int src = ((((s * D + u) * D + l) * D + dd) * D + a);
+    Ak[i] = ak[src];
+    Ab[i] = ab[src];
+  }
+  // F rows of the y tile, zero beyond K (and beyond the lattice edge in yf)
+  for (int row = wave; row < TY * 16; row += kVisitWaves) {
+    const bool ok = y0 + (row >> 4) < K;
+    for (int xf = lane; xf < K4; xf += 64)
+      Fs[row * FS + xf] = (ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
+  }
+  // local-update accumulators: TY x (KY/16) tiles of [(ty, l)][yb]; each
+  // tile's k range (tx, wb) is split over two waves when tiles are few
+  const int tne = KY >> 4, ntile_e = TY * tne;
+  const bool split_e = 2 * ntile_e <= kVisitWaves;
+  constexpr int kMaxE = 4;
+  v4d accE[kMaxE];
+#pragma unroll
+  for (int q = 0; q < kMaxE; ++q) accE[q] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  // The X and G tiles of the next xb step are fetched into registers while
+  // the current step computes.  Each thread moves up to kLd elements of each;
+  // their offsets (global relative to the tile, LDS) are decoded once.
+  constexpr int kLd = 8;  // host keeps K4*16*TX and KY*16*TX within 8*512
+  int xg[kLd], xl[kLd], gg[kLd], gl[kLd];
+  double xr[kLd], gr[kLd];
+#pragma unroll
+  for (int u = 0; u < kLd; ++u) {
+    const int i = tid + u * kVisitThreads;
+    int xf, a, tx;
+    if (rl) {
+      xf = i % K4;
+      const int r = i / K4;
+      a = r & 15;
+      tx = r >> 4;
+    } else {
+      tx = i % TX;
+      const int r = i / TX;
+      a = r & 15;
+      xf = r >> 4;
+    }
+    const bool ok = i < K4 * 16 * TX && xf < K;
+    xg[u] = !ok ? -1 : (rl ? (tx * P + a) * K + xf : (xf * P + a) * K + tx);
+    xl[u] = i < K4 * 16 * TX ? xf * XS + a * TX + tx : -1;
+    xl[u] |= (tx << 24);  // keep tx to test xb < K per step
+    const int gtx = i % TX, gr2 = i / TX, wb = gr2 & 15, yb = gr2 >> 4;
+    const bool gok = i < KY * 16 * TX && yb < K;
+    gg[u] = gok ? (yb * P + wb) * K + gtx : -1;
+    gl[u] = i < KY * 16 * TX ? ((gtx * 16 + wb) * GS + yb) | (gtx << 24) : -1;
+  }
+  auto fetch = [&](int x0) {
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int xtx = (xl[u] >> 24) & 0x7f, gtx = (gl[u] >> 24) & 0x7f;
+      const size_t xo = rl ? (size_t)x0 * P * K : (size_t)x0;
+      xr[u] = (xg[u] >= 0 && x0 + xtx < K) ? X[xo + xg[u]] : 0.0;
+      gr[u] = (v.do_local && gg[u] >= 0 && x0 + gtx < K) ? G[(size_t)x0 + gg[u]] : 0.0;
+    }
+  };
+  fetch(0);
+
+  for (int x0 = 0; x0 < K; x0 += TX) {
+    __syncthreads();  // the previous step's readers of Xs, Gs, T3s are done
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      if (xl[u] >= 0) Xs[xl[u] & 0xffffff] = xr[u];
+      if (gl[u] >= 0) Gs[gl[u] & 0xffffff] = gr[u];
+    }
+    __syncthreads();
+    if (x0 + TX < K) fetch(x0 + TX);
+    // (a) T1: tiles (ty, tn): rows (ty, wf), cols n = (a, tx) in [16 tn, 16 tn + 16)
+    for (int t = wave; t < TY * TX; t += kVisitWaves) {
+      const int ty = t / TX, tn = t % TX;
+      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+      const double *pa = Fs + (ty * 16 + lr) * FS + lq;
+      const double *pb = Xs + lq * XS + tn * 16 + lr;
+      int k0 = 0;
+      for (; k0 + 16 <= K4; k0 += 16) mma_steps<4>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
+      for (; k0 < K4; k0 += 4) mma_steps<1>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
+      const v4d c = acc[0] + acc[1];
+      const int n = tn * 16 + lr, a = n / TX, tx = n % TX;
+      double *dst = T1s + (ty * TX + tx) * P2 + (a >> 2) * 16 + lq * 4 + (a & 3);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[r * 64] = c[r];  // wf = 4r + lq: wfk = r, wfb = lq
+    }
+    __syncthreads();
+    // (b) ket: per pair, rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
+    for (int t = wave; t < 2 * NP; t += kVisitWaves) {
+      const int pp = t >> 1, sn = t & 1;
+      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+      mma_steps<4>(acc, T1s + pp * P2 + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
+      const v4d c = acc[0] + acc[1];
+      double *dst = T2s + (pp * 16 + lq) * T2S + sn * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[r * 4 * T2S] = c[r];
+    }
+    __syncthreads();
+    // (c) bra: per pair, rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb)
+    for (int t = wave; t < NP; t += kVisitWaves) {
+      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn)
+        mma_steps<4>(acc, T2s + (t * 16 + lq) * T2S + sn * 16 + lr, 4 * T2S,
+                     Ab + (sn * 16 + lq) * 16 + lr, 64);
+      const v4d c = acc[0] + acc[1];
+      // m = 4r + lq: lk = r, wbk = lq; n = lr: lb = lr/4, wbb = lr%4
+      double *dst = T3s + t * P2 + (lq * 4 + (lr & 3)) * 16 + (lr >> 2);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[r * 4] = c[r];
+    }
+    __syncthreads();
+    // T3 tile to HBM as T3[yf][l][xb][wb]
+    for (int i = tid; i < NP * P2; i += kVisitThreads) {
+      const int wb = i & 15, r = i >> 4, tx = r % TX, r2 = r / TX, l = r2 & 15, ty = r2 >> 4;
+      const int yf = y0 + ty, xb = x0 + tx;
+      if (yf < K && xb < K)
+        T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = T3s[(ty * TX + tx) * P2 + wb * 16 + l];
+    }
+    // (e) local update: Yt[(ty, l)][yb] += sum_{tx, wb} T3[(ty, l)][(tx, wb)] G[(tx, wb)][yb]
+    if (v.do_local) {
+      const int half = split_e ? wave / (kVisitWaves / 2) : 0;
+      const int wt = split_e ? wave % (kVisitWaves / 2) : wave;
+      const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wt + q * wstep;
+        if (t >= ntile_e) break;
+        const int ty = t / tne, n0 = (t % tne) << 4;
+        v4d acc[2] = {accE[q], v4d{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int tx = 0; tx < TX; ++tx)
+#pragma unroll
+          for (int wh = 0; wh < 2; ++wh) {  // wb in [8 wh, 8 wh + 8)
+            if (split_e && ((tx * 2 + wh) & 1) != half) continue;
+            mma_steps<2>(acc, T3s + (ty * TX + tx) * P2 + (wh * 8 + lq) * 16 + lr, 64,
+                         Gs + (tx * 16 + wh * 8 + lq) * GS + n0 + lr, 4 * GS);
+          }
+        accE[q] = acc[0] + acc[1];
+      }
+    }
+  }
+  if (v.do_local && split_e) {  // add the second k half into the first
+    __syncthreads();
+    double *red = sm;
+    if (wave >= kVisitWaves / 2) {
+      const int wt = wave - kVisitWaves / 2;
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wt + q * (kVisitWaves / 2);
+        if (t >= ntile_e) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(t * 4 + r) * 64 + lane] = accE[q][r];
+      }
+    }
+    __syncthreads();
+    if (wave < kVisitWaves / 2) {
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        const int t = wave + q * (kVisitWaves / 2);
+        if (t >= ntile_e) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accE[q][r] += red[(t * 4 + r) * 64 + lane];
+      }
+    }
+  }
+  if (v.do_local && (!split_e || wave < kVisitWaves / 2)) {
+    double *Y = v.Y.at(it);
+    const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
+#pragma unroll
+    for (int q = 0; q < kMaxE; ++q) {
+      const int t = wave + q * wstep;
+      if (t >= ntile_e) break;
+      const int ty = t / tne, n0 = (t % tne) << 4, yf = y0 + ty, yb = n0 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int l = 4 * r + lq;
+        if (yb < K && yf < K) {
+          const size_t idx = rl ? ((size_t)yb * P + l) * K + yf : ((size_t)yf * P + l) * K + yb;
           Y[idx] = accE[q][r];
         }
       }
@@ -1465,9 +1801,9 @@ static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   for (auto &c : cand) {
     const size_t ty = c[0], tx = c[1];
     if ((int)ty > f.K) continue;
-    const size_t n = ty * P * K + K * P * tx + ty * tx * P * P * (2 + d) +
-                     tx * P * K + 2 * d * P * P;
+    size_t n = visit_lds(f.K, f.P, f.d, (int)ty, (int)tx);
     const size_t tiles = ((ty * P + 15) / 16) * ((K + 15) / 16);
+    if (2 * tiles <= (size_t)kVisitWaves) n = std::max(n, tiles * 256);  // k-half sums
     if (n * 8 <= 150 * 1024 && tiles <= 4 * (size_t)kVisitWaves) {
       *TY = (int)ty;
       *TX = (int)tx;
@@ -1491,6 +1827,32 @@ static VisitKernel visit_kernel(int D) {
   }
 }
 
+// Tiles of the D = 4, d = 2 kernel: the first candidate whose LDS fits.
+static bool visit4_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
+  if (f.D != 4 || f.d != 2 || f.K > 128) return false;
+  const int cand[][2] = {{2, 4}, {4, 2}, {2, 2}, {1, 2}, {1, 1}};
+  for (auto &c : cand) {
+    if (c[0] > f.K) continue;
+    const size_t n = visit4_lds(f.K, c[0], c[1]);
+    const size_t moved = (size_t)std::max(ceil4(f.K), ceil16(f.K)) * 16 * c[1];
+    if (n * 8 <= 150 * 1024 && moved <= 8 * (size_t)kVisitThreads) {
+      *TY = c[0];
+      *TX = c[1];
+      *bytes = n * 8;
+      return true;
+    }
+  }
+  return false;
+}
+
+static VisitKernel visit4_kernel(int TY, int TX) {
+  if (TY == 2 && TX == 4) return k_visit4<2, 4>;
+  if (TY == 4 && TX == 2) return k_visit4<4, 2>;
+  if (TY == 2 && TX == 2) return k_visit4<2, 2>;
+  if (TY == 1 && TX == 2) return k_visit4<1, 2>;
+  return k_visit4<1, 1>;
+}
+
 static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
                                Ptr F, Ptr G, Ptr Y, bool do_local, int TY,
                                int TX, size_t lds, hipStream_t st) {
@@ -1502,8 +1864,18 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
     }
+    for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2), std::make_pair(2, 2),
+                   std::make_pair(1, 2), std::make_pair(1, 1)}) {
+      hipError_t e = hipFuncSetAttribute(
+          (const void *)visit4_kernel(t.first, t.second),
+          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      if (e != hipSuccess) return e;
+    }
     attr_set = true;
   }
+  int TY4, TX4;
+  size_t lds4;
+  const bool spec = visit4_tiles(f, &TY4, &TX4, &lds4);
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
   VisitArgs v;
   v.K = f.K; v.P = f.P; v.D = f.D; v.d = f.d; v.TY = TY; v.TX = TX;
@@ -1524,8 +1896,15 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     bytes += it * 8 * 2 * K * P * K;
   }
   Span sp(KC_VISIT, st, flops, bytes);
-  hipLaunchKernelGGL(visit_kernel(f.D), dim3((f.K + TY - 1) / TY, f.items),
-                     dim3(kVisitThreads), lds, st, v);
+  if (spec) {
+    v.TY = TY4;
+    v.TX = TX4;
+    hipLaunchKernelGGL(visit4_kernel(TY4, TX4), dim3((f.K + TY4 - 1) / TY4, f.items),
+                       dim3(kVisitThreads), lds4, st, v);
+  } else {
+    hipLaunchKernelGGL(visit_kernel(f.D), dim3((f.K + TY - 1) / TY, f.items),
+                       dim3(kVisitThreads), lds, st, v);
+  }
   return hipGetLastError();
 }
 
