@@ -181,8 +181,85 @@ bbp_status bbp_kernel_stats(bbp_ctx *c, int32_t cls, const char **name,
                             double *bytes);
 bbp_status bbp_kernel_stats_reset(bbp_ctx *c);
 
+/* Device bytes the context holds now and the most it has held (every
+ * buffer it allocated for messages, fits, environments and observables). */
+bbp_status bbp_memory(const bbp_ctx *c, size_t *now, size_t *peak);
+
 const char *bbp_last_error(const bbp_ctx *c);
 void bbp_destroy(bbp_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * Request server: independent block-BP solves of finite open lattices
+ * (Sec. II; each one the problem bbp_create states) served concurrently on
+ * one GPU.  A pool of max_slots worker threads takes requests first-in
+ * first-out, each once its device-memory estimate (bbp_server_estimate) fits
+ * in what budget_bytes leaves free; a worker owns one context and one HIP
+ * stream per request, sweeps until the residual drops below tol or after
+ * max_sweeps sweeps, evaluates the requested outputs and frees the memory.
+ * Requests join and leave between sweeps; resident requests run their
+ * kernels concurrently.  Requests share no state: a result does not depend
+ * on which other requests were resident.
+ * ------------------------------------------------------------------------ */
+typedef struct bbp_server bbp_server;
+
+typedef struct {
+  int32_t Lx, Ly;     /* open lattice, tensors as for bbp_set_tensors      */
+  int32_t bx, by;     /* block size (lattice padded with trivial sites)    */
+  int32_t D, chi;     /* bond dimension and message bond cap (<= 128)      */
+  int32_t max_sweeps; /* sweep cap (>= 1)                                  */
+  int32_t outputs;    /* BBP_OUT_* bits                                    */
+  double tol;         /* residual target (>= 0)                            */
+} bbp_request;
+
+enum { BBP_OUT_SZ = 1, BBP_OUT_SS = 2, BBP_OUT_LOGNORM = 4 };
+enum {
+  BBP_REQ_QUEUED = 0,
+  BBP_REQ_RUNNING = 1,
+  BBP_REQ_DONE = 2,
+  BBP_REQ_FAILED = 3,
+  BBP_REQ_CANCELLED = 4
+};
+
+/* Upper bound of the device bytes one request's context allocates.
+ * BBP_EINVAL for a malformed request. */
+bbp_status bbp_server_estimate(const bbp_request *r, size_t *bytes);
+
+/* budget_bytes > 0; 1 <= max_slots <= 64 concurrent requests. */
+bbp_status bbp_server_create(bbp_server **out, size_t budget_bytes, int32_t max_slots);
+
+/* Queues a request; the host tensors A (n doubles, layout of
+ * bbp_set_tensors) are copied.  *ticket identifies it in later calls.
+ * Errors: BBP_EINVAL (malformed request or n), BBP_ENOMEM (estimate above
+ * the whole budget: it could never be admitted), BBP_ESTATE (server
+ * stopping). */
+bbp_status bbp_server_submit(bbp_server *s, const bbp_request *r, const double *A, size_t n,
+                             int64_t *ticket);
+
+/* State of a request (BBP_REQ_*); times (3 doubles, may be NULL) receive
+ * the submit, admit and finish times in seconds since the server was
+ * created (0 until reached).  Once BBP_REQ_DONE, out (n >= *needed doubles)
+ * receives [converged (1/0), sweeps, last residual, log|Z|, sign of Z,
+ * device bytes peak, then <sigma_z> of every site (row-major, y outer) if
+ * BBP_OUT_SZ, then <S.S> of every horizontal bond (x,y)-(x+1,y) row-major,
+ * then of every vertical bond (x,y)-(x,y+1), if BBP_OUT_SS]; log|Z| and
+ * the sign are 0 unless BBP_OUT_LOGNORM.  Errors: BBP_EINVAL (unknown
+ * ticket, or out too short). */
+bbp_status bbp_server_poll(bbp_server *s, int64_t ticket, int32_t *state, double *out, size_t n,
+                           size_t *needed, double *times);
+
+/* Cancels a queued request at once, a running one before its next sweep. */
+bbp_status bbp_server_cancel(bbp_server *s, int64_t ticket);
+
+/* Requests running and queued now, the estimated bytes admitted now, and
+ * the most requests that have run at the same time. */
+bbp_status bbp_server_stats(bbp_server *s, int32_t *running, int32_t *queued,
+                            size_t *bytes_in_use, int32_t *max_running);
+
+/* Why a request failed (empty string otherwise); valid until destroy. */
+const char *bbp_server_error(bbp_server *s, int64_t ticket);
+
+/* Cancels what is queued or running, joins the workers, frees everything. */
+void bbp_server_destroy(bbp_server *s);
 
 #ifdef __cplusplus
 }

@@ -27,8 +27,23 @@ EXPORTS = (
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
     "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
     "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
-    "bbp_kernel_stats_reset", "bbp_last_error", "bbp_destroy",
+    "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
+    "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
+    "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
+    "bbp_server_error", "bbp_server_destroy",
 )
+
+OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
+
+class Request(ctypes.Structure):
+    """bbp_request of include/bbp.h."""
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32),
+                ("bx", ctypes.c_int32), ("by", ctypes.c_int32),
+                ("D", ctypes.c_int32), ("chi", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("outputs", ctypes.c_int32),
+                ("tol", ctypes.c_double)]
 
 STATUS = {0: "BBP_OK", 1: "BBP_EINVAL", 2: "BBP_ENOMEM", 3: "BBP_EDEVICE",
           4: "BBP_ESTATE", 5: "BBP_ENUMERIC"}
@@ -66,6 +81,15 @@ def _load():
         "bbp_kernel_stats": [P, c_int, ctypes.POINTER(ctypes.c_char_p),
                              ctypes.POINTER(ctypes.c_int64), dp, dp, dp],
         "bbp_kernel_stats_reset": [P],
+        "bbp_memory": [P, ctypes.POINTER(c_size), ctypes.POINTER(c_size)],
+        "bbp_server_estimate": [ctypes.POINTER(Request), ctypes.POINTER(c_size)],
+        "bbp_server_create": [ctypes.POINTER(P), c_size, c_int],
+        "bbp_server_submit": [P, ctypes.POINTER(Request), dp, c_size,
+                              ctypes.POINTER(ctypes.c_int64)],
+        "bbp_server_poll": [P, ctypes.c_int64, ip, dp, c_size,
+                            ctypes.POINTER(c_size), dp],
+        "bbp_server_cancel": [P, ctypes.c_int64],
+        "bbp_server_stats": [P, ip, ip, ctypes.POINTER(c_size), ip],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -75,6 +99,10 @@ def _load():
     lib.bbp_last_error.restype = ctypes.c_char_p
     lib.bbp_destroy.argtypes = [P]
     lib.bbp_destroy.restype = None
+    lib.bbp_server_error.argtypes = [P, ctypes.c_int64]
+    lib.bbp_server_error.restype = ctypes.c_char_p
+    lib.bbp_server_destroy.argtypes = [P]
+    lib.bbp_server_destroy.restype = None
     return lib
 
 
@@ -235,6 +263,12 @@ class BlockBP:
     def kernel_stats_reset(self):
         self._check(_lib.bbp_kernel_stats_reset(self._ctx))
 
+    def memory(self):
+        """(bytes held now, most bytes held) on the device."""
+        now, peak = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(_lib.bbp_memory(self._ctx, ctypes.byref(now), ctypes.byref(peak)))
+        return now.value, peak.value
+
     def close(self):
         if self._ctx:
             _lib.bbp_destroy(self._ctx)
@@ -251,3 +285,110 @@ class BlockBP:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _request(Lx, Ly, bx, by, D, chi, tol=1e-10, max_sweeps=40,
+             outputs=OUT_SZ | OUT_SS | OUT_LOGNORM):
+    return Request(Lx, Ly, bx, by, D, chi, max_sweeps, outputs, tol)
+
+
+def estimate_bytes(**req):
+    """bbp_server_estimate for a request given as keyword arguments."""
+    n = ctypes.c_size_t()
+    st = _lib.bbp_server_estimate(ctypes.byref(_request(**req)), ctypes.byref(n))
+    if st != 0:
+        raise BBPError(st, "malformed request")
+    return n.value
+
+
+class Server:
+    """A libbbp request server (bbp_server_*).  ``submit`` takes the request
+    as keyword arguments (Lx, Ly, bx, by, D, chi, tol, max_sweeps, outputs)
+    and the site tensors; ``poll`` returns (state, result dict or None,
+    (submit, admit, finish) times)."""
+
+    def __init__(self, budget_bytes, max_slots):
+        self._s = ctypes.c_void_p()
+        st = _lib.bbp_server_create(ctypes.byref(self._s), int(budget_bytes),
+                                    int(max_slots))
+        if st != 0:
+            raise BBPError(st, "bbp_server_create rejected its arguments")
+        self._req = {}
+
+    def submit(self, A, **req):
+        r = _request(**req)
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        t = ctypes.c_int64()
+        st = _lib.bbp_server_submit(self._s, ctypes.byref(r), _dptr(A), A.size,
+                                    ctypes.byref(t))
+        if st != 0:
+            raise BBPError(st, "bbp_server_submit rejected the request")
+        self._req[t.value] = r
+        return t.value
+
+    def poll(self, ticket):
+        state = ctypes.c_int32()
+        need = ctypes.c_size_t()
+        times = np.zeros(3)
+        st = _lib.bbp_server_poll(self._s, ticket, ctypes.byref(state), None, 0,
+                                  ctypes.byref(need), _dptr(times))
+        if st != 0:
+            raise BBPError(st, "unknown ticket")
+        if state.value != 2:
+            return REQ_STATES[state.value], None, tuple(times)
+        out = np.zeros(need.value)
+        st = _lib.bbp_server_poll(self._s, ticket, ctypes.byref(state), _dptr(out),
+                                  out.size, ctypes.byref(need), _dptr(times))
+        if st != 0:
+            raise BBPError(st, "poll")
+        r = self._req[ticket]
+        res = dict(converged=bool(out[0]), sweeps=int(out[1]), residual=out[2],
+                   log_norm=out[3], sign=int(out[4]), peak_bytes=int(out[5]))
+        o = 6
+        if r.outputs & OUT_SZ:
+            res["sz"] = out[o:o + r.Lx * r.Ly].reshape(r.Ly, r.Lx)
+            o += r.Lx * r.Ly
+        if r.outputs & OUT_SS:
+            nb = (r.Lx - 1) * r.Ly + r.Lx * (r.Ly - 1)
+            res["ss"] = out[o:o + nb]
+        return "done", res, tuple(times)
+
+    def wait(self, ticket, timeout=600.0, interval=0.002):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            state, res, times = self.poll(ticket)
+            if state in ("done", "failed", "cancelled"):
+                return state, res, times
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} still {state}")
+            time.sleep(interval)
+
+    def cancel(self, ticket):
+        st = _lib.bbp_server_cancel(self._s, ticket)
+        if st != 0:
+            raise BBPError(st, "unknown ticket")
+
+    def error(self, ticket):
+        return _lib.bbp_server_error(self._s, ticket).decode()
+
+    def stats(self):
+        r, q, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        b = ctypes.c_size_t()
+        st = _lib.bbp_server_stats(self._s, ctypes.byref(r), ctypes.byref(q),
+                                   ctypes.byref(b), ctypes.byref(m))
+        if st != 0:
+            raise BBPError(st, "stats")
+        return dict(running=r.value, queued=q.value, bytes_in_use=b.value,
+                    max_running=m.value)
+
+    def close(self):
+        if self._s:
+            _lib.bbp_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,18 +38,47 @@ void rot_perm(char d, int perm[5]) {
 }
 bool out_reversed(char d) { return d == 'R' || d == 'U'; }
 
+// Device bytes a context holds now and at most (every API entry that may
+// allocate names its context's account for the calling thread).
+struct MemAcct {
+  size_t now = 0, peak = 0;
+};
+thread_local MemAcct *tl_acct = nullptr;
+struct AcctScope {
+  MemAcct *prev;
+  explicit AcctScope(MemAcct *a) : prev(tl_acct) { tl_acct = a; }
+  ~AcctScope() { tl_acct = prev; }
+};
+
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
+  MemAcct *acct = nullptr;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) {
+      (void)hipFree(p);
+      if (acct) acct->now -= bytes;
+    }
+    p = nullptr;
+    bytes = 0;
+    acct = nullptr;
   }
   hipError_t alloc(size_t b) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = b;
+    release();
     if (b == 0) return hipSuccess;
-    return hipMalloc(&p, b);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = b;
+    acct = tl_acct;
+    if (acct) {
+      acct->now += b;
+      acct->peak = std::max(acct->peak, acct->now);
+    }
+    return hipSuccess;
   }
   double *d() const { return (double *)p; }
 };
@@ -98,6 +127,7 @@ struct RegionResult {
 }  // namespace
 
 struct bbp_ctx {
+  MemAcct mem;  // first member: outlives every buffer below
   // problem
   int infinite = 0, Lx = 0, Ly = 0, ucx = 1, ucy = 1, bx = 1, by = 1, D = 1,
       chi = 1, d = 2;
@@ -1450,6 +1480,7 @@ bbp_status bbp_set_stream(bbp_ctx *c, void *s) {
 
 bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   if (!c || !A) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   const int D = c->D, d = c->d;
   const size_t ss = (size_t)d * D * D * D * D;
   const size_t nsites = (size_t)c->ucx * c->ucy;
@@ -1541,6 +1572,7 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
 
 bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual) {
   if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
   if (n < 0) return c->fail(BBP_EINVAL, "negative sweep count");
   double r = 0.0;
@@ -1554,6 +1586,7 @@ bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual) {
 
 bbp_status bbp_get_messages(bbp_ctx *c, double *buf, size_t n, size_t *needed) {
   if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
   const size_t per = (size_t)c->Lmax * c->S;
   size_t total = 0;
@@ -1587,6 +1620,7 @@ bbp_status bbp_get_messages(bbp_ctx *c, double *buf, size_t n, size_t *needed) {
 
 bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n) {
   if (!c || !buf) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
   const size_t per = (size_t)c->Lmax * c->S;
   std::vector<double> host(per * c->msgs.size(), 0.0);
@@ -1637,27 +1671,36 @@ bbp_status bbp_stats(bbp_ctx *c, int32_t *n_messages, double *sweep_flops) {
 
 bbp_status bbp_expect_site(bbp_ctx *c, int32_t x, int32_t y, const double *op,
                            double *out) {
+  if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   return expect_many(c, 1, &x, &y, nullptr, nullptr, false, op, out);
 }
 
 bbp_status bbp_expect_bond(bbp_ctx *c, int32_t x0, int32_t y0, int32_t x1,
                            int32_t y1, const double *op, double *out) {
+  if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   return expect_many(c, 1, &x0, &y0, &x1, &y1, true, op, out);
 }
 
 bbp_status bbp_expect_sites(bbp_ctx *c, int32_t n, const int32_t *xs,
                             const int32_t *ys, const double *op, double *out) {
+  if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   return expect_many(c, n, xs, ys, nullptr, nullptr, false, op, out);
 }
 
 bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
                             const int32_t *y0, const int32_t *x1,
                             const int32_t *y1, const double *op, double *out) {
+  if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   return expect_many(c, n, x0, y0, x1, y1, true, op, out);
 }
 
 bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {
   if (!c || !log_abs) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
   if (c->chi_env < c->chi)
     return c->fail(BBP_EINVAL, "chi_env must be at least chi");
@@ -1721,6 +1764,13 @@ bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {
   }
   *log_abs = total;
   if (sign) *sign = sg;
+  return BBP_OK;
+}
+
+bbp_status bbp_memory(const bbp_ctx *c, size_t *now, size_t *peak) {
+  if (!c) return BBP_EINVAL;
+  if (now) *now = c->mem.now;
+  if (peak) *peak = c->mem.peak;
   return BBP_OK;
 }
 

@@ -6,6 +6,10 @@
 // bond cap, P = D^2 the fused double-layer leg), so all contractions of a
 // batch have the same shape; zero padding stays exactly zero through every
 // contraction, and the QR works on the true panel only.
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "bbp_internal.h"
@@ -21,8 +25,11 @@ struct TimedLaunch {
   hipEvent_t a, b;
   double flops, bytes;
 };
+// Launch timing is process-wide; its lists are guarded so contexts used from
+// several host threads (the request server) can time concurrently.
 struct TimingState {
-  bool on = false;
+  std::atomic<bool> on{false};
+  std::recursive_mutex mu;
   std::vector<TimedLaunch> done;
   std::vector<hipEvent_t> pool;
   long long launches[KC_COUNT] = {};
@@ -34,6 +41,7 @@ TimingState &timing() {
 }
 hipEvent_t take_event() {
   TimingState &t = timing();
+  std::lock_guard<std::recursive_mutex> lk(t.mu);
   if (!t.pool.empty()) {
     hipEvent_t e = t.pool.back();
     t.pool.pop_back();
@@ -46,6 +54,7 @@ hipEvent_t take_event() {
 // Folds completed event pairs into the per-class totals.
 hipError_t drain() {
   TimingState &t = timing();
+  std::lock_guard<std::recursive_mutex> lk(t.mu);
   for (TimedLaunch &l : t.done) {
     hipError_t e = hipEventSynchronize(l.b);
     if (e != hipSuccess) return e;
@@ -70,12 +79,14 @@ struct Span {
   hipEvent_t a = nullptr;
   Span(int c, hipStream_t s, double f, double b) : cls(c), st(s), flops(f), bytes(b) {
     if (!timing().on) return;
+    std::lock_guard<std::recursive_mutex> lk(timing().mu);
     if (timing().done.size() > 4096) (void)drain();
     a = take_event();
     if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
   }
   ~Span() {
     if (!a) return;
+    std::lock_guard<std::recursive_mutex> lk(timing().mu);
     hipEvent_t b = take_event();
     if (b && hipEventRecord(b, st) == hipSuccess)
       timing().done.push_back(TimedLaunch{cls, a, b, flops, bytes});
@@ -89,8 +100,9 @@ const char *kClassNames[KC_COUNT] = {"fit_visit", "fit_T1",  "fit_ket",
 void timing_enable(bool on) { timing().on = on; }
 bool timing_enabled() { return timing().on; }
 void timing_reset() {
-  (void)drain();
   TimingState &t = timing();
+  std::lock_guard<std::recursive_mutex> lk(t.mu);
+  (void)drain();
   for (int i = 0; i < KC_COUNT; ++i) {
     t.launches[i] = 0;
     t.ms[i] = t.flops[i] = t.bytes[i] = 0.0;
@@ -98,9 +110,10 @@ void timing_reset() {
 }
 hipError_t timing_query(int cls, const char **name, long long *launches,
                         double *ms, double *flops, double *bytes) {
+  TimingState &t = timing();
+  std::lock_guard<std::recursive_mutex> lk(t.mu);
   hipError_t e = drain();
   if (e != hipSuccess) return e;
-  TimingState &t = timing();
   if (name) *name = kClassNames[cls];
   if (launches) *launches = t.launches[cls];
   if (ms) *ms = t.ms[cls];
@@ -120,6 +133,18 @@ constexpr int kThreads = 256;
 // slices of A and B in LDS and 16 x 16 threads accumulate TM x TN tiles.
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// LDS row strides that keep the MFMA operand reads free of bank conflicts
+// (64-bit words, 32 word pairs per bank row; a read serves 16 lanes along the
+// tile and 2 lane groups along k together): a row that the 16 lanes walk as
+// the A operand gets a stride of 2 (mod 32), a row that 2 lane groups walk as
+// the B operand a stride of 16 (mod 32).
+__host__ __device__ constexpr int pad_a(int x) { return x + (34 - x % 32) % 32; }
+__host__ __device__ constexpr int pad_b(int x) { return x + (48 - x % 32) % 32; }
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 template <int BM, int BN, int BK, class Op>
 __global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
@@ -356,6 +381,94 @@ struct OpK5 {
   }
 };
 
+// ---- environment update after the QR, Lenv' = T3 . Y ----------------------
+// E[y'][wb][xb] = sum_{yf, l} Y[yf][l][y'] T3[yf][l][xb][wb]  (RL: Y[y'][l][yf]).
+// One workgroup of 4 waves per (item, 64 columns n = (xb, wb)); each wave owns
+// 16 columns and all MT row tiles of y'.  The T3 operand is read straight
+// from global memory (16 lanes, 128 contiguous bytes); Y is staged in LDS in
+// chunks of 32 k = (yf, l).  The next chunk of both is fetched into registers
+// while the current one is multiplied; one barrier per chunk.
+struct EnvArgs {
+  int K, P, rl;
+  const double *t3;
+  size_t t3s;
+  Ptr Y, E;
+};
+
+constexpr int kEnvThreads = 256;
+
+template <int MT>
+__global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
+  constexpr int MW = MT * 16, AS = pad_b(MW), CH = 32;
+  constexpr int NA = CH * MW / kEnvThreads;  // A elements staged per thread
+  __shared__ double As[2][CH][AS];
+  const int K = e.K, P = e.P, N = K * P, Kd = K * P;
+  const int it = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int n = blockIdx.x * 64 + wave * 16 + lr;
+  const double *T3 = e.t3 + (size_t)it * e.t3s;
+  const double *Y = e.Y.at(it);
+  const bool rl = e.rl != 0;
+  double an[NA], bn[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int i = tid + u * kEnvThreads, kk = i / MW, m = i % MW, k = k0 + kk;
+      double x = 0.0;
+      if (m < K && k < Kd) {
+        const int yf = k / P, l = k - yf * P;
+        x = rl ? Y[((size_t)m * P + l) * K + yf] : Y[(size_t)k * K + m];
+      }
+      an[u] = x;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + 4 * i + lq;
+      bn[i] = (n < N && k < Kd) ? T3[(size_t)k * N + n] : 0.0;
+    }
+  };
+  auto put = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int i = tid + u * kEnvThreads;
+      As[buf][i / MW][i % MW] = an[u];
+    }
+  };
+  v4d acc[MT][2];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = v4d{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  put(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < Kd; k0 += CH) {
+    double bc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bc[i] = bn[i];
+    if (k0 + CH < Kd) fetch(k0 + CH);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[mt][i & 1] = mfma16(As[buf][4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i & 1]);
+    if (k0 + CH < Kd) put(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (n >= N) return;
+  const int xb = n / P, wb = n - xb * P;
+  double *E = e.E.at(it);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const v4d c = acc[mt][0] + acc[mt][1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = mt * 16 + 4 * r + lq;
+      if (m < K) E[((size_t)m * P + wb) * K + xb] = c[r];
+    }
+  }
+}
+
 // ---- end-site visit (message site as MPO: Mend[a][q][a']) ----------------
 // T[a][q][xb] = sum_{a'} Mend[a][q][a'] X_e[a'][xb]
 struct OpE1 {
@@ -504,10 +617,6 @@ struct VisitArgs {
 constexpr int kVisitThreads = 512;
 constexpr int kVisitWaves = kVisitThreads / 64;
 
-__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 // One batched LDS GEMM: for batch p < nb, C_p[M][N] = A_p[M][Kd] B_p[Kd][N];
 // 16 x 16 output tiles spread over the waves, two per wave at a time when
 // there are enough; each tile keeps two accumulators (even and odd k-steps)
@@ -562,14 +671,6 @@ __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
     }
   }
 }
-
-// LDS row strides that keep the MFMA operand reads free of bank conflicts
-// (64-bit words, 32 word pairs per bank row; a read serves 16 lanes along the
-// tile and 2 lane groups along k together): a row that the 16 lanes walk as
-// the A operand gets a stride of 2 (mod 32), a row that 2 lane groups walk as
-// the B operand a stride of 16 (mod 32).
-__host__ __device__ constexpr int pad_a(int x) { return x + (34 - x % 32) % 32; }
-__host__ __device__ constexpr int pad_b(int x) { return x + (48 - x % 32) % 32; }
 
 // Doubles of dynamic LDS for one fused-visit workgroup with tiles TY x TX.
 __host__ __device__ inline size_t visit_lds(int K, int P, int d, int TY, int TX) {
@@ -1856,23 +1957,24 @@ static VisitKernel visit4_kernel(int TY, int TX) {
 static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
                                Ptr F, Ptr G, Ptr Y, bool do_local, int TY,
                                int TX, size_t lds, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] {
     for (int D : {0, 2, 3, 4, 5, 6}) {
       hipError_t e = hipFuncSetAttribute(
           (const void *)visit_kernel(D),
           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) return e;
+      if (e != hipSuccess) attr_err = e;
     }
     for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2), std::make_pair(2, 2),
                    std::make_pair(1, 2), std::make_pair(1, 1)}) {
       hipError_t e = hipFuncSetAttribute(
           (const void *)visit4_kernel(t.first, t.second),
           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) return e;
+      if (e != hipSuccess) attr_err = e;
     }
-    attr_set = true;
-  }
+  });
+  if (attr_err != hipSuccess) return attr_err;
   int TY4, TX4;
   size_t lds4;
   const bool spec = visit4_tiles(f, &TY4, &TX4, &lds4);
@@ -2009,11 +2111,21 @@ hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
 
 hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
                             hipStream_t st) {
-  OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
-          t1_stride(f), Y, envOut};
   const double it = f.items, K = f.K, P = f.P;
   Span sp(KC_ENV, st, it * 2 * K * K * P * K * P,
           it * 8 * (K * K * P * P + 2 * K * P * K));
+  if (f.K <= 64) {
+    EnvArgs e{f.K, f.P, rl ? 1 : 0, f.t3, t1_stride(f), Y, envOut};
+    const dim3 grid((f.K * f.P + 63) / 64, f.items);
+    const int mt = (f.K + 15) / 16;
+    if (mt <= 1) hipLaunchKernelGGL(k_env<1>, grid, dim3(kEnvThreads), 0, st, e);
+    else if (mt <= 2) hipLaunchKernelGGL(k_env<2>, grid, dim3(kEnvThreads), 0, st, e);
+    else if (mt <= 3) hipLaunchKernelGGL(k_env<3>, grid, dim3(kEnvThreads), 0, st, e);
+    else hipLaunchKernelGGL(k_env<4>, grid, dim3(kEnvThreads), 0, st, e);
+    return hipGetLastError();
+  }
+  OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
+          t1_stride(f), Y, envOut};
   return run_gemm<32, 64, 16>(k5, f.items, st);
 }
 
