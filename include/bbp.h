@@ -84,7 +84,9 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
 
 /* Launch all work of this context on the given hipStream_t (default: the
  * null stream).  The pointer is a HIP stream handle; NULL selects the null
- * stream. */
+ * stream.  Every transfer the context makes is ordered on this stream, so a
+ * non-blocking stream is fine; it must stay valid until bbp_destroy, which
+ * synchronises it. */
 bbp_status bbp_set_stream(bbp_ctx *c, void *hip_stream);
 
 /*

@@ -290,6 +290,21 @@ void column_dims(int W, int H, int K, int P, const std::vector<int> &mt,
 
 }  // namespace
 
+// Host <-> device transfers are ordered on the context's stream (a server
+// worker's stream is non-blocking, so the null stream would not wait for it);
+// the stream is synchronised before the host buffer is read or released.
+static hipError_t copy_sync(bbp_ctx *c, void *dst, const void *src, size_t bytes,
+                            hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+static hipError_t zero_sync(bbp_ctx *c, void *p, size_t bytes) {
+  hipError_t e = hipMemsetAsync(p, 0, bytes, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
 // ---------------------------------------------------------------------------
 static bbp_status ensure_device(bbp_ctx *c) {
   if (c->device_ready) return BBP_OK;
@@ -381,7 +396,7 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.err = (int32_t *)c->errflag.p;
   g.dims.assign(it * f.W, FitDims{});
   g.have.assign(it * f.W, 0);
-  e = hipMemcpy(f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
+  e = copy_sync(c, f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload slots");
   return BBP_OK;
 }
@@ -402,7 +417,7 @@ static bbp_status upload_rotated(bbp_ctx *c, Group &g) {
                     host.data() + (((size_t)i * f.H + yc) * f.W + xc) * ss);
       }
   }
-  hipError_t e = hipMemcpy(f.acan, host.data(), host.size() * 8,
+  hipError_t e = copy_sync(c, f.acan, host.data(), host.size() * 8,
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload tensors");
   return BBP_OK;
@@ -420,7 +435,7 @@ static bbp_status init_messages(bbp_ctx *c) {
       for (int k = 0; k < c->D; ++k)
         host[e * per + (size_t)s * c->S + (size_t)(k * c->D + k) * c->K] = v;
   }
-  hipError_t err = hipMemcpy(c->msgbuf[c->cur].p, host.data(), host.size() * 8,
+  hipError_t err = copy_sync(c, c->msgbuf[c->cur].p, host.data(), host.size() * 8,
                              hipMemcpyHostToDevice);
   if (err != hipSuccess) return c->hip_fail(err, "upload messages");
   for (auto &g : c->groups) std::fill(g->have.begin(), g->have.end(), 0);
@@ -673,7 +688,7 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
     for (size_t i = 0; i < ids.size(); ++i) ov[ids[i]] = part[i];
   }
   int32_t errv = 0;
-  e = hipMemcpy(&errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
+  e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return c->hip_fail(e, "error flag");
   double sum = 0.0;
   bool finite = true;
@@ -913,7 +928,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     sg.push_back(std::move(gp));
   }
   int32_t errv = 0;
-  e = hipMemcpy(&errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
+  e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return c->hip_fail(e, "error flag");
   if (errv) return c->fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
 
@@ -999,7 +1014,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     DevBuf djobs;
     if (djobs.alloc(sizeof(CopyJob) * jobs.size()) != hipSuccess)
       return c->fail(BBP_ENOMEM, "device allocation failed");
-    e = hipMemcpy(djobs.p, jobs.data(), sizeof(CopyJob) * jobs.size(),
+    e = copy_sync(c, djobs.p, jobs.data(), sizeof(CopyJob) * jobs.size(),
                   hipMemcpyHostToDevice);
     for (size_t o = 0; e == hipSuccess && o < jobs.size(); o += 60000)
       e = launch_copy_jobs((const CopyJob *)djobs.p + o,
@@ -1110,10 +1125,10 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         if (ujobs.alloc(sizeof(CopyJob) * uj.size()) != hipSuccess)
           return c->fail(BBP_ENOMEM, "device allocation failed");
         if (e == hipSuccess)
-          e = hipMemcpy(ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
+          e = copy_sync(c, ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
                         hipMemcpyHostToDevice);
         if (e == hipSuccess)
-          e = hipMemcpy(tabs.p, tab.data(), tab.size() * sizeof(double *),
+          e = copy_sync(c, tabs.p, tab.data(), tab.size() * sizeof(double *),
                         hipMemcpyHostToDevice);
         if (e == hipSuccess)
           e = launch_copy_jobs((const CopyJob *)ujobs.p, (int)uj.size(), Kenv, P, st);
@@ -1167,8 +1182,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         dout.alloc(pa.size() * 8) != hipSuccess)
       return c->fail(BBP_ENOMEM, "device allocation failed");
     std::vector<double> vals(pa.size());
-    e = hipMemcpy(da.p, pa.data(), pa.size() * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(db.p, pb.data(), pb.size() * 8, hipMemcpyHostToDevice);
+    e = copy_sync(c, da.p, pa.data(), pa.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = copy_sync(c, db.p, pb.data(), pb.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = launch_dots((int)pa.size(), (const double *const *)da.p,
                       (const double *const *)db.p, f.S, dout.d(), st);
@@ -1525,14 +1540,14 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       c->ovOut.alloc(nm * 8) != hipSuccess || c->ovA.alloc(nm * 8) != hipSuccess ||
       c->ovB.alloc(nm * 8) != hipSuccess || c->errflag.alloc(64) != hipSuccess)
     return c->fail(BBP_ENOMEM, "device allocation failed");
-  if (hipMemset(c->errflag.p, 0, c->errflag.bytes) != hipSuccess ||
-      hipMemset(c->msgbuf[0].p, 0, c->msgbuf[0].bytes) != hipSuccess ||
-      hipMemset(c->msgbuf[1].p, 0, c->msgbuf[1].bytes) != hipSuccess)
+  if (zero_sync(c, c->errflag.p, c->errflag.bytes) != hipSuccess ||
+      zero_sync(c, c->msgbuf[0].p, c->msgbuf[0].bytes) != hipSuccess ||
+      zero_sync(c, c->msgbuf[1].p, c->msgbuf[1].bytes) != hipSuccess)
     return c->fail(BBP_EDEVICE, "clear message buffers");
   {
     std::vector<double> triv(per, 0.0);
     for (int s2 = 0; s2 < c->Lmax; ++s2) triv[(size_t)s2 * c->S] = 1.0;
-    if (hipMemcpy(c->trivial.p, triv.data(), per * 8, hipMemcpyHostToDevice) !=
+    if (copy_sync(c, c->trivial.p, triv.data(), per * 8, hipMemcpyHostToDevice) !=
         hipSuccess)
       return c->fail(BBP_EDEVICE, "upload trivial message");
   }
@@ -1564,7 +1579,7 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   }
   if ((s = init_messages(c)) != BBP_OK) return s;
   c->obs.clear();
-  hipError_t e = hipDeviceSynchronize();
+  hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "set_tensors");
   c->tensors_set = true;
   return BBP_OK;
@@ -1599,7 +1614,7 @@ bbp_status bbp_get_messages(bbp_ctx *c, double *buf, size_t n, size_t *needed) {
   if (!buf) return BBP_OK;
   if (n < total) return c->fail(BBP_EINVAL, "buffer too small");
   std::vector<double> host(per * c->msgs.size());
-  hipError_t e = hipMemcpy(host.data(), c->msgbuf[c->cur].p, host.size() * 8,
+  hipError_t e = copy_sync(c, host.data(), c->msgbuf[c->cur].p, host.size() * 8,
                            hipMemcpyDeviceToHost);
   if (e != hipSuccess) return c->hip_fail(e, "download messages");
   size_t o = 0;
@@ -1653,7 +1668,7 @@ bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n) {
     }
   }
   if (o != n) return c->fail(BBP_EINVAL, "message buffer has trailing data");
-  hipError_t e = hipMemcpy(c->msgbuf[c->cur].p, host.data(), host.size() * 8,
+  hipError_t e = copy_sync(c, c->msgbuf[c->cur].p, host.data(), host.size() * 8,
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload messages");
   for (size_t i = 0; i < c->msgs.size(); ++i) c->msgs[i].bonds = bonds[i];
@@ -1742,9 +1757,9 @@ bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {
       pb.push_back(cur + (size_t)eb[t] * per);
     }
     std::vector<double> ov(pa.size());
-    hipError_t e = hipMemcpy(c->ovA.p, pa.data(), 8 * pa.size(), hipMemcpyHostToDevice);
+    hipError_t e = copy_sync(c, c->ovA.p, pa.data(), 8 * pa.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-      e = hipMemcpy(c->ovB.p, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice);
+      e = copy_sync(c, c->ovB.p, pb.data(), 8 * pb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = launch_overlap((int)pa.size(), c->K, c->P, kv.first,
                          (const double *const *)c->ovA.p,
@@ -1799,7 +1814,7 @@ const char *bbp_last_error(const bbp_ctx *c) {
 
 void bbp_destroy(bbp_ctx *c) {
   if (!c) return;
-  if (c->device_ready) (void)hipDeviceSynchronize();
+  if (c->device_ready) (void)hipStreamSynchronize(c->stream);
   delete c;
 }
 
