@@ -78,6 +78,12 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *   "n_fit"    full fit sweeps per column absorption (default 2, App. A)
  *   "seed"     seed of the counter-based fit initial states (default 0)
  *   "timing"   1: record per-kernel-class launch times (any time; resets)
+ *   "precision" 64 (default) or 32 (any time): with 32 the fit's visit and
+ *              environment contractions run on FP32 MFMA with FP32
+ *              accumulation (D = 4 kernels, bond cap <= 64; other shapes
+ *              stay FP64); QR, normalisation, overlaps and every stored
+ *              message stay FP64.  Sweeps in 32 followed by sweeps in 64
+ *              reach the FP64 fixed point from the FP32 one.
  * Unknown keys or out-of-range values: BBP_EINVAL.
  */
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);

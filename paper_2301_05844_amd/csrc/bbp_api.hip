@@ -133,6 +133,7 @@ struct bbp_ctx {
       chi = 1, d = 2;
   int gx = 1, gy = 1;
   int chi_env = -1, n_fit = 2;
+  int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   bool tensors_set = false;
@@ -343,6 +344,7 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.N = g.H + 2;
   f.S = (size_t)bond_cap * c->P * bond_cap;
   f.seed = c->seed;
+  f.prec = c->precision;
   const size_t it = f.items, S = f.S, K = f.K, P = f.P;
   const bool fused = visit_fused_fits(f);
   const bool fit = (need & NEED_FIT) != 0, scr = (need & NEED_SCRATCH) != 0;
@@ -1457,7 +1459,7 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   if (!c || !key) return BBP_EINVAL;
   std::string k(key);
-  const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing");
+  const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing" || k == "precision");
   if (c->tensors_set && !late_ok)
     return c->fail(BBP_ESTATE, "option must be set before bbp_set_tensors");
   if (!std::isfinite(v)) return c->fail(BBP_EINVAL, "non-finite option value");
@@ -1477,6 +1479,11 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   } else if (k == "timing") {
     bbp::timing_enable(v != 0.0);
     bbp::timing_reset();
+  } else if (k == "precision") {
+    if (v != 64 && v != 32) return c->fail(BBP_EINVAL, "precision must be 64 or 32");
+    c->precision = (int)v;
+    for (auto &g : c->groups) g->fb.prec = c->precision;
+    c->obs.clear();
   } else if (k == "seed") {
     if (v < 0 || v != std::floor(v) || v > 9007199254740992.0)
       return c->fail(BBP_EINVAL, "seed must be a non-negative integer");

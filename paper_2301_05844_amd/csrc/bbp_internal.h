@@ -49,6 +49,7 @@ struct FitBatch {
   FitDims *dims = nullptr;  // [items][W]
   uint64_t *slot = nullptr; // [items] random-state slot base
   uint64_t seed = 0;
+  int prec = 64;  // 64: FP64 contractions; 32: visit and environment update on FP32 MFMA
 };
 
 // Visit kinds of the fit engine.

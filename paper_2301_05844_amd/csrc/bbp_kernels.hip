@@ -146,6 +146,37 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Orders one wave's LDS writes before its later LDS reads (other lanes).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Contraction type of the specialised kernels: FP64, or FP32 on FP32 MFMA
+// with FP32 accumulation (the precision option).  LDS stride residues for
+// 4-byte words: A-operand rows 4 (mod 64), B-operand rows 16 (mod 64).
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <class T> struct Mma;
+// crow(r, lq): tile row held by accumulator register r of a lane in row
+// group lq (FP64 MFMA: 4r + lq; FP32 16x16x4 MFMA: 4lq + r, as probed).
+template <> struct Mma<double> {
+  typedef v4d acc;
+  static __device__ __forceinline__ int crow(int r, int lq) { return 4 * r + lq; }
+  static __device__ __forceinline__ v4d run(double a, double b, v4d c) { return mfma16(a, b, c); }
+  static __host__ __device__ constexpr int pad_a(int x) { return bbp::pad_a(x); }
+  static __host__ __device__ constexpr int pad_b(int x) { return bbp::pad_b(x); }
+};
+template <> struct Mma<float> {
+  typedef v4f acc;
+  static __device__ __forceinline__ int crow(int r, int lq) { return 4 * lq + r; }
+  static __device__ __forceinline__ v4f run(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __host__ __device__ constexpr int pad_a(int x) { return x + (68 - x % 64) % 64; }
+  static __host__ __device__ constexpr int pad_b(int x) { return x + (80 - x % 64) % 64; }
+};
+
 template <int BM, int BN, int BK, class Op>
 __global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
   const int it = blockIdx.z;
@@ -397,19 +428,21 @@ struct EnvArgs {
 
 constexpr int kEnvThreads = 256;
 
-template <int MT>
+template <int MT, class T>
 __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
-  constexpr int MW = MT * 16, AS = pad_b(MW), CH = 32;
+  typedef Mma<T> M;
+  typedef typename M::acc Acc;
+  constexpr int MW = MT * 16, AS = M::pad_b(MW), CH = 32;
   constexpr int NA = CH * MW / kEnvThreads;  // A elements staged per thread
-  __shared__ double As[2][CH][AS];
+  __shared__ T As[2][CH][AS];
   const int K = e.K, P = e.P, N = K * P, Kd = K * P;
   const int it = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   const int n = blockIdx.x * 64 + wave * 16 + lr;
-  const double *T3 = e.t3 + (size_t)it * e.t3s;
+  const T *T3 = reinterpret_cast<const T *>(e.t3) + (size_t)it * e.t3s;
   const double *Y = e.Y.at(it);
   const bool rl = e.rl != 0;
-  double an[NA], bn[8];
+  T an[NA], bn[8];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
@@ -419,12 +452,12 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
         const int yf = k / P, l = k - yf * P;
         x = rl ? Y[((size_t)m * P + l) * K + yf] : Y[(size_t)k * K + m];
       }
-      an[u] = x;
+      an[u] = (T)x;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + 4 * i + lq;
-      bn[i] = (n < N && k < Kd) ? T3[(size_t)k * N + n] : 0.0;
+      bn[i] = (n < N && k < Kd) ? T3[(size_t)k * N + n] : (T)0;
     }
   };
   auto put = [&](int buf) {
@@ -434,15 +467,15 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
       As[buf][i / MW][i % MW] = an[u];
     }
   };
-  v4d acc[MT][2];
+  Acc acc[MT][2];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = Acc{0, 0, 0, 0};
   fetch(0);
   put(0);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < Kd; k0 += CH) {
-    double bc[8];
+    T bc[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) bc[i] = bn[i];
     if (k0 + CH < Kd) fetch(k0 + CH);
@@ -450,7 +483,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        acc[mt][i & 1] = mfma16(As[buf][4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i & 1]);
+        acc[mt][i & 1] = M::run(As[buf][4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i & 1]);
     if (k0 + CH < Kd) put(buf ^ 1);
     __syncthreads();
     buf ^= 1;
@@ -460,11 +493,11 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
   double *E = e.E.at(it);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    const v4d c = acc[mt][0] + acc[mt][1];
+    const Acc c = acc[mt][0] + acc[mt][1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = mt * 16 + 4 * r + lq;
-      if (m < K) E[((size_t)m * P + wb) * K + xb] = c[r];
+      const int m = mt * 16 + M::crow(r, lq);
+      if (m < K) E[((size_t)m * P + wb) * K + xb] = (double)c[r];
     }
   }
 }
@@ -912,48 +945,55 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
 __host__ __device__ inline int ceil4(int x) { return (x + 3) & ~3; }
 __host__ __device__ inline int ceil16(int x) { return (x + 15) & ~15; }
 
+// LDS elements (of T) of one k_visit4 workgroup.
+template <class T>
 __host__ __device__ inline size_t visit4_lds(int K, int TY, int TX) {
+  typedef Mma<T> M;
   const int K4 = ceil4(K);
-  return (size_t)TY * 16 * pad_a(K4) + (size_t)K4 * pad_b(16 * TX) + (size_t)TY * TX * 256 +
-         (size_t)TY * TX * 16 * pad_b(32) + (size_t)TY * TX * 256 + (size_t)TX * 16 * pad_b(K) +
-         2 * 2 * 256;
+  return (size_t)TY * 16 * M::pad_a(K4) + (size_t)K4 * M::pad_b(16 * TX) + (size_t)TY * TX * 256 +
+         (size_t)TY * TX * 16 * M::pad_b(32) + (size_t)TY * TX * 256 +
+         (size_t)TX * 16 * M::pad_b(K) + 2 * 2 * 256;
 }
 
 // acc[0] / acc[1] += sum over N k-steps (even / odd) of A(pa + i*da) B(pb + i*db)
-template <int N>
-__device__ __forceinline__ void mma_steps(v4d (&acc)[2], const double *pa, int da,
-                                          const double *pb, int db) {
-  double av[N], bv[N];
+template <int N, class T>
+__device__ __forceinline__ void mma_steps(typename Mma<T>::acc (&acc)[2], const T *pa, int da,
+                                          const T *pb, int db) {
+  T av[N], bv[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     av[i] = pa[i * da];
     bv[i] = pb[i * db];
   }
 #pragma unroll
-  for (int i = 0; i < N; ++i) acc[i & 1] = mfma16(av[i], bv[i], acc[i & 1]);
+  for (int i = 0; i < N; ++i) acc[i & 1] = Mma<T>::run(av[i], bv[i], acc[i & 1]);
 }
 
-template <int TY, int TX>
+template <int TY, int TX, class T>
 __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
-  extern __shared__ double sm[];
+  extern __shared__ double sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
+  typedef Mma<T> M;
+  typedef typename M::acc Acc;
+  const Acc zero = Acc{0, 0, 0, 0};
   constexpr int D = 4, P = 16, P2 = 256, NP = TY * TX;
-  constexpr int XS = pad_b(16 * TX), T2S = pad_b(32);
-  const int K = v.K, K4 = ceil4(K), FS = pad_a(K4), GS = pad_b(K), KY = ceil16(K);
+  constexpr int XS = M::pad_b(16 * TX), T2S = M::pad_b(32);
+  const int K = v.K, K4 = ceil4(K), FS = M::pad_a(K4), GS = M::pad_b(K), KY = ceil16(K);
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
-  double *Fs = sm;
-  double *Xs = Fs + TY * 16 * FS;
-  double *T1s = Xs + K4 * XS;
-  double *T2s = T1s + NP * P2;
-  double *T3s = T2s + NP * 16 * T2S;
-  double *Gs = T3s + NP * P2;
-  double *Ak = Gs + TX * 16 * GS;
-  double *Ab = Ak + 2 * P2;
+  T *Fs = sm;
+  T *Xs = Fs + TY * 16 * FS;
+  T *T1s = Xs + K4 * XS;
+  T *T2s = T1s + NP * P2;
+  T *T3s = T2s + NP * 16 * T2S;
+  T *Gs = T3s + NP * P2;
+  T *Ak = Gs + TX * 16 * GS;
+  T *Ab = Ak + 2 * P2;
   const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
   const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
-  double *T3g = v.t3 + (size_t)it * v.t3_stride;
+  T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
   const bool rl = v.rl != 0;
 
   // site tensors as [s][wf][a][l][wb] of the front view (RL swaps u and d)
@@ -961,30 +1001,30 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
     const int wb = i & 3, l = (i >> 2) & 3, a = (i >> 4) & 3, wf = (i >> 6) & 3, s = i >> 8;
     const int u = rl ? wb : wf, dd = rl ? wf : wb;
     const int src = ((((s * D + u) * D + l) * D + dd) * D + a);
-    Ak[i] = ak[src];
-    Ab[i] = ab[src];
+    Ak[i] = (T)ak[src];
+    Ab[i] = (T)ab[src];
   }
   // F rows of the y tile, zero beyond K (and beyond the lattice edge in yf)
   for (int row = wave; row < TY * 16; row += kVisitWaves) {
     const bool ok = y0 + (row >> 4) < K;
     for (int xf = lane; xf < K4; xf += 64)
-      Fs[row * FS + xf] = (ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
+      Fs[row * FS + xf] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
   }
   // local-update accumulators: TY x (KY/16) tiles of [(ty, l)][yb]; each
   // tile's k range (tx, wb) is split over two waves when tiles are few
   const int tne = KY >> 4, ntile_e = TY * tne;
   const bool split_e = 2 * ntile_e <= kVisitWaves;
   constexpr int kMaxE = 4;
-  v4d accE[kMaxE];
+  Acc accE[kMaxE];
 #pragma unroll
-  for (int q = 0; q < kMaxE; ++q) accE[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < kMaxE; ++q) accE[q] = zero;
 
   // The X and G tiles of the next xb step are fetched into registers while
   // the current step computes.  Each thread moves up to kLd elements of each;
   // their offsets (global relative to the tile, LDS) are decoded once.
   constexpr int kLd = 8;  // host keeps K4*16*TX and KY*16*TX within 8*512
   int xg[kLd], xl[kLd], gg[kLd], gl[kLd];
-  double xr[kLd], gr[kLd];
+  T xr[kLd], gr[kLd];
 #pragma unroll
   for (int u = 0; u < kLd; ++u) {
     const int i = tid + u * kVisitThreads;
@@ -1014,8 +1054,8 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
     for (int u = 0; u < kLd; ++u) {
       const int xtx = (xl[u] >> 24) & 0x7f, gtx = (gl[u] >> 24) & 0x7f;
       const size_t xo = rl ? (size_t)x0 * P * K : (size_t)x0;
-      xr[u] = (xg[u] >= 0 && x0 + xtx < K) ? X[xo + xg[u]] : 0.0;
-      gr[u] = (v.do_local && gg[u] >= 0 && x0 + gtx < K) ? G[(size_t)x0 + gg[u]] : 0.0;
+      xr[u] = (T)((xg[u] >= 0 && x0 + xtx < K) ? X[xo + xg[u]] : 0.0);
+      gr[u] = (T)((v.do_local && gg[u] >= 0 && x0 + gtx < K) ? G[(size_t)x0 + gg[u]] : 0.0);
     }
   };
   fetch(0);
@@ -1032,42 +1072,48 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
     // (a) T1: tiles (ty, tn): rows (ty, wf), cols n = (a, tx) in [16 tn, 16 tn + 16)
     for (int t = wave; t < TY * TX; t += kVisitWaves) {
       const int ty = t / TX, tn = t % TX;
-      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
-      const double *pa = Fs + (ty * 16 + lr) * FS + lq;
-      const double *pb = Xs + lq * XS + tn * 16 + lr;
+      Acc acc[2] = {zero, zero};
+      const T *pa = Fs + (ty * 16 + lr) * FS + lq;
+      const T *pb = Xs + lq * XS + tn * 16 + lr;
       int k0 = 0;
       for (; k0 + 16 <= K4; k0 += 16) mma_steps<4>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
       for (; k0 < K4; k0 += 4) mma_steps<1>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
-      const v4d c = acc[0] + acc[1];
+      const Acc c = acc[0] + acc[1];
       const int n = tn * 16 + lr, a = n / TX, tx = n % TX;
-      double *dst = T1s + (ty * TX + tx) * P2 + (a >> 2) * 16 + lq * 4 + (a & 3);
+      T *dst = T1s + (ty * TX + tx) * P2 + (a >> 2) * 16 + (a & 3);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[r * 64] = c[r];  // wf = 4r + lq: wfk = r, wfb = lq
+      for (int r = 0; r < 4; ++r) {  // wf = (wfk, wfb)
+        const int wf = M::crow(r, lq);
+        dst[(wf >> 2) * 64 + (wf & 3) * 4] = c[r];
+      }
     }
     __syncthreads();
     // (b) ket: per pair, rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
     for (int t = wave; t < 2 * NP; t += kVisitWaves) {
       const int pp = t >> 1, sn = t & 1;
-      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+      Acc acc[2] = {zero, zero};
       mma_steps<4>(acc, T1s + pp * P2 + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
-      const v4d c = acc[0] + acc[1];
-      double *dst = T2s + (pp * 16 + lq) * T2S + sn * 16 + lr;
+      const Acc c = acc[0] + acc[1];
+      T *dst = T2s + pp * 16 * T2S + sn * 16 + lr;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[r * 4 * T2S] = c[r];
+      for (int r = 0; r < 4; ++r) dst[M::crow(r, lq) * T2S] = c[r];
     }
     __syncthreads();
     // (c) bra: per pair, rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb)
     for (int t = wave; t < NP; t += kVisitWaves) {
-      v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
+      Acc acc[2] = {zero, zero};
 #pragma unroll
       for (int sn = 0; sn < 2; ++sn)
         mma_steps<4>(acc, T2s + (t * 16 + lq) * T2S + sn * 16 + lr, 4 * T2S,
                      Ab + (sn * 16 + lq) * 16 + lr, 64);
-      const v4d c = acc[0] + acc[1];
-      // m = 4r + lq: lk = r, wbk = lq; n = lr: lb = lr/4, wbb = lr%4
-      double *dst = T3s + t * P2 + (lq * 4 + (lr & 3)) * 16 + (lr >> 2);
+      const Acc c = acc[0] + acc[1];
+      // m = (lk, wbk), n = lr: lb = lr/4, wbb = lr%4
+      T *dst = T3s + t * P2 + (lr & 3) * 16 + (lr >> 2);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[r * 4] = c[r];
+      for (int r = 0; r < 4; ++r) {
+        const int m = M::crow(r, lq);
+        dst[(m & 3) * 64 + (m >> 2) * 4] = c[r];
+      }
     }
     __syncthreads();
     // T3 tile to HBM as T3[yf][l][xb][wb]
@@ -1087,7 +1133,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
         const int t = wt + q * wstep;
         if (t >= ntile_e) break;
         const int ty = t / tne, n0 = (t % tne) << 4;
-        v4d acc[2] = {accE[q], v4d{0.0, 0.0, 0.0, 0.0}};
+        Acc acc[2] = {accE[q], zero};
 #pragma unroll
         for (int tx = 0; tx < TX; ++tx)
 #pragma unroll
@@ -1102,7 +1148,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
   }
   if (v.do_local && split_e) {  // add the second k half into the first
     __syncthreads();
-    double *red = sm;
+    T *red = sm;
     if (wave >= kVisitWaves / 2) {
       const int wt = wave - kVisitWaves / 2;
 #pragma unroll
@@ -1134,11 +1180,226 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
       const int ty = t / tne, n0 = (t % tne) << 4, yf = y0 + ty, yb = n0 + lr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int l = 4 * r + lq;
+        const int l = M::crow(r, lq);
         if (yb < K && yf < K) {
           const size_t idx = rl ? ((size_t)yb * P + l) * K + yf : ((size_t)yf * P + l) * K + yb;
-          Y[idx] = accE[q][r];
+          Y[idx] = (double)accE[q][r];
         }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same visit with one (yf, xb) pair per wave (TY * TX == 8 waves): each
+// wave runs T1 -> ket -> bra -> T3 store -> its local-update contribution for
+// its own pair with wave-level LDS ordering only, so an xb step needs just the
+// two barriers around the X/G refill.  The local-update partials of the TX
+// waves that share yf are summed at the end in a fixed order.
+// LDS: Fs as in k_visit4; Xs [tx][xf][a] (row stride pad_b(16)); per pair
+// T1 [wfk,akx][wfb,abx], T2 [wfb,abx][s,lk,wbk], T3 [wbk,wbb][lk,lb]; Gs, Ak,
+// Ab as in k_visit4.
+// ---------------------------------------------------------------------------
+template <class T>
+__host__ __device__ inline size_t visit4p_lds(int K, int TY, int TX) {
+  typedef Mma<T> M;
+  const int K4 = ceil4(K), tne = ceil16(K) / 16;
+  const size_t body = (size_t)TY * 16 * M::pad_a(K4) + (size_t)TX * K4 * M::pad_b(16) +
+                      (size_t)TY * TX * 256 + (size_t)TY * TX * 16 * M::pad_b(32) +
+                      (size_t)TY * TX * 256 + (size_t)TX * 16 * M::pad_b(K) + 2 * 2 * 256;
+  return std::max(body, (size_t)TY * TX * tne * 256);
+}
+
+template <int TY, int TX, class T>
+__global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
+  static_assert(TY * TX == kVisitWaves, "one pair per wave");
+  extern __shared__ double sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
+  typedef Mma<T> M;
+  typedef typename M::acc Acc;
+  const Acc zero = Acc{0, 0, 0, 0};
+  constexpr int D = 4, P = 16, P2 = 256, NP = TY * TX;
+  constexpr int XS = M::pad_b(16), T2S = M::pad_b(32);
+  const int K = v.K, K4 = ceil4(K), FS = M::pad_a(K4), GS = M::pad_b(K), KY = ceil16(K);
+  const int it = blockIdx.y, y0 = blockIdx.x * TY;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  T *Fs = sm;
+  T *Xs = Fs + TY * 16 * FS;
+  T *T1s = Xs + TX * K4 * XS;
+  T *T2s = T1s + NP * P2;
+  T *T3s = T2s + NP * 16 * T2S;
+  T *Gs = T3s + NP * P2;
+  T *Ak = Gs + TX * 16 * GS;
+  T *Ab = Ak + 2 * P2;
+  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
+  const double *ak = v.aket + (size_t)it * v.aket_stride;
+  const double *ab = v.abra + (size_t)it * v.abra_stride;
+  T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
+  const bool rl = v.rl != 0;
+  const int ty = wave / TX, tx = wave % TX, pp = wave;  // this wave's pair
+
+  for (int i = tid; i < 2 * P2; i += kVisitThreads) {
+    const int wb = i & 3, l = (i >> 2) & 3, a = (i >> 4) & 3, wf = (i >> 6) & 3, s = i >> 8;
+    const int u = rl ? wb : wf, dd = rl ? wf : wb;
+    const int src = ((((s * D + u) * D + l) * D + dd) * D + a);
+    Ak[i] = (T)ak[src];
+    Ab[i] = (T)ab[src];
+  }
+  for (int row = wave; row < TY * 16; row += kVisitWaves) {
+    const bool ok = y0 + (row >> 4) < K;
+    for (int xf = lane; xf < K4; xf += 64)
+      Fs[row * FS + xf] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
+  }
+  const int tne = KY >> 4;  // <= 4 (K <= 64)
+  constexpr int kMaxE = 4;
+  Acc accE[kMaxE];
+#pragma unroll
+  for (int q = 0; q < kMaxE; ++q) accE[q] = zero;
+
+  // X and G of the next xb step are fetched into registers while the
+  // current step computes; offsets decoded once (global relative to the
+  // step, LDS).
+  constexpr int kLd = 8;
+  int xg[kLd], xl[kLd], gg[kLd], gl[kLd];
+  T xr[kLd], gr[kLd];
+#pragma unroll
+  for (int u = 0; u < kLd; ++u) {
+    const int i = tid + u * kVisitThreads;
+    int xf, a, txx;
+    if (rl) {
+      xf = i % K4;
+      const int r = i / K4;
+      a = r & 15;
+      txx = r >> 4;
+    } else {
+      txx = i % TX;
+      const int r = i / TX;
+      a = r & 15;
+      xf = r >> 4;
+    }
+    const bool ok = i < K4 * 16 * TX && xf < K;
+    xg[u] = !ok ? -1 : (rl ? (txx * P + a) * K + xf : (xf * P + a) * K + txx);
+    xl[u] = i < K4 * 16 * TX ? ((txx * K4 + xf) * XS + a) | (txx << 24) : -1;
+    const int gtx = i % TX, gr2 = i / TX, wb = gr2 & 15, yb = gr2 >> 4;
+    const bool gok = i < KY * 16 * TX && yb < K;
+    gg[u] = gok ? (yb * P + wb) * K + gtx : -1;
+    gl[u] = i < KY * 16 * TX ? ((gtx * 16 + wb) * GS + yb) | (gtx << 24) : -1;
+  }
+  auto fetch = [&](int x0) {
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int xtx = (xl[u] >> 24) & 0x7f, gtx = (gl[u] >> 24) & 0x7f;
+      const size_t xo = rl ? (size_t)x0 * P * K : (size_t)x0;
+      xr[u] = (T)((xg[u] >= 0 && x0 + xtx < K) ? X[xo + xg[u]] : 0.0);
+      gr[u] = (T)((v.do_local && gg[u] >= 0 && x0 + gtx < K) ? G[(size_t)x0 + gg[u]] : 0.0);
+    }
+  };
+  fetch(0);
+
+  for (int x0 = 0; x0 < K; x0 += TX) {
+    __syncthreads();  // the previous step's readers of Xs and Gs are done
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      if (xl[u] >= 0) Xs[xl[u] & 0xffffff] = xr[u];
+      if (gl[u] >= 0) Gs[gl[u] & 0xffffff] = gr[u];
+    }
+    __syncthreads();
+    if (x0 + TX < K) fetch(x0 + TX);
+    // (a) T1 of the pair: rows wf, cols a, k = xf
+    {
+      Acc acc[2] = {zero, zero};
+      const T *pa = Fs + (ty * 16 + lr) * FS + lq;
+      const T *pb = Xs + (tx * K4 + lq) * XS + lr;
+      int k0 = 0;
+      for (; k0 + 16 <= K4; k0 += 16) mma_steps<4>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
+      for (; k0 < K4; k0 += 4) mma_steps<1>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
+      const Acc c = acc[0] + acc[1];
+      // a = lr (akx = lr/4, abx = lr%4), wf = (wfk, wfb)
+      T *dst = T1s + pp * P2 + (lr >> 2) * 16 + (lr & 3);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int wf = M::crow(r, lq);
+        dst[(wf >> 2) * 64 + (wf & 3) * 4] = c[r];
+      }
+    }
+    wave_lds_order();
+    // (b) ket: rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
+#pragma unroll
+    for (int sn = 0; sn < 2; ++sn) {
+      Acc acc[2] = {zero, zero};
+      mma_steps<4>(acc, T1s + pp * P2 + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
+      const Acc c = acc[0] + acc[1];
+      T *dst = T2s + pp * 16 * T2S + sn * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[M::crow(r, lq) * T2S] = c[r];
+    }
+    wave_lds_order();
+    // (c) bra: rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb)
+    {
+      Acc acc[2] = {zero, zero};
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn)
+        mma_steps<4>(acc, T2s + (pp * 16 + lq) * T2S + sn * 16 + lr, 4 * T2S,
+                     Ab + (sn * 16 + lq) * 16 + lr, 64);
+      const Acc c = acc[0] + acc[1];
+      T *dst = T3s + pp * P2 + (lr & 3) * 16 + (lr >> 2);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // m = (lk, wbk)
+        const int m = M::crow(r, lq);
+        dst[(m & 3) * 64 + (m >> 2) * 4] = c[r];
+      }
+    }
+    wave_lds_order();
+    // T3 of the pair to HBM as T3[yf][l][xb][wb] (16 lanes per 128-byte row)
+    {
+      const int yf = y0 + ty, xb = x0 + tx;
+      if (yf < K && xb < K) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = u * 64 + lane, wb = idx & 15, l = idx >> 4;
+          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = T3s[pp * P2 + wb * 16 + l];
+        }
+      }
+    }
+    // (e) this pair's contribution to Yt[(ty, l)][yb]: k = wb of column tx
+    if (v.do_local) {
+#pragma unroll
+      for (int q = 0; q < kMaxE; ++q) {
+        if (q >= tne) break;
+        Acc acc[2] = {accE[q], zero};
+        mma_steps<4>(acc, T3s + pp * P2 + lq * 16 + lr, 64,
+                     Gs + (tx * 16 + lq) * GS + q * 16 + lr, 4 * GS);
+        accE[q] = acc[0] + acc[1];
+      }
+    }
+  }
+  if (!v.do_local) return;
+  // sum the TX partials of each yf tile in a fixed order (tx = 0, 1, ...)
+  __syncthreads();
+  T *red = sm;
+#pragma unroll
+  for (int q = 0; q < kMaxE; ++q) {
+    if (q >= tne) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[((pp * tne + q) * 4 + r) * 64 + lane] = accE[q][r];
+  }
+  __syncthreads();
+  if (tx != 0) return;
+  double *Y = v.Y.at(it);
+  const int yf = y0 + ty;
+#pragma unroll
+  for (int q = 0; q < kMaxE; ++q) {
+    if (q >= tne) break;
+    const int yb = q * 16 + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      T acc = red[((pp * tne + q) * 4 + r) * 64 + lane];
+      for (int t2 = 1; t2 < TX; ++t2) acc += red[(((pp + t2) * tne + q) * 4 + r) * 64 + lane];
+      const int l = M::crow(r, lq);
+      if (yb < K && yf < K) {
+        const size_t idx = rl ? ((size_t)yb * P + l) * K + yf : ((size_t)yf * P + l) * K + yb;
+        Y[idx] = (double)acc;
       }
     }
   }
@@ -1305,12 +1566,6 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
 // the rounding order of sums and updates differs.  Cross-wave sums are taken
 // in a fixed order that every wave repeats, so all waves hold the same bits.
 // ---------------------------------------------------------------------------
-// Orders one wave's LDS writes before its later LDS reads (other lanes).
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 constexpr int kQmRowCap = 768;        // rows held by one workgroup, at most
 constexpr int kQmVs = kQmRowCap + 4;   // stride of a V column in LDS
@@ -1929,29 +2184,65 @@ static VisitKernel visit_kernel(int D) {
 }
 
 // Tiles of the D = 4, d = 2 kernel: the first candidate whose LDS fits.
+template <class T>
 static bool visit4_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   if (f.D != 4 || f.d != 2 || f.K > 128) return false;
   const int cand[][2] = {{2, 4}, {4, 2}, {2, 2}, {1, 2}, {1, 1}};
   for (auto &c : cand) {
     if (c[0] > f.K) continue;
-    const size_t n = visit4_lds(f.K, c[0], c[1]);
+    const size_t n = visit4_lds<T>(f.K, c[0], c[1]) * sizeof(T);
     const size_t moved = (size_t)std::max(ceil4(f.K), ceil16(f.K)) * 16 * c[1];
-    if (n * 8 <= 150 * 1024 && moved <= 8 * (size_t)kVisitThreads) {
+    if (n <= 150 * 1024 && moved <= 8 * (size_t)kVisitThreads) {
       *TY = c[0];
       *TX = c[1];
-      *bytes = n * 8;
+      *bytes = n;
       return true;
     }
   }
   return false;
 }
 
+template <class T>
 static VisitKernel visit4_kernel(int TY, int TX) {
-  if (TY == 2 && TX == 4) return k_visit4<2, 4>;
-  if (TY == 4 && TX == 2) return k_visit4<4, 2>;
-  if (TY == 2 && TX == 2) return k_visit4<2, 2>;
-  if (TY == 1 && TX == 2) return k_visit4<1, 2>;
-  return k_visit4<1, 1>;
+  if (TY == 2 && TX == 4) return k_visit4<2, 4, T>;
+  if (TY == 4 && TX == 2) return k_visit4<4, 2, T>;
+  if (TY == 2 && TX == 2) return k_visit4<2, 2, T>;
+  if (TY == 1 && TX == 2) return k_visit4<1, 2, T>;
+  return k_visit4<1, 1, T>;
+}
+
+// Pair-per-wave visit tiles (TY * TX = 8, K <= 64): the first that fits.
+template <class T>
+static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
+  if (f.D != 4 || f.d != 2 || f.K > 64) return false;
+  const int cand[][2] = {{2, 4}, {4, 2}};
+  for (auto &c : cand) {
+    if (c[0] > f.K) continue;
+    const size_t n = visit4p_lds<T>(f.K, c[0], c[1]) * sizeof(T);
+    const size_t moved = (size_t)std::max(ceil4(f.K), ceil16(f.K)) * 16 * c[1];
+    if (n <= 150 * 1024 && moved <= 8 * (size_t)kVisitThreads) {
+      *TY = c[0];
+      *TX = c[1];
+      *bytes = n;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <class T>
+static VisitKernel visit4p_kernel(int TY, int TX) {
+  if (TY == 2 && TX == 4) return k_visit4p<2, 4, T>;
+  return k_visit4p<4, 2, T>;
+}
+
+// FP32 contractions run where both the visit and the environment update have
+// an FP32 form (the specialised D = 4 kernels, K <= 64): T3 passes between
+// them in FP32.  Elsewhere the precision option leaves FP64 in place.
+static bool visit_f32(const FitBatch &f) {
+  int TY, TX;
+  size_t lds;
+  return f.prec == 32 && f.K <= 64 && visit4_tiles<float>(f, &TY, &TX, &lds);
 }
 
 static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
@@ -1967,17 +2258,27 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
       if (e != hipSuccess) attr_err = e;
     }
     for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2), std::make_pair(2, 2),
-                   std::make_pair(1, 2), std::make_pair(1, 1)}) {
-      hipError_t e = hipFuncSetAttribute(
-          (const void *)visit4_kernel(t.first, t.second),
-          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) attr_err = e;
-    }
+                   std::make_pair(1, 2), std::make_pair(1, 1)})
+      for (VisitKernel kf : {visit4_kernel<double>(t.first, t.second),
+                             visit4_kernel<float>(t.first, t.second)}) {
+        hipError_t e = hipFuncSetAttribute((const void *)kf,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) attr_err = e;
+      }
+    for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2)})
+      for (VisitKernel kf : {visit4p_kernel<double>(t.first, t.second),
+                             visit4p_kernel<float>(t.first, t.second)}) {
+        hipError_t e = hipFuncSetAttribute((const void *)kf,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) attr_err = e;
+      }
   });
   if (attr_err != hipSuccess) return attr_err;
   int TY4, TX4;
   size_t lds4;
-  const bool spec = visit4_tiles(f, &TY4, &TX4, &lds4);
+  const bool f32 = visit_f32(f);
+  const bool spec = f32 ? visit4_tiles<float>(f, &TY4, &TX4, &lds4)
+                        : visit4_tiles<double>(f, &TY4, &TX4, &lds4);
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
   VisitArgs v;
   v.K = f.K; v.P = f.P; v.D = f.D; v.d = f.d; v.TY = TY; v.TX = TX;
@@ -1998,11 +2299,20 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     bytes += it * 8 * 2 * K * P * K;
   }
   Span sp(KC_VISIT, st, flops, bytes);
-  if (spec) {
+  int TYp, TXp;
+  size_t ldsp;
+  const bool pairw = f32 ? visit4p_tiles<float>(f, &TYp, &TXp, &ldsp)
+                         : visit4p_tiles<double>(f, &TYp, &TXp, &ldsp);
+  if (pairw) {  // one (yf, xb) pair per wave
+    v.TY = TYp;
+    v.TX = TXp;
+    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(TYp, TXp) : visit4p_kernel<double>(TYp, TXp),
+                       dim3((f.K + TYp - 1) / TYp, f.items), dim3(kVisitThreads), ldsp, st, v);
+  } else if (spec) {
     v.TY = TY4;
     v.TX = TX4;
-    hipLaunchKernelGGL(visit4_kernel(TY4, TX4), dim3((f.K + TY4 - 1) / TY4, f.items),
-                       dim3(kVisitThreads), lds4, st, v);
+    hipLaunchKernelGGL(f32 ? visit4_kernel<float>(TY4, TX4) : visit4_kernel<double>(TY4, TX4),
+                       dim3((f.K + TY4 - 1) / TY4, f.items), dim3(kVisitThreads), lds4, st, v);
   } else {
     hipLaunchKernelGGL(visit_kernel(f.D), dim3((f.K + TY - 1) / TY, f.items),
                        dim3(kVisitThreads), lds, st, v);
@@ -2118,10 +2428,18 @@ hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
     EnvArgs e{f.K, f.P, rl ? 1 : 0, f.t3, t1_stride(f), Y, envOut};
     const dim3 grid((f.K * f.P + 63) / 64, f.items);
     const int mt = (f.K + 15) / 16;
-    if (mt <= 1) hipLaunchKernelGGL(k_env<1>, grid, dim3(kEnvThreads), 0, st, e);
-    else if (mt <= 2) hipLaunchKernelGGL(k_env<2>, grid, dim3(kEnvThreads), 0, st, e);
-    else if (mt <= 3) hipLaunchKernelGGL(k_env<3>, grid, dim3(kEnvThreads), 0, st, e);
-    else hipLaunchKernelGGL(k_env<4>, grid, dim3(kEnvThreads), 0, st, e);
+    // FP32 only where the visit wrote FP32 T3 (the specialised D = 4 kernel)
+    if (visit_f32(f)) {
+      if (mt <= 1) hipLaunchKernelGGL((k_env<1, float>), grid, dim3(kEnvThreads), 0, st, e);
+      else if (mt <= 2) hipLaunchKernelGGL((k_env<2, float>), grid, dim3(kEnvThreads), 0, st, e);
+      else if (mt <= 3) hipLaunchKernelGGL((k_env<3, float>), grid, dim3(kEnvThreads), 0, st, e);
+      else hipLaunchKernelGGL((k_env<4, float>), grid, dim3(kEnvThreads), 0, st, e);
+      return hipGetLastError();
+    }
+    if (mt <= 1) hipLaunchKernelGGL((k_env<1, double>), grid, dim3(kEnvThreads), 0, st, e);
+    else if (mt <= 2) hipLaunchKernelGGL((k_env<2, double>), grid, dim3(kEnvThreads), 0, st, e);
+    else if (mt <= 3) hipLaunchKernelGGL((k_env<3, double>), grid, dim3(kEnvThreads), 0, st, e);
+    else hipLaunchKernelGGL((k_env<4, double>), grid, dim3(kEnvThreads), 0, st, e);
     return hipGetLastError();
   }
   OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,

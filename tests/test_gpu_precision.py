@@ -1,0 +1,96 @@
+"""Mixed precision: FP32 sweeps (fit contractions on FP32 MFMA, QR and
+normalisation in FP64) followed by FP64 polish sweeps reach the FP64 fixed
+point.  After the polish every <sigma_z> and <S.S> agrees with the all-FP64
+GPU solve and with the FP64 oracle within POLISH_TOL; the FP32-only error is
+measured and reported, and must sit well above it (the polish is needed)."""
+
+import numpy as np
+import pytest
+
+from bbp_inputs import op_heis, op_sz, peps_finite
+
+pytestmark = pytest.mark.gpu
+
+POLISH_TOL = 1e-9     # |d observable| after the FP64 polish (residual < 1e-10)
+CFG = dict(Lx=8, Ly=8, bx=4, by=4, D=4, chi=16)
+
+
+def _bbp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_05844_amd import bbp
+    return bbp
+
+
+def _obs(g, L):
+    xs = [x for y in range(L) for x in range(L)]
+    ys = [y for y in range(L) for x in range(L)]
+    bonds = [(x, y, x + 1, y) for y in range(L) for x in range(L - 1)]
+    bonds += [(x, y, x, y + 1) for y in range(L - 1) for x in range(L)]
+    return np.array(g.expect_sites(xs, ys, op_sz())), np.array(g.expect_bonds(bonds, op_heis())), bonds
+
+
+def _sweep_to(g, tol, cap):
+    res, n = 1.0, 0
+    while res >= tol and n < cap:
+        res = g.sweep(1)
+        n += 1
+    return res, n
+
+
+def test_fp32_then_fp64_polish_reaches_the_fp64_fixed_point():
+    bbp = _bbp()
+    A = peps_finite(8, 8, 4, seed=0)
+    ref = bbp.BlockBP(**CFG)
+    ref.set_tensors(A)
+    r64, n64 = _sweep_to(ref, 1e-10, 40)
+    sz64, ss64, _ = _obs(ref, 8)
+
+    mix = bbp.BlockBP(**CFG)
+    mix.set_option("precision", 32)
+    mix.set_tensors(A)
+    r32, n32 = _sweep_to(mix, 1e-6, 40)
+    sz32, ss32, _ = _obs(mix, 8)
+    mix.set_option("precision", 64)
+    rp, npol = _sweep_to(mix, 1e-10, 40)
+    szp, ssp, _ = _obs(mix, 8)
+    print(f"fp64: {n64} sweeps to {r64:.1e}; fp32: {n32} sweeps to {r32:.1e}, "
+          f"then {npol} fp64 sweeps to {rp:.1e}")
+    e32 = max(np.abs(sz32 - sz64).max(), np.abs(ss32 - ss64).max())
+    ep = max(np.abs(szp - sz64).max(), np.abs(ssp - ss64).max())
+    print(f"max |d obs| vs all-FP64: fp32 only {e32:.2e}, after polish {ep:.2e}")
+    assert r64 < 1e-10 and rp < 1e-10
+    assert ep < POLISH_TOL
+    assert e32 > 10 * POLISH_TOL   # FP32 alone does not reach FP64 accuracy
+
+
+def test_polished_observables_match_the_oracle():
+    bbp = _bbp()
+    from oracle.blockbp import BlockBP as OracleBP
+    A = peps_finite(8, 8, 4, seed=1)
+    g = bbp.BlockBP(**CFG)
+    g.set_option("precision", 32)
+    g.set_tensors(A)
+    _sweep_to(g, 1e-6, 40)
+    g.set_option("precision", 64)
+    rp, npol = _sweep_to(g, 1e-10, 40)
+    sz, ss, bonds = _obs(g, 8)
+    ref = OracleBP(A, Lx=8, Ly=8, bx=4, by=4, D=4, chi=16)
+    rr = 1.0
+    for _ in range(40):
+        rr = ref.sweep()
+        if rr < 1e-10:
+            break
+    err_sz = max(abs(sz[y * 8 + x] - ref.expect_site(x, y, op_sz())) for y in range(8) for x in range(8))
+    err_ss = max(abs(ss[i] - ref.expect_bond(*b, op_heis())) for i, b in enumerate(bonds))
+    print(f"polished vs oracle: |d sz| {err_sz:.2e}, |d S.S| {err_ss:.2e}")
+    assert err_sz < POLISH_TOL and err_ss < POLISH_TOL
+
+
+def test_precision_option_validation():
+    bbp = _bbp()
+    g = bbp.BlockBP(**CFG)
+    for bad in (16, 0, 63.5):
+        with pytest.raises(bbp.BBPError):
+            g.set_option("precision", bad)
