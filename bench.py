@@ -12,6 +12,7 @@ timed on the host are added to the same JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
     python bench.py --calibrate-copy   (plain 1 GiB device copy, for counters)
+    python bench.py --serve [--requests 256] [--slots 8] [--rates 0.5 1 2 4]
 
 The roofline's `traffic` (HBM bytes per launch of the dominant kernel) comes
 from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ and is
@@ -116,6 +117,166 @@ def calibrate_copy():
     print(json.dumps(dict(copy_bytes=COPY_BYTES, kernel="neg (elementwise)")), flush=True)
 
 
+def serve_stream(n, seed):
+    """The request stream of the serving workload: lattice side uniform in
+    {6, 8, ..., 20}, D uniform in {2, 3, 4}, chi = 2 D^2, block side uniform in
+    {2, 3, 4} (lattices padded with trivial sites), seeded tensors."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        side = int(rng.choice(np.arange(6, 21, 2)))
+        D = int(rng.choice([2, 3, 4]))
+        b = int(rng.choice([2, 3, 4]))
+        reqs.append(dict(Lx=side, Ly=side, bx=b, by=b, D=D, chi=2 * D * D,
+                         tensor_seed=int(rng.integers(1 << 31))))
+    return reqs
+
+
+def serve(args):
+    """Serving pattern: every request one at a time (the plain path), then
+    the same stream through the request server with Poisson arrivals at
+    several multiples of the one-at-a-time service rate."""
+    import threading
+    import torch
+    from paper_2301_05844_amd import bbp
+    reqs = serve_stream(args.requests, args.seed)
+    tens = [peps_finite(r["Lx"], r["Ly"], r["D"], seed=r["tensor_seed"]) for r in reqs]
+    spec = [{k: v for k, v in r.items() if k != "tensor_seed"} for r in reqs]
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    kw = dict(tol=TOL, max_sweeps=MAX_SWEEPS)
+
+    def run(rate, slots):
+        srv = bbp.Server(budget_bytes=budget, max_slots=slots)
+        gaps = np.random.default_rng(args.seed + 1).exponential(1.0 / rate, len(reqs)) \
+            if rate else np.zeros(len(reqs))
+        tickets = []
+        t0 = time.perf_counter()
+
+        def feed():
+            nxt = t0
+            for g, r, A in zip(gaps, spec, tens):
+                nxt += g
+                dt = nxt - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(srv.submit(A, **r, **kw))
+        if slots == 1 and not rate:   # the plain path: one at a time
+            res = []
+            for i, (r, A) in enumerate(zip(spec, tens)):
+                t = srv.submit(A, **r, **kw)
+                res.append(srv.wait(t, timeout=600))
+                tickets.append(t)
+                if (i + 1) % 16 == 0:
+                    log(f"  {i + 1} requests done ({time.perf_counter() - t0:.1f} s)")
+        else:
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            res = [srv.wait(t, timeout=600) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        errs = [srv.error(t) for t in tickets]
+        srv.close()
+        bad = [e for (s, _, _), e in zip(res, errs) if s != "done"]
+        if bad:
+            raise RuntimeError(f"{len(bad)} requests failed: {bad[0]}")
+        lat = np.array([tm[2] - tm[0] for _, _, tm in res])
+        return res, dict(wall_s=wall, solves_per_s=len(res) / wall,
+                         p50_ms=float(np.percentile(lat, 50) * 1e3),
+                         p99_ms=float(np.percentile(lat, 99) * 1e3),
+                         max_running=st["max_running"])
+
+    log(f"serving: {len(reqs)} requests one at a time")
+    plain_res, plain = run(0.0, 1)
+    service = np.array([tm[2] - tm[1] for _, _, tm in plain_res])
+    mu = len(reqs) / service.sum()
+    log(f"one-at-a-time service rate {mu:.2f} solves/s")
+    lines = []
+    for mult in args.rates:
+        log(f"serving at {mult} x the one-at-a-time rate")
+        res, m = run(mult * mu, args.slots)
+        same = all(a[1]["residual"] == b[1]["residual"] and
+                   np.array_equal(a[1]["sz"], b[1]["sz"]) and
+                   np.array_equal(a[1]["ss"], b[1]["ss"]) for a, b in zip(plain_res, res))
+        m.update(rate_multiple=mult, arrival_rate=mult * mu, equal_to_alone=bool(same))
+        lines.append(m)
+    updates = sum(r[1]["sweeps"] for r in plain_res)
+    out = dict(metric="p50/p99 solve latency and solves/s under Poisson arrivals",
+               workload="serving stream (side 6..20, D 2..4, chi 2D^2, block 2..4)",
+               requests=len(reqs), slots=args.slots, budget_bytes=budget,
+               one_at_a_time=dict(plain, service_rate=mu, total_sweeps=updates),
+               served=lines, data="synthetic", dtype="f64")
+    print(json.dumps(out), flush=True)
+
+
+def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
+    """The precision pattern on the same workload: sweeps with the fit
+    contractions on FP32 MFMA until the residual stops improving (or drops
+    below 1e-7), then FP64 sweeps to the tolerance, observables in FP64.
+    Reports the per-observable error against the all-FP64 solve."""
+    ctx.set_option("precision", 32)
+    ctx.set_tensors(A)
+    n32, res, prev = 0, 1.0, None
+    while n32 < MAX_SWEEPS:
+        res = ctx.sweep(1)
+        n32 += 1
+        if res < 1e-7 or (prev is not None and res > 0.5 * prev):
+            break   # at the FP32 floor, or no longer improving
+        prev = res
+    ctx.set_option("precision", 64)
+    n64 = 0
+    while res >= TOL and n64 < MAX_SWEEPS:
+        res = ctx.sweep(1)
+        n64 += 1
+    log(f"mixed precision: {n32} FP32 sweeps, then {n64} FP64 sweeps to {res:.2e}")
+    times = []
+    for _ in range(steps):
+        sync()
+        t0 = time.perf_counter()
+        ctx.set_option("precision", 32)
+        ctx.set_tensors(A)
+        ctx.sweep(n32)
+        ctx.set_option("precision", 64)
+        res = ctx.sweep(n64)
+        sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+        ss = ctx.expect_bonds(bonds, op_heis())
+        ln = ctx.log_norm()
+        sync()
+        times.append(time.perf_counter() - t0)
+    ms = float(np.mean(times) * 1e3)
+    # tightly converged FP64 reference: how close each solve is to the fixed point
+    ctx.set_option("precision", 64)
+    ctx.set_tensors(A)
+    rt, nt = 1.0, 0
+    while rt >= 1e-14 and nt < MAX_SWEEPS:
+        rt = ctx.sweep(1)
+        nt += 1
+    szt = np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz()))
+    sst = np.array(ctx.expect_bonds(bonds, op_heis()))
+    err = lambda a, b: float(np.max(np.abs(np.array(a) - b)))
+    acc = dict(reference=f"FP64, {nt} sweeps to residual {rt:.1e}",
+               fp64_err_sz=err(ref[1], szt), fp64_err_ss=err(ref[2], sst),
+               mixed_err_sz=err(sz, szt), mixed_err_ss=err(ss, sst))
+    per = {}
+    for prec in (32, 64):   # time per sweep in each precision, same state
+        ctx.set_option("precision", prec)
+        sync()
+        t0 = time.perf_counter()
+        ctx.sweep(2)
+        sync()
+        per[f"fp{prec}_ms_per_sweep"] = (time.perf_counter() - t0) / 2 * 1e3
+    ctx.set_option("precision", 64)
+    return dict(fp32_sweeps=n32, fp64_sweeps=n64, residual=res, ms_per_solve=ms, **per,
+                accuracy_vs_converged=acc,
+                speedup_vs_fp64=fp64_ms / ms,
+                max_abs_diff_sz_vs_fp64=float(np.max(np.abs(np.array(sz) - np.array(ref[1])))),
+                max_abs_diff_ss_vs_fp64=float(np.max(np.abs(np.array(ss) - np.array(ref[2])))),
+                abs_err_log_norm=float(abs(ln[0] - ref[3][0])),
+                note="FP32 visit and environment contractions (FP32 accumulation); QR, "
+                     "normalisation and messages FP64; errors against the all-FP64 solve")
+
+
 def cpu_baseline(cfg, A):
     """The FP64 oracle on the host: one untimed sweep, then one timed sweep
     with every bond at its cap (48 directed-message updates)."""
@@ -145,6 +306,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving pattern instead of the default solve")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0])
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -154,6 +321,9 @@ def main():
               "workload runs on a single MI355X; --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
 
     from paper_2301_05844_amd import bbp
     cfg = CONFIGS[WORKLOAD]
@@ -225,6 +395,8 @@ def main():
                  for s in stats},
         cpu_baseline=None,
     )
+    line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
+                                              line["ms_per_step"])
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(cfg, A)
