@@ -10,7 +10,7 @@ the counted fit TFLOP/s, per-step latency percentiles, the dominant kernel's
 roofline figures (HIP events on its launch stream) and the FP64 CPU oracle
 timed on the host are added to the same JSON line.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-mixed]
     python bench.py --calibrate-copy   (plain 1 GiB device copy, for counters)
     python bench.py --serve [--requests 256] [--slots 8] [--rates 0.5 1 2 4]
 
@@ -305,6 +305,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision pattern (profiling runs: the timed "
+                         "solves are then the last kernels of the run)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--serve", action="store_true",
                     help="serving pattern instead of the default solve")
@@ -395,8 +398,9 @@ def main():
                  for s in stats},
         cpu_baseline=None,
     )
-    line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
-                                              line["ms_per_step"])
+    if not args.no_mixed:
+        line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
+                                                  line["ms_per_step"])
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(cfg, A)
