@@ -17,6 +17,7 @@ standing in for the imaginary-time-evolved ground states the paper measures on
 from .gen import (  # noqa: F401
     peps_finite,
     peps_infinite,
+    ising_peps,
     pauli,
     op_sz,
     op_sx,

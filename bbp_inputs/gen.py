@@ -41,6 +41,35 @@ def peps_infinite(ucx, ucy, D, d=2, seed=0):
     return A
 
 
+def ising_peps(beta, h=0.0, Lx=0, Ly=0):
+    """PEPS whose norm is the classical Ising partition function
+    ``Z = sum_sigma exp(beta * sum_<ij> s_i s_j + h * sum_i s_i)``: the state
+    ``psi(sigma) = prod_<ij> exp(beta s_i s_j / 2) prod_i exp(h s_i / 2)``
+    squares to the Boltzmann weight, so ``<psi|psi> = Z`` and ``<sigma_z>`` of
+    psi is the classical magnetisation.  Each bond factor is split as
+    ``exp(beta s s' / 2) = sum_k Q[s, k] Q[s', k]`` (both eigenvalues of the
+    2x2 factor are positive for beta > 0) and every site carries one ``Q`` per
+    leg: D = 2.  ``Lx = Ly = 0``: one tensor, the 1x1 unit cell of the
+    infinite lattice; otherwise the open ``Lx x Ly`` lattice, legs off the edge
+    of true dimension 1 (zero-padded)."""
+    w = np.array([[np.exp(beta / 2), np.exp(-beta / 2)],
+                  [np.exp(-beta / 2), np.exp(beta / 2)]])
+    lam, V = np.linalg.eigh(w)
+    Q = V * np.sqrt(lam)                      # w = Q Q^T
+    one = np.array([1.0, 0.0])
+    infinite = Lx == 0
+    nx, ny = (1, 1) if infinite else (Lx, Ly)
+    A = np.zeros((nx * ny, 2, 2, 2, 2, 2))
+    for y in range(ny):
+        for x in range(nx):
+            for s in range(2):
+                sg = 1.0 if s == 0 else -1.0
+                leg = lambda edge: one if (edge and not infinite) else Q[s]
+                A[y * nx + x, s] = np.exp(h * sg / 2) * np.einsum(
+                    "u,l,d,r->uldr", leg(y == 0), leg(x == 0), leg(y == ny - 1), leg(x == nx - 1))
+    return A
+
+
 def pauli():
     """Pauli matrices in the basis s=0 <-> sigma_z=+1; sigma_y returned as the
     real matrix i*sigma_y (so that sigma_y (x) sigma_y = -(i sy)(x)(i sy))."""

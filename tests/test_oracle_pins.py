@@ -325,3 +325,55 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(ob, "bond_caps", bad)
         err = _tree_error(4, 2)
     assert err > 1e-6
+
+
+# ---- classical Ising through the PEPS whose norm is its partition function ----
+
+def _ising_brute(beta, h, Lx, Ly):
+    """Classical sums over all 2^(Lx*Ly) configurations: <s> per site."""
+    import itertools
+    n = Lx * Ly
+    Z = 0.0
+    m = np.zeros(n)
+    for conf in itertools.product((1, -1), repeat=n):
+        s = np.array(conf).reshape(Ly, Lx)
+        e = beta * ((s[:, :-1] * s[:, 1:]).sum() + (s[:-1, :] * s[1:, :]).sum()) + h * s.sum()
+        w = np.exp(e)
+        Z += w
+        m += w * s.ravel()
+    return m / Z
+
+
+def test_ising_peps_norm_is_the_classical_partition_function():
+    """One block covering a 3x3 open lattice (exact): <sigma_z> of the Ising
+    PEPS equals the classical magnetisation summed over all configurations."""
+    from bbp_inputs import ising_peps
+    from oracle.blockbp import BlockBP
+    beta, h = 0.7, 0.3
+    A = ising_peps(beta, h, 3, 3)
+    g = BlockBP(A, D=2, chi=4, bx=3, by=3, Lx=3, Ly=3)
+    m = _ising_brute(beta, h, 3, 3)
+    for y in range(3):
+        for x in range(3):
+            assert abs(g.expect_site(x, y, op_sz()) - m[y * 3 + x]) < 1e-12
+
+
+def _ising_infinite_m(beta, b, chi, h=1e-6):
+    from bbp_inputs import ising_peps
+    from oracle.blockbp import BlockBP
+    g = BlockBP(ising_peps(beta, h), D=2, chi=chi, bx=b, by=b, infinite=True, ucx=1, ucy=1)
+    for _ in range(120):
+        if g.sweep() < 1e-12:
+            break
+    return g.expect_site(0, 0, op_sz())
+
+
+def test_ising_magnetisation_approaches_onsager():
+    """Infinite lattice below T_c (beta_c = 0.4407): block BP's magnetisation
+    approaches Onsager and Yang's closed form (1 - sinh(2 beta)^-4)^(1/8) and
+    improves with the block size."""
+    onsager = lambda beta: (1 - np.sinh(2 * beta) ** -4) ** 0.125
+    assert abs(_ising_infinite_m(0.8, 4, 8) - onsager(0.8)) < 1e-6
+    e2 = abs(_ising_infinite_m(0.6, 2, 4) - onsager(0.6))
+    e4 = abs(_ising_infinite_m(0.6, 4, 8) - onsager(0.6))
+    assert e4 < 1e-4 and e4 < 0.5 * e2
