@@ -115,6 +115,9 @@ CONFIGS = {
     # infinite lattice, 2x2 unit cell, D=4, 4x4 block, chi=32
     "inf2x2_D4_b4_chi32": dict(infinite=True, ucx=2, ucy=2, bx=4, by=4, D=4,
                                chi=32, tol=1e-10),
+    # 6x6 open lattice, D=6, 3x3 blocks, chi=6, chi_env=16, 2 sweeps (D=6 parity)
+    "obc6x6_D6_b3_chi6": dict(infinite=False, Lx=6, Ly=6, bx=3, by=3, D=6, chi=6,
+                              chi_env=16, sweeps=2),
     # 16x16 open lattice, D=6, 4x4 blocks, chi=64 (mixed-precision workload)
     "obc16x16_D6_b4_chi64": dict(infinite=False, Lx=16, Ly=16, bx=4, by=4, D=6,
                                  chi=64, tol=1e-10),

@@ -146,6 +146,27 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Device global memory seen through a pointer whose origin the compiler
+// cannot trace (taken from a pointer table or a struct member): accesses
+// through the returned pointer are global loads and stores, not flat ones,
+// which would also count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
+// Loads through a buffer descriptor: the base lives in SGPRs and each lane
+// supplies a 32-bit byte offset, so a loop keeps one 32-bit offset per element
+// instead of a 64-bit address.  Descriptor word 3 selects the 32-bit data
+// format, which untyped buffer loads on this GPU family require.  Callers
+// keep every offset inside the `bytes` they declare.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
 // Orders one wave's LDS writes before its later LDS reads (other lanes).
 __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -440,7 +461,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
   const int lr = lane & 15, lq = lane >> 4;
   const int n = blockIdx.x * 64 + wave * 16 + lr;
   const T *T3 = reinterpret_cast<const T *>(e.t3) + (size_t)it * e.t3s;
-  const double *Y = e.Y.at(it);
+  const auto *Y = gmem(e.Y.at(it));
   const bool rl = e.rl != 0;
   T an[NA], bn[8];
   auto fetch = [&](int k0) {
@@ -490,7 +511,7 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
   }
   if (n >= N) return;
   const int xb = n / P, wb = n - xb * P;
-  double *E = e.E.at(it);
+  auto *E = gmem(e.E.at(it));
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const Acc c = acc[mt][0] + acc[mt][1];
@@ -741,7 +762,9 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   double *Gs = T3s + (size_t)TY * TX * P2;
   double *Ak = Gs + (size_t)TX * P * GS;
   double *Ab = Ak + (size_t)d * P2;
-  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
+  const auto *F = gmem((const double *)v.F.at(it));
+  const auto *X = gmem((const double *)v.X.at(it));
+  const auto *G = gmem((const double *)v.G.at(it));
   const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
   double *T3g = v.t3 + (size_t)it * v.t3_stride;
@@ -913,7 +936,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
     }
   }
   if (v.do_local && (!split_e || wave < kVisitWaves / 2)) {
-    double *Y = v.Y.at(it);
+    auto *Y = gmem(v.Y.at(it));
     const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
 #pragma unroll
     for (int q = 0; q < kMaxE; ++q) {
@@ -990,7 +1013,9 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
   T *Gs = T3s + NP * P2;
   T *Ak = Gs + TX * 16 * GS;
   T *Ab = Ak + 2 * P2;
-  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
+  const auto *F = gmem((const double *)v.F.at(it));
+  const auto *X = gmem((const double *)v.X.at(it));
+  const auto *G = gmem((const double *)v.G.at(it));
   const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
   T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
@@ -1171,7 +1196,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
     }
   }
   if (v.do_local && (!split_e || wave < kVisitWaves / 2)) {
-    double *Y = v.Y.at(it);
+    auto *Y = gmem(v.Y.at(it));
     const int wstep = split_e ? kVisitWaves / 2 : kVisitWaves;
 #pragma unroll
     for (int q = 0; q < kMaxE; ++q) {
@@ -1196,22 +1221,42 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
 // its own pair with wave-level LDS ordering only, so an xb step needs just the
 // two barriers around the X/G refill.  The local-update partials of the TX
 // waves that share yf are summed at the end in a fixed order.
-// LDS: Fs as in k_visit4; Xs [tx][xf][a] (row stride pad_b(16)); per pair
-// T1 [wfk,akx][wfb,abx], T2 [wfb,abx][s,lk,wbk], T3 [wbk,wbb][lk,lb]; Gs, Ak,
-// Ab as in k_visit4.
+//
+// The ket's output tile for one s, C[(wfb, abx)][(lk, wbk)], sits in the MFMA
+// accumulator with register i of lane (lr, lq) holding row 4i + lq (FP64) or
+// 4lq + i (FP32) of column lr: that is the bra's A operand (rows (lk, wbk),
+// k = (s, wfb, abx)) for k step i, with the bra's B rows read in the matching
+// k order.  T2 therefore never leaves registers.  T1 and T3 share one LDS
+// region per pair (T1 is consumed by the ket before the bra writes T3).
+//
+// NE = ceil(K / 16) bounds the local-update tiles; each thread moves LD
+// elements of the X and G tiles per step.  Up to NE = 3 the kernel is held to
+// 128 VGPRs so that two workgroups (4 waves per SIMD) share a CU when the LDS
+// allows it.
+// LDS: Fs [(ty, wf)][xf] (row stride pad_a(K4)); Xs [tx][xf][a] (stride
+// pad_b(16)); per pair T1 [wfk,akx][wfb,abx] / T3 [wbk,wbb][lk,lb]; Gs
+// [(tx, wb)][yb] (stride pad_b(K)); Ak, Ab [s][wf][a][l][wb].
 // ---------------------------------------------------------------------------
 template <class T>
 __host__ __device__ inline size_t visit4p_lds(int K, int TY, int TX) {
   typedef Mma<T> M;
   const int K4 = ceil4(K), tne = ceil16(K) / 16;
   const size_t body = (size_t)TY * 16 * M::pad_a(K4) + (size_t)TX * K4 * M::pad_b(16) +
-                      (size_t)TY * TX * 256 + (size_t)TY * TX * 16 * M::pad_b(32) +
                       (size_t)TY * TX * 256 + (size_t)TX * 16 * M::pad_b(K) + 2 * 2 * 256;
   return std::max(body, (size_t)TY * TX * tne * 256);
 }
 
-template <int TY, int TX, class T>
-__global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
+template <int TY, int TX, int NE>
+struct Visit4pShape {
+  static constexpr int LD = (NE * TX + 1) / 2;  // 16 NE * 16 TX elements over 512 threads
+  // 4 waves per SIMD (128 VGPRs) only where the LDS can hold two workgroups
+  static constexpr int kWaves = (NE == 2 || (NE == 3 && TX == 2)) ? 4 : 2;
+};
+
+template <int TY, int TX, class T, int NE>
+__global__ __launch_bounds__(kVisitThreads)
+__attribute__((amdgpu_waves_per_eu(Visit4pShape<TY, TX, NE>::kWaves)))
+void k_visit4p(VisitArgs v) {
   static_assert(TY * TX == kVisitWaves, "one pair per wave");
   extern __shared__ double sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
@@ -1219,25 +1264,26 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
   typedef typename M::acc Acc;
   const Acc zero = Acc{0, 0, 0, 0};
   constexpr int D = 4, P = 16, P2 = 256, NP = TY * TX;
-  constexpr int XS = M::pad_b(16), T2S = M::pad_b(32);
+  constexpr int LD = Visit4pShape<TY, TX, NE>::LD;
+  constexpr int XS = M::pad_b(16);
+  constexpr bool f64 = sizeof(T) == 8;
   const int K = v.K, K4 = ceil4(K), FS = M::pad_a(K4), GS = M::pad_b(K), KY = ceil16(K);
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   T *Fs = sm;
   T *Xs = Fs + TY * 16 * FS;
-  T *T1s = Xs + TX * K4 * XS;
-  T *T2s = T1s + NP * P2;
-  T *T3s = T2s + NP * 16 * T2S;
-  T *Gs = T3s + NP * P2;
+  T *T13s = Xs + TX * K4 * XS;
+  T *Gs = T13s + NP * P2;
   T *Ak = Gs + TX * 16 * GS;
   T *Ab = Ak + 2 * P2;
-  const double *F = v.F.at(it), *X = v.X.at(it), *G = v.G.at(it);
-  const double *ak = v.aket + (size_t)it * v.aket_stride;
+  const auto *F = gmem((const double *)v.F.at(it));
+    const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
   T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
   const bool rl = v.rl != 0;
   const int ty = wave / TX, tx = wave % TX, pp = wave;  // this wave's pair
+  T *Tp = T13s + pp * P2;
 
   for (int i = tid; i < 2 * P2; i += kVisitThreads) {
     const int wb = i & 3, l = (i >> 2) & 3, a = (i >> 4) & 3, wf = (i >> 6) & 3, s = i >> 8;
@@ -1251,20 +1297,21 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
     for (int xf = lane; xf < K4; xf += 64)
       Fs[row * FS + xf] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
   }
-  const int tne = KY >> 4;  // <= 4 (K <= 64)
-  constexpr int kMaxE = 4;
-  Acc accE[kMaxE];
+  const int tne = KY >> 4;  // <= NE
+  Acc accE[NE];
 #pragma unroll
-  for (int q = 0; q < kMaxE; ++q) accE[q] = zero;
+  for (int q = 0; q < NE; ++q) accE[q] = zero;
 
   // X and G of the next xb step are fetched into registers while the
-  // current step computes; offsets decoded once (global relative to the
-  // step, LDS).
-  constexpr int kLd = 8;
-  int xg[kLd], xl[kLd], gg[kLd], gl[kLd];
-  T xr[kLd], gr[kLd];
+  // current step computes.  Each element's offsets are decoded once and
+  // packed in one word: global offset relative to the step (bits 0-15,
+  // 0xffff = zero fill), LDS offset (bits 16-28, 0x1fff = none), tile
+  // column (bits 29-31).  K <= 64 keeps every field in range.
+  constexpr unsigned kNoG = 0xffff, kNoL = 0x1fff;
+  unsigned xo[LD], go[LD];
+  T xr[LD], gr[LD];
 #pragma unroll
-  for (int u = 0; u < kLd; ++u) {
+  for (int u = 0; u < LD; ++u) {
     const int i = tid + u * kVisitThreads;
     int xf, a, txx;
     if (rl) {
@@ -1278,31 +1325,56 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
       a = r & 15;
       xf = r >> 4;
     }
-    const bool ok = i < K4 * 16 * TX && xf < K;
-    xg[u] = !ok ? -1 : (rl ? (txx * P + a) * K + xf : (xf * P + a) * K + txx);
-    xl[u] = i < K4 * 16 * TX ? ((txx * K4 + xf) * XS + a) | (txx << 24) : -1;
+    const bool xin = i < K4 * 16 * TX;
+    const unsigned xgl = (xin && xf < K) ? (rl ? (txx * P + a) * K + xf : (xf * P + a) * K + txx)
+                                         : kNoG;
+    const unsigned xll = xin ? (txx * K4 + xf) * XS + a : kNoL;
+    xo[u] = xgl | (xll << 16) | ((unsigned)(xin ? txx : 0) << 29);
     const int gtx = i % TX, gr2 = i / TX, wb = gr2 & 15, yb = gr2 >> 4;
-    const bool gok = i < KY * 16 * TX && yb < K;
-    gg[u] = gok ? (yb * P + wb) * K + gtx : -1;
-    gl[u] = i < KY * 16 * TX ? ((gtx * 16 + wb) * GS + yb) | (gtx << 24) : -1;
+    const bool gin = i < KY * 16 * TX;
+    const unsigned ggl = (gin && yb < K) ? (yb * P + wb) * K + gtx : kNoG;
+    const unsigned gll = gin ? (gtx * 16 + wb) * GS + yb : kNoL;
+    go[u] = ggl | (gll << 16) | ((unsigned)(gin ? gtx : 0) << 29);
   }
+  // X and G of one item are K * P * K doubles each; an element outside the
+  // tile loads offset 0 and is replaced by zero.  Without the local update
+  // there is no G (null): nothing is loaded from it.
+  const unsigned xgbytes = (unsigned)K * P * K * sizeof(double);
+  const __amdgpu_buffer_rsrc_t xrs = buf_rsrc(v.X.at(it), xgbytes);
+  const __amdgpu_buffer_rsrc_t grs = buf_rsrc(v.do_local ? v.G.at(it) : v.X.at(it), xgbytes);
   auto fetch = [&](int x0) {
+    const unsigned xs = rl ? (unsigned)x0 * P * K : (unsigned)x0;
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      const int xtx = (xl[u] >> 24) & 0x7f, gtx = (gl[u] >> 24) & 0x7f;
-      const size_t xo = rl ? (size_t)x0 * P * K : (size_t)x0;
-      xr[u] = (T)((xg[u] >= 0 && x0 + xtx < K) ? X[xo + xg[u]] : 0.0);
-      gr[u] = (T)((v.do_local && gg[u] >= 0 && x0 + gtx < K) ? G[(size_t)x0 + gg[u]] : 0.0);
+    for (int u = 0; u < LD; ++u) {
+      const unsigned xg = xo[u] & 0xffff;
+      const int xtx = xo[u] >> 29;
+      const bool xv = xg != kNoG && x0 + xtx < K;
+      const double xa = buf_ld(xrs, xv ? (xs + xg) * 8u : 0u);
+      xr[u] = (T)(xv ? xa : 0.0);
+    }
+    if (v.do_local) {
+#pragma unroll
+      for (int u = 0; u < LD; ++u) {
+        const unsigned gg = go[u] & 0xffff;
+        const int gtx = go[u] >> 29;
+        const bool gv = gg != kNoG && x0 + gtx < K;
+        const double ga = buf_ld(grs, gv ? ((unsigned)x0 + gg) * 8u : 0u);
+        gr[u] = (T)(gv ? ga : 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < LD; ++u) gr[u] = (T)0;
     }
   };
   fetch(0);
 
   for (int x0 = 0; x0 < K; x0 += TX) {
-    __syncthreads();  // the previous step's readers of Xs and Gs are done
+    __syncthreads();  // the previous step's readers of Xs, Gs and T3 are done
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      if (xl[u] >= 0) Xs[xl[u] & 0xffffff] = xr[u];
-      if (gl[u] >= 0) Gs[gl[u] & 0xffffff] = gr[u];
+    for (int u = 0; u < LD; ++u) {
+      const unsigned xl = (xo[u] >> 16) & kNoL, gl = (go[u] >> 16) & kNoL;
+      if (xl != kNoL) Xs[xl] = xr[u];
+      if (gl != kNoL) Gs[gl] = gr[u];
     }
     __syncthreads();
     if (x0 + TX < K) fetch(x0 + TX);
@@ -1316,7 +1388,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
       for (; k0 < K4; k0 += 4) mma_steps<1>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
       const Acc c = acc[0] + acc[1];
       // a = lr (akx = lr/4, abx = lr%4), wf = (wfk, wfb)
-      T *dst = T1s + pp * P2 + (lr >> 2) * 16 + (lr & 3);
+      T *dst = Tp + (lr >> 2) * 16 + (lr & 3);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int wf = M::crow(r, lq);
@@ -1324,26 +1396,32 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
       }
     }
     wave_lds_order();
-    // (b) ket: rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
+    // (b) ket, one tile per s: rows m = (wfb, abx), k = (wfk, akx), cols n = (lk, wbk)
+    Acc t2[2];
 #pragma unroll
     for (int sn = 0; sn < 2; ++sn) {
       Acc acc[2] = {zero, zero};
-      mma_steps<4>(acc, T1s + pp * P2 + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
-      const Acc c = acc[0] + acc[1];
-      T *dst = T2s + pp * 16 * T2S + sn * 16 + lr;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dst[M::crow(r, lq) * T2S] = c[r];
+      mma_steps<4>(acc, Tp + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
+      t2[sn] = acc[0] + acc[1];
     }
-    wave_lds_order();
-    // (c) bra: rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb)
+    wave_lds_order();  // every lane's T1 reads precede the T3 writes below
+    // (c) bra: rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb); the
+    // A operand of k step i is register i of t2[s]
     {
       Acc acc[2] = {zero, zero};
 #pragma unroll
-      for (int sn = 0; sn < 2; ++sn)
-        mma_steps<4>(acc, T2s + (pp * 16 + lq) * T2S + sn * 16 + lr, 4 * T2S,
-                     Ab + (sn * 16 + lq) * 16 + lr, 64);
+      for (int sn = 0; sn < 2; ++sn) {
+        // B rows in the order the accumulator holds k: 4i + lq (FP64), 4lq + i (FP32)
+        const T *pb = f64 ? Ab + (sn * 16 + lq) * 16 + lr : Ab + (sn * 16 + 4 * lq) * 16 + lr;
+        constexpr int db = f64 ? 64 : 16;
+        T bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[i] = pb[i * db];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i & 1] = M::run(t2[sn][i], bv[i], acc[i & 1]);
+      }
       const Acc c = acc[0] + acc[1];
-      T *dst = T3s + pp * P2 + (lr & 3) * 16 + (lr >> 2);
+      T *dst = Tp + (lr & 3) * 16 + (lr >> 2);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // m = (lk, wbk)
         const int m = M::crow(r, lq);
@@ -1358,18 +1436,17 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int idx = u * 64 + lane, wb = idx & 15, l = idx >> 4;
-          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = T3s[pp * P2 + wb * 16 + l];
+          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = Tp[wb * 16 + l];
         }
       }
     }
     // (e) this pair's contribution to Yt[(ty, l)][yb]: k = wb of column tx
     if (v.do_local) {
 #pragma unroll
-      for (int q = 0; q < kMaxE; ++q) {
+      for (int q = 0; q < NE; ++q) {
         if (q >= tne) break;
         Acc acc[2] = {accE[q], zero};
-        mma_steps<4>(acc, T3s + pp * P2 + lq * 16 + lr, 64,
-                     Gs + (tx * 16 + lq) * GS + q * 16 + lr, 4 * GS);
+        mma_steps<4>(acc, Tp + lq * 16 + lr, 64, Gs + (tx * 16 + lq) * GS + q * 16 + lr, 4 * GS);
         accE[q] = acc[0] + acc[1];
       }
     }
@@ -1379,23 +1456,23 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4p(VisitArgs v) {
   __syncthreads();
   T *red = sm;
 #pragma unroll
-  for (int q = 0; q < kMaxE; ++q) {
+  for (int q = 0; q < NE; ++q) {
     if (q >= tne) break;
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[((pp * tne + q) * 4 + r) * 64 + lane] = accE[q][r];
   }
   __syncthreads();
   if (tx != 0) return;
-  double *Y = v.Y.at(it);
+  auto *Y = gmem(v.Y.at(it));
   const int yf = y0 + ty;
 #pragma unroll
-  for (int q = 0; q < kMaxE; ++q) {
+  for (int q = 0; q < NE; ++q) {
     if (q >= tne) break;
     const int yb = q * 16 + lr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       T acc = red[((pp * tne + q) * 4 + r) * 64 + lane];
-      for (int t2 = 1; t2 < TX; ++t2) acc += red[(((pp + t2) * tne + q) * 4 + r) * 64 + lane];
+      for (int t2i = 1; t2i < TX; ++t2i) acc += red[(((pp + t2i) * tne + q) * 4 + r) * 64 + lane];
       const int l = M::crow(r, lq);
       if (yb < K && yf < K) {
         const size_t idx = rl ? ((size_t)yb * P + l) * K + yf : ((size_t)yf * P + l) * K + yb;
@@ -2215,25 +2292,36 @@ static VisitKernel visit4_kernel(int TY, int TX) {
 template <class T>
 static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   if (f.D != 4 || f.d != 2 || f.K > 64) return false;
+  // first choice: two workgroups per CU (160 KiB of LDS); else one
   const int cand[][2] = {{2, 4}, {4, 2}};
-  for (auto &c : cand) {
-    if (c[0] > f.K) continue;
-    const size_t n = visit4p_lds<T>(f.K, c[0], c[1]) * sizeof(T);
-    const size_t moved = (size_t)std::max(ceil4(f.K), ceil16(f.K)) * 16 * c[1];
-    if (n <= 150 * 1024 && moved <= 8 * (size_t)kVisitThreads) {
-      *TY = c[0];
-      *TX = c[1];
-      *bytes = n;
-      return true;
+  for (size_t cap : {(size_t)80 * 1024, (size_t)150 * 1024})
+    for (auto &c : cand) {
+      if (c[0] > f.K) continue;
+      const size_t n = visit4p_lds<T>(f.K, c[0], c[1]) * sizeof(T);
+      if (n <= cap) {
+        *TY = c[0];
+        *TX = c[1];
+        *bytes = n;
+        return true;
+      }
     }
-  }
   return false;
 }
 
+// NE = number of 16-wide local-update tiles the kernel is built for (>= 2).
+static int visit4p_ne(int K) { return std::max(2, ceil16(K) / 16); }
+
+template <class T, int NE>
+static VisitKernel visit4p_kernel_ne(int TY, int TX) {
+  if (TY == 2 && TX == 4) return k_visit4p<2, 4, T, NE>;
+  return k_visit4p<4, 2, T, NE>;
+}
+
 template <class T>
-static VisitKernel visit4p_kernel(int TY, int TX) {
-  if (TY == 2 && TX == 4) return k_visit4p<2, 4, T>;
-  return k_visit4p<4, 2, T>;
+static VisitKernel visit4p_kernel(int TY, int TX, int NE) {
+  if (NE <= 2) return visit4p_kernel_ne<T, 2>(TY, TX);
+  if (NE == 3) return visit4p_kernel_ne<T, 3>(TY, TX);
+  return visit4p_kernel_ne<T, 4>(TY, TX);
 }
 
 // FP32 contractions run where both the visit and the environment update have
@@ -2266,12 +2354,13 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
         if (e != hipSuccess) attr_err = e;
       }
     for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2)})
-      for (VisitKernel kf : {visit4p_kernel<double>(t.first, t.second),
-                             visit4p_kernel<float>(t.first, t.second)}) {
-        hipError_t e = hipFuncSetAttribute((const void *)kf,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) attr_err = e;
-      }
+      for (int ne = 2; ne <= 4; ++ne)
+        for (VisitKernel kf : {visit4p_kernel<double>(t.first, t.second, ne),
+                               visit4p_kernel<float>(t.first, t.second, ne)}) {
+          hipError_t e = hipFuncSetAttribute(
+              (const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          if (e != hipSuccess) attr_err = e;
+        }
   });
   if (attr_err != hipSuccess) return attr_err;
   int TY4, TX4;
@@ -2306,7 +2395,9 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   if (pairw) {  // one (yf, xb) pair per wave
     v.TY = TYp;
     v.TX = TXp;
-    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(TYp, TXp) : visit4p_kernel<double>(TYp, TXp),
+    const int ne = visit4p_ne(f.K);
+    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(TYp, TXp, ne)
+                           : visit4p_kernel<double>(TYp, TXp, ne),
                        dim3((f.K + TYp - 1) / TYp, f.items), dim3(kVisitThreads), ldsp, st, v);
   } else if (spec) {
     v.TY = TY4;

@@ -8,6 +8,7 @@ and the log-norm.
 
     python tests/golden/make_golden.py obc16x16_D4_b4_chi32
     python tests/golden/make_golden.py inf2x2_D4_b4_chi32
+    python tests/golden/make_golden.py obc6x6_D6_b3_chi6 3
 """
 
 import json
@@ -36,7 +37,7 @@ def run(name, seed=0):
     else:
         A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=seed)
         bp = BlockBP(A, D=cfg["D"], chi=cfg["chi"], bx=cfg["bx"], by=cfg["by"],
-                     Lx=cfg["Lx"], Ly=cfg["Ly"])
+                     Lx=cfg["Lx"], Ly=cfg["Ly"], chi_env=cfg.get("chi_env"))
     tol = cfg.get("tol")
     res = []
     while True:
@@ -77,5 +78,8 @@ def run(name, seed=0):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) == 3 and sys.argv[2].isdigit():
+        run(sys.argv[1], seed=int(sys.argv[2]))
+        sys.exit(0)
     for n in sys.argv[1:]:
         run(n)

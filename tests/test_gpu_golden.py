@@ -5,6 +5,10 @@ written by tests/golden/make_golden.py from the FP64 oracle only).
 2x2 unit cell, D=4, 4x4 block, chi=32: the same number of sweeps as the
 oracle needed to bring the residual below 1e-10, then every observable
 within 1e-10 absolute and the log-norm within 1e-10 relative.
+
+6x6 open lattice, D=6, 3x3 blocks, chi=6, chi_env=16 (seed 3): a fixed two
+sweeps, far from converged, so the comparison checks the D=6 kernels step by
+step rather than a fixed point both sides fall into; same tolerances.
 """
 
 import json
@@ -21,8 +25,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TOL = 1e-10
 
 
-def _golden(name):
-    path = os.path.join(HERE, "golden", f"{name}_seed0.json")
+def _golden(name, seed=0):
+    path = os.path.join(HERE, "golden", f"{name}_seed{seed}.json")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     with open(path) as f:
@@ -79,3 +83,26 @@ def test_inf2x2_D4_chi32_matches_oracle():
         assert abs(ctx.expect_bond(*b, op_szsz()) - g["szsz"][i]) < TOL
     lz, _ = ctx.log_norm()
     assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
+
+
+def test_obc6x6_D6_chi6_matches_oracle():
+    from paper_2301_05844_amd import bbp
+    g = _golden("obc6x6_D6_b3_chi6", seed=3)
+    cfg = CONFIGS["obc6x6_D6_b3_chi6"]
+    A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=g["seed"])
+    ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
+                      D=cfg["D"], chi=cfg["chi"], chi_env=g["chi_env"])
+    ctx.set_tensors(A)
+    res = [ctx.sweep(1) for _ in range(g["sweeps"])]
+    _check_residuals(res, g["residuals"])
+    sites = np.array(g["sites"], dtype=np.int32)
+    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+    err_sz = np.abs(sz - np.array(g["sz"])).max()
+    ss = ctx.expect_bonds(g["bonds"], op_heis())
+    err_ss = np.abs(ss - np.array(g["ss"])).max()
+    lz, sign = ctx.log_norm()
+    print(f"max |d sz| {err_sz:.2e}  max |d SS| {err_ss:.2e}  "
+          f"log-norm {lz:.12f} vs {g['log_norm']:.12f}", flush=True)
+    assert err_sz < TOL and err_ss < TOL
+    assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
+    assert sign == g["log_norm_sign"]
