@@ -315,6 +315,9 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="streams the message and boundary-stack batches spread over "
+                         "(library default when absent)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
@@ -335,8 +338,9 @@ def main():
                      dtype=np.int32)
     bonds = [(x, y, x + 1, y) for y in range(cfg["Ly"]) for x in range(cfg["Lx"] - 1)]
     bonds += [(x, y, x, y + 1) for y in range(cfg["Ly"] - 1) for x in range(cfg["Lx"])]
+    opts = {} if args.lanes is None else dict(lanes=args.lanes)
     ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
-                      D=cfg["D"], chi=cfg["chi"])
+                      D=cfg["D"], chi=cfg["chi"], **opts)
 
     # warm-up: find the sweep count that reaches the tolerance
     log("warm-up: sweeping to the tolerance")

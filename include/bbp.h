@@ -84,6 +84,12 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              stay FP64); QR, normalisation, overlaps and every stored
  *              message stay FP64.  Sweeps in 32 followed by sweeps in 64
  *              reach the FP64 fixed point from the FP32 one.
+ *   "lanes"    1..4 (default 1; before bbp_set_tensors): message batches and
+ *              boundary-stack batches are split over this many streams (the
+ *              context stream and lanes-1 streams the context creates) so
+ *              that independent batches overlap on the GPU.  Results do not
+ *              depend on it; the context stream waits for every lane before
+ *              a call returns.
  * Unknown keys or out-of-range values: BBP_EINVAL.
  */
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
@@ -92,7 +98,8 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
  * null stream).  The pointer is a HIP stream handle; NULL selects the null
  * stream.  Every transfer the context makes is ordered on this stream, so a
  * non-blocking stream is fine; it must stay valid until bbp_destroy, which
- * synchronises it. */
+ * synchronises it.  With "lanes" > 1 the context also launches on streams of
+ * its own, forked from and joined back into this one inside each call. */
 bbp_status bbp_set_stream(bbp_ctx *c, void *hip_stream);
 
 /*

@@ -105,6 +105,7 @@ struct Group {
   std::vector<FitDims> dims;  // [items][W], host copy
   std::vector<int> have;      // [items*W] warm start valid
   // host staging of the per-sweep tables (kept alive until the stream syncs)
+  std::vector<double> host;  // rotated region tensors of a boundary-stack batch
   std::vector<GatherSrc> gs;
   std::vector<double *> dsts;
   std::vector<int32_t> revs;
@@ -134,8 +135,11 @@ struct bbp_ctx {
   int gx = 1, gy = 1;
   int chi_env = -1, n_fit = 2;
   int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
+  int lanes = 1;       // streams that independent fit batches spread over
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
+  std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
+  std::vector<hipEvent_t> lane_ev;  // fork event, then one join event per aux lane
   bool tensors_set = false;
   bool device_ready = false;
   std::string err;
@@ -305,6 +309,74 @@ static hipError_t zero_sync(bbp_ctx *c, void *p, size_t bytes) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return e;
 }
+
+// ---- lanes: independent batches on several streams ------------------------
+// Lane 0 is the context stream; lanes 1.. are the context's own non-blocking
+// streams (default priority), created on first use.  Batches of different
+// messages (or boundary stacks) share no buffers, so they may run
+// concurrently; every kernel's result depends only on its own inputs, so the
+// results do not depend on the lane count.
+static hipError_t make_lanes(bbp_ctx *c, int n) {
+  while ((int)c->aux.size() < n - 1) {
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    c->aux.push_back(s);
+  }
+  while ((int)c->lane_ev.size() < n) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    c->lane_ev.push_back(ev);
+  }
+  return hipSuccess;
+}
+static hipStream_t lane_stream(const bbp_ctx *c, int l) {
+  return l == 0 ? c->stream : c->aux[l - 1];
+}
+
+// Work enqueued on lanes 1..n-1 after fork() is ordered after everything
+// enqueued on the context stream before it; after join() (also run by the
+// destructor, so an early error return still joins) the context stream
+// waits for all of it.
+struct LaneFork {
+  bbp_ctx *c;
+  int n = 1;
+  explicit LaneFork(bbp_ctx *ctx) : c(ctx) {}
+  hipError_t fork(int want) {
+    hipError_t e = make_lanes(c, want);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(c->lane_ev[0], c->stream);
+    for (int l = 1; e == hipSuccess && l < want; ++l)
+      e = hipStreamWaitEvent(c->aux[l - 1], c->lane_ev[0], 0);
+    if (e == hipSuccess) n = want;
+    return e;
+  }
+  hipError_t join() {
+    hipError_t e = hipSuccess;
+    for (int l = 1; l < n; ++l) {
+      hipError_t e1 = hipEventRecord(c->lane_ev[l], c->aux[l - 1]);
+      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(c->stream, c->lane_ev[l], 0);
+      if (e == hipSuccess) e = e1;
+    }
+    n = 1;
+    return e;
+  }
+  ~LaneFork() { (void)join(); }
+};
+
+// Splits a batch of ids into up to `parts` contiguous batches of at least
+// `min_items` each.
+static std::vector<std::vector<int>> split_batch(const std::vector<int> &ids, int parts,
+                                                 int min_items) {
+  const int n = (int)ids.size();
+  const int k = std::max(1, std::min(parts, n / std::max(1, min_items)));
+  std::vector<std::vector<int>> out(k);
+  for (int p = 0; p < k; ++p)
+    out[p].assign(ids.begin() + (size_t)n * p / k, ids.begin() + (size_t)n * (p + 1) / k);
+  return out;
+}
+constexpr int kLaneMinItems = 8;
 
 // ---------------------------------------------------------------------------
 static bbp_status ensure_device(bbp_ctx *c) {
@@ -488,8 +560,7 @@ static double column_macs(const FitDims &f, const std::vector<int> &xb_bonds,
 // Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
 // each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
 // for the bond caps and the random-start flags.
-static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo) {
-  hipStream_t st = c->stream;
+static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st) {
   FitBatch &f = g.fb;
   const int W = f.W, N = f.N;
   hipError_t e;
@@ -586,8 +657,12 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
   if (e != hipSuccess) return c->hip_fail(e, "memset");
   std::vector<std::vector<int>> new_bonds(c->msgs.size());
   double flops = 0.0;
-  for (auto &gp : c->groups) {
-    Group &g = *gp;
+  const int nl = std::max(1, std::min(c->lanes, (int)c->groups.size()));
+  LaneFork lanes(c);
+  if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+  for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+    Group &g = *c->groups[gi];
+    st = lane_stream(c, (int)(gi % nl));
     FitBatch &f = g.fb;
     const int W = f.W, H = f.H, N = f.N;
     std::vector<GatherSrc> &gs = g.gs;
@@ -656,11 +731,13 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
     e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
     if (e != hipSuccess) return c->hip_fail(e, "gather");
 
-    bbp_status bs = absorb_columns(c, g, 0);
+    bbp_status bs = absorb_columns(c, g, 0, st);
     if (bs != BBP_OK) return bs;
     e = launch_extract(f, (double *const *)g.dst.p, (const int32_t *)g.rev.p, st);
     if (e != hipSuccess) return c->hip_fail(e, "extract");
   }
+  st = c->stream;
+  if ((e = lanes.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
   // residual: overlaps of new and old messages, grouped by length
   const int nm = (int)c->msgs.size();
   std::vector<double> ov(nm, 0.0);
@@ -862,15 +939,19 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   std::map<std::pair<int, int>, std::vector<int>> sgroups;
   for (size_t i = 0; i < stacks.size(); ++i)
     sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
+  std::vector<std::vector<int>> batches;  // per shape, split for the lanes
+  for (auto &kv : sgroups)
+    for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) batches.push_back(part);
   std::vector<std::unique_ptr<Group>> sg;
   std::vector<std::pair<int, int>> where(stacks.size());  // (group, item)
   std::vector<std::vector<double>> nus;
-  for (auto &kv : sgroups) {
+  // allocate and stage every batch first: allocation waits on the context
+  // stream, which must not yet hold absorption work
+  for (const std::vector<int> &ids : batches) {
     std::unique_ptr<Group> gp(new Group);
     Group &g = *gp;
-    g.W = kv.first.first;
-    g.H = kv.first.second;
-    const std::vector<int> &ids = kv.second;
+    g.W = stacks[ids[0]].Wc;
+    g.H = stacks[ids[0]].Hc;
     std::vector<uint64_t> slots(ids.size());
     for (size_t i = 0; i < ids.size(); ++i) {
       const StackItem &it = stacks[ids[i]];
@@ -882,7 +963,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     if (bs != BBP_OK) return bs;
     FitBatch &f = g.fb;
     // rotated tensors, gather tables and bond caps
-    std::vector<double> host((size_t)f.items * f.H * f.W * asite);
+    g.host.assign((size_t)f.items * f.H * f.W * asite, 0.0);
     g.gs.assign(f.items, GatherSrc{});
     for (int i = 0; i < f.items; ++i) {
       const StackItem &it = stacks[ids[i]];
@@ -892,7 +973,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
           int y, x;
           canon_to_region(it.orient, R.H, R.W, yc, xc, &y, &x);
           rotate_site(c, region_site(c, R, y, x), it.orient,
-                      host.data() + (((size_t)i * f.H + yc) * f.W + xc) * asite);
+                      g.host.data() + (((size_t)i * f.H + yc) * f.W + xc) * asite);
         }
       char side[3];
       int rv[3];
@@ -908,27 +989,41 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         g.dims[(size_t)i * f.W + col] = cd[col];
       }
     }
-    e = hipMemcpyAsync(f.acan, host.data(), host.size() * 8,
-                       hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(g.gather.p, g.gs.data(), sizeof(GatherSrc) * f.items,
-                         hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);  // host staging reused
-    if (e != hipSuccess) return c->hip_fail(e, "region setup");
-    if (f.W > 1) {
-      bs = absorb_columns(c, g, 1);
-      if (bs != BBP_OK) return bs;
-    }
-    std::vector<double> nu((size_t)f.items * f.W, 1.0);
-    e = hipMemcpyAsync(nu.data(), f.nu, nu.size() * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return c->hip_fail(e, "region stacks");
-    if (f.W == 1) std::fill(nu.begin(), nu.end(), 1.0);
-    nus.push_back(nu);
     g.ids = ids;
     sg.push_back(std::move(gp));
   }
+  {  // uploads, gather and absorption; batch b on lane b % nl
+    const int nl = std::max(1, std::min(c->lanes, (int)sg.size()));
+    LaneFork lanes(c);
+    if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+    for (size_t b = 0; b < sg.size(); ++b) {
+      Group &g = *sg[b];
+      FitBatch &f = g.fb;
+      const hipStream_t sb = lane_stream(c, (int)(b % nl));
+      e = hipMemcpyAsync(f.acan, g.host.data(), g.host.size() * 8, hipMemcpyHostToDevice, sb);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g.gather.p, g.gs.data(), sizeof(GatherSrc) * f.items,
+                           hipMemcpyHostToDevice, sb);
+      if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, sb);
+      if (e != hipSuccess) return c->hip_fail(e, "region setup");
+      if (f.W > 1) {
+        bbp_status bs = absorb_columns(c, g, 1, sb);
+        if (bs != BBP_OK) return bs;
+      }
+    }
+    if ((e = lanes.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
+  }
+  for (auto &gp : sg) {  // column scales of every batch
+    const FitBatch &f = gp->fb;
+    nus.emplace_back((size_t)f.items * f.W, 1.0);
+    if (f.W > 1) {
+      e = hipMemcpyAsync(nus.back().data(), f.nu, nus.back().size() * 8,
+                         hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) return c->hip_fail(e, "region stacks");
+    }
+  }
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return c->hip_fail(e, "region stacks");
   int32_t errv = 0;
   e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return c->hip_fail(e, "error flag");
@@ -1484,6 +1579,10 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     c->precision = (int)v;
     for (auto &g : c->groups) g->fb.prec = c->precision;
     c->obs.clear();
+  } else if (k == "lanes") {
+    if (v < 1 || v > 4 || v != std::floor(v))
+      return c->fail(BBP_EINVAL, "lanes must be an integer in [1,4]");
+    c->lanes = (int)v;
   } else if (k == "seed") {
     if (v < 0 || v != std::floor(v) || v > 9007199254740992.0)
       return c->fail(BBP_EINVAL, "seed must be a non-negative integer");
@@ -1574,6 +1673,17 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       c->groups.back()->H = H;
     }
     c->groups[gid[key]]->ids.push_back((int)i);
+  }
+  {  // large batches split so that the lanes can overlap them
+    std::vector<std::unique_ptr<Group>> split;
+    for (auto &g : c->groups)
+      for (auto &part : split_batch(g->ids, c->lanes, kLaneMinItems)) {
+        split.emplace_back(new Group);
+        split.back()->W = g->W;
+        split.back()->H = g->H;
+        split.back()->ids = part;
+      }
+    c->groups.swap(split);
   }
   for (auto &g : c->groups) {
     // random-state slot bases: message e, column c -> (1<<40)|(e<<8)|c
@@ -1822,6 +1932,11 @@ const char *bbp_last_error(const bbp_ctx *c) {
 void bbp_destroy(bbp_ctx *c) {
   if (!c) return;
   if (c->device_ready) (void)hipStreamSynchronize(c->stream);
+  for (hipStream_t s : c->aux) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (hipEvent_t ev : c->lane_ev) (void)hipEventDestroy(ev);
   delete c;
 }
 

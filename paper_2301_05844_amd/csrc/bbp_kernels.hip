@@ -163,8 +163,18 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double *p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, (int)bytes, 0x00020000);
 }
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, (int)bytes, 0x00020000);
+}
 __device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+template <class T> __device__ __forceinline__ T buf_ld_t(__amdgpu_buffer_rsrc_t r, unsigned byte_off);
+template <> __device__ __forceinline__ double buf_ld_t<double>(__amdgpu_buffer_rsrc_t r, unsigned o) {
+  return buf_ld(r, o);
+}
+template <> __device__ __forceinline__ float buf_ld_t<float>(__amdgpu_buffer_rsrc_t r, unsigned o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
 }
 
 // Orders one wave's LDS writes before its later LDS reads (other lanes).
@@ -187,6 +197,9 @@ template <> struct Mma<double> {
   static __device__ __forceinline__ v4d run(double a, double b, v4d c) { return mfma16(a, b, c); }
   static __host__ __device__ constexpr int pad_a(int x) { return bbp::pad_a(x); }
   static __host__ __device__ constexpr int pad_b(int x) { return bbp::pad_b(x); }
+  // smallest A-operand row stride >= x whose 16 rows x 2 lane groups of a
+  // half wave fall in distinct banks: any stride = 2 (mod 4)
+  static __host__ __device__ constexpr int pad_a_min(int x) { return x + (6 - x % 4) % 4; }
 };
 template <> struct Mma<float> {
   typedef v4f acc;
@@ -196,6 +209,7 @@ template <> struct Mma<float> {
   }
   static __host__ __device__ constexpr int pad_a(int x) { return x + (68 - x % 64) % 64; }
   static __host__ __device__ constexpr int pad_b(int x) { return x + (80 - x % 64) % 64; }
+  static __host__ __device__ constexpr int pad_a_min(int x) { return x + (12 - x % 8) % 8; }
 };
 
 template <int BM, int BN, int BK, class Op>
@@ -435,11 +449,13 @@ struct OpK5 {
 
 // ---- environment update after the QR, Lenv' = T3 . Y ----------------------
 // E[y'][wb][xb] = sum_{yf, l} Y[yf][l][y'] T3[yf][l][xb][wb]  (RL: Y[y'][l][yf]).
-// One workgroup of 4 waves per (item, 64 columns n = (xb, wb)); each wave owns
-// 16 columns and all MT row tiles of y'.  The T3 operand is read straight
-// from global memory (16 lanes, 128 contiguous bytes); Y is staged in LDS in
-// chunks of 32 k = (yf, l).  The next chunk of both is fetched into registers
-// while the current one is multiplied; one barrier per chunk.
+// One workgroup per (item, 64 columns n = (xb, wb)) of 4 KS waves: wave w owns
+// the 16 columns w % 4 and all MT row tiles of y', over the k part w / 4 of
+// every chunk.  The T3 operand is read straight from global memory (16 lanes,
+// 128 contiguous bytes); Y is staged in LDS in chunks of 32 KS k = (yf, l).
+// The next chunk of both is fetched into registers while the current one is
+// multiplied; one barrier per chunk.  The KS partial sums of a column tile are
+// added at the end in a fixed order (k part 0, 1, ...).
 struct EnvArgs {
   int K, P, rl;
   const double *t3;
@@ -447,50 +463,67 @@ struct EnvArgs {
   Ptr Y, E;
 };
 
-constexpr int kEnvThreads = 256;
+// k parts per workgroup: two while the staged chunks stay small
+template <int MT> struct EnvShape {
+  static constexpr int KS = MT <= 3 ? 2 : 1;
+  static constexpr int kThreads = 256 * KS;
+  static constexpr int kWaves = KS == 2 ? 4 : 2;  // waves per SIMD the registers allow
+};
 
 template <int MT, class T>
-__global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
+__global__ __launch_bounds__(EnvShape<MT>::kThreads)
+__attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e) {
   typedef Mma<T> M;
   typedef typename M::acc Acc;
-  constexpr int MW = MT * 16, AS = M::pad_b(MW), CH = 32;
-  constexpr int NA = CH * MW / kEnvThreads;  // A elements staged per thread
+  constexpr int KS = EnvShape<MT>::KS, NT = EnvShape<MT>::kThreads;
+  constexpr int MW = MT * 16, AS = M::pad_b(MW), CH = 32 * KS;
+  constexpr int NA = CH * MW / NT;  // A elements staged per thread
   __shared__ T As[2][CH][AS];
   const int K = e.K, P = e.P, N = K * P, Kd = K * P;
   const int it = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lq = lane >> 4;
-  const int n = blockIdx.x * 64 + wave * 16 + lr;
+  const int lr = lane & 15, lq = lane >> 4, cg = wave & 3, h = wave >> 2;
+  const int n = blockIdx.x * 64 + cg * 16 + lr;
+  // Y (K P K doubles) and this item's T3 (K P x K P) through buffer
+  // descriptors; an element outside the operand loads offset 0 and is
+  // replaced by zero
   const T *T3 = reinterpret_cast<const T *>(e.t3) + (size_t)it * e.t3s;
-  const auto *Y = gmem(e.Y.at(it));
+  const __amdgpu_buffer_rsrc_t yrs = buf_rsrc(e.Y.at(it), (unsigned)(K * P * K) * 8u);
+  const __amdgpu_buffer_rsrc_t trs = buf_rsrc(T3, (unsigned)(Kd * N) * (unsigned)sizeof(T));
   const bool rl = e.rl != 0;
   T an[NA], bn[8];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int i = tid + u * kEnvThreads, kk = i / MW, m = i % MW, k = k0 + kk;
-      double x = 0.0;
-      if (m < K && k < Kd) {
-        const int yf = k / P, l = k - yf * P;
-        x = rl ? Y[((size_t)m * P + l) * K + yf] : Y[(size_t)k * K + m];
-      }
-      an[u] = (T)x;
+      const int i = tid + u * NT, kk = i / MW, m = i % MW, k = k0 + kk;
+      const bool ok = m < K && k < Kd;
+      const int yf = k / P, l = k - yf * P;
+      const unsigned off = rl ? (m * P + l) * K + yf : k * K + m;
+      const double x = buf_ld(yrs, ok ? off * 8u : 0u);
+      an[u] = (T)(ok ? x : 0.0);
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int k = k0 + 4 * i + lq;
-      bn[i] = (n < N && k < Kd) ? T3[(size_t)k * N + n] : (T)0;
+      const int k = k0 + h * 32 + 4 * i + lq;
+      const bool ok = n < N && k < Kd;
+      const T x = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : 0u);
+      bn[i] = ok ? x : (T)0;
     }
   };
   auto put = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      const int i = tid + u * kEnvThreads;
+      const int i = tid + u * NT;
       As[buf][i / MW][i % MW] = an[u];
     }
   };
-  Acc acc[MT][2];
+  // two accumulation chains per row tile, one where MT tiles already give
+  // three or more independent chains
+  constexpr int NC = MT >= 3 ? 1 : 2;
+  Acc acc[MT][NC];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = Acc{0, 0, 0, 0};
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[mt][q] = Acc{0, 0, 0, 0};
   fetch(0);
   put(0);
   __syncthreads();
@@ -504,21 +537,44 @@ __global__ __launch_bounds__(kEnvThreads) void k_env(EnvArgs e) {
     for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
-        acc[mt][i & 1] = M::run(As[buf][4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i & 1]);
+        acc[mt][i % NC] =
+            M::run(As[buf][h * 32 + 4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i % NC]);
     if (k0 + CH < Kd) put(buf ^ 1);
     __syncthreads();
     buf ^= 1;
+  }
+  Acc c[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) c[mt] = NC == 1 ? acc[mt][0] : acc[mt][0] + acc[mt][NC - 1];
+  if (KS > 1) {  // k parts 1.. hand their sums to part 0 through LDS
+    T *red = &As[0][0][0];
+    static_assert((KS - 1) * 4 * MT * 4 * 64 <= 2 * CH * AS, "reduction fits");
+    if (h > 0) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[((((h - 1) * 4 + cg) * MT + mt) * 4 + r) * 64 + lane] = c[mt][r];
+    }
+    __syncthreads();
+    if (h > 0) return;
+#pragma unroll
+    for (int hh = 1; hh < KS; ++hh)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          c[mt][r] += red[((((hh - 1) * 4 + cg) * MT + mt) * 4 + r) * 64 + lane];
   }
   if (n >= N) return;
   const int xb = n / P, wb = n - xb * P;
   auto *E = gmem(e.E.at(it));
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    const Acc c = acc[mt][0] + acc[mt][1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = mt * 16 + M::crow(r, lq);
-      if (m < K) E[((size_t)m * P + wb) * K + xb] = (double)c[r];
+      if (m < K) E[((size_t)m * P + wb) * K + xb] = (double)c[mt][r];
     }
   }
 }
@@ -1233,31 +1289,44 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
 // elements of the X and G tiles per step.  Up to NE = 3 the kernel is held to
 // 128 VGPRs so that two workgroups (4 waves per SIMD) share a CU when the LDS
 // allows it.
-// LDS: Fs [(ty, wf)][xf] (row stride pad_a(K4)); Xs [tx][xf][a] (stride
-// pad_b(16)); per pair T1 [wfk,akx][wfb,abx] / T3 [wbk,wbb][lk,lb]; Gs
-// [(tx, wb)][yb] (stride pad_b(K)); Ak, Ab [s][wf][a][l][wb].
+// LDS: Fs [(ty, wf)][xf] (row stride pad_a_min(K4)); Xs [tx][xf][a] (rows
+// of 16, tile stride 16 K4 + 32 / TX); per pair T1 [wfk,akx][wfb,abx] and
+// T3 [wbk,wbb][lk,lb] (rows of 16); Gs [(tx, wb)][yb] (stride pad_b(K));
+// Ak, Ab [s][wf][a][l][wb].  Rows of Xs, T1, T3 and Gs are stored with their
+// column index XOR-ed by a function of the row (v4p_*_sw below), which
+// leaves every MFMA operand read conflict-free and also makes the accesses
+// that walk a column (the refill stores, the MFMA result stores, the T3 read
+// for the HBM store) hit distinct LDS banks.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int v4p_x_sw(int xf) { return (xf >> 1) & 15; }
+__host__ __device__ constexpr int v4p_t1_sw(int k) { return ((k >> 1) & 1) << 3; }
+__host__ __device__ constexpr int v4p_t3_sw(int wb) { return ((wb << 1) & 12) | ((wb >> 2) & 2); }
+__host__ __device__ constexpr int v4p_g_sw(int row) { return ((row >> 1) ^ ((row >> 4) << 2)) & 15; }
+__host__ __device__ constexpr int v4p_xt(int K4, int TX) { return 16 * K4 + 32 / TX; }
 template <class T>
 __host__ __device__ inline size_t visit4p_lds(int K, int TY, int TX) {
   typedef Mma<T> M;
   const int K4 = ceil4(K), tne = ceil16(K) / 16;
-  const size_t body = (size_t)TY * 16 * M::pad_a(K4) + (size_t)TX * K4 * M::pad_b(16) +
+  const size_t body = (size_t)TY * 16 * M::pad_a_min(K4) + (size_t)TX * v4p_xt(K4, TX) +
                       (size_t)TY * TX * 256 + (size_t)TX * 16 * M::pad_b(K) + 2 * 2 * 256;
   return std::max(body, (size_t)TY * TX * tne * 256);
 }
 
+// One wave per (yf, xb) pair of a TY x TX tile: NT threads.  LD elements of
+// each of the X and G tiles (16 NE x 16 x TX) per thread and step.  At
+// NE = 2 (K <= 32) three workgroups of 2 x 2 share a CU (LDS <= 47 KB), so
+// the registers are held to 3 waves per SIMD; above, to 2.
 template <int TY, int TX, int NE>
 struct Visit4pShape {
-  static constexpr int LD = (NE * TX + 1) / 2;  // 16 NE * 16 TX elements over 512 threads
-  // 4 waves per SIMD (128 VGPRs) only where the LDS can hold two workgroups
-  static constexpr int kWaves = (NE == 2 || (NE == 3 && TX == 2)) ? 4 : 2;
+  static constexpr int NWV = TY * TX, NT = 64 * NWV;
+  static constexpr int LD = (NE * 16 * 16 * TX + NT - 1) / NT;
 };
 
 template <int TY, int TX, class T, int NE>
-__global__ __launch_bounds__(kVisitThreads)
-__attribute__((amdgpu_waves_per_eu(Visit4pShape<TY, TX, NE>::kWaves)))
+__global__ __launch_bounds__(64 * TY * TX)
+__attribute__((amdgpu_waves_per_eu(NE <= 2 ? 3 : 2)))
 void k_visit4p(VisitArgs v) {
-  static_assert(TY * TX == kVisitWaves, "one pair per wave");
+  constexpr int NT = Visit4pShape<TY, TX, NE>::NT, NWV = Visit4pShape<TY, TX, NE>::NWV;
   extern __shared__ double sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
   typedef Mma<T> M;
@@ -1265,15 +1334,15 @@ void k_visit4p(VisitArgs v) {
   const Acc zero = Acc{0, 0, 0, 0};
   constexpr int D = 4, P = 16, P2 = 256, NP = TY * TX;
   constexpr int LD = Visit4pShape<TY, TX, NE>::LD;
-  constexpr int XS = M::pad_b(16);
   constexpr bool f64 = sizeof(T) == 8;
-  const int K = v.K, K4 = ceil4(K), FS = M::pad_a(K4), GS = M::pad_b(K), KY = ceil16(K);
+  const int K = v.K, K4 = ceil4(K), FS = M::pad_a_min(K4), GS = M::pad_b(K), KY = ceil16(K);
+  const int XT = v4p_xt(K4, TX);
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   T *Fs = sm;
   T *Xs = Fs + TY * 16 * FS;
-  T *T13s = Xs + TX * K4 * XS;
+  T *T13s = Xs + TX * XT;
   T *Gs = T13s + NP * P2;
   T *Ak = Gs + TX * 16 * GS;
   T *Ab = Ak + 2 * P2;
@@ -1285,14 +1354,14 @@ void k_visit4p(VisitArgs v) {
   const int ty = wave / TX, tx = wave % TX, pp = wave;  // this wave's pair
   T *Tp = T13s + pp * P2;
 
-  for (int i = tid; i < 2 * P2; i += kVisitThreads) {
+  for (int i = tid; i < 2 * P2; i += NT) {
     const int wb = i & 3, l = (i >> 2) & 3, a = (i >> 4) & 3, wf = (i >> 6) & 3, s = i >> 8;
     const int u = rl ? wb : wf, dd = rl ? wf : wb;
     const int src = ((((s * D + u) * D + l) * D + dd) * D + a);
     Ak[i] = (T)ak[src];
     Ab[i] = (T)ab[src];
   }
-  for (int row = wave; row < TY * 16; row += kVisitWaves) {
+  for (int row = wave; row < TY * 16; row += NWV) {
     const bool ok = y0 + (row >> 4) < K;
     for (int xf = lane; xf < K4; xf += 64)
       Fs[row * FS + xf] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
@@ -1303,67 +1372,59 @@ void k_visit4p(VisitArgs v) {
   for (int q = 0; q < NE; ++q) accE[q] = zero;
 
   // X and G of the next xb step are fetched into registers while the
-  // current step computes.  Each element's offsets are decoded once and
-  // packed in one word: global offset relative to the step (bits 0-15,
-  // 0xffff = zero fill), LDS offset (bits 16-28, 0x1fff = none), tile
-  // column (bits 29-31).  K <= 64 keeps every field in range.
-  constexpr unsigned kNoG = 0xffff, kNoL = 0x1fff;
-  unsigned xo[LD], go[LD];
-  T xr[LD], gr[LD];
-#pragma unroll
-  for (int u = 0; u < LD; ++u) {
-    const int i = tid + u * kVisitThreads;
-    int xf, a, txx;
+  // current step computes.  Thread element u is i = tid + 512 u of the tile
+  // [xf][a][tx] (rl: [tx][a][xf]) and [yb][wb][tx], each index taken over
+  // the compile-time extent XF = 16 NE >= K4; the decode is recomputed where
+  // needed rather than held in registers.
+  constexpr int XF = 16 * NE, NX = XF * 16 * TX;
+  auto xdec = [&](int u, int &txx, int &a, int &xf) {
+    const int i = tid + u * NT;
     if (rl) {
-      xf = i % K4;
-      const int r = i / K4;
-      a = r & 15;
-      txx = r >> 4;
+      xf = i % XF;
+      a = (i / XF) & 15;
+      txx = i / (XF * 16);
     } else {
       txx = i % TX;
-      const int r = i / TX;
-      a = r & 15;
-      xf = r >> 4;
+      a = (i / TX) & 15;
+      xf = i / (TX * 16);
     }
-    const bool xin = i < K4 * 16 * TX;
-    const unsigned xgl = (xin && xf < K) ? (rl ? (txx * P + a) * K + xf : (xf * P + a) * K + txx)
-                                         : kNoG;
-    const unsigned xll = xin ? (txx * K4 + xf) * XS + a : kNoL;
-    xo[u] = xgl | (xll << 16) | ((unsigned)(xin ? txx : 0) << 29);
-    const int gtx = i % TX, gr2 = i / TX, wb = gr2 & 15, yb = gr2 >> 4;
-    const bool gin = i < KY * 16 * TX;
-    const unsigned ggl = (gin && yb < K) ? (yb * P + wb) * K + gtx : kNoG;
-    const unsigned gll = gin ? (gtx * 16 + wb) * GS + yb : kNoL;
-    go[u] = ggl | (gll << 16) | ((unsigned)(gin ? gtx : 0) << 29);
-  }
-  // X and G of one item are K * P * K doubles each; an element outside the
-  // tile loads offset 0 and is replaced by zero.  Without the local update
-  // there is no G (null): nothing is loaded from it.
+  };
+  auto gdec = [&](int u, int &gtx, int &wb, int &yb) {
+    const int i = tid + u * NT;
+    gtx = i % TX;
+    wb = (i / TX) & 15;
+    yb = i / (TX * 16);
+  };
+  // raw loads of the pending step and which of them are real elements (the
+  // rest become zero when stored): nothing waits on the loads before the
+  // refill at the next step.  X and G of one item are K P K doubles each; an
+  // element outside the tile loads offset 0.  Without the local update there
+  // is no G (null): nothing is loaded from it.
+  double xr[LD], gr[LD];
+  unsigned xm = 0, gm = 0;
   const unsigned xgbytes = (unsigned)K * P * K * sizeof(double);
   const __amdgpu_buffer_rsrc_t xrs = buf_rsrc(v.X.at(it), xgbytes);
   const __amdgpu_buffer_rsrc_t grs = buf_rsrc(v.do_local ? v.G.at(it) : v.X.at(it), xgbytes);
   auto fetch = [&](int x0) {
-    const unsigned xs = rl ? (unsigned)x0 * P * K : (unsigned)x0;
+    xm = gm = 0;
 #pragma unroll
     for (int u = 0; u < LD; ++u) {
-      const unsigned xg = xo[u] & 0xffff;
-      const int xtx = xo[u] >> 29;
-      const bool xv = xg != kNoG && x0 + xtx < K;
-      const double xa = buf_ld(xrs, xv ? (xs + xg) * 8u : 0u);
-      xr[u] = (T)(xv ? xa : 0.0);
+      int txx, a, xf;
+      xdec(u, txx, a, xf);
+      const bool xv = tid + u * NT < NX && xf < K && x0 + txx < K;
+      const unsigned off = rl ? ((x0 + txx) * P + a) * K + xf : (xf * P + a) * K + x0 + txx;
+      xr[u] = buf_ld(xrs, xv ? off * 8u : 0u);
+      xm |= (unsigned)xv << u;
     }
     if (v.do_local) {
 #pragma unroll
       for (int u = 0; u < LD; ++u) {
-        const unsigned gg = go[u] & 0xffff;
-        const int gtx = go[u] >> 29;
-        const bool gv = gg != kNoG && x0 + gtx < K;
-        const double ga = buf_ld(grs, gv ? ((unsigned)x0 + gg) * 8u : 0u);
-        gr[u] = (T)(gv ? ga : 0.0);
+        int gtx, wb, yb;
+        gdec(u, gtx, wb, yb);
+        const bool gv = tid + u * NT < NX && yb < K && x0 + gtx < K;
+        gr[u] = buf_ld(grs, gv ? ((yb * P + wb) * K + x0 + gtx) * 8u : 0u);
+        gm |= (unsigned)gv << u;
       }
-    } else {
-#pragma unroll
-      for (int u = 0; u < LD; ++u) gr[u] = (T)0;
     }
   };
   fetch(0);
@@ -1371,10 +1432,14 @@ void k_visit4p(VisitArgs v) {
   for (int x0 = 0; x0 < K; x0 += TX) {
     __syncthreads();  // the previous step's readers of Xs, Gs and T3 are done
 #pragma unroll
-    for (int u = 0; u < LD; ++u) {
-      const unsigned xl = (xo[u] >> 16) & kNoL, gl = (go[u] >> 16) & kNoL;
-      if (xl != kNoL) Xs[xl] = xr[u];
-      if (gl != kNoL) Gs[gl] = gr[u];
+    for (int u = 0; u < LD; ++u) {  // rows up to K4 and K rows of G (zero where not real)
+      if (tid + u * NT >= NX) continue;
+      int txx, a, xf, gtx, wb, yb;
+      xdec(u, txx, a, xf);
+      gdec(u, gtx, wb, yb);
+      if (xf < K4) Xs[txx * XT + xf * 16 + (a ^ v4p_x_sw(xf))] = (T)(((xm >> u) & 1) ? xr[u] : 0.0);
+      const int grow = gtx * 16 + wb;
+      if (yb < KY) Gs[grow * GS + (yb ^ v4p_g_sw(grow))] = (T)(((gm >> u) & 1) ? gr[u] : 0.0);
     }
     __syncthreads();
     if (x0 + TX < K) fetch(x0 + TX);
@@ -1382,17 +1447,31 @@ void k_visit4p(VisitArgs v) {
     {
       Acc acc[2] = {zero, zero};
       const T *pa = Fs + (ty * 16 + lr) * FS + lq;
-      const T *pb = Xs + (tx * K4 + lq) * XS + lr;
+      const T *px = Xs + tx * XT;
+      // Xs row xf = k0 + lq (k0 = 0 mod 4): swizzle ((k0 >> 1) & 15) ^ (lq >> 1)
+      const int xb0 = lq * 16 + (lr ^ (lq >> 1));
       int k0 = 0;
-      for (; k0 + 16 <= K4; k0 += 16) mma_steps<4>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
-      for (; k0 < K4; k0 += 4) mma_steps<1>(acc, pa + k0, 4, pb + k0 * XS, 4 * XS);
+      for (; k0 + 16 <= K4; k0 += 16) {
+        const T *pk = px + k0 * 16;
+        const int sw = (k0 >> 1) & 8;
+        T av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          av[i] = pa[k0 + 4 * i];
+          bv[i] = pk[(xb0 ^ (sw | 2 * i)) + 64 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i & 1] = M::run(av[i], bv[i], acc[i & 1]);
+      }
+      for (; k0 < K4; k0 += 4)
+        acc[0] = M::run(pa[k0], px[k0 * 16 + (xb0 ^ ((k0 >> 1) & 15))], acc[0]);
       const Acc c = acc[0] + acc[1];
-      // a = lr (akx = lr/4, abx = lr%4), wf = (wfk, wfb)
-      T *dst = Tp + (lr >> 2) * 16 + (lr & 3);
+      // a = lr (akx = lr/4, abx = lr%4), wf = (wfk, wfb): row (wfk, akx),
+      // column (wfb, abx)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int wf = M::crow(r, lq);
-        dst[(wf >> 2) * 64 + (wf & 3) * 4] = c[r];
+        const int wf = M::crow(r, lq), row = (wf >> 2) * 4 + (lr >> 2);
+        Tp[row * 16 + (((wf & 3) * 4 + (lr & 3)) ^ v4p_t1_sw(row))] = c[r];
       }
     }
     wave_lds_order();
@@ -1401,7 +1480,8 @@ void k_visit4p(VisitArgs v) {
 #pragma unroll
     for (int sn = 0; sn < 2; ++sn) {
       Acc acc[2] = {zero, zero};
-      mma_steps<4>(acc, Tp + lq * 16 + lr, 64, Ak + sn * P2 + lq * 16 + lr, 64);
+      // T1 row 4i + lq: its swizzle depends on lq only
+      mma_steps<4>(acc, Tp + lq * 16 + (lr ^ v4p_t1_sw(lq)), 64, Ak + sn * P2 + lq * 16 + lr, 64);
       t2[sn] = acc[0] + acc[1];
     }
     wave_lds_order();  // every lane's T1 reads precede the T3 writes below
@@ -1421,11 +1501,10 @@ void k_visit4p(VisitArgs v) {
         for (int i = 0; i < 4; ++i) acc[i & 1] = M::run(t2[sn][i], bv[i], acc[i & 1]);
       }
       const Acc c = acc[0] + acc[1];
-      T *dst = Tp + (lr & 3) * 16 + (lr >> 2);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {  // m = (lk, wbk)
-        const int m = M::crow(r, lq);
-        dst[(m & 3) * 64 + (m >> 2) * 4] = c[r];
+      for (int r = 0; r < 4; ++r) {  // m = (lk, wbk), n = lr = (lb, wbb)
+        const int m = M::crow(r, lq), wb = (m & 3) * 4 + (lr & 3), l = (m >> 2) * 4 + (lr >> 2);
+        Tp[wb * 16 + (l ^ v4p_t3_sw(wb))] = c[r];
       }
     }
     wave_lds_order();
@@ -1436,17 +1515,29 @@ void k_visit4p(VisitArgs v) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int idx = u * 64 + lane, wb = idx & 15, l = idx >> 4;
-          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = Tp[wb * 16 + l];
+          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = Tp[wb * 16 + (l ^ v4p_t3_sw(wb))];
         }
       }
     }
     // (e) this pair's contribution to Yt[(ty, l)][yb]: k = wb of column tx
     if (v.do_local) {
+      // A: T3 row wb = 4i + lq, column lr: swizzle 4 (lq >> 1) ^ (8 (i & 1) | 2 (i >> 1));
+      // B: Gs row tx 16 + 4i + lq: swizzle w ^ (lq >> 1) ^ 2i, w from tx
+      const int ta = lq * 16 + (lr ^ ((lq >> 1) << 2));
+      const int w = ((tx & 1) << 3) ^ ((tx << 2) & 15);
+      const int gb = (tx * 16 + lq) * GS + (lr ^ w ^ (lq >> 1));
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         if (q >= tne) break;
+        T av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          av[i] = Tp[(ta ^ (((i & 1) << 3) | ((i >> 1) << 1))) + 64 * i];
+          bv[i] = Gs[(gb ^ (2 * i)) + 4 * i * GS + q * 16];
+        }
         Acc acc[2] = {accE[q], zero};
-        mma_steps<4>(acc, Tp + lq * 16 + lr, 64, Gs + (tx * 16 + lq) * GS + q * 16 + lr, 4 * GS);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i & 1] = M::run(av[i], bv[i], acc[i & 1]);
         accE[q] = acc[0] + acc[1];
       }
     }
@@ -2288,40 +2379,26 @@ static VisitKernel visit4_kernel(int TY, int TX) {
   return k_visit4<1, 1, T>;
 }
 
-// Pair-per-wave visit tiles (TY * TX = 8, K <= 64): the first that fits.
+// Pair-per-wave visit (2 x 2 pairs, K <= 64).
 template <class T>
 static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   if (f.D != 4 || f.d != 2 || f.K > 64) return false;
-  // first choice: two workgroups per CU (160 KiB of LDS); else one
-  const int cand[][2] = {{2, 4}, {4, 2}};
-  for (size_t cap : {(size_t)80 * 1024, (size_t)150 * 1024})
-    for (auto &c : cand) {
-      if (c[0] > f.K) continue;
-      const size_t n = visit4p_lds<T>(f.K, c[0], c[1]) * sizeof(T);
-      if (n <= cap) {
-        *TY = c[0];
-        *TX = c[1];
-        *bytes = n;
-        return true;
-      }
-    }
-  return false;
+  const size_t n = visit4p_lds<T>(f.K, 2, 2) * sizeof(T);
+  if (n > 150 * 1024) return false;
+  *TY = 2;
+  *TX = 2;
+  *bytes = n;
+  return true;
 }
 
 // NE = number of 16-wide local-update tiles the kernel is built for (>= 2).
 static int visit4p_ne(int K) { return std::max(2, ceil16(K) / 16); }
 
-template <class T, int NE>
-static VisitKernel visit4p_kernel_ne(int TY, int TX) {
-  if (TY == 2 && TX == 4) return k_visit4p<2, 4, T, NE>;
-  return k_visit4p<4, 2, T, NE>;
-}
-
 template <class T>
-static VisitKernel visit4p_kernel(int TY, int TX, int NE) {
-  if (NE <= 2) return visit4p_kernel_ne<T, 2>(TY, TX);
-  if (NE == 3) return visit4p_kernel_ne<T, 3>(TY, TX);
-  return visit4p_kernel_ne<T, 4>(TY, TX);
+static VisitKernel visit4p_kernel(int NE) {
+  if (NE <= 2) return k_visit4p<2, 2, T, 2>;
+  if (NE == 3) return k_visit4p<2, 2, T, 3>;
+  return k_visit4p<2, 2, T, 4>;
 }
 
 // FP32 contractions run where both the visit and the environment update have
@@ -2353,14 +2430,12 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) attr_err = e;
       }
-    for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2)})
-      for (int ne = 2; ne <= 4; ++ne)
-        for (VisitKernel kf : {visit4p_kernel<double>(t.first, t.second, ne),
-                               visit4p_kernel<float>(t.first, t.second, ne)}) {
-          hipError_t e = hipFuncSetAttribute(
-              (const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          if (e != hipSuccess) attr_err = e;
-        }
+    for (int ne = 2; ne <= 4; ++ne)
+      for (VisitKernel kf : {visit4p_kernel<double>(ne), visit4p_kernel<float>(ne)}) {
+        hipError_t e = hipFuncSetAttribute(
+            (const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) attr_err = e;
+      }
   });
   if (attr_err != hipSuccess) return attr_err;
   int TY4, TX4;
@@ -2396,9 +2471,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     v.TY = TYp;
     v.TX = TXp;
     const int ne = visit4p_ne(f.K);
-    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(TYp, TXp, ne)
-                           : visit4p_kernel<double>(TYp, TXp, ne),
-                       dim3((f.K + TYp - 1) / TYp, f.items), dim3(kVisitThreads), ldsp, st, v);
+    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(ne) : visit4p_kernel<double>(ne),
+                       dim3((f.K + TYp - 1) / TYp, f.items), dim3(64 * TYp * TXp), ldsp, st, v);
   } else if (spec) {
     v.TY = TY4;
     v.TX = TX4;
@@ -2521,16 +2595,16 @@ hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
     const int mt = (f.K + 15) / 16;
     // FP32 only where the visit wrote FP32 T3 (the specialised D = 4 kernel)
     if (visit_f32(f)) {
-      if (mt <= 1) hipLaunchKernelGGL((k_env<1, float>), grid, dim3(kEnvThreads), 0, st, e);
-      else if (mt <= 2) hipLaunchKernelGGL((k_env<2, float>), grid, dim3(kEnvThreads), 0, st, e);
-      else if (mt <= 3) hipLaunchKernelGGL((k_env<3, float>), grid, dim3(kEnvThreads), 0, st, e);
-      else hipLaunchKernelGGL((k_env<4, float>), grid, dim3(kEnvThreads), 0, st, e);
+      if (mt <= 1) hipLaunchKernelGGL((k_env<1, float>), grid, dim3(EnvShape<1>::kThreads), 0, st, e);
+      else if (mt <= 2) hipLaunchKernelGGL((k_env<2, float>), grid, dim3(EnvShape<2>::kThreads), 0, st, e);
+      else if (mt <= 3) hipLaunchKernelGGL((k_env<3, float>), grid, dim3(EnvShape<3>::kThreads), 0, st, e);
+      else hipLaunchKernelGGL((k_env<4, float>), grid, dim3(EnvShape<4>::kThreads), 0, st, e);
       return hipGetLastError();
     }
-    if (mt <= 1) hipLaunchKernelGGL((k_env<1, double>), grid, dim3(kEnvThreads), 0, st, e);
-    else if (mt <= 2) hipLaunchKernelGGL((k_env<2, double>), grid, dim3(kEnvThreads), 0, st, e);
-    else if (mt <= 3) hipLaunchKernelGGL((k_env<3, double>), grid, dim3(kEnvThreads), 0, st, e);
-    else hipLaunchKernelGGL((k_env<4, double>), grid, dim3(kEnvThreads), 0, st, e);
+    if (mt <= 1) hipLaunchKernelGGL((k_env<1, double>), grid, dim3(EnvShape<1>::kThreads), 0, st, e);
+    else if (mt <= 2) hipLaunchKernelGGL((k_env<2, double>), grid, dim3(EnvShape<2>::kThreads), 0, st, e);
+    else if (mt <= 3) hipLaunchKernelGGL((k_env<3, double>), grid, dim3(EnvShape<3>::kThreads), 0, st, e);
+    else hipLaunchKernelGGL((k_env<4, double>), grid, dim3(EnvShape<4>::kThreads), 0, st, e);
     return hipGetLastError();
   }
   OpK5 k5{f.K, f.K * f.P, f.K * f.P, nullptr, shape_of(f), rl, f.t3,

@@ -1,0 +1,46 @@
+"""Lanes (the "lanes" option): message batches and boundary-stack batches
+split over several streams give bitwise the results of one stream, since
+every item is computed from its own inputs only."""
+
+import numpy as np
+import pytest
+
+from bbp_inputs import op_heis, op_sz, peps_finite
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(lanes, A, Lx, Ly, bx, by, D, chi, sweeps):
+    from paper_2301_05844_amd import bbp
+    ctx = bbp.BlockBP(Lx=Lx, Ly=Ly, bx=bx, by=by, D=D, chi=chi, lanes=lanes)
+    ctx.set_tensors(A)
+    res = [ctx.sweep(1) for _ in range(sweeps)]
+    xs = np.array([x for y in range(Ly) for x in range(Lx)], dtype=np.int32)
+    ys = np.array([y for y in range(Ly) for x in range(Lx)], dtype=np.int32)
+    sz = ctx.expect_sites(xs, ys, op_sz())
+    bonds = [(x, y, x + 1, y) for y in range(Ly) for x in range(Lx - 1)]
+    bonds += [(x, y, x, y + 1) for y in range(Ly - 1) for x in range(Lx)]
+    ss = ctx.expect_bonds(bonds, op_heis())
+    lz = ctx.log_norm()
+    msgs = ctx.get_messages_flat()
+    return np.array(res), sz, ss, np.array(lz), msgs
+
+
+@pytest.mark.parametrize("lanes", [2, 3, 4])
+def test_lanes_bitwise_equal(lanes):
+    # 8x8 lattice, 2x2 blocks: 48 messages of one shape, split into `lanes`
+    # batches; the region stacks split likewise
+    Lx = Ly = 8
+    A = peps_finite(Lx, Ly, 3, seed=5)
+    one = _run(1, A, Lx, Ly, 2, 2, 3, 9, 3)
+    many = _run(lanes, A, Lx, Ly, 2, 2, 3, 9, 3)
+    print(f"lanes {lanes}: residuals {many[0]}", flush=True)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+
+
+def test_lanes_option_validation():
+    from paper_2301_05844_amd import bbp
+    for bad in (0, 5, 1.5):
+        with pytest.raises(bbp.BBPError):
+            bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4, lanes=bad)
