@@ -490,30 +490,49 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   const __amdgpu_buffer_rsrc_t yrs = buf_rsrc(e.Y.at(it), (unsigned)(K * P * K) * 8u);
   const __amdgpu_buffer_rsrc_t trs = buf_rsrc(T3, (unsigned)(Kd * N) * (unsigned)sizeof(T));
   const bool rl = e.rl != 0;
-  T an[NA], bn[8];
-  auto fetch = [&](int k0) {
+  // Y elements of the next chunk: raw loads and a validity mask, applied
+  // when staged in LDS
+  double an[NA];
+  unsigned am = 0;
+  // RL layout: (yf, l) of k = k0 + kk for each staged element, packed as
+  // yf * 256 + l and carried from chunk to chunk (no division in the loop)
+  int yfl[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int kk = (tid + u * NT) / MW;
+    yfl[u] = (kk / P) * 256 + kk % P;
+  }
+  const int dyfl = (CH / P) * 256 + CH % P;
+  auto fetch_a = [&](int k0) {  // chunks in order 0, CH, 2 CH, ...
+    am = 0;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int i = tid + u * NT, kk = i / MW, m = i % MW, k = k0 + kk;
       const bool ok = m < K && k < Kd;
-      const int yf = k / P, l = k - yf * P;
-      const unsigned off = rl ? (m * P + l) * K + yf : k * K + m;
-      const double x = buf_ld(yrs, ok ? off * 8u : 0u);
-      an[u] = (T)(ok ? x : 0.0);
+      const unsigned off = rl ? (m * P + (yfl[u] & 255)) * K + (yfl[u] >> 8) : k * K + m;
+      an[u] = buf_ld(yrs, ok ? off * 8u : 0u);
+      am |= (unsigned)ok << u;
+      yfl[u] += dyfl;
+      if ((yfl[u] & 255) >= P) yfl[u] += 256 - P;
     }
+  };
+  // T3 rows of chunk k0 for this wave's k part: raw loads and a validity
+  // mask, applied when used (two chunks are in flight)
+  auto fetch_b = [&](int k0, T (&b)[8], unsigned &bm) {
+    bm = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + h * 32 + 4 * i + lq;
       const bool ok = n < N && k < Kd;
-      const T x = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : 0u);
-      bn[i] = ok ? x : (T)0;
+      b[i] = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : 0u);
+      bm |= (unsigned)ok << i;
     }
   };
   auto put = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int i = tid + u * NT;
-      As[buf][i / MW][i % MW] = an[u];
+      As[buf][i / MW][i % MW] = (T)(((am >> u) & 1) ? an[u] : 0.0);
     }
   };
   // two accumulation chains per row tile, one where MT tiles already give
@@ -524,24 +543,49 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int q = 0; q < NC; ++q) acc[mt][q] = Acc{0, 0, 0, 0};
-  fetch(0);
+  // T3 rows are fetched DB chunks ahead (two while the registers allow)
+  constexpr int DB = MT <= 2 ? 2 : 1;
+  T b0[8], b1[8];
+  unsigned m0 = 0, m1 = 0;
+  fetch_a(0);
+  fetch_b(0, b0, m0);
+  if (DB == 2 && CH < Kd) fetch_b(CH, b1, m1);
   put(0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < Kd; k0 += CH) {
-    T bc[8];
+  // one chunk: multiply with the staged Y and the given T3 rows, then
+  // refill those rows DB chunks ahead and stage the next Y chunk
+  auto step = [&](int k0, T (&b)[8], unsigned &bm) {
+    if (k0 + CH < Kd) fetch_a(k0 + CH);
+    if constexpr (DB == 1) {  // copy out, then refill the same registers
+      T bc[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) bc[i] = bn[i];
-    if (k0 + CH < Kd) fetch(k0 + CH);
+      for (int i = 0; i < 8; ++i) bc[i] = ((bm >> i) & 1) ? b[i] : (T)0;
+      if (k0 + CH < Kd) fetch_b(k0 + CH, b, bm);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        acc[mt][i % NC] =
-            M::run(As[buf][h * 32 + 4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i % NC]);
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][i % NC] =
+              M::run(As[buf][h * 32 + 4 * i + lq][mt * 16 + lr], bc[i], acc[mt][i % NC]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const T bc = ((bm >> i) & 1) ? b[i] : (T)0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][i % NC] =
+              M::run(As[buf][h * 32 + 4 * i + lq][mt * 16 + lr], bc, acc[mt][i % NC]);
+      }
+      if (k0 + 2 * CH < Kd) fetch_b(k0 + 2 * CH, b, bm);
+    }
     if (k0 + CH < Kd) put(buf ^ 1);
     __syncthreads();
     buf ^= 1;
+  };
+  for (int k0 = 0; k0 < Kd; k0 += DB * CH) {
+    step(k0, b0, m0);
+    if (DB == 2 && k0 + CH < Kd) step(k0 + CH, b1, m1);
   }
   Acc c[MT];
 #pragma unroll
