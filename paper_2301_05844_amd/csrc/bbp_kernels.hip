@@ -177,6 +177,25 @@ template <> __device__ __forceinline__ float buf_ld_t<float>(__amdgpu_buffer_rsr
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  For a (tile, item) grid this returns the tile and item of
+// the calling workgroup such that every tile of item i < 8 floor(items / 8)
+// runs on XCD i % 8 (an item's shared operands stay in one L2); the items
+// beyond follow in plain order.
+__device__ __forceinline__ void xcd_tile_item(int *tile, int *item) {
+  constexpr int kXcds = 8;
+  const int nx = gridDim.x, ny = gridDim.y, ny8 = ny - ny % kXcds;
+  const int w = blockIdx.x + nx * blockIdx.y;
+  if (w >= nx * ny8) {
+    *item = ny8 + (w - nx * ny8) / nx;
+    *tile = (w - nx * ny8) % nx;
+    return;
+  }
+  const int xcd = w % kXcds, slot = w / kXcds;
+  *item = (slot / nx) * kXcds + xcd;
+  *tile = slot % nx;
+}
+
 // Orders one wave's LDS writes before its later LDS reads (other lanes).
 __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -480,9 +499,11 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   constexpr int NA = CH * MW / NT;  // A elements staged per thread
   __shared__ T As[2][CH][AS];
   const int K = e.K, P = e.P, N = K * P, Kd = K * P;
-  const int it = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tile, it;
+  xcd_tile_item(&tile, &it);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4, cg = wave & 3, h = wave >> 2;
-  const int n = blockIdx.x * 64 + cg * 16 + lr;
+  const int n = tile * 64 + cg * 16 + lr;
   // Y (K P K doubles) and this item's T3 (K P x K P) through buffer
   // descriptors; an element outside the operand loads offset 0 and is
   // replaced by zero
@@ -1381,7 +1402,9 @@ void k_visit4p(VisitArgs v) {
   constexpr bool f64 = sizeof(T) == 8;
   const int K = v.K, K4 = ceil4(K), FS = M::pad_a_min(K4), GS = M::pad_b(K), KY = ceil16(K);
   const int XT = v4p_xt(K4, TX);
-  const int it = blockIdx.y, y0 = blockIdx.x * TY;
+  int tile, it;
+  xcd_tile_item(&tile, &it);
+  const int y0 = tile * TY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   T *Fs = sm;
@@ -1416,7 +1439,7 @@ void k_visit4p(VisitArgs v) {
   for (int q = 0; q < NE; ++q) accE[q] = zero;
 
   // X and G of the next xb step are fetched into registers while the
-  // current step computes.  Thread element u is i = tid + 512 u of the tile
+  // current step computes.  Thread element u is i = tid + NT u of the tile
   // [xf][a][tx] (rl: [tx][a][xf]) and [yb][wb][tx], each index taken over
   // the compile-time extent XF = 16 NE >= K4; the decode is recomputed where
   // needed rather than held in registers.
