@@ -64,7 +64,10 @@ struct DevBuf {
     bytes = 0;
     acct = nullptr;
   }
+  // (Re)allocates b bytes; an existing allocation of exactly b bytes is kept
+  // (its contents are not cleared).
   hipError_t alloc(size_t b) {
+    if (p && b == bytes && acct == tl_acct) return hipSuccess;
     release();
     if (b == 0) return hipSuccess;
     hipError_t e = hipMalloc(&p, b);
@@ -441,12 +444,18 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
       {&f.rbuf, fit ? it * K * K : 0, false},
       {&f.nu, fit ? it * f.W : 0, true},
   };
-  g.bufs.clear();
-  g.bufs.resize(reqs.size() + 4);
+  // a batch set up again with the same shapes keeps its allocations
+  if (g.bufs.size() != reqs.size() + 4) {
+    g.bufs.clear();
+    g.bufs.resize(reqs.size() + 4);
+  }
   hipError_t e;
   for (size_t i = 0; i < reqs.size(); ++i) {
     *reqs[i].dst = nullptr;
-    if (reqs[i].n == 0) continue;
+    if (reqs[i].n == 0) {
+      g.bufs[i].release();
+      continue;
+    }
     e = g.bufs[i].alloc(reqs[i].n * 8);
     if (e != hipSuccess) return c->fail(BBP_ENOMEM, "device allocation failed");
     *reqs[i].dst = g.bufs[i].d();
@@ -1180,6 +1189,26 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     const int CH = 256;
     std::vector<double *> out_ptr[2];
     DevBuf outbuf[2];
+    // chunk buffers, allocated once for the largest chunk and reused (stream
+    // order keeps a chunk's uploads behind the previous chunk's kernels); the
+    // host staging of every chunk lives until the stream is synchronised
+    const size_t chmax = std::min<size_t>(CH, std::max(units[0].size(), units[1].size()));
+    Group ug;
+    ug.W = 1;
+    ug.H = 1;
+    DevBuf kets, bras, tabs, ujobs;
+    std::vector<std::vector<CopyJob>> uj_keep;
+    std::vector<std::vector<double *>> tab_keep;
+    if (chmax > 0) {
+      bbp_status bs2 = alloc_batch(c, ug, (int)chmax, Kenv, std::vector<uint64_t>(chmax, 0),
+                                   NEED_SCRATCH);
+      if (bs2 != BBP_OK) return bs2;
+      if (kets.alloc(chmax * asite * 8) != hipSuccess ||
+          bras.alloc(chmax * asite * 8) != hipSuccess ||
+          tabs.alloc(chmax * 3 * sizeof(double *)) != hipSuccess ||
+          ujobs.alloc(sizeof(CopyJob) * 2 * chmax) != hipSuccess)
+        return c->fail(BBP_ENOMEM, "device allocation failed");
+    }
     for (int dir = 0; dir < 2; ++dir) {
       const std::vector<UnitItem> &U = units[dir];
       if (U.empty()) continue;
@@ -1190,21 +1219,13 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         out_ptr[dir][i] = outbuf[dir].d() + i * f.S;
       for (size_t o = 0; o < U.size(); o += CH) {
         const int n = (int)std::min<size_t>(CH, U.size() - o);
-        Group ug;
-        ug.W = 1;
-        ug.H = 1;
-        bbp_status bs2 = alloc_batch(c, ug, n, Kenv, std::vector<uint64_t>(n, 0),
-                                     NEED_SCRATCH);
-        if (bs2 != BBP_OK) return bs2;
         FitBatch &fu = ug.fb;
-        DevBuf kets, bras, tabs;
-        if (kets.alloc((size_t)n * asite * 8) != hipSuccess ||
-            bras.alloc((size_t)n * asite * 8) != hipSuccess ||
-            tabs.alloc((size_t)n * 3 * sizeof(double *)) != hipSuccess)
-          return c->fail(BBP_ENOMEM, "device allocation failed");
-        e = hipMemsetAsync(kets.p, 0, kets.bytes, st);
-        std::vector<CopyJob> uj;
-        std::vector<double *> tab(3 * (size_t)n);
+        fu.items = n;
+        e = hipMemsetAsync(kets.p, 0, (size_t)n * asite * 8, st);
+        uj_keep.emplace_back();
+        tab_keep.emplace_back(3 * (size_t)n);
+        std::vector<CopyJob> &uj = uj_keep.back();
+        std::vector<double *> &tab = tab_keep.back();
         const size_t slice = asite / d;
         for (int i = 0; i < n; ++i) {
           const UnitItem &ui = U[o + i];
@@ -1218,15 +1239,12 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
           tab[n + i] = (dir == 0 ? f.lenv : f.renv) + ((size_t)ui.line * N + ui.j) * f.S;
           tab[2 * n + i] = f.store + ((size_t)ui.line * N + ui.j) * f.S;
         }
-        DevBuf ujobs;
-        if (ujobs.alloc(sizeof(CopyJob) * uj.size()) != hipSuccess)
-          return c->fail(BBP_ENOMEM, "device allocation failed");
         if (e == hipSuccess)
-          e = copy_sync(c, ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
-                        hipMemcpyHostToDevice);
+          e = hipMemcpyAsync(ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
+                             hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
-          e = copy_sync(c, tabs.p, tab.data(), tab.size() * sizeof(double *),
-                        hipMemcpyHostToDevice);
+          e = hipMemcpyAsync(tabs.p, tab.data(), tab.size() * sizeof(double *),
+                             hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
           e = launch_copy_jobs((const CopyJob *)ujobs.p, (int)uj.size(), Kenv, P, st);
         if (e != hipSuccess) return c->hip_fail(e, "unit setup");
@@ -1238,10 +1256,10 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         if (e == hipSuccess)
           e = launch_inner_env(fu, dir == 1, Y, Ptr{outbuf[dir].d() + o * f.S, f.S},
                                st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return c->hip_fail(e, "unit steps");
       }
     }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return c->hip_fail(e, "unit steps");
     // ---- 4. contractions: line values, site and bond density matrices -----
     std::vector<const double *> pa, pb;
     struct Tag {
@@ -1658,33 +1676,39 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       return c->fail(BBP_EDEVICE, "upload trivial message");
   }
   c->cur = 0;
-  // groups by canonical (W, H)
-  c->groups.clear();
-  std::map<std::pair<int, int>, int> gid;
-  for (size_t i = 0; i < c->msgs.size(); ++i) {
-    const Message &m = c->msgs[i];
-    int W = (m.dir == 'L' || m.dir == 'R') ? c->bx : c->by;
-    int H = (m.dir == 'L' || m.dir == 'R') ? c->by : c->bx;
-    auto key = std::make_pair(W, H);
-    if (!gid.count(key)) {
-      gid[key] = (int)c->groups.size();
-      c->groups.emplace_back(new Group);
-      c->groups.back()->W = W;
-      c->groups.back()->H = H;
-    }
-    c->groups[gid[key]]->ids.push_back((int)i);
-  }
-  {  // large batches split so that the lanes can overlap them
-    std::vector<std::unique_ptr<Group>> split;
-    for (auto &g : c->groups)
-      for (auto &part : split_batch(g->ids, c->lanes, kLaneMinItems)) {
-        split.emplace_back(new Group);
-        split.back()->W = g->W;
-        split.back()->H = g->H;
-        split.back()->ids = part;
+  // groups by canonical (W, H), large ones split so that the lanes can
+  // overlap them; the groups of an earlier call are kept (with their device
+  // buffers) when the partition is the same
+  std::vector<std::unique_ptr<Group>> groups;
+  {
+    std::map<std::pair<int, int>, int> gid;
+    std::vector<std::unique_ptr<Group>> byshape;
+    for (size_t i = 0; i < c->msgs.size(); ++i) {
+      const Message &m = c->msgs[i];
+      int W = (m.dir == 'L' || m.dir == 'R') ? c->bx : c->by;
+      int H = (m.dir == 'L' || m.dir == 'R') ? c->by : c->bx;
+      auto key = std::make_pair(W, H);
+      if (!gid.count(key)) {
+        gid[key] = (int)byshape.size();
+        byshape.emplace_back(new Group);
+        byshape.back()->W = W;
+        byshape.back()->H = H;
       }
-    c->groups.swap(split);
+      byshape[gid[key]]->ids.push_back((int)i);
+    }
+    for (auto &g : byshape)
+      for (auto &part : split_batch(g->ids, c->lanes, kLaneMinItems)) {
+        groups.emplace_back(new Group);
+        groups.back()->W = g->W;
+        groups.back()->H = g->H;
+        groups.back()->ids = part;
+      }
   }
+  bool same = groups.size() == c->groups.size();
+  for (size_t i = 0; same && i < groups.size(); ++i)
+    same = groups[i]->W == c->groups[i]->W && groups[i]->H == c->groups[i]->H &&
+           groups[i]->ids == c->groups[i]->ids;
+  if (!same) c->groups.swap(groups);
   for (auto &g : c->groups) {
     // random-state slot bases: message e, column c -> (1<<40)|(e<<8)|c
     std::vector<uint64_t> slots(g->ids.size());
