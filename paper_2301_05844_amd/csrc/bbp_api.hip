@@ -54,6 +54,26 @@ struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
   MemAcct *acct = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.acct = nullptr;
+  }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      acct = o.acct;
+      o.p = nullptr;
+      o.bytes = 0;
+      o.acct = nullptr;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) {
@@ -153,6 +173,10 @@ struct bbp_ctx {
   DevBuf msgbuf[2], trivial, ovE, ovU, ovOut, ovA, ovB, errflag;
   int cur = 0;
   std::vector<std::unique_ptr<Group>> groups;
+  // observables' boundary-stack, line and unit-output buffers of earlier
+  // calls, kept for the next call with the same shapes
+  std::vector<std::unique_ptr<Group>> batch_cache;
+  std::vector<DevBuf> unit_out_cache;
   double last_flops = 0.0;
   std::map<std::tuple<int, int, int>, RegionResult> obs;  // (kind, bi, bj)
 
@@ -380,6 +404,43 @@ static std::vector<std::vector<int>> split_batch(const std::vector<int> &ids, in
   return out;
 }
 constexpr int kLaneMinItems = 8;
+
+// A batch of the given shape from the context's cache (the one set up last
+// time for the same W, H and item count keeps its device buffers), else new.
+static std::unique_ptr<Group> take_batch(bbp_ctx *c, int W, int H, int items) {
+  for (auto it = c->batch_cache.begin(); it != c->batch_cache.end(); ++it)
+    if ((*it)->W == W && (*it)->H == H && (*it)->fb.items == items) {
+      std::unique_ptr<Group> g = std::move(*it);
+      c->batch_cache.erase(it);
+      g->ids.clear();
+      return g;
+    }
+  std::unique_ptr<Group> g(new Group);
+  g->W = W;
+  g->H = H;
+  return g;
+}
+// Returns batches to the cache when the call that used them ends (also on an
+// early error return).
+struct BatchReturn {
+  bbp_ctx *c;
+  std::vector<std::unique_ptr<Group>> *v;
+  ~BatchReturn() {
+    for (auto &g : *v)
+      if (g) c->batch_cache.push_back(std::move(g));
+    v->clear();
+  }
+};
+// A device buffer of exactly `bytes` from the context's cache, else new.
+static DevBuf take_unit_out(bbp_ctx *c, size_t bytes) {
+  for (auto it = c->unit_out_cache.begin(); it != c->unit_out_cache.end(); ++it)
+    if (it->bytes == bytes) {
+      DevBuf b = std::move(*it);
+      c->unit_out_cache.erase(it);
+      return b;
+    }
+  return DevBuf();
+}
 
 // ---------------------------------------------------------------------------
 static bbp_status ensure_device(bbp_ctx *c) {
@@ -952,15 +1013,15 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   for (auto &kv : sgroups)
     for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) batches.push_back(part);
   std::vector<std::unique_ptr<Group>> sg;
+  BatchReturn sg_return{c, &sg};
   std::vector<std::pair<int, int>> where(stacks.size());  // (group, item)
   std::vector<std::vector<double>> nus;
   // allocate and stage every batch first: allocation waits on the context
   // stream, which must not yet hold absorption work
   for (const std::vector<int> &ids : batches) {
-    std::unique_ptr<Group> gp(new Group);
+    std::unique_ptr<Group> gp =
+        take_batch(c, stacks[ids[0]].Wc, stacks[ids[0]].Hc, (int)ids.size());
     Group &g = *gp;
-    g.W = stacks[ids[0]].Wc;
-    g.H = stacks[ids[0]].Hc;
     std::vector<uint64_t> slots(ids.size());
     for (size_t i = 0; i < ids.size(); ++i) {
       const StackItem &it = stacks[ids[i]];
@@ -1084,12 +1145,13 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   // unit results: (line, j, u) -> LR step value maps keyed in host tables
   std::map<std::tuple<int, int, int>, double> site_rho;        // (line,j,u)
   std::map<std::tuple<int, int, int, int>, double> bond_rho;   // (line,j,u,v)
+  std::vector<std::unique_ptr<Group>> lgs;
+  BatchReturn lg_return{c, &lgs};
   for (auto &kv : lgroups) {
     const int Hc = kv.first;
     const std::vector<int> &lids = kv.second;
-    Group lg;
-    lg.W = 1;
-    lg.H = Hc;
+    lgs.push_back(take_batch(c, 1, Hc, (int)lids.size()));
+    Group &lg = *lgs.back();
     std::vector<uint64_t> slots(lids.size(), 0);
     bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots);
     if (bs != BBP_OK) return bs;
@@ -1189,6 +1251,15 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     const int CH = 256;
     std::vector<double *> out_ptr[2];
     DevBuf outbuf[2];
+    struct OutReturn {  // unit outputs back to the context's cache
+      bbp_ctx *c;
+      DevBuf *b;
+      ~OutReturn() {
+        for (int i = 0; i < 2; ++i)
+          if (b[i].p) c->unit_out_cache.push_back(std::move(b[i]));
+        while (c->unit_out_cache.size() > 8) c->unit_out_cache.erase(c->unit_out_cache.begin());
+      }
+    } out_return{c, outbuf};
     // chunk buffers, allocated once for the largest chunk and reused (stream
     // order keeps a chunk's uploads behind the previous chunk's kernels); the
     // host staging of every chunk lives until the stream is synchronised
@@ -1212,6 +1283,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     for (int dir = 0; dir < 2; ++dir) {
       const std::vector<UnitItem> &U = units[dir];
       if (U.empty()) continue;
+      outbuf[dir] = take_unit_out(c, U.size() * f.S * 8);
       if (outbuf[dir].alloc(U.size() * f.S * 8) != hipSuccess)
         return c->fail(BBP_ENOMEM, "device allocation failed");
       out_ptr[dir].resize(U.size());
