@@ -678,10 +678,10 @@ struct OpE2 {
     return t3[(size_t)it * t3s + (size_t)m * Kd + k];
   }
   __device__ double b(int it, int k, int n) const {
-    return G.at(it)[(size_t)n * Kd + k];
+    return gmem((const double *)G.at(it))[(size_t)n * Kd + k];
   }
   __device__ void st(int it, int m, int n, double v) const {
-    Ye.at(it)[rl ? (size_t)n * s.K + m : (size_t)m * s.K + n] = v;
+    gmem(Ye.at(it))[rl ? (size_t)n * s.K + m : (size_t)m * s.K + n] = v;
   }
 };
 
@@ -2694,7 +2694,7 @@ hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
           G, Ye};
   const double it = f.items, K = f.K, P = f.P;
   Span sp(KC_END, st, it * 2 * K * K * P * K, it * 8 * (2 * K * P * K + K * K));
-  return run_gemm<32, 32, 16>(e2, f.items, st);
+  return run_gemm<32, 32, 64>(e2, f.items, st);  // one 32x32 tile, K P long
 }
 
 hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
@@ -2802,7 +2802,7 @@ hipError_t launch_overlap(int items, int K, int P, int L,
     hipError_t e = run_gemm<32, 64, 16>(o1, items, st);
     if (e != hipSuccess) return e;
     OpOv2 o2{K, K, K * P, nullptr, K, P, U, S, b, (size_t)i * S, E};
-    e = run_gemm<32, 32, 16>(o2, items, st);
+    e = run_gemm<32, 32, 64>(o2, items, st);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ov_out, dim3((items + 63) / 64), dim3(64), 0, st, E, K,
