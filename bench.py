@@ -293,10 +293,24 @@ def cpu_baseline(cfg, A):
     bp.sweep()
     dt = time.perf_counter() - t0
     n = len(bp.order)
-    return dict(value=n / dt, unit="message updates/s", cores=threads,
-                kind="oracle",
-                sample=f"second sweep of the same solve ({n} message updates, "
-                       f"bonds at chi), {dt:.1f} s")
+    out = dict(value=n / dt, unit="message updates/s", cores=threads,
+               kind="oracle",
+               sample=f"second sweep of the same solve ({n} message updates, "
+                      f"bonds at chi), {dt:.1f} s")
+    try:  # the same updates on one thread: the first 12 messages of a third sweep
+        from threadpoolctl import threadpool_limits
+        n1 = 12
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for e, key in enumerate(bp.order[:n1]):
+                bp.update_message(e, key, bp.msgs)
+            d1 = time.perf_counter() - t0
+        out["one_thread"] = dict(value=n1 / d1, unit="message updates/s", cores=1,
+                                 sample=f"first {n1} message updates of a third sweep, "
+                                        f"{d1:.1f} s")
+    except ImportError:
+        pass
+    return out
 
 
 def main():

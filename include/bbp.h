@@ -102,6 +102,19 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double value);
  * its own, forked from and joined back into this one inside each call. */
 bbp_status bbp_set_stream(bbp_ctx *c, void *hip_stream);
 
+/* Device memory through the caller's allocator instead of hipMalloc/hipFree
+ * (for example PyTorch's caching allocator, which then accounts for it).
+ * alloc(bytes, user) returns a device pointer, or NULL on failure (the call
+ * that needed it then returns BBP_ENOMEM); free_(ptr, user) takes back a
+ * pointer alloc returned.  The library synchronises its stream before it
+ * hands memory back, so a stream-ordered allocator may reuse it at once.
+ * Both functions or neither (NULL, NULL: hipMalloc/hipFree); user is passed
+ * through.  Must be called before bbp_set_tensors (BBP_ESTATE afterwards);
+ * both functions must stay callable until bbp_destroy returns. */
+typedef void *(*bbp_alloc_fn)(size_t bytes, void *user);
+typedef void (*bbp_free_fn)(void *ptr, void *user);
+bbp_status bbp_set_allocator(bbp_ctx *c, bbp_alloc_fn alloc, bbp_free_fn free_, void *user);
+
 /*
  * Upload the site tensors (host FP64, layout above; n = number of doubles =
  * nsites*d*D^4 with nsites = Lx*Ly or ucx*ucy), form the per-message rotated

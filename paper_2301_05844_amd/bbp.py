@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbbp.so")
 
 EXPORTS = (
-    "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_tensors",
+    "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_allocator",
+    "bbp_set_tensors",
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
     "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
     "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
@@ -34,6 +35,10 @@ EXPORTS = (
 )
 
 OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
+
+# bbp_alloc_fn / bbp_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
@@ -68,6 +73,7 @@ def _load():
         "bbp_create": [ctypes.POINTER(P)] + [c_int] * 9,
         "bbp_set_option": [P, ctypes.c_char_p, c_double],
         "bbp_set_stream": [P, P],
+        "bbp_set_allocator": [P, ALLOC_FN, FREE_FN, P],
         "bbp_set_tensors": [P, dp, c_size],
         "bbp_sweep": [P, c_int, dp],
         "bbp_expect_site": [P, c_int, c_int, dp, dp],
@@ -128,8 +134,9 @@ class BlockBP:
     ``bbp_set_option`` before the tensors."""
 
     def __init__(self, D, chi, bx, by, Lx=0, Ly=0, infinite=False, ucx=0,
-                 ucy=0, stream=None, **options):
+                 ucy=0, stream=None, allocator=None, **options):
         self._ctx = ctypes.c_void_p()
+        self._alloc_cb = None
         st = _lib.bbp_create(ctypes.byref(self._ctx), int(bool(infinite)),
                              Lx, Ly, ucx, ucy, bx, by, D, chi)
         if st != 0:
@@ -139,6 +146,8 @@ class BlockBP:
             self._check(_lib.bbp_set_option(self._ctx, k.encode(), float(v)))
         if stream is not None:
             self.set_stream(stream)
+        if allocator is not None:
+            self.set_allocator(*allocator)
 
     def _check(self, st):
         if st != 0:
@@ -148,6 +157,25 @@ class BlockBP:
         """``stream``: a torch.cuda.Stream, an integer handle, or None."""
         handle = getattr(stream, "cuda_stream", stream)
         self._check(_lib.bbp_set_stream(self._ctx, ctypes.c_void_p(handle)))
+
+    def set_allocator(self, alloc, free):
+        """Device memory through ``alloc(nbytes) -> int`` (0 on failure) and
+        ``free(ptr)`` (bbp_set_allocator); ``None, None`` restores
+        hipMalloc/hipFree.  Before ``set_tensors``."""
+        if alloc is None and free is None:
+            cbs = (ALLOC_FN(), FREE_FN())
+        else:
+            def _a(nbytes, _user):
+                try:
+                    return int(alloc(int(nbytes))) or None
+                except Exception:  # reported to the library as out of memory
+                    return None
+
+            def _f(ptr, _user):
+                free(int(ptr))
+            cbs = (ALLOC_FN(_a), FREE_FN(_f))
+        self._check(_lib.bbp_set_allocator(self._ctx, cbs[0], cbs[1], None))
+        self._alloc_cb = cbs  # kept alive while the context may call them
 
     def set_option(self, key, value):
         self._check(_lib.bbp_set_option(self._ctx, key.encode(), float(value)))
@@ -299,6 +327,21 @@ def estimate_bytes(**req):
     if st != 0:
         raise BBPError(st, "malformed request")
     return n.value
+
+
+def torch_allocator(device=None):
+    """(alloc, free) over PyTorch's caching allocator, for
+    ``BlockBP(allocator=...)``: the context's device memory then shows in
+    torch.cuda.memory_allocated and is reused by torch after the context
+    frees it."""
+    import torch as _torch
+
+    def alloc(nbytes):
+        return _torch.cuda.caching_allocator_alloc(nbytes, device=device)
+
+    def free(ptr):
+        _torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
 
 
 class Server:

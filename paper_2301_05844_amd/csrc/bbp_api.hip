@@ -39,9 +39,16 @@ void rot_perm(char d, int perm[5]) {
 bool out_reversed(char d) { return d == 'R' || d == 'U'; }
 
 // Device bytes a context holds now and at most (every API entry that may
-// allocate names its context's account for the calling thread).
+// allocate names its context's account for the calling thread), and the
+// allocator the context's device memory comes from (hipMalloc/hipFree unless
+// the caller supplied one; its memory is handed back only after the
+// context's stream has drained).
 struct MemAcct {
   size_t now = 0, peak = 0;
+  bbp_alloc_fn alloc_fn = nullptr;
+  bbp_free_fn free_fn = nullptr;
+  void *user = nullptr;
+  const hipStream_t *stream = nullptr;
 };
 thread_local MemAcct *tl_acct = nullptr;
 struct AcctScope {
@@ -77,7 +84,12 @@ struct DevBuf {
   ~DevBuf() { release(); }
   void release() {
     if (p) {
-      (void)hipFree(p);
+      if (acct && acct->free_fn) {
+        if (acct->stream) (void)hipStreamSynchronize(*acct->stream);
+        acct->free_fn(p, acct->user);
+      } else {
+        (void)hipFree(p);
+      }
       if (acct) acct->now -= bytes;
     }
     p = nullptr;
@@ -90,7 +102,13 @@ struct DevBuf {
     if (p && b == bytes && acct == tl_acct) return hipSuccess;
     release();
     if (b == 0) return hipSuccess;
-    hipError_t e = hipMalloc(&p, b);
+    hipError_t e;
+    if (tl_acct && tl_acct->alloc_fn) {
+      p = tl_acct->alloc_fn(b, tl_acct->user);
+      e = p ? hipSuccess : hipErrorOutOfMemory;
+    } else {
+      e = hipMalloc(&p, b);
+    }
     if (e != hipSuccess) {
       p = nullptr;
       return e;
@@ -1686,6 +1704,19 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
 bbp_status bbp_set_stream(bbp_ctx *c, void *s) {
   if (!c) return BBP_EINVAL;
   c->stream = (hipStream_t)s;
+  return BBP_OK;
+}
+
+bbp_status bbp_set_allocator(bbp_ctx *c, bbp_alloc_fn alloc, bbp_free_fn free_, void *user) {
+  if (!c) return BBP_EINVAL;
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return c->fail(BBP_EINVAL, "allocator needs both functions, or neither");
+  if (c->device_ready)
+    return c->fail(BBP_ESTATE, "allocator must be set before bbp_set_tensors");
+  c->mem.alloc_fn = alloc;
+  c->mem.free_fn = free_;
+  c->mem.user = user;
+  c->mem.stream = &c->stream;
   return BBP_OK;
 }
 

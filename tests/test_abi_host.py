@@ -84,6 +84,20 @@ def test_options_and_state_checks():
     assert e.value.status == 4
 
 
+def test_allocator_validation():
+    bbp = _bbp()
+    g = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
+    lib = bbp.lib()
+    # one function without the other
+    assert lib.bbp_set_allocator(g._ctx, bbp.ALLOC_FN(lambda n, u: None), bbp.FREE_FN(),
+                                 None) == 1
+    assert lib.bbp_set_allocator(None, bbp.ALLOC_FN(), bbp.FREE_FN(), None) == 1
+    calls = []
+    g.set_allocator(lambda n: calls.append(n) or 0, lambda p: None)
+    g.set_allocator(None, None)   # back to hipMalloc / hipFree
+    assert calls == []             # nothing allocates before the tensors
+
+
 def test_set_tensors_validates_before_device():
     bbp = _bbp()
     g = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
