@@ -1378,9 +1378,10 @@ __host__ __device__ inline size_t visit4p_lds(int K, int TY, int TX) {
 }
 
 // One wave per (yf, xb) pair of a TY x TX tile: NT threads.  LD elements of
-// each of the X and G tiles (16 NE x 16 x TX) per thread and step.  At
-// NE = 2 (K <= 32) three workgroups of 2 x 2 share a CU (LDS <= 47 KB), so
-// the registers are held to 3 waves per SIMD; above, to 2.
+// each of the X and G tiles (16 NE x 16 x TX) per thread and step.  Up to
+// NE = 3 (K <= 48) three workgroups share a CU (2 x 2 pairs at NE = 2, LDS
+// <= 47 KB; 4 x 1 at NE = 3, LDS <= 52 KB), so the registers are held to 3
+// waves per SIMD; at NE = 4 to 2.
 template <int TY, int TX, int NE>
 struct Visit4pShape {
   static constexpr int NWV = TY * TX, NT = 64 * NWV;
@@ -1389,7 +1390,7 @@ struct Visit4pShape {
 
 template <int TY, int TX, class T, int NE>
 __global__ __launch_bounds__(64 * TY * TX)
-__attribute__((amdgpu_waves_per_eu(NE <= 2 ? 3 : 2)))
+__attribute__((amdgpu_waves_per_eu(NE <= 3 ? 3 : 2)))
 void k_visit4p(VisitArgs v) {
   constexpr int NT = Visit4pShape<TY, TX, NE>::NT, NWV = Visit4pShape<TY, TX, NE>::NWV;
   extern __shared__ double sm_raw[];
@@ -2446,25 +2447,28 @@ static VisitKernel visit4_kernel(int TY, int TX) {
   return k_visit4<1, 1, T>;
 }
 
-// Pair-per-wave visit (2 x 2 pairs, K <= 64).
+// NE = number of 16-wide local-update tiles the kernel is built for (>= 2).
+static int visit4p_ne(int K) { return std::max(2, ceil16(K) / 16); }
+
+// Pair-per-wave visit (K <= 64): 2 x 2 pairs, 4 x 1 at NE = 3.
 template <class T>
 static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   if (f.D != 4 || f.d != 2 || f.K > 64) return false;
-  const size_t n = visit4p_lds<T>(f.K, 2, 2) * sizeof(T);
+  const bool ne3 = visit4p_ne(f.K) == 3;
+  const int ty = ne3 ? 4 : 2, tx = ne3 ? 1 : 2;
+  const size_t n = visit4p_lds<T>(f.K, ty, tx) * sizeof(T);
   if (n > 150 * 1024) return false;
-  *TY = 2;
-  *TX = 2;
+  *TY = ty;
+  *TX = tx;
   *bytes = n;
   return true;
 }
 
-// NE = number of 16-wide local-update tiles the kernel is built for (>= 2).
-static int visit4p_ne(int K) { return std::max(2, ceil16(K) / 16); }
 
 template <class T>
 static VisitKernel visit4p_kernel(int NE) {
   if (NE <= 2) return k_visit4p<2, 2, T, 2>;
-  if (NE == 3) return k_visit4p<2, 2, T, 3>;
+  if (NE == 3) return k_visit4p<4, 1, T, 3>;
   return k_visit4p<2, 2, T, 4>;
 }
 
