@@ -115,6 +115,10 @@ CONFIGS = {
     # infinite lattice, 2x2 unit cell, D=4, 4x4 block, chi=32
     "inf2x2_D4_b4_chi32": dict(infinite=True, ucx=2, ucy=2, bx=4, by=4, D=4,
                                chi=32, tol=1e-10),
+    # 8x8 open lattice, D=4, 4x4 blocks, chi=56, chi_env=64, 2 sweeps (bond caps
+    # 49..64 in the fits)
+    "obc8x8_D4_b4_chi56": dict(infinite=False, Lx=8, Ly=8, bx=4, by=4, D=4, chi=56,
+                               chi_env=64, sweeps=2),
     # 6x6 open lattice, D=6, 3x3 blocks, chi=6, chi_env=16, 2 sweeps (D=6 parity)
     "obc6x6_D6_b3_chi6": dict(infinite=False, Lx=6, Ly=6, bx=3, by=3, D=6, chi=6,
                               chi_env=16, sweeps=2),
