@@ -119,6 +119,10 @@ CONFIGS = {
     # 49..64 in the fits)
     "obc8x8_D4_b4_chi56": dict(infinite=False, Lx=8, Ly=8, bx=4, by=4, D=4, chi=56,
                                chi_env=64, sweeps=2),
+    # 4x4 open lattice as one D=4 block, chi_env=80: the observables' fits at a
+    # bond cap above 64
+    "obc4x4_D4_b4_env80": dict(infinite=False, Lx=4, Ly=4, bx=4, by=4, D=4, chi=16,
+                               chi_env=80, sweeps=1),
     # 6x6 open lattice, D=6, 3x3 blocks, chi=6, chi_env=16, 2 sweeps (D=6 parity)
     "obc6x6_D6_b3_chi6": dict(infinite=False, Lx=6, Ly=6, bx=3, by=3, D=6, chi=6,
                               chi_env=16, sweeps=2),

@@ -10,6 +10,7 @@ and the log-norm.
     python tests/golden/make_golden.py inf2x2_D4_b4_chi32
     python tests/golden/make_golden.py obc6x6_D6_b3_chi6 3
     python tests/golden/make_golden.py obc8x8_D4_b4_chi56 4
+    python tests/golden/make_golden.py obc4x4_D4_b4_env80 5
 """
 
 import json

@@ -12,6 +12,9 @@ step rather than a fixed point both sides fall into; same tolerances.
 
 8x8 open lattice, D=4, 4x4 blocks, chi=56, chi_env=64 (seed 4): two sweeps,
 the fits at bond caps 49..64 (the visit's widest pair-per-wave variant).
+
+4x4 open lattice as one D=4 block, chi_env=80 (seed 5): the observables'
+boundary fits at a bond cap above 64 (the tiled D=4 visit).
 """
 
 import json
@@ -121,6 +124,28 @@ def test_obc8x8_D4_chi56_matches_oracle():
     ctx.set_tensors(A)
     res = [ctx.sweep(1) for _ in range(g["sweeps"])]
     _check_residuals(res, g["residuals"])
+    sites = np.array(g["sites"], dtype=np.int32)
+    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+    err_sz = np.abs(sz - np.array(g["sz"])).max()
+    ss = ctx.expect_bonds(g["bonds"], op_heis())
+    err_ss = np.abs(ss - np.array(g["ss"])).max()
+    lz, sign = ctx.log_norm()
+    print(f"max |d sz| {err_sz:.2e}  max |d SS| {err_ss:.2e}  "
+          f"log-norm {lz:.12f} vs {g['log_norm']:.12f}", flush=True)
+    assert err_sz < TOL and err_ss < TOL
+    assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
+    assert sign == g["log_norm_sign"]
+
+
+def test_obc4x4_D4_env80_matches_oracle():
+    from paper_2301_05844_amd import bbp
+    g = _golden("obc4x4_D4_b4_env80", seed=5)
+    cfg = CONFIGS["obc4x4_D4_b4_env80"]
+    A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=g["seed"])
+    ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
+                      D=cfg["D"], chi=cfg["chi"], chi_env=g["chi_env"])
+    ctx.set_tensors(A)
+    ctx.sweep(g["sweeps"])
     sites = np.array(g["sites"], dtype=np.int32)
     sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
     err_sz = np.abs(sz - np.array(g["sz"])).max()
