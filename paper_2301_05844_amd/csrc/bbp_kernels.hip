@@ -1337,9 +1337,9 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
 }
 
 // ---------------------------------------------------------------------------
-// The same visit with one (yf, xb) pair per wave (TY * TX == 8 waves): each
-// wave runs T1 -> ket -> bra -> T3 store -> its local-update contribution for
-// its own pair with wave-level LDS ordering only, so an xb step needs just the
+// The same visit with one (yf, xb) pair per wave (TY * TX waves): each wave
+// runs T1 -> ket -> bra -> T3 store -> its local-update contribution for its
+// own pair with wave-level LDS ordering only, so an xb step needs just the
 // two barriers around the X/G refill.  The local-update partials of the TX
 // waves that share yf are summed at the end in a fixed order.
 //
@@ -1351,9 +1351,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
 // region per pair (T1 is consumed by the ket before the bra writes T3).
 //
 // NE = ceil(K / 16) bounds the local-update tiles; each thread moves LD
-// elements of the X and G tiles per step.  Up to NE = 3 the kernel is held to
-// 128 VGPRs so that two workgroups (4 waves per SIMD) share a CU when the LDS
-// allows it.
+// elements of the X and G tiles per step.
 // LDS: Fs [(ty, wf)][xf] (row stride pad_a_min(K4)); Xs [tx][xf][a] (rows
 // of 16, tile stride 16 K4 + 32 / TX); per pair T1 [wfk,akx][wfb,abx] and
 // T3 [wbk,wbb][lk,lb] (rows of 16); Gs [(tx, wb)][yb] (stride pad_b(K));
