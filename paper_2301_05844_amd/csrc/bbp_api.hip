@@ -152,6 +152,7 @@ struct Group {
   std::vector<int32_t> revs;
   std::vector<int32_t> flags;  // [W][items]
   DevBuf flagbuf;              // [W][items]
+  int cache_gen = 0;           // observables call that last used this batch
 };
 
 // Reduced density matrices of one region (block or union of two blocks)
@@ -193,8 +194,11 @@ struct bbp_ctx {
   std::vector<std::unique_ptr<Group>> groups;
   // observables' boundary-stack, line and unit-output buffers of earlier
   // calls, kept for the next call with the same shapes
+  // (entries tagged with the observables call that last used them; only the
+  // last two calls' entries are kept)
   std::vector<std::unique_ptr<Group>> batch_cache;
-  std::vector<DevBuf> unit_out_cache;
+  std::vector<std::pair<int, DevBuf>> unit_out_cache;
+  int obs_call = 0;
   double last_flops = 0.0;
   std::map<std::tuple<int, int, int>, RegionResult> obs;  // (kind, bi, bj)
 
@@ -445,20 +449,39 @@ struct BatchReturn {
   std::vector<std::unique_ptr<Group>> *v;
   ~BatchReturn() {
     for (auto &g : *v)
-      if (g) c->batch_cache.push_back(std::move(g));
+      if (g) {
+        g->cache_gen = c->obs_call;
+        c->batch_cache.push_back(std::move(g));
+      }
     v->clear();
   }
 };
 // A device buffer of exactly `bytes` from the context's cache, else new.
 static DevBuf take_unit_out(bbp_ctx *c, size_t bytes) {
   for (auto it = c->unit_out_cache.begin(); it != c->unit_out_cache.end(); ++it)
-    if (it->bytes == bytes) {
-      DevBuf b = std::move(*it);
+    if (it->second.bytes == bytes) {
+      DevBuf b = std::move(it->second);
       c->unit_out_cache.erase(it);
       return b;
     }
   return DevBuf();
 }
+// At the end of an observables call (also on an early error return): drop
+// the cached entries no call since the previous one has used.
+struct CacheTrim {
+  bbp_ctx *c;
+  ~CacheTrim() {
+    const int keep = c->obs_call - 1;
+    auto &b = c->batch_cache;
+    b.erase(std::remove_if(b.begin(), b.end(),
+                           [&](const std::unique_ptr<Group> &g) { return g->cache_gen < keep; }),
+            b.end());
+    auto &u = c->unit_out_cache;
+    u.erase(std::remove_if(u.begin(), u.end(),
+                           [&](const std::pair<int, DevBuf> &e) { return e.first < keep; }),
+            u.end());
+  }
+};
 
 // ---------------------------------------------------------------------------
 static bbp_status ensure_device(bbp_ctx *c) {
@@ -997,11 +1020,12 @@ static const double *region_site(const bbp_ctx *c, const RegionSpec &r, int y,
 }
 
 static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
+  ++c->obs_call;
+  CacheTrim trim{c};  // declared first: runs after every batch has been returned
   hipStream_t st = c->stream;
   hipError_t e = hipMemsetAsync(c->errflag.p, 0, 4, st);
   if (e != hipSuccess) return c->hip_fail(e, "memset");
   const int Kenv = c->chi_env, P = c->P, d = c->d, d2 = d * d;
-  const size_t Senv = (size_t)Kenv * P * Kenv;
   const size_t asite = (size_t)d * P * P;
   // ---- 1. boundary stacks, batched by rotated shape -----------------------
   std::vector<StackItem> stacks;
@@ -1274,8 +1298,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       DevBuf *b;
       ~OutReturn() {
         for (int i = 0; i < 2; ++i)
-          if (b[i].p) c->unit_out_cache.push_back(std::move(b[i]));
-        while (c->unit_out_cache.size() > 8) c->unit_out_cache.erase(c->unit_out_cache.begin());
+          if (b[i].p) c->unit_out_cache.emplace_back(c->obs_call, std::move(b[i]));
       }
     } out_return{c, outbuf};
     // chunk buffers, allocated once for the largest chunk and reused (stream

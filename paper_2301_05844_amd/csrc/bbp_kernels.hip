@@ -2360,7 +2360,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(const double *const *a,
   if (threadIdx.x == 0) out[it] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_ov_init(double *E, int K, int items) {
+__global__ void k_ov_init(double *E, int K) {
   const int it = blockIdx.x;
   for (int i = threadIdx.x; i < K * K; i += blockDim.x)
     E[(size_t)it * K * K + i] = (i == 0) ? 1.0 : 0.0;
@@ -2386,7 +2386,7 @@ static size_t a_stride(const FitBatch &f) { return (size_t)f.H * f.W * a_site(f)
 // Tile shape of the fused visit: the largest TY x TX pair set whose LDS
 // footprint fits, or TY = 0 when none does (generic chain then).
 static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
-  const size_t K = f.K, P = f.P, d = f.d;
+  const size_t K = f.K, P = f.P;
   const int cand[][2] = {{2, 8}, {2, 4}, {4, 2}, {2, 2}, {1, 4}, {1, 2}, {1, 1}};
   for (auto &c : cand) {
     const size_t ty = c[0], tx = c[1];
@@ -2798,7 +2798,7 @@ hipError_t launch_overlap(int items, int K, int P, int L,
                           double *E, double *U, double *out, hipStream_t st) {
   if (items <= 0) return hipSuccess;
   const size_t S = (size_t)K * P * K;
-  hipLaunchKernelGGL(k_ov_init, dim3(items), dim3(64), 0, st, E, K, items);
+  hipLaunchKernelGGL(k_ov_init, dim3(items), dim3(64), 0, st, E, K);
   for (int i = 0; i < L; ++i) {
     OpOv1 o1{K, P * K, K, nullptr, K, E, a, (size_t)i * S, U, S};
     hipError_t e = run_gemm<32, 64, 16>(o1, items, st);
