@@ -1,5 +1,6 @@
 """Benchmark: block-BP solves of a 16x16 open PEPS (D=4, 4x4 blocks, chi=32)
-on one MI355X.
+on one MI355X (the default workload; --workload picks the 4x4 open D=2 case
+or the infinite 2x2-cell D=4 case instead).
 
 One step is one complete solve on device-resident buffers: tensor setup and
 rotation (bbp_set_tensors), the synchronous sweeps needed to bring the
@@ -11,6 +12,7 @@ roofline figures (HIP events on its launch stream) and the FP64 CPU oracle
 timed on the host are added to the same JSON line.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline] [--no-mixed]
+    python bench.py --workload obc4x4_D2_b2_chi4 | inf2x2_D4_b4_chi32
     python bench.py --calibrate-copy   (plain 1 GiB device copy, for counters)
     python bench.py --serve [--requests 256] [--slots 8] [--rates 0.5 1 2 4]
 
@@ -31,9 +33,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from bbp_inputs import CONFIGS, op_heis, op_sz, peps_finite  # noqa: E402
+from bbp_inputs import (CONFIGS, op_heis, op_sx, op_sz, op_szsz,  # noqa: E402
+                        peps_finite, peps_infinite)
 
 WORKLOAD = "obc16x16_D4_b4_chi32"
+WORKLOADS = (WORKLOAD, "obc4x4_D2_b2_chi4", "inf2x2_D4_b4_chi32")
 TOL = 1e-10
 MAX_SWEEPS = 40
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
@@ -52,7 +56,33 @@ def sync():
     torch.cuda.synchronize()
 
 
-def solve(ctx, A, sweeps, sites, bonds, times=None):
+def lattice_terms(cfg):
+    """Sites and nearest-neighbour bonds whose terms a solve evaluates: every
+    site and bond of a finite lattice; the unit cell's sites and its
+    right/down bonds on the infinite lattice."""
+    if cfg["infinite"]:
+        cells = [(x, y) for y in range(cfg["ucy"]) for x in range(cfg["ucx"])]
+        bonds = [(x, y, x + 1, y) for (x, y) in cells] + [(x, y, x, y + 1) for (x, y) in cells]
+        return np.array(cells, dtype=np.int32), bonds
+    Lx, Ly = cfg["Lx"], cfg["Ly"]
+    sites = np.array([(x, y) for y in range(Ly) for x in range(Lx)], dtype=np.int32)
+    bonds = [(x, y, x + 1, y) for y in range(Ly) for x in range(Lx - 1)]
+    bonds += [(x, y, x, y + 1) for y in range(Ly - 1) for x in range(Lx)]
+    return sites, bonds
+
+
+def observables(ctx, cfg, sites, bonds):
+    """Finite lattice: <sigma_z> and <S.S>; infinite lattice: the transverse-Ising
+    terms <sigma_z>, <sigma_x>, <sigma_z sigma_z>.  Returns (site terms, bond terms)."""
+    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+    if cfg["infinite"]:
+        sx = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sx())
+        return np.concatenate([np.asarray(sz), np.asarray(sx)]), \
+            ctx.expect_bonds(bonds, op_szsz())
+    return sz, ctx.expect_bonds(bonds, op_heis())
+
+
+def solve(ctx, cfg, A, sweeps, sites, bonds, times=None):
     t0 = time.perf_counter()
     ctx.set_tensors(A)
     sync()
@@ -60,8 +90,7 @@ def solve(ctx, A, sweeps, sites, bonds, times=None):
     res = ctx.sweep(sweeps)
     sync()
     t2 = time.perf_counter()
-    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
-    ss = ctx.expect_bonds(bonds, op_heis())
+    sz, ss = observables(ctx, cfg, sites, bonds)
     ln = ctx.log_norm()
     sync()
     t3 = time.perf_counter()
@@ -70,7 +99,7 @@ def solve(ctx, A, sweeps, sites, bonds, times=None):
     return res, sz, ss, ln
 
 
-def roofline(stats):
+def roofline(stats, workload=WORKLOAD):
     """Dominant kernel class by summed time; achieved rate of its launches."""
     dom = max(stats, key=lambda s: s["ms"])
     n = max(dom["launches"], 1)
@@ -85,7 +114,8 @@ def roofline(stats):
         achieved = flops / avg_s / 1e12
         r = dict(bound="mfma", achieved=achieved, peak=PEAK_FP64_TFLOPS,
                  unit="TFLOP/s", frac=achieved / PEAK_FP64_TFLOPS)
-    r.update(traffic=measured_traffic(dom["name"]), kernel=dom["name"], launches=dom["launches"],
+    r.update(traffic=measured_traffic(dom["name"]) if workload == WORKLOAD else None,
+             kernel=dom["name"], launches=dom["launches"],
              avg_us=dom["ms"] / n * 1e3, flops_per_launch=flops,
              bytes_per_launch=bytes_, intensity=intensity)
     return r
@@ -278,35 +308,43 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
 
 
 def cpu_baseline(cfg, A):
-    """The FP64 oracle on the host: one untimed sweep, then one timed sweep
-    with every bond at its cap (48 directed-message updates)."""
+    """The FP64 oracle on the host: one untimed sweep, then timed sweeps of
+    the same solve (bonds at their caps) until about two seconds have passed
+    (one sweep on the 16x16 lattice)."""
     from oracle.blockbp import BlockBP
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    bp = BlockBP(A, D=cfg["D"], chi=cfg["chi"], bx=cfg["bx"], by=cfg["by"],
-                 Lx=cfg["Lx"], Ly=cfg["Ly"])
+    geo = dict(infinite=True, ucx=cfg["ucx"], ucy=cfg["ucy"]) if cfg["infinite"] \
+        else dict(Lx=cfg["Lx"], Ly=cfg["Ly"])
+    bp = BlockBP(A, D=cfg["D"], chi=cfg["chi"], bx=cfg["bx"], by=cfg["by"], **geo)
     bp.sweep()
+    nsw = 0
     t0 = time.perf_counter()
-    bp.sweep()
-    dt = time.perf_counter() - t0
-    n = len(bp.order)
+    while True:
+        bp.sweep()
+        nsw += 1
+        dt = time.perf_counter() - t0
+        if dt >= 2.0 or nsw >= 50:
+            break
+    n = len(bp.order) * nsw
+    what = "second sweep" if nsw == 1 else f"sweeps 2..{nsw + 1}"
     out = dict(value=n / dt, unit="message updates/s", cores=threads,
                kind="oracle",
-               sample=f"second sweep of the same solve ({n} message updates, "
+               sample=f"{what} of the same solve ({n} message updates, "
                       f"bonds at chi), {dt:.1f} s")
-    try:  # the same updates on one thread: the first 12 messages of a third sweep
+    try:  # the same updates on one thread: the first messages of the next sweep
         from threadpoolctl import threadpool_limits
-        n1 = 12
+        n1 = min(12, len(bp.order))
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             for e, key in enumerate(bp.order[:n1]):
                 bp.update_message(e, key, bp.msgs)
             d1 = time.perf_counter() - t0
         out["one_thread"] = dict(value=n1 / d1, unit="message updates/s", cores=1,
-                                 sample=f"first {n1} message updates of a third sweep, "
+                                 sample=f"first {n1} message updates of sweep {nsw + 2}, "
                                         f"{d1:.1f} s")
     except ImportError:
         pass
@@ -329,6 +367,8 @@ def main():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workload", choices=WORKLOADS, default=WORKLOAD,
+                    help="workload of the solve (default: the 16x16 open lattice)")
     ap.add_argument("--lanes", type=int, default=None,
                     help="streams the message and boundary-stack batches spread over "
                          "(library default when absent)")
@@ -346,27 +386,38 @@ def main():
         return
 
     from paper_2301_05844_amd import bbp
-    cfg = CONFIGS[WORKLOAD]
-    A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=0)
-    sites = np.array([(x, y) for y in range(cfg["Ly"]) for x in range(cfg["Lx"])],
-                     dtype=np.int32)
-    bonds = [(x, y, x + 1, y) for y in range(cfg["Ly"]) for x in range(cfg["Lx"] - 1)]
-    bonds += [(x, y, x, y + 1) for y in range(cfg["Ly"] - 1) for x in range(cfg["Lx"])]
+    cfg = CONFIGS[args.workload]
     opts = {} if args.lanes is None else dict(lanes=args.lanes)
-    ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
-                      D=cfg["D"], chi=cfg["chi"], **opts)
+    if cfg["infinite"]:
+        A = peps_infinite(cfg["ucx"], cfg["ucy"], cfg["D"], seed=0)
+        geo = dict(infinite=True, ucx=cfg["ucx"], ucy=cfg["ucy"])
+        lattice = f"infinite, {cfg['ucx']}x{cfg['ucy']} unit cell"
+        outputs = "unit cell's sigma_z and sigma_x, sigma_z sigma_z on its bonds, log-norm"
+    else:
+        A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=0)
+        geo = dict(Lx=cfg["Lx"], Ly=cfg["Ly"])
+        lattice = f"{cfg['Lx']}x{cfg['Ly']} open"
+        outputs = None
+    sites, bonds = lattice_terms(cfg)
+    if outputs is None:
+        outputs = f"{len(sites)} sigma_z, {len(bonds)} S.S, log-norm"
+    ctx = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo, **opts)
 
-    # warm-up: find the sweep count that reaches the tolerance
-    log("warm-up: sweeping to the tolerance")
     ctx.set_tensors(A)
-    sweeps, res = 0, 1.0
-    while res >= TOL and sweeps < MAX_SWEEPS:
-        res = ctx.sweep(1)
-        sweeps += 1
+    if "sweeps" in cfg:   # a fixed sweep count
+        sweeps = cfg["sweeps"]
+        res = ctx.sweep(sweeps)
+        log(f"{sweeps} sweeps (fixed) reach residual {res:.2e}")
+    else:                 # warm-up: find the sweep count that reaches the tolerance
+        log("warm-up: sweeping to the tolerance")
+        sweeps, res = 0, 1.0
+        while res >= TOL and sweeps < MAX_SWEEPS:
+            res = ctx.sweep(1)
+            sweeps += 1
+        log(f"{sweeps} sweeps reach residual {res:.2e}")
     n_msgs, flops_sweep = ctx.stats()
-    log(f"{sweeps} sweeps reach residual {res:.2e}")
     for _ in range(args.warmup):
-        solve(ctx, A, sweeps, sites, bonds)
+        solve(ctx, cfg, A, sweeps, sites, bonds)
         log("warm-up solve done")
 
     # timed region: K solves, no instrumentation (per-launch timing events
@@ -375,21 +426,27 @@ def main():
     sync()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        out = solve(ctx, A, sweeps, sites, bonds, times)
+        out = solve(ctx, cfg, A, sweeps, sites, bonds, times)
         log(f"step {k}: {sum(times[-1]) * 1e3:.1f} ms")
     sync()
     total = time.perf_counter() - t0
     # the same K solves again with every launch bracketed by HIP events on its
-    # stream: per-kernel-class durations for the roofline
-    ctx.set_option("timing", 1)
+    # stream: per-kernel-class durations for the roofline.  A context on one
+    # stream runs them, so that no two kernels overlap (the bracket of a kernel
+    # that shares the GPU with another lane's would include the other's time)
+    ctx1 = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
+                       lanes=1)
+    solve(ctx1, cfg, A, sweeps, sites, bonds)
+    ctx1.set_option("timing", 1)
     sync()
     ti0 = time.perf_counter()
     for k in range(args.steps):
-        solve(ctx, A, sweeps, sites, bonds)
+        solve(ctx1, cfg, A, sweeps, sites, bonds)
     sync()
     timed_total = time.perf_counter() - ti0
-    stats = ctx.kernel_stats()
-    ctx.set_option("timing", 0)
+    stats = ctx1.kernel_stats()
+    ctx1.set_option("timing", 0)   # the timing switch is process-wide
+    ctx1.close()
 
     step_s = np.array([sum(t) for t in times])
     sweep_s = np.array([t[1] for t in times])
@@ -408,11 +465,12 @@ def main():
         vs_baseline=None,
         dtype="f64",
         data="synthetic",
-        config=dict(workload=WORKLOAD, lattice="16x16 open", D=cfg["D"],
-                    chi=cfg["chi"], block="4x4", chi_env=2 * cfg["D"] ** 2 + 10,
+        config=dict(workload=args.workload, lattice=lattice, D=cfg["D"],
+                    chi=cfg["chi"], block=f"{cfg['bx']}x{cfg['by']}",
+                    chi_env=cfg.get("chi_env", 2 * cfg["D"] ** 2 + 10),
                     n_fit=2, sweeps_per_solve=sweeps, messages_per_sweep=n_msgs,
                     residual=out[0],
-                    outputs="256 sigma_z, 480 S.S, log-norm"),
+                    outputs=outputs),
         fit_tflops=flops_sweep * sweeps / sweep_s.mean() / 1e12,
         fit_tflops_frac=flops_sweep * sweeps / sweep_s.mean() / 1e12
         / PEAK_FP64_TFLOPS,
@@ -421,14 +479,15 @@ def main():
                       observables=float(np.mean([t[2] for t in times]) * 1e3)),
         solve_latency_ms=dict(p50=float(np.percentile(step_s, 50) * 1e3),
                               p99=float(np.percentile(step_s, 99) * 1e3)),
-        roofline=dict(roofline(stats), measured_in="second pass of the same K solves, "
-                      "every launch bracketed by HIP events",
+        roofline=dict(roofline(stats, args.workload), measured_in="second pass of the same K "
+                      "solves on a one-stream context (lanes 1), every launch bracketed by "
+                      "HIP events",
                       pass_ms_per_step=timed_total / args.steps * 1e3),
         kernels={s["name"]: dict(launches=s["launches"], ms=s["ms"])
                  for s in stats},
         cpu_baseline=None,
     )
-    if not args.no_mixed:
+    if not args.no_mixed and "tol" in cfg and not cfg["infinite"]:
         line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
                                                   line["ms_per_step"])
     if not args.no_cpu_baseline:

@@ -84,10 +84,11 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              stay FP64); QR, normalisation, overlaps and every stored
  *              message stay FP64.  Sweeps in 32 followed by sweeps in 64
  *              reach the FP64 fixed point from the FP32 one.
- *   "lanes"    1..4 (default 1; before bbp_set_tensors): message batches and
- *              boundary-stack batches are split over this many streams (the
- *              context stream and lanes-1 streams the context creates) so
- *              that independent batches overlap on the GPU.  Results do not
+ *   "lanes"    1..4 (default 3; before bbp_set_tensors): independent batches
+ *              run on this many streams (the context stream and lanes-1
+ *              streams the context creates) and overlap on the GPU: the
+ *              message batches one per shape, the observables' boundary
+ *              stacks with every shape split over the lanes.  Results do not
  *              depend on it; the context stream waits for every lane before
  *              a call returns.
  * Unknown keys or out-of-range values: BBP_EINVAL.

@@ -177,7 +177,7 @@ struct bbp_ctx {
   int gx = 1, gy = 1;
   int chi_env = -1, n_fit = 2;
   int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
-  int lanes = 1;       // streams that independent fit batches spread over
+  int lanes = 3;       // streams that independent fit batches spread over
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
@@ -1051,7 +1051,10 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   std::map<std::pair<int, int>, std::vector<int>> sgroups;
   for (size_t i = 0; i < stacks.size(); ++i)
     sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
-  std::vector<std::vector<int>> batches;  // per shape, split for the lanes
+  // every shape split over the lanes: each lane then runs a share of every
+  // shape, and the lanes' kernels overlap at different steps of their fits
+  // (one lane's QR, which holds few CUs, beside another's visit)
+  std::vector<std::vector<int>> batches;
   for (auto &kv : sgroups)
     for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) batches.push_back(part);
   std::vector<std::unique_ptr<Group>> sg;
@@ -1743,6 +1746,12 @@ bbp_status bbp_set_allocator(bbp_ctx *c, bbp_alloc_fn alloc, bbp_free_fn free_, 
   return BBP_OK;
 }
 
+// Canonical (W, H) of a message's fit: columns absorbed and sites per column.
+static std::pair<int, int> message_shape(const bbp_ctx *c, const Message &m) {
+  const bool lr = m.dir == 'L' || m.dir == 'R';
+  return {lr ? c->bx : c->by, lr ? c->by : c->bx};
+}
+
 bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   if (!c || !A) return BBP_EINVAL;
   AcctScope acct_scope(&c->mem);
@@ -1802,33 +1811,23 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       return c->fail(BBP_EDEVICE, "upload trivial message");
   }
   c->cur = 0;
-  // groups by canonical (W, H), large ones split so that the lanes can
-  // overlap them; the groups of an earlier call are kept (with their device
-  // buffers) when the partition is the same
+  // groups by canonical (W, H), one per lane in turn, each kept whole: the
+  // message fits run at a bond cap whose launches fill the GPU, and splitting
+  // a group over the lanes was measured slower; the groups of an earlier call
+  // are kept (with their device buffers) when the partition is the same
   std::vector<std::unique_ptr<Group>> groups;
   {
     std::map<std::pair<int, int>, int> gid;
-    std::vector<std::unique_ptr<Group>> byshape;
     for (size_t i = 0; i < c->msgs.size(); ++i) {
-      const Message &m = c->msgs[i];
-      int W = (m.dir == 'L' || m.dir == 'R') ? c->bx : c->by;
-      int H = (m.dir == 'L' || m.dir == 'R') ? c->by : c->bx;
-      auto key = std::make_pair(W, H);
+      const auto key = message_shape(c, c->msgs[i]);
       if (!gid.count(key)) {
-        gid[key] = (int)byshape.size();
-        byshape.emplace_back(new Group);
-        byshape.back()->W = W;
-        byshape.back()->H = H;
-      }
-      byshape[gid[key]]->ids.push_back((int)i);
-    }
-    for (auto &g : byshape)
-      for (auto &part : split_batch(g->ids, c->lanes, kLaneMinItems)) {
+        gid[key] = (int)groups.size();
         groups.emplace_back(new Group);
-        groups.back()->W = g->W;
-        groups.back()->H = g->H;
-        groups.back()->ids = part;
+        groups.back()->W = key.first;
+        groups.back()->H = key.second;
       }
+      groups[gid[key]]->ids.push_back((int)i);
+    }
   }
   bool same = groups.size() == c->groups.size();
   for (size_t i = 0; same && i < groups.size(); ++i)

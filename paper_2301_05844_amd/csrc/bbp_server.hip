@@ -119,6 +119,11 @@ void bbp_server::serve(Request &q) {
   bbp_status s = bbp_create(&c, 0, r.Lx, r.Ly, 0, 0, r.bx, r.by, r.D, r.chi);
   bool ok = s == BBP_OK;
   if (!ok) fail(s, "bbp_create");
+  // requests overlap on their own streams; each keeps to its one stream
+  if (ok && (s = bbp_set_option(c, "lanes", 1)) != BBP_OK) {
+    fail(s, "bbp_set_option");
+    ok = false;
+  }
   if (ok && hipSetDevice(0) == hipSuccess &&
       hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess) {
     (void)bbp_set_stream(c, st);

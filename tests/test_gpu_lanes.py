@@ -1,6 +1,7 @@
-"""Lanes (the "lanes" option): message batches and boundary-stack batches
-split over several streams give bitwise the results of one stream, since
-every item is computed from its own inputs only."""
+"""Lanes (the "lanes" option): message batches (one per shape) and
+boundary-stack batches (every shape split) on several streams give bitwise
+the results of one stream, since every item is computed from its own inputs
+only."""
 
 import numpy as np
 import pytest
@@ -27,14 +28,16 @@ def _run(lanes, A, Lx, Ly, bx, by, D, chi, sweeps):
 
 
 @pytest.mark.parametrize("lanes", [2, 3, 4])
-def test_lanes_bitwise_equal(lanes):
-    # 8x8 lattice, 2x2 blocks: 48 messages of one shape, split into `lanes`
-    # batches; the region stacks split likewise
-    Lx = Ly = 8
+@pytest.mark.parametrize("lat", [(8, 8, 2, 2), (8, 6, 2, 3)])
+def test_lanes_bitwise_equal(lanes, lat):
+    # 8x8 lattice, 2x2 blocks: 48 messages of one shape in one batch, the
+    # region stacks split over the lanes; 8x6 lattice, 2x3 blocks: two message
+    # shapes, one batch on each lane
+    Lx, Ly, bx, by = lat
     A = peps_finite(Lx, Ly, 3, seed=5)
-    one = _run(1, A, Lx, Ly, 2, 2, 3, 9, 3)
-    many = _run(lanes, A, Lx, Ly, 2, 2, 3, 9, 3)
-    print(f"lanes {lanes}: residuals {many[0]}", flush=True)
+    one = _run(1, A, Lx, Ly, bx, by, 3, 9, 3)
+    many = _run(lanes, A, Lx, Ly, bx, by, 3, 9, 3)
+    print(f"lanes {lanes}, lattice {lat}: residuals {many[0]}", flush=True)
     for a, b in zip(one, many):
         assert np.array_equal(a, b)
 
