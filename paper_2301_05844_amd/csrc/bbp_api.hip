@@ -42,13 +42,17 @@ bool out_reversed(char d) { return d == 'R' || d == 'U'; }
 // allocate names its context's account for the calling thread), and the
 // allocator the context's device memory comes from (hipMalloc/hipFree unless
 // the caller supplied one; its memory is handed back only after the
-// context's stream has drained).
+// context's stream has drained).  When an allocation fails, `evict` frees
+// what the context only keeps for reuse and the allocation is tried once
+// more.
 struct MemAcct {
   size_t now = 0, peak = 0;
   bbp_alloc_fn alloc_fn = nullptr;
   bbp_free_fn free_fn = nullptr;
   void *user = nullptr;
   const hipStream_t *stream = nullptr;
+  void (*evict)(void *) = nullptr;
+  void *evict_user = nullptr;
 };
 thread_local MemAcct *tl_acct = nullptr;
 struct AcctScope {
@@ -102,15 +106,15 @@ struct DevBuf {
     if (p && b == bytes && acct == tl_acct) return hipSuccess;
     release();
     if (b == 0) return hipSuccess;
-    hipError_t e;
-    if (tl_acct && tl_acct->alloc_fn) {
-      p = tl_acct->alloc_fn(b, tl_acct->user);
-      e = p ? hipSuccess : hipErrorOutOfMemory;
-    } else {
-      e = hipMalloc(&p, b);
+    hipError_t e = raw_alloc(b);
+    if (e != hipSuccess && tl_acct && tl_acct->evict) {
+      (void)hipGetLastError();  // the failed attempt's error is not a launch error
+      tl_acct->evict(tl_acct->evict_user);
+      e = raw_alloc(b);
     }
     if (e != hipSuccess) {
       p = nullptr;
+      (void)hipGetLastError();
       return e;
     }
     bytes = b;
@@ -122,6 +126,15 @@ struct DevBuf {
     return hipSuccess;
   }
   double *d() const { return (double *)p; }
+
+ private:
+  hipError_t raw_alloc(size_t b) {
+    if (tl_acct && tl_acct->alloc_fn) {
+      p = tl_acct->alloc_fn(b, tl_acct->user);
+      return p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(&p, b);
+  }
 };
 
 struct Message {
@@ -482,6 +495,14 @@ struct CacheTrim {
             u.end());
   }
 };
+
+// Frees the observables' kept buffers (every entry belongs to a call that
+// has returned, so no device work uses them).
+static void evict_caches(void *ctx) {
+  bbp_ctx *c = static_cast<bbp_ctx *>(ctx);
+  c->batch_cache.clear();
+  c->unit_out_cache.clear();
+}
 
 // ---------------------------------------------------------------------------
 static bbp_status ensure_device(bbp_ctx *c) {
@@ -1293,7 +1314,10 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       for (int j : rl)
         for (int u = 0; u < d2; ++u) units[1].push_back(UnitItem{(int)li, j, u});
     }
-    const int CH = 256;
+    // units per chunk: 256, fewer where a unit's contraction scratch (T1,
+    // T2, T3: up to (2 + d) K^2 P^2 doubles) would pass 16 GiB per chunk
+    const size_t unit_scratch = 8ull * (2 + d) * Kenv * Kenv * (size_t)P * P;
+    const int CH = (int)std::max<size_t>(8, std::min<size_t>(256, (16ull << 30) / unit_scratch));
     std::vector<double *> out_ptr[2];
     DevBuf outbuf[2];
     struct OutReturn {  // unit outputs back to the context's cache
@@ -1656,6 +1680,8 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
   }
   bbp_ctx *c = new (std::nothrow) bbp_ctx;
   if (!c) return BBP_ENOMEM;
+  c->mem.evict = evict_caches;
+  c->mem.evict_user = c;
   c->infinite = infinite ? 1 : 0;
   c->Lx = infinite ? 0 : Lx;
   c->Ly = infinite ? 0 : Ly;
