@@ -1782,6 +1782,212 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
 }
 
 // ---------------------------------------------------------------------------
+// The same Householder QR for tall panels kept in a global scratch (D = 6
+// and larger bonds): one workgroup of 16 waves per item.  Each reflector is
+// staged in LDS once (read in place where a panel has more than kQrgRows
+// rows), and a wave updates up to kQrgCols trailing columns in
+// one pass over the rows (one dot product and one axpy per column, the
+// columns' loads interleaved), so the trailing matrix is read twice and
+// written once per reflector.  Reflectors, their order and the formation of
+// Q are those of the kernel above.
+// ---------------------------------------------------------------------------
+constexpr int kQrgThreads = 1024;
+constexpr int kQrgWaves = kQrgThreads / 64;
+constexpr int kQrgRows = 8192;  // rows of the staged reflector (64 KB of LDS)
+constexpr int kQrgCols = 8;     // trailing columns per wave and pass (n <= 128)
+
+// a_c -= tau v (a_kc + v^T a_c) for the columns c = c0, c0 + kQrgWaves, ...
+// (< n) of this wave; v = (1, vs[k+1..m-1]).  Rows go kQrgUnroll at a time
+// per lane, their loads issued together (the panel streams from L2).
+constexpr int kQrgUnroll = 2;
+__device__ __forceinline__ void qrg_apply(double *A, const double *vs, int m, int n, int k,
+                                          double tau, int c0, int lane) {
+  double *a[kQrgCols];
+  double w[kQrgCols];
+  int nc = 0;
+#pragma unroll
+  for (int u = 0; u < kQrgCols; ++u) {
+    const int c = c0 + u * kQrgWaves;
+    a[u] = A + (size_t)(c < n ? c : k) * m;
+    w[u] = 0.0;
+    if (c < n) nc = u + 1;
+  }
+  if (nc == 0) return;
+  for (int i0 = k + 1 + lane; i0 < m; i0 += 64 * kQrgUnroll) {
+    double v[kQrgUnroll], x[kQrgUnroll][kQrgCols];
+#pragma unroll
+    for (int r = 0; r < kQrgUnroll; ++r) {
+      const int i = i0 + 64 * r;
+      v[r] = i < m ? vs[i] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kQrgCols; ++u) x[r][u] = (u < nc && i < m) ? a[u][i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kQrgUnroll; ++r)
+#pragma unroll
+      for (int u = 0; u < kQrgCols; ++u) w[u] = fma(v[r], x[r][u], w[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kQrgCols; ++u) {
+    if (u >= nc) break;
+    w[u] = tau * (wave_sum(w[u]) + a[u][k]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int u = 0; u < kQrgCols; ++u)
+      if (u < nc) a[u][k] -= w[u];
+  }
+  for (int i0 = k + 1 + lane; i0 < m; i0 += 64 * kQrgUnroll) {
+    double v[kQrgUnroll], x[kQrgUnroll][kQrgCols];
+#pragma unroll
+    for (int r = 0; r < kQrgUnroll; ++r) {
+      const int i = i0 + 64 * r;
+      v[r] = i < m ? vs[i] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kQrgCols; ++u) x[r][u] = (u < nc && i < m) ? a[u][i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kQrgUnroll; ++r) {
+      const int i = i0 + 64 * r;
+      if (i >= m) break;
+#pragma unroll
+      for (int u = 0; u < kQrgCols; ++u)
+        if (u < nc) a[u][i] = x[r][u] - v[r] * w[u];
+    }
+  }
+}
+
+// Copies between the strided panel and the column-major scratch, eight
+// elements in flight per thread.
+template <bool kIn>
+__device__ __forceinline__ void qrg_copy(double *A, double *base, int m, int n, int n2,
+                                         size_t s1, size_t s2, size_t sc, int tid) {
+  constexpr int U = 8;
+  const int total = m * n;
+  for (int i0 = tid; i0 < total; i0 += kQrgThreads * U) {
+    double x[U];
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      const int idx = i0 + r * kQrgThreads;
+      const int col = idx / m, row = idx - col * m;
+      const int r1 = row / n2, r2 = row - r1 * n2;
+      const size_t g = r1 * s1 + r2 * s2 + col * sc;
+      x[r] = idx < total ? (kIn ? base[g] : A[idx]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < U; ++r) {
+      const int idx = i0 + r * kQrgThreads;
+      if (idx >= total) break;
+      const int col = idx / m, row = idx - col * m;
+      const int r1 = row / n2, r2 = row - r1 * n2;
+      const size_t g = r1 * s1 + r2 * s2 + col * sc;
+      if (kIn) A[idx] = x[r];
+      else base[g] = x[r];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kQrgThreads) void k_qrg(QrArgs q) {
+  const int it = blockIdx.x;
+  if (q.flag && !q.flag[it]) return;
+  const FitDims &dm = q.dims[(size_t)it * q.W + q.c];
+  const int K = q.K, P = q.P, j = q.j;
+  int n1, n2, ncol;
+  size_t s1, s2, sc;
+  switch (q.mode) {
+    case LR_INNER:
+      n1 = dm.bl[j]; s1 = (size_t)P * K; n2 = P; s2 = K; ncol = dm.br[j]; sc = 1;
+      break;
+    case RL_INNER:  // rows (l, yb), l-major, as in the QR of the transpose
+      n1 = P; s1 = K; n2 = dm.br[j]; s2 = 1; ncol = dm.bl[j]; sc = (size_t)P * K;
+      break;
+    case LR_TOP:
+      n1 = dm.p[j]; s1 = K; n2 = 1; s2 = 0; ncol = dm.br[j]; sc = 1;
+      break;
+    default:  // RL_BOT
+      n1 = dm.p[j]; s1 = 1; n2 = 1; s2 = 0; ncol = dm.bl[j]; sc = K;
+      break;
+  }
+  const int m = n1 * n2, n = ncol;
+  double *base = q.Y.at(it);
+  __shared__ double vs[kQrgRows];
+  __shared__ double red[kQrgWaves];
+  __shared__ double tau_s[128];
+  __shared__ double scal_s;
+  double *A = q.scratch + (size_t)it * q.scratch_stride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool stage = m <= kQrgRows;
+
+  qrg_copy<true>(A, base, m, n, n2, s1, s2, sc, tid);
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    double *v = A + (size_t)k * m;
+    double part = 0.0;
+    for (int i = k + 1 + tid; i < m; i += kQrgThreads) part = fma(v[i], v[i], part);
+    part = wave_sum(part);
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (tid == 0) {  // dlarfg
+      double sigma2 = 0.0;
+      for (int w = 0; w < kQrgWaves; ++w) sigma2 += red[w];
+      const double alpha = v[k];
+      double tau = 0.0, scal = 0.0, beta = alpha;
+      if (sigma2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      tau_s[k] = tau;
+      scal_s = scal;
+      v[k] = beta;
+    }
+    __syncthreads();
+    const double tau = tau_s[k];
+    if (tau != 0.0) {
+      const double scal = scal_s;
+      for (int i = k + 1 + tid; i < m; i += kQrgThreads) {
+        const double x = v[i] * scal;
+        v[i] = x;
+        if (stage) vs[i] = x;
+      }
+      __syncthreads();
+      qrg_apply(A, stage ? vs : v, m, n, k, tau, k + 1 + wave, lane);
+    }
+    __syncthreads();
+  }
+
+  if (q.want_r) {
+    double *R = q.rbuf + (size_t)it * K * K;
+    for (int idx = tid; idx < K * K; idx += kQrgThreads) {
+      const int r = idx / K, cc = idx - r * K;
+      R[idx] = (r < n && cc < n && r <= cc) ? A[(size_t)cc * m + r] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  // Q = H_0 ... H_{n-1} [I; 0], formed in place from the last reflector.
+  for (int k = n - 1; k >= 0; --k) {
+    double *v = A + (size_t)k * m;
+    const double tau = tau_s[k];
+    if (stage)
+      for (int i = k + 1 + tid; i < m; i += kQrgThreads) vs[i] = v[i];
+    __syncthreads();
+    if (k < n - 1 && tau != 0.0) qrg_apply(A, stage ? vs : v, m, n, k, tau, k + 1 + wave, lane);
+    if (!stage) __syncthreads();  // column k is read in place by the update
+    for (int i = tid; i < m; i += kQrgThreads) {
+      if (i > k) v[i] = -tau * (stage ? vs[i] : v[i]);
+      else if (i == k) v[i] = 1.0 - tau;
+      else v[i] = 0.0;
+    }
+    __syncthreads();
+  }
+
+  qrg_copy<false>(A, base, m, n, n2, s1, s2, sc, tid);
+}
+
+// ---------------------------------------------------------------------------
 // Blocked Householder QR on FP64 MFMA tiles, one workgroup of NW waves per
 // item.  The panel stays in registers as 16x16 tiles in the MFMA accumulator
 // layout (register s of lane l holds row 4s + l/16, column l%16 of its tile);
@@ -2717,7 +2923,8 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
   Span sp(KC_QR, st, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
           f.items * 16.0 * m * n);
   // The blocked MFMA kernel for panels up to 768 x 48 (every shape of the
-  // D <= 4 workloads); otherwise the LDS kernel, or its global-memory form.
+  // D <= 4 workloads); otherwise the LDS kernel, or the 16-wave global-memory
+  // one (up to 128 columns, every bond cap the context accepts).
   if (qrm_fits(f)) {
     launch_qrm(f, st, q);
   } else if (panel <= (size_t)kQrLds) {
@@ -2725,7 +2932,10 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
   } else {
     if (!f.t1 || t1_stride(f) < panel)
       return hipErrorInvalidValue;  // global panel scratch missing or too small
-    hipLaunchKernelGGL(k_qr<false>, dim3(f.items), dim3(kThreads), 0, st, q);
+    if (f.K <= kQrgWaves * kQrgCols)
+      hipLaunchKernelGGL(k_qrg, dim3(f.items), dim3(kQrgThreads), 0, st, q);
+    else
+      hipLaunchKernelGGL(k_qr<false>, dim3(f.items), dim3(kThreads), 0, st, q);
   }
   (void)panel;
   return hipGetLastError();
