@@ -533,6 +533,7 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
                               unsigned need = NEED_FIT | NEED_SCRATCH) {
   FitBatch &f = g.fb;
   f.items = items;
+  f.tile_items = items;
   f.K = bond_cap;
   f.P = c->P;
   f.D = c->D;
@@ -1076,15 +1077,20 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   // shape, and the lanes' kernels overlap at different steps of their fits
   // (one lane's QR, which holds few CUs, beside another's visit)
   std::vector<std::vector<int>> batches;
+  std::vector<int> shape_items;  // items of the shape each batch belongs to
   for (auto &kv : sgroups)
-    for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) batches.push_back(part);
+    for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) {
+      batches.push_back(part);
+      shape_items.push_back((int)kv.second.size());
+    }
   std::vector<std::unique_ptr<Group>> sg;
   BatchReturn sg_return{c, &sg};
   std::vector<std::pair<int, int>> where(stacks.size());  // (group, item)
   std::vector<std::vector<double>> nus;
   // allocate and stage every batch first: allocation waits on the context
   // stream, which must not yet hold absorption work
-  for (const std::vector<int> &ids : batches) {
+  for (size_t bi = 0; bi < batches.size(); ++bi) {
+    const std::vector<int> &ids = batches[bi];
     std::unique_ptr<Group> gp =
         take_batch(c, stacks[ids[0]].Wc, stacks[ids[0]].Hc, (int)ids.size());
     Group &g = *gp;
@@ -1098,6 +1104,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     bbp_status bs = alloc_batch(c, g, (int)ids.size(), Kenv, slots);
     if (bs != BBP_OK) return bs;
     FitBatch &f = g.fb;
+    f.tile_items = shape_items[bi];
     // rotated tensors, gather tables and bond caps
     g.host.assign((size_t)f.items * f.H * f.W * asite, 0.0);
     g.gs.assign(f.items, GatherSrc{});

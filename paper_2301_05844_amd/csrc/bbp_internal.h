@@ -27,6 +27,9 @@ struct FitDims {
 // first K*K doubles of their slot as a [phys][bond] or [bond][phys] matrix.
 struct FitBatch {
   int items = 0;
+  // items the visit's tiling is chosen for: the whole batch's count where a
+  // batch is split over streams, so that every part runs the same kernels
+  int tile_items = 0;
   int K = 0, P = 0, D = 0, d = 0;  // bond cap, D^2, D, physical dim
   int H = 0, W = 0, N = 0;          // column height, width, N = H + 2
   size_t S = 0;                     // slot size (doubles)

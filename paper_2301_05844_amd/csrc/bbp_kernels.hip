@@ -1379,7 +1379,8 @@ __host__ __device__ inline size_t visit4p_lds(int K, int TY, int TX) {
 // each of the X and G tiles (16 NE x 16 x TX) per thread and step.  Up to
 // NE = 3 (K <= 48) three workgroups share a CU (2 x 2 pairs at NE = 2, LDS
 // <= 47 KB; 4 x 1 at NE = 3, LDS <= 52 KB), so the registers are held to 3
-// waves per SIMD; at NE = 4 to 2.
+// waves per SIMD; at NE = 4 to 2, and for the 1 x 4 tiles of small batches
+// (which leave most of the CUs free anyway) to 2.
 template <int TY, int TX, int NE>
 struct Visit4pShape {
   static constexpr int NWV = TY * TX, NT = 64 * NWV;
@@ -1388,7 +1389,7 @@ struct Visit4pShape {
 
 template <int TY, int TX, class T, int NE>
 __global__ __launch_bounds__(64 * TY * TX)
-__attribute__((amdgpu_waves_per_eu(NE <= 3 ? 3 : 2)))
+__attribute__((amdgpu_waves_per_eu(NE <= 3 && TY > 1 ? 3 : 2)))
 void k_visit4p(VisitArgs v) {
   constexpr int NT = Visit4pShape<TY, TX, NE>::NT, NWV = Visit4pShape<TY, TX, NE>::NWV;
   extern __shared__ double sm_raw[];
@@ -2654,12 +2655,17 @@ static VisitKernel visit4_kernel(int TY, int TX) {
 // NE = number of 16-wide local-update tiles the kernel is built for (>= 2).
 static int visit4p_ne(int K) { return std::max(2, ceil16(K) / 16); }
 
-// Pair-per-wave visit (K <= 64): 2 x 2 pairs, 4 x 1 at NE = 3.
+// Pair-per-wave visit (K <= 64): 2 x 2 pairs, 4 x 1 at NE = 3.  A small
+// batch at NE <= 2, whose 2 x 2 grid would not give every CU a workgroup,
+// takes 1 x 4 pairs: twice the workgroups, each walking a quarter of the
+// columns xb.
 template <class T>
 static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
   if (f.D != 4 || f.d != 2 || f.K > 64) return false;
-  const bool ne3 = visit4p_ne(f.K) == 3;
-  const int ty = ne3 ? 4 : 2, tx = ne3 ? 1 : 2;
+  const int ne = visit4p_ne(f.K);
+  const long sel = f.tile_items > 0 ? f.tile_items : f.items;
+  const bool small = ne <= 2 && sel * ((f.K + 1) / 2) < 256;
+  const int ty = ne == 3 ? 4 : small ? 1 : 2, tx = ne == 3 ? 1 : small ? 4 : 2;
   const size_t n = visit4p_lds<T>(f.K, ty, tx) * sizeof(T);
   if (n > 150 * 1024) return false;
   *TY = ty;
@@ -2670,8 +2676,8 @@ static bool visit4p_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
 
 
 template <class T>
-static VisitKernel visit4p_kernel(int NE) {
-  if (NE <= 2) return k_visit4p<2, 2, T, 2>;
+static VisitKernel visit4p_kernel(int NE, int TY) {
+  if (NE <= 2) return TY == 1 ? k_visit4p<1, 4, T, 2> : k_visit4p<2, 2, T, 2>;
   if (NE == 3) return k_visit4p<4, 1, T, 3>;
   return k_visit4p<2, 2, T, 4>;
 }
@@ -2706,7 +2712,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
         if (e != hipSuccess) attr_err = e;
       }
     for (int ne = 2; ne <= 4; ++ne)
-      for (VisitKernel kf : {visit4p_kernel<double>(ne), visit4p_kernel<float>(ne)}) {
+      for (VisitKernel kf : {visit4p_kernel<double>(ne, 2), visit4p_kernel<float>(ne, 2),
+                             visit4p_kernel<double>(ne, 1), visit4p_kernel<float>(ne, 1)}) {
         hipError_t e = hipFuncSetAttribute(
             (const void *)kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) attr_err = e;
@@ -2746,7 +2753,7 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     v.TY = TYp;
     v.TX = TXp;
     const int ne = visit4p_ne(f.K);
-    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(ne) : visit4p_kernel<double>(ne),
+    hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(ne, TYp) : visit4p_kernel<double>(ne, TYp),
                        dim3((f.K + TYp - 1) / TYp, f.items), dim3(64 * TYp * TXp), ldsp, st, v);
   } else if (spec) {
     v.TY = TY4;
