@@ -155,7 +155,8 @@ struct Group {
   std::vector<int> ids;  // message ids in this batch
   FitBatch fb;
   std::vector<DevBuf> bufs;
-  DevBuf gather, dst, rev, dims_host_unused;
+  DevBuf gather, dst, rev;
+  DevBuf t3r;  // line batches: the right environment chain's own T3 scratch
   std::vector<FitDims> dims;  // [items][W], host copy
   std::vector<int> have;      // [items*W] warm start valid
   // host staging of the per-sweep tables (kept alive until the stream syncs)
@@ -1271,25 +1272,42 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     if ((e = launch_set_unit(f, Le(0), st)) != hipSuccess ||
         (e = launch_set_unit(f, Re(N - 1), st)) != hipSuccess)
       return c->hip_fail(e, "set_unit");
-    for (int j = 0; j < N - 1; ++j) {
-      if (j == 0) {
-        e = launch_end_chain(f, false, MT, Xs(0), st);
-        if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
-      } else {
-        e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), st);
-        if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+    {
+      // the left and right environment chains are independent: with more
+      // than one lane the right one runs on lane 1 with a T3 scratch of its
+      // own, where the visit is fused (T3 is then the only buffer the two
+      // would share; the unfused contractions also stage T1 and T2)
+      const int nl2 = visit_fused_fits(f) ? std::min(c->lanes, 2) : 1;
+      FitBatch fr = f;
+      if (nl2 > 1) {
+        if (lg.t3r.alloc((size_t)f.items * f.K * f.P * f.P * f.K * 8) != hipSuccess)
+          return c->fail(BBP_ENOMEM, "device allocation failed");
+        fr.t3 = lg.t3r.d();
       }
-      if (e != hipSuccess) return c->hip_fail(e, "line left environments");
-    }
-    for (int j = N - 1; j >= 1; --j) {
-      if (j == N - 1) {
-        e = launch_end_chain(f, true, MB, Xs(N - 1), st);
-        if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
-      } else {
-        e = launch_inner_chain(f, 0, j, true, Xs(j), Re(j), st);
-        if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
+      LaneFork chains(c);
+      if ((e = chains.fork(nl2)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+      const hipStream_t sr = lane_stream(c, nl2 - 1);
+      for (int j = 0; j < N - 1; ++j) {
+        if (j == 0) {
+          e = launch_end_chain(f, false, MT, Xs(0), st);
+          if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
+        } else {
+          e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), st);
+          if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+        }
+        if (e != hipSuccess) return c->hip_fail(e, "line left environments");
       }
-      if (e != hipSuccess) return c->hip_fail(e, "line right environments");
+      for (int j = N - 1; j >= 1; --j) {
+        if (j == N - 1) {
+          e = launch_end_chain(fr, true, MB, Xs(N - 1), sr);
+          if (e == hipSuccess) e = launch_end_env(fr, true, Ys(N - 1), Re(N - 2), sr);
+        } else {
+          e = launch_inner_chain(fr, 0, j, true, Xs(j), Re(j), sr);
+          if (e == hipSuccess) e = launch_inner_env(fr, true, Ys(j), Re(j - 1), sr);
+        }
+        if (e != hipSuccess) return c->hip_fail(e, "line right environments");
+      }
+      if ((e = chains.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
     }
     // ---- 3. matrix-unit steps ------------------------------------------
     // needed (line, j, direction): sites and the first site of a bond take
