@@ -1643,8 +1643,8 @@ void k_visit4p(VisitArgs v) {
 // ---------------------------------------------------------------------------
 // Householder QR (LAPACK conventions: dlarfg reflectors, dorg2r formation).
 // One workgroup per item; the true panel (rows r = r1*n2 + r2, columns c at
-// base[r1*s1 + r2*s2 + c*sc]) is copied column-major into LDS (or a global
-// scratch when it does not fit), factorised, and Q written back in place.
+// base[r1*s1 + r2*s2 + c*sc]) is copied column-major into LDS, factorised,
+// and Q written back in place (panels too large for LDS: k_qrg below).
 // ---------------------------------------------------------------------------
 struct QrArgs {
   FitDims *dims;
@@ -1665,7 +1665,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <bool kLds>
 __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
   const int it = blockIdx.x;
   if (q.flag && !q.flag[it]) return;
@@ -1689,10 +1688,10 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
   }
   const int m = n1 * n2, n = ncol;
   double *base = q.Y.at(it);
-  __shared__ double lds[kLds > 0 ? (kLds ? kQrLds : 1) : 1];
+  __shared__ double lds[kQrLds];
   __shared__ double red[8];
   __shared__ double tau_s[128];
-  double *A = kLds ? lds : q.scratch + (size_t)it * q.scratch_stride;
+  double *A = lds;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   for (int idx = tid; idx < m * n; idx += kThreads) {
@@ -2931,18 +2930,16 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
           f.items * 16.0 * m * n);
   // The blocked MFMA kernel for panels up to 768 x 48 (every shape of the
   // D <= 4 workloads); otherwise the LDS kernel, or the 16-wave global-memory
-  // one (up to 128 columns, every bond cap the context accepts).
+  // one (up to 128 columns: every bond cap the context accepts).
   if (qrm_fits(f)) {
     launch_qrm(f, st, q);
   } else if (panel <= (size_t)kQrLds) {
-    hipLaunchKernelGGL(k_qr<true>, dim3(f.items), dim3(kThreads), 0, st, q);
+    hipLaunchKernelGGL(k_qr, dim3(f.items), dim3(kThreads), 0, st, q);
   } else {
     if (!f.t1 || t1_stride(f) < panel)
       return hipErrorInvalidValue;  // global panel scratch missing or too small
-    if (f.K <= kQrgWaves * kQrgCols)
-      hipLaunchKernelGGL(k_qrg, dim3(f.items), dim3(kQrgThreads), 0, st, q);
-    else
-      hipLaunchKernelGGL(k_qr<false>, dim3(f.items), dim3(kThreads), 0, st, q);
+    if (f.K > kQrgWaves * kQrgCols) return hipErrorInvalidValue;  // bond caps are <= 128
+    hipLaunchKernelGGL(k_qrg, dim3(f.items), dim3(kQrgThreads), 0, st, q);
   }
   (void)panel;
   return hipGetLastError();
