@@ -105,13 +105,17 @@ bbp_status bbp_set_stream(bbp_ctx *c, void *hip_stream);
 
 /* Device memory through the caller's allocator instead of hipMalloc/hipFree
  * (for example PyTorch's caching allocator, which then accounts for it).
- * alloc(bytes, user) returns a device pointer, or NULL on failure (the call
- * that needed it then returns BBP_ENOMEM); free_(ptr, user) takes back a
- * pointer alloc returned.  The library synchronises its stream before it
- * hands memory back, so a stream-ordered allocator may reuse it at once.
+ * alloc(bytes, user) returns a device pointer, or NULL on failure;
+ * free_(ptr, user) takes back a pointer alloc returned.  The library
+ * synchronises its stream before it hands memory back, so a stream-ordered
+ * allocator may reuse it at once.
  * Both functions or neither (NULL, NULL: hipMalloc/hipFree); user is passed
  * through.  Must be called before bbp_set_tensors (BBP_ESTATE afterwards);
- * both functions must stay callable until bbp_destroy returns. */
+ * both functions must stay callable until bbp_destroy returns.
+ * Out of memory (either allocator): the context frees the device buffers it
+ * only keeps for reuse by later observable calls and tries the allocation
+ * once more; if that fails too, the call returns BBP_ENOMEM and the context
+ * stays usable. */
 typedef void *(*bbp_alloc_fn)(size_t bytes, void *user);
 typedef void (*bbp_free_fn)(void *ptr, void *user);
 bbp_status bbp_set_allocator(bbp_ctx *c, bbp_alloc_fn alloc, bbp_free_fn free_, void *user);
