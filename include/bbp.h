@@ -84,6 +84,11 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              stay FP64); QR, normalisation, overlaps and every stored
  *              message stay FP64.  Sweeps in 32 followed by sweeps in 64
  *              reach the FP64 fixed point from the FP32 one.
+ *   "graphs"   1 (default) or 0 (any time): once a message batch's column
+ *              absorptions all start warm (from the second sweep on), their
+ *              launches are captured as a HIP graph and replayed in later
+ *              sweeps; 0 launches them one by one.  Results do not depend
+ *              on it.  Not used while "timing" is 1.
  *   "lanes"    1..4 (default 3; before bbp_set_tensors): independent batches
  *              run on this many streams (the context stream and lanes-1
  *              streams the context creates) and overlap on the GPU: the

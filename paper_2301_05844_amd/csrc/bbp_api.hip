@@ -167,6 +167,17 @@ struct Group {
   std::vector<int32_t> flags;  // [W][items]
   DevBuf flagbuf;              // [W][items]
   int cache_gen = 0;           // observables call that last used this batch
+  // a message batch's column absorptions as a HIP graph, replayed in later
+  // sweeps while the launch sequence and its arguments stay the same
+  hipGraphExec_t graph = nullptr;
+  FitBatch graph_fb;  // the batch the graph was captured with
+  int graph_nfit = 0;
+  Group() = default;
+  Group(const Group &) = delete;
+  Group &operator=(const Group &) = delete;
+  ~Group() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
 };
 
 // Reduced density matrices of one region (block or union of two blocks)
@@ -192,10 +203,12 @@ struct bbp_ctx {
   int chi_env = -1, n_fit = 2;
   int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
   int lanes = 3;       // streams that independent fit batches spread over
+  int graphs = 1;      // 1: message batches replay their column absorptions as HIP graphs
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
   std::vector<hipEvent_t> lane_ev;  // fork event, then one join event per aux lane
+  hipStream_t cap = nullptr;        // stream HIP graphs are captured on (never run)
   bool tensors_set = false;
   bool device_ready = false;
   std::string err;
@@ -694,9 +707,19 @@ static double column_macs(const FitDims &f, const std::vector<int> &xb_bonds,
 // Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
 // each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
 // for the bond caps and the random-start flags.
-static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st) {
+static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
+                                  const std::vector<int> &any_rnd);
+static bool same_batch(const FitBatch &a, const FitBatch &b);
+
+// Absorbs columns W-1..col_lo of every item of the batch.  A message batch
+// (graph = true) whose columns all start warm has the same launch sequence,
+// with the same arguments, in every sweep: it is captured as a HIP graph
+// once and replayed, which removes the per-launch cost that bounds small
+// lattices.  Timing brackets (a process-wide switch) are not captured.
+static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
+                                 bool graph = false) {
   FitBatch &f = g.fb;
-  const int W = f.W, N = f.N;
+  const int W = f.W;
   hipError_t e;
   std::vector<int> any_rnd(W, 0);
   for (int i = 0; i < f.items; ++i)
@@ -705,80 +728,132 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t s
   e = hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
                      hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return c->hip_fail(e, "upload dims");
-    const size_t sN = (size_t)N * f.S, sWN = (size_t)W * N * f.S;
-    g.flags.assign((size_t)W * f.items, 0);
-    for (int col = 0; col < W; ++col)
-      for (int i = 0; i < f.items; ++i)
-        g.flags[(size_t)col * f.items + i] = g.dims[(size_t)i * W + col].rnd;
-    e = hipMemcpyAsync(g.flagbuf.p, g.flags.data(), 4 * g.flags.size(),
-                       hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return c->hip_fail(e, "upload flags");
-    for (int col = W - 1; col >= col_lo; --col) {
-      Ptr X = col == W - 1 ? Ptr{f.xin, sN}
-                           : Ptr{f.store + slot_store(f, col + 1, 0), sWN};
-      auto Xs = [&](int j) { return Ptr{X.p + (size_t)j * f.S, X.stride}; };
-      auto Ys = [&](int j) { return Ptr{f.store + slot_store(f, col, j), sWN}; };
-      auto Le = [&](int j) { return Ptr{f.lenv + (size_t)j * f.S, sN}; };
-      auto Re = [&](int j) { return Ptr{f.renv + (size_t)j * f.S, sN}; };
-      Ptr MT{f.mt + (size_t)col * f.S, (size_t)W * f.S};
-      Ptr MB{f.mb + (size_t)col * f.S, (size_t)W * f.S};
-      if (any_rnd[col]) {
-        f.flag = (int32_t *)g.flagbuf.p + (size_t)col * f.items;
-        if ((e = launch_rand_init(f, col, Ys(0), st)) != hipSuccess)
-          return c->hip_fail(e, "rand_init");
-        for (int j = N - 1; j >= 1; --j) {
-          e = launch_qr(f, col, j, j == N - 1 ? RL_BOT : RL_INNER, Ys(j), true,
-                        true, st);
-          if (e == hipSuccess) e = launch_apply_l(f, j - 1 == 0, Ys(j - 1), st);
-          if (e != hipSuccess) return c->hip_fail(e, "canonicalise");
-        }
+  g.flags.assign((size_t)W * f.items, 0);
+  for (int col = 0; col < W; ++col)
+    for (int i = 0; i < f.items; ++i)
+      g.flags[(size_t)col * f.items + i] = g.dims[(size_t)i * W + col].rnd;
+  e = hipMemcpyAsync(g.flagbuf.p, g.flags.data(), 4 * g.flags.size(),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return c->hip_fail(e, "upload flags");
+  bool warm = true;
+  for (int col = col_lo; col < W; ++col) warm = warm && !any_rnd[col];
+  if (!graph || !c->graphs || !warm || bbp::timing_enabled())
+    return enqueue_columns(c, g, col_lo, st, any_rnd);
+  if (g.graph && (g.graph_nfit != c->n_fit || !same_batch(g.graph_fb, f))) {
+    (void)hipGraphExecDestroy(g.graph);
+    g.graph = nullptr;
+  }
+  if (!g.graph) {
+    // captured on a stream of its own (the context stream may be the null
+    // stream, which cannot be captured); the graph is then launched on st
+    if (!c->cap && (e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking)) != hipSuccess)
+      return c->hip_fail(e, "capture stream");
+    hipGraph_t gr = nullptr;
+    if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return c->hip_fail(e, "begin capture");
+    bbp_status bs = enqueue_columns(c, g, col_lo, c->cap, any_rnd);
+    e = hipStreamEndCapture(c->cap, &gr);
+    if (bs != BBP_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return bs;
+    }
+    if (e != hipSuccess) return c->hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&g.graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+      g.graph = nullptr;
+      return c->hip_fail(e, "instantiate graph");
+    }
+    g.graph_fb = f;
+    g.graph_nfit = c->n_fit;
+  }
+  if ((e = hipGraphLaunch(g.graph, st)) != hipSuccess) return c->hip_fail(e, "graph launch");
+  return BBP_OK;
+}
+
+static bool same_batch(const FitBatch &a, const FitBatch &b) {
+  return a.items == b.items && a.tile_items == b.tile_items && a.K == b.K && a.P == b.P &&
+         a.D == b.D && a.d == b.d && a.H == b.H && a.W == b.W && a.N == b.N && a.S == b.S &&
+         a.store == b.store && a.xin == b.xin && a.mt == b.mt && a.mb == b.mb &&
+         a.lenv == b.lenv && a.renv == b.renv && a.t1 == b.t1 && a.t2 == b.t2 &&
+         a.t3 == b.t3 && a.tmp == b.tmp && a.acan == b.acan && a.abra == b.abra &&
+         a.rbuf == b.rbuf && a.nu == b.nu && a.flag == b.flag && a.err == b.err &&
+         a.dims == b.dims && a.slot == b.slot && a.seed == b.seed && a.prec == b.prec;
+}
+
+// The launches of absorb_columns, enqueued on st.
+static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
+                                  const std::vector<int> &any_rnd) {
+  FitBatch &f = g.fb;
+  const int W = f.W, N = f.N;
+  hipError_t e;
+  const size_t sN = (size_t)N * f.S, sWN = (size_t)W * N * f.S;
+  for (int col = W - 1; col >= col_lo; --col) {
+    Ptr X = col == W - 1 ? Ptr{f.xin, sN}
+                         : Ptr{f.store + slot_store(f, col + 1, 0), sWN};
+    auto Xs = [&](int j) { return Ptr{X.p + (size_t)j * f.S, X.stride}; };
+    auto Ys = [&](int j) { return Ptr{f.store + slot_store(f, col, j), sWN}; };
+    auto Le = [&](int j) { return Ptr{f.lenv + (size_t)j * f.S, sN}; };
+    auto Re = [&](int j) { return Ptr{f.renv + (size_t)j * f.S, sN}; };
+    Ptr MT{f.mt + (size_t)col * f.S, (size_t)W * f.S};
+    Ptr MB{f.mb + (size_t)col * f.S, (size_t)W * f.S};
+    if (any_rnd[col]) {
+      f.flag = (int32_t *)g.flagbuf.p + (size_t)col * f.items;
+      if ((e = launch_rand_init(f, col, Ys(0), st)) != hipSuccess)
+        return c->hip_fail(e, "rand_init");
+      for (int j = N - 1; j >= 1; --j) {
+        e = launch_qr(f, col, j, j == N - 1 ? RL_BOT : RL_INNER, Ys(j), true,
+                      true, st);
+        if (e == hipSuccess) e = launch_apply_l(f, j - 1 == 0, Ys(j - 1), st);
+        if (e != hipSuccess) return c->hip_fail(e, "canonicalise");
       }
-      if ((e = launch_set_unit(f, Le(0), st)) != hipSuccess ||
-          (e = launch_set_unit(f, Re(N - 1), st)) != hipSuccess)
-        return c->hip_fail(e, "set_unit");
+    }
+    if ((e = launch_set_unit(f, Le(0), st)) != hipSuccess ||
+        (e = launch_set_unit(f, Re(N - 1), st)) != hipSuccess)
+      return c->hip_fail(e, "set_unit");
+    for (int j = N - 1; j >= 1; --j) {
+      if (j == N - 1) {
+        e = launch_end_chain(f, true, MB, Xs(N - 1), st);
+        if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
+      } else {
+        e = launch_inner_chain(f, col, j, true, Xs(j), Re(j), st);
+        if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
+      }
+      if (e != hipSuccess) return c->hip_fail(e, "right environments");
+    }
+    for (int sw = 0; sw < c->n_fit; ++sw) {
+      for (int j = 0; j < N - 1; ++j) {
+        if (j == 0) {
+          e = launch_end_chain(f, false, MT, Xs(0), st);
+          if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
+          if (e == hipSuccess) e = launch_qr(f, col, 0, LR_TOP, Ys(0), false, false, st);
+          if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
+        } else {
+          e = launch_inner_visit(f, col, j, false, Xs(j), Le(j), Re(j), Ys(j), st);
+          if (e == hipSuccess) e = launch_qr(f, col, j, LR_INNER, Ys(j), false, false, st);
+          if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+        }
+        if (e != hipSuccess) return c->hip_fail(e, "left-to-right visit");
+      }
       for (int j = N - 1; j >= 1; --j) {
         if (j == N - 1) {
           e = launch_end_chain(f, true, MB, Xs(N - 1), st);
+          if (e == hipSuccess) e = launch_end_local(f, true, Le(N - 1), Ys(N - 1), st);
+          if (e == hipSuccess) e = launch_qr(f, col, N - 1, RL_BOT, Ys(N - 1), false, false, st);
           if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
         } else {
-          e = launch_inner_chain(f, col, j, true, Xs(j), Re(j), st);
+          e = launch_inner_visit(f, col, j, true, Xs(j), Re(j), Le(j), Ys(j), st);
+          if (e == hipSuccess) e = launch_qr(f, col, j, RL_INNER, Ys(j), false, false, st);
           if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
         }
-        if (e != hipSuccess) return c->hip_fail(e, "right environments");
+        if (e != hipSuccess) return c->hip_fail(e, "right-to-left visit");
       }
-      for (int sw = 0; sw < c->n_fit; ++sw) {
-        for (int j = 0; j < N - 1; ++j) {
-          if (j == 0) {
-            e = launch_end_chain(f, false, MT, Xs(0), st);
-            if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
-            if (e == hipSuccess) e = launch_qr(f, col, 0, LR_TOP, Ys(0), false, false, st);
-            if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
-          } else {
-            e = launch_inner_visit(f, col, j, false, Xs(j), Le(j), Re(j), Ys(j), st);
-            if (e == hipSuccess) e = launch_qr(f, col, j, LR_INNER, Ys(j), false, false, st);
-            if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
-          }
-          if (e != hipSuccess) return c->hip_fail(e, "left-to-right visit");
-        }
-        for (int j = N - 1; j >= 1; --j) {
-          if (j == N - 1) {
-            e = launch_end_chain(f, true, MB, Xs(N - 1), st);
-            if (e == hipSuccess) e = launch_end_local(f, true, Le(N - 1), Ys(N - 1), st);
-            if (e == hipSuccess) e = launch_qr(f, col, N - 1, RL_BOT, Ys(N - 1), false, false, st);
-            if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
-          } else {
-            e = launch_inner_visit(f, col, j, true, Xs(j), Re(j), Le(j), Ys(j), st);
-            if (e == hipSuccess) e = launch_qr(f, col, j, RL_INNER, Ys(j), false, false, st);
-            if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
-          }
-          if (e != hipSuccess) return c->hip_fail(e, "right-to-left visit");
-        }
-      }
-      e = launch_end_chain(f, false, MT, Xs(0), st);
-      if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
-      if (e == hipSuccess) e = launch_normalize(f, col, Ys(0), st);
-      if (e != hipSuccess) return c->hip_fail(e, "final visit");
     }
+    e = launch_end_chain(f, false, MT, Xs(0), st);
+    if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
+    if (e == hipSuccess) e = launch_normalize(f, col, Ys(0), st);
+    if (e != hipSuccess) return c->hip_fail(e, "final visit");
+  }
   return BBP_OK;
 }
 
@@ -865,7 +940,7 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
     e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
     if (e != hipSuccess) return c->hip_fail(e, "gather");
 
-    bbp_status bs = absorb_columns(c, g, 0, st);
+    bbp_status bs = absorb_columns(c, g, 0, st, true);
     if (bs != BBP_OK) return bs;
     e = launch_extract(f, (double *const *)g.dst.p, (const int32_t *)g.rev.p, st);
     if (e != hipSuccess) return c->hip_fail(e, "extract");
@@ -1739,7 +1814,8 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
 bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   if (!c || !key) return BBP_EINVAL;
   std::string k(key);
-  const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing" || k == "precision");
+  const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing" || k == "precision" ||
+                        k == "graphs");
   if (c->tensors_set && !late_ok)
     return c->fail(BBP_ESTATE, "option must be set before bbp_set_tensors");
   if (!std::isfinite(v)) return c->fail(BBP_EINVAL, "non-finite option value");
@@ -1764,6 +1840,9 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     c->precision = (int)v;
     for (auto &g : c->groups) g->fb.prec = c->precision;
     c->obs.clear();
+  } else if (k == "graphs") {
+    if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "graphs must be 0 or 1");
+    c->graphs = (int)v;
   } else if (k == "lanes") {
     if (v < 1 || v > 4 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "lanes must be an integer in [1,4]");
@@ -2137,6 +2216,7 @@ void bbp_destroy(bbp_ctx *c) {
     (void)hipStreamDestroy(s);
   }
   for (hipEvent_t ev : c->lane_ev) (void)hipEventDestroy(ev);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
 
