@@ -69,13 +69,17 @@ def test_options_and_state_checks():
         g.set_option("no_such_option", 1)
     assert e.value.status == 1
     for key, val in [("n_fit", 0), ("n_fit", 2.5), ("chi_env", 0),
-                     ("chi_env", 500), ("d", 0), ("seed", -1), ("precision", 16)]:
+                     ("chi_env", 500), ("d", 0), ("seed", -1), ("precision", 16),
+                     ("lanes", 0), ("lanes", 5), ("graphs", 2), ("graphs", 0.5)]:
         with pytest.raises(bbp.BBPError):
             g.set_option(key, val)
     g.set_option("n_fit", 3)
     g.set_option("chi_env", 20)
     g.set_option("precision", 32)
     g.set_option("precision", 64)
+    g.set_option("lanes", 1)
+    g.set_option("graphs", 0)
+    g.set_option("graphs", 1)
     with pytest.raises(bbp.BBPError) as e:
         g.sweep(1)
     assert e.value.status == 4  # BBP_ESTATE before the tensors
@@ -135,3 +139,22 @@ def test_bench_refuses_several_gpus():
                         "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_bench_lattice_terms():
+    # the sites and nearest-neighbour bonds a bench solve evaluates: every
+    # site and bond of a finite lattice; the unit cell and its right/down
+    # bonds on the infinite lattice
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from bbp_inputs import CONFIGS
+    sites, bonds = bench.lattice_terms(CONFIGS["obc16x16_D4_b4_chi32"])
+    assert len(sites) == 256 and len(bonds) == 2 * 16 * 15
+    assert len(set(map(tuple, sites.tolist()))) == 256
+    assert all(abs(x1 - x0) + abs(y1 - y0) == 1 for x0, y0, x1, y1 in bonds)
+    sites, bonds = bench.lattice_terms(CONFIGS["obc4x4_D2_b2_chi4"])
+    assert len(sites) == 16 and len(bonds) == 24
+    sites, bonds = bench.lattice_terms(CONFIGS["inf2x2_D4_b4_chi32"])
+    assert sorted(map(tuple, sites.tolist())) == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    assert len(bonds) == 8 and len(set(bonds)) == 8
