@@ -4,6 +4,11 @@
         kernel table (calls, average and total time) from a
         ``rocprofv3 --kernel-trace --stats --output-format csv`` run.
 
+    python -m paper_2301_05844_amd.profiling counters DIR [DIR ...] --kernels k_visit4p ... \
+        --title T --cmd C [--cmd C ...] > out.md
+        per-kernel averages of the counters of ``--pmc`` runs, with the MFMA
+        busy fraction and the LDS bank-conflict share where the counters allow.
+
     python -m paper_2301_05844_amd.profiling traffic --kernel k_visit \
         --kernel-class fit_visit --launches N --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \
         --copy-bytes B --out FILE.json
@@ -102,6 +107,69 @@ def counter_values(outdir, counter, kernel):
     return [per[k] for k in sorted(per)]
 
 
+def counter_table(dirs, kernels):
+    """Average per dispatch of every counter in the given --pmc runs, per
+    kernel (short name with template arguments) whose name starts with one
+    of `kernels`."""
+    acc = {}
+    for d in dirs:
+        rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
+        per = {}
+        for r in rows:
+            name = short_name(r["Kernel_Name"])
+            if not any(name.startswith(k) for k in kernels):
+                continue
+            key = (name, r["Counter_Name"], int(r["Dispatch_Id"]))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        for (name, counter, _), v in per.items():
+            s, n = acc.get((name, counter), (0.0, 0))
+            acc[(name, counter)] = (s + v, n + 1)
+    out = {}
+    for (name, counter), (s, n) in acc.items():
+        out.setdefault(name, {})[counter] = (s / n, n)
+    return out
+
+
+def gpu_agent(outdir):
+    """SIMD and XCD counts of the GPU agent of a run."""
+    for r in csv.DictReader(open(_one(os.path.join(outdir, "**", "*agent_info.csv")))):
+        if r["Agent_Type"].strip('"') == "GPU":
+            return int(r["Simd_Count"]), int(r["Num_Xcc"])
+    raise ValueError("no GPU agent in " + outdir)
+
+
+def counters_markdown(dirs, kernels, title, cmds):
+    """Counter averages per kernel, with the MFMA-busy fraction
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x SIMDs) (GRBM_GUI_ACTIVE
+    sums the busy clocks of every XCD) and the LDS bank-conflict share
+    SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE."""
+    tab = counter_table(dirs, kernels)
+    simds, xcds = gpu_agent(dirs[0])
+    counters = sorted({c for v in tab.values() for c in v})
+    lines = [f"# {title}", "", "Commands (from the repository root, on one MI355X):", "", "```"]
+    lines += list(cmds) + ["```", "",
+                           "Averages per dispatch over every dispatch of the run "
+                           f"(dispatches in parentheses); {simds} SIMDs in {xcds} XCDs.", ""]
+    names = sorted(tab, key=lambda n: -tab[n].get("GRBM_GUI_ACTIVE", (0, 0))[0])
+    for name in names:
+        v = tab[name]
+        lines.append(f"## `{name}`")
+        lines.append("")
+        lines.append("| counter | average per dispatch |")
+        lines.append("|---|---:|")
+        for c in counters:
+            if c in v:
+                lines.append(f"| {c} | {v[c][0]:.4g} ({v[c][1]}) |")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in v and "GRBM_GUI_ACTIVE" in v:
+            f = v["SQ_VALU_MFMA_BUSY_CYCLES"][0] / (v["GRBM_GUI_ACTIVE"][0] / xcds * simds)
+            lines.append(f"| MFMA busy (derived) | {100 * f:.1f}% |")
+        if "SQ_LDS_BANK_CONFLICT" in v and "SQ_LDS_IDX_ACTIVE" in v and v["SQ_LDS_IDX_ACTIVE"][0]:
+            f = v["SQ_LDS_BANK_CONFLICT"][0] / v["SQ_LDS_IDX_ACTIVE"][0]
+            lines.append(f"| LDS bank-conflict share (derived) | {100 * f:.1f}% |")
+        lines.append("")
+    return "\n".join(lines) + "\n"
+
+
 def traffic(kernel, kernel_class, launches, fetch, write, copy_fetch, copy_write, copy_bytes,
             copy_kernel):
     f = counter_values(fetch, "FETCH_SIZE", kernel)[-launches:]
@@ -136,8 +204,15 @@ def main(argv=None):
     c.add_argument("--launches", type=int, required=True)
     c.add_argument("--copy-bytes", type=float, required=True)
     c.add_argument("--copy-kernel", default="")
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernels", nargs="+", required=True)
+    k.add_argument("--title", required=True)
+    k.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args(argv)
-    if a.action == "trace":
+    if a.action == "counters":
+        sys.stdout.write(counters_markdown(a.dirs, a.kernels, a.title, a.cmd))
+    elif a.action == "trace":
         sys.stdout.write(trace_markdown(a.dir, a.title, a.cmd))
         if a.timed_kernel:
             us, n = last_dispatches_us(a.dir, a.timed_kernel, a.timed_launches)
