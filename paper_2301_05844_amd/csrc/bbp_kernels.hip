@@ -482,9 +482,10 @@ struct EnvArgs {
   Ptr Y, E;
 };
 
-// k parts per workgroup: two while the staged chunks stay small
+// k parts per workgroup: two up to 32 rows (MT <= 2); from MT = 3 one, which
+// leaves the registers for T3 two chunks ahead at MT = 3
 template <int MT> struct EnvShape {
-  static constexpr int KS = MT <= 3 ? 2 : 1;
+  static constexpr int KS = MT <= 2 ? 2 : 1;
   static constexpr int kThreads = 256 * KS;
   static constexpr int kWaves = KS == 2 ? 4 : 2;  // waves per SIMD the registers allow
 };
@@ -565,7 +566,7 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
 #pragma unroll
     for (int q = 0; q < NC; ++q) acc[mt][q] = Acc{0, 0, 0, 0};
   // T3 rows are fetched DB chunks ahead (two while the registers allow)
-  constexpr int DB = MT <= 2 ? 2 : 1;
+  constexpr int DB = MT <= 3 ? 2 : 1;
   T b0[8], b1[8];
   unsigned m0 = 0, m1 = 0;
   fetch_a(0);
