@@ -2009,7 +2009,13 @@ __global__ __launch_bounds__(kQrgThreads) void k_qrg(QrArgs q) {
 // ---------------------------------------------------------------------------
 
 constexpr int kQmRowCap = 768;        // rows held by one workgroup, at most
-constexpr int kQmVs = kQmRowCap + 4;   // stride of a V column in LDS
+// V column c of the block starts at c * kQmVs + (c & 14) doubles: with the
+// column stride 16 (mod 32) and that shift, both the per-lane column walk
+// (lane (lr, lc) reads column lc, rows 4s + lr) and the MFMA operand read
+// (column 4kk + lr, row lc) touch 32 distinct banks per half-wave, and the
+// per-lane part of every address stays a base plus compile-time offsets.
+constexpr int kQmVs = kQmRowCap + 16;
+__device__ __forceinline__ int qm_col(int c) { return c * kQmVs + (c & 14); }
 
 __device__ __forceinline__ double join_f64(int lo, int hi) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
@@ -2089,7 +2095,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
   }
   const int m = n1 * n2, n = min(ncol, m);
   double *base = q.Y.at(it);
-  __shared__ double VT[16][kQmVs];  // V of the current block, column-major
+  __shared__ double VT[16 * kQmVs];  // V of the current block, column c at qm_col(c)
   __shared__ double wred[NW][256];
   __shared__ double Ws[256], Zs[256];
   __shared__ double Tm[CT][16][16];
@@ -2122,7 +2128,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int row = rowof(t, s), pr = 16 * b + lc;
-        VT[lc][row] = lc < nbb ? ((t > 0 || row > pr) ? a[t][b][s] : (row == pr ? 1.0 : 0.0))
+        VT[qm_col(lc) + row] = lc < nbb ? ((t > 0 || row > pr) ? a[t][b][s] : (row == pr ? 1.0 : 0.0))
                                : 0.0;
       }
     wave_lds_order();
@@ -2148,7 +2154,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
-        c[t] = mfma16(VT[4 * kk + lr][16 * (wave + NW * t) + lc],
+        c[t] = mfma16(VT[qm_col(4 * kk + lr) + 16 * (wave + NW * t) + lc],
                       Zs[(4 * kk + lr) * 16 + lc], c[t]);
   };
 
@@ -2158,7 +2164,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
 #pragma unroll
     for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) xo[t][s] = VT[lc][16 * (wave + NW * t) + 4 * s + lr];
+      for (int s = 0; s < 4; ++s) xo[t][s] = VT[qm_col(lc) + 16 * (wave + NW * t) + 4 * s + lr];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       if (ct <= b || 16 * ct >= n) continue;
@@ -2283,7 +2289,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const double x = VT[lc][16 * (wave + NW * t) + 4 * s + lr];
+        const double x = VT[qm_col(lc) + 16 * (wave + NW * t) + 4 * s + lr];
         g[s & 1] = mfma16(x, x, g[s & 1]);
       }
     reduce_tiles(g[0] + g[1]);
@@ -2345,7 +2351,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
       const int p = tid >> 4, jj = tid & 15;
       double z = 0.0;
 #pragma unroll 4
-      for (int qq = 0; qq < 16; ++qq) z += Tm[b][p][qq] * VT[qq][b0 + jj];
+      for (int qq = 0; qq < 16; ++qq) z += Tm[b][p][qq] * VT[qm_col(qq) + b0 + jj];
       Zs[tid] = -z;
     }
     __syncthreads();
