@@ -1356,15 +1356,20 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit4(VisitArgs v) {
 // LDS: Fs [(ty, wf)][xf] (row stride pad_a_min(K4)); Xs [tx][xf][a] (rows
 // of 16, tile stride 16 K4 + 32 / TX); per pair T1 [wfk,akx][wfb,abx] and
 // T3 [wbk,wbb][lk,lb] (rows of 16); Gs [(tx, wb)][yb] (stride pad_b(K));
-// Ak, Ab [s][wf][a][l][wb].  Rows of Xs, T1, T3 and Gs are stored with their
-// column index XOR-ed by a function of the row (v4p_*_sw below), which
+// Ak, Ab [s][wf][a][l][wb].  Rows of Fs, Xs, T1, T3 and Gs are stored with
+// their column index XOR-ed by a function of the row (v4p_*_sw below), which
 // leaves every MFMA operand read conflict-free and also makes the accesses
 // that walk a column (the refill stores, the MFMA result stores, the T3 read
-// for the HBM store) hit distinct LDS banks.
+// for the HBM store) hit distinct LDS banks, for both a half wave over 32
+// 8-byte banks and a quarter wave over 16 (the F, T1 and T3 swizzles were
+// chosen to satisfy both).
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int v4p_x_sw(int xf) { return (xf >> 1) & 15; }
-__host__ __device__ constexpr int v4p_t1_sw(int k) { return ((k >> 1) & 1) << 3; }
-__host__ __device__ constexpr int v4p_t3_sw(int wb) { return ((wb << 1) & 12) | ((wb >> 2) & 2); }
+__host__ __device__ constexpr int v4p_t1_sw(int k) { return (k & 3) << 2; }
+__host__ __device__ constexpr int v4p_t3_sw(int wb) {
+  return ((wb & 3) << 2) ^ (((wb >> 2) & 1) * 5) ^ (((wb >> 3) & 1) << 1);
+}
+__host__ __device__ constexpr int v4p_f_sw(int row) { return (row >> 3) & 1; }
 __host__ __device__ constexpr int v4p_g_sw(int row) { return ((row >> 1) ^ ((row >> 4) << 2)) & 15; }
 __host__ __device__ constexpr int v4p_xt(int K4, int TX) { return 16 * K4 + 32 / TX; }
 template <class T>
@@ -1432,7 +1437,7 @@ void k_visit4p(VisitArgs v) {
   for (int row = wave; row < TY * 16; row += NWV) {
     const bool ok = y0 + (row >> 4) < K;
     for (int xf = lane; xf < K4; xf += 64)
-      Fs[row * FS + xf] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
+      Fs[row * FS + (xf ^ v4p_f_sw(row))] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
   }
   const int tne = KY >> 4;  // <= NE
   Acc accE[NE];
@@ -1514,7 +1519,7 @@ void k_visit4p(VisitArgs v) {
     // (a) T1 of the pair: rows wf, cols a, k = xf
     {
       Acc acc[2] = {zero, zero};
-      const T *pa = Fs + (ty * 16 + lr) * FS + lq;
+      const T *pa = Fs + (ty * 16 + lr) * FS + (lq ^ v4p_f_sw(lr));
       const T *px = Xs + tx * XT;
       // Xs row xf = k0 + lq (k0 = 0 mod 4): swizzle ((k0 >> 1) & 15) ^ (lq >> 1)
       const int xb0 = lq * 16 + (lr ^ (lq >> 1));
@@ -1589,9 +1594,9 @@ void k_visit4p(VisitArgs v) {
     }
     // (e) this pair's contribution to Yt[(ty, l)][yb]: k = wb of column tx
     if (v.do_local) {
-      // A: T3 row wb = 4i + lq, column lr: swizzle 4 (lq >> 1) ^ (8 (i & 1) | 2 (i >> 1));
+      // A: T3 row wb = 4i + lq, column lr: swizzle t3_sw(lq) ^ t3_sw(4i) (linear);
       // B: Gs row tx 16 + 4i + lq: swizzle w ^ (lq >> 1) ^ 2i, w from tx
-      const int ta = lq * 16 + (lr ^ ((lq >> 1) << 2));
+      const int ta = lq * 16 + (lr ^ v4p_t3_sw(lq));
       const int w = ((tx & 1) << 3) ^ ((tx << 2) & 15);
       const int gb = (tx * 16 + lq) * GS + (lr ^ w ^ (lq >> 1));
 #pragma unroll
@@ -1600,7 +1605,7 @@ void k_visit4p(VisitArgs v) {
         T av[4], bv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          av[i] = Tp[(ta ^ (((i & 1) << 3) | ((i >> 1) << 1))) + 64 * i];
+          av[i] = Tp[(ta ^ v4p_t3_sw(4 * i)) + 64 * i];
           bv[i] = Gs[(gb ^ (2 * i)) + 4 * i * GS + q * 16];
         }
         Acc acc[2] = {accE[q], zero};
