@@ -704,18 +704,17 @@ static double column_macs(const FitDims &f, const std::vector<int> &xb_bonds,
   return t;
 }
 
-// Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
-// each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
-// for the bond caps and the random-start flags.
 static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
                                   const std::vector<int> &any_rnd);
 static bool same_batch(const FitBatch &a, const FitBatch &b);
 
-// Absorbs columns W-1..col_lo of every item of the batch.  A message batch
+// Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
+// each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
+// for the bond caps and the random-start flags.  A message batch
 // (graph = true) whose columns all start warm has the same launch sequence,
 // with the same arguments, in every sweep: it is captured as a HIP graph
-// once and replayed, which removes the per-launch cost that bounds small
-// lattices.  Timing brackets (a process-wide switch) are not captured.
+// once and replayed, one launch instead of one per kernel.  Timing brackets
+// (a process-wide switch) are not captured.
 static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
                                  bool graph = false) {
   FitBatch &f = g.fb;
