@@ -18,6 +18,9 @@ from .gen import (  # noqa: F401
     peps_finite,
     peps_infinite,
     ising_peps,
+    peps_tiled,
+    peps_rotate,
+    peps_transpose,
     pauli,
     op_sz,
     op_sx,

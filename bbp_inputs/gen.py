@@ -130,3 +130,48 @@ CONFIGS = {
     "obc16x16_D6_b4_chi64": dict(infinite=False, Lx=16, Ly=16, bx=4, by=4, D=6,
                                  chi=64, tol=1e-10),
 }
+
+
+def peps_tiled(cell, ucx, ucy, Lx, Ly):
+    """Open ``Lx x Ly`` lattice tiled with the unit-cell tensors ``cell``
+    (``ucy*ucx`` tensors, row-major): site (x, y) takes cell tensor
+    ``(y % ucy, x % ucx)`` with every leg that points off the lattice
+    restricted to index 0 (the other entries set to zero)."""
+    cell = np.asarray(cell, dtype=np.float64)
+    A = np.zeros((Ly * Lx,) + cell.shape[1:])
+    for y in range(Ly):
+        for x in range(Lx):
+            t = cell[(y % ucy) * ucx + (x % ucx)].copy()
+            if y == 0:
+                t[:, 1:, :, :, :] = 0.0
+            if x == 0:
+                t[:, :, 1:, :, :] = 0.0
+            if y == Ly - 1:
+                t[:, :, :, 1:, :] = 0.0
+            if x == Lx - 1:
+                t[:, :, :, :, 1:] = 0.0
+            A[y * Lx + x] = t
+    return A
+
+
+def peps_rotate(A, Lx, Ly):
+    """The same network turned a quarter turn clockwise: an ``Ly x Lx``
+    lattice whose site (Ly-1-y, x) holds old site (x, y) with legs
+    (u, l, d, r) <- old (l, d, r, u).  Returns ``(B, Lx', Ly')``."""
+    A = np.asarray(A)
+    B = np.zeros_like(A)
+    for y in range(Ly):
+        for x in range(Lx):
+            B[x * Ly + (Ly - 1 - y)] = A[y * Lx + x].transpose(0, 2, 3, 4, 1)
+    return B, Ly, Lx
+
+
+def peps_transpose(A, Lx, Ly):
+    """Mirror image in the main diagonal: site (y, x) of an ``Ly x Lx``
+    lattice holds old site (x, y) with legs (u, l, d, r) <- old (l, u, r, d)."""
+    A = np.asarray(A)
+    B = np.zeros_like(A)
+    for y in range(Ly):
+        for x in range(Lx):
+            B[x * Ly + y] = A[y * Lx + x].transpose(0, 2, 1, 4, 3)
+    return B, Ly, Lx

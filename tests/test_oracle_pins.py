@@ -12,8 +12,13 @@ P1c  one loop (4x4 lattice, 2x2 blocks): a small, nonzero block-BP error.
 P2   D=1 product states: closed forms.
 P3   blocks of one site reduce to plain BP (Sec. II).
 P4   the fit's loss identity (App. A) and exactness when chi >= rank.
-P5   rescaling invariance and log-norm shift; gauge invariance (untruncated).
+P5   rescaling invariance and log-norm shift; gauge invariance, a quarter
+     turn and a mirror image of the lattice (untruncated cases).
 P6   ket<->bra symmetry of messages (real tensors, untruncated).
+P7   the fixed-point iteration converges: per-sweep observable changes
+     bounded by the residual, and below 1e-10 at the rounding floor.
+P8   the infinite lattice is the limit of finite tilings of its unit cell
+     (Sec. II iPEPS paragraph; App. E), which pins the self-message routing.
 Mutations planted in the oracle must make the pins fail.
 """
 
@@ -377,3 +382,176 @@ def test_ising_magnetisation_approaches_onsager():
     e2 = abs(_ising_infinite_m(0.6, 2, 4) - onsager(0.6))
     e4 = abs(_ising_infinite_m(0.6, 4, 8) - onsager(0.6))
     assert e4 < 1e-4 and e4 < 0.5 * e2
+
+
+# --- P5: lattice symmetries (untruncated loopy case) ---------------------------
+def _c1_observables(A, Lx, Ly):
+    bp = ob.BlockBP(A, D=2, chi=4, bx=2, by=2, Lx=Lx, Ly=Ly, chi_env=18)
+    bp.sweep(30)
+    sz = {(x, y): bp.expect_site(x, y, op_sz())
+          for y in range(Ly) for x in range(Lx)}
+    ss = {}
+    for y in range(Ly):
+        for x in range(Lx):
+            if x + 1 < Lx:
+                ss[frozenset({(x, y), (x + 1, y)})] = bp.expect_bond(
+                    x, y, x + 1, y, op_heis())
+            if y + 1 < Ly:
+                ss[frozenset({(x, y), (x, y + 1)})] = bp.expect_bond(
+                    x, y, x, y + 1, op_heis())
+    return sz, ss, bp.log_norm()[0]
+
+
+@pytest.mark.parametrize("how", ["rotate", "transpose"])
+def test_p5_rotation_and_transpose_invariance(how):
+    """The 4x4 lattice with 2x2 blocks is a loop of four blocks with chi and
+    chi_env above every exact rank: its block-BP fixed point is a property of
+    the network, so turning or mirroring the lattice permutes the observables
+    and keeps the log-norm (to rounding), although every message now runs
+    through other orientation code."""
+    from bbp_inputs import peps_rotate, peps_transpose
+    A = peps_finite(4, 4, 2, seed=7)
+    if how == "rotate":
+        B, Lx2, Ly2 = peps_rotate(A, 4, 4)
+        where = lambda x, y: (4 - 1 - y, x)
+    else:
+        B, Lx2, Ly2 = peps_transpose(A, 4, 4)
+        where = lambda x, y: (y, x)
+    sz, ss, lz = _c1_observables(A, 4, 4)
+    sz2, ss2, lz2 = _c1_observables(B, Lx2, Ly2)
+    for (x, y), v in sz.items():
+        assert abs(v - sz2[where(x, y)]) < TOL
+    for key, v in ss.items():
+        assert abs(v - ss2[frozenset(where(*p) for p in key)]) < TOL
+    assert abs(lz - lz2) < TOL
+
+
+def test_p5_infinite_rotation_invariance():
+    """An infinite lattice of an anisotropic 2x2 cell, one cell per block and
+    chi above the exact ranks: turning the cell a quarter turn permutes the
+    cell's observables."""
+    from bbp_inputs import peps_rotate
+    cell = peps_infinite(2, 2, 2, seed=11)
+    rot, _, _ = peps_rotate(cell, 2, 2)
+
+    def run(c):
+        bp = ob.BlockBP(c, D=2, chi=16, bx=2, by=2, infinite=True, ucx=2, ucy=2)
+        bp.sweep(12)
+        return bp
+    a, b = run(cell), run(rot)
+    for y in range(2):
+        for x in range(2):
+            xr, yr = 1 - y, x
+            assert abs(a.expect_site(x, y, op_sz()) - b.expect_site(xr, yr, op_sz())) < TOL
+            assert abs(a.expect_site(x, y, op_sx()) - b.expect_site(xr, yr, op_sx())) < TOL
+            # horizontal bond (x,y)-(x+1,y) becomes the vertical bond between
+            # (1-y, x) and (1-y, x+1)
+            assert abs(a.expect_bond(x, y, x + 1, y, op_szsz())
+                       - b.expect_bond(xr, yr, xr, yr + 1, op_szsz())) < TOL
+
+
+# --- P7: convergence of the fixed-point iteration -------------------------------
+@pytest.mark.parametrize("case", ["finite", "infinite"])
+def test_p7_extra_sweeps_converge(case):
+    """Truncated loopy cases: once the residual (a squared message distance)
+    is below 1e-10, the observables move by at most a small multiple of its
+    square root per sweep, and once it reaches the rounding floor one more
+    sweep moves every observable by less than 1e-10."""
+    if case == "finite":
+        A = peps_finite(8, 8, 2, seed=3)
+        bp = ob.BlockBP(A, D=2, chi=6, bx=4, by=4, Lx=8, Ly=8, chi_env=18)
+        sites = [(1, 1), (4, 3), (6, 6), (3, 5)]
+        bonds = [(3, 3, 4, 3), (5, 3, 5, 4), (1, 2, 2, 2)]
+    else:
+        A = peps_infinite(2, 2, 2, seed=11)
+        bp = ob.BlockBP(A, D=2, chi=6, bx=4, by=4, infinite=True, ucx=2, ucy=2)
+        sites = [(0, 0), (1, 0), (0, 1), (1, 1)]
+        bonds = [(0, 0, 1, 0), (1, 1, 1, 2), (0, 1, 1, 1)]
+
+    def obs():
+        bp._cache = {}
+        return np.array([bp.expect_site(x, y, op_sz()) for (x, y) in sites]
+                        + [bp.expect_bond(*b, op_heis()) for b in bonds])
+    r = bp.sweep()
+    n = 1
+    while r >= 1e-10:
+        r = bp.sweep()
+        n += 1
+        assert n < 30
+    o1 = obs()
+    bp.sweep()
+    o2 = obs()
+    assert np.abs(o2 - o1).max() < 10 * math.sqrt(r)
+    while r > 1e-15 and n < 40:
+        r = bp.sweep()
+        n += 1
+    o1 = obs()
+    bp.sweep()
+    assert np.abs(obs() - o1).max() < 1e-10
+
+
+# --- P8: the infinite lattice as the limit of finite tilings --------------------
+def _p8_gap(D, b, chi, sizes, seed=11):
+    """Largest difference, over the unit cell's <sigma_z>, <sigma_x> and
+    horizontal <sigma_z sigma_z>, between the infinite-lattice oracle and the
+    centre block of finite L x L tilings of the same anisotropic 2x2 cell."""
+    from bbp_inputs import peps_tiled
+    cell = peps_infinite(2, 2, D, seed=seed)
+    inf = ob.BlockBP(cell, D=D, chi=chi, bx=b, by=b, infinite=True, ucx=2, ucy=2)
+    for _ in range(40):
+        if inf.sweep() < 1e-15:
+            break
+    ox = (b - 2) // 2
+    gaps = []
+    for L in sizes:
+        fin = ob.BlockBP(peps_tiled(cell, 2, 2, L, L), D=D, chi=chi, bx=b, by=b,
+                         Lx=L, Ly=L)
+        for _ in range(40):
+            if fin.sweep() < 1e-15:
+                break
+        g = L // b
+        pos = lambda x: (g // 2) * b + ox + (x - ox) % 2  # cell coordinate x
+        gap = 0.0
+        for y in range(2):
+            for x in range(2):
+                for op in (op_sz(), op_sx()):
+                    gap = max(gap, abs(inf.expect_site(x, y, op)
+                                       - fin.expect_site(pos(x), pos(y), op)))
+                gap = max(gap, abs(inf.expect_bond(x, y, x + 1, y, op_szsz())
+                                   - fin.expect_bond(pos(x), pos(y), pos(x) + 1,
+                                                     pos(y), op_szsz())))
+        gaps.append(gap)
+    return gaps
+
+
+def test_p8_finite_tilings_approach_the_infinite_lattice():
+    """Sec. II (iPEPS: one block exchanging messages with its own copies) and
+    App. E: the centre block of growing finite tilings of an anisotropic 2x2
+    cell (no reflection symmetry, so the four self-messages all differ)
+    converges geometrically to the infinite-lattice values.  One cell per
+    block; chi above the exact ranks."""
+    gaps = _p8_gap(2, 2, 16, [6, 10, 14])
+    assert gaps[0] > gaps[1] * 20 > gaps[2] * 400
+    assert gaps[2] < 1e-7
+
+
+def test_p8_block_of_four_cells():
+    """The same limit for a 4x4 block holding four copies of the cell (the
+    block shape of the infinite workload), chi = 16 truncated nowhere."""
+    gaps = _p8_gap(2, 4, 16, [12])
+    assert gaps[0] < 1e-6
+
+
+def test_p8_catches_same_direction_routing(monkeypatch):
+    """Planted mistake: on the infinite lattice a block receives its own
+    message in the same direction instead of its neighbour's opposite one."""
+    orig = ob.BlockBP.incoming
+
+    def bad(self, bi, bj, side, msgs=None):
+        if not self.infinite:
+            return orig(self, bi, bj, side, msgs)
+        msgs = self.msgs if msgs is None else msgs
+        return msgs[(bi, bj, side)]
+    monkeypatch.setattr(ob.BlockBP, "incoming", bad)
+    assert _p8_gap(2, 2, 16, [14])[0] > 1e-4
+    assert _p8_gap(2, 4, 16, [12])[0] > 1e-5
