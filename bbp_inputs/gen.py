@@ -126,6 +126,10 @@ CONFIGS = {
     # 6x6 open lattice, D=6, 3x3 blocks, chi=6, chi_env=16, 2 sweeps (D=6 parity)
     "obc6x6_D6_b3_chi6": dict(infinite=False, Lx=6, Ly=6, bx=3, by=3, D=6, chi=6,
                               chi_env=16, sweeps=2),
+    # 8x8 open lattice, D=6, 4x4 blocks, chi=64, chi_env=82, 2 sweeps: the
+    # D=6 workload's bond caps (message fits at 64, observables at 82)
+    "obc8x8_D6_b4_chi64": dict(infinite=False, Lx=8, Ly=8, bx=4, by=4, D=6, chi=64,
+                               chi_env=82, sweeps=2),
     # 16x16 open lattice, D=6, 4x4 blocks, chi=64 (mixed-precision workload)
     "obc16x16_D6_b4_chi64": dict(infinite=False, Lx=16, Ly=16, bx=4, by=4, D=6,
                                  chi=64, tol=1e-10),

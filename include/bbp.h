@@ -89,6 +89,10 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              launches are captured as a HIP graph and replayed in later
  *              sweeps; 0 launches them one by one.  Results do not depend
  *              on it.  Not used while "timing" is 1.
+ *   "skip_padding" 1 (default) or 0 (any time): the column absorptions'
+ *              visit and environment kernels stop at every item's true bond
+ *              dimensions instead of the padded cap (the skipped terms are
+ *              zeros, so results are bitwise the same); 0 runs the padding.
  *   "lanes"    1..4 (default 3; before bbp_set_tensors): independent batches
  *              run on this many streams (the context stream and lanes-1
  *              streams the context creates) and overlap on the GPU: the
@@ -205,18 +209,30 @@ bbp_status bbp_stats(bbp_ctx *c, int32_t *n_messages, double *sweep_flops);
  * "timing" option is 1, summed over the process since the last reset: the
  * class name (static string), number of launches, total duration in ms
  * measured with HIP events on the stream the kernels were launched on, and
- * the algorithmic floating-point operations and HBM bytes (operands read
- * plus results written, once each) of those launches.  Synchronises the
- * recorded events.  Classes: fit_visit (the fused contractions of one fit
- * visit, App. A Eq. (update), on MFMA), fit_T1, fit_ket, fit_bra, fit_local
- * (the same contractions as separate kernels, used when the fused tiles do
- * not fit in LDS), fit_env (environment recursion of App. A), fit_end
- * (end-site contractions), qr (Householder QR/LQ), other.  Errors:
- * BBP_EINVAL for cls out of range.
+ * the algorithmic floating-point operations and HBM bytes of those launches:
+ * the split-layer contractions of App. A Eq. (update) and its environment
+ * recursion counted on every item's true bond dimensions, and the bytes of
+ * their operands read plus results written, once each (for a fit visit and
+ * its environment update together: Lenv, X, Renv, the site tensor, Yt, Y and
+ * the new environment).  The observables' final line contractions count at
+ * the bond cap chi_env.  Synchronises the recorded events.  Classes:
+ * fit_visit (the fused contractions of one fit visit on MFMA), fit_T1,
+ * fit_ket, fit_bra, fit_local (the same contractions as separate kernels,
+ * used when the fused tiles do not fit in LDS), fit_env (environment
+ * recursion of App. A), fit_end (end-site contractions), qr (Householder
+ * QR/LQ of the true panels), other.  Errors: BBP_EINVAL for cls out of
+ * range.
  */
 bbp_status bbp_kernel_stats(bbp_ctx *c, int32_t cls, const char **name,
                             int64_t *launches, double *ms, double *flops,
                             double *bytes);
+
+/* The same launches counted the way the kernels are shaped: every
+ * contraction at the padded bond cap K, and the bytes of the kernels' own
+ * data flow (padded operands and the intermediate T3 a fused visit hands to
+ * the environment update through HBM).  Errors as bbp_kernel_stats. */
+bbp_status bbp_kernel_stats_padded(bbp_ctx *c, int32_t cls, double *flops,
+                                   double *bytes);
 bbp_status bbp_kernel_stats_reset(bbp_ctx *c);
 
 /* Device bytes the context holds now and the most it has held (every

@@ -28,7 +28,7 @@ EXPORTS = (
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
     "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
     "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
-    "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
+    "bbp_kernel_stats_padded", "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
     "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
     "bbp_server_error", "bbp_server_destroy",
@@ -86,6 +86,7 @@ def _load():
         "bbp_stats": [P, ip, dp],
         "bbp_kernel_stats": [P, c_int, ctypes.POINTER(ctypes.c_char_p),
                              ctypes.POINTER(ctypes.c_int64), dp, dp, dp],
+        "bbp_kernel_stats_padded": [P, c_int, dp, dp],
         "bbp_kernel_stats_reset": [P],
         "bbp_memory": [P, ctypes.POINTER(c_size), ctypes.POINTER(c_size)],
         "bbp_server_estimate": [ctypes.POINTER(Request), ctypes.POINTER(c_size)],
@@ -275,17 +276,23 @@ class BlockBP:
 
     def kernel_stats(self):
         """Per-kernel-class launch statistics (``timing`` option): list of
-        dicts with name, launches, ms, flops, bytes."""
+        dicts with name, launches, ms, flops and bytes (true extents,
+        algorithmic), padded_flops and padded_bytes (bond cap, kernel data
+        flow)."""
         out = []
         for i in range(9):
             name = ctypes.c_char_p()
             n = ctypes.c_int64()
             ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            pf, pb = ctypes.c_double(), ctypes.c_double()
             self._check(_lib.bbp_kernel_stats(self._ctx, i, ctypes.byref(name),
                                               ctypes.byref(n), ctypes.byref(ms),
                                               ctypes.byref(fl), ctypes.byref(by)))
+            self._check(_lib.bbp_kernel_stats_padded(self._ctx, i, ctypes.byref(pf),
+                                                     ctypes.byref(pb)))
             out.append(dict(name=name.value.decode(), launches=n.value,
-                            ms=ms.value, flops=fl.value, bytes=by.value))
+                            ms=ms.value, flops=fl.value, bytes=by.value,
+                            padded_flops=pf.value, padded_bytes=pb.value))
         return out
 
     def kernel_stats_reset(self):

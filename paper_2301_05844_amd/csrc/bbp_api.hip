@@ -204,6 +204,7 @@ struct bbp_ctx {
   int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
   int lanes = 3;       // streams that independent fit batches spread over
   int graphs = 1;      // 1: message batches replay their column absorptions as HIP graphs
+  int skip_pad = 1;    // 1: the column absorptions' kernels stop at the true bond extents
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
@@ -365,6 +366,7 @@ void column_dims(int W, int H, int K, int P, const std::vector<int> &mt,
       f.bl[j] = j ? b[j - 1] : 1;
       f.br[j] = j < N - 1 ? b[j] : 1;
     }
+    for (int j = 0; j < N - 1; ++j) f.xb[j] = xb[j];
     xb = b;
   }
 }
@@ -724,6 +726,17 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t s
   for (int i = 0; i < f.items; ++i)
     for (int col = 0; col < W; ++col)
       any_rnd[col] |= g.dims[(size_t)i * W + col].rnd;
+  // the kernels that skip zero padding read the true extents (f.dims) only
+  // while the batch's dims describe what is being absorbed: during this call
+  struct TrueDims {
+    FitBatch &f;
+    ~TrueDims() {
+      f.hdims = nullptr;
+      f.bounded = 0;
+    }
+  } true_dims{f};
+  f.hdims = g.dims.data();
+  f.bounded = c->skip_pad;
   e = hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
                      hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return c->hip_fail(e, "upload dims");
@@ -777,7 +790,8 @@ static bool same_batch(const FitBatch &a, const FitBatch &b) {
          a.lenv == b.lenv && a.renv == b.renv && a.t1 == b.t1 && a.t2 == b.t2 &&
          a.t3 == b.t3 && a.tmp == b.tmp && a.acan == b.acan && a.abra == b.abra &&
          a.rbuf == b.rbuf && a.nu == b.nu && a.flag == b.flag && a.err == b.err &&
-         a.dims == b.dims && a.slot == b.slot && a.seed == b.seed && a.prec == b.prec;
+         a.dims == b.dims && a.slot == b.slot && a.seed == b.seed && a.prec == b.prec &&
+         a.bounded == b.bounded;
 }
 
 // The launches of absorb_columns, enqueued on st.
@@ -812,44 +826,44 @@ static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t 
       return c->hip_fail(e, "set_unit");
     for (int j = N - 1; j >= 1; --j) {
       if (j == N - 1) {
-        e = launch_end_chain(f, true, MB, Xs(N - 1), st);
-        if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
+        e = launch_end_chain(f, col, true, MB, Xs(N - 1), st);
+        if (e == hipSuccess) e = launch_end_env(f, col, true, Ys(N - 1), Re(N - 2), st);
       } else {
         e = launch_inner_chain(f, col, j, true, Xs(j), Re(j), st);
-        if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
+        if (e == hipSuccess) e = launch_inner_env(f, col, j, true, Ys(j), Re(j - 1), st);
       }
       if (e != hipSuccess) return c->hip_fail(e, "right environments");
     }
     for (int sw = 0; sw < c->n_fit; ++sw) {
       for (int j = 0; j < N - 1; ++j) {
         if (j == 0) {
-          e = launch_end_chain(f, false, MT, Xs(0), st);
-          if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
+          e = launch_end_chain(f, col, false, MT, Xs(0), st);
+          if (e == hipSuccess) e = launch_end_local(f, col, false, Re(0), Ys(0), st);
           if (e == hipSuccess) e = launch_qr(f, col, 0, LR_TOP, Ys(0), false, false, st);
-          if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
+          if (e == hipSuccess) e = launch_end_env(f, col, false, Ys(0), Le(1), st);
         } else {
           e = launch_inner_visit(f, col, j, false, Xs(j), Le(j), Re(j), Ys(j), st);
           if (e == hipSuccess) e = launch_qr(f, col, j, LR_INNER, Ys(j), false, false, st);
-          if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+          if (e == hipSuccess) e = launch_inner_env(f, col, j, false, Ys(j), Le(j + 1), st);
         }
         if (e != hipSuccess) return c->hip_fail(e, "left-to-right visit");
       }
       for (int j = N - 1; j >= 1; --j) {
         if (j == N - 1) {
-          e = launch_end_chain(f, true, MB, Xs(N - 1), st);
-          if (e == hipSuccess) e = launch_end_local(f, true, Le(N - 1), Ys(N - 1), st);
+          e = launch_end_chain(f, col, true, MB, Xs(N - 1), st);
+          if (e == hipSuccess) e = launch_end_local(f, col, true, Le(N - 1), Ys(N - 1), st);
           if (e == hipSuccess) e = launch_qr(f, col, N - 1, RL_BOT, Ys(N - 1), false, false, st);
-          if (e == hipSuccess) e = launch_end_env(f, true, Ys(N - 1), Re(N - 2), st);
+          if (e == hipSuccess) e = launch_end_env(f, col, true, Ys(N - 1), Re(N - 2), st);
         } else {
           e = launch_inner_visit(f, col, j, true, Xs(j), Re(j), Le(j), Ys(j), st);
           if (e == hipSuccess) e = launch_qr(f, col, j, RL_INNER, Ys(j), false, false, st);
-          if (e == hipSuccess) e = launch_inner_env(f, true, Ys(j), Re(j - 1), st);
+          if (e == hipSuccess) e = launch_inner_env(f, col, j, true, Ys(j), Re(j - 1), st);
         }
         if (e != hipSuccess) return c->hip_fail(e, "right-to-left visit");
       }
     }
-    e = launch_end_chain(f, false, MT, Xs(0), st);
-    if (e == hipSuccess) e = launch_end_local(f, false, Re(0), Ys(0), st);
+    e = launch_end_chain(f, col, false, MT, Xs(0), st);
+    if (e == hipSuccess) e = launch_end_local(f, col, false, Re(0), Ys(0), st);
     if (e == hipSuccess) e = launch_normalize(f, col, Ys(0), st);
     if (e != hipSuccess) return c->hip_fail(e, "final visit");
   }
@@ -1363,21 +1377,21 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       const hipStream_t sr = lane_stream(c, nl2 - 1);
       for (int j = 0; j < N - 1; ++j) {
         if (j == 0) {
-          e = launch_end_chain(f, false, MT, Xs(0), st);
-          if (e == hipSuccess) e = launch_end_env(f, false, Ys(0), Le(1), st);
+          e = launch_end_chain(f, 0, false, MT, Xs(0), st);
+          if (e == hipSuccess) e = launch_end_env(f, 0, false, Ys(0), Le(1), st);
         } else {
           e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), st);
-          if (e == hipSuccess) e = launch_inner_env(f, false, Ys(j), Le(j + 1), st);
+          if (e == hipSuccess) e = launch_inner_env(f, 0, j, false, Ys(j), Le(j + 1), st);
         }
         if (e != hipSuccess) return c->hip_fail(e, "line left environments");
       }
       for (int j = N - 1; j >= 1; --j) {
         if (j == N - 1) {
-          e = launch_end_chain(fr, true, MB, Xs(N - 1), sr);
-          if (e == hipSuccess) e = launch_end_env(fr, true, Ys(N - 1), Re(N - 2), sr);
+          e = launch_end_chain(fr, 0, true, MB, Xs(N - 1), sr);
+          if (e == hipSuccess) e = launch_end_env(fr, 0, true, Ys(N - 1), Re(N - 2), sr);
         } else {
           e = launch_inner_chain(fr, 0, j, true, Xs(j), Re(j), sr);
-          if (e == hipSuccess) e = launch_inner_env(fr, true, Ys(j), Re(j - 1), sr);
+          if (e == hipSuccess) e = launch_inner_env(fr, 0, j, true, Ys(j), Re(j - 1), sr);
         }
         if (e != hipSuccess) return c->hip_fail(e, "line right environments");
       }
@@ -1493,7 +1507,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         Ptr X{nullptr, 0, tp}, F{nullptr, 0, tp + n}, Y{nullptr, 0, tp + 2 * n};
         e = launch_inner_chain(fu, 0, 1, dir == 1, X, F, st);
         if (e == hipSuccess)
-          e = launch_inner_env(fu, dir == 1, Y, Ptr{outbuf[dir].d() + o * f.S, f.S},
+          e = launch_inner_env(fu, 0, 1, dir == 1, Y, Ptr{outbuf[dir].d() + o * f.S, f.S},
                                st);
         if (e != hipSuccess) return c->hip_fail(e, "unit steps");
       }
@@ -1814,7 +1828,7 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   if (!c || !key) return BBP_EINVAL;
   std::string k(key);
   const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing" || k == "precision" ||
-                        k == "graphs");
+                        k == "graphs" || k == "skip_padding");
   if (c->tensors_set && !late_ok)
     return c->fail(BBP_ESTATE, "option must be set before bbp_set_tensors");
   if (!std::isfinite(v)) return c->fail(BBP_EINVAL, "non-finite option value");
@@ -1842,6 +1856,9 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   } else if (k == "graphs") {
     if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "graphs must be 0 or 1");
     c->graphs = (int)v;
+  } else if (k == "skip_padding") {
+    if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "skip_padding must be 0 or 1");
+    c->skip_pad = (int)v;
   } else if (k == "lanes") {
     if (v < 1 || v > 4 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "lanes must be an integer in [1,4]");
@@ -2194,6 +2211,17 @@ bbp_status bbp_kernel_stats(bbp_ctx *c, int32_t cls, const char **name,
   hipError_t e = bbp::timing_query(cls, name, &n, ms, flops, bytes);
   if (e != hipSuccess) return c->hip_fail(e, "kernel timing");
   if (launches) *launches = n;
+  return BBP_OK;
+}
+
+bbp_status bbp_kernel_stats_padded(bbp_ctx *c, int32_t cls, double *flops,
+                                   double *bytes) {
+  if (!c) return BBP_EINVAL;
+  if (cls < 0 || cls >= bbp::KC_COUNT)
+    return c->fail(BBP_EINVAL, "kernel class out of range");
+  hipError_t e = bbp::timing_query(cls, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   flops, bytes);
+  if (e != hipSuccess) return c->hip_fail(e, "kernel timing");
   return BBP_OK;
 }
 

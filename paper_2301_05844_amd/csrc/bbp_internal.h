@@ -12,14 +12,34 @@ namespace bbp {
 constexpr int NMAX = 68;
 
 // Shapes of the fit result Y for one work item and one absorbed column:
-// site j of Y is (bl[j], p[j], br[j]) with bl[0] = br[N-1] = 1.
+// site j of Y is (bl[j], p[j], br[j]) with bl[0] = br[N-1] = 1.  xb[j]
+// (j = 0..N-2) is the bond j|j+1 of the boundary X the column is absorbed
+// into, so X site j is (j ? xb[j-1] : 1, ., j < N-1 ? xb[j] : 1).  Every
+// slot entry outside these true extents is zero.
 struct FitDims {
   int32_t bl[NMAX];
   int32_t br[NMAX];
   int32_t p[NMAX];
+  int32_t xb[NMAX];
   int32_t rnd;      // 1: start from the counter-based random state
   int32_t pad_[3];
 };
+
+// True extents of inner site j of one item in one visit direction: the
+// front/back bonds of Y (yf, yb) and of X (xf, xb), "front" being the side
+// the sweep comes from (left for LR, right for RL).
+struct SiteExt {
+  int yf, yb, xf, xb;
+};
+__host__ __device__ inline SiteExt site_ext(const FitDims &d, int j, int N, bool rl) {
+  const int xl = j ? d.xb[j - 1] : 1, xr = j < N - 1 ? d.xb[j] : 1;
+  SiteExt e;
+  e.yf = rl ? d.br[j] : d.bl[j];
+  e.yb = rl ? d.bl[j] : d.br[j];
+  e.xf = rl ? xr : xl;
+  e.xb = rl ? xl : xr;
+  return e;
+}
 
 // Device buffers of one batch of independent column absorptions ("items"),
 // all with the same boundary length N, width W and bond cap K.  Every MPS
@@ -50,6 +70,12 @@ struct FitBatch {
   int32_t *flag = nullptr;  // [items] per-item active flags
   int32_t *err = nullptr;   // [1] numeric error flag
   FitDims *dims = nullptr;  // [items][W]
+  // host copy of dims (same layout), read by the launchers only to count
+  // the floating-point operations and bytes of the true shapes
+  const FitDims *hdims = nullptr;
+  // 1: kernels that can read dims stop at the true extents (the padding
+  // they skip only ever adds zeros)
+  int bounded = 0;
   uint64_t *slot = nullptr; // [items] random-state slot base
   uint64_t seed = 0;
   int prec = 64;  // 64: FP64 contractions; 32: visit and environment update on FP32 MFMA
@@ -95,17 +121,17 @@ bool qr_needs_scratch(const FitBatch &f);
 hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
                               Ptr F, Ptr G, Ptr Y, hipStream_t st);
 // Yt = T3 . G  (local update), written into Y.
-hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
-                              hipStream_t st);
-// env' = Y . T3
-hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
-                            hipStream_t st);
+hipError_t launch_inner_local(const FitBatch &f, int c, int j, bool rl, Ptr G,
+                              Ptr Y, hipStream_t st);
+// env' = Y . T3 after the visit of site j of column c
+hipError_t launch_inner_env(const FitBatch &f, int c, int j, bool rl, Ptr Y,
+                            Ptr envOut, hipStream_t st);
 // End-site chain T = Mend . Xe (top corner in LR, bottom corner in RL).
-hipError_t launch_end_chain(const FitBatch &f, bool rl, Ptr Mend, Ptr Xe,
+hipError_t launch_end_chain(const FitBatch &f, int c, bool rl, Ptr Mend, Ptr Xe,
                             hipStream_t st);
-hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
+hipError_t launch_end_local(const FitBatch &f, int c, bool rl, Ptr G, Ptr Ye,
                             hipStream_t st);
-hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
+hipError_t launch_end_env(const FitBatch &f, int c, bool rl, Ptr Ye, Ptr envOut,
                           hipStream_t st);
 // Householder QR of the site panel (mode: VisitMode); Q replaces the panel.
 hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
@@ -176,7 +202,11 @@ void timing_enable(bool on);
 bool timing_enabled();
 void timing_reset();
 // Synchronises the recorded events and returns the totals of one class.
+// flops/bytes: the algorithmic counts on every item's true bond dimensions;
+// pflops/pbytes: the same contractions counted at the padded bond cap K and
+// the bytes the kernels' own data flow moves (padded operands, T3 spills).
 hipError_t timing_query(int cls, const char **name, long long *launches,
-                        double *ms, double *flops, double *bytes);
+                        double *ms, double *flops, double *bytes,
+                        double *pflops = nullptr, double *pbytes = nullptr);
 
 }  // namespace bbp

@@ -23,7 +23,7 @@ namespace {
 struct TimedLaunch {
   int cls;
   hipEvent_t a, b;
-  double flops, bytes;
+  double flops, bytes, pflops, pbytes;
 };
 // Launch timing is process-wide; its lists are guarded so contexts used from
 // several host threads (the request server) can time concurrently.
@@ -34,6 +34,7 @@ struct TimingState {
   std::vector<hipEvent_t> pool;
   long long launches[KC_COUNT] = {};
   double ms[KC_COUNT] = {}, flops[KC_COUNT] = {}, bytes[KC_COUNT] = {};
+  double pflops[KC_COUNT] = {}, pbytes[KC_COUNT] = {};
 };
 TimingState &timing() {
   static TimingState t;
@@ -65,19 +66,24 @@ hipError_t drain() {
     t.ms[l.cls] += ms;
     t.flops[l.cls] += l.flops;
     t.bytes[l.cls] += l.bytes;
+    t.pflops[l.cls] += l.pflops;
+    t.pbytes[l.cls] += l.pbytes;
     t.pool.push_back(l.a);
     t.pool.push_back(l.b);
   }
   t.done.clear();
   return hipSuccess;
 }
-// Brackets one launch with events when timing is on.
+// Brackets one launch with events when timing is on.  f, b: algorithmic
+// counts on the true extents; pf, pb: padded counts and the kernel's own
+// byte traffic (the same as f, b where a launch has no padding).
 struct Span {
   int cls;
   hipStream_t st;
-  double flops, bytes;
+  double flops, bytes, pflops, pbytes;
   hipEvent_t a = nullptr;
-  Span(int c, hipStream_t s, double f, double b) : cls(c), st(s), flops(f), bytes(b) {
+  Span(int c, hipStream_t s, double f, double b, double pf = -1.0, double pb = -1.0)
+      : cls(c), st(s), flops(f), bytes(b), pflops(pf < 0 ? f : pf), pbytes(pb < 0 ? b : pb) {
     if (!timing().on) return;
     std::lock_guard<std::recursive_mutex> lk(timing().mu);
     if (timing().done.size() > 4096) (void)drain();
@@ -89,7 +95,7 @@ struct Span {
     std::lock_guard<std::recursive_mutex> lk(timing().mu);
     hipEvent_t b = take_event();
     if (b && hipEventRecord(b, st) == hipSuccess)
-      timing().done.push_back(TimedLaunch{cls, a, b, flops, bytes});
+      timing().done.push_back(TimedLaunch{cls, a, b, flops, bytes, pflops, pbytes});
   }
 };
 const char *kClassNames[KC_COUNT] = {"fit_visit", "fit_T1",  "fit_ket",
@@ -105,11 +111,12 @@ void timing_reset() {
   (void)drain();
   for (int i = 0; i < KC_COUNT; ++i) {
     t.launches[i] = 0;
-    t.ms[i] = t.flops[i] = t.bytes[i] = 0.0;
+    t.ms[i] = t.flops[i] = t.bytes[i] = t.pflops[i] = t.pbytes[i] = 0.0;
   }
 }
 hipError_t timing_query(int cls, const char **name, long long *launches,
-                        double *ms, double *flops, double *bytes) {
+                        double *ms, double *flops, double *bytes, double *pflops,
+                        double *pbytes) {
   TimingState &t = timing();
   std::lock_guard<std::recursive_mutex> lk(t.mu);
   hipError_t e = drain();
@@ -119,6 +126,8 @@ hipError_t timing_query(int cls, const char **name, long long *launches,
   if (ms) *ms = t.ms[cls];
   if (flops) *flops = t.flops[cls];
   if (bytes) *bytes = t.bytes[cls];
+  if (pflops) *pflops = t.pflops[cls];
+  if (pbytes) *pbytes = t.pbytes[cls];
   return hipSuccess;
 }
 
@@ -480,6 +489,11 @@ struct EnvArgs {
   const double *t3;
   size_t t3s;
   Ptr Y, E;
+  // true extents of site j of column c (null: the full bond cap K): the k
+  // range stops at the true front bond of Y and the T3 columns past the
+  // true X bond are not read (the pair-per-wave visit does not write them)
+  const FitDims *dims;
+  int W, c, j, N;
 };
 
 // k parts per workgroup: two up to 32 rows (MT <= 2); from MT = 3 one, which
@@ -499,12 +513,33 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   constexpr int MW = MT * 16, AS = M::pad_b(MW), CH = 32 * KS;
   constexpr int NA = CH * MW / NT;  // A elements staged per thread
   __shared__ T As[2][CH][AS];
-  const int K = e.K, P = e.P, N = K * P, Kd = K * P;
+  const int K = e.K, P = e.P, N = K * P;
   int tile, it;
   xcd_tile_item(&tile, &it);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4, cg = wave & 3, h = wave >> 2;
   const int n = tile * 64 + cg * 16 + lr;
+  // k = (yf, l) runs to the true front bond of Y, columns n = (xb, wb) to the
+  // true X bond; past them every product is zero (Y padding) or T3 was not
+  // written, so they are skipped (or masked) without changing any sum.  E is
+  // still written in full (zeros in the padding).
+  int Kd = K * P, Nt = N;
+  if (e.dims) {
+    const SiteExt ex = site_ext(e.dims[(size_t)it * e.W + e.c], e.j, e.N, e.rl != 0);
+    Kd = ex.yf * P;
+    Nt = ex.xb * P;
+  }
+  if (tile * 64 >= Nt) {  // every column of the tile is padding
+    if (tid < 64 * 4) {
+      auto *Ez = gmem(e.E.at(it));
+      const int nz = tile * 64 + tid % 64;
+      if (nz < N) {
+        const int xb = nz / P, wb = nz - xb * P;
+        for (int m = tid / 64; m < K; m += 4) Ez[((size_t)m * P + wb) * K + xb] = 0.0;
+      }
+    }
+    return;
+  }
   // Y (K P K doubles) and this item's T3 (K P x K P) through buffer
   // descriptors; an element outside the operand loads offset 0 and is
   // replaced by zero
@@ -545,7 +580,7 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + h * 32 + 4 * i + lq;
-      const bool ok = n < N && k < Kd;
+      const bool ok = n < Nt && k < Kd;
       b[i] = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : 0u);
       bm |= (unsigned)ok << i;
     }
@@ -781,6 +816,10 @@ struct OpOv2 {  // E'[a][b] = sum_{b',q} U[b'][q][a] b_i[b'][q][b]
 struct VisitArgs {
   int K, P, D, d, TY, TX;
   int rl, do_local;
+  // true extents of site j of column c (null: the full bond cap K); only
+  // the pair-per-wave D = 4 kernel uses them to skip zero padding
+  const FitDims *dims;
+  int W, c, j, N;
   Ptr F, X, G, Y;
   const double *aket;
   size_t aket_stride;
@@ -1413,6 +1452,31 @@ void k_visit4p(VisitArgs v) {
   const int y0 = tile * TY;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lq = lane >> 4;
+  // True extents of this item's operands; every slot entry beyond them is
+  // zero, so tiles, xb steps, k blocks and local-update tiles past them
+  // would only add zeros: they are skipped, which leaves every sum's order
+  // over its nonzero terms, and so its bits, unchanged.  Y is still written
+  // in full (zeros in the padding).
+  int nyf = K, nyb = K, nxf = K, nxb = K;
+  if (v.dims) {
+    const SiteExt ex = site_ext(v.dims[(size_t)it * v.W + v.c], v.j, v.N, v.rl != 0);
+    nyf = ex.yf;
+    nyb = ex.yb;
+    nxf = ex.xf;
+    nxb = ex.xb;
+  }
+  if (y0 >= nyf) {  // every front bond of the tile is padding: Y rows are zero
+    if (v.do_local) {
+      auto *Yz = gmem(v.Y.at(it));
+      const int rows = min(TY, K - y0);
+      for (int i = tid; i < rows * P * K; i += NT) {
+        const int yb = i % K, l = (i / K) % P, yf = y0 + i / (K * P);
+        Yz[v.rl ? ((size_t)yb * P + l) * K + yf : ((size_t)yf * P + l) * K + yb] = 0.0;
+      }
+    }
+    return;
+  }
+  const int K4x = ceil4(nxf), tnb = ceil16(nyb) >> 4;
   T *Fs = sm;
   T *Xs = Fs + TY * 16 * FS;
   T *T13s = Xs + TX * XT;
@@ -1435,9 +1499,9 @@ void k_visit4p(VisitArgs v) {
     Ab[i] = (T)ab[src];
   }
   for (int row = wave; row < TY * 16; row += NWV) {
-    const bool ok = y0 + (row >> 4) < K;
+    const bool ok = y0 + (row >> 4) < nyf;
     for (int xf = lane; xf < K4; xf += 64)
-      Fs[row * FS + (xf ^ v4p_f_sw(row))] = (T)((ok && xf < K) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
+      Fs[row * FS + (xf ^ v4p_f_sw(row))] = (T)((ok && xf < nxf) ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
   }
   const int tne = KY >> 4;  // <= NE
   Acc accE[NE];
@@ -1484,7 +1548,7 @@ void k_visit4p(VisitArgs v) {
     for (int u = 0; u < LD; ++u) {
       int txx, a, xf;
       xdec(u, txx, a, xf);
-      const bool xv = tid + u * NT < NX && xf < K && x0 + txx < K;
+      const bool xv = tid + u * NT < NX && xf < nxf && x0 + txx < nxb;
       const unsigned off = rl ? ((x0 + txx) * P + a) * K + xf : (xf * P + a) * K + x0 + txx;
       xr[u] = buf_ld(xrs, xv ? off * 8u : 0u);
       xm |= (unsigned)xv << u;
@@ -1494,7 +1558,7 @@ void k_visit4p(VisitArgs v) {
       for (int u = 0; u < LD; ++u) {
         int gtx, wb, yb;
         gdec(u, gtx, wb, yb);
-        const bool gv = tid + u * NT < NX && yb < K && x0 + gtx < K;
+        const bool gv = tid + u * NT < NX && yb < nyb && x0 + gtx < nxb;
         gr[u] = buf_ld(grs, gv ? ((yb * P + wb) * K + x0 + gtx) * 8u : 0u);
         gm |= (unsigned)gv << u;
       }
@@ -1502,7 +1566,7 @@ void k_visit4p(VisitArgs v) {
   };
   fetch(0);
 
-  for (int x0 = 0; x0 < K; x0 += TX) {
+  for (int x0 = 0; x0 < nxb; x0 += TX) {
     __syncthreads();  // the previous step's readers of Xs, Gs and T3 are done
 #pragma unroll
     for (int u = 0; u < LD; ++u) {  // rows up to K4 and K rows of G (zero where not real)
@@ -1515,7 +1579,7 @@ void k_visit4p(VisitArgs v) {
       if (yb < KY) Gs[grow * GS + (yb ^ v4p_g_sw(grow))] = (T)(((gm >> u) & 1) ? gr[u] : 0.0);
     }
     __syncthreads();
-    if (x0 + TX < K) fetch(x0 + TX);
+    if (x0 + TX < nxb) fetch(x0 + TX);
     // (a) T1 of the pair: rows wf, cols a, k = xf
     {
       Acc acc[2] = {zero, zero};
@@ -1524,7 +1588,7 @@ void k_visit4p(VisitArgs v) {
       // Xs row xf = k0 + lq (k0 = 0 mod 4): swizzle ((k0 >> 1) & 15) ^ (lq >> 1)
       const int xb0 = lq * 16 + (lr ^ (lq >> 1));
       int k0 = 0;
-      for (; k0 + 16 <= K4; k0 += 16) {
+      for (; k0 + 16 <= K4x; k0 += 16) {
         const T *pk = px + k0 * 16;
         const int sw = (k0 >> 1) & 8;
         T av[4], bv[4];
@@ -1536,7 +1600,7 @@ void k_visit4p(VisitArgs v) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i & 1] = M::run(av[i], bv[i], acc[i & 1]);
       }
-      for (; k0 < K4; k0 += 4)
+      for (; k0 < K4x; k0 += 4)
         acc[0] = M::run(pa[k0], px[k0 * 16 + (xb0 ^ ((k0 >> 1) & 15))], acc[0]);
       const Acc c = acc[0] + acc[1];
       // a = lr (akx = lr/4, abx = lr%4), wf = (wfk, wfb): row (wfk, akx),
@@ -1584,7 +1648,7 @@ void k_visit4p(VisitArgs v) {
     // T3 of the pair to HBM as T3[yf][l][xb][wb] (16 lanes per 128-byte row)
     {
       const int yf = y0 + ty, xb = x0 + tx;
-      if (yf < K && xb < K) {
+      if (yf < nyf && xb < nxb) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int idx = u * 64 + lane, wb = idx & 15, l = idx >> 4;
@@ -1601,7 +1665,7 @@ void k_visit4p(VisitArgs v) {
       const int gb = (tx * 16 + lq) * GS + (lr ^ w ^ (lq >> 1));
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
-        if (q >= tne) break;
+        if (q >= tnb) break;
         T av[4], bv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -2702,6 +2766,79 @@ static bool visit_f32(const FitBatch &f) {
   return f.prec == 32 && f.K <= 64 && visit4_tiles<float>(f, &TY, &TX, &lds);
 }
 
+// ---- algorithmic counts on the true extents (timing only) -----------------
+// Floating-point operations and operand bytes of the split-layer
+// contractions of one launch, summed over its items with each item's true
+// bonds (f.hdims, present for the column absorptions).  Launches without
+// them (the observables' line sandwiches) count at the bond cap.
+enum : int { TC_T1 = 1, TC_KET = 2, TC_BRA = 4, TC_LOCAL = 8, TC_ENV = 16 };
+struct Count {
+  double flops = 0.0, bytes = 0.0;
+};
+static Count count_inner(const FitBatch &f, int c, int j, bool rl, int parts) {
+  Count t;
+  if (!timing_enabled()) return t;
+  const double P = f.P, d = f.d;
+  for (int i = 0; i < f.items; ++i) {
+    double yf = f.K, yb = f.K, xf = f.K, xb = f.K;
+    if (f.hdims) {
+      const SiteExt e = site_ext(f.hdims[(size_t)i * f.W + c], j, f.N, rl);
+      yf = e.yf, yb = e.yb, xf = e.xf, xb = e.xb;
+    }
+    double m = 0.0, b = 0.0;  // multiply-adds, doubles moved
+    if (parts & TC_T1) m += yf * P * xf * P * xb, b += yf * P * xf + xf * P * xb;
+    if (parts & TC_KET) m += yf * xb * d * P * P * P, b += d * P * P;
+    if (parts & TC_BRA) m += yf * xb * d * P * P * P;
+    if (parts & TC_LOCAL) m += yf * P * xb * P * yb, b += yb * P * xb + yf * P * yb;
+    if (parts & TC_ENV) m += yb * P * xb * yf * P, b += yf * P * yb + yb * P * xb;
+    t.flops += 2.0 * m;
+    t.bytes += 8.0 * b;
+  }
+  return t;
+}
+// End site (0 in LR, N-1 in RL): the message site of the column as an MPO
+// Mend[a][q][a'] against the X corner [a'][xe]; parts 1 chain, 2 local, 4 env.
+static Count count_end(const FitBatch &f, int c, bool rl, int parts) {
+  Count t;
+  if (!timing_enabled()) return t;
+  const double P = f.P;
+  for (int i = 0; i < f.items; ++i) {
+    double a = f.K, ap = f.K, xe = f.K, ye = f.K;
+    if (f.hdims) {
+      const FitDims &d = f.hdims[(size_t)i * f.W + c];
+      const int j = rl ? f.N - 1 : 0;
+      a = d.p[j];
+      ap = c == f.W - 1 ? 1 : f.hdims[(size_t)i * f.W + c + 1].p[j];
+      xe = rl ? d.xb[f.N - 2] : d.xb[0];
+      ye = rl ? d.bl[f.N - 1] : d.br[0];
+    }
+    double m = 0.0, b = 0.0;
+    if (parts & 1) m += a * P * ap * xe, b += a * P * ap + ap * xe;
+    if (parts & 2) m += a * P * xe * ye, b += ye * P * xe + a * ye;
+    if (parts & 4) m += ye * a * P * xe, b += a * ye + ye * P * xe;
+    t.flops += 2.0 * m;
+    t.bytes += 8.0 * b;
+  }
+  return t;
+}
+// Householder QR/LQ of the true panels: 4 m n^2 - 4 n^3 / 3 (R and Q).
+static Count count_qr(const FitBatch &f, int c, int j, int mode) {
+  Count t;
+  if (!timing_enabled()) return t;
+  for (int i = 0; i < f.items; ++i) {
+    double m = (double)f.K * f.P, n = f.K;
+    if (f.hdims) {
+      const FitDims &d = f.hdims[(size_t)i * f.W + c];
+      const bool lr = mode == LR_INNER || mode == LR_TOP;
+      m = (double)(lr ? d.bl[j] : d.br[j]) * d.p[j];
+      n = lr ? d.br[j] : d.bl[j];
+    }
+    t.flops += 4.0 * m * n * n - 4.0 * n * n * n / 3.0;
+    t.bytes += 16.0 * m * n;
+  }
+  return t;
+}
+
 static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
                                Ptr F, Ptr G, Ptr Y, bool do_local, int TY,
                                int TX, size_t lds, hipStream_t st) {
@@ -2748,6 +2885,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   v.abra_stride = a_stride(f);
   v.t3 = f.t3;
   v.t3_stride = t1_stride(f);
+  v.dims = nullptr;
+  v.W = f.W; v.c = c; v.j = j; v.N = f.N;
   const double it = f.items, K = f.K, P = f.P, d = f.d;
   double flops = it * (2 * K * K * K * P * P + 4 * d * K * K * P * P * P);
   double bytes = it * 8 * (2 * K * P * K + K * K * P * P + 2 * d * P * P);
@@ -2755,14 +2894,16 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     flops += it * 2 * K * K * K * P * P;
     bytes += it * 8 * 2 * K * P * K;
   }
-  Span sp(KC_VISIT, st, flops, bytes);
+  const Count tc = count_inner(f, c, j, rl, TC_T1 | TC_KET | TC_BRA | (do_local ? TC_LOCAL : 0));
+  Span sp(KC_VISIT, st, tc.flops, tc.bytes, flops, bytes);
   int TYp, TXp;
   size_t ldsp;
   const bool pairw = f32 ? visit4p_tiles<float>(f, &TYp, &TXp, &ldsp)
                          : visit4p_tiles<double>(f, &TYp, &TXp, &ldsp);
-  if (pairw) {  // one (yf, xb) pair per wave
+  if (pairw) {  // one (yf, xb) pair per wave; skips the zero padding
     v.TY = TYp;
     v.TX = TXp;
+    v.dims = f.bounded && f.hdims ? f.dims : nullptr;
     const int ne = visit4p_ne(f.K);
     hipLaunchKernelGGL(f32 ? visit4p_kernel<float>(ne, TYp) : visit4p_kernel<double>(ne, TYp),
                        dim3((f.K + TYp - 1) / TYp, f.items), dim3(64 * TYp * TXp), ldsp, st, v);
@@ -2823,7 +2964,7 @@ hipError_t launch_inner_visit(const FitBatch &f, int c, int j, bool rl, Ptr X,
   if (TY > 0) return launch_fused(f, c, j, rl, X, F, G, Y, true, TY, TX, lds, st);
   hipError_t e = launch_inner_chain_generic(f, c, j, rl, X, F, st);
   if (e != hipSuccess) return e;
-  return launch_inner_local(f, rl, G, Y, st);
+  return launch_inner_local(f, c, j, rl, G, Y, st);
 }
 
 hipError_t launch_inner_chain(const FitBatch &f, int c, int j, bool rl, Ptr X,
@@ -2847,7 +2988,8 @@ hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
   OpK1 k1{f.K * f.P, f.P * f.K, f.K, nullptr, s, rl, X, F, f.t1, t1s};
   hipError_t e;
   {
-    Span sp(KC_T1, st, it * 2 * K * P * P * K * K,
+    const Count tc = count_inner(f, c, j, rl, TC_T1);
+    Span sp(KC_T1, st, tc.flops, tc.bytes, it * 2 * K * P * P * K * K,
             it * 8 * (2 * K * P * K + K * K * P * P));
     e = run_gemm<64, 64, 16>(k1, f.items, st);
   }
@@ -2855,35 +2997,40 @@ hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
   OpK2 k2{f.K * f.P * f.K, f.d * f.P, f.P, nullptr, s, rl, f.t1, t1s, Ak,
           a_stride(f), f.t2, t2s};
   {
-    Span sp(KC_KET, st, it * 2 * K * P * K * d * P * P,
+    const Count tc = count_inner(f, c, j, rl, TC_KET);
+    Span sp(KC_KET, st, tc.flops, tc.bytes, it * 2 * K * P * K * d * P * P,
             it * 8 * (K * K * P * P + d * P * P + d * K * K * P * P));
     e = run_gemm<128, 32, 16>(k2, f.items, st);
   }
   if (e != hipSuccess) return e;
   OpK3 k3{f.K * f.K * f.P, f.P, f.d * f.P, nullptr, s, rl, f.t2, t2s, Ab,
           a_stride(f), f.t3, t3s};
-  Span sp(KC_BRA, st, it * 2 * K * K * P * P * d * P,
+  const Count tc = count_inner(f, c, j, rl, TC_BRA);
+  Span sp(KC_BRA, st, tc.flops, tc.bytes, it * 2 * K * K * P * P * d * P,
           it * 8 * (d * K * K * P * P + d * P * P + K * K * P * P));
   return run_gemm<256, 16, 16>(k3, f.items, st);
 }
 
-hipError_t launch_inner_local(const FitBatch &f, bool rl, Ptr G, Ptr Y,
+hipError_t launch_inner_local(const FitBatch &f, int c, int j, bool rl, Ptr G, Ptr Y,
                               hipStream_t st) {
   OpK4 k4{f.K * f.P, f.K, f.K * f.P, nullptr, shape_of(f), rl, f.t3,
           t1_stride(f), G, Y};
   const double it = f.items, K = f.K, P = f.P;
-  Span sp(KC_LOCAL, st, it * 2 * K * P * K * K * P,
+  const Count tc = count_inner(f, c, j, rl, TC_LOCAL);
+  Span sp(KC_LOCAL, st, tc.flops, tc.bytes, it * 2 * K * P * K * K * P,
           it * 8 * (K * K * P * P + 2 * K * P * K));
   return run_gemm<64, 32, 16>(k4, f.items, st);
 }
 
-hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
-                            hipStream_t st) {
+hipError_t launch_inner_env(const FitBatch &f, int c, int j, bool rl, Ptr Y,
+                            Ptr envOut, hipStream_t st) {
   const double it = f.items, K = f.K, P = f.P;
-  Span sp(KC_ENV, st, it * 2 * K * K * P * K * P,
+  const Count tc = count_inner(f, c, j, rl, TC_ENV);
+  Span sp(KC_ENV, st, tc.flops, tc.bytes, it * 2 * K * K * P * K * P,
           it * 8 * (K * K * P * P + 2 * K * P * K));
   if (f.K <= 64) {
-    EnvArgs e{f.K, f.P, rl ? 1 : 0, f.t3, t1_stride(f), Y, envOut};
+    EnvArgs e{f.K, f.P, rl ? 1 : 0, f.t3, t1_stride(f), Y, envOut,
+              f.bounded && f.hdims ? f.dims : nullptr, f.W, c, j, f.N};
     const dim3 grid((f.K * f.P + 63) / 64, f.items);
     const int mt = (f.K + 15) / 16;
     // FP32 only where the visit wrote FP32 T3 (the specialised D = 4 kernel)
@@ -2905,30 +3052,36 @@ hipError_t launch_inner_env(const FitBatch &f, bool rl, Ptr Y, Ptr envOut,
   return run_gemm<32, 64, 16>(k5, f.items, st);
 }
 
-hipError_t launch_end_chain(const FitBatch &f, bool rl, Ptr Mend, Ptr Xe,
+hipError_t launch_end_chain(const FitBatch &f, int c, bool rl, Ptr Mend, Ptr Xe,
                             hipStream_t st) {
   OpE1 e1{f.K * f.P, f.K, f.K, nullptr, shape_of(f), rl, Mend, Xe, f.t3,
           t1_stride(f)};
   const double it = f.items, K = f.K, P = f.P;
-  Span sp(KC_END, st, it * 2 * K * P * K * K, it * 8 * (2 * K * P * K + K * K));
+  const Count tc = count_end(f, c, rl, 1);
+  Span sp(KC_END, st, tc.flops, tc.bytes, it * 2 * K * P * K * K,
+          it * 8 * (2 * K * P * K + K * K));
   return run_gemm<64, 32, 16>(e1, f.items, st);
 }
 
-hipError_t launch_end_local(const FitBatch &f, bool rl, Ptr G, Ptr Ye,
+hipError_t launch_end_local(const FitBatch &f, int c, bool rl, Ptr G, Ptr Ye,
                             hipStream_t st) {
   OpE2 e2{f.K, f.K, f.P * f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
           G, Ye};
   const double it = f.items, K = f.K, P = f.P;
-  Span sp(KC_END, st, it * 2 * K * K * P * K, it * 8 * (2 * K * P * K + K * K));
+  const Count tc = count_end(f, c, rl, 2);
+  Span sp(KC_END, st, tc.flops, tc.bytes, it * 2 * K * K * P * K,
+          it * 8 * (2 * K * P * K + K * K));
   return run_gemm<32, 32, 64>(e2, f.items, st);  // one 32x32 tile, K P long
 }
 
-hipError_t launch_end_env(const FitBatch &f, bool rl, Ptr Ye, Ptr envOut,
+hipError_t launch_end_env(const FitBatch &f, int c, bool rl, Ptr Ye, Ptr envOut,
                           hipStream_t st) {
   OpE3 e3{f.K, f.P * f.K, f.K, nullptr, shape_of(f), rl, f.t3, t1_stride(f),
           Ye, envOut};
   const double it = f.items, K = f.K, P = f.P;
-  Span sp(KC_END, st, it * 2 * K * P * K * K, it * 8 * (2 * K * P * K + K * K));
+  const Count tc = count_end(f, c, rl, 4);
+  Span sp(KC_END, st, tc.flops, tc.bytes, it * 2 * K * P * K * K,
+          it * 8 * (2 * K * P * K + K * K));
   return run_gemm<32, 64, 16>(e3, f.items, st);
 }
 
@@ -2938,7 +3091,8 @@ hipError_t launch_qr(const FitBatch &f, int c, int j, int mode, Ptr Y,
            only_flagged ? f.flag : nullptr, want_r ? 1 : 0};
   const size_t panel = (size_t)f.K * f.P * f.K;  // upper bound of m*n
   const double m = (double)f.K * f.P, n = f.K;
-  Span sp(KC_QR, st, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
+  const Count tc = count_qr(f, c, j, mode);
+  Span sp(KC_QR, st, tc.flops, tc.bytes, f.items * (4.0 * m * n * n - 4.0 * n * n * n / 3.0),
           f.items * 16.0 * m * n);
   // The blocked MFMA kernel for panels up to 768 x 48 (every shape of the
   // D <= 4 workloads); otherwise the LDS kernel, or the 16-wave global-memory
