@@ -93,6 +93,10 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              visit and environment kernels stop at every item's true bond
  *              dimensions instead of the padded cap (the skipped terms are
  *              zeros, so results are bitwise the same); 0 runs the padding.
+ *   "message_split" 1..4 (default 2; before bbp_set_tensors): the messages
+ *              of one shape are updated as this many batches (of at least 8
+ *              messages each), one per lane, so that one batch's QRs overlap
+ *              another's visits.  Results do not depend on it.
  *   "lanes"    1..4 (default 3; before bbp_set_tensors): independent batches
  *              run on this many streams (the context stream and lanes-1
  *              streams the context creates) and overlap on the GPU: the

@@ -47,3 +47,18 @@ def test_lanes_option_validation():
     for bad in (0, 5, 1.5):
         with pytest.raises(bbp.BBPError):
             bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4, lanes=bad)
+
+
+@pytest.mark.parametrize("split", [2, 3])
+def test_message_split_bitwise_equal(split):
+    # 8x8 lattice with 2x2 blocks, D=3: the 48 messages of one shape split
+    # into `split` batches on their own lanes
+    from paper_2301_05844_amd import bbp
+    A = peps_finite(8, 8, 3, seed=6)
+    one = _run(3, A, 8, 8, 2, 2, 3, 9, 3)
+    ctx_kw = dict(message_split=split)
+    ctx = bbp.BlockBP(Lx=8, Ly=8, bx=2, by=2, D=3, chi=9, lanes=3, **ctx_kw)
+    ctx.set_tensors(A)
+    res = np.array([ctx.sweep(1) for _ in range(3)])
+    assert np.array_equal(res, one[0])
+    assert np.array_equal(ctx.get_messages_flat(), one[4])
