@@ -11,6 +11,7 @@ and the log-norm.
     python tests/golden/make_golden.py obc6x6_D6_b3_chi6 3
     python tests/golden/make_golden.py obc8x8_D4_b4_chi56 4
     python tests/golden/make_golden.py obc4x4_D4_b4_env80 5
+    python tests/golden/make_golden.py obc8x8_D6_b4_chi64 0
 """
 
 import json

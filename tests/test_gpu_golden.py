@@ -15,6 +15,10 @@ the fits at bond caps 49..64 (the visit's widest pair-per-wave variant).
 
 4x4 open lattice as one D=4 block, chi_env=80 (seed 5): the observables'
 boundary fits at a bond cap above 64 (the tiled D=4 visit).
+
+8x8 open lattice, D=6, 4x4 blocks, chi=64, chi_env=82 (seed 0): two sweeps
+at the bond caps of the 16x16 D=6 workload (fused D=6 visit at 64, unfused
+chain at 82, global-memory QR on both).
 """
 
 import json
@@ -154,6 +158,42 @@ def test_obc4x4_D4_env80_matches_oracle():
     lz, sign = ctx.log_norm()
     print(f"max |d sz| {err_sz:.2e}  max |d SS| {err_ss:.2e}  "
           f"log-norm {lz:.12f} vs {g['log_norm']:.12f}", flush=True)
+    assert err_sz < TOL and err_ss < TOL
+    assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
+    assert sign == g["log_norm_sign"]
+
+
+def test_obc8x8_D6_chi64_env82_matches_oracle():
+    """8x8 open lattice, D=6, 4x4 blocks, chi=64, chi_env=82 (seed 0), two
+    sweeps: the D=6 workload's bond caps.  The message fits run the fused
+    D=6 visit at K=64 with the global-memory QR on its 2304 x 64 panels; the
+    observables' boundary fits at K=82 run the unfused contraction chain
+    (T1, ket, bra, local) with 2952 x 82 QR panels."""
+    from paper_2301_05844_amd import bbp
+    g = _golden("obc8x8_D6_b4_chi64", seed=0)
+    cfg = CONFIGS["obc8x8_D6_b4_chi64"]
+    A = peps_finite(cfg["Lx"], cfg["Ly"], cfg["D"], seed=g["seed"])
+    ctx = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"],
+                      D=cfg["D"], chi=cfg["chi"], chi_env=g["chi_env"])
+    ctx.set_tensors(A)
+    ctx.set_option("timing", 1)
+    res = [ctx.sweep(1) for _ in range(g["sweeps"])]
+    _check_residuals(res, g["residuals"])
+    sweeps = {k["name"]: k["launches"] for k in ctx.kernel_stats()}
+    ctx.kernel_stats_reset()
+    sites = np.array(g["sites"], dtype=np.int32)
+    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+    err_sz = np.abs(sz - np.array(g["sz"])).max()
+    ss = ctx.expect_bonds(g["bonds"], op_heis())
+    err_ss = np.abs(ss - np.array(g["ss"])).max()
+    lz, sign = ctx.log_norm()
+    obs = {k["name"]: k["launches"] for k in ctx.kernel_stats()}
+    ctx.set_option("timing", 0)
+    print(f"max |d sz| {err_sz:.2e}  max |d SS| {err_ss:.2e}  "
+          f"log-norm {lz:.12f} vs {g['log_norm']:.12f}; launches: sweeps {sweeps}, "
+          f"observables {obs}", flush=True)
+    assert sweeps["fit_visit"] > 0 and sweeps["fit_T1"] == 0   # fused D=6 visit at K=64
+    assert obs["fit_T1"] > 0 and obs["fit_bra"] > 0            # unfused chain at K=82
     assert err_sz < TOL and err_ss < TOL
     assert abs(lz - g["log_norm"]) < TOL * abs(g["log_norm"])
     assert sign == g["log_norm_sign"]
