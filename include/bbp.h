@@ -247,6 +247,59 @@ const char *bbp_last_error(const bbp_ctx *c);
 void bbp_destroy(bbp_ctx *c);
 
 /* ------------------------------------------------------------------------
+ * One directed message update outside a context: Eq. (1) for a single
+ * message, the block contracted with its three other incoming messages
+ * column by column, each column an MPO x MPS variational fit truncated to
+ * bond chi (App. A), as one step of bbp_sweep computes it.
+ *
+ * Canonical frame: the receiving block lies to the left of this block.  A
+ * holds the block's H x W site tensors in that frame, row-major (y outer, x
+ * inner), each [s][u][l][d][r] with every leg stored with dimension D (a
+ * sweep rotates the lattice's tensors into this frame for each direction).
+ * Messages are open MPSs whose site i is a chi x D^2 x chi slot of doubles,
+ * [b_i][(k,k')][b_{i+1}] zero-padded to chi, with true bonds b (n+1 ints, 1
+ * at both ends): mt the top message (W sites, left to right), mr the right
+ * message (H sites, top to bottom), mb the bottom message (W sites, left to
+ * right).  A null message (and its null bond list) is the trivial message of
+ * a lattice edge.  The columns are absorbed from W-1 down to 0; each fit
+ * starts from the counter-based random state of (seed, slot + column)
+ * (a sweep uses slot = 2^40 + 256 e for message e) and makes n_fit full
+ * sweeps.
+ *
+ * Outputs: out (device, H slots) the message m_{A->B}, top to bottom, scaled
+ * to unit 2-norm; out_bonds (host, H+1 ints) its bond dimensions;
+ * *log_scale (host) the logarithm of the scale removed.  All tensor and
+ * message pointers are device pointers (HIP), read and written on
+ * hip_stream (NULL: the null stream); the call returns once the update is
+ * done.  The caller owns every buffer.
+ * Errors: BBP_EINVAL (malformed spec, bonds, null pointers), BBP_ENOMEM,
+ * BBP_EDEVICE, BBP_ENUMERIC (a column's fit has zero or non-finite norm;
+ * out is then unspecified).  The message is in bbp_update_last_error().
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t H, W;   /* block rows (sites of the message) and columns       */
+  int32_t D, d;   /* PEPS bond dimension (<= 8), physical dimension      */
+  int32_t chi;    /* message bond cap (<= 128): slots are chi x D^2 x chi */
+  int32_t n_fit;  /* full fit sweeps per column (>= 1, App. A)           */
+  uint64_t seed;  /* seed of the counter-based fit starts                */
+  uint64_t slot;  /* slot base: column c uses slot + c                   */
+} bbp_update_spec;
+
+/* Device bytes of the workspace one update of this shape uses. */
+bbp_status bbp_update_workspace(const bbp_update_spec *spec, size_t *bytes);
+
+/* The update, with a workspace allocated (hipMalloc) and freed by the call. */
+bbp_status bbp_update_message(const bbp_update_spec *spec, const double *A,
+                              const double *mt, const int32_t *mt_bonds,
+                              const double *mr, const int32_t *mr_bonds,
+                              const double *mb, const int32_t *mb_bonds,
+                              double *out, int32_t *out_bonds, double *log_scale,
+                              void *hip_stream);
+
+/* Error message of the calling thread's last failed update call. */
+const char *bbp_update_last_error(void);
+
+/* ------------------------------------------------------------------------
  * Request server: independent block-BP solves of finite open lattices
  * (Sec. II; each one the problem bbp_create states) served concurrently on
  * one GPU.  A pool of max_slots worker threads takes requests first-in

@@ -32,6 +32,7 @@ EXPORTS = (
     "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
     "bbp_server_error", "bbp_server_destroy",
+    "bbp_update_workspace", "bbp_update_message", "bbp_update_last_error",
 )
 
 OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
@@ -49,6 +50,14 @@ class Request(ctypes.Structure):
                 ("D", ctypes.c_int32), ("chi", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int32), ("outputs", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
+
+class UpdateSpec(ctypes.Structure):
+    """bbp_update_spec of include/bbp.h."""
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("D", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("chi", ctypes.c_int32), ("n_fit", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("slot", ctypes.c_uint64)]
+
 
 STATUS = {0: "BBP_OK", 1: "BBP_EINVAL", 2: "BBP_ENOMEM", 3: "BBP_EDEVICE",
           4: "BBP_ESTATE", 5: "BBP_ENUMERIC"}
@@ -97,6 +106,9 @@ def _load():
                             ctypes.POINTER(c_size), dp],
         "bbp_server_cancel": [P, ctypes.c_int64],
         "bbp_server_stats": [P, ip, ip, ctypes.POINTER(c_size), ip],
+        "bbp_update_workspace": [ctypes.POINTER(UpdateSpec), ctypes.POINTER(c_size)],
+        "bbp_update_message": [ctypes.POINTER(UpdateSpec), P, P, ip, P, ip, P, ip, P, ip,
+                               dp, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -110,6 +122,8 @@ def _load():
     lib.bbp_server_error.restype = ctypes.c_char_p
     lib.bbp_server_destroy.argtypes = [P]
     lib.bbp_server_destroy.restype = None
+    lib.bbp_update_last_error.argtypes = []
+    lib.bbp_update_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -333,6 +347,61 @@ def estimate_bytes(**req):
     st = _lib.bbp_server_estimate(ctypes.byref(_request(**req)), ctypes.byref(n))
     if st != 0:
         raise BBPError(st, "malformed request")
+    return n.value
+
+
+def _update_args(H, W, D, chi, d, n_fit, seed, slot, A, mt, mr, mb):
+    spec = UpdateSpec(H, W, D, d, chi, n_fit, seed, slot)
+    S = chi * D * D * chi
+
+    def side(m, n):
+        if m is None:
+            return None, None, None
+        t, bonds = m
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() \
+                or t.numel() < n * S:
+            raise ValueError(f"a message needs {n} contiguous float64 device slots of {S}")
+        b = np.ascontiguousarray(bonds, dtype=np.int32)
+        if b.shape != (n + 1,):
+            raise ValueError(f"a message of {n} sites needs {n + 1} bonds")
+        return ctypes.c_void_p(t.data_ptr()), _iptr(b), b
+    if A.dtype != torch.float64 or not A.is_cuda or not A.is_contiguous() \
+            or A.numel() != H * W * d * D ** 4:
+        raise ValueError(f"A must hold H*W*d*D^4 = {H * W * d * D ** 4} contiguous "
+                         "float64 device values")
+    out = torch.zeros(H * S, dtype=torch.float64, device=A.device)
+    sides = [side(mt, W), side(mr, H), side(mb, W)]
+    return spec, out, sides
+
+
+def update_message(A, mt=None, mr=None, mb=None, *, H, W, D, chi, d=2, n_fit=2,
+                   seed=0, slot=0, stream=None):
+    """bbp_update_message: one directed message update of an H x W block in
+    the canonical frame (receiver on the left).  ``A``: device float64 tensor
+    of the H*W rotated site tensors; ``mt``, ``mr``, ``mb``: ``(tensor,
+    bonds)`` of the top, right and bottom messages in chi x D^2 x chi slots,
+    or None (trivial).  Returns ``(out, bonds, log_scale)`` with ``out`` a
+    device tensor of H slots."""
+    spec, out, sides = _update_args(H, W, D, chi, d, n_fit, seed, slot, A, mt, mr, mb)
+    bonds = np.zeros(H + 1, dtype=np.int32)
+    ls = ctypes.c_double()
+    handle = getattr(stream, "cuda_stream", stream)
+    st = _lib.bbp_update_message(ctypes.byref(spec), ctypes.c_void_p(A.data_ptr()),
+                                 sides[0][0], sides[0][1], sides[1][0], sides[1][1],
+                                 sides[2][0], sides[2][1], ctypes.c_void_p(out.data_ptr()),
+                                 _iptr(bonds), ctypes.byref(ls), ctypes.c_void_p(handle))
+    if st != 0:
+        raise BBPError(st, _lib.bbp_update_last_error().decode())
+    return out, bonds, ls.value
+
+
+def update_workspace(H, W, D, chi, d=2, n_fit=2):
+    """bbp_update_workspace: device bytes one update of this shape uses."""
+    n = ctypes.c_size_t()
+    st = _lib.bbp_update_workspace(ctypes.byref(UpdateSpec(H, W, D, d, chi, n_fit, 0, 0)),
+                                   ctypes.byref(n))
+    if st != 0:
+        raise BBPError(st, _lib.bbp_update_last_error().decode())
     return n.value
 
 

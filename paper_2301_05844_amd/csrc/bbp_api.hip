@@ -65,13 +65,15 @@ struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
   MemAcct *acct = nullptr;
+  bool borrowed = false;  // memory owned elsewhere (a caller's workspace): never freed here
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct) {
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), acct(o.acct), borrowed(o.borrowed) {
     o.p = nullptr;
     o.bytes = 0;
     o.acct = nullptr;
+    o.borrowed = false;
   }
   DevBuf &operator=(DevBuf &&o) noexcept {
     if (this != &o) {
@@ -79,15 +81,24 @@ struct DevBuf {
       p = o.p;
       bytes = o.bytes;
       acct = o.acct;
+      borrowed = o.borrowed;
       o.p = nullptr;
       o.bytes = 0;
       o.acct = nullptr;
+      o.borrowed = false;
     }
     return *this;
   }
   ~DevBuf() { release(); }
+  // Points at b bytes of memory that someone else owns.
+  void borrow(void *q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    borrowed = true;
+  }
   void release() {
-    if (p) {
+    if (p && !borrowed) {
       if (acct && acct->free_fn) {
         if (acct->stream) (void)hipStreamSynchronize(*acct->stream);
         acct->free_fn(p, acct->user);
@@ -99,6 +110,7 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
     acct = nullptr;
+    borrowed = false;
   }
   // (Re)allocates b bytes; an existing allocation of exactly b bytes is kept
   // (its contents are not cleared).
@@ -2255,5 +2267,243 @@ void bbp_destroy(bbp_ctx *c) {
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// One directed message update outside a context (Eq. (1); App. A): a block
+// of H x W tensors in the canonical frame (the receiver on its left), its
+// incoming top, right and bottom messages, column absorptions W-1 .. 0 as
+// variational fits, the two dimension-1 end sites contracted into the
+// message.  The same batch engine as a sweep, with one item whose buffers
+// are carved from one workspace allocated per call.
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local std::string tl_update_err;
+
+bbp_status update_fail(bbp_status s, const std::string &m) {
+  tl_update_err = m;
+  return s;
+}
+
+// Byte layout of one update's workspace (256-byte aligned pieces).
+struct UpdateLayout {
+  size_t store, xin, mt, mb, lenv, renv, t1, t2, t3, tmp, rbuf, nu, triv, err, flag,
+      dims, slot, gather, dst, rev, total;
+  size_t zero_end;  // [0, zero_end) is cleared before the update
+};
+
+UpdateLayout update_layout(const FitBatch &f) {
+  UpdateLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  const size_t S = f.S, K = f.K, P = f.P;
+  const bool fused = visit_fused_fits(f);
+  L.store = take(8 * f.W * f.N * S);
+  L.xin = take(8 * f.N * S);
+  L.mt = take(8 * f.W * S);
+  L.mb = take(8 * f.W * S);
+  L.lenv = take(8 * f.N * S);
+  L.renv = take(8 * f.N * S);
+  L.nu = take(8 * f.W);
+  L.err = take(4);
+  L.zero_end = off;
+  L.triv = take(8 * std::max(f.W, f.H) * S);
+  L.t1 = (!fused || qr_needs_scratch(f)) ? take(8 * K * P * P * K) : 0;
+  L.t2 = !fused ? take(8 * (size_t)f.d * K * K * P * P) : 0;
+  L.t3 = take(8 * K * P * P * K);
+  L.tmp = take(8 * S);
+  L.rbuf = take(8 * K * K);
+  L.flag = take(4 * f.W);
+  L.dims = take(sizeof(FitDims) * f.W);
+  L.slot = take(8);
+  L.gather = take(sizeof(GatherSrc));
+  L.dst = take(sizeof(double *));
+  L.rev = take(4);
+  L.total = off;
+  return L;
+}
+
+bool valid_bonds(const int32_t *b, int n, int chi, std::vector<int> &out) {
+  out.assign(n + 1, 1);
+  if (!b) return true;
+  if (b[0] != 1 || b[n] != 1) return false;
+  for (int i = 0; i <= n; ++i) {
+    if (b[i] < 1 || b[i] > chi) return false;
+    out[i] = b[i];
+  }
+  return true;
+}
+
+// The batch of one update: shapes from the spec, no buffers yet.
+bbp_status update_batch(const bbp_update_spec *sp, FitBatch &f) {
+  if (!sp) return update_fail(BBP_EINVAL, "null spec");
+  if (sp->H < 1 || sp->W < 1 || sp->H + 2 > NMAX)
+    return update_fail(BBP_EINVAL, "H must be in [1, " + std::to_string(NMAX - 2) +
+                                       "] and W >= 1");
+  if (sp->D < 1 || sp->D > 8 || sp->d < 1 || sp->d > 8)
+    return update_fail(BBP_EINVAL, "D and d must be in [1, 8]");
+  if (sp->chi < 1 || sp->chi > 128) return update_fail(BBP_EINVAL, "chi must be in [1, 128]");
+  if (sp->n_fit < 1 || sp->n_fit > 64) return update_fail(BBP_EINVAL, "n_fit must be in [1, 64]");
+  f = FitBatch{};
+  f.items = f.tile_items = 1;
+  f.K = sp->chi;
+  f.D = sp->D;
+  f.P = sp->D * sp->D;
+  f.d = sp->d;
+  f.H = sp->H;
+  f.W = sp->W;
+  f.N = sp->H + 2;
+  f.S = (size_t)f.K * f.P * f.K;
+  f.seed = sp->seed;
+  f.prec = 64;
+  return BBP_OK;
+}
+
+// workspace: null to allocate one for the call, else ws_bytes of device
+// memory the caller provides (checked against the layout's size).
+bbp_status update_message(const bbp_update_spec *sp, const double *A, const double *mt,
+                          const int32_t *mt_bonds, const double *mr,
+                          const int32_t *mr_bonds, const double *mb,
+                          const int32_t *mb_bonds, double *out, int32_t *out_bonds,
+                          double *log_scale, void *stream, void *workspace,
+                          size_t ws_bytes) {
+  FitBatch f;
+  bbp_status bs = update_batch(sp, f);
+  if (bs != BBP_OK) return bs;
+  if (!A || !out || !out_bonds || !log_scale)
+    return update_fail(BBP_EINVAL, "null tensor, output, bonds or log-scale pointer");
+  std::vector<int> bt, br, bb;
+  if (!valid_bonds(mt ? mt_bonds : nullptr, f.W, f.K, bt) ||
+      !valid_bonds(mr ? mr_bonds : nullptr, f.H, f.K, br) ||
+      !valid_bonds(mb ? mb_bonds : nullptr, f.W, f.K, bb))
+    return update_fail(BBP_EINVAL, "message bonds must be 1 at both ends and in [1, chi]");
+  if ((mt && !mt_bonds) || (mr && !mr_bonds) || (mb && !mb_bonds))
+    return update_fail(BBP_EINVAL, "a message needs its bond list");
+  const UpdateLayout L = update_layout(f);
+  hipStream_t st = (hipStream_t)stream;
+  unsigned char *ws = (unsigned char *)workspace;
+  DevBuf owned;
+  hipError_t e;
+  if (!ws) {
+    if ((e = owned.alloc(L.total)) != hipSuccess)
+      return update_fail(BBP_ENOMEM, "device allocation failed");
+    ws = (unsigned char *)owned.p;
+  } else if (L.total > ws_bytes) {
+    return update_fail(BBP_EINVAL, "update needs " + std::to_string(L.total) +
+                                       " bytes of workspace, " + std::to_string(ws_bytes) +
+                                       " given");
+  }
+  // nothing returns before the stream is done with the workspace
+  struct Drain {
+    hipStream_t st;
+    ~Drain() { (void)hipStreamSynchronize(st); }
+  } drain{st};
+  auto at = [&](size_t off) { return (double *)(ws + off); };
+  f.store = at(L.store);
+  f.xin = at(L.xin);
+  f.mt = at(L.mt);
+  f.mb = at(L.mb);
+  f.lenv = at(L.lenv);
+  f.renv = at(L.renv);
+  f.t1 = L.t1 ? at(L.t1) : nullptr;
+  f.t2 = L.t2 ? at(L.t2) : nullptr;
+  f.t3 = at(L.t3);
+  f.tmp = at(L.tmp);
+  f.acan = const_cast<double *>(A);
+  f.rbuf = at(L.rbuf);
+  f.nu = at(L.nu);
+  f.err = (int32_t *)(ws + L.err);
+  f.dims = (FitDims *)(ws + L.dims);
+  f.slot = (uint64_t *)(ws + L.slot);
+  // the fit engine's bookkeeping (no device memory of its own)
+  bbp_ctx host;
+  host.n_fit = sp->n_fit;
+  host.stream = st;
+  Group g;
+  g.W = f.W;
+  g.H = f.H;
+  g.fb = f;
+  g.flagbuf.borrow(ws + L.flag, 4 * f.W);
+  g.fb.flag = (int32_t *)(ws + L.flag);
+  std::vector<FitDims> cd;
+  column_dims(f.W, f.H, f.K, f.P, bt, bb, br, cd);
+  for (auto &x : cd) x.rnd = 1;
+  g.dims = cd;
+  g.have.assign(f.W, 0);
+  // workspace: zero padding, trivial message sites, tables
+  double *triv = at(L.triv);
+  GatherSrc gs{};
+  gs.ksrc = f.K;
+  const double *src[3] = {mt, mr, mb};
+  const int nsite[3] = {f.W, f.H, f.W};
+  for (int k = 0; k < 3; ++k) {
+    gs.src[k][0] = src[k] ? src[k] : triv;
+    gs.n[k][0] = nsite[k];
+  }
+  double *dst_tab = out;
+  const int32_t rev0 = 0;
+  const uint64_t slot0 = sp->slot;
+  FitBatch ft = f;
+  ft.items = std::max(f.W, f.H);
+  if ((e = launch_zero(ws, L.zero_end, st)) != hipSuccess ||
+      (e = launch_set_unit(ft, Ptr{triv, f.S}, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws + L.slot, &slot0, 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(ws + L.gather, &gs, sizeof gs, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(ws + L.dst, &dst_tab, sizeof dst_tab, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(ws + L.rev, &rev0, 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = launch_gather(g.fb, (const GatherSrc *)(ws + L.gather), st)) != hipSuccess)
+    return update_fail(BBP_EDEVICE, std::string("update setup: ") + hipGetErrorString(e));
+  bs = absorb_columns(&host, g, 0, st, false);
+  if (bs != BBP_OK) return update_fail(bs, host.err);
+  if ((e = launch_extract(g.fb, (double *const *)(ws + L.dst), (const int32_t *)(ws + L.rev),
+                          st)) != hipSuccess)
+    return update_fail(BBP_EDEVICE, std::string("extract: ") + hipGetErrorString(e));
+  std::vector<double> nu(f.W, 0.0);
+  int32_t errv = 0;
+  if ((e = hipMemcpyAsync(nu.data(), f.nu, 8 * f.W, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(&errv, f.err, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return update_fail(BBP_EDEVICE, std::string("update: ") + hipGetErrorString(e));
+  if (errv) return update_fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
+  double ls = 0.0;
+  for (double v : nu) ls += std::log(v);
+  *log_scale = ls;
+  const FitDims &c0 = cd[0];
+  out_bonds[0] = out_bonds[f.H] = 1;
+  for (int s2 = 0; s2 + 1 < f.H; ++s2) out_bonds[s2 + 1] = c0.br[s2 + 1];
+  return BBP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bbp_status bbp_update_workspace(const bbp_update_spec *spec, size_t *bytes) {
+  FitBatch f;
+  bbp_status bs = update_batch(spec, f);
+  if (bs != BBP_OK) return bs;
+  if (!bytes) return update_fail(BBP_EINVAL, "null bytes pointer");
+  *bytes = update_layout(f).total;
+  return BBP_OK;
+}
+
+bbp_status bbp_update_message(const bbp_update_spec *spec, const double *A, const double *mt,
+                              const int32_t *mt_bonds, const double *mr,
+                              const int32_t *mr_bonds, const double *mb,
+                              const int32_t *mb_bonds, double *out, int32_t *out_bonds,
+                              double *log_scale, void *hip_stream) {
+  return update_message(spec, A, mt, mt_bonds, mr, mr_bonds, mb, mb_bonds, out, out_bonds,
+                        log_scale, hip_stream, nullptr, 0);
+}
+
+const char *bbp_update_last_error(void) { return tl_update_err.c_str(); }
 
 }  // extern "C"

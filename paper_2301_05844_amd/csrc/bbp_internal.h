@@ -142,6 +142,8 @@ hipError_t launch_apply_l(const FitBatch &f, bool end_site, Ptr Y,
 // Counter-based random start for all N sites of column c (flagged items).
 hipError_t launch_rand_init(const FitBatch &f, int c, Ptr Ybase,
                             hipStream_t st);
+// Clear bytes (a multiple of 4) at p with a fill kernel.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 // Set slot (per item) to the 1x1x1 unit tensor.
 hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st);
 // Normalise the end slot Y0 to unit norm; nu[item*W + c] = its norm.

@@ -3130,6 +3130,20 @@ hipError_t launch_rand_init(const FitBatch &f, int c, Ptr Ybase,
   return hipGetLastError();
 }
 
+__global__ void k_zero_words(uint32_t *p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<size_t>(1024, (n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(kThreads), 0, st, (uint32_t *)p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_unit(const FitBatch &f, Ptr slot, hipStream_t st) {
   hipLaunchKernelGGL(k_set_unit, dim3(16, f.items), dim3(kThreads), 0, st,
                      slot, f.S);
