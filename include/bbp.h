@@ -296,6 +296,23 @@ bbp_status bbp_update_message(const bbp_update_spec *spec, const double *A,
                               double *out, int32_t *out_bonds, double *log_scale,
                               void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update (bitwise the same results) with its workspace in a static device
+ * array of BBP_UPDATE_NOALLOC_BYTES that each GPU holds until the process
+ * ends; no hipMalloc, hipFree or allocating library routine is called.  The
+ * caller still passes the inputs and outputs.  Every call on a GPU shares
+ * that GPU's array (the workspace is cleared at the start of each call), so
+ * calls that overlap on one GPU race.  A shape whose workspace
+ * (bbp_update_workspace) exceeds the array returns BBP_EINVAL. */
+#define BBP_UPDATE_NOALLOC_BYTES (64ull << 20)
+bbp_status bbp_update_message_noalloc(const bbp_update_spec *spec, const double *A,
+                                      const double *mt, const int32_t *mt_bonds,
+                                      const double *mr, const int32_t *mr_bonds,
+                                      const double *mb, const int32_t *mb_bonds,
+                                      double *out, int32_t *out_bonds,
+                                      double *log_scale, void *hip_stream);
+
 /* Error message of the calling thread's last failed update call. */
 const char *bbp_update_last_error(void);
 

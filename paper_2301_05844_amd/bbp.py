@@ -32,7 +32,8 @@ EXPORTS = (
     "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
     "bbp_server_error", "bbp_server_destroy",
-    "bbp_update_workspace", "bbp_update_message", "bbp_update_last_error",
+    "bbp_update_workspace", "bbp_update_message", "bbp_update_message_noalloc",
+    "bbp_update_last_error",
 )
 
 OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
@@ -109,6 +110,8 @@ def _load():
         "bbp_update_workspace": [ctypes.POINTER(UpdateSpec), ctypes.POINTER(c_size)],
         "bbp_update_message": [ctypes.POINTER(UpdateSpec), P, P, ip, P, ip, P, ip, P, ip,
                                dp, P],
+        "bbp_update_message_noalloc": [ctypes.POINTER(UpdateSpec), P, P, ip, P, ip, P, ip,
+                                       P, ip, dp, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -374,19 +377,25 @@ def _update_args(H, W, D, chi, d, n_fit, seed, slot, A, mt, mr, mb):
     return spec, out, sides
 
 
+NOALLOC_BYTES = 64 << 20   # BBP_UPDATE_NOALLOC_BYTES
+
+
 def update_message(A, mt=None, mr=None, mb=None, *, H, W, D, chi, d=2, n_fit=2,
-                   seed=0, slot=0, stream=None):
+                   seed=0, slot=0, stream=None, noalloc=False):
     """bbp_update_message: one directed message update of an H x W block in
     the canonical frame (receiver on the left).  ``A``: device float64 tensor
     of the H*W rotated site tensors; ``mt``, ``mr``, ``mb``: ``(tensor,
     bonds)`` of the top, right and bottom messages in chi x D^2 x chi slots,
     or None (trivial).  Returns ``(out, bonds, log_scale)`` with ``out`` a
-    device tensor of H slots."""
+    device tensor of H slots.  ``noalloc``: bbp_update_message_noalloc (the
+    library's static workspace; the output tensor is still allocated here, by
+    the caller)."""
     spec, out, sides = _update_args(H, W, D, chi, d, n_fit, seed, slot, A, mt, mr, mb)
     bonds = np.zeros(H + 1, dtype=np.int32)
     ls = ctypes.c_double()
     handle = getattr(stream, "cuda_stream", stream)
-    st = _lib.bbp_update_message(ctypes.byref(spec), ctypes.c_void_p(A.data_ptr()),
+    fn = _lib.bbp_update_message_noalloc if noalloc else _lib.bbp_update_message
+    st = fn(ctypes.byref(spec), ctypes.c_void_p(A.data_ptr()),
                                  sides[0][0], sides[0][1], sides[1][0], sides[1][1],
                                  sides[2][0], sides[2][1], ctypes.c_void_p(out.data_ptr()),
                                  _iptr(bonds), ctypes.byref(ls), ctypes.c_void_p(handle))

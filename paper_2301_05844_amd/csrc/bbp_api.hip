@@ -12,6 +12,7 @@
 #include <map>
 #include <tuple>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2287,6 +2288,36 @@ bbp_status update_fail(bbp_status s, const std::string &m) {
   return s;
 }
 
+// Workspace of bbp_update_message_noalloc, for callers that cannot
+// allocate device memory.  Each GPU holds its own copy until the process
+// ends; every call on a GPU shares it, so calls that overlap on one GPU race.
+constexpr size_t kUpdateScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kUpdateScratchBytes];
+
+// Device address of `scratch` on the current device, taken once per device
+// with that device current (in host code the array's name is a host-side
+// stand-in, not a device address).
+std::mutex scratch_mu;
+std::map<int, void *> scratch_ptr;
+
+hipError_t device_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  auto it = scratch_ptr.find(dev);
+  if (it != scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *ptr = nullptr;
+  e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
+
 // Byte layout of one update's workspace (256-byte aligned pieces).
 struct UpdateLayout {
   size_t store, xin, mt, mb, lenv, renv, t1, t2, t3, tmp, rbuf, nu, triv, err, flag,
@@ -2502,6 +2533,28 @@ bbp_status bbp_update_message(const bbp_update_spec *spec, const double *A, cons
                               double *log_scale, void *hip_stream) {
   return update_message(spec, A, mt, mt_bonds, mr, mr_bonds, mb, mb_bonds, out, out_bonds,
                         log_scale, hip_stream, nullptr, 0);
+}
+
+bbp_status bbp_update_message_noalloc(const bbp_update_spec *spec, const double *A,
+                                      const double *mt, const int32_t *mt_bonds,
+                                      const double *mr, const int32_t *mr_bonds,
+                                      const double *mb, const int32_t *mb_bonds, double *out,
+                                      int32_t *out_bonds, double *log_scale,
+                                      void *hip_stream) {
+  FitBatch f;
+  bbp_status bs = update_batch(spec, f);
+  if (bs != BBP_OK) return bs;
+  const size_t need = update_layout(f).total;
+  if (need > kUpdateScratchBytes)
+    return update_fail(BBP_EINVAL, "update needs " + std::to_string(need) +
+                                       " bytes of workspace; the static workspace holds " +
+                                       std::to_string(kUpdateScratchBytes));
+  void *ws = nullptr;
+  hipError_t e = device_scratch(&ws);
+  if (e != hipSuccess)
+    return update_fail(BBP_EDEVICE, std::string("static workspace: ") + hipGetErrorString(e));
+  return update_message(spec, A, mt, mt_bonds, mr, mr_bonds, mb, mb_bonds, out, out_bonds,
+                        log_scale, hip_stream, ws, kUpdateScratchBytes);
 }
 
 const char *bbp_update_last_error(void) { return tl_update_err.c_str(); }
