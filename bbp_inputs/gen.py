@@ -3,22 +3,24 @@
 import numpy as np
 
 
-def _draw_site(rng, d, dims, D):
-    """One site: ``0.1 * N(0,1)`` over the true leg dimensions, plus 1 at the
-    all-zero entry, zero-padded to ``D`` on every virtual leg."""
+def _draw_site(rng, d, dims, D, noise=0.1):
+    """One site: ``noise * N(0,1)`` over the true leg dimensions, plus 1 at
+    the all-zero entry, zero-padded to ``D`` on every virtual leg."""
     du, dl, dd, dr = dims
-    t = 0.1 * rng.standard_normal((d, du, dl, dd, dr))
+    t = noise * rng.standard_normal((d, du, dl, dd, dr))
     t[0, 0, 0, 0, 0] += 1.0
     out = np.zeros((d, D, D, D, D))
     out[:, :du, :dl, :dd, :dr] = t
     return out
 
 
-def peps_finite(Lx, Ly, D, d=2, seed=0):
+def peps_finite(Lx, Ly, D, d=2, seed=0, noise=0.1):
     """Finite open-boundary PEPS on an ``Lx`` x ``Ly`` square lattice.
 
     Returns an array of shape ``(Ly*Lx, d, D, D, D, D)``; sites in row-major
     order; legs pointing off the lattice have true dimension 1 (zero-padded).
+    ``noise`` scales the Gaussian part (0.1 for every named workload; larger
+    values give a more strongly correlated state).
     """
     rng = np.random.default_rng(seed)
     A = np.zeros((Ly * Lx, d, D, D, D, D))
@@ -28,7 +30,7 @@ def peps_finite(Lx, Ly, D, d=2, seed=0):
                     1 if x == 0 else D,
                     1 if y == Ly - 1 else D,
                     1 if x == Lx - 1 else D)
-            A[y * Lx + x] = _draw_site(rng, d, dims, D)
+            A[y * Lx + x] = _draw_site(rng, d, dims, D, noise)
     return A
 
 

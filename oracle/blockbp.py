@@ -361,7 +361,7 @@ class BlockBP:
     """
 
     def __init__(self, A, D, chi, bx, by, Lx=0, Ly=0, infinite=False,
-                 ucx=1, ucy=1, chi_env=None, n_fit=2, seed=0, d=2):
+                 ucx=1, ucy=1, chi_env=None, n_fit=2, seed=0, d=2, shift=(0, 0)):
         self.D, self.chi, self.bx, self.by = D, chi, bx, by
         self.infinite = infinite
         self.d = d
@@ -375,14 +375,23 @@ class BlockBP:
             self.gx = self.gy = 1
             self.site = lambda x, y: A[(y % ucy) * ucx + (x % ucx)]
         else:
+            # shifted partition (Sec. II: partitions that differ by a shift
+            # of the lattice): sx trivial columns on the left and sy trivial
+            # rows on top, the same as shifting an OBC lattice embedded in a
+            # periodic one with dimension-1 bonds at its edges
+            sx, sy = shift
+            if not (0 <= sx < bx and 0 <= sy < by):
+                raise ValueError("shift must lie inside one block")
             self.Lx, self.Ly = Lx, Ly
-            self.gx = -(-Lx // bx)
-            self.gy = -(-Ly // by)
+            self.sx, self.sy = sx, sy
+            self.gx = -(-(Lx + sx) // bx)
+            self.gy = -(-(Ly + sy) // by)
             triv = np.zeros((d, D, D, D, D))
             triv[0, 0, 0, 0, 0] = 1.0
 
             def site(x, y, A=A):
-                if x < Lx and y < Ly:
+                x, y = x - sx, y - sy
+                if 0 <= x < Lx and 0 <= y < Ly:
                     return A[y * Lx + x]
                 return triv
             self.site = site
@@ -576,6 +585,8 @@ class BlockBP:
             oy = (self.by - self.ucy) // 2
             x = ox + (x - ox) % self.ucx
             y = oy + (y - oy) % self.ucy
+        else:
+            x, y = x + self.sx, y + self.sy
         return x // self.bx, y // self.by, x % self.bx, y % self.by
 
     def expect_site(self, x, y, op):
@@ -610,6 +621,31 @@ class BlockBP:
         den = self._contract_line(up, dn, sites, ends, legs, {})
         return num / den
 
+    def rdm_site(self, x, y):
+        """One-site reduced density matrix ``rho[s, s']`` with
+        ``<O> = Tr(rho O)``: entry (s, s') is the expectation of the matrix
+        unit |s'><s|."""
+        d = self.d
+        rho = np.zeros((d, d))
+        for s in range(d):
+            for sp in range(d):
+                unit = np.zeros((d, d))
+                unit[sp, s] = 1.0
+                rho[s, sp] = self.expect_site(x, y, unit)
+        return rho
+
+    def rdm_bond(self, x0, y0, x1, y1):
+        """Two-site reduced density matrix ``rho[(s0,s1), (s0',s1')]`` of a
+        nearest-neighbour bond, (x0, y0) the major index."""
+        d2 = self.d * self.d
+        rho = np.zeros((d2, d2))
+        for a in range(d2):
+            for b in range(d2):
+                unit = np.zeros((d2, d2))
+                unit[b, a] = 1.0
+                rho[a, b] = self.expect_bond(x0, y0, x1, y1, unit)
+        return rho
+
     def log_norm(self):
         """Block Bethe formula: ``sum_A log|Z_A| - sum_edges log|Z_AB|``, with
         ``Z_A`` the contraction of block A with its four incoming messages
@@ -631,3 +667,35 @@ class BlockBP:
             total -= math.log(abs(zab))
             sign *= math.copysign(1.0, zab)
         return total, sign
+
+
+# ---------------------------------------------------------------------------
+# Shifted partitions and trace distances (Sec. II; App. C)
+# ---------------------------------------------------------------------------
+def trace_distance(rho, sigma):
+    """``D(rho, sigma) = Tr|rho - sigma| / 2`` with ``|Z| = sqrt(Z^T Z)``
+    (App. C): half the sum of the singular values of the difference."""
+    return 0.5 * float(np.sum(np.linalg.svd(np.asarray(rho) - np.asarray(sigma),
+                                            compute_uv=False)))
+
+
+def centre_depth(b, s, x0, x1):
+    """How deep the coordinates x0..x1 (x1 = x0 or x0 + 1) lie inside their
+    block of size b along one axis when the partition is shifted by s: the
+    distance to the nearer block edge, or -1 when they fall in two blocks."""
+    u0, u1 = (x0 + s) % b, (x1 + s) % b
+    if (x0 + s) // b != (x1 + s) // b:
+        return -1
+    return min(u0, b - 1 - u1)
+
+
+def best_shift(bx, by, shifts, x0, y0, x1, y1):
+    """The partition shift among ``shifts`` that puts a site (x1, y1 =
+    x0, y0) or a bond deepest inside one block: the observable is then
+    taken at the centre of its block (Sec. II).  Ties go to the first."""
+    best, depth = None, -2
+    for (sx, sy) in shifts:
+        dep = min(centre_depth(bx, sx, x0, x1), centre_depth(by, sy, y0, y1))
+        if dep > depth:
+            best, depth = (sx, sy), dep
+    return best, depth
