@@ -93,6 +93,15 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              visit and environment kernels stop at every item's true bond
  *              dimensions instead of the padded cap (the skipped terms are
  *              zeros, so results are bitwise the same); 0 runs the padding.
+ *   "shift_x", "shift_y" 0..bx-1, 0..by-1 (default 0; finite lattices,
+ *              before bbp_set_tensors): a partition of the lattice into blocks
+ *              shifted by (shift_x, shift_y) sites (Sec. II: several
+ *              partitions that differ by a shift cover every bond at the
+ *              centre of some block).  The lattice is padded with shift_x
+ *              trivial columns on the left and shift_y trivial rows on top,
+ *              the same as shifting an open lattice embedded in a periodic
+ *              one with dimension-1 bonds at its edges; sites keep their
+ *              lattice coordinates in every call.
  *   "message_split" 1..4 (default 2; before bbp_set_tensors): the messages
  *              of one shape are updated as this many batches (of at least 8
  *              messages each), one per lane, so that one batch's QRs overlap
@@ -184,6 +193,30 @@ bbp_status bbp_expect_sites(bbp_ctx *c, int32_t n, const int32_t *xs,
 bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
                             const int32_t *y0, const int32_t *x1,
                             const int32_t *y1, const double *op, double *out);
+
+/*
+ * Reduced density matrices from the same region contractions as the
+ * expectation values (App. C): rho[a][b] with <O> = Tr(rho O), unit trace.
+ * Sites: n matrices of d x d (a = s, b = s').  Bonds (the pairs of
+ * bbp_expect_bonds): n matrices of d^2 x d^2 with a = (s0, s1), b =
+ * (s0', s1'), the first site the major index.  rho receives n*d^2 or n*d^4
+ * doubles.  Errors as bbp_expect_sites / bbp_expect_bonds.
+ */
+bbp_status bbp_rdm_sites(bbp_ctx *c, int32_t n, const int32_t *xs,
+                         const int32_t *ys, double *rho);
+bbp_status bbp_rdm_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
+                         const int32_t *y0, const int32_t *x1,
+                         const int32_t *y1, double *rho);
+
+/*
+ * Trace distance D(rho, sigma) = Tr|rho - sigma| / 2 with |Z| = sqrt(Z^T Z)
+ * (App. C) of two m x m real matrices (row-major, host): half the sum of the
+ * singular values of the difference (one-sided Jacobi on the host).  No
+ * context.  Errors: BBP_EINVAL for m outside [1, 64], null or non-finite
+ * input.
+ */
+bbp_status bbp_trace_distance(int32_t m, const double *rho, const double *sigma,
+                              double *out);
 
 /*
  * log|<psi|psi>| estimated by the block Bethe formula

@@ -26,7 +26,8 @@ EXPORTS = (
     "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_allocator",
     "bbp_set_tensors",
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
-    "bbp_expect_bonds", "bbp_log_norm", "bbp_get_messages",
+    "bbp_expect_bonds", "bbp_rdm_sites", "bbp_rdm_bonds", "bbp_trace_distance",
+    "bbp_log_norm", "bbp_get_messages",
     "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
     "bbp_kernel_stats_padded", "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
     "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
@@ -90,6 +91,9 @@ def _load():
         "bbp_expect_bond": [P, c_int, c_int, c_int, c_int, dp, dp],
         "bbp_expect_sites": [P, c_int, ip, ip, dp, dp],
         "bbp_expect_bonds": [P, c_int, ip, ip, ip, ip, dp, dp],
+        "bbp_rdm_sites": [P, c_int, ip, ip, dp],
+        "bbp_rdm_bonds": [P, c_int, ip, ip, ip, ip, dp],
+        "bbp_trace_distance": [c_int, dp, dp, dp],
         "bbp_log_norm": [P, dp, ip],
         "bbp_get_messages": [P, dp, c_size, ctypes.POINTER(c_size)],
         "bbp_set_messages": [P, dp, c_size],
@@ -160,6 +164,7 @@ class BlockBP:
         if st != 0:
             raise BBPError(st, "bbp_create rejected its arguments")
         self.D, self.chi = D, chi
+        self.d = int(options.get("d", 2))
         for k, v in options.items():
             self._check(_lib.bbp_set_option(self._ctx, k.encode(), float(v)))
         if stream is not None:
@@ -238,6 +243,26 @@ class BlockBP:
         self._check(_lib.bbp_expect_bonds(self._ctx, len(b),
                                           *[_iptr(c) for c in cols],
                                           _dptr(op), _dptr(out)))
+        return out
+
+    def rdm_sites(self, xs, ys):
+        """One-site reduced density matrices, shape (n, d, d)."""
+        xs = np.ascontiguousarray(xs, dtype=np.int32)
+        ys = np.ascontiguousarray(ys, dtype=np.int32)
+        d = self.d
+        out = np.zeros((len(xs), d, d))
+        self._check(_lib.bbp_rdm_sites(self._ctx, len(xs), _iptr(xs), _iptr(ys), _dptr(out)))
+        return out
+
+    def rdm_bonds(self, bonds):
+        """Two-site reduced density matrices of bonds (x0, y0, x1, y1),
+        shape (n, d^2, d^2)."""
+        b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 4))
+        cols = [np.ascontiguousarray(b[:, k]) for k in range(4)]
+        d2 = self.d * self.d
+        out = np.zeros((len(b), d2, d2))
+        self._check(_lib.bbp_rdm_bonds(self._ctx, len(b), *[_iptr(c) for c in cols],
+                                       _dptr(out)))
         return out
 
     def log_norm(self):
@@ -402,6 +427,19 @@ def update_message(A, mt=None, mr=None, mb=None, *, H, W, D, chi, d=2, n_fit=2,
     if st != 0:
         raise BBPError(st, _lib.bbp_update_last_error().decode())
     return out, bonds, ls.value
+
+
+def trace_distance(rho, sigma):
+    """bbp_trace_distance: Tr|rho - sigma| / 2 of two m x m real matrices."""
+    a = np.ascontiguousarray(rho, dtype=np.float64)
+    b = np.ascontiguousarray(sigma, dtype=np.float64)
+    if a.ndim != 2 or a.shape[0] != a.shape[1] or a.shape != b.shape:
+        raise ValueError("two square matrices of one size")
+    out = ctypes.c_double()
+    st = _lib.bbp_trace_distance(a.shape[0], _dptr(a), _dptr(b), ctypes.byref(out))
+    if st != 0:
+        raise BBPError(st, "bbp_trace_distance rejected its arguments")
+    return out.value
 
 
 def update_workspace(H, W, D, chi, d=2, n_fit=2):

@@ -212,6 +212,7 @@ struct bbp_ctx {
   // problem
   int infinite = 0, Lx = 0, Ly = 0, ucx = 1, ucy = 1, bx = 1, by = 1, D = 1,
       chi = 1, d = 2;
+  int sx = 0, sy = 0;  // partition shift: trivial columns left, rows on top
   int gx = 1, gy = 1;
   int chi_env = -1, n_fit = 2;
   int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
@@ -286,7 +287,9 @@ struct bbp_ctx {
       int cx = ((x % ucx) + ucx) % ucx, cy = ((y % ucy) + ucy) % ucy;
       return A.data() + (size_t)(cy * ucx + cx) * ss;
     }
-    if (x < Lx && y < Ly) return A.data() + (size_t)(y * Lx + x) * ss;
+    x -= sx;
+    y -= sy;
+    if (x >= 0 && y >= 0 && x < Lx && y < Ly) return A.data() + (size_t)(y * Lx + x) * ss;
     return nullptr;
   }
 };
@@ -1666,6 +1669,12 @@ static bbp_status make_query(bbp_ctx *c, int x0, int y0, int x1, int y1,
     if (!in0 || (bond && !in1)) return c->fail(BBP_EINVAL, "site outside the lattice");
   }
   int bi, bj, lx, ly;
+  if (!c->infinite) {  // lattice coordinates in the shifted partition
+    x0 += c->sx;
+    y0 += c->sy;
+    x1 += c->sx;
+    y1 += c->sy;
+  }
   locate(c, x0, y0, &bi, &bj, &lx, &ly);
   q.bi = bi;
   q.bj = bj;
@@ -1760,6 +1769,76 @@ static bbp_status answer(bbp_ctx *c, const Query &q, const double *op,
   return BBP_OK;
 }
 
+// Block grid and directed messages of the (shifted) partition.
+static void partition(bbp_ctx *c) {
+  if (c->infinite) {
+    c->gx = c->gy = 1;
+  } else {
+    c->gx = (c->Lx + c->sx + c->bx - 1) / c->bx;
+    c->gy = (c->Ly + c->sy + c->by - 1) / c->by;
+  }
+  c->msgs.clear();
+  for (int bj = 0; bj < c->gy; ++bj)
+    for (int bi = 0; bi < c->gx; ++bi)
+      for (char dr : kDirs) {
+        int ni, nj;
+        if (c->neighbour(bi, bj, dr, &ni, &nj)) {
+          Message m{bi, bj, dr, (dr == 'L' || dr == 'R') ? c->by : c->bx, {}};
+          m.bonds.assign(m.n + 1, 1);
+          c->msgs.push_back(m);
+        }
+      }
+}
+
+// Normalised reduced density matrices of n sites (d x d) or bonds
+// (d^2 x d^2), rho[a][b] with <O> = Tr(rho O), from the same region
+// contractions as the expectation values.
+static bbp_status rdm_many(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
+                           const int32_t *x1, const int32_t *y1, bool bond, double *out) {
+  if (!c) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (n < 0 || (n > 0 && (!x0 || !y0 || !out || (bond && (!x1 || !y1)))))
+    return c->fail(BBP_EINVAL, "null argument");
+  if (c->chi_env < c->chi) return c->fail(BBP_EINVAL, "chi_env must be at least chi");
+  std::vector<Query> qs(n);
+  for (int i = 0; i < n; ++i) {
+    bbp_status s = make_query(c, x0[i], y0[i], bond ? x1[i] : 0, bond ? y1[i] : 0, bond, qs[i]);
+    if (s != BBP_OK) return s;
+  }
+  bbp_status s = ensure_regions(c, qs);
+  if (s != BBP_OK) return s;
+  const int d = c->d, d2 = d * d, m = bond ? d2 : d;
+  for (int i = 0; i < n; ++i) {
+    const Query &q = qs[i];
+    const RegionResult &res = c->obs.at(std::make_tuple(q.kind, q.bi, q.bj));
+    double *rho = out + (size_t)i * m * m;
+    double den = 0.0;
+    if (!q.bond) {
+      // unit (s', s) at s' d + s is the expectation of |s'><s|: rho[s][s']
+      const double *u = &res.site[((size_t)q.line * res.W + q.pos) * d2];
+      for (int s0 = 0; s0 < d; ++s0) den += u[s0 * d + s0];
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) rho[a * d + b] = u[b * d + a];
+    } else {
+      const double *u = q.row ? &res.hbond[((size_t)q.line * (res.W - 1) + q.pos) * d2 * d2]
+                              : &res.vbond[((size_t)q.line * (res.H - 1) + q.pos) * d2 * d2];
+      for (int s0 = 0; s0 < d; ++s0)
+        for (int s1 = 0; s1 < d; ++s1) den += u[(s0 * d + s0) * d2 + s1 * d + s1];
+      // unit ((s0',s1'),(s0,s1)) at (s0' d + s0) d^2 + s1' d + s1
+      for (int s0 = 0; s0 < d; ++s0)
+        for (int s1 = 0; s1 < d; ++s1)
+          for (int s0p = 0; s0p < d; ++s0p)
+            for (int s1p = 0; s1p < d; ++s1p)
+              rho[(s0 * d + s1) * d2 + s0p * d + s1p] =
+                  u[(s0p * d + s0) * d2 + s1p * d + s1];
+    }
+    if (!std::isfinite(den) || den == 0.0)
+      return c->fail(BBP_ENUMERIC, "vanishing or non-finite region contraction");
+    for (int k = 0; k < m * m; ++k) rho[k] /= den;
+  }
+  return BBP_OK;
+}
+
 static bbp_status expect_many(bbp_ctx *c, int n, const int32_t *x0,
                               const int32_t *y0, const int32_t *x1,
                               const int32_t *y1, bool bond, const double *op,
@@ -1818,22 +1897,7 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
   c->by = by;
   c->D = D;
   c->chi = chi;
-  if (infinite) {
-    c->gx = c->gy = 1;
-  } else {
-    c->gx = (Lx + bx - 1) / bx;
-    c->gy = (Ly + by - 1) / by;
-  }
-  for (int bj = 0; bj < c->gy; ++bj)
-    for (int bi = 0; bi < c->gx; ++bi)
-      for (char dr : kDirs) {
-        int ni, nj;
-        if (c->neighbour(bi, bj, dr, &ni, &nj)) {
-          Message m{bi, bj, dr, (dr == 'L' || dr == 'R') ? by : bx, {}};
-          m.bonds.assign(m.n + 1, 1);
-          c->msgs.push_back(m);
-        }
-      }
+  partition(c);
   *out = c;
   return BBP_OK;
 }
@@ -1870,6 +1934,13 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   } else if (k == "graphs") {
     if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "graphs must be 0 or 1");
     c->graphs = (int)v;
+  } else if (k == "shift_x" || k == "shift_y") {
+    const int b = k == "shift_x" ? c->bx : c->by;
+    if (c->infinite) return c->fail(BBP_EINVAL, "partition shifts are for finite lattices");
+    if (v < 0 || v >= b || v != std::floor(v))
+      return c->fail(BBP_EINVAL, "a partition shift must be an integer in [0, block size)");
+    (k == "shift_x" ? c->sx : c->sy) = (int)v;
+    partition(c);
   } else if (k == "message_split") {
     if (v < 1 || v > 4 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "message_split must be an integer in [1,4]");
@@ -2145,6 +2216,61 @@ bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
   if (!c) return BBP_EINVAL;
   AcctScope acct_scope(&c->mem);
   return expect_many(c, n, x0, y0, x1, y1, true, op, out);
+}
+
+bbp_status bbp_rdm_sites(bbp_ctx *c, int32_t n, const int32_t *xs, const int32_t *ys,
+                         double *rho) {
+  return rdm_many(c, n, xs, ys, nullptr, nullptr, false, rho);
+}
+
+bbp_status bbp_rdm_bonds(bbp_ctx *c, int32_t n, const int32_t *x0, const int32_t *y0,
+                         const int32_t *x1, const int32_t *y1, double *rho) {
+  return rdm_many(c, n, x0, y0, x1, y1, true, rho);
+}
+
+bbp_status bbp_trace_distance(int32_t m, const double *rho, const double *sigma,
+                              double *out) {
+  if (m < 1 || m > 64 || !rho || !sigma || !out) return BBP_EINVAL;
+  // Tr|Z| / 2 = half the sum of the singular values of Z = rho - sigma, by
+  // one-sided Jacobi rotations of Z's columns (Hestenes): once every column
+  // pair is orthogonal, the column norms are the singular values.
+  std::vector<double> z((size_t)m * m);
+  for (int i = 0; i < m * m; ++i) {
+    z[i] = rho[i] - sigma[i];
+    if (!std::isfinite(z[i])) return BBP_EINVAL;
+  }
+  auto col = [&](int r, int cidx) -> double & { return z[(size_t)r * m + cidx]; };
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int r = 0; r < m; ++r) {
+          a += col(r, p) * col(r, p);
+          b += col(r, q) * col(r, q);
+          g += col(r, p) * col(r, q);
+        }
+        if (g == 0.0 || std::fabs(g) <= 1e-300) continue;
+        off = std::max(off, std::fabs(g) / std::sqrt(a * b));
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int r = 0; r < m; ++r) {
+          const double u = col(r, p), w = col(r, q);
+          col(r, p) = cs * u - sn * w;
+          col(r, q) = sn * u + cs * w;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+  double tr = 0.0;
+  for (int cidx = 0; cidx < m; ++cidx) {
+    double nrm = 0.0;
+    for (int r = 0; r < m; ++r) nrm += col(r, cidx) * col(r, cidx);
+    tr += std::sqrt(nrm);
+  }
+  *out = 0.5 * tr;
+  return BBP_OK;
 }
 
 bbp_status bbp_log_norm(bbp_ctx *c, double *log_abs, int32_t *sign) {

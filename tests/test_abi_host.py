@@ -158,3 +158,16 @@ def test_bench_lattice_terms():
     sites, bonds = bench.lattice_terms(CONFIGS["inf2x2_D4_b4_chi32"])
     assert sorted(map(tuple, sites.tolist())) == [(0, 0), (0, 1), (1, 0), (1, 1)]
     assert len(bonds) == 8 and len(set(bonds)) == 8
+
+
+def test_trace_distance_on_the_host():
+    # bbp_trace_distance is host arithmetic: no device needed
+    import numpy as np
+    from oracle.blockbp import trace_distance
+    from paper_2301_05844_amd import bbp
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal((4, 4)), rng.standard_normal((4, 4))
+    r, s = a @ a.T / np.trace(a @ a.T), b @ b.T / np.trace(b @ b.T)
+    assert abs(bbp.trace_distance(r, s) - trace_distance(r, s)) < 1e-13
+    p, q = np.diag([0.5, 0.3, 0.2, 0.0]), np.diag([0.25, 0.25, 0.25, 0.25])
+    assert abs(bbp.trace_distance(p, q) - 0.5 * (0.25 + 0.05 + 0.05 + 0.25)) < 1e-15
