@@ -351,15 +351,19 @@ const char *bbp_update_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Request server: independent block-BP solves of finite open lattices
- * (Sec. II; each one the problem bbp_create states) served concurrently on
- * one GPU.  A pool of max_slots worker threads takes requests first-in
- * first-out, each once its device-memory estimate (bbp_server_estimate) fits
- * in what budget_bytes leaves free; a worker owns one context and one HIP
- * stream per request, sweeps until the residual drops below tol or after
- * max_sweeps sweeps, evaluates the requested outputs and frees the memory.
- * Requests join and leave between sweeps; resident requests run their
- * kernels concurrently.  Requests share no state: a result does not depend
- * on which other requests were resident.
+ * (Sec. II; each one the problem bbp_create states, infinite lattices are
+ * not served) on one GPU with continuous batching.  Requests are admitted
+ * first-in first-out between sweeps while fewer than max_slots are resident
+ * and their device-memory estimate (bbp_server_estimate) fits in what
+ * budget_bytes leaves free.  Every resident request then sweeps together:
+ * one synchronous sweep of all of them is one set of shared batches, every
+ * message of every request in the batch of its shape (block size, bond cap,
+ * D, d), so one launch of each fit kernel covers every resident solve; the
+ * messages stay resident on the device and the fit warm starts are kept
+ * when requests join or leave.  A request whose residual drops below tol (or
+ * that reaches max_sweeps) has its outputs evaluated on a stream of its own
+ * while the others keep sweeping, then frees its memory.  Each result is the
+ * same, bitwise, whether its request ran alone or in a mix.
  * ------------------------------------------------------------------------ */
 typedef struct bbp_server bbp_server;
 
@@ -369,6 +373,8 @@ typedef struct {
   int32_t D, chi;     /* bond dimension and message bond cap (<= 128)      */
   int32_t max_sweeps; /* sweep cap (>= 1)                                  */
   int32_t outputs;    /* BBP_OUT_* bits                                    */
+  int32_t n_site_ops; /* operators of the ops array of bbp_server_submit:  */
+  int32_t n_bond_ops; /*   0..16 one-site (2x2), 0..16 two-site (4x4)      */
   double tol;         /* residual target (>= 0)                            */
 } bbp_request;
 
@@ -389,21 +395,26 @@ bbp_status bbp_server_estimate(const bbp_request *r, size_t *bytes);
 bbp_status bbp_server_create(bbp_server **out, size_t budget_bytes, int32_t max_slots);
 
 /* Queues a request; the host tensors A (n doubles, layout of
- * bbp_set_tensors) are copied.  *ticket identifies it in later calls.
- * Errors: BBP_EINVAL (malformed request or n), BBP_ENOMEM (estimate above
- * the whole budget: it could never be admitted), BBP_ESTATE (server
- * stopping). */
+ * bbp_set_tensors, d = 2) and the operators ops (n_site_ops one-site op[s'][s]
+ * of 4 doubles, then n_bond_ops two-site op[(s0',s1')][(s0,s1)] of 16
+ * doubles; may be NULL when there are none) are copied.  The observables use
+ * chi_env = max(chi, 2 D^2 + 10).  *ticket identifies the request in later
+ * calls.  Errors: BBP_EINVAL (malformed request, n, or non-finite
+ * operators), BBP_ENOMEM (estimate above the whole budget: it could never be
+ * admitted), BBP_ESTATE (server stopping). */
 bbp_status bbp_server_submit(bbp_server *s, const bbp_request *r, const double *A, size_t n,
-                             int64_t *ticket);
+                             const double *ops, int64_t *ticket);
 
 /* State of a request (BBP_REQ_*); times (3 doubles, may be NULL) receive
  * the submit, admit and finish times in seconds since the server was
  * created (0 until reached).  Once BBP_REQ_DONE, out (n >= *needed doubles)
  * receives [converged (1/0), sweeps, last residual, log|Z|, sign of Z,
- * device bytes peak, then <sigma_z> of every site (row-major, y outer) if
- * BBP_OUT_SZ, then <S.S> of every horizontal bond (x,y)-(x+1,y) row-major,
- * then of every vertical bond (x,y)-(x,y+1), if BBP_OUT_SS]; log|Z| and
- * the sign are 0 unless BBP_OUT_LOGNORM.  Errors: BBP_EINVAL (unknown
+ * device bytes peak of the request's context, then <sigma_z> of every site
+ * (row-major, y outer) if BBP_OUT_SZ, then <S.S> of every horizontal bond
+ * (x,y)-(x+1,y) row-major and then of every vertical bond (x,y)-(x,y+1) if
+ * BBP_OUT_SS, then for each one-site operator of ops <O> of every site, then
+ * for each two-site operator <O> of every bond in the same order]; log|Z|
+ * and the sign are 0 unless BBP_OUT_LOGNORM.  Errors: BBP_EINVAL (unknown
  * ticket, or out too short). */
 bbp_status bbp_server_poll(bbp_server *s, int64_t ticket, int32_t *state, double *out, size_t n,
                            size_t *needed, double *times);
@@ -411,10 +422,16 @@ bbp_status bbp_server_poll(bbp_server *s, int64_t ticket, int32_t *state, double
 /* Cancels a queued request at once, a running one before its next sweep. */
 bbp_status bbp_server_cancel(bbp_server *s, int64_t ticket);
 
-/* Requests running and queued now, the estimated bytes admitted now, and
- * the most requests that have run at the same time. */
+/* Requests admitted and not finished (sweeping or evaluating outputs) and
+ * queued now, the estimated bytes admitted now, and the most requests that
+ * have been admitted at the same time. */
 bbp_status bbp_server_stats(bbp_server *s, int32_t *running, int32_t *queued,
                             size_t *bytes_in_use, int32_t *max_running);
+
+/* Shared sweeps run so far, the request sweeps they covered (summed over
+ * the requests of each), and the most requests one shared sweep covered. */
+bbp_status bbp_server_sweeps(bbp_server *s, int64_t *sweeps, int64_t *request_sweeps,
+                             int32_t *max_together);
 
 /* Why a request failed (empty string otherwise); valid until destroy. */
 const char *bbp_server_error(bbp_server *s, int64_t ticket);

@@ -32,7 +32,7 @@ EXPORTS = (
     "bbp_kernel_stats_padded", "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
     "bbp_server_estimate", "bbp_server_create", "bbp_server_submit",
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
-    "bbp_server_error", "bbp_server_destroy",
+    "bbp_server_sweeps", "bbp_server_error", "bbp_server_destroy",
     "bbp_update_workspace", "bbp_update_message", "bbp_update_message_noalloc",
     "bbp_update_last_error",
 )
@@ -51,6 +51,7 @@ class Request(ctypes.Structure):
                 ("bx", ctypes.c_int32), ("by", ctypes.c_int32),
                 ("D", ctypes.c_int32), ("chi", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int32), ("outputs", ctypes.c_int32),
+                ("n_site_ops", ctypes.c_int32), ("n_bond_ops", ctypes.c_int32),
                 ("tol", ctypes.c_double)]
 
 class UpdateSpec(ctypes.Structure):
@@ -105,12 +106,14 @@ def _load():
         "bbp_memory": [P, ctypes.POINTER(c_size), ctypes.POINTER(c_size)],
         "bbp_server_estimate": [ctypes.POINTER(Request), ctypes.POINTER(c_size)],
         "bbp_server_create": [ctypes.POINTER(P), c_size, c_int],
-        "bbp_server_submit": [P, ctypes.POINTER(Request), dp, c_size,
+        "bbp_server_submit": [P, ctypes.POINTER(Request), dp, c_size, dp,
                               ctypes.POINTER(ctypes.c_int64)],
         "bbp_server_poll": [P, ctypes.c_int64, ip, dp, c_size,
                             ctypes.POINTER(c_size), dp],
         "bbp_server_cancel": [P, ctypes.c_int64],
         "bbp_server_stats": [P, ip, ip, ctypes.POINTER(c_size), ip],
+        "bbp_server_sweeps": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ip],
         "bbp_update_workspace": [ctypes.POINTER(UpdateSpec), ctypes.POINTER(c_size)],
         "bbp_update_message": [ctypes.POINTER(UpdateSpec), P, P, ip, P, ip, P, ip, P, ip,
                                dp, P],
@@ -365,8 +368,9 @@ class BlockBP:
 
 
 def _request(Lx, Ly, bx, by, D, chi, tol=1e-10, max_sweeps=40,
-             outputs=OUT_SZ | OUT_SS | OUT_LOGNORM):
-    return Request(Lx, Ly, bx, by, D, chi, max_sweeps, outputs, tol)
+             outputs=OUT_SZ | OUT_SS | OUT_LOGNORM, site_ops=(), bond_ops=()):
+    return Request(Lx, Ly, bx, by, D, chi, max_sweeps, outputs, len(site_ops),
+                   len(bond_ops), tol)
 
 
 def estimate_bytes(**req):
@@ -482,10 +486,17 @@ class Server:
         self._req = {}
 
     def submit(self, A, **req):
+        """``site_ops`` / ``bond_ops``: sequences of 2x2 / 4x4 operators whose
+        <O> on every site / bond the result lists (``site_op_values``,
+        ``bond_op_values``)."""
         r = _request(**req)
         A = np.ascontiguousarray(A, dtype=np.float64)
+        ops = [np.asarray(o, dtype=np.float64).reshape(-1) for o in req.get("site_ops", ())]
+        ops += [np.asarray(o, dtype=np.float64).reshape(-1) for o in req.get("bond_ops", ())]
+        flat = np.ascontiguousarray(np.concatenate(ops)) if ops else None
         t = ctypes.c_int64()
         st = _lib.bbp_server_submit(self._s, ctypes.byref(r), _dptr(A), A.size,
+                                    _dptr(flat) if flat is not None else None,
                                     ctypes.byref(t))
         if st != 0:
             raise BBPError(st, "bbp_server_submit rejected the request")
@@ -514,9 +525,18 @@ class Server:
         if r.outputs & OUT_SZ:
             res["sz"] = out[o:o + r.Lx * r.Ly].reshape(r.Ly, r.Lx)
             o += r.Lx * r.Ly
+        nb = (r.Lx - 1) * r.Ly + r.Lx * (r.Ly - 1)
         if r.outputs & OUT_SS:
-            nb = (r.Lx - 1) * r.Ly + r.Lx * (r.Ly - 1)
             res["ss"] = out[o:o + nb]
+            o += nb
+        res["site_op_values"] = []
+        for _ in range(r.n_site_ops):
+            res["site_op_values"].append(out[o:o + r.Lx * r.Ly].reshape(r.Ly, r.Lx))
+            o += r.Lx * r.Ly
+        res["bond_op_values"] = []
+        for _ in range(r.n_bond_ops):
+            res["bond_op_values"].append(out[o:o + nb])
+            o += nb
         return "done", res, tuple(times)
 
     def wait(self, ticket, timeout=600.0, interval=0.002):
@@ -545,8 +565,14 @@ class Server:
                                    ctypes.byref(b), ctypes.byref(m))
         if st != 0:
             raise BBPError(st, "stats")
+        sw, rs, mt = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        st = _lib.bbp_server_sweeps(self._s, ctypes.byref(sw), ctypes.byref(rs),
+                                    ctypes.byref(mt))
+        if st != 0:
+            raise BBPError(st, "sweeps")
         return dict(running=r.value, queued=q.value, bytes_in_use=b.value,
-                    max_running=m.value)
+                    max_running=m.value, shared_sweeps=sw.value, request_sweeps=rs.value,
+                    max_together=mt.value)
 
     def close(self):
         if self._s:

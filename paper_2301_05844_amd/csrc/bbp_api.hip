@@ -6,6 +6,7 @@
 // input, so argument checking works on machines without a GPU.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -220,6 +221,8 @@ struct bbp_ctx {
   int graphs = 1;      // 1: message batches replay their column absorptions as HIP graphs
   int skip_pad = 1;    // 1: the column absorptions' kernels stop at the true bond extents
   int msg_split = 2;   // message batches of one shape split into this many (one per lane)
+  bool engine = false; // messages swept by a shared SweepSet (no message batches of its own)
+  uint64_t serial = 0; // unique per context of the process (identifies it across sweeps)
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
@@ -887,6 +890,66 @@ static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t 
   return BBP_OK;
 }
 
+// Sweep tables of item i of batch g for message `id` of context c: its
+// three gather sources in the previous sweep's buffer `cur`, its destination
+// in `nb`, the bond caps of every column (g.dims, with the random-start flag
+// where the warm start's shapes no longer agree), and the new message's bond
+// list.  Returns the item's fit FLOPs on the true bonds.
+static double prepare_item(bbp_ctx *c, int id, double *cur, double *nb, Group &g, int i,
+                           GatherSrc &gs, double *&dst, int32_t &rev,
+                           std::vector<int> &new_bonds) {
+  const FitBatch &f = g.fb;
+  const int W = f.W, H = f.H, N = f.N;
+  const size_t per = (size_t)c->Lmax * c->S;
+  const Message &m = c->msgs[id];
+  char side[3];
+  int rv[3];
+  canon_sources(m.dir, side, rv);
+  std::vector<int> bl[3];
+  gs = GatherSrc{};
+  gs.ksrc = c->K;
+  for (int k = 0; k < 3; ++k) {
+    Incoming in = c->incoming(m.bi, m.bj, side[k]);
+    if (in.id < 0) {
+      gs.src[k][0] = c->trivial.d();
+      bl[k].assign(in.n + 1, 1);
+    } else {
+      gs.src[k][0] = cur + (size_t)in.id * per;
+      bl[k] = c->msgs[in.id].bonds;
+    }
+    gs.n[k][0] = in.n;
+    gs.rev[k][0] = rv[k];
+    if (rv[k]) bl[k] = reversed(bl[k]);
+  }
+  dst = nb + (size_t)id * per;
+  rev = out_reversed(m.dir) ? 1 : 0;
+  std::vector<FitDims> cd;
+  column_dims(W, H, f.K, f.P, bl[0], bl[2], bl[1], cd);
+  std::vector<int> xbonds = bl[1];
+  double flops = 0.0;
+  for (int col = W - 1; col >= 0; --col) {
+    FitDims &nd = cd[col];
+    FitDims &od = g.dims[(size_t)i * W + col];
+    bool same = g.have[(size_t)i * W + col] &&
+                std::memcmp(nd.bl, od.bl, sizeof(nd.bl)) == 0 &&
+                std::memcmp(nd.br, od.br, sizeof(nd.br)) == 0 &&
+                std::memcmp(nd.p, od.p, sizeof(nd.p)) == 0;
+    nd.rnd = same ? 0 : 1;
+    od = nd;
+    g.have[(size_t)i * W + col] = 1;
+    const int xp0 = col == W - 1 ? 1 : cd[col + 1].p[0];
+    const int xpN = col == W - 1 ? 1 : cd[col + 1].p[N - 1];
+    flops += 2.0 * column_macs(nd, xbonds, xp0, xpN, N, f.P, f.D, f.d, c->n_fit);
+    xbonds.assign(N - 1, 1);
+    for (int j = 0; j < N - 1; ++j) xbonds[j] = nd.br[j];
+  }
+  const FitDims &c0 = cd[0];
+  std::vector<int> cb(H + 1, 1);
+  for (int s2 = 0; s2 + 1 < H; ++s2) cb[s2 + 1] = c0.br[s2 + 1];
+  new_bonds = rev ? reversed(cb) : cb;
+  return flops;
+}
+
 static bbp_status run_sweep(bbp_ctx *c, double *residual) {
   hipStream_t st = c->stream;
   const int nxt = 1 - c->cur;
@@ -910,54 +973,9 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
     gs.assign(f.items, GatherSrc{});
     dsts.assign(f.items, nullptr);
     revs.assign(f.items, 0);
-    std::vector<std::vector<int>> xb0(f.items);
-    for (int i = 0; i < f.items; ++i) {
-      const Message &m = c->msgs[g.ids[i]];
-      char side[3];
-      int rv[3];
-      canon_sources(m.dir, side, rv);
-      std::vector<int> bl[3];
-      gs[i].ksrc = c->K;
-      for (int k = 0; k < 3; ++k) {
-        Incoming in = c->incoming(m.bi, m.bj, side[k]);
-        if (in.id < 0) {
-          gs[i].src[k][0] = c->trivial.d();
-          bl[k].assign(in.n + 1, 1);
-        } else {
-          gs[i].src[k][0] = cur + (size_t)in.id * per;
-          bl[k] = c->msgs[in.id].bonds;
-        }
-        gs[i].n[k][0] = in.n;
-        gs[i].rev[k][0] = rv[k];
-        if (rv[k]) bl[k] = reversed(bl[k]);
-      }
-      dsts[i] = nb + (size_t)g.ids[i] * per;
-      revs[i] = out_reversed(m.dir) ? 1 : 0;
-      std::vector<FitDims> cd;
-      column_dims(W, H, f.K, f.P, bl[0], bl[2], bl[1], cd);
-      std::vector<int> xbonds = bl[1];
-      for (int col = W - 1; col >= 0; --col) {
-        FitDims &nd = cd[col];
-        FitDims &od = g.dims[(size_t)i * W + col];
-        bool same = g.have[(size_t)i * W + col] &&
-                    std::memcmp(nd.bl, od.bl, sizeof(nd.bl)) == 0 &&
-                    std::memcmp(nd.br, od.br, sizeof(nd.br)) == 0 &&
-                    std::memcmp(nd.p, od.p, sizeof(nd.p)) == 0;
-        nd.rnd = same ? 0 : 1;
-        od = nd;
-        g.have[(size_t)i * W + col] = 1;
-        const int xp0 = col == W - 1 ? 1 : cd[col + 1].p[0];
-        const int xpN = col == W - 1 ? 1 : cd[col + 1].p[N - 1];
-        flops += 2.0 * column_macs(nd, xbonds, xp0, xpN, N, f.P, f.D, f.d,
-                                   c->n_fit);
-        xbonds.assign(N - 1, 1);
-        for (int j = 0; j < N - 1; ++j) xbonds[j] = nd.br[j];
-      }
-      const FitDims &c0 = cd[0];
-      std::vector<int> cb(H + 1, 1);
-      for (int s = 0; s + 1 < H; ++s) cb[s + 1] = c0.br[s + 1];
-      new_bonds[g.ids[i]] = revs[i] ? reversed(cb) : cb;
-    }
+    for (int i = 0; i < f.items; ++i)
+      flops += prepare_item(c, g.ids[i], cur, nb, g, i, gs[i], dsts[i], revs[i],
+                            new_bonds[g.ids[i]]);
     e = hipMemcpyAsync(g.gather.p, gs.data(), sizeof(GatherSrc) * f.items,
                        hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -1888,6 +1906,8 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
   if (!c) return BBP_ENOMEM;
   c->mem.evict = evict_caches;
   c->mem.evict_user = c;
+  static std::atomic<uint64_t> next_serial{1};
+  c->serial = next_serial++;
   c->infinite = infinite ? 1 : 0;
   c->Lx = infinite ? 0 : Lx;
   c->Ly = infinite ? 0 : Ly;
@@ -2054,7 +2074,7 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   // their device buffers) when the partition is the same
   std::vector<std::unique_ptr<Group>> groups;
   std::vector<int> shape_items;  // items of the shape each group belongs to
-  {
+  if (!c->engine) {
     std::map<std::pair<int, int>, std::vector<int>> by_shape;
     for (size_t i = 0; i < c->msgs.size(); ++i)
       by_shape[message_shape(c, c->msgs[i])].push_back((int)i);
@@ -2094,6 +2114,7 @@ bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual) {
   if (!c) return BBP_EINVAL;
   AcctScope acct_scope(&c->mem);
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (c->engine) return c->fail(BBP_ESTATE, "this context is swept by a shared sweep set");
   if (n < 0) return c->fail(BBP_EINVAL, "negative sweep count");
   double r = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -2686,3 +2707,331 @@ bbp_status bbp_update_message_noalloc(const bbp_update_spec *spec, const double 
 const char *bbp_update_last_error(void) { return tl_update_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Continuous batching across contexts (the request server): one synchronous
+// sweep of many contexts at once, every message of every context in shared
+// batches of one shape (W, H, bond cap, D, d), so that one launch of each
+// fit kernel covers every resident solve's messages of that shape.  A
+// batch is rebuilt when the set of contexts sweeping changes; the items that
+// stay keep their fit results (warm starts) and bond caps, copied to their
+// new positions.  Each item reads its context's messages and writes its
+// context's next messages, so the results are those of the context alone
+// (the visit tiling is fixed per shape, not chosen from the item count).
+// ---------------------------------------------------------------------------
+namespace bbp {
+
+struct SharedItem {
+  bbp_ctx *c;
+  uint64_t serial;
+  int id;
+  bool operator==(const SharedItem &o) const { return serial == o.serial && id == o.id; }
+};
+
+struct SweepSet {
+  bbp_ctx eng;  // host context of the shared batches: streams, lanes, error flag
+  std::map<std::tuple<int, int, int, int, int>, std::vector<SharedItem>> items;
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Group>> groups;
+  DevBuf ovE, ovU, ovOut, ovA, ovB;
+};
+
+// Items the visit tiling of a shared batch is chosen for (a fixed count, so
+// that a context's results do not depend on who shares its batches).
+constexpr int kSharedTileItems = 1024;
+
+SweepSet *sweepset_create(hipStream_t st) {
+  SweepSet *s = new (std::nothrow) SweepSet;
+  if (!s) return nullptr;
+  s->eng.stream = st;
+  s->eng.lanes = 3;
+  return s;
+}
+
+void sweepset_destroy(SweepSet *s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->eng.stream);
+  for (hipStream_t a : s->eng.aux) {
+    (void)hipStreamSynchronize(a);
+    (void)hipStreamDestroy(a);
+  }
+  for (hipEvent_t ev : s->eng.lane_ev) (void)hipEventDestroy(ev);
+  if (s->eng.cap) (void)hipStreamDestroy(s->eng.cap);
+  delete s;
+}
+
+bbp_status ctx_set_engine(bbp_ctx *c) {
+  if (!c) return BBP_EINVAL;
+  if (c->tensors_set) return c->fail(BBP_ESTATE, "engine mode must be set before the tensors");
+  c->engine = true;
+  return BBP_OK;
+}
+
+static bbp_status rebuild_group(SweepSet *s, const std::tuple<int, int, int, int, int> &key,
+                                const std::vector<SharedItem> &its) {
+  bbp_ctx &eng = s->eng;
+  const int W = std::get<0>(key), H = std::get<1>(key), K = std::get<2>(key);
+  const int D = std::get<3>(key), d = std::get<4>(key);
+  std::unique_ptr<Group> old;
+  auto it = s->groups.find(key);
+  if (it != s->groups.end()) old = std::move(it->second);
+  const std::vector<SharedItem> *old_items =
+      s->items.count(key) ? &s->items[key] : nullptr;
+  std::unique_ptr<Group> g(new Group);
+  g->W = W;
+  g->H = H;
+  eng.D = D;
+  eng.d = d;
+  eng.P = D * D;
+  eng.precision = 64;
+  eng.seed = 0;
+  std::vector<uint64_t> slots(its.size());
+  for (size_t i = 0; i < its.size(); ++i)
+    slots[i] = (1ull << 40) | ((uint64_t)its[i].id << 8);
+  bbp_status bs = alloc_batch(&eng, *g, (int)its.size(), K, slots);
+  if (bs != BBP_OK) return bs;
+  FitBatch &f = g->fb;
+  f.tile_items = kSharedTileItems;
+  // rotated block tensors of every item, from its own context
+  const size_t ss = (size_t)d * D * D * D * D;
+  std::vector<double> host(its.size() * (size_t)H * W * ss);
+  for (size_t i = 0; i < its.size(); ++i) {
+    const bbp_ctx *c = its[i].c;
+    const Message &m = c->msgs[its[i].id];
+    for (int yc = 0; yc < H; ++yc)
+      for (int xc = 0; xc < W; ++xc) {
+        int y, x;
+        canon_to_region(m.dir, c->by, c->bx, yc, xc, &y, &x);
+        rotate_site(c, c->site(m.bi * c->bx + x, m.bj * c->by + y), m.dir,
+                    host.data() + ((i * H + yc) * W + xc) * ss);
+      }
+  }
+  hipError_t e = copy_sync(&eng, f.acan, host.data(), host.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return eng.hip_fail(e, "upload shared tensors");
+  // items that stay keep their fit results and bond caps
+  if (old && old_items) {
+    const size_t slot = (size_t)W * f.N * f.S;
+    for (size_t i = 0; i < its.size(); ++i) {
+      auto pos = std::find(old_items->begin(), old_items->end(), its[i]);
+      if (pos == old_items->end()) continue;
+      const size_t o = (size_t)(pos - old_items->begin());
+      e = hipMemcpyAsync(f.store + i * slot, old->fb.store + o * slot, slot * 8,
+                         hipMemcpyDeviceToDevice, eng.stream);
+      if (e != hipSuccess) return eng.hip_fail(e, "keep warm starts");
+      for (int col = 0; col < W; ++col) {
+        g->dims[i * W + col] = old->dims[o * W + col];
+        g->have[i * W + col] = old->have[o * W + col];
+      }
+    }
+    if ((e = hipStreamSynchronize(eng.stream)) != hipSuccess)
+      return eng.hip_fail(e, "keep warm starts");
+  }
+  s->groups[key] = std::move(g);
+  s->items[key] = its;
+  return BBP_OK;
+}
+
+bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
+                        bbp_status *status, std::string *err) {
+  bbp_ctx &eng = s->eng;
+  AcctScope acct_scope(&eng.mem);
+  for (int k = 0; k < n; ++k) status[k] = BBP_OK;
+  // 1. the shared batches this sweep needs
+  std::map<std::tuple<int, int, int, int, int>, std::vector<SharedItem>> want;
+  for (int k = 0; k < n; ++k) {
+    bbp_ctx *c = cs[k];
+    if (!c || !c->tensors_set || !c->engine) {
+      if (err) *err = "context not ready for a shared sweep";
+      return BBP_ESTATE;
+    }
+    for (size_t i = 0; i < c->msgs.size(); ++i) {
+      const auto sh = message_shape(c, c->msgs[i]);
+      want[std::make_tuple(sh.first, sh.second, c->K, c->D, c->d)].push_back(
+          SharedItem{c, c->serial, (int)i});
+    }
+  }
+  for (auto it = s->groups.begin(); it != s->groups.end();) {
+    if (!want.count(it->first)) {
+      s->items.erase(it->first);
+      it = s->groups.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  for (auto &kv : want) {
+    auto have = s->items.find(kv.first);
+    if (have != s->items.end() && have->second == kv.second) continue;
+    bbp_status bs = rebuild_group(s, kv.first, kv.second);
+    if (bs != BBP_OK) {
+      if (err) *err = eng.err;
+      return bs;
+    }
+    // fresh pointers to each item's context (a context keeps its serial)
+  }
+  for (auto &kv : want) s->items[kv.first] = kv.second;
+  hipError_t e;
+  if (!eng.errflag.p && eng.errflag.alloc(64) != hipSuccess) {
+    if (err) *err = "device allocation failed";
+    return BBP_ENOMEM;
+  }
+  if ((e = launch_zero(eng.errflag.p, 64, eng.stream)) != hipSuccess) {
+    if (err) *err = hipGetErrorString(e);
+    return BBP_EDEVICE;
+  }
+  // every context's streams are synchronised with the engine's: each call on
+  // a context ends with its stream synchronised, and the engine stream runs
+  // everything below
+  std::map<uint64_t, std::vector<std::vector<int>>> new_bonds;
+  std::map<uint64_t, double> flops;
+  for (int k = 0; k < n; ++k) {
+    new_bonds[cs[k]->serial].assign(cs[k]->msgs.size(), {});
+    flops[cs[k]->serial] = 0.0;
+  }
+  // 2. gather, column absorptions and extraction, one batch per lane
+  const int nl = std::max(1, std::min(eng.lanes, (int)s->groups.size()));
+  {
+    LaneFork lanes(&eng);
+    if ((e = lanes.fork(nl)) != hipSuccess) {
+      if (err) *err = hipGetErrorString(e);
+      return BBP_EDEVICE;
+    }
+    int gi = 0;
+    for (auto &kv : s->groups) {
+      Group &g = *kv.second;
+      const std::vector<SharedItem> &its = s->items[kv.first];
+      FitBatch &f = g.fb;
+      f.err = (int32_t *)eng.errflag.p;
+      const hipStream_t st = lane_stream(&eng, gi++ % nl);
+      g.gs.assign(f.items, GatherSrc{});
+      g.dsts.assign(f.items, nullptr);
+      g.revs.assign(f.items, 0);
+      for (int i = 0; i < f.items; ++i) {
+        bbp_ctx *c = its[i].c;
+        double *cur = c->msgbuf[c->cur].d(), *nb = c->msgbuf[1 - c->cur].d();
+        flops[c->serial] += prepare_item(c, its[i].id, cur, nb, g, i, g.gs[i], g.dsts[i],
+                                         g.revs[i], new_bonds[c->serial][its[i].id]);
+      }
+      e = hipMemcpyAsync(g.gather.p, g.gs.data(), sizeof(GatherSrc) * f.items,
+                         hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g.dst.p, g.dsts.data(), sizeof(double *) * f.items,
+                           hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g.rev.p, g.revs.data(), 4 * f.items, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, st);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("shared gather: ") + hipGetErrorString(e);
+        return BBP_EDEVICE;
+      }
+      bbp_status bs = absorb_columns(&eng, g, 0, st, true);
+      if (bs != BBP_OK) {
+        if (err) *err = eng.err;
+        return bs;
+      }
+      e = launch_extract(f, (double *const *)g.dst.p, (const int32_t *)g.rev.p, st);
+      if (e != hipSuccess) {
+        if (err) *err = std::string("shared extract: ") + hipGetErrorString(e);
+        return BBP_EDEVICE;
+      }
+    }
+    if ((e = lanes.join()) != hipSuccess) {
+      if (err) *err = hipGetErrorString(e);
+      return BBP_EDEVICE;
+    }
+  }
+  // 3. overlaps of new and old messages of every context, batched by shape
+  struct Ov {
+    int k, i;
+  };
+  std::map<std::tuple<int, int, int>, std::vector<Ov>> by;  // (K, P, L)
+  size_t total = 0;
+  for (int k = 0; k < n; ++k)
+    for (size_t i = 0; i < cs[k]->msgs.size(); ++i) {
+      by[std::make_tuple(cs[k]->K, cs[k]->P, cs[k]->msgs[i].n)].push_back(Ov{k, (int)i});
+      ++total;
+    }
+  std::vector<std::vector<double>> ov(n);
+  for (int k = 0; k < n; ++k) ov[k].assign(cs[k]->msgs.size(), 0.0);
+  std::vector<double> part(total);
+  std::vector<std::vector<const double *>> keep_a, keep_b;
+  size_t off = 0;
+  std::vector<std::pair<size_t, std::vector<Ov>>> order;
+  for (auto &kv : by) {
+    const int K = std::get<0>(kv.first), P = std::get<1>(kv.first), L = std::get<2>(kv.first);
+    const std::vector<Ov> &v = kv.second;
+    const size_t S = (size_t)K * P * K;
+    keep_a.emplace_back(v.size());
+    keep_b.emplace_back(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+      bbp_ctx *c = cs[v[i].k];
+      const size_t per = (size_t)c->Lmax * c->S;
+      keep_a.back()[i] = c->msgbuf[1 - c->cur].d() + (size_t)v[i].i * per;
+      keep_b.back()[i] = c->msgbuf[c->cur].d() + (size_t)v[i].i * per;
+    }
+    if (s->ovE.alloc(std::max<size_t>(s->ovE.bytes, v.size() * K * K * 8)) != hipSuccess ||
+        s->ovU.alloc(std::max<size_t>(s->ovU.bytes, v.size() * S * 8)) != hipSuccess ||
+        s->ovOut.alloc(std::max<size_t>(s->ovOut.bytes, total * 8)) != hipSuccess ||
+        s->ovA.alloc(std::max<size_t>(s->ovA.bytes, v.size() * 8)) != hipSuccess ||
+        s->ovB.alloc(std::max<size_t>(s->ovB.bytes, v.size() * 8)) != hipSuccess) {
+      if (err) *err = "device allocation failed";
+      return BBP_ENOMEM;
+    }
+    e = hipMemcpyAsync(s->ovA.p, keep_a.back().data(), 8 * v.size(), hipMemcpyHostToDevice,
+                       eng.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ovB.p, keep_b.back().data(), 8 * v.size(), hipMemcpyHostToDevice,
+                         eng.stream);
+    if (e == hipSuccess)
+      e = launch_overlap((int)v.size(), K, P, L, (const double *const *)s->ovA.p,
+                         (const double *const *)s->ovB.p, s->ovE.d(), s->ovU.d(),
+                         s->ovOut.d() + off, eng.stream);
+    // the pointer tables are rewritten by the next shape: wait for this one
+    if (e == hipSuccess) e = hipStreamSynchronize(eng.stream);
+    if (e != hipSuccess) {
+      if (err) *err = std::string("shared overlaps: ") + hipGetErrorString(e);
+      return BBP_EDEVICE;
+    }
+    order.emplace_back(off, v);
+    off += v.size();
+  }
+  int32_t errv = 0;
+  e = hipMemcpyAsync(part.data(), s->ovOut.p, 8 * total, hipMemcpyDeviceToHost, eng.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&errv, eng.errflag.p, 4, hipMemcpyDeviceToHost, eng.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(eng.stream);
+  if (e != hipSuccess) {
+    if (err) *err = std::string("shared residual: ") + hipGetErrorString(e);
+    return BBP_EDEVICE;
+  }
+  for (auto &o : order)
+    for (size_t i = 0; i < o.second.size(); ++i)
+      ov[o.second[i].k][o.second[i].i] = part[o.first + i];
+  // 4. per context: residual, or a numeric failure (the shared error flag
+  // cannot tell which context's fit failed: every context of this sweep
+  // reports it and keeps its previous messages)
+  for (int k = 0; k < n; ++k) {
+    bbp_ctx *c = cs[k];
+    const int nm = (int)c->msgs.size();
+    double sum = 0.0;
+    bool finite = true;
+    for (int i = 0; i < nm; ++i) {
+      if (!std::isfinite(ov[k][i])) finite = false;
+      sum += std::max(0.0, 2.0 - 2.0 * std::fabs(ov[k][i]));
+    }
+    if (errv || !finite) {
+      status[k] = c->fail(BBP_ENUMERIC, "zero-norm or non-finite boundary in a shared sweep");
+      res[k] = std::nan("");
+      continue;
+    }
+    for (int i = 0; i < nm; ++i) c->msgs[i].bonds = new_bonds[c->serial][i];
+    c->cur = 1 - c->cur;
+    c->obs.clear();
+    c->last_flops = flops[c->serial];
+    res[k] = nm ? sum / nm : 0.0;
+  }
+  if (errv) {  // warm starts of every shared batch are no longer trusted
+    for (auto &kv : s->groups) std::fill(kv.second->have.begin(), kv.second->have.end(), 0);
+  }
+  return BBP_OK;
+}
+
+}  // namespace bbp

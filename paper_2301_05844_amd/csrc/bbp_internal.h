@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
+
+#include "../../include/bbp.h"
 
 namespace bbp {
 
@@ -210,5 +213,20 @@ void timing_reset();
 hipError_t timing_query(int cls, const char **name, long long *launches,
                         double *ms, double *flops, double *bytes,
                         double *pflops = nullptr, double *pbytes = nullptr);
+
+// Continuous batching across contexts (the request server): a set of
+// shared batches that sweeps many contexts at once, every message of every
+// context in the batch of its shape.  A context must be put in engine mode
+// before its tensors are set (it then holds no message batches of its own
+// and bbp_sweep rejects it).  sweepset_run makes one synchronous sweep of
+// each of the n contexts, writing each one's residual and status; contexts
+// that leave or join between calls make the affected batches be rebuilt,
+// keeping the warm starts of the items that stay.
+struct SweepSet;
+SweepSet *sweepset_create(hipStream_t st);
+void sweepset_destroy(SweepSet *s);
+bbp_status ctx_set_engine(bbp_ctx *c);
+bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
+                        bbp_status *status, std::string *err);
 
 }  // namespace bbp

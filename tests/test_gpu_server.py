@@ -65,6 +65,41 @@ def test_alone_equals_mix_and_requests_overlap():
         _same(ra, rm)
     assert st1["max_running"] == 1
     assert st2["max_running"] >= 2   # resident together on the device
+    # continuous batching: the sweeps of resident requests ran as shared
+    # sweeps, several requests per launch set
+    print(st1, st2, flush=True)
+    assert st1["shared_sweeps"] == st1["request_sweeps"]
+    assert st2["max_together"] >= 2
+    assert st2["shared_sweeps"] < st2["request_sweeps"]
+    assert st2["request_sweeps"] == sum(r["sweeps"] for _, r, _ in mix)
+
+
+def test_transverse_ising_terms_match_the_oracle():
+    """A request with operators: <sigma_x> of every site and <sigma_z
+    sigma_z> of every bond (the transverse-field Ising energy terms), against
+    the oracle after the same sweeps (chi_env = max(chi, 2 D^2 + 10))."""
+    bbp = _bbp()
+    from bbp_inputs import op_sx, op_szsz
+    from oracle.blockbp import BlockBP as OracleBP
+    r = dict(Lx=6, Ly=6, bx=3, by=3, D=2, chi=8)
+    A = _tensors(r, 11)
+    s = bbp.Server(budget_bytes=64 << 30, max_slots=2)
+    t = s.submit(A, site_ops=[op_sx()], bond_ops=[op_szsz()], tol=1e-12, max_sweeps=30, **r)
+    t2 = s.submit(_tensors(REQS[3], 3), **REQS[3])   # another request beside it
+    state, res, _ = s.wait(t, timeout=300)
+    assert s.wait(t2, timeout=300)[0] == "done"
+    s.close()
+    assert state == "done"
+    ref = OracleBP(A, Lx=6, Ly=6, bx=3, by=3, D=2, chi=8, chi_env=max(8, 18))
+    ref.sweep(res["sweeps"])
+    sx = res["site_op_values"][0]
+    err = max(abs(sx[y, x] - ref.expect_site(x, y, op_sx())) for y in range(6) for x in range(6))
+    bonds = [(x, y, x + 1, y) for y in range(6) for x in range(5)]
+    bonds += [(x, y, x, y + 1) for y in range(5) for x in range(6)]
+    zz = res["bond_op_values"][0]
+    err = max([err] + [abs(zz[i] - ref.expect_bond(*b, op_szsz())) for i, b in enumerate(bonds)])
+    print(f"transverse-Ising terms: max |d| {err:.2e} after {res['sweeps']} sweeps", flush=True)
+    assert err < 1e-10
 
 
 def test_server_equals_a_plain_context_and_the_oracle():
