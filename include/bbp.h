@@ -429,9 +429,12 @@ bbp_status bbp_server_stats(bbp_server *s, int32_t *running, int32_t *queued,
                             size_t *bytes_in_use, int32_t *max_running);
 
 /* Shared sweeps run so far, the request sweeps they covered (summed over
- * the requests of each), and the most requests one shared sweep covered. */
+ * the requests of each), the most requests one shared sweep covered, and
+ * (busy, 3 doubles, may be NULL) the seconds spent in shared sweeps, in
+ * admitting requests (contexts, tensor uploads), and in evaluating outputs
+ * (summed over the finisher threads). */
 bbp_status bbp_server_sweeps(bbp_server *s, int64_t *sweeps, int64_t *request_sweeps,
-                             int32_t *max_together);
+                             int32_t *max_together, double *busy);
 
 /* Why a request failed (empty string otherwise); valid until destroy. */
 const char *bbp_server_error(bbp_server *s, int64_t ticket);

@@ -113,7 +113,7 @@ def _load():
         "bbp_server_cancel": [P, ctypes.c_int64],
         "bbp_server_stats": [P, ip, ip, ctypes.POINTER(c_size), ip],
         "bbp_server_sweeps": [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                              ip],
+                              ip, dp],
         "bbp_update_workspace": [ctypes.POINTER(UpdateSpec), ctypes.POINTER(c_size)],
         "bbp_update_message": [ctypes.POINTER(UpdateSpec), P, P, ip, P, ip, P, ip, P, ip,
                                dp, P],
@@ -566,13 +566,15 @@ class Server:
         if st != 0:
             raise BBPError(st, "stats")
         sw, rs, mt = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        busy = np.zeros(3)
         st = _lib.bbp_server_sweeps(self._s, ctypes.byref(sw), ctypes.byref(rs),
-                                    ctypes.byref(mt))
+                                    ctypes.byref(mt), _dptr(busy))
         if st != 0:
             raise BBPError(st, "sweeps")
         return dict(running=r.value, queued=q.value, bytes_in_use=b.value,
                     max_running=m.value, shared_sweeps=sw.value, request_sweeps=rs.value,
-                    max_together=mt.value)
+                    max_together=mt.value, sweep_s=busy[0], admit_s=busy[1],
+                    outputs_s=busy[2])
 
     def close(self):
         if self._s:

@@ -222,6 +222,8 @@ struct bbp_ctx {
   int skip_pad = 1;    // 1: the column absorptions' kernels stop at the true bond extents
   int msg_split = 2;   // message batches of one shape split into this many (one per lane)
   bool engine = false; // messages swept by a shared SweepSet (no message batches of its own)
+  DevBuf rot;                   // engine mode: rotated block tensors of every message
+  std::vector<size_t> rot_off;  // doubles from rot's start to message i's block
   uint64_t serial = 0; // unique per context of the process (identifies it across sweeps)
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
@@ -2074,7 +2076,29 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   // their device buffers) when the partition is the same
   std::vector<std::unique_ptr<Group>> groups;
   std::vector<int> shape_items;  // items of the shape each group belongs to
-  if (!c->engine) {
+  if (c->engine) {  // the shared batches copy each message's rotated block from here
+    const size_t ssite = (size_t)c->d * c->P * c->P;
+    std::vector<double> host;
+    c->rot_off.assign(c->msgs.size(), 0);
+    for (size_t i = 0; i < c->msgs.size(); ++i) {
+      const Message &m = c->msgs[i];
+      const auto sh = message_shape(c, m);
+      c->rot_off[i] = host.size();
+      host.resize(host.size() + (size_t)sh.first * sh.second * ssite);
+      for (int yc = 0; yc < sh.second; ++yc)
+        for (int xc = 0; xc < sh.first; ++xc) {
+          int y, x;
+          canon_to_region(m.dir, c->by, c->bx, yc, xc, &y, &x);
+          rotate_site(c, c->site(m.bi * c->bx + x, m.bj * c->by + y), m.dir,
+                      host.data() + c->rot_off[i] + ((size_t)yc * sh.first + xc) * ssite);
+        }
+    }
+    if (c->rot.alloc(std::max<size_t>(host.size(), 1) * 8) != hipSuccess)
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    if (!host.empty() &&
+        copy_sync(c, c->rot.p, host.data(), host.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return c->fail(BBP_EDEVICE, "upload rotated tensors");
+  } else {
     std::map<std::pair<int, int>, std::vector<int>> by_shape;
     for (size_t i = 0; i < c->msgs.size(); ++i)
       by_shape[message_shape(c, c->msgs[i])].push_back((int)i);
@@ -2732,7 +2756,12 @@ struct SweepSet {
   bbp_ctx eng;  // host context of the shared batches: streams, lanes, error flag
   std::map<std::tuple<int, int, int, int, int>, std::vector<SharedItem>> items;
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Group>> groups;
+  // the previous batch of each shape, kept with its buffers: a rebuild fills
+  // it (when its capacity suffices) and the two swap
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Group>> spare;
   DevBuf ovE, ovU, ovOut, ovA, ovB;
+  DevBuf jobs;                      // copy jobs of a rebuild
+  std::vector<CopyJob> jobs_host;
 };
 
 // Items the visit tiling of a shared batch is chosen for (a fixed count, so
@@ -2759,6 +2788,13 @@ void sweepset_destroy(SweepSet *s) {
   delete s;
 }
 
+void sweepset_set_allocator(SweepSet *s, bbp_alloc_fn alloc, bbp_free_fn free_, void *user) {
+  s->eng.mem.alloc_fn = alloc;
+  s->eng.mem.free_fn = free_;
+  s->eng.mem.user = user;
+  s->eng.mem.stream = &s->eng.stream;
+}
+
 bbp_status ctx_set_engine(bbp_ctx *c) {
   if (!c) return BBP_EINVAL;
   if (c->tensors_set) return c->fail(BBP_ESTATE, "engine mode must be set before the tensors");
@@ -2771,60 +2807,64 @@ static bbp_status rebuild_group(SweepSet *s, const std::tuple<int, int, int, int
   bbp_ctx &eng = s->eng;
   const int W = std::get<0>(key), H = std::get<1>(key), K = std::get<2>(key);
   const int D = std::get<3>(key), d = std::get<4>(key);
-  std::unique_ptr<Group> old;
-  auto it = s->groups.find(key);
-  if (it != s->groups.end()) old = std::move(it->second);
-  const std::vector<SharedItem> *old_items =
-      s->items.count(key) ? &s->items[key] : nullptr;
-  std::unique_ptr<Group> g(new Group);
-  g->W = W;
-  g->H = H;
+  const int n = (int)its.size();
+  int cap = 8;
+  while (cap < n) cap *= 2;
+  Group *old = s->groups.count(key) ? s->groups[key].get() : nullptr;
+  const std::vector<SharedItem> *old_items = s->items.count(key) ? &s->items[key] : nullptr;
+  std::unique_ptr<Group> g = std::move(s->spare[key]);
+  if (!g) {
+    g.reset(new Group);
+    g->W = W;
+    g->H = H;
+  }
   eng.D = D;
   eng.d = d;
   eng.P = D * D;
   eng.precision = 64;
   eng.seed = 0;
-  std::vector<uint64_t> slots(its.size());
-  for (size_t i = 0; i < its.size(); ++i)
-    slots[i] = (1ull << 40) | ((uint64_t)its[i].id << 8);
-  bbp_status bs = alloc_batch(&eng, *g, (int)its.size(), K, slots);
+  // buffers for `cap` items (kept from the spare when its capacity is the
+  // same; cleared again), the first n in use
+  std::vector<uint64_t> slots(cap, 0);
+  for (int i = 0; i < n; ++i) slots[i] = (1ull << 40) | ((uint64_t)its[i].id << 8);
+  bbp_status bs = alloc_batch(&eng, *g, cap, K, slots);
   if (bs != BBP_OK) return bs;
   FitBatch &f = g->fb;
+  f.items = n;
   f.tile_items = kSharedTileItems;
-  // rotated block tensors of every item, from its own context
-  const size_t ss = (size_t)d * D * D * D * D;
-  std::vector<double> host(its.size() * (size_t)H * W * ss);
-  for (size_t i = 0; i < its.size(); ++i) {
+  // each item's rotated block from its context; the fit results (warm
+  // starts) and bond caps of the items that stay from the previous batch
+  const size_t ablock = (size_t)H * W * d * D * D * D * D;
+  const size_t fslot = (size_t)W * f.N * f.S;
+  s->jobs_host.clear();
+  for (int i = 0; i < n; ++i) {
     const bbp_ctx *c = its[i].c;
-    const Message &m = c->msgs[its[i].id];
-    for (int yc = 0; yc < H; ++yc)
-      for (int xc = 0; xc < W; ++xc) {
-        int y, x;
-        canon_to_region(m.dir, c->by, c->bx, yc, xc, &y, &x);
-        rotate_site(c, c->site(m.bi * c->bx + x, m.bj * c->by + y), m.dir,
-                    host.data() + ((i * H + yc) * W + xc) * ss);
-      }
-  }
-  hipError_t e = copy_sync(&eng, f.acan, host.data(), host.size() * 8, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return eng.hip_fail(e, "upload shared tensors");
-  // items that stay keep their fit results and bond caps
-  if (old && old_items) {
-    const size_t slot = (size_t)W * f.N * f.S;
-    for (size_t i = 0; i < its.size(); ++i) {
-      auto pos = std::find(old_items->begin(), old_items->end(), its[i]);
-      if (pos == old_items->end()) continue;
-      const size_t o = (size_t)(pos - old_items->begin());
-      e = hipMemcpyAsync(f.store + i * slot, old->fb.store + o * slot, slot * 8,
-                         hipMemcpyDeviceToDevice, eng.stream);
-      if (e != hipSuccess) return eng.hip_fail(e, "keep warm starts");
-      for (int col = 0; col < W; ++col) {
-        g->dims[i * W + col] = old->dims[o * W + col];
-        g->have[i * W + col] = old->have[o * W + col];
-      }
+    s->jobs_host.push_back(CopyJob{c->rot.d() + c->rot_off[its[i].id], f.acan + i * ablock,
+                                   (int64_t)ablock, 0, 0});
+    if (!old || !old_items) continue;
+    auto pos = std::find(old_items->begin(), old_items->end(), its[i]);
+    if (pos == old_items->end()) continue;
+    const size_t o = (size_t)(pos - old_items->begin());
+    s->jobs_host.push_back(CopyJob{old->fb.store + o * fslot, f.store + i * fslot,
+                                   (int64_t)fslot, 0, 0});
+    for (int col = 0; col < W; ++col) {
+      g->dims[(size_t)i * W + col] = old->dims[o * W + col];
+      g->have[(size_t)i * W + col] = old->have[o * W + col];
     }
-    if ((e = hipStreamSynchronize(eng.stream)) != hipSuccess)
-      return eng.hip_fail(e, "keep warm starts");
   }
+  hipError_t e = hipSuccess;
+  const size_t nj = s->jobs_host.size();
+  if (s->jobs.bytes < nj * sizeof(CopyJob) &&
+      s->jobs.alloc(nj * sizeof(CopyJob) * 2) != hipSuccess)
+    return eng.fail(BBP_ENOMEM, "device allocation failed");
+  e = copy_sync(&eng, s->jobs.p, s->jobs_host.data(), nj * sizeof(CopyJob),
+                hipMemcpyHostToDevice);
+  for (size_t o = 0; e == hipSuccess && o < nj; o += 60000)
+    e = launch_copy_jobs((const CopyJob *)s->jobs.p + o, (int)std::min<size_t>(60000, nj - o),
+                         K, D * D, eng.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(eng.stream);
+  if (e != hipSuccess) return eng.hip_fail(e, "shared batch setup");
+  if (s->groups.count(key)) s->spare[key] = std::move(s->groups[key]);
   s->groups[key] = std::move(g);
   s->items[key] = its;
   return BBP_OK;
@@ -2852,6 +2892,7 @@ bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
   for (auto it = s->groups.begin(); it != s->groups.end();) {
     if (!want.count(it->first)) {
       s->items.erase(it->first);
+      s->spare.erase(it->first);
       it = s->groups.erase(it);
     } else {
       ++it;

@@ -225,6 +225,8 @@ hipError_t timing_query(int cls, const char **name, long long *launches,
 struct SweepSet;
 SweepSet *sweepset_create(hipStream_t st);
 void sweepset_destroy(SweepSet *s);
+// Device memory of the shared batches through the given allocator.
+void sweepset_set_allocator(SweepSet *s, bbp_alloc_fn alloc, bbp_free_fn free_, void *user);
 bbp_status ctx_set_engine(bbp_ctx *c);
 bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
                         bbp_status *status, std::string *err);

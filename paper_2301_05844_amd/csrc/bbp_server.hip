@@ -75,6 +75,71 @@ size_t item_doubles(int W, int H, int Kc, int D) {
          (size_t)H * W * 2 * P * P + (size_t)Kc * Kc + (size_t)W + 64;
 }
 
+// Device memory of the server's contexts and shared batches: a block freed
+// by one request is kept for the next allocation of about its size, so that
+// admissions and departures (every few sweeps) call neither hipMalloc nor
+// hipFree, whose device-wide synchronisation would stall the resident
+// requests' work.  Beyond `limit` cached bytes the largest blocks are
+// released; everything is released when the server is destroyed.
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> free_blocks;  // size -> block
+  std::map<void *, size_t> size_of;           // every live or cached block
+  size_t cached = 0, limit = 0;
+
+  void release_all_cached() {
+    for (auto &kv : free_blocks) {
+      (void)hipFree(kv.second);
+      size_of.erase(kv.second);
+    }
+    free_blocks.clear();
+    cached = 0;
+  }
+  ~BlockCache() {
+    release_all_cached();
+    for (auto &kv : size_of) (void)hipFree(kv.first);
+  }
+};
+
+void *cache_alloc(size_t bytes, void *user) {
+  BlockCache *bc = (BlockCache *)user;
+  std::lock_guard<std::mutex> lk(bc->mu);
+  auto it = bc->free_blocks.lower_bound(bytes);
+  if (it != bc->free_blocks.end() && it->first <= bytes + bytes / 4) {
+    void *p = it->second;
+    bc->cached -= it->first;
+    bc->free_blocks.erase(it);
+    return p;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    bc->release_all_cached();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  bc->size_of[p] = bytes;
+  return p;
+}
+
+void cache_free(void *p, void *user) {
+  BlockCache *bc = (BlockCache *)user;
+  std::lock_guard<std::mutex> lk(bc->mu);
+  auto it = bc->size_of.find(p);
+  if (it == bc->size_of.end()) return;
+  bc->free_blocks.insert({it->second, p});
+  bc->cached += it->second;
+  while (bc->cached > bc->limit && !bc->free_blocks.empty()) {
+    auto big = std::prev(bc->free_blocks.end());
+    (void)hipFree(big->second);
+    bc->cached -= big->first;
+    bc->size_of.erase(big->second);
+    bc->free_blocks.erase(big);
+  }
+}
+
 }  // namespace
 
 struct bbp_server {
@@ -82,6 +147,8 @@ struct bbp_server {
   int32_t slots = 1, running = 0, max_running = 0;
   int64_t shared_sweeps = 0, request_sweeps = 0;  // sweeps run, and their requests summed
   int32_t max_together = 0;                       // most requests in one shared sweep
+  double t_sweep = 0.0, t_admit_s = 0.0, t_finish_s = 0.0;  // busy seconds: shared sweeps,
+                                                            // admissions, output evaluation
   bool stop = false;
   int64_t next_id = 1;
   std::mutex mu;
@@ -91,6 +158,7 @@ struct bbp_server {
   std::map<int64_t, std::shared_ptr<Request>> all;
   std::thread engine;
   std::vector<std::thread> finishers;
+  BlockCache cache;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -149,6 +217,8 @@ bool bbp_server::setup(Request &q) {
   if (why.empty() && (s = bbp_set_option(q.c, "chi_env", chi_env_of(r))) != BBP_OK)
     why = "chi_env";
   if (why.empty() && (s = bbp::ctx_set_engine(q.c)) != BBP_OK) why = "engine mode";
+  if (why.empty() && (s = bbp_set_allocator(q.c, cache_alloc, cache_free, &cache)) != BBP_OK)
+    why = "allocator";
   if (why.empty()) {
     if (hipSetDevice(0) == hipSuccess &&
         hipStreamCreateWithFlags(&q.st, hipStreamNonBlocking) == hipSuccess)
@@ -266,6 +336,7 @@ void bbp_server::engine_loop() {
   if (hipSetDevice(0) != hipSuccess || hipStreamCreateWithFlags(&est, hipStreamNonBlocking) != hipSuccess)
     est = nullptr;
   bbp::SweepSet *set = bbp::sweepset_create(est);
+  if (set) bbp::sweepset_set_allocator(set, cache_alloc, cache_free, &cache);
   std::vector<std::shared_ptr<Request>> resident;
   for (;;) {
     std::vector<std::shared_ptr<Request>> admit;
@@ -287,6 +358,7 @@ void bbp_server::engine_loop() {
         admit.push_back(q);
       }
     }
+    const double ta = now();
     for (auto &q : admit) {
       if (setup(*q) && set) {
         resident.push_back(q);
@@ -302,6 +374,7 @@ void bbp_server::engine_loop() {
     // cancellations take effect before the next sweep
     {
       std::lock_guard<std::mutex> lk(mu);
+      t_admit_s += now() - ta;
       for (auto &q : resident) q->cancelled = q->cancel;
     }
     for (auto it = resident.begin(); it != resident.end();) {
@@ -318,9 +391,11 @@ void bbp_server::engine_loop() {
     std::vector<double> res(cs.size(), 0.0);
     std::vector<bbp_status> st(cs.size(), BBP_OK);
     std::string why;
+    const double ts = now();
     bbp_status bs = bbp::sweepset_run(set, cs.data(), (int)cs.size(), res.data(), st.data(), &why);
     {
       std::lock_guard<std::mutex> lk(mu);
+      t_sweep += now() - ts;
       ++shared_sweeps;
       request_sweeps += (int64_t)resident.size();
       max_together = std::max(max_together, (int32_t)resident.size());
@@ -375,7 +450,12 @@ void bbp_server::finisher_loop() {
       q = finishing.front();
       finishing.pop_front();
     }
+    const double tf = now();
     outputs(*q);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      t_finish_s += now() - tf;
+    }
     done(q);
   }
 }
@@ -415,9 +495,10 @@ bbp_status bbp_server_create(bbp_server **out, size_t budget_bytes, int32_t max_
   if (!s) return BBP_ENOMEM;
   s->budget = budget_bytes;
   s->slots = max_slots;
+  s->cache.limit = budget_bytes / 4;
   try {
     s->engine = std::thread([s] { s->engine_loop(); });
-    for (int i = 0; i < 2; ++i) s->finishers.emplace_back([s] { s->finisher_loop(); });
+    for (int i = 0; i < 3; ++i) s->finishers.emplace_back([s] { s->finisher_loop(); });
   } catch (...) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -523,12 +604,17 @@ bbp_status bbp_server_stats(bbp_server *s, int32_t *running, int32_t *queued,
 }
 
 bbp_status bbp_server_sweeps(bbp_server *s, int64_t *sweeps, int64_t *request_sweeps,
-                             int32_t *max_together) {
+                             int32_t *max_together, double *busy) {
   if (!s) return BBP_EINVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   if (sweeps) *sweeps = s->shared_sweeps;
   if (request_sweeps) *request_sweeps = s->request_sweeps;
   if (max_together) *max_together = s->max_together;
+  if (busy) {
+    busy[0] = s->t_sweep;
+    busy[1] = s->t_admit_s;
+    busy[2] = s->t_finish_s;
+  }
   return BBP_OK;
 }
 
