@@ -208,9 +208,11 @@ def serve_stream(n, seed):
 
 
 def serve(args):
-    """Serving pattern: every request one at a time (the plain path), then
-    the same stream through the request server with Poisson arrivals at
-    several multiples of the one-at-a-time service rate."""
+    """Serving pattern: every request on a plain context of its own, one at a
+    time; every request through the request server one at a time; then the
+    same stream through the server (continuous batching) with Poisson
+    arrivals at several multiples of the one-at-a-time service rate, and all
+    of it submitted at once."""
     import threading
     import torch
     from paper_2301_05844_amd import bbp
@@ -224,7 +226,7 @@ def serve(args):
     def run(rate, slots):
         srv = bbp.Server(budget_bytes=budget, max_slots=slots)
         gaps = np.random.default_rng(args.seed + 1).exponential(1.0 / rate, len(reqs)) \
-            if rate else np.zeros(len(reqs))
+            if rate and rate != float("inf") else np.zeros(len(reqs))
         tickets = []
         t0 = time.perf_counter()
 
@@ -260,8 +262,38 @@ def serve(args):
         return res, dict(wall_s=wall, solves_per_s=len(res) / wall,
                          p50_ms=float(np.percentile(lat, 50) * 1e3),
                          p99_ms=float(np.percentile(lat, 99) * 1e3),
-                         max_running=st["max_running"])
+                         max_running=st["max_running"], shared_sweeps=st["shared_sweeps"],
+                         request_sweeps=st["request_sweeps"],
+                         max_together=st["max_together"],
+                         busy_s=dict(sweeps=st["sweep_s"], admit=st["admit_s"],
+                                     outputs=st["outputs_s"]))
 
+    # the plain per-context path: each request its own context, one at a time
+    log(f"serving: {len(reqs)} requests on plain contexts, one at a time")
+    t0 = time.perf_counter()
+    lat_plain = []
+    for i, (r, A) in enumerate(zip(spec, tens)):
+        ts = time.perf_counter()
+        g = bbp.BlockBP(Lx=r["Lx"], Ly=r["Ly"], bx=r["bx"], by=r["by"], D=r["D"], chi=r["chi"],
+                        chi_env=max(r["chi"], min(128, 2 * r["D"] ** 2 + 10)))
+        g.set_tensors(A)
+        res_ = 1.0
+        n = 0
+        while res_ >= TOL and n < MAX_SWEEPS:
+            res_ = g.sweep(1)
+            n += 1
+        sites, bonds = lattice_terms(dict(infinite=False, Lx=r["Lx"], Ly=r["Ly"]))
+        g.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+        g.expect_bonds(bonds, op_heis())
+        g.log_norm()
+        g.close()
+        lat_plain.append(time.perf_counter() - ts)
+        if (i + 1) % 32 == 0:
+            log(f"  {i + 1} plain solves done ({time.perf_counter() - t0:.1f} s)")
+    wall_plain = time.perf_counter() - t0
+    plain_ctx = dict(wall_s=wall_plain, solves_per_s=len(reqs) / wall_plain,
+                     p50_ms=float(np.percentile(lat_plain, 50) * 1e3),
+                     p99_ms=float(np.percentile(lat_plain, 99) * 1e3))
     log(f"serving: {len(reqs)} requests one at a time")
     plain_res, plain = run(0.0, 1)
     service = np.array([tm[2] - tm[1] for _, _, tm in plain_res])
@@ -277,11 +309,14 @@ def serve(args):
         m.update(rate_multiple=mult, arrival_rate=mult * mu, equal_to_alone=bool(same))
         lines.append(m)
     updates = sum(r[1]["sweeps"] for r in plain_res)
+    log("serving: the whole stream submitted at once")
+    res_all, burst = run(float("inf"), args.slots)
     out = dict(metric="p50/p99 solve latency and solves/s under Poisson arrivals",
                workload="serving stream (side 6..20, D 2..4, chi 2D^2, block 2..4)",
                requests=len(reqs), slots=args.slots, budget_bytes=budget,
+               plain_contexts=plain_ctx,
                one_at_a_time=dict(plain, service_rate=mu, total_sweeps=updates),
-               served=lines, data="synthetic", dtype="f64")
+               served=lines, all_at_once=burst, data="synthetic", dtype="f64")
     print(json.dumps(out), flush=True)
 
 
@@ -293,7 +328,7 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
     ctx.set_option("precision", 32)
     ctx.set_tensors(A)
     n32, res, prev = 0, 1.0, None
-    while n32 < MAX_SWEEPS:
+    while n32 < SEARCH_MAX_SWEEPS:
         res = ctx.sweep(1)
         n32 += 1
         if res < 1e-7 or (prev is not None and res > 0.5 * prev):
@@ -301,7 +336,7 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
         prev = res
     ctx.set_option("precision", 64)
     n64 = 0
-    while res >= TOL and n64 < MAX_SWEEPS:
+    while res >= TOL and n64 < SEARCH_MAX_SWEEPS:
         res = ctx.sweep(1)
         n64 += 1
     log(f"mixed precision: {n32} FP32 sweeps, then {n64} FP64 sweeps to {res:.2e}")
@@ -324,7 +359,7 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
     ctx.set_option("precision", 64)
     ctx.set_tensors(A)
     rt, nt = 1.0, 0
-    while rt >= 1e-14 and nt < MAX_SWEEPS:
+    while rt >= 1e-14 and nt < SEARCH_MAX_SWEEPS:
         rt = ctx.sweep(1)
         nt += 1
     szt = np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz()))
@@ -533,8 +568,8 @@ def main():
                  for s in stats},
         cpu_baseline=None,
     )
-    # the precision pattern: FP32 contractions exist for the D = 4 kernels
-    if not args.no_mixed and "tol" in cfg and not cfg["infinite"] and cfg["D"] == 4:
+    # the precision pattern (FP32 contractions in the fused visits)
+    if not args.no_mixed and "tol" in cfg and not cfg["infinite"]:
         line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
                                                   line["ms_per_step"])
     if not args.no_cpu_baseline:

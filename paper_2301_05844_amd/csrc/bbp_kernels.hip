@@ -836,10 +836,14 @@ constexpr int kVisitWaves = kVisitThreads / 64;
 // 16 x 16 output tiles spread over the waves, two per wave at a time when
 // there are enough; each tile keeps two accumulators (even and odd k-steps)
 // and its operands are read two k-steps ahead of the MFMAs.  afn/bfn read
-// operands (zero outside), sfn stores the result tile element.
-template <class AF, class BF, class SF>
+// operands (zero outside), sfn stores the result tile element.  T: FP64, or
+// FP32 on FP32 MFMA with FP32 accumulation.
+template <class T, class AF, class BF, class SF>
 __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
                                          BF bfn, SF sfn) {
+  typedef Mma<T> MM;
+  typedef typename MM::acc Acc;
+  const Acc zero = Acc{0, 0, 0, 0};
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lq = lane >> 4;
   const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
@@ -855,32 +859,31 @@ __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
       n0[h] = (r2 % tn) << 4;
     }
     const bool two = t0 + kVisitWaves < ntiles;
-    v4d acc[2][2] = {{{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}},
-                     {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}};
+    Acc acc[2][2] = {{zero, zero}, {zero, zero}};
     for (int k0 = 0; k0 < Kd; k0 += 8) {
-      double av[2][2], bv[2][2];
+      T av[2][2], bv[2][2];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const int k = k0 + 4 * u + lq, am = m0[h] + lr, bn = n0[h] + lr;
           const bool on = h == 0 || two;
-          av[h][u] = (on && am < M && k < Kd) ? afn(p[h], am, k) : 0.0;
-          bv[h][u] = (on && bn < N && k < Kd) ? bfn(p[h], k, bn) : 0.0;
+          av[h][u] = (on && am < M && k < Kd) ? afn(p[h], am, k) : (T)0;
+          bv[h][u] = (on && bn < N && k < Kd) ? bfn(p[h], k, bn) : (T)0;
         }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        acc[0][u] = mfma16(av[0][u], bv[0][u], acc[0][u]);
-        if (two) acc[1][u] = mfma16(av[1][u], bv[1][u], acc[1][u]);
+        acc[0][u] = MM::run(av[0][u], bv[0][u], acc[0][u]);
+        if (two) acc[1][u] = MM::run(av[1][u], bv[1][u], acc[1][u]);
       }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h == 1 && !two) break;
-      const v4d c = acc[h][0] + acc[h][1];
+      const Acc c = acc[h][0] + acc[h][1];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0[h] + 4 * r + lq, n = n0[h] + lr;
+        const int m = m0[h] + MM::crow(r, lq), n = n0[h] + lr;
         if (m < M && n < N) sfn(p[h], m, n, c[r]);
       }
     }
@@ -904,9 +907,12 @@ __host__ __device__ inline size_t visit_lds(int K, int P, int d, int TY, int TX)
 //   T3s[pair][wbk, wbb][lk, lb]
 //   Gs [tx, wb][yb]          stride pad_b(K)
 //   Ak, Ab [s][wf][a][l][wb] of the front view (ket and bra roles alike)
-template <int DT>
+template <int DT, class T>
 __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
-  extern __shared__ double sm[];
+  extern __shared__ double sm_raw[];
+  T *sm = reinterpret_cast<T *>(sm_raw);
+  typedef Mma<T> MM;
+  typedef typename MM::acc Acc;
   constexpr bool kFixed = DT > 0;
   const int D = kFixed ? DT : v.D;
   const int P = kFixed ? DT * DT : v.P;
@@ -915,20 +921,20 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   const int FS = pad_a(K), XS = pad_b(P * TX), T2S = pad_b(dP), GS = pad_b(K);
   const int it = blockIdx.y, y0 = blockIdx.x * TY;
   const int tid = threadIdx.x;
-  double *Fs = sm;
-  double *Xs = Fs + (size_t)TY * P * FS;
-  double *T1s = Xs + (size_t)K * XS;
-  double *T2s = T1s + (size_t)TY * TX * P2;
-  double *T3s = T2s + (size_t)TY * TX * P * T2S;
-  double *Gs = T3s + (size_t)TY * TX * P2;
-  double *Ak = Gs + (size_t)TX * P * GS;
-  double *Ab = Ak + (size_t)d * P2;
+  T *Fs = sm;
+  T *Xs = Fs + (size_t)TY * P * FS;
+  T *T1s = Xs + (size_t)K * XS;
+  T *T2s = T1s + (size_t)TY * TX * P2;
+  T *T3s = T2s + (size_t)TY * TX * P * T2S;
+  T *Gs = T3s + (size_t)TY * TX * P2;
+  T *Ak = Gs + (size_t)TX * P * GS;
+  T *Ab = Ak + (size_t)d * P2;
   const auto *F = gmem((const double *)v.F.at(it));
   const auto *X = gmem((const double *)v.X.at(it));
   const auto *G = gmem((const double *)v.G.at(it));
   const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
-  double *T3g = v.t3 + (size_t)it * v.t3_stride;
+  T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
   const bool rl = v.rl != 0;
 
   // front-view site tensors A_f[s][wf][l][wb][a] (RL swaps the u/d legs),
@@ -942,14 +948,14 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
     const int s = t / D;
     const int u = rl ? wb : wf, dd = rl ? wf : wb;
     const size_t src = ((((size_t)s * D + u) * D + l) * D + dd) * D + a;
-    Ak[i] = ak[src];
-    Ab[i] = ab[src];
+    Ak[i] = (T)ak[src];
+    Ab[i] = (T)ab[src];
   }
   // F rows of this y tile: F[yf][wf][xf]
   for (int i = tid; i < TY * P * K; i += kVisitThreads) {
     const int row = i / K, xf = i - row * K;
     const int yf = y0 + row / P;
-    Fs[row * FS + xf] = yf < K ? F[(size_t)(y0 * P + row) * K + xf] : 0.0;
+    Fs[row * FS + xf] = (T)(yf < K ? F[(size_t)(y0 * P + row) * K + xf] : 0.0);
   }
   // Yt accumulators: tiles of [(ty,l)][yb], kept in registers.  With at
   // most half as many tiles as waves, each tile's k range is split over two
@@ -960,9 +966,9 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   const int ntile_e = tme * tne;
   const bool split_e = 2 * ntile_e <= kVisitWaves;
   constexpr int kMaxE = 4;  // tiles per wave (host keeps ntile_e <= 4 * waves)
-  v4d accE[kMaxE];
+  Acc accE[kMaxE];
 #pragma unroll
-  for (int q = 0; q < kMaxE; ++q) accE[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < kMaxE; ++q) accE[q] = Acc{0, 0, 0, 0};
 
   for (int x0 = 0; x0 < K; x0 += TX) {
     __syncthreads();  // previous tile's Xs/Gs/T3s consumers are done
@@ -985,47 +991,47 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
       double val = 0.0;
       if (xb < K)
         val = rl ? X[((size_t)xb * P + a) * K + xf] : X[((size_t)xf * P + a) * K + xb];
-      Xs[xf * XS + a * TX + tx] = val;
+      Xs[xf * XS + a * TX + tx] = (T)val;
     }
     if (v.do_local)
       // G[yb][wb][xb] as Gs[(tx*P + wb)][yb], read along xb
       for (int i = tid; i < TX * P * K; i += kVisitThreads) {
         const int tx = i % TX, r = i / TX;
         const int wb = r % P, yb = r / P, xb = x0 + tx;
-        Gs[(tx * P + wb) * GS + yb] = xb < K ? G[((size_t)yb * P + wb) * K + xb] : 0.0;
+        Gs[(tx * P + wb) * GS + yb] = (T)(xb < K ? G[((size_t)yb * P + wb) * K + xb] : 0.0);
       }
     __syncthreads();
     // (a) T1: rows (ty, wf), cols (a, tx), stored [pair][wfk, akx][wfb, abx]
-    lds_gemm(
+    lds_gemm<T>(
         1, TY * P, P * TX, K,
         [&](int, int m, int k) { return Fs[m * FS + k]; },
         [&](int, int k, int n) { return Xs[k * XS + n]; },
-        [&](int, int m, int n, double val) {
+        [&](int, int m, int n, T val) {
           const int ty = m / P, wf = m - ty * P, a = n / TX, tx = n - a * TX;
           const int wfk = wf / D, wfb = wf - wfk * D, akx = a / D, abx = a - akx * D;
           T1s[(ty * TX + tx) * P2 + (wfk * D + akx) * P + wfb * D + abx] = val;
         });
     __syncthreads();
     // (b) ket: per pair, rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
-    lds_gemm(
+    lds_gemm<T>(
         TY * TX, P, dP, P,
         [&](int p, int m, int k) { return T1s[p * P2 + k * P + m]; },
         [&](int, int k, int n) {
           const int s = n / P;
           return Ak[(s * P + k) * P + (n - s * P)];
         },
-        [&](int p, int m, int n, double val) { T2s[(p * P + m) * T2S + n] = val; });
+        [&](int p, int m, int n, T val) { T2s[(p * P + m) * T2S + n] = val; });
     __syncthreads();
     // (c) bra: per pair, rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb);
     // stored as T3s[pair][wb][l]
-    lds_gemm(
+    lds_gemm<T>(
         TY * TX, P, P, dP,
         [&](int p, int m, int k) {
           const int s = k / P;
           return T2s[(p * P + (k - s * P)) * T2S + s * P + m];
         },
         [&](int, int k, int n) { return Ab[k * P + n]; },
-        [&](int p, int m, int n, double val) {
+        [&](int p, int m, int n, T val) {
           const int lk = m / D, wbk = m - lk * D, lb = n / D, wbb = n - lb * D;
           T3s[p * P2 + (wbk * D + wbb) * P + lk * D + lb] = val;
         });
@@ -1055,18 +1061,18 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
         const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
         const int am = m0 + lr, bn = n0 + lr;
         const int ty = am / P, l = am - ty * P;
-        v4d acc[2] = {accE[q], v4d{0.0, 0.0, 0.0, 0.0}};
+        Acc acc[2] = {accE[q], Acc{0, 0, 0, 0}};
         for (int k0 = kb; k0 < ke; k0 += 8) {
-          double av[2], bv[2];
+          T av[2], bv[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             const int k = k0 + 4 * u + lq;
             const int tx = k / P, wb = k - tx * P;
-            av[u] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : 0.0;
-            bv[u] = (bn < K && k < ke) ? Gs[k * GS + bn] : 0.0;
+            av[u] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : (T)0;
+            bv[u] = (bn < K && k < ke) ? Gs[k * GS + bn] : (T)0;
           }
-          acc[0] = mfma16(av[0], bv[0], acc[0]);
-          acc[1] = mfma16(av[1], bv[1], acc[1]);
+          acc[0] = MM::run(av[0], bv[0], acc[0]);
+          acc[1] = MM::run(av[1], bv[1], acc[1]);
         }
         accE[q] = acc[0] + acc[1];
       }
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   }
   if (v.do_local && split_e) {  // add the second k half into the first
     __syncthreads();
-    double *red = sm;  // every LDS buffer is free after the last tile
+    T *red = sm;  // every LDS buffer is free after the last tile
     if (wave >= kVisitWaves / 2) {
       const int wt = wave - kVisitWaves / 2;
 #pragma unroll
@@ -1106,12 +1112,12 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
       const int m0 = (t / tne) << 4, n0 = (t % tne) << 4;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + 4 * r + lq, yb = n0 + lr;
+        const int m = m0 + MM::crow(r, lq), yb = n0 + lr;
         const int ty = m / P, l = m - ty * P, yf = y0 + ty;
         if (m < Me && yb < K && yf < K) {
           const size_t idx = rl ? ((size_t)yb * P + l) * K + yf
                                 : ((size_t)yf * P + l) * K + yb;
-          Y[idx] = accE[q][r];
+          Y[idx] = (double)accE[q][r];
         }
       }
     }
@@ -2688,14 +2694,15 @@ static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
 
 using VisitKernel = void (*)(VisitArgs);
 
+template <class T>
 static VisitKernel visit_kernel(int D) {
   switch (D) {
-    case 2: return k_visit<2>;
-    case 3: return k_visit<3>;
-    case 4: return k_visit<4>;
-    case 5: return k_visit<5>;
-    case 6: return k_visit<6>;
-    default: return k_visit<0>;
+    case 2: return k_visit<2, T>;
+    case 3: return k_visit<3, T>;
+    case 4: return k_visit<4, T>;
+    case 5: return k_visit<5, T>;
+    case 6: return k_visit<6, T>;
+    default: return k_visit<0, T>;
   }
 }
 
@@ -2763,7 +2770,10 @@ static VisitKernel visit4p_kernel(int NE, int TY) {
 static bool visit_f32(const FitBatch &f) {
   int TY, TX;
   size_t lds;
-  return f.prec == 32 && f.K <= 64 && visit4_tiles<float>(f, &TY, &TX, &lds);
+  if (f.prec != 32 || f.K > 64) return false;
+  if (visit4_tiles<float>(f, &TY, &TX, &lds)) return true;
+  visit_tiles(f, &TY, &TX, &lds);  // the generic fused visit
+  return f.D != 4 && TY > 0;
 }
 
 // ---- algorithmic counts on the true extents (timing only) -----------------
@@ -2845,12 +2855,12 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   static std::once_flag attr_once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] {
-    for (int D : {0, 2, 3, 4, 5, 6}) {
-      hipError_t e = hipFuncSetAttribute(
-          (const void *)visit_kernel(D),
-          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) attr_err = e;
-    }
+    for (int D : {0, 2, 3, 4, 5, 6})
+      for (VisitKernel kf : {visit_kernel<double>(D), visit_kernel<float>(D)}) {
+        hipError_t e = hipFuncSetAttribute((const void *)kf,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) attr_err = e;
+      }
     for (auto t : {std::make_pair(2, 4), std::make_pair(4, 2), std::make_pair(2, 2),
                    std::make_pair(1, 2), std::make_pair(1, 1)})
       for (VisitKernel kf : {visit4_kernel<double>(t.first, t.second),
@@ -2913,8 +2923,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     hipLaunchKernelGGL(f32 ? visit4_kernel<float>(TY4, TX4) : visit4_kernel<double>(TY4, TX4),
                        dim3((f.K + TY4 - 1) / TY4, f.items), dim3(kVisitThreads), lds4, st, v);
   } else {
-    hipLaunchKernelGGL(visit_kernel(f.D), dim3((f.K + TY - 1) / TY, f.items),
-                       dim3(kVisitThreads), lds, st, v);
+    hipLaunchKernelGGL(f32 ? visit_kernel<float>(f.D) : visit_kernel<double>(f.D),
+                       dim3((f.K + TY - 1) / TY, f.items), dim3(kVisitThreads), lds, st, v);
   }
   return hipGetLastError();
 }

@@ -94,3 +94,37 @@ def test_precision_option_validation():
     for bad in (16, 0, 63.5):
         with pytest.raises(bbp.BBPError):
             g.set_option("precision", bad)
+
+
+def test_fp32_polish_at_the_D6_bond_caps():
+    """D=6 with the 16x16 D=6 workload's caps (chi=64, chi_env=82) on an 8x8
+    lattice: FP32 sweeps (the fused D=6 visit and the environment update on
+    FP32 MFMA) to 1e-6, then FP64 sweeps to 1e-10, against the all-FP64
+    solve (whose kernels the D=6 golden pins to the oracle)."""
+    bbp = _bbp()
+    cfg = dict(Lx=8, Ly=8, bx=4, by=4, D=6, chi=64, chi_env=82)
+    A = peps_finite(8, 8, 6, seed=2)
+    ref = bbp.BlockBP(**cfg)
+    ref.set_tensors(A)
+    r64, n64 = _sweep_to(ref, 1e-10, 60)
+    sz64, ss64, _ = _obs(ref, 8)
+    mix = bbp.BlockBP(**cfg)
+    mix.set_option("precision", 32)
+    mix.set_option("timing", 1)
+    mix.set_tensors(A)
+    r32, n32 = _sweep_to(mix, 1e-6, 60)
+    ks = {k["name"]: k for k in mix.kernel_stats()}
+    mix.set_option("timing", 0)
+    sz32, ss32, _ = _obs(mix, 8)
+    mix.set_option("precision", 64)
+    rp, npol = _sweep_to(mix, 1e-10, 60)
+    szp, ssp, _ = _obs(mix, 8)
+    e32 = max(np.abs(sz32 - sz64).max(), np.abs(ss32 - ss64).max())
+    ep = max(np.abs(szp - sz64).max(), np.abs(ssp - ss64).max())
+    print(f"D=6: fp64 {n64} sweeps to {r64:.1e}; fp32 {n32} sweeps to {r32:.1e}, then "
+          f"{npol} fp64 to {rp:.1e}; max |d obs|: fp32 {e32:.2e}, polished {ep:.2e}; "
+          f"fp32 visits {ks['fit_visit']['launches']}", flush=True)
+    assert ks["fit_visit"]["launches"] > 0 and ks["fit_T1"]["launches"] == 0
+    assert r64 < 1e-10 and rp < 1e-10
+    assert ep < POLISH_TOL
+    assert e32 > 10 * POLISH_TOL
