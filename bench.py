@@ -42,6 +42,8 @@ TOL = 1e-10
 MAX_SWEEPS = 40
 SEARCH_MAX_SWEEPS = 80   # the sweep-count search (the D=6 lattice needs about 50)
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix (no BF16 stage is built)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fit_visit_obc16x16_D4_chi32.json")
@@ -88,7 +90,15 @@ def solve(ctx, cfg, A, sweeps, sites, bonds, times=None):
     ctx.set_tensors(A)
     sync()
     t1 = time.perf_counter()
-    res = ctx.sweep(sweeps)
+    if sweeps <= 20:
+        res = ctx.sweep(sweeps)
+    else:   # long solves report their progress (a run silent for minutes looks hung)
+        done = 0
+        while done < sweeps:
+            k = min(20, sweeps - done)
+            res = ctx.sweep(k)
+            done += k
+            log(f"    {done}/{sweeps} sweeps")
     sync()
     t2 = time.perf_counter()
     sz, ss = observables(ctx, cfg, sites, bonds)
@@ -331,9 +341,11 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
     while n32 < SEARCH_MAX_SWEEPS:
         res = ctx.sweep(1)
         n32 += 1
-        if res < 1e-7 or (prev is not None and res > 0.5 * prev):
-            break   # at the FP32 floor, or no longer improving
+        if res < TOL or (prev is not None and res >= prev):
+            break   # converged, or at the FP32 floor (no longer falling)
         prev = res
+        if n32 % 10 == 0:
+            log(f"  fp32 sweep {n32}: residual {res:.2e}")
     ctx.set_option("precision", 64)
     n64 = 0
     while res >= TOL and n64 < SEARCH_MAX_SWEEPS:
@@ -341,14 +353,23 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
         n64 += 1
     log(f"mixed precision: {n32} FP32 sweeps, then {n64} FP64 sweeps to {res:.2e}")
     times = []
+    def chunked(n):
+        r, done = None, 0
+        while done < n:
+            k = min(20, n - done)
+            r = ctx.sweep(k)
+            done += k
+            if n > 20:
+                log(f"    {done}/{n} sweeps")
+        return r
     for _ in range(steps):
         sync()
         t0 = time.perf_counter()
         ctx.set_option("precision", 32)
         ctx.set_tensors(A)
-        ctx.sweep(n32)
+        chunked(n32)
         ctx.set_option("precision", 64)
-        res = ctx.sweep(n64)
+        res = chunked(n64)
         sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
         ss = ctx.expect_bonds(bonds, op_heis())
         ln = ctx.log_norm()
@@ -362,6 +383,8 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
     while rt >= 1e-14 and nt < SEARCH_MAX_SWEEPS:
         rt = ctx.sweep(1)
         nt += 1
+        if nt % 10 == 0:
+            log(f"  reference sweep {nt}: residual {rt:.2e}")
     szt = np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz()))
     sst = np.array(ctx.expect_bonds(bonds, op_heis()))
     err = lambda a, b: float(np.max(np.abs(np.array(a) - b)))
@@ -376,21 +399,32 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
         ctx.sweep(2)
         sync()
         per[f"fp{prec}_ms_per_sweep"] = (time.perf_counter() - t0) / 2 * 1e3
+        _, fl = ctx.stats()   # fit FLOPs of the last sweep, true bonds
+        per[f"fp{prec}_fit_tflops"] = fl / (per[f"fp{prec}_ms_per_sweep"] * 1e-3) / 1e12
     ctx.set_option("precision", 64)
+    per["peaks_tflops"] = dict(fp64=PEAK_FP64_TFLOPS, fp32=PEAK_FP32_TFLOPS,
+                               bf16=PEAK_BF16_TFLOPS)
+    per["fp32_frac_of_fp32_peak"] = per["fp32_fit_tflops"] / PEAK_FP32_TFLOPS
+    per["fp64_frac_of_fp64_peak"] = per["fp64_fit_tflops"] / PEAK_FP64_TFLOPS
     return dict(fp32_sweeps=n32, fp64_sweeps=n64, residual=res, ms_per_solve=ms, **per,
                 accuracy_vs_converged=acc,
                 speedup_vs_fp64=fp64_ms / ms,
                 max_abs_diff_sz_vs_fp64=float(np.max(np.abs(np.array(sz) - np.array(ref[1])))),
                 max_abs_diff_ss_vs_fp64=float(np.max(np.abs(np.array(ss) - np.array(ref[2])))),
                 abs_err_log_norm=float(abs(ln[0] - ref[3][0])),
-                note="FP32 visit and environment contractions (FP32 accumulation); QR, "
-                     "normalisation and messages FP64; errors against the all-FP64 solve")
+                note="FP32 visit and environment contractions (FP32 accumulation) until the "
+                     "residual stops falling, then FP64 sweeps to the tolerance; QR, "
+                     "normalisation and messages FP64; no BF16 stage; errors against the "
+                     "all-FP64 solve and against a tightly converged FP64 reference")
 
 
 def cpu_baseline(cfg, A):
     """The FP64 oracle on the host: one untimed sweep, then timed sweeps of
     the same solve (bonds at their caps) until about two seconds have passed
-    (one sweep on the 16x16 lattice)."""
+    (one sweep on the 16x16 lattice).  Workloads with D >= 6 (a sweep is
+    tens of minutes there) time the first message updates of the first
+    sweep instead, about 20 s of them: inside each column fit the bonds
+    already reach their caps."""
     from oracle.blockbp import BlockBP
     try:
         from threadpoolctl import threadpool_info
@@ -400,6 +434,19 @@ def cpu_baseline(cfg, A):
     geo = dict(infinite=True, ucx=cfg["ucx"], ucy=cfg["ucy"]) if cfg["infinite"] \
         else dict(Lx=cfg["Lx"], Ly=cfg["Ly"])
     bp = BlockBP(A, D=cfg["D"], chi=cfg["chi"], bx=cfg["bx"], by=cfg["by"], **geo)
+    if cfg["D"] >= 6:
+        t0 = time.perf_counter()
+        n = 0
+        for e, key in enumerate(bp.order):
+            bp.update_message(e, key, bp.msgs)
+            n += 1
+            log(f"  oracle message update {n}: {time.perf_counter() - t0:.1f} s")
+            if time.perf_counter() - t0 >= 20.0:
+                break
+        dt = time.perf_counter() - t0
+        return dict(value=n / dt, unit="message updates/s", cores=threads, kind="oracle",
+                    sample=f"first {n} message updates of the first sweep, {dt:.1f} s",
+                    **host_cpu())
     bp.sweep()
     nsw = 0
     t0 = time.perf_counter()
@@ -437,6 +484,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-pass", action="store_true",
+                    help="skip the second, event-timed pass (no roofline figures)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision pattern (profiling runs: the timed "
                          "solves are then the last kernels of the run)")
@@ -515,18 +564,21 @@ def main():
     # stream: per-kernel-class durations for the roofline.  A context on one
     # stream runs them, so that no two kernels overlap (the bracket of a kernel
     # that shares the GPU with another lane's would include the other's time)
-    ctx1 = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
-                       lanes=1)
-    ctx1.set_option("timing", 1)
-    sync()
-    ti0 = time.perf_counter()
-    for k in range(args.steps):
-        solve(ctx1, cfg, A, sweeps, sites, bonds)
-    sync()
-    timed_total = time.perf_counter() - ti0
-    stats = ctx1.kernel_stats()
-    ctx1.set_option("timing", 0)   # the timing switch is process-wide
-    ctx1.close()
+    stats, timed_total = None, None
+    if not args.no_kernel_pass:
+        log("event-timed pass")
+        ctx1 = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
+                           lanes=1)
+        ctx1.set_option("timing", 1)
+        sync()
+        ti0 = time.perf_counter()
+        for k in range(args.steps):
+            solve(ctx1, cfg, A, sweeps, sites, bonds)
+        sync()
+        timed_total = time.perf_counter() - ti0
+        stats = ctx1.kernel_stats()
+        ctx1.set_option("timing", 0)   # the timing switch is process-wide
+        ctx1.close()
 
     step_s = np.array([sum(t) for t in times])
     sweep_s = np.array([t[1] for t in times])
@@ -559,13 +611,14 @@ def main():
                       observables=float(np.mean([t[2] for t in times]) * 1e3)),
         solve_latency_ms=dict(p50=float(np.percentile(step_s, 50) * 1e3),
                               p99=float(np.percentile(step_s, 99) * 1e3)),
-        roofline=dict(roofline(stats, args.workload), measured_in="second pass of the same K "
-                      "solves on a one-stream context (lanes 1), every launch bracketed by "
-                      "HIP events",
-                      pass_ms_per_step=timed_total / args.steps * 1e3),
-        kernels={s["name"]: dict(launches=s["launches"], ms=s["ms"],
-                                 tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
-                 for s in stats},
+        roofline=None if stats is None else dict(
+            roofline(stats, args.workload), measured_in="second pass of the same K "
+            "solves on a one-stream context (lanes 1), every launch bracketed by HIP events",
+            pass_ms_per_step=timed_total / args.steps * 1e3),
+        kernels=None if stats is None else {
+            s["name"]: dict(launches=s["launches"], ms=s["ms"],
+                            tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
+            for s in stats},
         cpu_baseline=None,
     )
     # the precision pattern (FP32 contractions in the fused visits)
