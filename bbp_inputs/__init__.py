@@ -18,6 +18,7 @@ from .gen import (  # noqa: F401
     peps_finite,
     peps_infinite,
     ising_peps,
+    ising_single_layer,
     peps_tiled,
     peps_rotate,
     peps_transpose,

@@ -72,6 +72,33 @@ def ising_peps(beta, h=0.0, Lx=0, Ly=0):
     return A
 
 
+def ising_single_layer(beta, h=0.0, Lx=0, Ly=0):
+    """Single-layer tensor network of the classical Ising partition function
+    ``Z = sum_sigma exp(beta * sum_<ij> s_i s_j + h * sum_i s_i)`` (bond
+    dimension 2), split by the spin value: site tensor ``A[s, u, l, d, r] =
+    exp(h s) W[s, u] W[s, l] W[s, d] W[s, r]`` with ``exp(beta s s') =
+    sum_k W[s, k] W[s', k]``, so the network tensor is ``sum_s A[s]`` and
+    ``sum_s s A[s]`` is the impurity of the magnetisation.  ``Lx = Ly = 0``:
+    the 1x1 unit cell of the infinite lattice; otherwise the open ``Lx x Ly``
+    lattice, legs off the edge of true dimension 1 (zero-padded)."""
+    w = np.array([[np.exp(beta), np.exp(-beta)],
+                  [np.exp(-beta), np.exp(beta)]])
+    lam, V = np.linalg.eigh(w)
+    W = V * np.sqrt(lam)                      # w = W W^T
+    one = np.array([1.0, 0.0])
+    infinite = Lx == 0
+    nx, ny = (1, 1) if infinite else (Lx, Ly)
+    A = np.zeros((nx * ny, 2, 2, 2, 2, 2))
+    for y in range(ny):
+        for x in range(nx):
+            for s in range(2):
+                sg = 1.0 if s == 0 else -1.0
+                leg = lambda edge: one if (edge and not infinite) else W[s]
+                A[y * nx + x, s] = np.exp(h * sg) * np.einsum(
+                    "u,l,d,r->uldr", leg(y == 0), leg(x == 0), leg(y == ny - 1), leg(x == nx - 1))
+    return A
+
+
 def pauli():
     """Pauli matrices in the basis s=0 <-> sigma_z=+1; sigma_y returned as the
     real matrix i*sigma_y (so that sigma_y (x) sigma_y = -(i sy)(x)(i sy))."""

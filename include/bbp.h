@@ -93,6 +93,15 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              visit and environment kernels stop at every item's true bond
  *              dimensions instead of the padded cap (the skipped terms are
  *              zeros, so results are bitwise the same); 0 runs the padding.
+ *   "single_layer" 0 (default) or 1 (before bbp_set_tensors): the network
+ *              is the single layer sum_s A[s] (Sec. V classical Ising: a
+ *              tensor network of bond dimension D, messages MPSs over its
+ *              bonds, App. A) instead of the double layer <psi|psi>: the
+ *              bra layer of every site is fixed to index 0 on every leg, so
+ *              the fused leg (k, k') carries the network's bond k at k' = 0.
+ *              A one-site operator O then inserts sum_s (sum_s' O[s',s]) A[s]
+ *              (for a diagonal O the impurity sum_s O[s,s] A[s]), and
+ *              bbp_log_norm gives log|Z| of the network.
  *   "shift_x", "shift_y" 0..bx-1, 0..by-1 (default 0; finite lattices,
  *              before bbp_set_tensors): a partition of the lattice into blocks
  *              shifted by (shift_x, shift_y) sites (Sec. II: several

@@ -109,6 +109,19 @@ def double_layer(A, Aket=None):
     return E.reshape(D * D, D * D, D * D, D * D)
 
 
+def single_layer_bra(A):
+    """Bra tensor of a single-layer network (Sec. V classical Ising; App. A
+    single-layer messages): every virtual leg at index 0 for each value of
+    the split index s, so that the double layer ``sum_s A[s] (x) bra[s]``
+    is the single-layer tensor ``T = sum_s A[s]`` placed at the fused
+    indices (k, 0), and a one-site operator O inserts
+    ``sum_s (sum_s' O[s', s]) A[s]`` (for a diagonal O: the impurity
+    tensor ``sum_s O[s, s] A[s]``)."""
+    B = np.zeros_like(A)
+    B[:, 0, 0, 0, 0] = 1.0
+    return B
+
+
 def apply_op(op, A):
     """Ket tensor with a one-site operator applied: ``sum_s op[s', s] A[s]``."""
     return np.einsum("ts,suldr->tuldr", op, A)
@@ -306,16 +319,17 @@ def column_mpo(Egrid, MT, MB, c):
 
 
 def absorb(grid, MT, MR, MB, chi, n_fit, seed, slot_fn, ncols=None,
-           warm=None, keep=False):
+           warm=None, keep=False, bra=None):
     """Contract canonical columns right to left into a boundary MPS.
 
     The boundary starts as ``[1, MR..., 1]`` (trivial corners) and after each
     column is replaced by ``fit(column MPO, boundary)`` normalised to unit
     norm, the logarithm of the norm being accumulated.  Returns the final
     boundary, its log-scale, the list of ``(boundary, logscale)`` after
-    0, 1, ... columns when ``keep``, and the per-column fit results."""
+    0, 1, ... columns when ``keep``, and the per-column fit results.
+    ``bra`` maps a site tensor to its bra layer (default: the tensor itself)."""
     H, W = len(grid), len(grid[0])
-    Egrid = [[double_layer(t) for t in row] for row in grid]
+    Egrid = [[double_layer(bra(t) if bra else t, t) for t in row] for row in grid]
     one = np.ones((1, 1, 1))
     X = [one] + list(MR) + [one]
     log_scale = 0.0
@@ -361,8 +375,12 @@ class BlockBP:
     """
 
     def __init__(self, A, D, chi, bx, by, Lx=0, Ly=0, infinite=False,
-                 ucx=1, ucy=1, chi_env=None, n_fit=2, seed=0, d=2, shift=(0, 0)):
+                 ucx=1, ucy=1, chi_env=None, n_fit=2, seed=0, d=2, shift=(0, 0),
+                 single_layer=False):
         self.D, self.chi, self.bx, self.by = D, chi, bx, by
+        # single-layer network: the tensors' sum over s is the network
+        # tensor, the bra layer a fixed index-0 tensor
+        self.bra = single_layer_bra if single_layer else None
         self.infinite = infinite
         self.d = d
         self.chi_env = (2 * D * D + 10) if chi_env is None else chi_env
@@ -448,7 +466,7 @@ class BlockBP:
         Y, _, _, fits = absorb(grid, MT, MR, MB, self.chi, self.n_fit,
                                self.seed,
                                lambda c: slot_message(e_index, c),
-                               warm=self.warm[key])
+                               warm=self.warm[key], bra=self.bra)
         self.warm[key] = fits
         m = extract_message(Y)
         return mps_reverse(m) if OUT_REVERSED[dr] else m
@@ -495,7 +513,7 @@ class BlockBP:
             _, _, stack, _ = absorb(
                 grid, MT, MR, MB, self.chi_env, self.n_fit, self.seed,
                 lambda c: slot_region(kind, bi, bj, orient, c),
-                ncols=W - 1, keep=True)
+                ncols=W - 1, keep=True, bra=self.bra)
             self._cache[key] = (reg, stack)
         return self._cache[key]
 
@@ -538,26 +556,28 @@ class BlockBP:
         i = 0
         while i < n:
             A = sites[i].transpose((0,) + legs)
+            B = self.bra(A) if self.bra else A
             if pair is not None and i == pair[0]:
                 A1 = sites[i + 1].transpose((0,) + legs)
+                B1 = self.bra(A1) if self.bra else A1
                 op2 = ops[pair].reshape(self.d, self.d, self.d, self.d)
                 env = self._pair(env, up[i + 1], up[i + 2], dn[i + 1],
-                                 dn[i + 2], op2, A, A1)
+                                 dn[i + 2], op2, A, A1, B, B1)
                 i += 2
                 continue
             Ak = apply_op(ops[i], A) if i in ops else A
-            E = double_layer(A, Ak)  # O[w_left, p_up, p_down, w_right]
+            E = double_layer(B, Ak)  # O[w_left, p_up, p_down, w_right]
             env = env_left(env, up[i + 1], E, dn[i + 1])
             i += 1
         env = env_left(env, up[n + 1], last.transpose(1, 0, 2)[..., None],
                        dn[n + 1])
         return float(env[0, 0, 0])
 
-    def _pair(self, env, y0, y1, x0, x1, op2, A0, A1):
+    def _pair(self, env, y0, y1, x0, x1, op2, A0, A1, B0, B1):
         """Environment step over two neighbouring sites with a two-site
         operator ``op2[s0', s1', s0, s1]`` between their ket (``s``) and bra
-        (``s'``) layers.  ``A0``, ``A1`` are in line-MPO leg order
-        ``[s, w_left, p_up, p_down, w_right]``."""
+        (``s'``) layers.  ``A0``, ``A1`` (ket) and ``B0``, ``B1`` (bra) are
+        in line-MPO leg order ``[s, w_left, p_up, p_down, w_right]``."""
         Dk = A0.shape[1]
         e = env.reshape(env.shape[0], Dk, Dk, env.shape[2])
         y0 = y0.reshape(y0.shape[0], Dk, Dk, y0.shape[2])
@@ -566,15 +586,15 @@ class BlockBP:
         x1 = x1.reshape(x1.shape[0], Dk, Dk, x1.shape[2])
         # out[d,w,y,g] = sum e[a,i,j,b] y0[a,k,l,c] y1[c,m,n,d] x0[b,o,p,e]
         #   x1[e,q,r,g] op2[t,u,s,v] A0[s,i,k,o,h] A1[v,h,m,q,w]
-        #   A0[t,j,l,p,x] A1[u,x,n,r,y], one pair at a time
+        #   B0[t,j,l,p,x] B1[u,x,n,r,y], one pair at a time
         t = np.einsum("aijb,aklc->ijbklc", e, y0, optimize=True)
         t = np.einsum("ijbklc,sikoh->jblcsoh", t, A0, optimize=True)
-        t = np.einsum("jblcsoh,tjlpx->bcsohtpx", t, A0, optimize=True)
+        t = np.einsum("jblcsoh,tjlpx->bcsohtpx", t, B0, optimize=True)
         t = np.einsum("bcsohtpx,bope->cshtxe", t, x0, optimize=True)
         t = np.einsum("cshtxe,tusv->chxeuv", t, op2, optimize=True)
         t = np.einsum("chxeuv,cmnd->hxeuvmnd", t, y1, optimize=True)
         t = np.einsum("hxeuvmnd,vhmqw->xeundqw", t, A1, optimize=True)
-        t = np.einsum("xeundqw,uxnry->edqwry", t, A1, optimize=True)
+        t = np.einsum("xeundqw,uxnry->edqwry", t, B1, optimize=True)
         out = np.einsum("edqwry,eqrg->dwyg", t, x1, optimize=True)
         return out.reshape(out.shape[0], Dk * Dk, out.shape[3])
 

@@ -222,6 +222,8 @@ struct bbp_ctx {
   int skip_pad = 1;    // 1: the column absorptions' kernels stop at the true bond extents
   int msg_split = 2;   // message batches of one shape split into this many (one per lane)
   bool engine = false; // messages swept by a shared SweepSet (no message batches of its own)
+  int single_layer = 0; // 1: the network is sum_s A[s] (bra layer fixed at index 0)
+  DevBuf delta;         // single layer: the bra tensor, [s][0][0][0][0] = 1
   DevBuf rot;                   // engine mode: rotated block tensors of every message
   std::vector<size_t> rot_off;  // doubles from rot's start to message i's block
   uint64_t serial = 0; // unique per context of the process (identifies it across sweeps)
@@ -582,6 +584,7 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.S = (size_t)bond_cap * c->P * bond_cap;
   f.seed = c->seed;
   f.prec = c->precision;
+  f.bra_one = c->single_layer ? c->delta.d() : nullptr;
   const size_t it = f.items, S = f.S, K = f.K, P = f.P;
   const bool fused = visit_fused_fits(f);
   const bool fit = (need & NEED_FIT) != 0, scr = (need & NEED_SCRATCH) != 0;
@@ -813,7 +816,7 @@ static bool same_batch(const FitBatch &a, const FitBatch &b) {
          a.t3 == b.t3 && a.tmp == b.tmp && a.acan == b.acan && a.abra == b.abra &&
          a.rbuf == b.rbuf && a.nu == b.nu && a.flag == b.flag && a.err == b.err &&
          a.dims == b.dims && a.slot == b.slot && a.seed == b.seed && a.prec == b.prec &&
-         a.bounded == b.bounded;
+         a.bounded == b.bounded && a.bra_one == b.bra_one;
 }
 
 // The launches of absorb_columns, enqueued on st.
@@ -1956,6 +1959,9 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   } else if (k == "graphs") {
     if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "graphs must be 0 or 1");
     c->graphs = (int)v;
+  } else if (k == "single_layer") {
+    if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "single_layer must be 0 or 1");
+    c->single_layer = (int)v;
   } else if (k == "shift_x" || k == "shift_y") {
     const int b = k == "shift_x" ? c->bx : c->by;
     if (c->infinite) return c->fail(BBP_EINVAL, "partition shifts are for finite lattices");
@@ -2056,6 +2062,15 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
       c->ovOut.alloc(nm * 8) != hipSuccess || c->ovA.alloc(nm * 8) != hipSuccess ||
       c->ovB.alloc(nm * 8) != hipSuccess || c->errflag.alloc(64) != hipSuccess)
     return c->fail(BBP_ENOMEM, "device allocation failed");
+  if (c->single_layer) {
+    const size_t ss1 = (size_t)c->d * c->P * c->P;
+    std::vector<double> dl(ss1, 0.0);
+    for (int s1 = 0; s1 < c->d; ++s1) dl[(size_t)s1 * c->P * c->P] = 1.0;
+    if (c->delta.alloc(ss1 * 8) != hipSuccess)
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    if (copy_sync(c, c->delta.p, dl.data(), ss1 * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return c->fail(BBP_EDEVICE, "upload single-layer bra");
+  }
   if (zero_sync(c, c->errflag.p, c->errflag.bytes) != hipSuccess ||
       zero_sync(c, c->msgbuf[0].p, c->msgbuf[0].bytes) != hipSuccess ||
       zero_sync(c, c->msgbuf[1].p, c->msgbuf[1].bytes) != hipSuccess)

@@ -68,6 +68,9 @@ struct FitBatch {
   double *tmp = nullptr;    // [items][S]
   double *acan = nullptr;   // [items][H][W][d*D^4]  rotated site tensors (ket)
   double *abra = nullptr;   // bra tensors if different from acan (or null)
+  // single-layer networks: one bra tensor (every virtual leg at index 0) for
+  // every site and item, in place of abra/acan
+  const double *bra_one = nullptr;
   double *rbuf = nullptr;   // [items][K*K]
   double *nu = nullptr;     // [items][W] norm of each column's fit
   int32_t *flag = nullptr;  // [items] per-item active flags

@@ -2891,8 +2891,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   v.F = F; v.X = X; v.G = G; v.Y = Y;
   v.aket = f.acan + site_off;
   v.aket_stride = a_stride(f);
-  v.abra = (f.abra ? f.abra : f.acan) + site_off;
-  v.abra_stride = a_stride(f);
+  v.abra = f.bra_one ? f.bra_one : (f.abra ? f.abra : f.acan) + site_off;
+  v.abra_stride = f.bra_one ? 0 : a_stride(f);
   v.t3 = f.t3;
   v.t3_stride = t1_stride(f);
   v.dims = nullptr;
@@ -2993,7 +2993,7 @@ hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
   const size_t t1s = t1_stride(f), t2s = t2_stride(f), t3s = t1s;
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
   const double *Ak = f.acan + site_off;
-  const double *Ab = (f.abra ? f.abra : f.acan) + site_off;
+  const double *Ab = f.bra_one ? f.bra_one : (f.abra ? f.abra : f.acan) + site_off;
   const double it = f.items, K = f.K, P = f.P, d = f.d;
   OpK1 k1{f.K * f.P, f.P * f.K, f.K, nullptr, s, rl, X, F, f.t1, t1s};
   hipError_t e;
@@ -3014,7 +3014,7 @@ hipError_t launch_inner_chain_generic(const FitBatch &f, int c, int j, bool rl,
   }
   if (e != hipSuccess) return e;
   OpK3 k3{f.K * f.K * f.P, f.P, f.d * f.P, nullptr, s, rl, f.t2, t2s, Ab,
-          a_stride(f), f.t3, t3s};
+          f.bra_one ? 0 : a_stride(f), f.t3, t3s};
   const Count tc = count_inner(f, c, j, rl, TC_BRA);
   Span sp(KC_BRA, st, tc.flops, tc.bytes, it * 2 * K * K * P * P * d * P,
           it * 8 * (d * K * K * P * P + d * P * P + K * K * P * P));

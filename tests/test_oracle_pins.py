@@ -555,3 +555,70 @@ def test_p8_catches_same_direction_routing(monkeypatch):
     monkeypatch.setattr(ob.BlockBP, "incoming", bad)
     assert _p8_gap(2, 2, 16, [14])[0] > 1e-4
     assert _p8_gap(2, 4, 16, [12])[0] > 1e-5
+
+
+# ---- single-layer networks (Sec. V classical Ising, bond dimension 2) -------------
+
+def test_single_layer_ising_is_exact_on_one_block():
+    """One block covering a 3x3 open lattice: the single-layer network of the
+    Ising Gibbs weights gives the classical magnetisation of every site and
+    log Z, summed over all configurations."""
+    from bbp_inputs import ising_single_layer
+    beta, h = 0.7, 0.3
+    A = ising_single_layer(beta, h, 3, 3)
+    g = ob.BlockBP(A, D=2, chi=4, bx=3, by=3, Lx=3, Ly=3, chi_env=16, single_layer=True)
+    m = _ising_brute(beta, h, 3, 3)
+    for y in range(3):
+        for x in range(3):
+            assert abs(g.expect_site(x, y, op_sz()) - m[y * 3 + x]) < 1e-12
+    import itertools
+    Z = 0.0
+    for conf in itertools.product((1, -1), repeat=9):
+        s = np.array(conf).reshape(3, 3)
+        Z += np.exp(beta * ((s[:, :-1] * s[:, 1:]).sum() + (s[:-1, :] * s[1:, :]).sum())
+                    + h * s.sum())
+    assert abs(g.log_norm()[0] - math.log(Z)) < 1e-12
+
+
+def test_single_layer_ising_approaches_onsager():
+    """Infinite single-layer Ising network below T_c: block BP's magnetisation
+    at the block centre approaches Onsager and Yang's closed form and
+    improves with the block size (Sec. V)."""
+    from bbp_inputs import ising_single_layer
+    onsager = lambda beta: (1 - np.sinh(2 * beta) ** -4) ** 0.125
+
+    def m(beta, b, chi):
+        g = ob.BlockBP(ising_single_layer(beta, 1e-6), D=2, chi=chi, bx=b, by=b,
+                       infinite=True, ucx=1, ucy=1, single_layer=True)
+        for _ in range(200):
+            if g.sweep() < 1e-13:
+                break
+        return g.expect_site(0, 0, op_sz())
+    assert abs(m(0.8, 4, 4) - onsager(0.8)) < 1e-6
+    e2 = abs(m(0.6, 2, 2) - onsager(0.6))
+    e4 = abs(m(0.6, 4, 4) - onsager(0.6))
+    assert e4 < 1e-4 and e4 < 0.2 * e2
+
+
+@pytest.mark.parametrize("mutation", ["double_layer", "bra_index_1"])
+def test_single_layer_bra_planted_mistakes(mutation):
+    """The bra layer taken as the tensor itself (the double layer of the split
+    tensors) or fixed at the wrong index breaks the exactness pin."""
+    from bbp_inputs import ising_single_layer
+    beta, h = 0.7, 0.3
+    A = ising_single_layer(beta, h, 3, 3)
+    g = ob.BlockBP(A, D=2, chi=4, bx=3, by=3, Lx=3, Ly=3, chi_env=16, single_layer=True)
+    if mutation == "double_layer":
+        g.bra = None
+    else:
+        def bra(t):
+            B = np.zeros_like(t)
+            B[:, 0, 0, 0, 0] = 1.0
+            B[1, 0, 0, 0, 0] = 0.0
+            B[1, 1, 1, 1, 1] = 1.0
+            return B
+        g.bra = bra
+    m = _ising_brute(beta, h, 3, 3)
+    err = max(abs(g.expect_site(x, y, op_sz()) - m[y * 3 + x])
+              for y in range(3) for x in range(3))
+    assert err > 1e-6
