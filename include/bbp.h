@@ -162,6 +162,14 @@ bbp_status bbp_set_allocator(bbp_ctx *c, bbp_alloc_fn alloc, bbp_free_fn free_, 
 bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n);
 
 /*
+ * Copy the context's site tensors (as last set, or as bbp_ite_step left
+ * them) to host memory A, the layout of bbp_set_tensors; n must be that
+ * count.  Errors: BBP_ESTATE before bbp_set_tensors, BBP_EINVAL for a wrong
+ * n or a null pointer.
+ */
+bbp_status bbp_get_tensors(bbp_ctx *c, double *A, size_t n);
+
+/*
  * Exactly n synchronous sweeps of Eq. (1): every directed message between
  * neighbouring blocks is recomputed from the previous sweep's messages
  * (Sec. II: all messages of one iteration are independent).  No early exit.
@@ -287,6 +295,60 @@ bbp_status bbp_memory(const bbp_ctx *c, size_t *now, size_t *peak);
 
 const char *bbp_last_error(const bbp_ctx *c);
 void bbp_destroy(bbp_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * The blockBP update (App. B, Eq. (Ut)): one first-order Trotter step of
+ * imaginary time evolution of a finite open double-layer PEPS, the
+ * environment of every gate taken from the context's block-BP messages.
+ *
+ * gate (host, d^2 x d^2, row-major [(s0',s1')][(s0,s1)], the first site of
+ * a bond the major index) is applied to every nearest-neighbour bond,
+ * horizontal bonds row by row (y, then x ascending), then vertical bonds
+ * column by column (x, then y ascending); the first site is the left or
+ * upper one.  For each bond the two tensors are split into isometries on
+ * their outer legs and reduced tensors R_a [k][s][shared], L_b
+ * [shared][s][k] (k = min(D^3, d D), QR and LQ); the environment N of the
+ * reduced tensors is the normalised two-site reduced density matrix of the
+ * network whose two sites carry their isometries (the isometry bond as
+ * their physical index, the shared leg at index 0), contracted on the GPU
+ * by the same region contraction as bbp_rdm_bonds with the messages the
+ * step started from; R_a L_b is then refitted at bond D to the gate applied
+ * to it, minimising the distance in the metric of N (bbp_ite_fit), and the
+ * two new tensors are scaled to a largest entry of 1 and replace the old
+ * ones at once, so that later gates of the step see them.  The messages
+ * stay fixed through the step (the caller sweeps between steps); on
+ * return the context holds the new tensors with the messages it had
+ * (their fit warm starts cleared).
+ *
+ * n_als: alternating least-squares passes per gate (1..64).  info (host,
+ * optional, 2 doubles): the number of gates applied and the sum over the
+ * gates of the relative fit error in the metric of N.
+ * Errors: BBP_ESTATE (no tensors), BBP_EINVAL (infinite or single-layer
+ * context, min(D^3, d D) > 8, n_als out of range, null or non-finite gate),
+ * BBP_ENUMERIC (singular fit or a vanishing region contraction); the
+ * context's tensors are then those before the failing gate's bond.
+ * ------------------------------------------------------------------------ */
+bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als, double *info);
+
+/*
+ * The reduced-tensor fit of one gate (App. B), host only: R[k][d][D] and
+ * L[D][d][kb] minimising || R L - G Theta || in the metric
+ * N[(a,b)][(a',b')] (k kb x k kb), where Theta[k][d][d][kb] is the pair's
+ * product and G = gate as in bbp_ite_step.  Starts from the rank-D
+ * truncated SVD of G Theta (singular values split evenly, each singular
+ * pair signed so that the largest-magnitude entry of its left vector is
+ * positive, which fixes the gauge of the bond R L) and makes n_als
+ * passes, each solving the normal equations for R, then for L, with N
+ * symmetrised and 1e-12 trace(M)/n added to each system's diagonal.
+ * *loss (optional): the relative error of the fit in the metric of N.
+ * All pointers are host memory owned by the caller.
+ * Errors: BBP_EINVAL (d, D outside [1, 8], k, kb outside [1, 64], n_als
+ * outside [1, 64], null or non-finite input), BBP_ENUMERIC (singular
+ * system or non-finite result).
+ */
+bbp_status bbp_ite_fit(int32_t d, int32_t D, int32_t k, int32_t kb, const double *N,
+                       const double *theta, const double *gate, int32_t n_als,
+                       double *R, double *L, double *loss);
 
 /* ------------------------------------------------------------------------
  * One directed message update outside a context: Eq. (1) for a single

@@ -23,12 +23,16 @@ tensors are then fitted by alternating least squares.
 Readings (the paper leaves these open):
 * gate order: horizontal bonds by rows (y, then x ascending), then vertical
   bonds by columns (x, then y ascending);
-* the reduced tensors: the first site's legs other than the shared one form
-  the rows of its QR, ``(s, shared)`` the columns; the second site's
-  ``(shared, s)`` form the rows of its LQ; both isometries keep
-  ``k = min(D^3, d D)`` columns (rows);
+* the reduced tensors: the first site's legs other than the shared one, at
+  their true dimensions (1 on the lattice edge, D inside), form the rows of
+  its QR, ``(s, shared)`` the columns; the second site's ``(shared, s)``
+  form the rows of its LQ; the isometries keep ``k = min(rows, d D)``
+  columns (rows), so that every isometry column is a physical direction and
+  the edge padding of the new tensors stays zero;
 * the fit starts from the rank-D truncated SVD of ``G Theta`` (singular
-  values split evenly) and makes ``n_als`` passes, each solving the normal
+  values split evenly, each singular pair signed so that the largest-
+  magnitude entry of its left vector is positive: the fitted tensors' bond
+  gauge then does not depend on the SVD routine) and makes ``n_als`` passes, each solving the normal
   equations for the first reduced tensor, then for the second, with the
   environment symmetrised and ``1e-12 * trace / n`` added to the diagonal;
 * after the fit both tensors are scaled to a largest entry of 1 (the state
@@ -48,12 +52,20 @@ def bond_order(Lx, Ly):
     return out
 
 
-def split_pair(Aa, Ab, horizontal):
+def leg_dims(x, y, Lx, Ly, D):
+    """True dimensions of the legs (u, l, d, r) of site (x, y) of an open
+    lattice: 1 on the lattice edge, D inside."""
+    return (1 if y == 0 else D, 1 if x == 0 else D,
+            1 if y == Ly - 1 else D, 1 if x == Lx - 1 else D)
+
+
+def split_pair(Aa, Ab, horizontal, dims_a, dims_b):
     """Reduced tensors of a bond: ``Aa = X_a . R_a`` (QR over the rows
-    formed by Aa's legs other than the shared one) and ``Ab = L_b . Y_b``
-    (LQ over the columns formed by Ab's other legs).  Returns X_a
-    [rows, k], R_a [k, s, r], L_b [r, s, k'], Y_b [k', cols], and the leg
-    orders used to rebuild the tensors."""
+    formed by Aa's legs other than the shared one, at their true
+    dimensions dims_a) and ``Ab = L_b . Y_b`` (LQ over the columns formed
+    by Ab's other legs, at dims_b).  Returns X_a [rows, k], R_a [k, s, r],
+    L_b [r, s, k'], Y_b [k', cols], and the leg orders used to rebuild the
+    tensors."""
     d, D = Aa.shape[0], Aa.shape[1]
     # site tensor legs (s, u, l, d, r); shared leg of a: r (horizontal) or
     # d (vertical); of b: l or u
@@ -61,29 +73,35 @@ def split_pair(Aa, Ab, horizontal):
     sb = 2 if horizontal else 1
     oa = [i for i in (1, 2, 3, 4) if i != sa]
     ob_ = [i for i in (1, 2, 3, 4) if i != sb]
-    Ma = Aa.transpose(oa + [0, sa]).reshape(D ** 3, d * D)
-    Q, R = np.linalg.qr(Ma)              # Q: D^3 x k, R: k x (d D)
+    ta = Aa[(slice(None),) + tuple(slice(0, n) for n in dims_a)]
+    tb = Ab[(slice(None),) + tuple(slice(0, n) for n in dims_b)]
+    ra = int(np.prod([dims_a[i - 1] for i in oa]))
+    cb = int(np.prod([dims_b[i - 1] for i in ob_]))
+    Ma = ta.transpose(oa + [0, sa]).reshape(ra, d * D)
+    Q, R = np.linalg.qr(Ma)              # Q: rows x k, R: k x (d D)
     k = Q.shape[1]
-    Mb = Ab.transpose([sb, 0] + ob_).reshape(D * d, D ** 3)
+    Mb = tb.transpose([sb, 0] + ob_).reshape(D * d, cb)
     Qt, Rt = np.linalg.qr(Mb.T)          # Mb = Rt^T Qt^T
-    L, Y = Rt.T, Qt.T                    # L: (D d) x k', Y: k' x D^3
+    L, Y = Rt.T, Qt.T                    # L: (D d) x k', Y: k' x cols
     kb = Y.shape[0]
     return (Q, R.reshape(k, d, D), L.reshape(D, d, kb), Y, oa, ob_, sa, sb)
 
 
-def _reduced_site(Xmat, legs, shared, k, dp, D):
+def _reduced_site(Xmat, legs, shared, dims, k, dp, D):
     """Site tensor [k, u, l, d, r] (physical dimension dp >= k) of an
     isometry ``Xmat[(legs), k]``, the rows formed by the three legs in
-    ``legs`` order, with the shared leg at index 0 only."""
+    ``legs`` order at their true dimensions ``dims`` (u, l, d, r), with the
+    shared leg at index 0 only and zero padding to D."""
+    n = [dims[i - 1] for i in legs]
     E = np.zeros((k, D, D, D, D))        # axes: k, legs[0], legs[1], legs[2], shared
-    E[..., 0] = np.moveaxis(Xmat.reshape(D, D, D, k), 3, 0)
+    E[:, :n[0], :n[1], :n[2], 0] = np.moveaxis(Xmat.reshape(n[0], n[1], n[2], k), 3, 0)
     pos = {legs[0]: 1, legs[1]: 2, legs[2]: 3, shared: 4}
     t = np.zeros((dp, D, D, D, D))
     t[:k] = E.transpose([0, pos[1], pos[2], pos[3], pos[4]])
     return t
 
 
-def bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb):
+def bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb, dims_a, dims_b):
     """Environment N[(k_a,k_b),(k_a',k_b')] of the two reduced tensors: the
     two-site reduced density matrix of the network in which sites a and b
     carry their isometries with the isometry bond as the physical index (the
@@ -97,8 +115,8 @@ def bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb):
     M[:, :d] = A
     ia = a[1] * Lx + a[0]
     ib = b[1] * Lx + b[0]
-    M[ia] = _reduced_site(Xa, oa, sa, k, dp, D)
-    M[ib] = _reduced_site(Yb.T, ob_, sb, kb, dp, D)
+    M[ia] = _reduced_site(Xa, oa, sa, dims_a, k, dp, D)
+    M[ib] = _reduced_site(Yb.T, ob_, sb, dims_b, kb, dp, D)
     env = ob.BlockBP(M, D=D, chi=bp.chi, bx=bp.bx, by=bp.by, Lx=Lx, Ly=Ly,
                      chi_env=bp.chi_env, n_fit=bp.n_fit, seed=bp.seed, d=dp)
     env.msgs = {key: [t.copy() for t in m] for key, m in bp.msgs.items()}
@@ -124,6 +142,11 @@ def fit_pair(N, Theta, G, D, n_als):
     T = np.einsum("tusv,asvb->atub", G4, Theta)          # [ka, s0', s1', kb]
     U, S, Vt = np.linalg.svd(T.reshape(k * d, d * kb), full_matrices=False)
     r = min(D, S.size)
+    # sign of each singular pair: the largest-magnitude entry of u_r positive
+    for j in range(r):
+        if U[np.argmax(np.abs(U[:, j])), j] < 0:
+            U[:, j] = -U[:, j]
+            Vt[j] = -Vt[j]
     R = np.zeros((k * d, D))
     Lm = np.zeros((D, d * kb))
     R[:, :r] = U[:, :r] * np.sqrt(S[:r])
@@ -145,14 +168,21 @@ def fit_pair(N, Theta, G, D, n_als):
     return R, L
 
 
-def rebuild(Xa, R, L, Yb, oa, ob_, sa, sb, d, D):
+def rebuild(Xa, R, L, Yb, oa, ob_, sa, sb, d, D, dims_a, dims_b):
     """Site tensors [s, u, l, d, r] from the isometries and the fitted
-    reduced tensors, each scaled to a largest entry of 1."""
+    reduced tensors (zero padding to D on the edge legs), each scaled to a
+    largest entry of 1."""
     k, kb = Xa.shape[1], Yb.shape[0]
-    Ma = (Xa @ R.reshape(k, d * D)).reshape(D, D, D, d, D)   # legs oa, then s, shared
-    Mb = (L.reshape(D * d, kb) @ Yb).reshape(D, d, D, D, D)  # shared, s, legs ob_
-    Aa = _untranspose(Ma, oa + [0, sa])
-    Ab = _untranspose(Mb, [sb, 0] + ob_)
+    na = [dims_a[i - 1] for i in oa]
+    nb = [dims_b[i - 1] for i in ob_]
+    Ma = (Xa @ R.reshape(k, d * D)).reshape(na + [d, D])    # legs oa, then s, shared
+    Mb = (L.reshape(D * d, kb) @ Yb).reshape([D, d] + nb)   # shared, s, legs ob_
+    Aa = np.zeros((d, D, D, D, D))
+    Ab = np.zeros((d, D, D, D, D))
+    ta = _untranspose(Ma, oa + [0, sa])
+    tb = _untranspose(Mb, [sb, 0] + ob_)
+    Aa[(slice(None),) + tuple(slice(0, n) for n in ta.shape[1:])] = ta
+    Ab[(slice(None),) + tuple(slice(0, n) for n in tb.shape[1:])] = tb
     return Aa / np.abs(Aa).max(), Ab / np.abs(Ab).max()
 
 
@@ -177,10 +207,12 @@ def ite_step(A, Lx, Ly, D, chi, bx, by, gate, n_als=4, chi_env=None, sweeps=30,
     for (a, b) in bond_order(Lx, Ly):
         horizontal = a[1] == b[1]
         ia, ib = a[1] * Lx + a[0], b[1] * Lx + b[0]
-        Xa, Ra, Lb, Yb, oa, ob_, sa, sb = split_pair(A[ia], A[ib], horizontal)
+        da = leg_dims(a[0], a[1], Lx, Ly, D)
+        db = leg_dims(b[0], b[1], Lx, Ly, D)
+        Xa, Ra, Lb, Yb, oa, ob_, sa, sb = split_pair(A[ia], A[ib], horizontal, da, db)
         k, kb = Xa.shape[1], Yb.shape[0]
-        N = bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb)
+        N = bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb, da, db)
         Theta = np.einsum("asr,rtb->astb", Ra, Lb)
         R, L = fit_pair(N, Theta, gate, D, n_als)
-        A[ia], A[ib] = rebuild(Xa, R, L, Yb, oa, ob_, sa, sb, d, D)
+        A[ia], A[ib] = rebuild(Xa, R, L, Yb, oa, ob_, sa, sb, d, D, da, db)
     return A, bp

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libbbp.so")
 
 EXPORTS = (
     "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_allocator",
-    "bbp_set_tensors",
+    "bbp_set_tensors", "bbp_get_tensors",
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
     "bbp_expect_bonds", "bbp_rdm_sites", "bbp_rdm_bonds", "bbp_trace_distance",
     "bbp_log_norm", "bbp_get_messages",
@@ -34,7 +34,7 @@ EXPORTS = (
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
     "bbp_server_sweeps", "bbp_server_error", "bbp_server_destroy",
     "bbp_update_workspace", "bbp_update_message", "bbp_update_message_noalloc",
-    "bbp_update_last_error",
+    "bbp_update_last_error", "bbp_ite_step", "bbp_ite_fit",
 )
 
 OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
@@ -87,6 +87,7 @@ def _load():
         "bbp_set_stream": [P, P],
         "bbp_set_allocator": [P, ALLOC_FN, FREE_FN, P],
         "bbp_set_tensors": [P, dp, c_size],
+        "bbp_get_tensors": [P, dp, c_size],
         "bbp_sweep": [P, c_int, dp],
         "bbp_expect_site": [P, c_int, c_int, dp, dp],
         "bbp_expect_bond": [P, c_int, c_int, c_int, c_int, dp, dp],
@@ -95,6 +96,8 @@ def _load():
         "bbp_rdm_sites": [P, c_int, ip, ip, dp],
         "bbp_rdm_bonds": [P, c_int, ip, ip, ip, ip, dp],
         "bbp_trace_distance": [c_int, dp, dp, dp],
+        "bbp_ite_step": [P, dp, c_int, dp],
+        "bbp_ite_fit": [c_int, c_int, c_int, c_int, dp, dp, dp, c_int, dp, dp, dp],
         "bbp_log_norm": [P, dp, ip],
         "bbp_get_messages": [P, dp, c_size, ctypes.POINTER(c_size)],
         "bbp_set_messages": [P, dp, c_size],
@@ -209,6 +212,13 @@ class BlockBP:
     def set_tensors(self, A):
         A = np.ascontiguousarray(A, dtype=np.float64)
         self._check(_lib.bbp_set_tensors(self._ctx, _dptr(A), A.size))
+        self._tensor_shape = A.shape
+
+    def get_tensors(self):
+        """bbp_get_tensors: the site tensors, shape as last set."""
+        out = np.zeros(self._tensor_shape)
+        self._check(_lib.bbp_get_tensors(self._ctx, _dptr(out), out.size))
+        return out
 
     def sweep(self, n=1):
         r = ctypes.c_double(0.0)
@@ -267,6 +277,17 @@ class BlockBP:
         self._check(_lib.bbp_rdm_bonds(self._ctx, len(b), *[_iptr(c) for c in cols],
                                        _dptr(out)))
         return out
+
+    def ite_step(self, gate, n_als=4):
+        """bbp_ite_step: one Trotter step of the blockBP update with the
+        gate (d^2 x d^2) on every bond, the current messages fixed.  Returns
+        (gates applied, summed relative fit error)."""
+        g = np.ascontiguousarray(gate, dtype=np.float64).reshape(-1)
+        if g.size != self.d ** 4:
+            raise ValueError(f"gate needs {self.d ** 4} entries")
+        info = np.zeros(2)
+        self._check(_lib.bbp_ite_step(self._ctx, _dptr(g), int(n_als), _dptr(info)))
+        return int(info[0]), float(info[1])
 
     def log_norm(self):
         v = ctypes.c_double()
@@ -444,6 +465,25 @@ def trace_distance(rho, sigma):
     if st != 0:
         raise BBPError(st, "bbp_trace_distance rejected its arguments")
     return out.value
+
+
+def ite_fit(N, theta, gate, D, n_als=4):
+    """bbp_ite_fit: R[k, d, D], L[D, d, kb] fitted to gate . theta in the
+    metric N[(k kb), (k kb)]; returns (R, L, relative fit error)."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    k, d, _, kb = th.shape
+    n = np.ascontiguousarray(N, dtype=np.float64).reshape(-1)
+    g = np.ascontiguousarray(gate, dtype=np.float64).reshape(-1)
+    if n.size != (k * kb) ** 2 or g.size != d ** 4:
+        raise ValueError("N must be (k kb)^2 and the gate d^4 entries")
+    R = np.zeros((k, d, D))
+    L = np.zeros((D, d, kb))
+    loss = ctypes.c_double()
+    st = _lib.bbp_ite_fit(d, D, k, kb, _dptr(n), _dptr(th), _dptr(g), int(n_als),
+                          _dptr(R), _dptr(L), ctypes.byref(loss))
+    if st != 0:
+        raise BBPError(st, "bbp_ite_fit rejected its arguments or the fit is singular")
+    return R, L, loss.value
 
 
 def update_workspace(H, W, D, chi, d=2, n_fit=2):

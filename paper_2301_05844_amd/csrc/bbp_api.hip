@@ -2015,6 +2015,14 @@ static std::pair<int, int> message_shape(const bbp_ctx *c, const Message &m) {
   return {lr ? c->bx : c->by, lr ? c->by : c->bx};
 }
 
+bbp_status bbp_get_tensors(bbp_ctx *c, double *A, size_t n) {
+  if (!c || !A) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (n != c->A.size()) return c->fail(BBP_EINVAL, "tensor size does not match the lattice");
+  std::copy(c->A.begin(), c->A.end(), A);
+  return BBP_OK;
+}
+
 bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   if (!c || !A) return BBP_EINVAL;
   AcctScope acct_scope(&c->mem);
@@ -3088,6 +3096,22 @@ bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
     for (auto &kv : s->groups) std::fill(kv.second->have.begin(), kv.second->have.end(), 0);
   }
   return BBP_OK;
+}
+
+bbp_status ctx_info(bbp_ctx *c, CtxInfo *o) {
+  if (!c || !o) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  *o = CtxInfo{c->infinite, c->Lx, c->Ly, c->bx, c->by, c->D, c->chi, c->d,
+               c->chi_env, c->n_fit, c->sx, c->sy, c->single_layer, c->seed,
+               c->stream};
+  return BBP_OK;
+}
+
+bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m) { return c->fail(s, m); }
+
+const double *ctx_tensors(bbp_ctx *c, size_t *n) {
+  *n = c->A.size();
+  return c->A.data();
 }
 
 }  // namespace bbp

@@ -234,4 +234,15 @@ bbp_status ctx_set_engine(bbp_ctx *c);
 bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
                         bbp_status *status, std::string *err);
 
+// What the blockBP update (bbp_ite_step) needs of a context: its problem,
+// options, stream and host copy of the tensors, and its error slot.
+struct CtxInfo {
+  int infinite, Lx, Ly, bx, by, D, chi, d, chi_env, n_fit, sx, sy, single_layer;
+  uint64_t seed;
+  hipStream_t stream;
+};
+bbp_status ctx_info(bbp_ctx *c, CtxInfo *out);
+bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m);
+const double *ctx_tensors(bbp_ctx *c, size_t *n);
+
 }  // namespace bbp

@@ -1,0 +1,552 @@
+// libbbp: the blockBP update, imaginary time evolution of a finite PEPS with
+// block-BP environments (App. B of Guo, Poletti, Arad; Eq. (Ut)).
+//
+// One Trotter step applies the gate G = exp(-h dtau) to every nearest-
+// neighbour bond, horizontal bonds row by row, then vertical bonds column
+// by column, with the context's current messages as the boundary of every
+// region.  A gate is fitted by minimising ||psi' - G psi||^2 over the two
+// tensors of its bond in the reduced form of the full update: the first
+// tensor is split by QR into an isometry on its three outer legs and a
+// reduced tensor [k][s][shared], the second by LQ into [shared][s][k'] and
+// an isometry; the environment of the two reduced tensors is the two-site
+// reduced density matrix of the network in which the two sites carry their
+// isometries (the isometry bond as the physical index, the shared leg cut to
+// index 0) -- computed on the GPU by a second context that shares the
+// lattice, the block partition and the messages; the reduced tensors are
+// then fitted by alternating least squares on the host (their systems have
+// at most k d D unknowns), and the new tensors replace the old ones.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bbp.h"
+#include "bbp_internal.h"
+
+namespace {
+
+using Mat = std::vector<double>;  // row-major
+
+// Thin Householder QR of an m x n matrix (m >= n or not): Q (m x k), R
+// (k x n), k = min(m, n); Q's columns orthonormal, A = Q R.
+void qr_thin(const Mat &A, int m, int n, Mat &Q, Mat &R) {
+  const int k = std::min(m, n);
+  Mat a = A;
+  std::vector<Mat> vs;
+  std::vector<double> taus;
+  for (int j = 0; j < k; ++j) {
+    double sigma = 0.0;
+    for (int i = j + 1; i < m; ++i) sigma += a[(size_t)i * n + j] * a[(size_t)i * n + j];
+    const double alpha = a[(size_t)j * n + j];
+    Mat v(m, 0.0);
+    double tau = 0.0;
+    if (sigma > 0.0) {
+      const double nrm = std::sqrt(alpha * alpha + sigma);
+      const double beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      v[j] = 1.0;
+      for (int i = j + 1; i < m; ++i) v[i] = a[(size_t)i * n + j] * scal;
+      // apply H = I - tau v v^T to the columns j..n-1
+      for (int c = j; c < n; ++c) {
+        double w = 0.0;
+        for (int i = j; i < m; ++i) w += v[i] * a[(size_t)i * n + c];
+        w *= tau;
+        for (int i = j; i < m; ++i) a[(size_t)i * n + c] -= w * v[i];
+      }
+    }
+    vs.push_back(v);
+    taus.push_back(tau);
+  }
+  R.assign((size_t)k * n, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int c = i; c < n; ++c) R[(size_t)i * n + c] = a[(size_t)i * n + c];
+  // Q = H_0 ... H_{k-1} [I_k; 0]
+  Q.assign((size_t)m * k, 0.0);
+  for (int i = 0; i < k; ++i) Q[(size_t)i * k + i] = 1.0;
+  for (int j = k - 1; j >= 0; --j) {
+    if (taus[j] == 0.0) continue;
+    const Mat &v = vs[j];
+    for (int c = 0; c < k; ++c) {
+      double w = 0.0;
+      for (int i = j; i < m; ++i) w += v[i] * Q[(size_t)i * k + c];
+      w *= taus[j];
+      for (int i = j; i < m; ++i) Q[(size_t)i * k + c] -= w * v[i];
+    }
+  }
+}
+
+// Singular value decomposition of an m x n matrix by one-sided Jacobi
+// rotations of its columns (Hestenes): A = U diag(S) V^T with S descending,
+// U m x n, V n x n.
+void svd_jacobi(const Mat &A, int m, int n, Mat &U, std::vector<double> &S, Mat &V) {
+  Mat a = A;
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int r = 0; r < m; ++r) {
+          al += a[(size_t)r * n + p] * a[(size_t)r * n + p];
+          be += a[(size_t)r * n + q] * a[(size_t)r * n + q];
+          ga += a[(size_t)r * n + p] * a[(size_t)r * n + q];
+        }
+        if (std::fabs(ga) <= 1e-300 || al == 0.0 || be == 0.0) continue;
+        off = std::max(off, std::fabs(ga) / std::sqrt(al * be));
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+        for (int r = 0; r < m; ++r) {
+          const double x = a[(size_t)r * n + p], y = a[(size_t)r * n + q];
+          a[(size_t)r * n + p] = cs * x - sn * y;
+          a[(size_t)r * n + q] = sn * x + cs * y;
+        }
+        for (int r = 0; r < n; ++r) {
+          const double x = V[(size_t)r * n + p], y = V[(size_t)r * n + q];
+          V[(size_t)r * n + p] = cs * x - sn * y;
+          V[(size_t)r * n + q] = sn * x + cs * y;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+  std::vector<double> nrm(n);
+  for (int c = 0; c < n; ++c) {
+    double s = 0.0;
+    for (int r = 0; r < m; ++r) s += a[(size_t)r * n + c] * a[(size_t)r * n + c];
+    nrm[c] = std::sqrt(s);
+  }
+  std::vector<int> order(n);
+  for (int c = 0; c < n; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
+  U.assign((size_t)m * n, 0.0);
+  S.assign(n, 0.0);
+  Mat Vs((size_t)n * n);
+  for (int c = 0; c < n; ++c) {
+    const int o = order[c];
+    S[c] = nrm[o];
+    for (int r = 0; r < m; ++r) U[(size_t)r * n + c] = nrm[o] > 0 ? a[(size_t)r * n + o] / nrm[o] : 0.0;
+    for (int r = 0; r < n; ++r) Vs[(size_t)r * n + c] = V[(size_t)r * n + o];
+  }
+  V.swap(Vs);
+}
+
+// Solves M x = y for the normal equations of a fit: M symmetrised, 1e-12
+// trace/n added to the diagonal, Gaussian elimination with partial pivoting.
+bool solve_normal(Mat M, int n, std::vector<double> &y) {
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i) tr += M[(size_t)i * n + i];
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double s = 0.5 * (M[(size_t)i * n + j] + M[(size_t)j * n + i]);
+      M[(size_t)i * n + j] = M[(size_t)j * n + i] = s;
+    }
+  for (int i = 0; i < n; ++i) M[(size_t)i * n + i] += 1e-12 * tr / n;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)piv * n + c])) piv = r;
+    if (M[(size_t)piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(M[(size_t)c * n + j], M[(size_t)piv * n + j]);
+      std::swap(y[c], y[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = M[(size_t)r * n + c] / M[(size_t)c * n + c];
+      if (f == 0.0) continue;
+      for (int j = c; j < n; ++j) M[(size_t)r * n + j] -= f * M[(size_t)c * n + j];
+      y[r] -= f * y[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double s = y[c];
+    for (int j = c + 1; j < n; ++j) s -= M[(size_t)c * n + j] * y[j];
+    y[c] = s / M[(size_t)c * n + c];
+  }
+  return true;
+}
+
+// Index of a site tensor entry [s][u][l][d][r] with dimensions (dd, D).
+inline size_t aidx5(int D, int s, const int leg[5]) {
+  (void)s;
+  return ((((size_t)leg[0] * D + leg[1]) * D + leg[2]) * D + leg[3]) * D + leg[4];
+}
+
+// The reduced-tensor fit of one gate: R[ka][s][r] L[r][t][kb] (bond D)
+// closest to T = G Theta in the metric of the environment
+// N[(ka,kb)][(ka',kb')], by alternating least squares started from the
+// rank-D truncated SVD of T with the singular values split evenly and each
+// singular pair signed so that the largest-magnitude entry of its left
+// vector is positive.  Writes
+// the relative error of the fit in that metric to *loss.
+bool fit_pair(int d, int D, int k, int kb, const double *Nm, const double *Th,
+              const double *gate, int n_als, double *Rout, double *Lout, double *loss) {
+  auto N = [&](int a, int b, int a2, int b2) {
+    return Nm[((size_t)(a * kb + b) * k + a2) * kb + b2];
+  };
+  const int nT = k * d * d * kb;
+  std::vector<double> T(nT, 0.0);
+  for (int a = 0; a < k; ++a)
+    for (int s2 = 0; s2 < d; ++s2)
+      for (int t2 = 0; t2 < d; ++t2)
+        for (int b = 0; b < kb; ++b) {
+          double v = 0.0;
+          for (int s = 0; s < d; ++s)
+            for (int t = 0; t < d; ++t)
+              v += gate[(size_t)(s2 * d + t2) * d * d + s * d + t] *
+                   Th[((a * d + s) * d + t) * kb + b];
+          T[((a * d + s2) * d + t2) * kb + b] = v;
+        }
+  Mat Tm(T.begin(), T.end()), U, V;
+  std::vector<double> S;
+  const int nc = d * kb, rk = std::min(D, std::min(k * d, nc));
+  if (k * d >= nc) {
+    svd_jacobi(Tm, k * d, nc, U, S, V);
+  } else {
+    // more columns than rows: decompose T^T = V S U^T instead
+    Mat Tt((size_t)nc * k * d);
+    for (int i = 0; i < k * d; ++i)
+      for (int j = 0; j < nc; ++j) Tt[(size_t)j * k * d + i] = Tm[(size_t)i * nc + j];
+    svd_jacobi(Tt, nc, k * d, V, S, U);
+  }
+  const int ur = (int)(U.size() / (size_t)(k * d)), vr = (int)(V.size() / (size_t)nc);
+  // sign of each singular pair: the largest-magnitude entry of u_r positive
+  // (the first one on ties), which fixes the bond gauge of the fitted pair
+  for (int r = 0; r < rk; ++r) {
+    int im = 0;
+    for (int i = 1; i < k * d; ++i)
+      if (std::fabs(U[(size_t)i * ur + r]) > std::fabs(U[(size_t)im * ur + r])) im = i;
+    if (U[(size_t)im * ur + r] < 0.0) {
+      for (int i = 0; i < k * d; ++i) U[(size_t)i * ur + r] = -U[(size_t)i * ur + r];
+      for (int j = 0; j < nc; ++j) V[(size_t)j * vr + r] = -V[(size_t)j * vr + r];
+    }
+  }
+  std::vector<double> R((size_t)k * d * D, 0.0), L((size_t)D * nc, 0.0);
+  for (int i = 0; i < k * d; ++i)
+    for (int r = 0; r < rk; ++r) R[(size_t)i * D + r] = U[(size_t)i * ur + r] * std::sqrt(S[r]);
+  for (int r = 0; r < rk; ++r)
+    for (int j = 0; j < nc; ++j) L[(size_t)r * nc + j] = std::sqrt(S[r]) * V[(size_t)j * vr + r];
+  for (int pass = 0; pass < n_als; ++pass) {
+    // R with L fixed: M[(a,s,r),(a',s,q)] = sum L[r,u,b] N[a,b,a',b'] L[q,u,b']
+    const int nr = k * d * D;
+    Mat Mr((size_t)nr * nr, 0.0);
+    std::vector<double> y(nr, 0.0);
+    for (int a = 0; a < k; ++a)
+      for (int r = 0; r < D; ++r)
+        for (int a2 = 0; a2 < k; ++a2)
+          for (int q = 0; q < D; ++q) {
+            double v = 0.0;
+            for (int u = 0; u < d; ++u)
+              for (int b = 0; b < kb; ++b)
+                for (int b2 = 0; b2 < kb; ++b2)
+                  v += L[((size_t)r * d + u) * kb + b] * N(a, b, a2, b2) *
+                       L[((size_t)q * d + u) * kb + b2];
+            for (int s = 0; s < d; ++s)
+              Mr[((size_t)(a * d + s) * D + r) * nr + (a2 * d + s) * D + q] = v;
+          }
+    for (int a = 0; a < k; ++a)
+      for (int s = 0; s < d; ++s)
+        for (int r = 0; r < D; ++r) {
+          double v = 0.0;
+          for (int u = 0; u < d; ++u)
+            for (int b = 0; b < kb; ++b)
+              for (int a2 = 0; a2 < k; ++a2)
+                for (int b2 = 0; b2 < kb; ++b2)
+                  v += L[((size_t)r * d + u) * kb + b] * N(a, b, a2, b2) *
+                       T[((a2 * d + s) * d + u) * kb + b2];
+          y[(a * d + s) * D + r] = v;
+        }
+    if (!solve_normal(Mr, nr, y)) return false;
+    R.assign(y.begin(), y.end());
+    // L with R fixed: M[(r,u,b),(q,u,b')] = sum R[a,s,r] N[a,b,a',b'] R[a',s,q]
+    const int nl = D * d * kb;
+    Mat Ml((size_t)nl * nl, 0.0);
+    std::vector<double> z(nl, 0.0);
+    for (int r = 0; r < D; ++r)
+      for (int b = 0; b < kb; ++b)
+        for (int q = 0; q < D; ++q)
+          for (int b2 = 0; b2 < kb; ++b2) {
+            double v = 0.0;
+            for (int a = 0; a < k; ++a)
+              for (int s = 0; s < d; ++s)
+                for (int a2 = 0; a2 < k; ++a2)
+                  v += R[((size_t)a * d + s) * D + r] * N(a, b, a2, b2) *
+                       R[((size_t)a2 * d + s) * D + q];
+            for (int u = 0; u < d; ++u)
+              Ml[((size_t)(r * d + u) * kb + b) * nl + (q * d + u) * kb + b2] = v;
+          }
+    for (int r = 0; r < D; ++r)
+      for (int u = 0; u < d; ++u)
+        for (int b = 0; b < kb; ++b) {
+          double v = 0.0;
+          for (int a = 0; a < k; ++a)
+            for (int s = 0; s < d; ++s)
+              for (int a2 = 0; a2 < k; ++a2)
+                for (int b2 = 0; b2 < kb; ++b2)
+                  v += R[((size_t)a * d + s) * D + r] * N(a, b, a2, b2) *
+                       T[((a2 * d + s) * d + u) * kb + b2];
+          z[(r * d + u) * kb + b] = v;
+        }
+    if (!solve_normal(Ml, nl, z)) return false;
+    L.assign(z.begin(), z.end());
+  }
+  double num = 0.0, den = 0.0;
+  std::vector<double> diff(nT);
+  for (int a = 0; a < k; ++a)
+    for (int s = 0; s < d; ++s)
+      for (int t = 0; t < d; ++t)
+        for (int b = 0; b < kb; ++b) {
+          double v = 0.0;
+          for (int r = 0; r < D; ++r)
+            v += R[((size_t)a * d + s) * D + r] * L[((size_t)r * d + t) * kb + b];
+          diff[((a * d + s) * d + t) * kb + b] = v - T[((a * d + s) * d + t) * kb + b];
+        }
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < kb; ++b)
+      for (int a2 = 0; a2 < k; ++a2)
+        for (int b2 = 0; b2 < kb; ++b2) {
+          const double n4 = N(a, b, a2, b2);
+          for (int s = 0; s < d; ++s)
+            for (int t = 0; t < d; ++t) {
+              num += diff[((a * d + s) * d + t) * kb + b] * n4 *
+                     diff[((a2 * d + s) * d + t) * kb + b2];
+              den += T[((a * d + s) * d + t) * kb + b] * n4 * T[((a2 * d + s) * d + t) * kb + b2];
+            }
+        }
+  *loss = den > 0.0 ? num / den : 0.0;
+  for (double v : R)
+    if (!std::isfinite(v)) return false;
+  for (double v : L)
+    if (!std::isfinite(v)) return false;
+  std::copy(R.begin(), R.end(), Rout);
+  std::copy(L.begin(), L.end(), Lout);
+  return true;
+}
+
+}  // namespace
+
+extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als,
+                                   double *info) {
+  if (!c) return BBP_EINVAL;
+  bbp::CtxInfo ci;
+  bbp_status st = bbp::ctx_info(c, &ci);
+  if (st != BBP_OK) return st;
+  if (!gate || n_als < 1 || n_als > 64)
+    return bbp::ctx_fail(c, BBP_EINVAL, "gate needed and n_als in [1, 64]");
+  if (ci.infinite || ci.single_layer)
+    return bbp::ctx_fail(c, BBP_EINVAL, "the update is for finite double-layer lattices");
+  const int d = ci.d, D = ci.D, Lx = ci.Lx, Ly = ci.Ly;
+  for (int i = 0; i < d * d * d * d; ++i)
+    if (!std::isfinite(gate[i])) return bbp::ctx_fail(c, BBP_EINVAL, "non-finite gate");
+  size_t nA = 0;
+  const double *A0 = bbp::ctx_tensors(c, &nA);
+  std::vector<double> A(A0, A0 + nA);
+  const size_t ss = (size_t)d * D * D * D * D, D3 = (size_t)D * D * D;
+  // physical dimension of the environment network: the widest isometry bond
+  const int dp = std::max(d, (int)std::min<size_t>(D3, (size_t)d * D));
+  if (dp > 8)
+    return bbp::ctx_fail(c, BBP_EINVAL, "the update needs min(D^3, d D) <= 8 (the environment's "
+                                        "physical dimension)");
+  if (Lx < 2 && Ly < 2) return bbp::ctx_fail(c, BBP_EINVAL, "a lattice without bonds");
+  // the messages every region's boundary is built from, kept through the step
+  size_t need = 0;
+  if ((st = bbp_get_messages(c, nullptr, 0, &need)) != BBP_OK) return st;
+  std::vector<double> msgs(need);
+  if ((st = bbp_get_messages(c, msgs.data(), need, &need)) != BBP_OK) return st;
+  // the environment context: the same lattice, partition, bond caps and fit
+  // settings, physical dimension dp (the isometry bond of the two sites)
+  bbp_ctx *e = nullptr;
+  if ((st = bbp_create(&e, 0, Lx, Ly, 0, 0, ci.bx, ci.by, D, ci.chi)) != BBP_OK)
+    return bbp::ctx_fail(c, st, "environment context");
+  struct Free {
+    bbp_ctx *e;
+    ~Free() { bbp_destroy(e); }
+  } free_e{e};
+  const std::pair<const char *, double> opts[] = {
+      {"d", (double)dp}, {"chi_env", (double)ci.chi_env}, {"n_fit", (double)ci.n_fit},
+      {"seed", (double)ci.seed}, {"shift_x", (double)ci.sx}, {"shift_y", (double)ci.sy},
+      {"lanes", 1.0}};
+  for (auto &o : opts)
+    if ((st = bbp_set_option(e, o.first, o.second)) != BBP_OK)
+      return bbp::ctx_fail(c, st, std::string("environment option ") + o.first + ": " +
+                                      bbp_last_error(e));
+  (void)bbp_set_stream(e, ci.stream);
+  double loss_sum = 0.0;
+  int gates = 0;
+  // gate order: horizontal bonds row by row, then vertical bonds column by column
+  std::vector<std::array<int, 4>> bonds;
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x + 1 < Lx; ++x) bonds.push_back({x, y, x + 1, y});
+  for (int x = 0; x < Lx; ++x)
+    for (int y = 0; y + 1 < Ly; ++y) bonds.push_back({x, y, x, y + 1});
+  std::vector<double> M((size_t)Lx * Ly * dp * D * D * D * D);
+  // true dimensions of the legs (index 1..4 = u, l, d, r) of a site: 1 on
+  // the lattice edge, so that the isometries span physical directions only
+  auto leg_dims = [&](int x, int y, int n[5]) {
+    n[0] = d;
+    n[1] = y == 0 ? 1 : D;
+    n[2] = x == 0 ? 1 : D;
+    n[3] = y == Ly - 1 ? 1 : D;
+    n[4] = x == Lx - 1 ? 1 : D;
+  };
+  for (const auto &bd : bonds) {
+    const bool horiz = bd[1] == bd[3];
+    const int ia = bd[1] * Lx + bd[0], ib = bd[3] * Lx + bd[2];
+    const int sa = horiz ? 4 : 3, sb = horiz ? 2 : 1;  // shared leg (0 = s)
+    int oa[3], ob[3];
+    for (int t = 1, u = 0, w = 0; t <= 4; ++t) {
+      if (t != sa) oa[u++] = t;
+      if (t != sb) ob[w++] = t;
+    }
+    int da[5], db[5];
+    leg_dims(bd[0], bd[1], da);
+    leg_dims(bd[2], bd[3], db);
+    const int rows_a = da[oa[0]] * da[oa[1]] * da[oa[2]];
+    const int cols_b = db[ob[0]] * db[ob[1]] * db[ob[2]];
+    auto row_of = [](const int leg[5], const int o[3], const int n[5]) {
+      return ((size_t)leg[o[0]] * n[o[1]] + leg[o[1]]) * n[o[2]] + leg[o[2]];
+    };
+    const double *Aa = A.data() + ia * ss, *Ab = A.data() + ib * ss;
+    // Ma[(oa legs), (s, shared)] and Mb^T[(ob legs), (shared, s)], true extents
+    Mat Ma((size_t)rows_a * d * D, 0.0), MbT((size_t)cols_b * D * d, 0.0);
+    int leg[5];
+    for (leg[0] = 0; leg[0] < d; ++leg[0])
+      for (leg[1] = 0; leg[1] < D; ++leg[1])
+        for (leg[2] = 0; leg[2] < D; ++leg[2])
+          for (leg[3] = 0; leg[3] < D; ++leg[3])
+            for (leg[4] = 0; leg[4] < D; ++leg[4]) {
+              const size_t src = aidx5(D, 0, leg);
+              if (leg[1] < da[1] && leg[2] < da[2] && leg[3] < da[3] && leg[4] < da[4])
+                Ma[row_of(leg, oa, da) * d * D + (size_t)leg[0] * D + leg[sa]] = Aa[src];
+              if (leg[1] < db[1] && leg[2] < db[2] && leg[3] < db[3] && leg[4] < db[4])
+                MbT[row_of(leg, ob, db) * D * d + (size_t)leg[sb] * d + leg[0]] = Ab[src];
+            }
+    Mat Xa, Ra, Qt, Rt;
+    qr_thin(Ma, rows_a, d * D, Xa, Ra);     // Xa: rows_a x k, Ra: k x (d D)
+    qr_thin(MbT, cols_b, D * d, Qt, Rt);    // Mb^T = Qt Rt: L = Rt^T, Y = Qt^T
+    const int k = std::min(rows_a, d * D), kb = std::min(cols_b, D * d);
+    // the environment network: every site padded to dp, sites a and b
+    // carrying their isometries with the shared leg at index 0
+    std::fill(M.begin(), M.end(), 0.0);
+    const size_t sp = (size_t)dp * D * D * D * D;
+    for (int i = 0; i < Lx * Ly; ++i)
+      if (i != ia && i != ib)
+        std::copy(A.begin() + i * ss, A.begin() + (i + 1) * ss, M.begin() + i * sp);
+    for (int q = 0; q < k; ++q)
+      for (int r = 0; r < rows_a; ++r) {
+        int lg[5] = {0, 0, 0, 0, 0};
+        lg[oa[0]] = r / (da[oa[1]] * da[oa[2]]);
+        lg[oa[1]] = r / da[oa[2]] % da[oa[1]];
+        lg[oa[2]] = r % da[oa[2]];
+        M[ia * sp + (size_t)q * D3 * D + aidx5(D, 0, lg)] = Xa[(size_t)r * k + q];
+      }
+    for (int q = 0; q < kb; ++q)
+      for (int cc = 0; cc < cols_b; ++cc) {
+        int lg[5] = {0, 0, 0, 0, 0};
+        lg[ob[0]] = cc / (db[ob[1]] * db[ob[2]]);
+        lg[ob[1]] = cc / db[ob[2]] % db[ob[1]];
+        lg[ob[2]] = cc % db[ob[2]];
+        M[ib * sp + (size_t)q * D3 * D + aidx5(D, 0, lg)] = Qt[(size_t)cc * kb + q];
+      }
+    if ((st = bbp_set_tensors(e, M.data(), M.size())) != BBP_OK ||
+        (!msgs.empty() && (st = bbp_set_messages(e, msgs.data(), msgs.size())) != BBP_OK))
+      return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
+    std::vector<double> rho((size_t)dp * dp * dp * dp);
+    const int32_t x0 = bd[0], y0 = bd[1], x1 = bd[2], y1 = bd[3];
+    if ((st = bbp_rdm_bonds(e, 1, &x0, &y0, &x1, &y1, rho.data())) != BBP_OK)
+      return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
+    // N[(ka,kb),(ka',kb')], the isometry columns of the two sites
+    auto N = [&](int a, int b, int a2, int b2) {
+      return rho[((size_t)a * dp + b) * dp * dp + (size_t)a2 * dp + b2];
+    };
+    std::vector<double> Nm((size_t)k * kb * k * kb);
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < kb; ++b)
+        for (int a2 = 0; a2 < k; ++a2)
+          for (int b2 = 0; b2 < kb; ++b2)
+            Nm[((size_t)(a * kb + b) * k + a2) * kb + b2] = N(a, b, a2, b2);
+    // Theta[ka][s][t][kb] = sum_r Ra[ka][(s, r)] Lb[(r, t)][kb], Lb = Rt^T
+    std::vector<double> Th((size_t)k * d * d * kb, 0.0);
+    for (int a = 0; a < k; ++a)
+      for (int s = 0; s < d; ++s)
+        for (int t = 0; t < d; ++t)
+          for (int b = 0; b < kb; ++b) {
+            double v = 0.0;
+            for (int r = 0; r < D; ++r)
+              v += Ra[(size_t)a * d * D + s * D + r] * Rt[(size_t)b * D * d + r * d + t];
+            Th[((a * d + s) * d + t) * kb + b] = v;
+          }
+    std::vector<double> R((size_t)k * d * D), L((size_t)D * d * kb);
+    double loss = 0.0;
+    if (!fit_pair(d, D, k, kb, Nm.data(), Th.data(), gate, n_als, R.data(), L.data(), &loss))
+      return bbp::ctx_fail(c, BBP_ENUMERIC, "singular reduced-tensor fit");
+    loss_sum += loss;
+    // new tensors: A_a = X_a R, A_b = L Y (Y = Qt^T) on the true extents,
+    // zero padding elsewhere, each scaled to a largest entry of 1
+    std::vector<double> na(ss, 0.0), nb(ss, 0.0);
+    for (leg[0] = 0; leg[0] < d; ++leg[0])
+      for (leg[1] = 0; leg[1] < D; ++leg[1])
+        for (leg[2] = 0; leg[2] < D; ++leg[2])
+          for (leg[3] = 0; leg[3] < D; ++leg[3])
+            for (leg[4] = 0; leg[4] < D; ++leg[4]) {
+              const size_t dst = aidx5(D, 0, leg);
+              if (leg[1] < da[1] && leg[2] < da[2] && leg[3] < da[3] && leg[4] < da[4]) {
+                const size_t ra = row_of(leg, oa, da);
+                double v = 0.0;
+                for (int q = 0; q < k; ++q)
+                  v += Xa[ra * k + q] * R[((size_t)q * d + leg[0]) * D + leg[sa]];
+                na[dst] = v;
+              }
+              if (leg[1] < db[1] && leg[2] < db[2] && leg[3] < db[3] && leg[4] < db[4]) {
+                const size_t cb = row_of(leg, ob, db);
+                double w = 0.0;
+                for (int q = 0; q < kb; ++q)
+                  w += L[((size_t)leg[sb] * d + leg[0]) * kb + q] * Qt[cb * kb + q];
+                nb[dst] = w;
+              }
+            }
+    double ma = 0.0, mb = 0.0;
+    for (size_t i = 0; i < ss; ++i) {
+      ma = std::max(ma, std::fabs(na[i]));
+      mb = std::max(mb, std::fabs(nb[i]));
+    }
+    if (!(ma > 0.0) || !(mb > 0.0) || !std::isfinite(ma) || !std::isfinite(mb))
+      return bbp::ctx_fail(c, BBP_ENUMERIC, "vanishing or non-finite fitted tensor");
+    for (size_t i = 0; i < ss; ++i) {
+      A[ia * ss + i] = na[i] / ma;
+      A[ib * ss + i] = nb[i] / mb;
+    }
+    ++gates;
+  }
+  // the new tensors, with the messages the step started from
+  if ((st = bbp_set_tensors(c, A.data(), A.size())) != BBP_OK) return st;
+  if (!msgs.empty() && (st = bbp_set_messages(c, msgs.data(), msgs.size())) != BBP_OK)
+    return st;
+  if (info) {
+    info[0] = gates;
+    info[1] = loss_sum;
+  }
+  return BBP_OK;
+}
+
+extern "C" bbp_status bbp_ite_fit(int32_t d, int32_t D, int32_t k, int32_t kb, const double *N,
+                                  const double *theta, const double *gate, int32_t n_als,
+                                  double *R, double *L, double *loss) {
+  if (d < 1 || d > 8 || D < 1 || D > 8 || k < 1 || k > 64 || kb < 1 || kb > 64 || n_als < 1 ||
+      n_als > 64 || !N || !theta || !gate || !R || !L)
+    return BBP_EINVAL;
+  const size_t nn = (size_t)k * kb * k * kb, nt = (size_t)k * d * d * kb;
+  for (size_t i = 0; i < nn; ++i)
+    if (!std::isfinite(N[i])) return BBP_EINVAL;
+  for (size_t i = 0; i < nt; ++i)
+    if (!std::isfinite(theta[i])) return BBP_EINVAL;
+  for (int i = 0; i < d * d * d * d; ++i)
+    if (!std::isfinite(gate[i])) return BBP_EINVAL;
+  double l = 0.0;
+  if (!fit_pair(d, D, k, kb, N, theta, gate, n_als, R, L, &l)) return BBP_ENUMERIC;
+  if (loss) *loss = l;
+  return BBP_OK;
+}

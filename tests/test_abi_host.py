@@ -171,3 +171,59 @@ def test_trace_distance_on_the_host():
     assert abs(bbp.trace_distance(r, s) - trace_distance(r, s)) < 1e-13
     p, q = np.diag([0.5, 0.3, 0.2, 0.0]), np.diag([0.25, 0.25, 0.25, 0.25])
     assert abs(bbp.trace_distance(p, q) - 0.5 * (0.25 + 0.05 + 0.05 + 0.25)) < 1e-15
+
+
+def _ite_case(seed, k, kb, d=2, D=2, rank=None):
+    from scipy.linalg import expm
+    rng = np.random.default_rng(seed)
+    n = k * kb
+    B = rng.standard_normal((n, rank or n))
+    N = B @ B.T
+    N /= np.trace(N)
+    theta = rng.standard_normal((k, d, d, kb))
+    sz = np.diag([0.5, -0.5])
+    sx = np.array([[0.0, 0.5], [0.5, 0.0]])
+    h = -np.kron(sz, sz) * 4 - 0.5 * (np.kron(sx, np.eye(2)) + np.kron(np.eye(2), sx)) * 2
+    return N, theta, expm(-0.1 * h)
+
+
+@pytest.mark.parametrize("case", [(0, 4, 4, None), (1, 8, 8, None), (2, 6, 6, 20),
+                                  (3, 4, 8, None)])
+def test_ite_fit_on_the_host_matches_oracle(case):
+    """bbp_ite_fit (host least squares of App. B) against the oracle's
+    fit_pair on the same environment: the fitted pair R L (invariant under
+    the bond gauge, which the SVD start's signs fix differently) and the
+    fit error agree; a rank-deficient environment (k kb = 36, rank 20)
+    included."""
+    from oracle import ite
+    bbp = _bbp()
+    seed, k, kb, rank = case
+    N, theta, gate = _ite_case(seed, k, kb, rank=rank)
+    D = 2 if k == 4 and kb == 4 else 3
+    R, L, loss = bbp.ite_fit(N, theta, gate, D, n_als=4)
+    Ro, Lo = ite.fit_pair(N, theta, gate, D, 4)
+    # the SVD start is signed by one convention on both sides: R, L agree
+    assert np.abs(R - Ro).max() < 1e-9 * np.abs(Ro).max()
+    assert np.abs(L - Lo).max() < 1e-9 * np.abs(Lo).max()
+    pair = np.einsum("asr,rtb->astb", R, L)
+    pair_o = np.einsum("asr,rtb->astb", Ro, Lo)
+    err = np.abs(pair - pair_o).max() / np.abs(pair_o).max()
+    T = np.einsum("tusv,asvb->atub", gate.reshape(2, 2, 2, 2), theta)
+    diff = (pair_o - T).transpose(1, 2, 0, 3).reshape(4, -1)
+    Tm = T.transpose(1, 2, 0, 3).reshape(4, -1)
+    N4 = N.reshape(k * kb, k * kb)
+    loss_o = np.trace(diff @ N4 @ diff.T) / np.trace(Tm @ N4 @ Tm.T)
+    print(f"k {k} kb {kb} D {D}: max rel |d(RL)| {err:.2e}, loss {loss:.3e} vs {loss_o:.3e}")
+    assert err < 1e-9
+    assert abs(loss - loss_o) < 1e-9 * max(loss_o, 1e-3)
+
+
+def test_ite_fit_rejects_bad_arguments():
+    bbp = _bbp()
+    N, theta, gate = _ite_case(0, 4, 4)
+    with pytest.raises(bbp.BBPError):
+        bbp.ite_fit(N, theta, gate, 2, n_als=0)
+    bad = N.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(bbp.BBPError):
+        bbp.ite_fit(bad, theta, gate, 2)

@@ -112,3 +112,63 @@ def test_planted_gate_order_mistake():
         p2 = brute.state_vector(A2, 3, 2)
         ov = abs(np.vdot(p2, ref)) / (np.linalg.norm(p2) * np.linalg.norm(ref))
         assert (1.0 - ov < 1e-12) == want
+
+
+def test_edge_padding_stays_zero_and_state_moves_with_blocks():
+    """4x4 lattice in 2x2 blocks (block-BP messages as the environments):
+    the new tensors keep zero entries on every open-edge leg index above 0
+    (the isometries span the true leg extents only), and the step lowers
+    the transverse-field Ising energy as the exact (one-block) update does."""
+    h = _ti_hamiltonian(3.0)
+    G = expm(-0.1 * h)
+    A = peps_finite(4, 3, 2, seed=6)
+    A2, _ = ite.ite_step(A, 4, 3, 2, 8, 2, 2, G, n_als=3, chi_env=16, sweeps=6, tol=0.0)
+    for y in range(3):
+        for x in range(4):
+            t = A2[y * 4 + x]
+            for leg, edge in ((1, y == 0), (2, x == 0), (3, y == 2), (4, x == 3)):
+                if edge:
+                    assert np.all(np.take(t, [1], axis=leg) == 0.0)
+    assert _energy(A2, 4, 3, h) < _energy(A, 4, 3, h)
+
+
+def _exact_trotter(psi, Lx, Ly, G, steps):
+    """The state vector after `steps` Trotter steps: G applied to every bond
+    in the update's order (first site of a bond the major index of G)."""
+    n = Lx * Ly
+    for _ in range(steps):
+        for a, b in ite.bond_order(Lx, Ly):
+            i, j = a[1] * Lx + a[0], b[1] * Lx + b[0]
+            t = np.moveaxis(psi.reshape([2] * n), [i, j], [0, 1]).reshape(4, -1)
+            t = (G @ t).reshape([2, 2] + [2] * (n - 2))
+            psi = np.moveaxis(t, [0, 1], [i, j]).reshape(-1)
+    return psi
+
+
+@pytest.mark.parametrize("lat", [(3, 1, 2), (1, 3, 2)])
+def test_chain_evolution_is_exact(lat):
+    """Open chains of 3 sites at D = 2, horizontal and vertical (every
+    cut's Schmidt rank fits the bond): the update reproduces exact Trotterised
+    evolution of the state vector, for a generic real two-site gate (no
+    symmetry under transposition or under exchange of its sites), one
+    block, three steps; the gate transposed or with its sites exchanged
+    does not."""
+    Lx, Ly, D = lat
+    rng = np.random.default_rng(8)
+    G = np.eye(4) + 0.3 * rng.standard_normal((4, 4))
+    A = peps_finite(Lx, Ly, D, seed=3)
+    ref = _exact_trotter(brute.state_vector(A, Lx, Ly), Lx, Ly, G, 3)
+    for _ in range(3):
+        A, _ = ite.ite_step(A, Lx, Ly, D, 16, Lx, Ly, G, n_als=2, chi_env=16, sweeps=1)
+    psi = brute.state_vector(A, Lx, Ly)
+    ov = abs(np.vdot(psi, ref)) / (np.linalg.norm(psi) * np.linalg.norm(ref))
+    assert 1.0 - ov < 1e-12
+    # planted: the gate transposed, or its two sites exchanged
+    swap = G.reshape(2, 2, 2, 2).transpose(1, 0, 3, 2).reshape(4, 4)
+    for bad in (G.T, swap):
+        B = peps_finite(Lx, Ly, D, seed=3)
+        for _ in range(3):
+            B, _ = ite.ite_step(B, Lx, Ly, D, 16, Lx, Ly, bad, n_als=2, chi_env=16, sweeps=1)
+        pb = brute.state_vector(B, Lx, Ly)
+        ovb = abs(np.vdot(pb, ref)) / (np.linalg.norm(pb) * np.linalg.norm(ref))
+        assert 1.0 - ovb > 1e-6
