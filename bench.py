@@ -15,6 +15,7 @@ timed on the host are added to the same JSON line.
     python bench.py --workload obc4x4_D2_b2_chi4 | inf2x2_D4_b4_chi32 | obc16x16_D6_b4_chi64
     python bench.py --calibrate-copy   (plain 1 GiB device copy, for counters)
     python bench.py --serve [--requests 256] [--slots 8] [--rates 0.5 1 2 4]
+    python bench.py --ite ite_ti_obc10x10_D2_b5 | ite_afh_obc14x14_D3_b7  (blockBP update)
 
 The roofline's `traffic` (HBM bytes per launch of the dominant kernel) comes
 from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/ and is
@@ -478,6 +479,168 @@ def cpu_baseline(cfg, A):
     return out
 
 
+ITE_WORKLOADS = {
+    # transverse-field Ising (B = 3) on a 10x10 open lattice in 5x5 blocks, D = 2
+    "ite_ti_obc10x10_D2_b5": dict(model="ti", B=3.0, Lx=10, Ly=10, bx=5, by=5, D=2, chi=4,
+                                  chi_env=18, dtau=0.05),
+    # antiferromagnetic Heisenberg on a 14x14 open lattice in 7x7 blocks, D = 3
+    "ite_afh_obc14x14_D3_b7": dict(model="afh", Lx=14, Ly=14, bx=7, by=7, D=3, chi=9,
+                                   chi_env=28, dtau=0.05),
+}
+ITE_TOL, ITE_MAX_SWEEPS = 1e-6, 10
+
+
+def ite_hamiltonian(w):
+    """Bond Hamiltonian h (d^2 x d^2) of an ITE workload: transverse-field
+    Ising -sz sz - B/4 (sx 1 + 1 sx) with Pauli-type op_sz/op_sx, or the
+    Heisenberg S.S."""
+    if w["model"] == "afh":
+        return op_heis()
+    sz, sx = op_sz(), op_sx()
+    return -np.kron(sz, sz) - w["B"] / 4 * (np.kron(sx, np.eye(2)) + np.kron(np.eye(2), sx))
+
+
+def ite_bench(args):
+    """ITE steps of the blockBP update (App. B): each step sweeps block BP
+    from the previous step's messages until the residual is below 1e-6 (at
+    most 10 sweeps), then applies the Trotter gates exp(-h dtau) to every
+    bond (bbp_ite_step, 4 ALS passes).  Reports ITE steps/s over K timed
+    steps after W warm-up steps, the phase split, the energy per bond after
+    the run, the fit-visit roofline of a second, event-timed step, and the
+    oracle's per-step time on a bounded sample of the same step."""
+    from scipy.linalg import expm
+    from paper_2301_05844_amd import bbp
+    w = ITE_WORKLOADS[args.ite]
+    h = ite_hamiltonian(w)
+    G = expm(-w["dtau"] * h)
+    A0 = peps_finite(w["Lx"], w["Ly"], w["D"], seed=args.seed)
+    ctx = bbp.BlockBP(Lx=w["Lx"], Ly=w["Ly"], bx=w["bx"], by=w["by"], D=w["D"],
+                      chi=w["chi"], chi_env=w["chi_env"])
+    ctx.set_tensors(A0)
+    _, bonds = lattice_terms(dict(infinite=False, Lx=w["Lx"], Ly=w["Ly"]))
+
+    def step(times=None, sweeps_log=None):
+        t0 = time.perf_counter()
+        n, res = 0, 1.0
+        while n < ITE_MAX_SWEEPS and res >= ITE_TOL:
+            res = ctx.sweep(1)
+            n += 1
+        sync()
+        t1 = time.perf_counter()
+        gates, loss = ctx.ite_step(G, n_als=4)
+        sync()
+        t2 = time.perf_counter()
+        if times is not None:
+            times.append((t1 - t0, t2 - t1, n, res, gates, loss, ctx.ite_info))
+        return gates
+
+    e0 = float(np.mean(ctx.expect_bonds(bonds, h)))
+    log(f"ITE {args.ite}: energy per bond {e0:.8f} at the start")
+    for k in range(args.warmup):
+        step()
+        log(f"warm-up ITE step {k} done")
+    times = []
+    sync()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(times)
+        t = times[-1]
+        log(f"ITE step {k}: {t[2]} sweeps ({t[0] * 1e3:.1f} ms, residual {t[3]:.1e}), "
+            f"{t[4]} gates ({t[1] * 1e3:.1f} ms)")
+    sync()
+    total = time.perf_counter() - t0
+    ctx.sweep(ITE_MAX_SWEEPS)
+    e1 = float(np.mean(ctx.expect_bonds(bonds, h)))
+    log(f"energy per bond {e1:.8f} after {args.warmup + args.steps} steps")
+    # one more step with every launch bracketed by HIP events (process-wide)
+    stats = None
+    if not args.no_kernel_pass:
+        ctx.set_option("timing", 1)
+        step()
+        stats = ctx.kernel_stats()
+        ctx.set_option("timing", 0)
+    gates = times[0][4]
+    line = dict(
+        metric="ITE steps/s (blockBP update: BP sweeps to 1e-6 plus one Trotter step of "
+               "gates on every bond)",
+        value=args.steps / total,
+        unit="ITE steps/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=total / args.steps * 1e3,
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=args.ite, model=w["model"], lattice=f"{w['Lx']}x{w['Ly']} open",
+                    block=f"{w['bx']}x{w['by']}", D=w["D"], chi=w["chi"],
+                    chi_env=w["chi_env"], dtau=w["dtau"], n_als=4, gates_per_step=gates,
+                    sweep_tol=ITE_TOL, max_sweeps=ITE_MAX_SWEEPS),
+        gates_per_s=gates * args.steps / total,
+        phase_ms=dict(sweeps=float(np.mean([t[0] for t in times]) * 1e3),
+                      update=float(np.mean([t[1] for t in times]) * 1e3),
+                      update_environments=float(np.mean([t[6]["env_s"] for t in times]) * 1e3),
+                      update_host_fits=float(np.mean([t[6]["host_s"] for t in times]) * 1e3)),
+        gate_levels=times[0][6]["levels"],
+        sweeps_per_step=[t[2] for t in times],
+        fit_error_per_step=[t[5] for t in times],
+        energy_per_bond=dict(start=e0, end=e1),
+        roofline=None if stats is None else dict(
+            roofline(stats, None), measured_in="one further ITE step with every launch "
+            "bracketed by HIP events (sweeps and the environment contractions)"),
+        kernels=None if stats is None else {
+            s["name"]: dict(launches=s["launches"], ms=s["ms"],
+                            tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
+            for s in stats},
+        cpu_baseline=None if args.no_cpu_baseline else ite_cpu_baseline(w, A0, G, gates),
+    )
+    print(json.dumps(line), flush=True)
+
+
+def ite_cpu_baseline(w, A, G, gates):
+    """The oracle's blockBP update on the host, on a bounded sample: block BP
+    converged to 1e-6 (at most 10 sweeps) from the start, then gates of the
+    first Trotter step in order until about 20 s have passed; the per-step
+    time is sweeps + gates x the mean gate time."""
+    from oracle import blockbp as ob
+    from oracle import ite
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    Lx, Ly, D = w["Lx"], w["Ly"], w["D"]
+    bp = ob.BlockBP(A, D=D, chi=w["chi"], bx=w["bx"], by=w["by"], Lx=Lx, Ly=Ly,
+                    chi_env=w["chi_env"])
+    t0 = time.perf_counter()
+    n = 0
+    while n < ITE_MAX_SWEEPS:
+        n += 1
+        if bp.sweep() < ITE_TOL:
+            break
+        log(f"  oracle sweep {n}: {time.perf_counter() - t0:.1f} s")
+    t_sweeps = time.perf_counter() - t0
+    A = np.array(A, dtype=np.float64)
+    t0 = time.perf_counter()
+    done = 0
+    for (a, b) in ite.bond_order(Lx, Ly):
+        horizontal = a[1] == b[1]
+        ia, ib = a[1] * Lx + a[0], b[1] * Lx + b[0]
+        da, db = ite.leg_dims(a[0], a[1], Lx, Ly, D), ite.leg_dims(b[0], b[1], Lx, Ly, D)
+        Xa, Ra, Lb, Yb, oa, ob_, sa, sb = ite.split_pair(A[ia], A[ib], horizontal, da, db)
+        k, kb = Xa.shape[1], Yb.shape[0]
+        N = ite.bond_environment(bp, A, a, b, Xa, Yb, oa, ob_, sa, sb, k, kb, da, db)
+        R, L = ite.fit_pair(N, np.einsum("asr,rtb->astb", Ra, Lb), G, D, 4)
+        A[ia], A[ib] = ite.rebuild(Xa, R, L, Yb, oa, ob_, sa, sb, A.shape[1], D, da, db)
+        done += 1
+        if time.perf_counter() - t0 >= 20.0:
+            break
+    t_gate = (time.perf_counter() - t0) / done
+    per_step = t_sweeps + gates * t_gate
+    log(f"  oracle: {n} sweeps {t_sweeps:.1f} s, {done} gates at {t_gate:.2f} s each")
+    return dict(value=1.0 / per_step, unit="ITE steps/s", cores=threads, kind="oracle",
+                sample=f"{n} block-BP sweeps ({t_sweeps:.1f} s) and the first {done} of "
+                       f"{gates} gates of a step ({t_gate:.2f} s per gate); per step = "
+                       "sweeps + gates x mean gate time", **host_cpu())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -498,6 +661,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", choices=WORKLOADS, default=WORKLOAD,
                     help="workload of the solve (default: the 16x16 open lattice)")
+    ap.add_argument("--ite", choices=sorted(ITE_WORKLOADS), default=None,
+                    help="ITE steps of the blockBP update on this workload instead of the "
+                         "default solve")
     ap.add_argument("--lanes", type=int, default=None,
                     help="streams the message and boundary-stack batches spread over "
                          "(library default when absent)")
@@ -512,6 +678,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve(args)
+        return
+    if args.ite:
+        ite_bench(args)
         return
 
     from paper_2301_05844_amd import bbp

@@ -318,15 +318,21 @@ void bbp_destroy(bbp_ctx *c);
  * ones at once, so that later gates of the step see them.  The messages
  * stay fixed through the step (the caller sweeps between steps); on
  * return the context holds the new tensors with the messages it had
- * (their fit warm starts cleared).
+ * (their fit warm starts cleared).  A gate's result depends only on the
+ * tensors of its region (its block, or the two blocks its bond joins), so
+ * gates whose regions share no block run together: their environments in
+ * one batched contraction, their fits on host threads; the result is that
+ * of the sequential order.
  *
  * n_als: alternating least-squares passes per gate (1..64).  info (host,
- * optional, 2 doubles): the number of gates applied and the sum over the
- * gates of the relative fit error in the metric of N.
+ * optional, 5 doubles): the number of gates applied, the sum over the
+ * gates of the relative fit error in the metric of N, the seconds spent in
+ * the environment contractions (GPU, with their setup), the seconds in the
+ * host splits and fits, and the number of levels of gates run together.
  * Errors: BBP_ESTATE (no tensors), BBP_EINVAL (infinite or single-layer
  * context, min(D^3, d D) > 8, n_als out of range, null or non-finite gate),
  * BBP_ENUMERIC (singular fit or a vanishing region contraction); the
- * context's tensors are then those before the failing gate's bond.
+ * context then keeps the tensors and messages it had before the step.
  * ------------------------------------------------------------------------ */
 bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als, double *info);
 

@@ -281,12 +281,15 @@ class BlockBP:
     def ite_step(self, gate, n_als=4):
         """bbp_ite_step: one Trotter step of the blockBP update with the
         gate (d^2 x d^2) on every bond, the current messages fixed.  Returns
-        (gates applied, summed relative fit error)."""
+        (gates applied, summed relative fit error); ``self.ite_info`` holds
+        the environment and host seconds and the number of gate levels."""
         g = np.ascontiguousarray(gate, dtype=np.float64).reshape(-1)
         if g.size != self.d ** 4:
             raise ValueError(f"gate needs {self.d ** 4} entries")
-        info = np.zeros(2)
+        info = np.zeros(5)
         self._check(_lib.bbp_ite_step(self._ctx, _dptr(g), int(n_als), _dptr(info)))
+        self.ite_info = dict(env_s=float(info[2]), host_s=float(info[3]),
+                             levels=int(info[4]))
         return int(info[0]), float(info[1])
 
     def log_norm(self):

@@ -1066,11 +1066,27 @@ struct Seg {
   int n;   // sites
 };
 
+// A bond whose two-site values are wanted: frame, line and the position of
+// its first site along the line (region coordinates).
+struct Target {
+  bool row;
+  int line, pos;
+};
+
 struct RegionSpec {
   int kind, bi, bj;  // 0 block, 1 block + right neighbour, 2 block + lower
   int H, W;
   std::vector<Seg> side[4];  // incoming on 'U','D','L','R', natural order
   bool row, col;             // frames needed
+  // empty: every line of the frames and every site and bond on it;
+  // otherwise only the lines and bonds listed
+  std::vector<Target> targets;
+  bool wants_line(bool r, int k) const {
+    if (targets.empty()) return true;
+    for (const Target &t : targets)
+      if (t.row == r && t.line == k) return true;
+    return false;
+  }
 };
 
 int side_slot(char s) { return s == 'U' ? 0 : s == 'D' ? 1 : s == 'L' ? 2 : 3; }
@@ -1324,6 +1340,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     const RegionSpec &R = regs[r];
     if (R.row)
       for (int k = 0; k < R.H; ++k) {
+        if (!R.wants_line(true, k)) continue;
         LineItem L{(int)r, true, k, stack_of[r][dir_index('D')],
                    stack_of[r][dir_index('U')], R.H - 1 - k, k, 0.0};
         L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
@@ -1331,6 +1348,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       }
     if (R.col)
       for (int k = 0; k < R.W; ++k) {
+        if (!R.wants_line(false, k)) continue;
         LineItem L{(int)r, false, k, stack_of[r][dir_index('L')],
                    stack_of[r][dir_index('R')], k, R.W - 1 - k, 0.0};
         L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
@@ -1445,7 +1463,13 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       const LineItem &L = lines[lids[li]];
       const RegionSpec &R = regs[L.region];
       std::vector<int> lr, rl;
-      if (L.row) {
+      if (!R.targets.empty()) {  // the listed bonds (j, j+1), j = pos + 1
+        for (const Target &t : R.targets)
+          if (t.row == L.row && t.line == L.k) {
+            lr.push_back(t.pos + 1);
+            rl.push_back(t.pos + 2);
+          }
+      } else if (L.row) {
         if (R.kind == 0) {
           for (int j = 1; j <= Hc; ++j) lr.push_back(j);
           for (int j = 2; j <= Hc; ++j) rl.push_back(j);
@@ -1858,6 +1882,72 @@ static bbp_status rdm_many(bbp_ctx *c, int n, const int32_t *x0, const int32_t *
     if (!std::isfinite(den) || den == 0.0)
       return c->fail(BBP_ENUMERIC, "vanishing or non-finite region contraction");
     for (int k = 0; k < m * m; ++k) rho[k] /= den;
+  }
+  return BBP_OK;
+}
+
+// Two-site reduced density matrices of n bonds computed on their own: the
+// region of each bond contracted in the bond's frame only (two boundary
+// stacks), its line only, and the matrix-unit steps of its two sites only.
+// The partial region results are dropped afterwards, so that later queries
+// recompute whole regions.
+static bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
+                                 const int32_t *x1, const int32_t *y1, double *out) {
+  if (!c) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (n < 0 || (n > 0 && (!x0 || !y0 || !x1 || !y1 || !out)))
+    return c->fail(BBP_EINVAL, "null argument");
+  if (c->chi_env < c->chi) return c->fail(BBP_EINVAL, "chi_env must be at least chi");
+  std::vector<Query> qs(n);
+  std::map<std::tuple<int, int, int>, RegionSpec> want;
+  for (int i = 0; i < n; ++i) {
+    bbp_status s = make_query(c, x0[i], y0[i], x1[i], y1[i], true, qs[i]);
+    if (s != BBP_OK) return s;
+    const Query &q = qs[i];
+    auto key = std::make_tuple(q.kind, q.bi, q.bj);
+    auto it = want.find(key);
+    if (it == want.end()) {
+      RegionSpec r = region_spec(c, q.kind, q.bi, q.bj);
+      r.row = r.col = false;
+      it = want.emplace(key, r).first;
+    }
+    (q.row ? it->second.row : it->second.col) = true;
+    it->second.targets.push_back(Target{q.row, q.line, q.pos});
+  }
+  std::vector<RegionSpec> regs;
+  for (auto &kv : want) {
+    c->obs.erase(kv.first);
+    regs.push_back(kv.second);
+  }
+  struct Drop {  // partial results never serve a later query
+    bbp_ctx *c;
+    const std::map<std::tuple<int, int, int>, RegionSpec> &w;
+    ~Drop() {
+      for (auto &kv : w) c->obs.erase(kv.first);
+    }
+  } drop{c, want};
+  if (!regs.empty()) {
+    bbp_status s = compute_regions(c, regs);
+    if (s != BBP_OK) return s;
+  }
+  const int d = c->d, d2 = d * d;
+  for (int i = 0; i < n; ++i) {
+    const Query &q = qs[i];
+    const RegionResult &res = c->obs.at(std::make_tuple(q.kind, q.bi, q.bj));
+    const double *u = q.row ? &res.hbond[((size_t)q.line * (res.W - 1) + q.pos) * d2 * d2]
+                            : &res.vbond[((size_t)q.line * (res.H - 1) + q.pos) * d2 * d2];
+    double *rho = out + (size_t)i * d2 * d2;
+    double den = 0.0;
+    for (int s0 = 0; s0 < d; ++s0)
+      for (int s1 = 0; s1 < d; ++s1) den += u[(s0 * d + s0) * d2 + s1 * d + s1];
+    for (int s0 = 0; s0 < d; ++s0)
+      for (int s1 = 0; s1 < d; ++s1)
+        for (int s0p = 0; s0p < d; ++s0p)
+          for (int s1p = 0; s1p < d; ++s1p)
+            rho[(s0 * d + s1) * d2 + s0p * d + s1p] = u[(s0p * d + s0) * d2 + s1p * d + s1];
+    if (!std::isfinite(den) || den == 0.0)
+      return c->fail(BBP_ENUMERIC, "vanishing or non-finite region contraction");
+    for (int k = 0; k < d2 * d2; ++k) rho[k] /= den;
   }
   return BBP_OK;
 }
@@ -3108,6 +3198,11 @@ bbp_status ctx_info(bbp_ctx *c, CtxInfo *o) {
 }
 
 bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m) { return c->fail(s, m); }
+
+bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
+                          const int32_t *x1, const int32_t *y1, double *rho) {
+  return ::rdm_bonds_only(c, n, x0, y0, x1, y1, rho);
+}
 
 const double *ctx_tensors(bbp_ctx *c, size_t *n) {
   *n = c->A.size();

@@ -244,5 +244,10 @@ struct CtxInfo {
 bbp_status ctx_info(bbp_ctx *c, CtxInfo *out);
 bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m);
 const double *ctx_tensors(bbp_ctx *c, size_t *n);
+// bbp_rdm_bonds restricted to what the n bonds need: each region in its
+// bond's frame only, the bond's line and its two sites' unit steps; nothing
+// is kept for later queries.  Same values as bbp_rdm_bonds.
+bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
+                          const int32_t *x1, const int32_t *y1, double *rho);
 
 }  // namespace bbp

@@ -15,11 +15,19 @@
 // lattice, the block partition and the messages; the reduced tensors are
 // then fitted by alternating least squares on the host (their systems have
 // at most k d D unknowns), and the new tensors replace the old ones.
+//
+// With the messages fixed, gates in different blocks are independent (the
+// blocks run in parallel, Sec. II): the gates are grouped into levels of
+// gates whose regions share no block, and each level's environments are
+// contracted in one batched call and its fits run on host threads.
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/bbp.h"
@@ -326,6 +334,175 @@ bool fit_pair(int d, int D, int k, int kb, const double *Nm, const double *Th,
   return true;
 }
 
+// One gate of a Trotter step and its work: the bond (x0, y0, x1, y1), the
+// first site the left or upper one; the reduced tensors of its two sites.
+struct Gate {
+  std::array<int, 4> b;
+  int level = 0;
+  int ia = 0, ib = 0, sa = 0, sb = 0, oa[3] = {}, ob[3] = {};
+  int da[5] = {}, db[5] = {};  // true leg extents (s, u, l, d, r)
+  int rows_a = 0, cols_b = 0, k = 0, kb = 0;
+  Mat Xa, Ra, Qt, Rt;  // Ma = Xa Ra; Mb^T = Qt Rt
+};
+
+// f(0..n-1) on up to `threads` host threads.
+template <class F>
+void parallel_for(int n, int threads, F f) {
+  threads = std::min(threads, n);
+  if (threads <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&] {
+      for (int i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto &th : pool) th.join();
+}
+
+// Row of a site entry among the rows formed by three legs o (true extents n).
+inline size_t row_of(const int leg[5], const int o[3], const int n[5]) {
+  return ((size_t)leg[o[0]] * n[o[1]] + leg[o[1]]) * n[o[2]] + leg[o[2]];
+}
+
+// True extents of the legs of site (x, y): 1 on the lattice edge, so that
+// the isometries span physical directions only.
+void leg_dims(int x, int y, int d, int D, int Lx, int Ly, int n[5]) {
+  n[0] = d;
+  n[1] = y == 0 ? 1 : D;
+  n[2] = x == 0 ? 1 : D;
+  n[3] = y == Ly - 1 ? 1 : D;
+  n[4] = x == Lx - 1 ? 1 : D;
+}
+
+// QR of the first site over its outer legs, LQ of the second (App. B's
+// reduced tensors): Ma[(outer), (s, shared)] = Xa Ra and
+// Mb[(shared, s), (outer)] = Rt^T Qt^T.
+void split_gate(Gate &g, const double *A, int d, int D, int Lx, int Ly) {
+  const size_t ss = (size_t)d * D * D * D * D;
+  const bool horiz = g.b[1] == g.b[3];
+  g.ia = g.b[1] * Lx + g.b[0];
+  g.ib = g.b[3] * Lx + g.b[2];
+  g.sa = horiz ? 4 : 3;  // shared leg of each site (0 = s)
+  g.sb = horiz ? 2 : 1;
+  for (int t = 1, u = 0, w = 0; t <= 4; ++t) {
+    if (t != g.sa) g.oa[u++] = t;
+    if (t != g.sb) g.ob[w++] = t;
+  }
+  leg_dims(g.b[0], g.b[1], d, D, Lx, Ly, g.da);
+  leg_dims(g.b[2], g.b[3], d, D, Lx, Ly, g.db);
+  g.rows_a = g.da[g.oa[0]] * g.da[g.oa[1]] * g.da[g.oa[2]];
+  g.cols_b = g.db[g.ob[0]] * g.db[g.ob[1]] * g.db[g.ob[2]];
+  const double *Aa = A + g.ia * ss, *Ab = A + g.ib * ss;
+  Mat Ma((size_t)g.rows_a * d * D, 0.0), MbT((size_t)g.cols_b * D * d, 0.0);
+  int leg[5];
+  for (leg[0] = 0; leg[0] < d; ++leg[0])
+    for (leg[1] = 0; leg[1] < D; ++leg[1])
+      for (leg[2] = 0; leg[2] < D; ++leg[2])
+        for (leg[3] = 0; leg[3] < D; ++leg[3])
+          for (leg[4] = 0; leg[4] < D; ++leg[4]) {
+            const size_t src = aidx5(D, 0, leg);
+            if (leg[1] < g.da[1] && leg[2] < g.da[2] && leg[3] < g.da[3] && leg[4] < g.da[4])
+              Ma[row_of(leg, g.oa, g.da) * d * D + (size_t)leg[0] * D + leg[g.sa]] = Aa[src];
+            if (leg[1] < g.db[1] && leg[2] < g.db[2] && leg[3] < g.db[3] && leg[4] < g.db[4])
+              MbT[row_of(leg, g.ob, g.db) * D * d + (size_t)leg[g.sb] * d + leg[0]] = Ab[src];
+          }
+  qr_thin(Ma, g.rows_a, d * D, g.Xa, g.Ra);
+  qr_thin(MbT, g.cols_b, D * d, g.Qt, g.Rt);
+  g.k = std::min(g.rows_a, d * D);
+  g.kb = std::min(g.cols_b, D * d);
+}
+
+// The gate's two sites in the environment network (site stride sp): the
+// isometry columns as the physical index, the shared leg at index 0.
+void place_isometries(const Gate &g, double *M, size_t sp, int D) {
+  const size_t D4 = (size_t)D * D * D * D;
+  std::fill(M + g.ia * sp, M + (g.ia + 1) * sp, 0.0);
+  std::fill(M + g.ib * sp, M + (g.ib + 1) * sp, 0.0);
+  for (int q = 0; q < g.k; ++q)
+    for (int r = 0; r < g.rows_a; ++r) {
+      int lg[5] = {0, 0, 0, 0, 0};
+      lg[g.oa[0]] = r / (g.da[g.oa[1]] * g.da[g.oa[2]]);
+      lg[g.oa[1]] = r / g.da[g.oa[2]] % g.da[g.oa[1]];
+      lg[g.oa[2]] = r % g.da[g.oa[2]];
+      M[g.ia * sp + (size_t)q * D4 + aidx5(D, 0, lg)] = g.Xa[(size_t)r * g.k + q];
+    }
+  for (int q = 0; q < g.kb; ++q)
+    for (int cc = 0; cc < g.cols_b; ++cc) {
+      int lg[5] = {0, 0, 0, 0, 0};
+      lg[g.ob[0]] = cc / (g.db[g.ob[1]] * g.db[g.ob[2]]);
+      lg[g.ob[1]] = cc / g.db[g.ob[2]] % g.db[g.ob[1]];
+      lg[g.ob[2]] = cc % g.db[g.ob[2]];
+      M[g.ib * sp + (size_t)q * D4 + aidx5(D, 0, lg)] = g.Qt[(size_t)cc * g.kb + q];
+    }
+}
+
+// Fit of one gate from its environment rho (the two-site RDM of the
+// isometry network, dp^4 doubles), then the new tensors A_a = Xa R and
+// A_b = L Qt^T written into A, each scaled to a largest entry of 1.
+bool fit_gate(const Gate &g, const double *rho, int dp, const double *gate, int n_als, int d,
+              int D, double *A, double *loss) {
+  const int k = g.k, kb = g.kb;
+  const size_t ss = (size_t)d * D * D * D * D;
+  std::vector<double> Nm((size_t)k * kb * k * kb);
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < kb; ++b)
+      for (int a2 = 0; a2 < k; ++a2)
+        for (int b2 = 0; b2 < kb; ++b2)
+          Nm[((size_t)(a * kb + b) * k + a2) * kb + b2] =
+              rho[((size_t)a * dp + b) * dp * dp + (size_t)a2 * dp + b2];
+  // Theta[ka][s][t][kb] = sum_r Ra[ka][(s, r)] Lb[(r, t)][kb], Lb = Rt^T
+  std::vector<double> Th((size_t)k * d * d * kb, 0.0);
+  for (int a = 0; a < k; ++a)
+    for (int s = 0; s < d; ++s)
+      for (int t = 0; t < d; ++t)
+        for (int b = 0; b < kb; ++b) {
+          double v = 0.0;
+          for (int r = 0; r < D; ++r)
+            v += g.Ra[(size_t)a * d * D + s * D + r] * g.Rt[(size_t)b * D * d + r * d + t];
+          Th[((a * d + s) * d + t) * kb + b] = v;
+        }
+  std::vector<double> R((size_t)k * d * D), L((size_t)D * d * kb);
+  if (!fit_pair(d, D, k, kb, Nm.data(), Th.data(), gate, n_als, R.data(), L.data(), loss))
+    return false;
+  std::vector<double> na(ss, 0.0), nb(ss, 0.0);
+  int leg[5];
+  for (leg[0] = 0; leg[0] < d; ++leg[0])
+    for (leg[1] = 0; leg[1] < D; ++leg[1])
+      for (leg[2] = 0; leg[2] < D; ++leg[2])
+        for (leg[3] = 0; leg[3] < D; ++leg[3])
+          for (leg[4] = 0; leg[4] < D; ++leg[4]) {
+            const size_t dst = aidx5(D, 0, leg);
+            if (leg[1] < g.da[1] && leg[2] < g.da[2] && leg[3] < g.da[3] && leg[4] < g.da[4]) {
+              const size_t ra = row_of(leg, g.oa, g.da);
+              double v = 0.0;
+              for (int q = 0; q < k; ++q)
+                v += g.Xa[ra * k + q] * R[((size_t)q * d + leg[0]) * D + leg[g.sa]];
+              na[dst] = v;
+            }
+            if (leg[1] < g.db[1] && leg[2] < g.db[2] && leg[3] < g.db[3] && leg[4] < g.db[4]) {
+              const size_t cb = row_of(leg, g.ob, g.db);
+              double w = 0.0;
+              for (int q = 0; q < kb; ++q)
+                w += L[((size_t)leg[g.sb] * d + leg[0]) * kb + q] * g.Qt[cb * kb + q];
+              nb[dst] = w;
+            }
+          }
+  double ma = 0.0, mb = 0.0;
+  for (size_t i = 0; i < ss; ++i) {
+    ma = std::max(ma, std::fabs(na[i]));
+    mb = std::max(mb, std::fabs(nb[i]));
+  }
+  if (!(ma > 0.0) || !(mb > 0.0) || !std::isfinite(ma) || !std::isfinite(mb)) return false;
+  for (size_t i = 0; i < ss; ++i) {
+    A[g.ia * ss + i] = na[i] / ma;
+    A[g.ib * ss + i] = nb[i] / mb;
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als,
@@ -367,159 +544,91 @@ extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als
   } free_e{e};
   const std::pair<const char *, double> opts[] = {
       {"d", (double)dp}, {"chi_env", (double)ci.chi_env}, {"n_fit", (double)ci.n_fit},
-      {"seed", (double)ci.seed}, {"shift_x", (double)ci.sx}, {"shift_y", (double)ci.sy},
-      {"lanes", 1.0}};
+      {"seed", (double)ci.seed}, {"shift_x", (double)ci.sx}, {"shift_y", (double)ci.sy}};
   for (auto &o : opts)
     if ((st = bbp_set_option(e, o.first, o.second)) != BBP_OK)
       return bbp::ctx_fail(c, st, std::string("environment option ") + o.first + ": " +
                                       bbp_last_error(e));
   (void)bbp_set_stream(e, ci.stream);
-  double loss_sum = 0.0;
-  int gates = 0;
   // gate order: horizontal bonds row by row, then vertical bonds column by column
-  std::vector<std::array<int, 4>> bonds;
+  std::vector<Gate> gl;
   for (int y = 0; y < Ly; ++y)
-    for (int x = 0; x + 1 < Lx; ++x) bonds.push_back({x, y, x + 1, y});
+    for (int x = 0; x + 1 < Lx; ++x) gl.push_back(Gate{{x, y, x + 1, y}});
   for (int x = 0; x < Lx; ++x)
-    for (int y = 0; y + 1 < Ly; ++y) bonds.push_back({x, y, x, y + 1});
+    for (int y = 0; y + 1 < Ly; ++y) gl.push_back(Gate{{x, y, x, y + 1}});
+  // Schedule.  With the messages fixed, a gate's result depends on the
+  // tensors of its region only: the block of its bond, or the two blocks a
+  // bond between blocks joins.  Two gates whose regions share no block
+  // therefore commute, and the gates are grouped into levels: a gate's level
+  // is one more than the last level that touched any block of its region.
+  // Running the levels in order, each level's gates together, gives the
+  // result of the sequential order gate for gate.
+  const int gx = (Lx + ci.sx + ci.bx - 1) / ci.bx, gy = (Ly + ci.sy + ci.by - 1) / ci.by;
+  std::vector<int> last((size_t)gx * gy, -1);
+  int n_levels = 0;
+  for (Gate &g : gl) {
+    const int b0 = ((g.b[1] + ci.sy) / ci.by) * gx + (g.b[0] + ci.sx) / ci.bx;
+    const int b1 = ((g.b[3] + ci.sy) / ci.by) * gx + (g.b[2] + ci.sx) / ci.bx;
+    g.level = std::max(last[b0], last[b1]) + 1;
+    last[b0] = last[b1] = g.level;
+    n_levels = std::max(n_levels, g.level + 1);
+  }
+  std::vector<std::vector<int>> levels(n_levels);
+  for (size_t q = 0; q < gl.size(); ++q) levels[gl[q].level].push_back((int)q);
   std::vector<double> M((size_t)Lx * Ly * dp * D * D * D * D);
-  // true dimensions of the legs (index 1..4 = u, l, d, r) of a site: 1 on
-  // the lattice edge, so that the isometries span physical directions only
-  auto leg_dims = [&](int x, int y, int n[5]) {
-    n[0] = d;
-    n[1] = y == 0 ? 1 : D;
-    n[2] = x == 0 ? 1 : D;
-    n[3] = y == Ly - 1 ? 1 : D;
-    n[4] = x == Lx - 1 ? 1 : D;
+  const size_t sp = (size_t)dp * D * D * D * D;
+  const int nthreads =
+      (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  double loss_sum = 0.0, t_env = 0.0, t_host = 0.0;
+  int gates = 0;
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double>(b - a).count();
   };
-  for (const auto &bd : bonds) {
-    const bool horiz = bd[1] == bd[3];
-    const int ia = bd[1] * Lx + bd[0], ib = bd[3] * Lx + bd[2];
-    const int sa = horiz ? 4 : 3, sb = horiz ? 2 : 1;  // shared leg (0 = s)
-    int oa[3], ob[3];
-    for (int t = 1, u = 0, w = 0; t <= 4; ++t) {
-      if (t != sa) oa[u++] = t;
-      if (t != sb) ob[w++] = t;
-    }
-    int da[5], db[5];
-    leg_dims(bd[0], bd[1], da);
-    leg_dims(bd[2], bd[3], db);
-    const int rows_a = da[oa[0]] * da[oa[1]] * da[oa[2]];
-    const int cols_b = db[ob[0]] * db[ob[1]] * db[ob[2]];
-    auto row_of = [](const int leg[5], const int o[3], const int n[5]) {
-      return ((size_t)leg[o[0]] * n[o[1]] + leg[o[1]]) * n[o[2]] + leg[o[2]];
-    };
-    const double *Aa = A.data() + ia * ss, *Ab = A.data() + ib * ss;
-    // Ma[(oa legs), (s, shared)] and Mb^T[(ob legs), (shared, s)], true extents
-    Mat Ma((size_t)rows_a * d * D, 0.0), MbT((size_t)cols_b * D * d, 0.0);
-    int leg[5];
-    for (leg[0] = 0; leg[0] < d; ++leg[0])
-      for (leg[1] = 0; leg[1] < D; ++leg[1])
-        for (leg[2] = 0; leg[2] < D; ++leg[2])
-          for (leg[3] = 0; leg[3] < D; ++leg[3])
-            for (leg[4] = 0; leg[4] < D; ++leg[4]) {
-              const size_t src = aidx5(D, 0, leg);
-              if (leg[1] < da[1] && leg[2] < da[2] && leg[3] < da[3] && leg[4] < da[4])
-                Ma[row_of(leg, oa, da) * d * D + (size_t)leg[0] * D + leg[sa]] = Aa[src];
-              if (leg[1] < db[1] && leg[2] < db[2] && leg[3] < db[3] && leg[4] < db[4])
-                MbT[row_of(leg, ob, db) * D * d + (size_t)leg[sb] * d + leg[0]] = Ab[src];
-            }
-    Mat Xa, Ra, Qt, Rt;
-    qr_thin(Ma, rows_a, d * D, Xa, Ra);     // Xa: rows_a x k, Ra: k x (d D)
-    qr_thin(MbT, cols_b, D * d, Qt, Rt);    // Mb^T = Qt Rt: L = Rt^T, Y = Qt^T
-    const int k = std::min(rows_a, d * D), kb = std::min(cols_b, D * d);
-    // the environment network: every site padded to dp, sites a and b
-    // carrying their isometries with the shared leg at index 0
+  for (const std::vector<int> &lv : levels) {
+    const auto t0 = clk::now();
+    // 1. reduced tensors of every gate of the level (their sites differ)
+    parallel_for((int)lv.size(), nthreads,
+                 [&](int q) { split_gate(gl[lv[q]], A.data(), d, D, Lx, Ly); });
+    // 2. the environment network: current tensors padded to dp, each gate's
+    // two sites carrying its isometries
     std::fill(M.begin(), M.end(), 0.0);
-    const size_t sp = (size_t)dp * D * D * D * D;
     for (int i = 0; i < Lx * Ly; ++i)
-      if (i != ia && i != ib)
-        std::copy(A.begin() + i * ss, A.begin() + (i + 1) * ss, M.begin() + i * sp);
-    for (int q = 0; q < k; ++q)
-      for (int r = 0; r < rows_a; ++r) {
-        int lg[5] = {0, 0, 0, 0, 0};
-        lg[oa[0]] = r / (da[oa[1]] * da[oa[2]]);
-        lg[oa[1]] = r / da[oa[2]] % da[oa[1]];
-        lg[oa[2]] = r % da[oa[2]];
-        M[ia * sp + (size_t)q * D3 * D + aidx5(D, 0, lg)] = Xa[(size_t)r * k + q];
-      }
-    for (int q = 0; q < kb; ++q)
-      for (int cc = 0; cc < cols_b; ++cc) {
-        int lg[5] = {0, 0, 0, 0, 0};
-        lg[ob[0]] = cc / (db[ob[1]] * db[ob[2]]);
-        lg[ob[1]] = cc / db[ob[2]] % db[ob[1]];
-        lg[ob[2]] = cc % db[ob[2]];
-        M[ib * sp + (size_t)q * D3 * D + aidx5(D, 0, lg)] = Qt[(size_t)cc * kb + q];
-      }
+      std::copy(A.begin() + i * ss, A.begin() + (i + 1) * ss, M.begin() + i * sp);
+    for (int q : lv) place_isometries(gl[q], M.data(), sp, D);
+    const auto t1 = clk::now();
     if ((st = bbp_set_tensors(e, M.data(), M.size())) != BBP_OK ||
         (!msgs.empty() && (st = bbp_set_messages(e, msgs.data(), msgs.size())) != BBP_OK))
       return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
-    std::vector<double> rho((size_t)dp * dp * dp * dp);
-    const int32_t x0 = bd[0], y0 = bd[1], x1 = bd[2], y1 = bd[3];
-    if ((st = bbp_rdm_bonds(e, 1, &x0, &y0, &x1, &y1, rho.data())) != BBP_OK)
+    const int n = (int)lv.size();
+    std::vector<int32_t> x0(n), y0(n), x1(n), y1(n);
+    for (int q = 0; q < n; ++q) {
+      x0[q] = gl[lv[q]].b[0];
+      y0[q] = gl[lv[q]].b[1];
+      x1[q] = gl[lv[q]].b[2];
+      y1[q] = gl[lv[q]].b[3];
+    }
+    std::vector<double> rho((size_t)n * dp * dp * dp * dp);
+    if ((st = bbp::rdm_bonds_only(e, n, x0.data(), y0.data(), x1.data(), y1.data(),
+                                  rho.data())) != BBP_OK)
       return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
-    // N[(ka,kb),(ka',kb')], the isometry columns of the two sites
-    auto N = [&](int a, int b, int a2, int b2) {
-      return rho[((size_t)a * dp + b) * dp * dp + (size_t)a2 * dp + b2];
-    };
-    std::vector<double> Nm((size_t)k * kb * k * kb);
-    for (int a = 0; a < k; ++a)
-      for (int b = 0; b < kb; ++b)
-        for (int a2 = 0; a2 < k; ++a2)
-          for (int b2 = 0; b2 < kb; ++b2)
-            Nm[((size_t)(a * kb + b) * k + a2) * kb + b2] = N(a, b, a2, b2);
-    // Theta[ka][s][t][kb] = sum_r Ra[ka][(s, r)] Lb[(r, t)][kb], Lb = Rt^T
-    std::vector<double> Th((size_t)k * d * d * kb, 0.0);
-    for (int a = 0; a < k; ++a)
-      for (int s = 0; s < d; ++s)
-        for (int t = 0; t < d; ++t)
-          for (int b = 0; b < kb; ++b) {
-            double v = 0.0;
-            for (int r = 0; r < D; ++r)
-              v += Ra[(size_t)a * d * D + s * D + r] * Rt[(size_t)b * D * d + r * d + t];
-            Th[((a * d + s) * d + t) * kb + b] = v;
-          }
-    std::vector<double> R((size_t)k * d * D), L((size_t)D * d * kb);
-    double loss = 0.0;
-    if (!fit_pair(d, D, k, kb, Nm.data(), Th.data(), gate, n_als, R.data(), L.data(), &loss))
-      return bbp::ctx_fail(c, BBP_ENUMERIC, "singular reduced-tensor fit");
-    loss_sum += loss;
-    // new tensors: A_a = X_a R, A_b = L Y (Y = Qt^T) on the true extents,
-    // zero padding elsewhere, each scaled to a largest entry of 1
-    std::vector<double> na(ss, 0.0), nb(ss, 0.0);
-    for (leg[0] = 0; leg[0] < d; ++leg[0])
-      for (leg[1] = 0; leg[1] < D; ++leg[1])
-        for (leg[2] = 0; leg[2] < D; ++leg[2])
-          for (leg[3] = 0; leg[3] < D; ++leg[3])
-            for (leg[4] = 0; leg[4] < D; ++leg[4]) {
-              const size_t dst = aidx5(D, 0, leg);
-              if (leg[1] < da[1] && leg[2] < da[2] && leg[3] < da[3] && leg[4] < da[4]) {
-                const size_t ra = row_of(leg, oa, da);
-                double v = 0.0;
-                for (int q = 0; q < k; ++q)
-                  v += Xa[ra * k + q] * R[((size_t)q * d + leg[0]) * D + leg[sa]];
-                na[dst] = v;
-              }
-              if (leg[1] < db[1] && leg[2] < db[2] && leg[3] < db[3] && leg[4] < db[4]) {
-                const size_t cb = row_of(leg, ob, db);
-                double w = 0.0;
-                for (int q = 0; q < kb; ++q)
-                  w += L[((size_t)leg[sb] * d + leg[0]) * kb + q] * Qt[cb * kb + q];
-                nb[dst] = w;
-              }
-            }
-    double ma = 0.0, mb = 0.0;
-    for (size_t i = 0; i < ss; ++i) {
-      ma = std::max(ma, std::fabs(na[i]));
-      mb = std::max(mb, std::fabs(nb[i]));
+    // 3. fits and new tensors, every gate of the level at once
+    const auto t2 = clk::now();
+    std::vector<int> ok(n, 1);
+    std::vector<double> loss(n, 0.0);
+    parallel_for(n, nthreads, [&](int q) {
+      ok[q] = fit_gate(gl[lv[q]], rho.data() + (size_t)q * dp * dp * dp * dp, dp, gate, n_als,
+                       d, D, A.data(), &loss[q]);
+    });
+    for (int q = 0; q < n; ++q) {
+      if (!ok[q])
+        return bbp::ctx_fail(c, BBP_ENUMERIC,
+                             "singular reduced-tensor fit or vanishing fitted tensor");
+      loss_sum += loss[q];
+      ++gates;
     }
-    if (!(ma > 0.0) || !(mb > 0.0) || !std::isfinite(ma) || !std::isfinite(mb))
-      return bbp::ctx_fail(c, BBP_ENUMERIC, "vanishing or non-finite fitted tensor");
-    for (size_t i = 0; i < ss; ++i) {
-      A[ia * ss + i] = na[i] / ma;
-      A[ib * ss + i] = nb[i] / mb;
-    }
-    ++gates;
+    t_host += secs(t0, t1) + secs(t2, clk::now());
+    t_env += secs(t1, t2);
   }
   // the new tensors, with the messages the step started from
   if ((st = bbp_set_tensors(c, A.data(), A.size())) != BBP_OK) return st;
@@ -528,6 +637,9 @@ extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als
   if (info) {
     info[0] = gates;
     info[1] = loss_sum;
+    info[2] = t_env;
+    info[3] = t_host;
+    info[4] = n_levels;
   }
   return BBP_OK;
 }
