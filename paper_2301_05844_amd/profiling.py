@@ -16,8 +16,9 @@
         dispatch) of its last N dispatches, each scaled by what the same
         counter reads for a plain copy of B bytes read and B bytes written.
 
-``source_sha()`` hashes the HIP sources, so a traffic figure can be dropped
-once the kernels have changed since the counters were taken.
+``source_sha()`` hashes the kernel sources (kernels, launchers and the shapes
+they share with the host), so a traffic figure is dropped once the kernels
+have changed since the counters were taken.
 """
 
 import argparse
@@ -30,7 +31,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ("csrc/bbp_kernels.hip", "csrc/bbp_api.hip", "csrc/bbp_internal.h")
+SOURCES = ("csrc/bbp_kernels.hip", "csrc/bbp_internal.h")
 
 
 def source_sha():
