@@ -80,10 +80,12 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *   "timing"   1: record per-kernel-class launch times (any time; resets)
  *   "precision" 64 (default) or 32 (any time): with 32 the fit's visit and
  *              environment contractions run on FP32 MFMA with FP32
- *              accumulation (D = 4 kernels, bond cap <= 64; other shapes
- *              stay FP64); QR, normalisation, overlaps and every stored
- *              message stay FP64.  Sweeps in 32 followed by sweeps in 64
- *              reach the FP64 fixed point from the FP32 one.
+ *              accumulation in every fused visit (any D, bond cap <= 64);
+ *              fits whose visits run as separate kernels (bond caps above
+ *              64, e.g. the observables at a chi_env above 64) stay FP64;
+ *              QR, normalisation, overlaps and every stored message stay
+ *              FP64.  Sweeps in 32 followed by sweeps in 64 reach the FP64
+ *              fixed point from the FP32 one.
  *   "graphs"   1 (default) or 0 (any time): once a message batch's column
  *              absorptions all start warm (from the second sweep on), their
  *              launches are captured as a HIP graph and replayed in later
