@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <tuple>
 #include <memory>
 #include <mutex>
@@ -248,6 +249,19 @@ struct bbp_ctx {
   // last two calls' entries are kept)
   std::vector<std::unique_ptr<Group>> batch_cache;
   std::vector<std::pair<int, DevBuf>> unit_out_cache;
+  // Boundary stacks kept from earlier bond-only region contractions (the
+  // blockBP update's environment context, stack_reuse on): each with the
+  // rotated tensors of every column it absorbed, reused by a later call
+  // while the columns that call needs are unchanged.
+  struct KeptStack {
+    Group *g;
+    int item;
+    std::vector<double> cols;  // [H][W][site] in the stack's canonical frame
+    std::vector<double> nu;    // [W] column scales
+  };
+  bool stack_reuse = false;
+  std::map<std::tuple<int, int, int, char>, KeptStack> kept_stacks;
+  std::vector<std::unique_ptr<Group>> kept_groups;
   int obs_call = 0;
   double last_flops = 0.0;
   std::map<std::tuple<int, int, int>, RegionResult> obs;  // (kind, bi, bj)
@@ -509,6 +523,24 @@ struct BatchReturn {
     v->clear();
   }
 };
+// Kept boundary stacks: groups no stack refers to any more go back to the
+// batch cache; release_kept drops every kept stack.
+static void gc_kept(bbp_ctx *c) {
+  std::set<const Group *> used;
+  for (auto &kv : c->kept_stacks) used.insert(kv.second.g);
+  auto &v = c->kept_groups;
+  for (auto &g : v)
+    if (g && !used.count(g.get())) {
+      g->cache_gen = c->obs_call;
+      c->batch_cache.push_back(std::move(g));
+    }
+  v.erase(std::remove(v.begin(), v.end(), nullptr), v.end());
+}
+static void release_kept(bbp_ctx *c) {
+  c->kept_stacks.clear();
+  gc_kept(c);
+}
+
 // A device buffer of exactly `bytes` from the context's cache, else new.
 static DevBuf take_unit_out(bbp_ctx *c, size_t bytes) {
   for (auto it = c->unit_out_cache.begin(); it != c->unit_out_cache.end(); ++it)
@@ -732,18 +764,19 @@ static double column_macs(const FitDims &f, const std::vector<int> &xb_bonds,
 }
 
 static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
-                                  const std::vector<int> &any_rnd);
+                                  const std::vector<int> &any_rnd, int col_hi = -1);
 static bool same_batch(const FitBatch &a, const FitBatch &b);
 
 // Absorb canonical columns W-1 .. col_lo of every item of a batch (App. A:
-// each column is an MPO x MPS variational fit).  Uses g.dims (uploaded here)
-// for the bond caps and the random-start flags.  A message batch
+// each column is an MPO x MPS variational fit), or col_hi .. col_lo when
+// col_hi >= 0 (the batch's store then holds column col_hi + 1's result).
+// Uses g.dims (uploaded here) for the bond caps and the random-start flags.  A message batch
 // (graph = true) whose columns all start warm has the same launch sequence,
 // with the same arguments, in every sweep: it is captured as a HIP graph
 // once and replayed, one launch instead of one per kernel.  Timing brackets
 // (a process-wide switch) are not captured.
 static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
-                                 bool graph = false) {
+                                 bool graph = false, int col_hi = -1) {
   FitBatch &f = g.fb;
   const int W = f.W;
   hipError_t e;
@@ -774,8 +807,8 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t s
   if (e != hipSuccess) return c->hip_fail(e, "upload flags");
   bool warm = true;
   for (int col = col_lo; col < W; ++col) warm = warm && !any_rnd[col];
-  if (!graph || !c->graphs || !warm || bbp::timing_enabled())
-    return enqueue_columns(c, g, col_lo, st, any_rnd);
+  if (!graph || !c->graphs || !warm || bbp::timing_enabled() || col_hi >= 0)
+    return enqueue_columns(c, g, col_lo, st, any_rnd, col_hi);
   if (g.graph && (g.graph_nfit != c->n_fit || !same_batch(g.graph_fb, f))) {
     (void)hipGraphExecDestroy(g.graph);
     g.graph = nullptr;
@@ -821,12 +854,12 @@ static bool same_batch(const FitBatch &a, const FitBatch &b) {
 
 // The launches of absorb_columns, enqueued on st.
 static bbp_status enqueue_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
-                                  const std::vector<int> &any_rnd) {
+                                  const std::vector<int> &any_rnd, int col_hi) {
   FitBatch &f = g.fb;
   const int W = f.W, N = f.N;
   hipError_t e;
   const size_t sN = (size_t)N * f.S, sWN = (size_t)W * N * f.S;
-  for (int col = W - 1; col >= col_lo; --col) {
+  for (int col = col_hi >= 0 ? col_hi : W - 1; col >= col_lo; --col) {
     Ptr X = col == W - 1 ? Ptr{f.xin, sN}
                          : Ptr{f.store + slot_store(f, col + 1, 0), sWN};
     auto Xs = [&](int j) { return Ptr{X.p + (size_t)j * f.S, X.stride}; };
@@ -1044,6 +1077,7 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
   for (int i = 0; i < nm; ++i) c->msgs[i].bonds = new_bonds[i];
   c->cur = nxt;
   c->obs.clear();
+  release_kept(c);
   c->last_flops = flops;
   if (residual) *residual = nm ? sum / nm : 0.0;
   return BBP_OK;
@@ -1104,6 +1138,14 @@ struct LineItem {
   int xs, ys;   // stack item indices of the X and Y boundaries
   int cx, cy;   // canonical column of the line in the X / Y frames
   double ls;    // log scale of the two boundaries
+};
+
+// Where a boundary stack's results live: its batch, its item there and its
+// column scales.
+struct StackRef {
+  Group *g = nullptr;
+  int item = 0;
+  const double *nu = nullptr;
 };
 
 struct UnitItem {
@@ -1215,22 +1257,78 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       stacks.push_back(it);
     }
   }
+  // Reuse of kept stacks (bond-only contractions with stack_reuse on): a
+  // line at canonical column cx reads its stack after the absorption of
+  // columns W-1..cx+1, so a kept stack serves while those columns' rotated
+  // tensors are unchanged; its boundary messages and fit settings are fixed
+  // while stacks are kept.
+  bool reuse = c->stack_reuse;
+  for (const RegionSpec &R : regs) reuse = reuse && !R.targets.empty();
+  std::vector<std::vector<double>> rot(reuse ? stacks.size() : 0);
+  std::vector<char> reused(stacks.size(), 0);
+  std::vector<int> need_lo(stacks.size(), 1), redo_hi(stacks.size(), -1);
+  std::vector<StackRef> where(stacks.size());  // group, item, column scales
+  if (reuse)
+    for (size_t sidx = 0; sidx < stacks.size(); ++sidx) {
+      const StackItem &it = stacks[sidx];
+      const RegionSpec &R = regs[it.region];
+      std::vector<double> &t = rot[sidx];
+      t.assign((size_t)it.Hc * it.Wc * asite, 0.0);
+      for (int yc = 0; yc < it.Hc; ++yc)
+        for (int xc = 0; xc < it.Wc; ++xc) {
+          int y, x;
+          canon_to_region(it.orient, R.H, R.W, yc, xc, &y, &x);
+          rotate_site(c, region_site(c, R, y, x), it.orient,
+                      t.data() + ((size_t)yc * it.Wc + xc) * asite);
+        }
+      int lo = it.Wc;  // lowest canonical column any of its lines needs absorbed
+      for (const Target &tg : R.targets) {
+        int cx = -1;
+        if (tg.row && it.orient == 'D') cx = R.H - 1 - tg.line;
+        if (tg.row && it.orient == 'U') cx = tg.line;
+        if (!tg.row && it.orient == 'L') cx = tg.line;
+        if (!tg.row && it.orient == 'R') cx = R.W - 1 - tg.line;
+        if (cx >= 0) lo = std::min(lo, cx + 1);
+      }
+      need_lo[sidx] = lo;
+      auto kv = c->kept_stacks.find(std::make_tuple(R.kind, R.bi, R.bj, it.orient));
+      if (kv == c->kept_stacks.end() || kv->second.cols.size() != t.size()) continue;
+      // the first column in absorption order (W-1 first) whose tensors changed
+      int c0 = -1;
+      for (int xc = it.Wc - 1; xc >= lo && c0 < 0; --xc)
+        for (int yc = 0; yc < it.Hc; ++yc) {
+          const size_t o = ((size_t)yc * it.Wc + xc) * asite;
+          if (std::memcmp(t.data() + o, kv->second.cols.data() + o, asite * 8) != 0) {
+            c0 = xc;
+            break;
+          }
+        }
+      if (c0 >= 0 && kv->second.g->fb.items != 1) continue;  // recomputed whole
+      reused[sidx] = 1;
+      redo_hi[sidx] = c0;  // >= 0: columns c0..lo re-absorbed in the kept batch
+      where[sidx] = StackRef{kv->second.g, kv->second.item, kv->second.nu.data()};
+    }
   std::map<std::pair<int, int>, std::vector<int>> sgroups;
   for (size_t i = 0; i < stacks.size(); ++i)
-    sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
+    if (!reused[i]) sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
   // every shape split over the lanes: each lane then runs a share of every
   // shape, and the lanes' kernels overlap at different steps of their fits
   // (one lane's QR, which holds few CUs, beside another's visit)
   std::vector<std::vector<int>> batches;
   std::vector<int> shape_items;  // items of the shape each batch belongs to
   for (auto &kv : sgroups)
-    for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) {
-      batches.push_back(part);
-      shape_items.push_back((int)kv.second.size());
-    }
+    if (reuse)  // kept stacks are updated in place, one per batch
+      for (int id : kv.second) {
+        batches.push_back({id});
+        shape_items.push_back(1);
+      }
+    else
+      for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) {
+        batches.push_back(part);
+        shape_items.push_back((int)kv.second.size());
+      }
   std::vector<std::unique_ptr<Group>> sg;
   BatchReturn sg_return{c, &sg};
-  std::vector<std::pair<int, int>> where(stacks.size());  // (group, item)
   std::vector<std::vector<double>> nus;
   // allocate and stage every batch first: allocation waits on the context
   // stream, which must not yet hold absorption work
@@ -1244,7 +1342,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       const StackItem &it = stacks[ids[i]];
       const RegionSpec &R = regs[it.region];
       slots[i] = region_slot(R.kind, R.bi, R.bj, it.orient);
-      where[ids[i]] = {(int)sg.size(), (int)i};
+      where[ids[i]] = StackRef{gp.get(), (int)i, nullptr};
     }
     bbp_status bs = alloc_batch(c, g, (int)ids.size(), Kenv, slots);
     if (bs != BBP_OK) return bs;
@@ -1280,10 +1378,25 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     g.ids = ids;
     sg.push_back(std::move(gp));
   }
+  // kept stacks whose columns from redo_hi down changed: those columns are
+  // re-absorbed in place (their batch holds the earlier columns' results)
+  std::vector<int> redo;
+  for (size_t sidx = 0; sidx < stacks.size(); ++sidx)
+    if (reused[sidx] && redo_hi[sidx] >= 0) redo.push_back((int)sidx);
   {  // uploads, gather and absorption; batch b on lane b % nl
-    const int nl = std::max(1, std::min(c->lanes, (int)sg.size()));
+    const int nl = std::max(1, std::min(c->lanes, (int)(sg.size() + redo.size())));
     LaneFork lanes(c);
     if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+    for (size_t r = 0; r < redo.size(); ++r) {
+      const int sidx = redo[r];
+      Group &g = *where[sidx].g;
+      const hipStream_t sb = lane_stream(c, (int)((sg.size() + r) % nl));
+      e = hipMemcpyAsync(g.fb.acan, rot[sidx].data(), rot[sidx].size() * 8,
+                         hipMemcpyHostToDevice, sb);
+      if (e != hipSuccess) return c->hip_fail(e, "region setup");
+      bbp_status bs = absorb_columns(c, g, need_lo[sidx], sb, false, redo_hi[sidx]);
+      if (bs != BBP_OK) return bs;
+    }
     for (size_t b = 0; b < sg.size(); ++b) {
       Group &g = *sg[b];
       FitBatch &f = g.fb;
@@ -1310,27 +1423,54 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       if (e != hipSuccess) return c->hip_fail(e, "region stacks");
     }
   }
+  for (int sidx : redo) {  // the kept entry: its new scales and tensors
+    const RegionSpec &R = regs[stacks[sidx].region];
+    bbp_ctx::KeptStack &k =
+        c->kept_stacks.at(std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient));
+    e = hipMemcpyAsync(k.nu.data(), k.g->fb.nu, k.nu.size() * 8, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return c->hip_fail(e, "region stacks");
+    k.cols = rot[sidx];
+    const StackItem &it = stacks[sidx];
+    for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed now
+      for (int xc = 0; xc < need_lo[sidx]; ++xc)
+        std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
+  }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return c->hip_fail(e, "region stacks");
   int32_t errv = 0;
   e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return c->hip_fail(e, "error flag");
   if (errv) return c->fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
+  for (size_t b = 0; b < sg.size(); ++b)  // column scales of the computed stacks
+    for (size_t i = 0; i < sg[b]->ids.size(); ++i)
+      where[sg[b]->ids[i]].nu = nus[b].data() + i * sg[b]->fb.W;
+  if (reuse) {  // keep the computed stacks (and their batches) for later calls
+    for (size_t sidx = 0; sidx < stacks.size(); ++sidx) {
+      if (reused[sidx]) continue;
+      const RegionSpec &R = regs[stacks[sidx].region];
+      const StackRef &w = where[sidx];
+      c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient)] =
+          bbp_ctx::KeptStack{w.g, w.item, rot[sidx],
+                             std::vector<double>(w.nu, w.nu + w.g->fb.W)};
+      where[sidx].nu = c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj,
+                                                      stacks[sidx].orient)].nu.data();
+    }
+    for (auto &gp : sg) c->kept_groups.push_back(std::move(gp));
+    sg.clear();
+    gc_kept(c);
+  }
 
   // boundary after absorbing canonical columns W-1..col+1 (col = W-1: none)
   auto boundary = [&](int sidx, int col, size_t j) -> const double * {
-    const Group &g = *sg[where[sidx].first];
-    const int i = where[sidx].second;
-    const FitBatch &f = g.fb;
+    const FitBatch &f = where[sidx].g->fb;
+    const int i = where[sidx].item;
     if (col == f.W - 1) return f.xin + ((size_t)i * f.N + j) * f.S;
     return f.store + ((size_t)i * f.W * f.N) * f.S + slot_store(f, col + 1, (int)j);
   };
   auto logscale = [&](int sidx, int col) {
-    const Group &g = *sg[where[sidx].first];
-    const int i = where[sidx].second;
+    const int W = where[sidx].g->fb.W;
     double t = 0.0;
-    for (int cc = col + 1; cc < g.fb.W; ++cc)
-      t += std::log(nus[where[sidx].first][(size_t)i * g.fb.W + cc]);
+    for (int cc = col + 1; cc < W; ++cc) t += std::log(where[sidx].nu[cc]);
     return t;
   };
 
@@ -1367,6 +1507,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   std::map<std::tuple<int, int, int, int>, double> bond_rho;   // (line,j,u,v)
   std::vector<std::unique_ptr<Group>> lgs;
   BatchReturn lg_return{c, &lgs};
+  std::vector<std::vector<double>> line_sites;  // host staging, alive until the sync
   for (auto &kv : lgroups) {
     const int Hc = kv.first;
     const std::vector<int> &lids = kv.second;
@@ -1378,10 +1519,12 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     FitBatch &f = lg.fb;
     const int N = f.N;
     std::vector<CopyJob> jobs;
+    std::vector<double> &fresh = line_sites.emplace_back();  // reuse: current tensors
+    if (reuse) fresh.assign(lids.size() * (size_t)Hc * asite, 0.0);
     for (size_t li = 0; li < lids.size(); ++li) {
       const LineItem &L = lines[lids[li]];
-      const Group &gx = *sg[where[L.xs].first];
-      const int ix = where[L.xs].second;
+      const Group &gx = *where[L.xs].g;
+      const int ix = where[L.xs].item;
       for (int j = 0; j < N; ++j) {
         jobs.push_back(CopyJob{boundary(L.xs, L.cx, j),
                                f.xin + (li * N + j) * f.S, (int64_t)f.S, 0, 0});
@@ -1391,9 +1534,13 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
                                endsite ? 2 : 1, 0});
       }
       for (int j = 0; j < Hc; ++j)
-        jobs.push_back(CopyJob{
-            gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
-            f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
+        if (reuse)  // a kept stack's tensors may be older than the line's
+          std::memcpy(fresh.data() + (li * Hc + j) * asite,
+                      rot[L.xs].data() + ((size_t)j * gx.fb.W + L.cx) * asite, asite * 8);
+        else
+          jobs.push_back(CopyJob{
+              gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
+              f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
       jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
                              f.mt + li * f.S, (int64_t)f.S, 0, 0});
       jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
@@ -1404,6 +1551,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       return c->fail(BBP_ENOMEM, "device allocation failed");
     e = copy_sync(c, djobs.p, jobs.data(), sizeof(CopyJob) * jobs.size(),
                   hipMemcpyHostToDevice);
+    if (e == hipSuccess && reuse)
+      e = hipMemcpyAsync(f.acan, fresh.data(), fresh.size() * 8, hipMemcpyHostToDevice, st);
     for (size_t o = 0; e == hipSuccess && o < jobs.size(); o += 60000)
       e = launch_copy_jobs((const CopyJob *)djobs.p + o,
                            (int)std::min<size_t>(60000, jobs.size() - o), Kenv,
@@ -2033,11 +2182,13 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
       return c->fail(BBP_EINVAL, "chi_env must be an integer in [1,128]");
     c->chi_env = (int)v;
     c->obs.clear();
+    release_kept(c);
   } else if (k == "n_fit") {
     if (v < 1 || v > 64 || v != std::floor(v))
       return c->fail(BBP_EINVAL, "n_fit must be an integer in [1,64]");
     c->n_fit = (int)v;
     c->obs.clear();
+    release_kept(c);
   } else if (k == "timing") {
     bbp::timing_enable(v != 0.0);
     bbp::timing_reset();
@@ -2046,6 +2197,7 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     c->precision = (int)v;
     for (auto &g : c->groups) g->fb.prec = c->precision;
     c->obs.clear();
+    release_kept(c);
   } else if (k == "graphs") {
     if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "graphs must be 0 or 1");
     c->graphs = (int)v;
@@ -2241,6 +2393,7 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   }
   if ((s = init_messages(c)) != BBP_OK) return s;
   c->obs.clear();
+  release_kept(c);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "set_tensors");
   c->tensors_set = true;
@@ -2337,6 +2490,7 @@ bbp_status bbp_set_messages(bbp_ctx *c, const double *buf, size_t n) {
   for (size_t i = 0; i < c->msgs.size(); ++i) c->msgs[i].bonds = bonds[i];
   for (auto &g : c->groups) std::fill(g->have.begin(), g->have.end(), 0);
   c->obs.clear();
+  release_kept(c);
   return BBP_OK;
 }
 
@@ -3179,6 +3333,7 @@ bbp_status sweepset_run(SweepSet *s, bbp_ctx *const *cs, int n, double *res,
     for (int i = 0; i < nm; ++i) c->msgs[i].bonds = new_bonds[c->serial][i];
     c->cur = 1 - c->cur;
     c->obs.clear();
+    release_kept(c);
     c->last_flops = flops[c->serial];
     res[k] = nm ? sum / nm : 0.0;
   }
@@ -3202,6 +3357,21 @@ bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m) { return c->
 bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
                           const int32_t *x1, const int32_t *y1, double *rho) {
   return ::rdm_bonds_only(c, n, x0, y0, x1, y1, rho);
+}
+
+void ctx_keep_stacks(bbp_ctx *c) { c->stack_reuse = true; }
+
+bbp_status ctx_replace_sites(bbp_ctx *c, int n, const int *site, const double *A) {
+  if (!c || n < 0 || (n > 0 && (!site || !A))) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  const size_t ss = (size_t)c->d * c->D * c->D * c->D * c->D;
+  const int nsites = c->ucx * c->ucy;
+  for (int i = 0; i < n; ++i) {
+    if (site[i] < 0 || site[i] >= nsites) return c->fail(BBP_EINVAL, "site out of range");
+    std::copy(A + (size_t)i * ss, A + (size_t)(i + 1) * ss, c->A.begin() + (size_t)site[i] * ss);
+  }
+  c->obs.clear();  // kept stacks stay: each is checked against the tensors it absorbed
+  return BBP_OK;
 }
 
 const double *ctx_tensors(bbp_ctx *c, size_t *n) {

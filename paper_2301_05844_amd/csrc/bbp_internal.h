@@ -249,5 +249,14 @@ const double *ctx_tensors(bbp_ctx *c, size_t *n);
 // is kept for later queries.  Same values as bbp_rdm_bonds.
 bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
                           const int32_t *x1, const int32_t *y1, double *rho);
+// Keep the boundary stacks of bond-only contractions for later calls (reused
+// while the columns a later call needs are unchanged).  For a context whose
+// messages and settings stay fixed after its first contraction.
+void ctx_keep_stacks(bbp_ctx *c);
+// Replace the host tensors of n sites (lattice site indices, site layout of
+// bbp_set_tensors) for the observables only: regions are contracted from
+// them, the sweeps' rotated copies are not rebuilt, so a context updated
+// this way must not be swept.
+bbp_status ctx_replace_sites(bbp_ctx *c, int n, const int *site, const double *A);
 
 }  // namespace bbp

@@ -585,21 +585,49 @@ extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als
   auto secs = [](clk::time_point a, clk::time_point b) {
     return std::chrono::duration<double>(b - a).count();
   };
+  // the environment network, padded to dp (every site's current tensor)
+  for (int i = 0; i < Lx * Ly; ++i)
+    std::copy(A.begin() + i * ss, A.begin() + (i + 1) * ss, M.begin() + i * sp);
+  std::vector<int> prev_sites;  // the previous level's gate sites
+  bool env_ready = false;
   for (const std::vector<int> &lv : levels) {
     const auto t0 = clk::now();
     // 1. reduced tensors of every gate of the level (their sites differ)
     parallel_for((int)lv.size(), nthreads,
                  [&](int q) { split_gate(gl[lv[q]], A.data(), d, D, Lx, Ly); });
     // 2. the environment network: current tensors padded to dp, each gate's
-    // two sites carrying its isometries
-    std::fill(M.begin(), M.end(), 0.0);
-    for (int i = 0; i < Lx * Ly; ++i)
+    // two sites carrying its isometries.  The environment context holds the
+    // network of the previous level; only the sites that differ are replaced
+    // (the previous level's sites, now with their new tensors, and this
+    // level's), so that boundary stacks over unchanged rows or columns are
+    // reused.
+    std::vector<int> changed(prev_sites);
+    prev_sites.clear();
+    for (int q : lv) {
+      prev_sites.push_back(gl[q].ia);
+      prev_sites.push_back(gl[q].ib);
+    }
+    changed.insert(changed.end(), prev_sites.begin(), prev_sites.end());
+    for (int i : changed) {
+      std::fill(M.begin() + i * sp, M.begin() + (i + 1) * sp, 0.0);
       std::copy(A.begin() + i * ss, A.begin() + (i + 1) * ss, M.begin() + i * sp);
+    }
     for (int q : lv) place_isometries(gl[q], M.data(), sp, D);
+    std::vector<double> sites_buf(changed.size() * sp);
+    for (size_t q = 0; q < changed.size(); ++q)
+      std::copy(M.begin() + changed[q] * sp, M.begin() + (changed[q] + 1) * sp,
+                sites_buf.begin() + q * sp);
     const auto t1 = clk::now();
-    if ((st = bbp_set_tensors(e, M.data(), M.size())) != BBP_OK ||
-        (!msgs.empty() && (st = bbp_set_messages(e, msgs.data(), msgs.size())) != BBP_OK))
+    if (!env_ready) {
+      if ((st = bbp_set_tensors(e, M.data(), M.size())) != BBP_OK ||
+          (!msgs.empty() && (st = bbp_set_messages(e, msgs.data(), msgs.size())) != BBP_OK))
+        return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
+      bbp::ctx_keep_stacks(e);
+      env_ready = true;
+    } else if ((st = bbp::ctx_replace_sites(e, (int)changed.size(), changed.data(),
+                                            sites_buf.data())) != BBP_OK) {
       return bbp::ctx_fail(c, st, std::string("environment: ") + bbp_last_error(e));
+    }
     const int n = (int)lv.size();
     std::vector<int32_t> x0(n), y0(n), x1(n), y1(n);
     for (int q = 0; q < n; ++q) {
