@@ -1722,6 +1722,24 @@ void k_visit4p(VisitArgs v) {
 // base[r1*s1 + r2*s2 + c*sc]) is copied column-major into LDS, factorised,
 // and Q written back in place (panels too large for LDS: k_qrg below).
 // ---------------------------------------------------------------------------
+// x / n and x % n for 0 <= x < 2^22 and 1 <= n < 2^22 through one FP32
+// multiply: x and 1/n are within one rounding of exact, so the truncated
+// product is the quotient or one off, and the remainder's sign and size
+// correct it.  Replaces an integer division (a few dozen VALU operations)
+// in the panel copies.
+struct DivN {
+  int n;
+  float inv;
+  __device__ explicit DivN(int n_) : n(n_), inv(1.0f / (float)n_) {}
+  __device__ __forceinline__ int quot(int x) const {
+    int q = (int)((float)x * inv);
+    const int r = x - q * n;
+    if (r < 0) --q;
+    else if (r >= n) ++q;
+    return q;
+  }
+};
+
 struct QrArgs {
   FitDims *dims;
   int W, c, j, mode, K, P;
@@ -1770,9 +1788,10 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
   double *A = lds;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
+  const DivN divm(m), dn2(n2);
   for (int idx = tid; idx < m * n; idx += kThreads) {
-    const int col = idx / m, r = idx - col * m;
-    const int r1 = r / n2, r2 = r - r1 * n2;
+    const int col = divm.quot(idx), r = idx - col * m;
+    const int r1 = dn2.quot(r), r2 = r - r1 * n2;
     A[idx] = base[r1 * s1 + r2 * s2 + col * sc];
   }
   __syncthreads();
@@ -1851,8 +1870,8 @@ __global__ __launch_bounds__(kThreads) void k_qr(QrArgs q) {
   }
 
   for (int idx = tid; idx < m * n; idx += kThreads) {
-    const int col = idx / m, r = idx - col * m;
-    const int r1 = r / n2, r2 = r - r1 * n2;
+    const int col = divm.quot(idx), r = idx - col * m;
+    const int r1 = dn2.quot(r), r2 = r - r1 * n2;
     base[r1 * s1 + r2 * s2 + col * sc] = A[idx];
   }
 }
@@ -1940,13 +1959,14 @@ __device__ __forceinline__ void qrg_copy(double *A, double *base, int m, int n, 
                                          size_t s1, size_t s2, size_t sc, int tid) {
   constexpr int U = 8;
   const int total = m * n;
+  const DivN divm(m), dn2(n2);
   for (int i0 = tid; i0 < total; i0 += kQrgThreads * U) {
     double x[U];
 #pragma unroll
     for (int r = 0; r < U; ++r) {
       const int idx = i0 + r * kQrgThreads;
-      const int col = idx / m, row = idx - col * m;
-      const int r1 = row / n2, r2 = row - r1 * n2;
+      const int col = divm.quot(idx), row = idx - col * m;
+      const int r1 = dn2.quot(row), r2 = row - r1 * n2;
       const size_t g = r1 * s1 + r2 * s2 + col * sc;
       x[r] = idx < total ? (kIn ? base[g] : A[idx]) : 0.0;
     }
@@ -1954,8 +1974,8 @@ __device__ __forceinline__ void qrg_copy(double *A, double *base, int m, int n, 
     for (int r = 0; r < U; ++r) {
       const int idx = i0 + r * kQrgThreads;
       if (idx >= total) break;
-      const int col = idx / m, row = idx - col * m;
-      const int r1 = row / n2, r2 = row - r1 * n2;
+      const int col = divm.quot(idx), row = idx - col * m;
+      const int r1 = dn2.quot(row), r2 = row - r1 * n2;
       const size_t g = r1 * s1 + r2 * s2 + col * sc;
       if (kIn) A[idx] = x[r];
       else base[g] = x[r];
@@ -2180,8 +2200,9 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
   const int lr = lane >> 4, lc = lane & 15;
   // Row tiles t > 0 start at row 16 * NW >= n, below every diagonal entry.
   auto rowof = [&](int t, int s) { return 16 * (wave + NW * t) + 4 * s + lr; };
+  const DivN dn2(n2);
   auto gaddr = [&](int row, int col) {
-    const int r1 = row / n2, r2 = row - r1 * n2;
+    const int r1 = dn2.quot(row), r2 = row - r1 * n2;
     return r1 * s1 + r2 * s2 + col * sc;
   };
 
@@ -2445,6 +2466,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
   size_t os1 = s1, os2 = s2, osc = sc;
   int on2 = n2;
   asm volatile("" : "+s"(os1), "+s"(os2), "+s"(osc), "+s"(on2));
+  const DivN don2(on2);
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -2452,7 +2474,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int row = rowof(t, s), col = 16 * ct + lc;
-        const int r1 = row / on2, r2 = row - r1 * on2;
+        const int r1 = don2.quot(row), r2 = row - r1 * on2;
         if (row < m && col < n) base[r1 * os1 + r2 * os2 + col * osc] = a[t][ct][s];
       }
 }
