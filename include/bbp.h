@@ -77,6 +77,15 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *   "chi_env"  boundary bond for observables (default 2*D^2+10, Sec. II)
  *   "n_fit"    full fit sweeps per column absorption (default 2, App. A)
  *   "seed"     seed of the counter-based fit initial states (default 0)
+ *   "init"     initial messages (before bbp_set_tensors, which applies
+ *              them): 0 (default) the identity product MPDO; 1 a random
+ *              product MPDO (App. A), per site m[(k,k')] = sum_a R[k][a]
+ *              R[k'][a] with R the D x D counter-based uniform values of
+ *              (seed, 2^41 + message index, site), scaled to unit 2-norm
+ *   "hbm_budget" device bytes the context may hold (any time; default 0: no
+ *              limit): an allocation that would pass it fails like an
+ *              out-of-memory one (the kept buffers are freed and it is tried
+ *              once more, then BBP_ENOMEM; the context stays usable)
  *   "timing"   1: record per-kernel-class launch times (any time; resets)
  *   "precision" 64 (default) or 32 (any time): with 32 the fit's visit and
  *              environment contractions run on FP32 MFMA with FP32
@@ -430,8 +439,11 @@ const char *bbp_update_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Request server: independent block-BP solves of finite open lattices
- * (Sec. II; each one the problem bbp_create states, infinite lattices are
- * not served) on one GPU with continuous batching.  Requests are admitted
+ * (Sec. II; each one the problem bbp_create states) on one GPU with
+ * continuous batching.  Infinite lattices are not served: their solve is
+ * one block's four self-messages with outputs over the unit cell, a problem
+ * of another shape than the request below describes; run it on a context of
+ * its own.  Requests are admitted
  * first-in first-out between sweeps while fewer than max_slots are resident
  * and their device-memory estimate (bbp_server_estimate) fits in what
  * budget_bytes leaves free.  Every resident request then sweeps together:

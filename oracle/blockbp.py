@@ -140,6 +140,20 @@ def identity_mps(n, D):
     return [t.copy() for _ in range(n)]
 
 
+def random_mpdo(n, D, seed, e):
+    """Random product MPDO (App. A's random initial message, here with the
+    counter-based uniform values instead of normal ones so that every
+    implementation draws the same numbers): site i is ``R R^T`` for the D x D
+    matrix R of ``counter_uniform(seed, 2^41 + e, i, D*D)``, scaled to unit
+    Frobenius norm; positive semidefinite, bonds 1."""
+    out = []
+    for i in range(n):
+        R = counter_uniform(seed, (1 << 41) + e, i, D * D).reshape(D, D)
+        M = R @ R.T
+        out.append((M / np.linalg.norm(M)).reshape(1, D * D, 1))
+    return out
+
+
 def mps_reverse(m):
     """Reverse the site order; each site's two bond legs swap."""
     return [t.transpose(2, 1, 0).copy() for t in reversed(m)]
@@ -376,7 +390,7 @@ class BlockBP:
 
     def __init__(self, A, D, chi, bx, by, Lx=0, Ly=0, infinite=False,
                  ucx=1, ucy=1, chi_env=None, n_fit=2, seed=0, d=2, shift=(0, 0),
-                 single_layer=False):
+                 single_layer=False, init=0):
         self.D, self.chi, self.bx, self.by = D, chi, bx, by
         # single-layer network: the tensors' sum over s is the network
         # tensor, the bra layer a fixed index-0 tensor
@@ -420,9 +434,10 @@ class BlockBP:
                 for dr in DIRS:
                     if self.neighbour(bi, bj, dr) is not None:
                         self.order.append((bi, bj, dr))
-        for (bi, bj, dr) in self.order:
+        for e, (bi, bj, dr) in enumerate(self.order):
             n = by if dr in ("L", "R") else bx
-            self.msgs[(bi, bj, dr)] = identity_mps(n, D)
+            self.msgs[(bi, bj, dr)] = (identity_mps(n, D) if init == 0
+                                       else random_mpdo(n, D, seed, e))
         self.warm = {k: {} for k in self.order}
         self.residuals = []
         self._cache = {}

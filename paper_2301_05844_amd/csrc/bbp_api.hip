@@ -50,6 +50,7 @@ bool out_reversed(char d) { return d == 'R' || d == 'U'; }
 // more.
 struct MemAcct {
   size_t now = 0, peak = 0;
+  size_t budget = 0;  // bytes the owner may hold (0: no limit)
   bbp_alloc_fn alloc_fn = nullptr;
   bbp_free_fn free_fn = nullptr;
   void *user = nullptr;
@@ -144,6 +145,8 @@ struct DevBuf {
 
  private:
   hipError_t raw_alloc(size_t b) {
+    if (tl_acct && tl_acct->budget && tl_acct->now + b > tl_acct->budget)
+      return hipErrorOutOfMemory;  // beyond the context's byte budget
     if (tl_acct && tl_acct->alloc_fn) {
       p = tl_acct->alloc_fn(b, tl_acct->user);
       return p ? hipSuccess : hipErrorOutOfMemory;
@@ -224,6 +227,7 @@ struct bbp_ctx {
   int msg_split = 2;   // message batches of one shape split into this many (one per lane)
   bool engine = false; // messages swept by a shared SweepSet (no message batches of its own)
   int single_layer = 0; // 1: the network is sum_s A[s] (bra layer fixed at index 0)
+  int init = 0;         // initial messages: 0 identity product MPDO, 1 random product MPDO
   DevBuf delta;         // single layer: the bra tensor, [s][0][0][0][0] = 1
   DevBuf rot;                   // engine mode: rotated block tensors of every message
   std::vector<size_t> rot_off;  // doubles from rot's start to message i's block
@@ -703,17 +707,54 @@ static bbp_status upload_rotated(bbp_ctx *c, Group &g) {
   return BBP_OK;
 }
 
+// Uniform value in [-1, 1) number i of the counter-based stream of (seed,
+// slot, site): SplitMix64 (Steele, Lea, Flood 2014) chained over the
+// counters, the top 53 bits scaled; the same values the fit's random starts
+// draw (k_rand_init).
+static double host_counter_uniform(uint64_t seed, uint64_t slot, uint64_t site, uint64_t i) {
+  auto sm = [](uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const uint64_t h = sm(sm(sm(sm(seed) ^ slot) ^ site) ^ i);
+  return (double)(h >> 11) * 0x1p-52 - 1.0;
+}
+
 static bbp_status init_messages(bbp_ctx *c) {
-  // identity product MPDO: m[(k,k')] = delta_kk' / sqrt(D), bonds 1
+  // init 0: identity product MPDO, m[(k,k')] = delta_kk' / sqrt(D), bonds 1.
+  // init 1: random product MPDO (App. A), per site m[(k,k')] = sum_a
+  // R[k][a] R[k'][a] with R the D x D counter-based uniform values of (seed,
+  // 2^41 + message, site), scaled to unit 2-norm; bonds 1.
   const size_t per = (size_t)c->Lmax * c->S;
   std::vector<double> host(per * c->msgs.size(), 0.0);
-  const double v = 1.0 / std::sqrt((double)c->D);
+  const int D = c->D;
+  const double v = 1.0 / std::sqrt((double)D);
+  std::vector<double> R((size_t)D * D), M((size_t)D * D);
   for (size_t e = 0; e < c->msgs.size(); ++e) {
     Message &m = c->msgs[e];
     m.bonds.assign(m.n + 1, 1);
-    for (int s = 0; s < m.n; ++s)
-      for (int k = 0; k < c->D; ++k)
-        host[e * per + (size_t)s * c->S + (size_t)(k * c->D + k) * c->K] = v;
+    for (int s = 0; s < m.n; ++s) {
+      double *site = &host[e * per + (size_t)s * c->S];
+      if (c->init == 0) {
+        for (int k = 0; k < D; ++k) site[(size_t)(k * D + k) * c->K] = v;
+        continue;
+      }
+      for (int i = 0; i < D * D; ++i)
+        R[i] = host_counter_uniform(c->seed, (1ull << 41) + e, (uint64_t)s, (uint64_t)i);
+      double nrm = 0.0;
+      for (int k = 0; k < D; ++k)
+        for (int kp = 0; kp < D; ++kp) {
+          double x = 0.0;
+          for (int a = 0; a < D; ++a) x += R[k * D + a] * R[kp * D + a];
+          M[k * D + kp] = x;
+          nrm += x * x;
+        }
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0)) return c->fail(BBP_ENUMERIC, "zero random initial message");
+      for (int q = 0; q < D * D; ++q) site[(size_t)q * c->K] = M[q] / nrm;
+    }
   }
   hipError_t err = copy_sync(c, c->msgbuf[c->cur].p, host.data(), host.size() * 8,
                              hipMemcpyHostToDevice);
@@ -2170,7 +2211,7 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
   if (!c || !key) return BBP_EINVAL;
   std::string k(key);
   const bool late_ok = (k == "n_fit" || k == "chi_env" || k == "timing" || k == "precision" ||
-                        k == "graphs" || k == "skip_padding");
+                        k == "graphs" || k == "skip_padding" || k == "hbm_budget");
   if (c->tensors_set && !late_ok)
     return c->fail(BBP_ESTATE, "option must be set before bbp_set_tensors");
   if (!std::isfinite(v)) return c->fail(BBP_EINVAL, "non-finite option value");
@@ -2226,6 +2267,13 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     if (v < 0 || v != std::floor(v) || v > 9007199254740992.0)
       return c->fail(BBP_EINVAL, "seed must be a non-negative integer");
     c->seed = (uint64_t)v;
+  } else if (k == "init") {
+    if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "init must be 0 or 1");
+    c->init = (int)v;
+  } else if (k == "hbm_budget") {
+    if (v < 0 || v != std::floor(v) || v > 1e18)
+      return c->fail(BBP_EINVAL, "hbm_budget must be a non-negative integer (bytes)");
+    c->mem.budget = (size_t)v;
   } else {
     return c->fail(BBP_EINVAL, "unknown option " + k);
   }

@@ -227,3 +227,13 @@ def test_ite_fit_rejects_bad_arguments():
     bad[0, 0] = np.nan
     with pytest.raises(bbp.BBPError):
         bbp.ite_fit(bad, theta, gate, 2)
+
+
+def test_init_and_hbm_budget_option_validation():
+    bbp = _bbp()
+    c = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4)
+    for key, bad in (("init", 2), ("init", 0.5), ("hbm_budget", -1), ("hbm_budget", 1.5)):
+        with pytest.raises(bbp.BBPError):
+            c.set_option(key, bad)
+    c.set_option("init", 1)
+    c.set_option("hbm_budget", 1 << 30)

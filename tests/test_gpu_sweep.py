@@ -89,3 +89,49 @@ def test_set_messages_round_trip():
     for a, b in zip(m, m2):
         for ta, tb in zip(a, b):
             assert np.array_equal(ta, tb)
+
+
+@pytest.mark.parametrize("lat", [(6, 6, 2, 2, 2, 4), (8, 8, 4, 4, 2, 8), (6, 6, 3, 3, 3, 9)])
+def test_random_initial_messages_match_oracle(lat):
+    """init 1 (App. A's random product MPDO start): the initial messages
+    equal the oracle's entry by entry, and the sweeps from them follow the
+    oracle's residuals and messages on loopy and truncated lattices."""
+    bbp = _lib()
+    Lx, Ly, bx, by, D, chi = lat
+    A = peps_finite(Lx, Ly, D, seed=4)
+    ref = ob.BlockBP(A, D=D, chi=chi, bx=bx, by=by, Lx=Lx, Ly=Ly, init=1, seed=7)
+    g = bbp.BlockBP(Lx=Lx, Ly=Ly, bx=bx, by=by, D=D, chi=chi, init=1, seed=7)
+    g.set_tensors(A)
+    init_err = max(np.abs(tg - to).max() for mg, mo in
+                   zip(g.get_messages(), [ref.msgs[k] for k in ref.order])
+                   for tg, to in zip(mg, mo))
+    print(f"{lat}: initial messages max |d| {init_err:.2e}", flush=True)
+    assert init_err < 1e-15
+    for s in range(3):
+        r_ref, r_gpu = ref.sweep(), g.sweep()
+        print(f"  sweep {s}: gpu {r_gpu:.6e} oracle {r_ref:.6e}", flush=True)
+        assert abs(r_gpu - r_ref) <= 1e-6 * r_ref + 1e-14
+    worst = _compare(g.get_messages(), [ref.msgs[k] for k in ref.order])
+    assert worst < 1e-12
+
+
+def test_hbm_budget_limits_device_memory():
+    """hbm_budget: a context held to 64 KiB cannot set its tensors (BBP_ENOMEM
+    after freeing its kept buffers once); with the limit lifted the same
+    context works, and a budget above its need changes nothing."""
+    bbp = _lib()
+    A = peps_finite(8, 8, 2, seed=2)
+    g = bbp.BlockBP(Lx=8, Ly=8, bx=4, by=4, D=2, chi=8, hbm_budget=1 << 16)
+    with pytest.raises(bbp.BBPError) as ei:
+        g.set_tensors(A)
+        g.sweep(2)
+    assert ei.value.status == 2
+    g.set_option("hbm_budget", 0)
+    g.set_tensors(A)
+    r = g.sweep(3)
+    ref = bbp.BlockBP(Lx=8, Ly=8, bx=4, by=4, D=2, chi=8, hbm_budget=1 << 34)
+    ref.set_tensors(A)
+    assert r == ref.sweep(3)
+    now, peak = ref.memory()
+    print(f"budget test: peak {peak} bytes", flush=True)
+    assert peak <= 1 << 34

@@ -116,6 +116,34 @@ def test_p1b_tree_block_graph_is_exact(Lx, Ly, bx, by, chi, chi_env, sweeps):
     assert err < TOL and lerr < TOL and sign == 1.0
 
 
+@pytest.mark.parametrize("Lx,Ly,bx,by,chi,chi_env,sweeps", [
+    (6, 2, 2, 2, 4, 18, 5),
+    (4, 3, 2, 3, 9, 36, 4),
+])
+def test_random_initial_messages_reach_the_exact_fixed_point(Lx, Ly, bx, by, chi,
+                                                            chi_env, sweeps):
+    """The random product MPDO start (init 1, App. A): every initial site is
+    positive semidefinite with unit norm, the start differs from the
+    identity one, and on a tree block graph the sweeps still reach the
+    exact contraction (BP's fixed point on a tree does not depend on the
+    start)."""
+    A = peps_finite(Lx, Ly, 2, seed=1)
+    bp = ob.BlockBP(A, D=2, chi=chi, bx=bx, by=by, Lx=Lx, Ly=Ly,
+                    chi_env=chi_env, init=1, seed=7)
+    ident = ob.identity_mps(by, 2)
+    for key, m in bp.msgs.items():
+        for t in m:
+            M = t.reshape(2, 2)
+            assert abs(np.linalg.norm(M) - 1.0) < 1e-14
+            assert np.allclose(M, M.T) and np.linalg.eigvalsh(M).min() > -1e-14
+        if key[2] in ("L", "R"):
+            assert not np.allclose(m[0], ident[0])
+    res = bp.sweep(sweeps)
+    assert res < 1e-13
+    err, lerr, sign = _psi_checks(A, Lx, Ly, bp)
+    assert err < TOL and lerr < TOL and sign == 1.0
+
+
 def test_p1b_large_blocks_strip():
     A = peps_finite(8, 4, 2, seed=2)
     bp = ob.BlockBP(A, D=2, chi=16, bx=4, by=4, Lx=8, Ly=4, chi_env=64)
