@@ -187,6 +187,10 @@ bbp_status bbp_get_tensors(bbp_ctx *c, double *A, size_t n);
  * *residual (may be NULL) receives the last sweep's residual: the mean over
  * directed messages of max(0, 2 - 2|<m_new, m_old>|) for unit-norm messages
  * (the squared sign-aligned distance; App. A's mean-square error).
+ * With the environment variable BBP_SWEEP_LOG naming a file, every sweep
+ * appends one JSON line to it: {"ctx", "sweep" (counted from the last
+ * bbp_set_tensors), "residual", "ms" (host wall time of the sweep),
+ * "fit_flops" (counted on the split-layer schedule), "messages"}.
  * Errors: BBP_ESTATE before bbp_set_tensors, BBP_ENUMERIC for a zero-norm
  * or non-finite message (messages then stay at their previous values).
  */

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -232,6 +234,7 @@ struct bbp_ctx {
   DevBuf rot;                   // engine mode: rotated block tensors of every message
   std::vector<size_t> rot_off;  // doubles from rot's start to message i's block
   uint64_t serial = 0; // unique per context of the process (identifies it across sweeps)
+  int64_t sweeps_done = 0;  // sweeps since the tensors were set
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
@@ -2445,7 +2448,25 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "set_tensors");
   c->tensors_set = true;
+  c->sweeps_done = 0;
   return BBP_OK;
+}
+
+// One JSON line per sweep, appended to the file the environment variable
+// BBP_SWEEP_LOG names (nothing when it is unset or empty).
+static void log_sweep(const bbp_ctx *c, double r, double ms) {
+  const char *path = std::getenv("BBP_SWEEP_LOG");
+  if (!path || !*path) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"ctx\": %llu, \"sweep\": %lld, \"residual\": %.17g, \"ms\": %.6f, "
+               "\"fit_flops\": %.17g, \"messages\": %zu}\n",
+               (unsigned long long)c->serial, (long long)c->sweeps_done, r, ms, c->last_flops,
+               c->msgs.size());
+  std::fclose(f);
 }
 
 bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual) {
@@ -2456,8 +2477,12 @@ bbp_status bbp_sweep(bbp_ctx *c, int32_t n, double *residual) {
   if (n < 0) return c->fail(BBP_EINVAL, "negative sweep count");
   double r = 0.0;
   for (int i = 0; i < n; ++i) {
+    const auto t0 = std::chrono::steady_clock::now();
     bbp_status s = run_sweep(c, &r);
     if (s != BBP_OK) return s;
+    ++c->sweeps_done;
+    log_sweep(c, r, std::chrono::duration<double, std::milli>(
+                        std::chrono::steady_clock::now() - t0).count());
   }
   if (residual) *residual = r;
   return BBP_OK;

@@ -135,3 +135,22 @@ def test_hbm_budget_limits_device_memory():
     now, peak = ref.memory()
     print(f"budget test: peak {peak} bytes", flush=True)
     assert peak <= 1 << 34
+
+
+def test_sweep_log_lines(tmp_path, monkeypatch):
+    """BBP_SWEEP_LOG: one JSON line per sweep with the residual bbp_sweep
+    returned, counted from the last set_tensors."""
+    import json
+    bbp = _lib()
+    path = tmp_path / "sweeps.jsonl"
+    monkeypatch.setenv("BBP_SWEEP_LOG", str(path))
+    A = peps_finite(6, 6, 2, seed=2)
+    g = bbp.BlockBP(Lx=6, Ly=6, bx=2, by=2, D=2, chi=4)
+    g.set_tensors(A)
+    res = [g.sweep(1) for _ in range(3)]
+    monkeypatch.delenv("BBP_SWEEP_LOG")
+    g.sweep(1)
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert [ln["sweep"] for ln in lines] == [1, 2, 3]
+    assert [ln["residual"] for ln in lines] == res
+    assert all(ln["messages"] == 24 and ln["fit_flops"] > 0 and ln["ms"] > 0 for ln in lines)
