@@ -86,7 +86,10 @@ def observables(ctx, cfg, sites, bonds):
     return sz, ctx.expect_bonds(bonds, op_heis())
 
 
-def solve(ctx, cfg, A, sweeps, sites, bonds, times=None):
+def solve(ctx, cfg, A, sweeps, sites, bonds, times=None, phase_ms=None):
+    """One solve; with ``phase_ms`` (a dict, timing on) the event-timed
+    kernel milliseconds of its sweeps and of its observables are added to
+    ``phase_ms["sweeps"]`` and ``phase_ms["observables"]`` per class."""
     t0 = time.perf_counter()
     ctx.set_tensors(A)
     sync()
@@ -102,10 +105,20 @@ def solve(ctx, cfg, A, sweeps, sites, bonds, times=None):
             log(f"    {done}/{sweeps} sweeps")
     sync()
     t2 = time.perf_counter()
+    if phase_ms is not None:
+        mid = {k["name"]: k["ms"] for k in ctx.kernel_stats()}
     sz, ss = observables(ctx, cfg, sites, bonds)
     ln = ctx.log_norm()
     sync()
     t3 = time.perf_counter()
+    if phase_ms is not None:
+        end = {k["name"]: k["ms"] for k in ctx.kernel_stats()}
+        for name, ms in mid.items():
+            sw = phase_ms.setdefault("sweeps", {})
+            ob = phase_ms.setdefault("observables", {})
+            sw[name] = sw.get(name, 0.0) + ms - phase_ms.get("_last", {}).get(name, 0.0)
+            ob[name] = ob.get(name, 0.0) + end[name] - ms
+        phase_ms["_last"] = end
     if times is not None:
         times.append((t1 - t0, t2 - t1, t3 - t2))
     return res, sz, ss, ln
@@ -734,6 +747,7 @@ def main():
     # stream runs them, so that no two kernels overlap (the bracket of a kernel
     # that shares the GPU with another lane's would include the other's time)
     stats, timed_total = None, None
+    phase_kernels = {}
     if not args.no_kernel_pass:
         log("event-timed pass")
         ctx1 = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
@@ -742,7 +756,7 @@ def main():
         sync()
         ti0 = time.perf_counter()
         for k in range(args.steps):
-            solve(ctx1, cfg, A, sweeps, sites, bonds)
+            solve(ctx1, cfg, A, sweeps, sites, bonds, phase_ms=phase_kernels)
         sync()
         timed_total = time.perf_counter() - ti0
         stats = ctx1.kernel_stats()
@@ -788,6 +802,9 @@ def main():
             s["name"]: dict(launches=s["launches"], ms=s["ms"],
                             tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
             for s in stats},
+        kernel_ms_per_solve_by_phase=None if stats is None else {
+            ph: {n: v / args.steps for n, v in d.items() if v > 0}
+            for ph, d in phase_kernels.items() if not ph.startswith("_")},
         cpu_baseline=None,
     )
     # the precision pattern (FP32 contractions in the fused visits)
