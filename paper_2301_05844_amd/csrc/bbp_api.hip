@@ -1452,7 +1452,9 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, sb);
       if (e != hipSuccess) return c->hip_fail(e, "region setup");
       if (f.W > 1) {
-        bbp_status bs = absorb_columns(c, g, 1, sb);
+        // with kept stacks only the columns the lines need now: later calls
+        // extend a kept stack in place
+        bbp_status bs = absorb_columns(c, g, reuse ? std::max(1, need_lo[g.ids[0]]) : 1, sb);
         if (bs != BBP_OK) return bs;
       }
     }
@@ -1493,11 +1495,15 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       if (reused[sidx]) continue;
       const RegionSpec &R = regs[stacks[sidx].region];
       const StackRef &w = where[sidx];
-      c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient)] =
-          bbp_ctx::KeptStack{w.g, w.item, rot[sidx],
+      bbp_ctx::KeptStack &k =
+          c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient)];
+      k = bbp_ctx::KeptStack{w.g, w.item, rot[sidx],
                              std::vector<double>(w.nu, w.nu + w.g->fb.W)};
-      where[sidx].nu = c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj,
-                                                      stacks[sidx].orient)].nu.data();
+      const StackItem &it = stacks[sidx];
+      for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed
+        for (int xc = 0; xc < need_lo[sidx]; ++xc)
+          std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
+      where[sidx].nu = k.nu.data();
     }
     for (auto &gp : sg) c->kept_groups.push_back(std::move(gp));
     sg.clear();
