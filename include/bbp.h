@@ -339,6 +339,9 @@ void bbp_destroy(bbp_ctx *c);
  * one batched contraction, their fits on host threads; the result is that
  * of the sequential order.
  *
+ * The environment contractions run on a second context that the call
+ * creates and destroys, on the context's stream, with the context's
+ * allocator and a device budget equal to its "hbm_budget" (if set).
  * n_als: alternating least-squares passes per gate (1..64).  info (host,
  * optional, 5 doubles): the number of gates applied, the sum over the
  * gates of the relative fit error in the metric of N, the seconds spent in

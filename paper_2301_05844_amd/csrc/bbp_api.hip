@@ -3427,7 +3427,7 @@ bbp_status ctx_info(bbp_ctx *c, CtxInfo *o) {
   if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
   *o = CtxInfo{c->infinite, c->Lx, c->Ly, c->bx, c->by, c->D, c->chi, c->d,
                c->chi_env, c->n_fit, c->sx, c->sy, c->single_layer, c->seed,
-               c->stream};
+               c->stream, c->mem.alloc_fn, c->mem.free_fn, c->mem.user, c->mem.budget};
   return BBP_OK;
 }
 

@@ -240,6 +240,10 @@ struct CtxInfo {
   int infinite, Lx, Ly, bx, by, D, chi, d, chi_env, n_fit, sx, sy, single_layer;
   uint64_t seed;
   hipStream_t stream;
+  bbp_alloc_fn alloc_fn;  // the caller's allocator (null: hipMalloc)
+  bbp_free_fn free_fn;
+  void *alloc_user;
+  size_t hbm_budget;  // 0: no limit
 };
 bbp_status ctx_info(bbp_ctx *c, CtxInfo *out);
 bbp_status ctx_fail(bbp_ctx *c, bbp_status s, const std::string &m);

@@ -550,6 +550,14 @@ extern "C" bbp_status bbp_ite_step(bbp_ctx *c, const double *gate, int32_t n_als
       return bbp::ctx_fail(c, st, std::string("environment option ") + o.first + ": " +
                                       bbp_last_error(e));
   (void)bbp_set_stream(e, ci.stream);
+  // device memory as the caller's context obtains it: its allocator, and a
+  // budget of its own equal to the context's
+  if (ci.alloc_fn &&
+      (st = bbp_set_allocator(e, ci.alloc_fn, ci.free_fn, ci.alloc_user)) != BBP_OK)
+    return bbp::ctx_fail(c, st, std::string("environment allocator: ") + bbp_last_error(e));
+  if (ci.hbm_budget &&
+      (st = bbp_set_option(e, "hbm_budget", (double)ci.hbm_budget)) != BBP_OK)
+    return bbp::ctx_fail(c, st, std::string("environment budget: ") + bbp_last_error(e));
   // gate order: horizontal bonds row by row, then vertical bonds column by column
   std::vector<Gate> gl;
   for (int y = 0; y < Ly; ++y)

@@ -152,3 +152,32 @@ def test_ite_step_validation():
     big.set_tensors(peps_finite(4, 4, 5, seed=1))
     with pytest.raises(bbp.BBPError):
         big.ite_step(G)                      # min(D^3, d D) = 10 > 8
+
+
+def test_ite_step_through_the_torch_allocator():
+    """The environment contractions allocate through the context's allocator
+    (PyTorch's caching allocator here) and the step's result is bitwise the
+    hipMalloc context's; a context held to a device budget too small for the
+    environment fails with BBP_ENOMEM and keeps its tensors."""
+    import torch
+    from paper_2301_05844_amd import bbp
+    G = expm(-0.1 * _ti(3.0))
+    A0 = peps_finite(4, 4, 2, seed=11)
+    out = []
+    for alloc in (None, bbp.torch_allocator()):
+        kw = {} if alloc is None else dict(allocator=alloc)
+        ctx = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=8, chi_env=16, **kw)
+        ctx.set_tensors(A0)
+        ctx.sweep(4)
+        ctx.ite_step(G, n_als=3)
+        out.append(ctx.get_tensors())
+        torch.cuda.synchronize()
+    assert np.array_equal(out[0], out[1])
+    ctx = bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=8, chi_env=16)
+    ctx.set_tensors(A0)
+    ctx.sweep(4)
+    ctx.set_option("hbm_budget", 1 << 16)  # 64 KiB: nothing left for the environment
+    with pytest.raises(bbp.BBPError) as ei:
+        ctx.ite_step(G, n_als=3)
+    assert ei.value.status == 2
+    assert np.array_equal(ctx.get_tensors(), A0)
