@@ -1082,32 +1082,42 @@ static bbp_status run_sweep(bbp_ctx *c, double *residual) {
   std::vector<double> ov(nm, 0.0);
   std::map<int, std::vector<int>> by_len;
   for (int i = 0; i < nm; ++i) by_len[c->msgs[i].n].push_back(i);
+  // every length group's overlaps go to their own part of the output, read
+  // back with the error flag after one synchronisation (the groups share the
+  // overlap kernel's scratch, in stream order)
+  std::vector<const double *> pa(nm), pb(nm);
+  std::vector<double> out(nm, 0.0);
+  int off = 0;
   for (auto &kv : by_len) {
     const std::vector<int> &ids = kv.second;
-    std::vector<const double *> pa(ids.size()), pb(ids.size());
     for (size_t i = 0; i < ids.size(); ++i) {
-      pa[i] = nb + (size_t)ids[i] * per;
-      pb[i] = cur + (size_t)ids[i] * per;
+      pa[off + i] = nb + (size_t)ids[i] * per;
+      pb[off + i] = cur + (size_t)ids[i] * per;
     }
-    e = hipMemcpyAsync(c->ovA.p, pa.data(), 8 * ids.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(c->ovB.p, pb.data(), 8 * ids.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = launch_overlap((int)ids.size(), c->K, c->P, kv.first,
-                         (const double *const *)c->ovA.p,
-                         (const double *const *)c->ovB.p, c->ovE.d(),
-                         c->ovU.d(), c->ovOut.d(), st);
-    std::vector<double> part(ids.size());
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(part.data(), c->ovOut.p, 8 * ids.size(),
-                         hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return c->hip_fail(e, "overlap");
-    for (size_t i = 0; i < ids.size(); ++i) ov[ids[i]] = part[i];
+    off += (int)ids.size();
+  }
+  e = hipMemcpyAsync(c->ovA.p, pa.data(), 8 * (size_t)nm, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ovB.p, pb.data(), 8 * (size_t)nm, hipMemcpyHostToDevice, st);
+  off = 0;
+  for (auto &kv : by_len) {
+    if (e != hipSuccess) break;
+    const int n = (int)kv.second.size();
+    e = launch_overlap(n, c->K, c->P, kv.first, (const double *const *)c->ovA.p + off,
+                       (const double *const *)c->ovB.p + off, c->ovE.d(), c->ovU.d(),
+                       c->ovOut.d() + off, st);
+    off += n;
   }
   int32_t errv = 0;
-  e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return c->hip_fail(e, "error flag");
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out.data(), c->ovOut.p, 8 * (size_t)nm, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&errv, c->errflag.p, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return c->hip_fail(e, "overlap");
+  off = 0;
+  for (auto &kv : by_len)
+    for (int id : kv.second) ov[id] = out[off++];
   double sum = 0.0;
   bool finite = true;
   for (int i = 0; i < nm; ++i) {
