@@ -177,9 +177,9 @@ bool solve_normal(Mat M, int n, std::vector<double> &y) {
   return true;
 }
 
-// Index of a site tensor entry [s][u][l][d][r] with dimensions (dd, D).
-inline size_t aidx5(int D, int s, const int leg[5]) {
-  (void)s;
+// Offset of the site tensor entry leg = (s, u, l, d, r), every virtual leg
+// of dimension D (the physical index leg[0] is the slowest).
+inline size_t aidx5(int D, const int leg[5]) {
   return ((((size_t)leg[0] * D + leg[1]) * D + leg[2]) * D + leg[3]) * D + leg[4];
 }
 
@@ -403,7 +403,7 @@ void split_gate(Gate &g, const double *A, int d, int D, int Lx, int Ly) {
       for (leg[2] = 0; leg[2] < D; ++leg[2])
         for (leg[3] = 0; leg[3] < D; ++leg[3])
           for (leg[4] = 0; leg[4] < D; ++leg[4]) {
-            const size_t src = aidx5(D, 0, leg);
+            const size_t src = aidx5(D, leg);
             if (leg[1] < g.da[1] && leg[2] < g.da[2] && leg[3] < g.da[3] && leg[4] < g.da[4])
               Ma[row_of(leg, g.oa, g.da) * d * D + (size_t)leg[0] * D + leg[g.sa]] = Aa[src];
             if (leg[1] < g.db[1] && leg[2] < g.db[2] && leg[3] < g.db[3] && leg[4] < g.db[4])
@@ -427,7 +427,7 @@ void place_isometries(const Gate &g, double *M, size_t sp, int D) {
       lg[g.oa[0]] = r / (g.da[g.oa[1]] * g.da[g.oa[2]]);
       lg[g.oa[1]] = r / g.da[g.oa[2]] % g.da[g.oa[1]];
       lg[g.oa[2]] = r % g.da[g.oa[2]];
-      M[g.ia * sp + (size_t)q * D4 + aidx5(D, 0, lg)] = g.Xa[(size_t)r * g.k + q];
+      M[g.ia * sp + (size_t)q * D4 + aidx5(D, lg)] = g.Xa[(size_t)r * g.k + q];
     }
   for (int q = 0; q < g.kb; ++q)
     for (int cc = 0; cc < g.cols_b; ++cc) {
@@ -435,7 +435,7 @@ void place_isometries(const Gate &g, double *M, size_t sp, int D) {
       lg[g.ob[0]] = cc / (g.db[g.ob[1]] * g.db[g.ob[2]]);
       lg[g.ob[1]] = cc / g.db[g.ob[2]] % g.db[g.ob[1]];
       lg[g.ob[2]] = cc % g.db[g.ob[2]];
-      M[g.ib * sp + (size_t)q * D4 + aidx5(D, 0, lg)] = g.Qt[(size_t)cc * g.kb + q];
+      M[g.ib * sp + (size_t)q * D4 + aidx5(D, lg)] = g.Qt[(size_t)cc * g.kb + q];
     }
 }
 
@@ -474,7 +474,7 @@ bool fit_gate(const Gate &g, const double *rho, int dp, const double *gate, int 
       for (leg[2] = 0; leg[2] < D; ++leg[2])
         for (leg[3] = 0; leg[3] < D; ++leg[3])
           for (leg[4] = 0; leg[4] < D; ++leg[4]) {
-            const size_t dst = aidx5(D, 0, leg);
+            const size_t dst = aidx5(D, leg);
             if (leg[1] < g.da[1] && leg[2] < g.da[2] && leg[3] < g.da[3] && leg[4] < g.da[4]) {
               const size_t ra = row_of(leg, g.oa, g.da);
               double v = 0.0;
