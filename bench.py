@@ -44,7 +44,7 @@ MAX_SWEEPS = 40
 SEARCH_MAX_SWEEPS = 80   # the sweep-count search (the D=6 lattice needs about 50)
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector and matrix)
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
-PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix (no BF16 stage is built)
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 RIDGE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fit_visit_obc16x16_D4_chi32.json")
@@ -345,28 +345,30 @@ def serve(args):
 
 
 def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
-    """The precision pattern on the same workload: sweeps with the fit
-    contractions on FP32 MFMA until the residual stops improving (or drops
-    below 1e-7), then FP64 sweeps to the tolerance, observables in FP64.
-    Reports the per-observable error against the all-FP64 solve."""
-    ctx.set_option("precision", 32)
-    ctx.set_tensors(A)
-    n32, res, prev = 0, 1.0, None
-    while n32 < SEARCH_MAX_SWEEPS:
-        res = ctx.sweep(1)
-        n32 += 1
-        if res < TOL or (prev is not None and res >= prev):
-            break   # converged, or at the FP32 floor (no longer falling)
-        prev = res
-        if n32 % 10 == 0:
-            log(f"  fp32 sweep {n32}: residual {res:.2e}")
+    """The precision pattern on the same workload, two protocols: FP32 sweeps
+    until the residual stops falling (or drops below the tolerance), then
+    FP64 sweeps to the tolerance; and BF16, then FP32, then FP64 the same
+    way.  Observables are computed in FP64.  Reports each stage's error
+    against a tightly converged FP64 solve, each protocol's time per solve
+    against the all-FP64 one, and each precision's sweep time and fit rate."""
+    err = lambda a, b: float(np.max(np.abs(np.array(a) - np.array(b))))
+
+    def observables():
+        ctx.set_option("precision", 64)
+        return (np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())),
+                np.array(ctx.expect_bonds(bonds, op_heis())))
+
+    # tightly converged FP64 reference: how close each stage is to the fixed point
     ctx.set_option("precision", 64)
-    n64 = 0
-    while res >= TOL and n64 < SEARCH_MAX_SWEEPS:
-        res = ctx.sweep(1)
-        n64 += 1
-    log(f"mixed precision: {n32} FP32 sweeps, then {n64} FP64 sweeps to {res:.2e}")
-    times = []
+    ctx.set_tensors(A)
+    rt, nt = 1.0, 0
+    while rt >= 1e-14 and nt < SEARCH_MAX_SWEEPS:
+        rt = ctx.sweep(1)
+        nt += 1
+        if nt % 10 == 0:
+            log(f"  reference sweep {nt}: residual {rt:.2e}")
+    szt, sst = observables()
+
     def chunked(n):
         r, done = None, 0
         while done < n:
@@ -376,60 +378,77 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
             if n > 20:
                 log(f"    {done}/{n} sweeps")
         return r
-    for _ in range(steps):
-        sync()
-        t0 = time.perf_counter()
-        ctx.set_option("precision", 32)
+
+    def protocol(stages):
+        # search: the sweep count of each stage, and its error at the end
+        ctx.set_option("precision", stages[0])
         ctx.set_tensors(A)
-        chunked(n32)
-        ctx.set_option("precision", 64)
-        res = chunked(n64)
-        sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
-        ss = ctx.expect_bonds(bonds, op_heis())
-        ln = ctx.log_norm()
-        sync()
-        times.append(time.perf_counter() - t0)
-    ms = float(np.mean(times) * 1e3)
-    # tightly converged FP64 reference: how close each solve is to the fixed point
-    ctx.set_option("precision", 64)
-    ctx.set_tensors(A)
-    rt, nt = 1.0, 0
-    while rt >= 1e-14 and nt < SEARCH_MAX_SWEEPS:
-        rt = ctx.sweep(1)
-        nt += 1
-        if nt % 10 == 0:
-            log(f"  reference sweep {nt}: residual {rt:.2e}")
-    szt = np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz()))
-    sst = np.array(ctx.expect_bonds(bonds, op_heis()))
-    err = lambda a, b: float(np.max(np.abs(np.array(a) - b)))
-    acc = dict(reference=f"FP64, {nt} sweeps to residual {rt:.1e}",
-               fp64_err_sz=err(ref[1], szt), fp64_err_ss=err(ref[2], sst),
-               mixed_err_sz=err(sz, szt), mixed_err_ss=err(ss, sst))
+        counts, stage_err, res = [], {}, 1.0
+        for p in stages:
+            ctx.set_option("precision", p)
+            n, prev = 0, None
+            while n < SEARCH_MAX_SWEEPS:
+                res = ctx.sweep(1)
+                n += 1
+                if res < TOL or (p != 64 and prev is not None and res >= prev):
+                    break   # converged, or at this precision's floor
+                prev = res
+                if n % 10 == 0:
+                    log(f"  precision {p} sweep {n}: residual {res:.2e}")
+            counts.append(n)
+            sz, ss = observables()
+            stage_err[f"fp{p}" if p != 16 else "bf16"] = dict(
+                sweeps=n, residual=res, err_sz=err(sz, szt), err_ss=err(ss, sst))
+        name = ">".join("bf16" if p == 16 else f"fp{p}" for p in stages)
+        log(f"{name}: sweeps {counts}, residual {res:.2e}")
+        times = []
+        for _ in range(steps):
+            sync()
+            t0 = time.perf_counter()
+            ctx.set_option("precision", stages[0])
+            ctx.set_tensors(A)
+            for p, n in zip(stages, counts):
+                ctx.set_option("precision", p)
+                res = chunked(n)
+            sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
+            ss = ctx.expect_bonds(bonds, op_heis())
+            ln = ctx.log_norm()
+            sync()
+            times.append(time.perf_counter() - t0)
+        ms = float(np.mean(times) * 1e3)
+        return dict(stages=stage_err, residual=res, ms_per_solve=ms,
+                    speedup_vs_fp64=fp64_ms / ms,
+                    max_abs_diff_sz_vs_fp64=err(sz, ref[1]),
+                    max_abs_diff_ss_vs_fp64=err(ss, ref[2]),
+                    abs_err_log_norm=float(abs(ln[0] - ref[3][0])),
+                    err_sz_vs_converged=err(sz, szt), err_ss_vs_converged=err(ss, sst))
+
+    protocols = {"fp32>fp64": protocol((32, 64)), "bf16>fp32>fp64": protocol((16, 32, 64))}
     per = {}
-    for prec in (32, 64):   # time per sweep in each precision, same state
+    names = {16: "bf16", 32: "fp32", 64: "fp64"}
+    peaks = {16: PEAK_BF16_TFLOPS, 32: PEAK_FP32_TFLOPS, 64: PEAK_FP64_TFLOPS}
+    for prec in (16, 32, 64):   # time per sweep in each precision, same state
         ctx.set_option("precision", prec)
         sync()
         t0 = time.perf_counter()
         ctx.sweep(2)
         sync()
-        per[f"fp{prec}_ms_per_sweep"] = (time.perf_counter() - t0) / 2 * 1e3
+        ms = (time.perf_counter() - t0) / 2 * 1e3
         _, fl = ctx.stats()   # fit FLOPs of the last sweep, true bonds
-        per[f"fp{prec}_fit_tflops"] = fl / (per[f"fp{prec}_ms_per_sweep"] * 1e-3) / 1e12
+        tf = fl / (ms * 1e-3) / 1e12
+        per[names[prec]] = dict(ms_per_sweep=ms, fit_tflops=tf, frac_of_peak=tf / peaks[prec])
     ctx.set_option("precision", 64)
-    per["peaks_tflops"] = dict(fp64=PEAK_FP64_TFLOPS, fp32=PEAK_FP32_TFLOPS,
-                               bf16=PEAK_BF16_TFLOPS)
-    per["fp32_frac_of_fp32_peak"] = per["fp32_fit_tflops"] / PEAK_FP32_TFLOPS
-    per["fp64_frac_of_fp64_peak"] = per["fp64_fit_tflops"] / PEAK_FP64_TFLOPS
-    return dict(fp32_sweeps=n32, fp64_sweeps=n64, residual=res, ms_per_solve=ms, **per,
-                accuracy_vs_converged=acc,
-                speedup_vs_fp64=fp64_ms / ms,
-                max_abs_diff_sz_vs_fp64=float(np.max(np.abs(np.array(sz) - np.array(ref[1])))),
-                max_abs_diff_ss_vs_fp64=float(np.max(np.abs(np.array(ss) - np.array(ref[2])))),
-                abs_err_log_norm=float(abs(ln[0] - ref[3][0])),
-                note="FP32 visit and environment contractions (FP32 accumulation) until the "
-                     "residual stops falling, then FP64 sweeps to the tolerance; QR, "
-                     "normalisation and messages FP64; no BF16 stage; errors against the "
-                     "all-FP64 solve and against a tightly converged FP64 reference")
+    return dict(protocols=protocols, per_precision=per,
+                peaks_tflops=dict(fp64=PEAK_FP64_TFLOPS, fp32=PEAK_FP32_TFLOPS,
+                                  bf16=PEAK_BF16_TFLOPS),
+                reference=f"FP64, {nt} sweeps to residual {rt:.1e}",
+                fp64_err_sz=err(ref[1], szt), fp64_err_ss=err(ref[2], sst),
+                note="each stage until the residual stops falling, the last (FP64) to the "
+                     "tolerance; BF16 and FP32 stages run the fused visit and environment "
+                     "contractions on BF16 / FP32 MFMA with FP32 accumulation (the BF16 "
+                     "stage in the generic fused visit); QR, normalisation and messages "
+                     "FP64; observables FP64; errors against the all-FP64 solve and "
+                     "against a tightly converged FP64 reference")
 
 
 def cpu_baseline(cfg, A):
@@ -807,7 +826,7 @@ def main():
             for ph, d in phase_kernels.items() if not ph.startswith("_")},
         cpu_baseline=None,
     )
-    # the precision pattern (FP32 contractions in the fused visits)
+    # the precision pattern (BF16 / FP32 contractions in the fused visits)
     if not args.no_mixed and "tol" in cfg and not cfg["infinite"]:
         line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
                                                   line["ms_per_step"])

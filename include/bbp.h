@@ -87,14 +87,17 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              out-of-memory one (the kept buffers are freed and it is tried
  *              once more, then BBP_ENOMEM; the context stays usable)
  *   "timing"   1: record per-kernel-class launch times (any time; resets)
- *   "precision" 64 (default) or 32 (any time): with 32 the fit's visit and
- *              environment contractions run on FP32 MFMA with FP32
- *              accumulation in every fused visit (any D, bond cap <= 64);
- *              fits whose visits run as separate kernels (bond caps above
- *              64, e.g. the observables at a chi_env above 64) stay FP64;
- *              QR, normalisation, overlaps and every stored message stay
- *              FP64.  Sweeps in 32 followed by sweeps in 64 reach the FP64
- *              fixed point from the FP32 one.
+ *   "precision" 64 (default), 32 or 16 (any time): with 32 the fit's
+ *              visit and environment contractions run on FP32 MFMA with
+ *              FP32 accumulation in every fused visit (any D, bond cap
+ *              <= 64); with 16 they run on BF16 MFMA (operands rounded to
+ *              BF16, FP32 accumulation) in the generic fused visit (any D,
+ *              bond cap <= 64; at D=4 that visit is slower than the
+ *              specialised FP32 one); fits whose visits run as separate
+ *              kernels (bond caps above 64, e.g. the observables at a
+ *              chi_env above 64) stay FP64; QR, normalisation, overlaps and
+ *              every stored message stay FP64.  Sweeps in 16, then 32, then
+ *              64 reach the FP64 fixed point from the lower-precision ones.
  *   "graphs"   1 (default) or 0 (any time): once a message batch's column
  *              absorptions all start warm (from the second sweep on), their
  *              launches are captured as a HIP graph and replayed in later

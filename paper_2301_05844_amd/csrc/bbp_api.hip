@@ -222,7 +222,7 @@ struct bbp_ctx {
   int sx = 0, sy = 0;  // partition shift: trivial columns left, rows on top
   int gx = 1, gy = 1;
   int chi_env = -1, n_fit = 2;
-  int precision = 64;  // 64, or 32: fit contractions on FP32 MFMA
+  int precision = 64;  // 64; 32: fit contractions on FP32 MFMA; 16: on BF16 MFMA
   int lanes = 3;       // streams that independent fit batches spread over
   int graphs = 1;      // 1: message batches replay their column absorptions as HIP graphs
   int skip_pad = 1;    // 1: the column absorptions' kernels stop at the true bond extents
@@ -2253,7 +2253,8 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     bbp::timing_enable(v != 0.0);
     bbp::timing_reset();
   } else if (k == "precision") {
-    if (v != 64 && v != 32) return c->fail(BBP_EINVAL, "precision must be 64 or 32");
+    if (v != 64 && v != 32 && v != 16)
+      return c->fail(BBP_EINVAL, "precision must be 64, 32 or 16");
     c->precision = (int)v;
     for (auto &g : c->groups) g->fb.prec = c->precision;
     c->obs.clear();

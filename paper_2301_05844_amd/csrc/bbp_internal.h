@@ -84,7 +84,7 @@ struct FitBatch {
   int bounded = 0;
   uint64_t *slot = nullptr; // [items] random-state slot base
   uint64_t seed = 0;
-  int prec = 64;  // 64: FP64 contractions; 32: visit and environment update on FP32 MFMA
+  int prec = 64;  // 64: FP64 contractions; 32 (16): visit and environment update on FP32 (BF16) MFMA
 };
 
 // Visit kinds of the fit engine.

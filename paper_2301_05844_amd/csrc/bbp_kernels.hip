@@ -240,6 +240,25 @@ template <> struct Mma<float> {
   static __host__ __device__ constexpr int pad_a_min(int x) { return x + (12 - x % 8) % 8; }
 };
 
+// BF16 contraction step (the precision option's lowest stage): FP32 operands
+// rounded to BF16 (nearest even), BF16 MFMA 16x16x16 with FP32 accumulation.
+// Each lane supplies four k values of its A row and B column; the product
+// sums over the 16 (lane group, slot) pairs, so any assignment of k values
+// to slots is valid as long as A and B use the same one.  The accumulator
+// layout is that of the FP32 MFMA (Mma<float>::crow).
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4f mfma_bf16(const float *a, const float *b, v4f c) {
+  v4bf x, y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[j] = (__bf16)a[j];
+    y[j] = (__bf16)b[j];
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, x),
+                                                   __builtin_bit_cast(v4s, y), c, 0, 0, 0);
+}
+
 template <int BM, int BN, int BK, class Op>
 __global__ __launch_bounds__(kThreads) void k_gemm(Op op) {
   const int it = blockIdx.z;
@@ -504,7 +523,9 @@ template <int MT> struct EnvShape {
   static constexpr int kWaves = KS == 2 ? 4 : 2;  // waves per SIMD the registers allow
 };
 
-template <int MT, class T>
+// B16 (T = float): BF16 MFMA, the eight T3 rows a lane holds per chunk
+// feeding two 16-deep steps (rows 4i + lq, i = 0-3 and 4-7).
+template <int MT, class T, bool B16 = false>
 __global__ __launch_bounds__(EnvShape<MT>::kThreads)
 __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e) {
   typedef Mma<T> M;
@@ -614,7 +635,20 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   // refill those rows DB chunks ahead and stage the next Y chunk
   auto step = [&](int k0, T (&b)[8], unsigned &bm) {
     if (k0 + CH < Kd) fetch_a(k0 + CH);
-    if constexpr (DB == 1) {  // copy out, then refill the same registers
+    if constexpr (B16) {  // copy out, refill, then two BF16 steps per row tile
+      float bc[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) bc[i] = ((bm >> i) & 1) ? (float)b[i] : 0.f;
+      if (k0 + DB * CH < Kd) fetch_b(k0 + DB * CH, b, bm);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        float a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = As[buf][h * 32 + 4 * i + lq][mt * 16 + lr];
+        acc[mt][0] = mfma_bf16(a, bc, acc[mt][0]);
+        acc[mt][NC - 1] = mfma_bf16(a + 4, bc + 4, acc[mt][NC - 1]);
+      }
+    } else if constexpr (DB == 1) {  // copy out, then refill the same registers
       T bc[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) bc[i] = ((bm >> i) & 1) ? b[i] : (T)0;
@@ -837,8 +871,10 @@ constexpr int kVisitWaves = kVisitThreads / 64;
 // there are enough; each tile keeps two accumulators (even and odd k-steps)
 // and its operands are read two k-steps ahead of the MFMAs.  afn/bfn read
 // operands (zero outside), sfn stores the result tile element.  T: FP64, or
-// FP32 on FP32 MFMA with FP32 accumulation.
-template <class T, class AF, class BF, class SF>
+// FP32 on FP32 MFMA with FP32 accumulation; B16 (T = float): BF16 MFMA, 32
+// k per step, lane slot s holding k = k0 + 4s + lq (slots 0-3 and 4-7 feed
+// the two accumulators).
+template <class T, bool B16 = false, class AF, class BF, class SF>
 __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
                                          BF bfn, SF sfn) {
   typedef Mma<T> MM;
@@ -860,21 +896,44 @@ __device__ __forceinline__ void lds_gemm(int nb, int M, int N, int Kd, AF afn,
     }
     const bool two = t0 + kVisitWaves < ntiles;
     Acc acc[2][2] = {{zero, zero}, {zero, zero}};
-    for (int k0 = 0; k0 < Kd; k0 += 8) {
-      T av[2][2], bv[2][2];
+    if constexpr (B16) {
+      static_assert(sizeof(T) == 4, "BF16 steps stage FP32 operands");
+      for (int k0 = 0; k0 < Kd; k0 += 32) {
+        float av[2][8], bv[2][8];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int k = k0 + 4 * s + lq, am = m0[h] + lr, bn = n0[h] + lr;
+            const bool on = h == 0 || two;
+            av[h][s] = (on && am < M && k < Kd) ? (float)afn(p[h], am, k) : 0.f;
+            bv[h][s] = (on && bn < N && k < Kd) ? (float)bfn(p[h], k, bn) : 0.f;
+          }
+        const bool hi = k0 + 16 < Kd;  // slots 4-7 hold k0 + 16 .. k0 + 31
+        acc[0][0] = mfma_bf16(av[0], bv[0], acc[0][0]);
+        if (hi) acc[0][1] = mfma_bf16(av[0] + 4, bv[0] + 4, acc[0][1]);
+        if (two) {
+          acc[1][0] = mfma_bf16(av[1], bv[1], acc[1][0]);
+          if (hi) acc[1][1] = mfma_bf16(av[1] + 4, bv[1] + 4, acc[1][1]);
+        }
+      }
+    } else {
+      for (int k0 = 0; k0 < Kd; k0 += 8) {
+        T av[2][2], bv[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int k = k0 + 4 * u + lq, am = m0[h] + lr, bn = n0[h] + lr;
+            const bool on = h == 0 || two;
+            av[h][u] = (on && am < M && k < Kd) ? afn(p[h], am, k) : (T)0;
+            bv[h][u] = (on && bn < N && k < Kd) ? bfn(p[h], k, bn) : (T)0;
+          }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int k = k0 + 4 * u + lq, am = m0[h] + lr, bn = n0[h] + lr;
-          const bool on = h == 0 || two;
-          av[h][u] = (on && am < M && k < Kd) ? afn(p[h], am, k) : (T)0;
-          bv[h][u] = (on && bn < N && k < Kd) ? bfn(p[h], k, bn) : (T)0;
+          acc[0][u] = MM::run(av[0][u], bv[0][u], acc[0][u]);
+          if (two) acc[1][u] = MM::run(av[1][u], bv[1][u], acc[1][u]);
         }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        acc[0][u] = MM::run(av[0][u], bv[0][u], acc[0][u]);
-        if (two) acc[1][u] = MM::run(av[1][u], bv[1][u], acc[1][u]);
       }
     }
 #pragma unroll
@@ -899,6 +958,7 @@ __host__ __device__ inline size_t visit_lds(int K, int P, int d, int TY, int TX)
 }
 
 // DT > 0 fixes D (and P = D^2) at compile time; DT = 0 reads them at run time.
+// B16 (T = float): every contraction on BF16 MFMA with FP32 accumulation.
 // LDS layouts (index order, fastest last):
 //   Fs [ty, wf][xf]          stride pad_a(K)
 //   Xs [xf][a, tx]           stride pad_b(P TX)
@@ -907,7 +967,7 @@ __host__ __device__ inline size_t visit_lds(int K, int P, int d, int TY, int TX)
 //   T3s[pair][wbk, wbb][lk, lb]
 //   Gs [tx, wb][yb]          stride pad_b(K)
 //   Ak, Ab [s][wf][a][l][wb] of the front view (ket and bra roles alike)
-template <int DT, class T>
+template <int DT, class T, bool B16 = false>
 __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
   extern __shared__ double sm_raw[];
   T *sm = reinterpret_cast<T *>(sm_raw);
@@ -1002,7 +1062,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
       }
     __syncthreads();
     // (a) T1: rows (ty, wf), cols (a, tx), stored [pair][wfk, akx][wfb, abx]
-    lds_gemm<T>(
+    lds_gemm<T, B16>(
         1, TY * P, P * TX, K,
         [&](int, int m, int k) { return Fs[m * FS + k]; },
         [&](int, int k, int n) { return Xs[k * XS + n]; },
@@ -1013,7 +1073,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
         });
     __syncthreads();
     // (b) ket: per pair, rows m = (wfb, abx), k = (wfk, akx), cols n = (s, lk, wbk)
-    lds_gemm<T>(
+    lds_gemm<T, B16>(
         TY * TX, P, dP, P,
         [&](int p, int m, int k) { return T1s[p * P2 + k * P + m]; },
         [&](int, int k, int n) {
@@ -1024,7 +1084,7 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
     __syncthreads();
     // (c) bra: per pair, rows m = (lk, wbk), k = (s, wfb, abx), cols n = (lb, wbb);
     // stored as T3s[pair][wb][l]
-    lds_gemm<T>(
+    lds_gemm<T, B16>(
         TY * TX, P, P, dP,
         [&](int p, int m, int k) {
           const int s = k / P;
@@ -1062,17 +1122,32 @@ __global__ __launch_bounds__(kVisitThreads) void k_visit(VisitArgs v) {
         const int am = m0 + lr, bn = n0 + lr;
         const int ty = am / P, l = am - ty * P;
         Acc acc[2] = {accE[q], Acc{0, 0, 0, 0}};
-        for (int k0 = kb; k0 < ke; k0 += 8) {
-          T av[2], bv[2];
+        if constexpr (B16) {  // 32 k per step, slot s holding k0 + 4s + lq
+          for (int k0 = kb; k0 < ke; k0 += 32) {
+            float av[8], bv[8];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int k = k0 + 4 * u + lq;
-            const int tx = k / P, wb = k - tx * P;
-            av[u] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : (T)0;
-            bv[u] = (bn < K && k < ke) ? Gs[k * GS + bn] : (T)0;
+            for (int s = 0; s < 8; ++s) {
+              const int k = k0 + 4 * s + lq;
+              const int tx = k / P, wb = k - tx * P;
+              av[s] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : 0.f;
+              bv[s] = (bn < K && k < ke) ? Gs[k * GS + bn] : 0.f;
+            }
+            acc[0] = mfma_bf16(av, bv, acc[0]);
+            if (k0 + 16 < ke) acc[1] = mfma_bf16(av + 4, bv + 4, acc[1]);
           }
-          acc[0] = MM::run(av[0], bv[0], acc[0]);
-          acc[1] = MM::run(av[1], bv[1], acc[1]);
+        } else {
+          for (int k0 = kb; k0 < ke; k0 += 8) {
+            T av[2], bv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int k = k0 + 4 * u + lq;
+              const int tx = k / P, wb = k - tx * P;
+              av[u] = (am < Me && k < ke) ? T3s[(ty * TX + tx) * P2 + wb * P + l] : (T)0;
+              bv[u] = (bn < K && k < ke) ? Gs[k * GS + bn] : (T)0;
+            }
+            acc[0] = MM::run(av[0], bv[0], acc[0]);
+            acc[1] = MM::run(av[1], bv[1], acc[1]);
+          }
         }
         accE[q] = acc[0] + acc[1];
       }
@@ -2716,15 +2791,15 @@ static void visit_tiles(const FitBatch &f, int *TY, int *TX, size_t *bytes) {
 
 using VisitKernel = void (*)(VisitArgs);
 
-template <class T>
+template <class T, bool B16 = false>
 static VisitKernel visit_kernel(int D) {
   switch (D) {
-    case 2: return k_visit<2, T>;
-    case 3: return k_visit<3, T>;
-    case 4: return k_visit<4, T>;
-    case 5: return k_visit<5, T>;
-    case 6: return k_visit<6, T>;
-    default: return k_visit<0, T>;
+    case 2: return k_visit<2, T, B16>;
+    case 3: return k_visit<3, T, B16>;
+    case 4: return k_visit<4, T, B16>;
+    case 5: return k_visit<5, T, B16>;
+    case 6: return k_visit<6, T, B16>;
+    default: return k_visit<0, T, B16>;
   }
 }
 
@@ -2786,12 +2861,25 @@ static VisitKernel visit4p_kernel(int NE, int TY) {
   return k_visit4p<2, 2, T, 4>;
 }
 
-// FP32 contractions run where both the visit and the environment update have
-// an FP32 form (the specialised D = 4 kernels, K <= 64): T3 passes between
-// them in FP32.  Elsewhere the precision option leaves FP64 in place.
+// BF16 contractions (precision 16) run in the generic fused visit and the
+// environment update at bond caps <= 64, any D; T3 passes between them in
+// FP32.  Elsewhere precision 16 leaves FP64 in place.
+static bool visit_bf16(const FitBatch &f) {
+  int TY, TX;
+  size_t lds;
+  if (f.prec != 16 || f.K > 64) return false;
+  visit_tiles(f, &TY, &TX, &lds);
+  return TY > 0;
+}
+
+// FP32 T3 and environment update: the FP32 contractions (precision 32) run
+// where both the visit and the environment update have an FP32 form (every
+// fused visit at K <= 64), and the BF16 ones (above) keep T3 in FP32 too.
+// Elsewhere the precision option leaves FP64 in place.
 static bool visit_f32(const FitBatch &f) {
   int TY, TX;
   size_t lds;
+  if (f.prec == 16) return visit_bf16(f);
   if (f.prec != 32 || f.K > 64) return false;
   if (visit4_tiles<float>(f, &TY, &TX, &lds)) return true;
   visit_tiles(f, &TY, &TX, &lds);  // the generic fused visit
@@ -2878,7 +2966,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] {
     for (int D : {0, 2, 3, 4, 5, 6})
-      for (VisitKernel kf : {visit_kernel<double>(D), visit_kernel<float>(D)}) {
+      for (VisitKernel kf : {visit_kernel<double>(D), visit_kernel<float>(D),
+                             visit_kernel<float, true>(D)}) {
         hipError_t e = hipFuncSetAttribute((const void *)kf,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) attr_err = e;
@@ -2902,9 +2991,9 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   if (attr_err != hipSuccess) return attr_err;
   int TY4, TX4;
   size_t lds4;
-  const bool f32 = visit_f32(f);
-  const bool spec = f32 ? visit4_tiles<float>(f, &TY4, &TX4, &lds4)
-                        : visit4_tiles<double>(f, &TY4, &TX4, &lds4);
+  const bool b16 = visit_bf16(f), f32 = visit_f32(f);
+  const bool spec = !b16 && (f32 ? visit4_tiles<float>(f, &TY4, &TX4, &lds4)
+                                 : visit4_tiles<double>(f, &TY4, &TX4, &lds4));
   const size_t site_off = ((size_t)(j - 1) * f.W + c) * a_site(f);
   VisitArgs v;
   v.K = f.K; v.P = f.P; v.D = f.D; v.d = f.d; v.TY = TY; v.TX = TX;
@@ -2930,8 +3019,8 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
   Span sp(KC_VISIT, st, tc.flops, tc.bytes, flops, bytes);
   int TYp, TXp;
   size_t ldsp;
-  const bool pairw = f32 ? visit4p_tiles<float>(f, &TYp, &TXp, &ldsp)
-                         : visit4p_tiles<double>(f, &TYp, &TXp, &ldsp);
+  const bool pairw = !b16 && (f32 ? visit4p_tiles<float>(f, &TYp, &TXp, &ldsp)
+                                  : visit4p_tiles<double>(f, &TYp, &TXp, &ldsp));
   if (pairw) {  // one (yf, xb) pair per wave; skips the zero padding
     v.TY = TYp;
     v.TX = TXp;
@@ -2945,8 +3034,10 @@ static hipError_t launch_fused(const FitBatch &f, int c, int j, bool rl, Ptr X,
     hipLaunchKernelGGL(f32 ? visit4_kernel<float>(TY4, TX4) : visit4_kernel<double>(TY4, TX4),
                        dim3((f.K + TY4 - 1) / TY4, f.items), dim3(kVisitThreads), lds4, st, v);
   } else {
-    hipLaunchKernelGGL(f32 ? visit_kernel<float>(f.D) : visit_kernel<double>(f.D),
-                       dim3((f.K + TY - 1) / TY, f.items), dim3(kVisitThreads), lds, st, v);
+    const VisitKernel kf = b16   ? visit_kernel<float, true>(f.D)
+                           : f32 ? visit_kernel<float>(f.D)
+                                 : visit_kernel<double>(f.D);
+    hipLaunchKernelGGL(kf, dim3((f.K + TY - 1) / TY, f.items), dim3(kVisitThreads), lds, st, v);
   }
   return hipGetLastError();
 }
@@ -3065,7 +3156,14 @@ hipError_t launch_inner_env(const FitBatch &f, int c, int j, bool rl, Ptr Y,
               f.bounded && f.hdims ? f.dims : nullptr, f.W, c, j, f.N};
     const dim3 grid((f.K * f.P + 63) / 64, f.items);
     const int mt = (f.K + 15) / 16;
-    // FP32 only where the visit wrote FP32 T3 (the specialised D = 4 kernel)
+    // BF16 or FP32 only where the visit wrote FP32 T3
+    if (visit_bf16(f)) {
+      if (mt <= 1) hipLaunchKernelGGL((k_env<1, float, true>), grid, dim3(EnvShape<1>::kThreads), 0, st, e);
+      else if (mt <= 2) hipLaunchKernelGGL((k_env<2, float, true>), grid, dim3(EnvShape<2>::kThreads), 0, st, e);
+      else if (mt <= 3) hipLaunchKernelGGL((k_env<3, float, true>), grid, dim3(EnvShape<3>::kThreads), 0, st, e);
+      else hipLaunchKernelGGL((k_env<4, float, true>), grid, dim3(EnvShape<4>::kThreads), 0, st, e);
+      return hipGetLastError();
+    }
     if (visit_f32(f)) {
       if (mt <= 1) hipLaunchKernelGGL((k_env<1, float>), grid, dim3(EnvShape<1>::kThreads), 0, st, e);
       else if (mt <= 2) hipLaunchKernelGGL((k_env<2, float>), grid, dim3(EnvShape<2>::kThreads), 0, st, e);

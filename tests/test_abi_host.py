@@ -69,13 +69,14 @@ def test_options_and_state_checks():
         g.set_option("no_such_option", 1)
     assert e.value.status == 1
     for key, val in [("n_fit", 0), ("n_fit", 2.5), ("chi_env", 0),
-                     ("chi_env", 500), ("d", 0), ("seed", -1), ("precision", 16),
+                     ("chi_env", 500), ("d", 0), ("seed", -1), ("precision", 8),
                      ("lanes", 0), ("lanes", 5), ("graphs", 2), ("graphs", 0.5)]:
         with pytest.raises(bbp.BBPError):
             g.set_option(key, val)
     g.set_option("n_fit", 3)
     g.set_option("chi_env", 20)
     g.set_option("precision", 32)
+    g.set_option("precision", 16)
     g.set_option("precision", 64)
     g.set_option("lanes", 1)
     g.set_option("graphs", 0)
