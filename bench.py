@@ -78,12 +78,11 @@ def lattice_terms(cfg):
 def observables(ctx, cfg, sites, bonds):
     """Finite lattice: <sigma_z> and <S.S>; infinite lattice: the transverse-Ising
     terms <sigma_z>, <sigma_x>, <sigma_z sigma_z>.  Returns (site terms, bond terms)."""
-    sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
     if cfg["infinite"]:
+        sz, zz = ctx.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_szsz())
         sx = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sx())
-        return np.concatenate([np.asarray(sz), np.asarray(sx)]), \
-            ctx.expect_bonds(bonds, op_szsz())
-    return sz, ctx.expect_bonds(bonds, op_heis())
+        return np.concatenate([np.asarray(sz), np.asarray(sx)]), zz
+    return ctx.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_heis())
 
 
 def solve(ctx, cfg, A, sweeps, sites, bonds, times=None, phase_ms=None):
@@ -307,8 +306,7 @@ def serve(args):
             res_ = g.sweep(1)
             n += 1
         sites, bonds = lattice_terms(dict(infinite=False, Lx=r["Lx"], Ly=r["Ly"]))
-        g.expect_sites(sites[:, 0], sites[:, 1], op_sz())
-        g.expect_bonds(bonds, op_heis())
+        g.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_heis())
         g.log_norm()
         g.close()
         lat_plain.append(time.perf_counter() - ts)
@@ -355,8 +353,8 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
 
     def observables():
         ctx.set_option("precision", 64)
-        return (np.array(ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())),
-                np.array(ctx.expect_bonds(bonds, op_heis())))
+        sz, ss = ctx.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_heis())
+        return np.array(sz), np.array(ss)
 
     # tightly converged FP64 reference: how close each stage is to the fixed point
     ctx.set_option("precision", 64)
@@ -410,8 +408,7 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
             for p, n in zip(stages, counts):
                 ctx.set_option("precision", p)
                 res = chunked(n)
-            sz = ctx.expect_sites(sites[:, 0], sites[:, 1], op_sz())
-            ss = ctx.expect_bonds(bonds, op_heis())
+            sz, ss = ctx.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_heis())
             ln = ctx.log_norm()
             sync()
             times.append(time.perf_counter() - t0)

@@ -230,6 +230,20 @@ bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
                             const int32_t *y1, const double *op, double *out);
 
 /*
+ * Site and bond expectation values from one call (Sec. II; App. B): the
+ * results of bbp_expect_sites(ns, xs, ys, op_site, out_sites) and
+ * bbp_expect_bonds(nb, x0, y0, x1, y1, op_bond, out_bonds), bit for bit,
+ * with the regions of both (blocks, and the unions of two blocks that
+ * bonds crossing blocks need) contracted together, so that their boundary
+ * stacks run side by side on the context's lanes.  ns or nb may be 0 (the
+ * matching arrays may then be null).  Errors as the two calls.
+ */
+bbp_status bbp_expect_terms(bbp_ctx *c, int32_t ns, const int32_t *xs, const int32_t *ys,
+                            const double *op_site, int32_t nb, const int32_t *x0,
+                            const int32_t *y0, const int32_t *x1, const int32_t *y1,
+                            const double *op_bond, double *out_sites, double *out_bonds);
+
+/*
  * Reduced density matrices from the same region contractions as the
  * expectation values (App. C): rho[a][b] with <O> = Tr(rho O), unit trace.
  * Sites: n matrices of d x d (a = s, b = s').  Bonds (the pairs of

@@ -26,7 +26,7 @@ EXPORTS = (
     "bbp_create", "bbp_set_option", "bbp_set_stream", "bbp_set_allocator",
     "bbp_set_tensors", "bbp_get_tensors",
     "bbp_sweep", "bbp_expect_site", "bbp_expect_bond", "bbp_expect_sites",
-    "bbp_expect_bonds", "bbp_rdm_sites", "bbp_rdm_bonds", "bbp_trace_distance",
+    "bbp_expect_bonds", "bbp_expect_terms", "bbp_rdm_sites", "bbp_rdm_bonds", "bbp_trace_distance",
     "bbp_log_norm", "bbp_get_messages",
     "bbp_set_messages", "bbp_stats", "bbp_kernel_stats",
     "bbp_kernel_stats_padded", "bbp_kernel_stats_reset", "bbp_memory", "bbp_last_error", "bbp_destroy",
@@ -93,6 +93,7 @@ def _load():
         "bbp_expect_bond": [P, c_int, c_int, c_int, c_int, dp, dp],
         "bbp_expect_sites": [P, c_int, ip, ip, dp, dp],
         "bbp_expect_bonds": [P, c_int, ip, ip, ip, ip, dp, dp],
+        "bbp_expect_terms": [P, c_int, ip, ip, dp, c_int, ip, ip, ip, ip, dp, dp, dp],
         "bbp_rdm_sites": [P, c_int, ip, ip, dp],
         "bbp_rdm_bonds": [P, c_int, ip, ip, ip, ip, dp],
         "bbp_trace_distance": [c_int, dp, dp, dp],
@@ -257,6 +258,23 @@ class BlockBP:
                                           *[_iptr(c) for c in cols],
                                           _dptr(op), _dptr(out)))
         return out
+
+    def expect_terms(self, xs, ys, op_site, bonds, op_bond):
+        """Site values with op_site and bond values with op_bond from one
+        call (bbp_expect_terms); returns (sites, bonds)."""
+        xs = np.ascontiguousarray(xs, dtype=np.int32)
+        ys = np.ascontiguousarray(ys, dtype=np.int32)
+        b = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 4))
+        cols = [np.ascontiguousarray(b[:, i]) for i in range(4)]
+        op_site = np.ascontiguousarray(op_site, dtype=np.float64)
+        op_bond = np.ascontiguousarray(op_bond, dtype=np.float64)
+        out_s = np.zeros(len(xs))
+        out_b = np.zeros(len(b))
+        self._check(_lib.bbp_expect_terms(self._ctx, len(xs), _iptr(xs), _iptr(ys),
+                                          _dptr(op_site), len(b),
+                                          *[_iptr(c) for c in cols], _dptr(op_bond),
+                                          _dptr(out_s), _dptr(out_b)))
+        return out_s, out_b
 
     def rdm_sites(self, xs, ys):
         """One-site reduced density matrices, shape (n, d, d)."""

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <set>
 #include <tuple>
@@ -157,6 +158,61 @@ struct DevBuf {
   }
 };
 
+// Page-locked host staging for transfers that must not wait on the device:
+// a copy from pageable memory is carried out synchronously, behind the
+// work already queued on its stream.  Blocks are kept by the context and
+// handed out in order; a call that stages through them resets the pool at
+// its start and synchronises before it returns, so the next call may reuse
+// every block.  A pageable pool (the request server's contexts, whose
+// calls run while another thread captures the shared sweeps into a graph,
+// which a page-locked allocation would break) gives the same results with
+// transfers that wait.
+struct PinnedPool {
+  struct Block {
+    char *p;
+    size_t size;
+  };
+  std::vector<Block> blocks;
+  size_t bi = 0, off = 0;
+  bool pageable = false;
+  PinnedPool() = default;
+  PinnedPool(const PinnedPool &) = delete;
+  PinnedPool &operator=(const PinnedPool &) = delete;
+  void reset() {
+    bi = 0;
+    off = 0;
+  }
+  // `bytes` of staging (256-byte aligned), or nullptr when none can be had.
+  void *get(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    while (bi < blocks.size() && off + bytes > blocks[bi].size) {
+      ++bi;
+      off = 0;
+    }
+    if (bi == blocks.size()) {
+      void *q = nullptr;
+      const size_t sz = std::max(bytes, (size_t)8 << 20);
+      if (pageable) {
+        q = std::malloc(sz);
+        if (!q) return nullptr;
+      } else if (hipHostMalloc(&q, sz, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      blocks.push_back(Block{(char *)q, sz});
+      off = 0;
+    }
+    void *r = blocks[bi].p + off;
+    off += bytes;
+    return r;
+  }
+  ~PinnedPool() {
+    for (Block &b : blocks)
+      if (pageable) std::free(b.p);
+      else (void)hipHostFree(b.p);
+  }
+};
+
 struct Message {
   int bi, bj;
   char dir;
@@ -239,6 +295,8 @@ struct bbp_ctx {
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> aux;     // lanes 1.. (lane 0 is `stream`)
   std::vector<hipEvent_t> lane_ev;  // fork event, then one join event per aux lane
+  std::vector<hipEvent_t> dep_ev;   // ordering events between lanes within one call
+  PinnedPool pin;                   // host staging of the observables' transfers
   hipStream_t cap = nullptr;        // stream HIP graphs are captured on (never run)
   bool tensors_set = false;
   bool device_ready = false;
@@ -487,6 +545,34 @@ struct LaneFork {
   }
   ~LaneFork() { (void)join(); }
 };
+
+// Work enqueued on `dst` after this call is ordered after the work enqueued
+// on `src` before it; `k` counts the context's dependency events used so far
+// by the current call (each wait gets an event of its own).
+static hipError_t lane_after(bbp_ctx *c, hipStream_t dst, hipStream_t src, size_t &k) {
+  if (dst == src) return hipSuccess;
+  while (c->dep_ev.size() <= k) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    c->dep_ev.push_back(ev);
+  }
+  hipEvent_t ev = c->dep_ev[k++];
+  hipError_t e = hipEventRecord(ev, src);
+  if (e == hipSuccess) e = hipStreamWaitEvent(dst, ev, 0);
+  return e;
+}
+
+// Copies `bytes` from host memory to the device on `st` through the pinned
+// pool, so that the call returns without waiting for the stream.
+static hipError_t upload_pinned(bbp_ctx *c, void *dst, const void *src, size_t bytes,
+                                hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  void *h = c->pin.get(bytes);
+  if (!h) return hipErrorOutOfMemory;
+  std::memcpy(h, src, bytes);
+  return hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st);
+}
 
 // Splits a batch of ids into up to `parts` contiguous batches of at least
 // `min_items` each.
@@ -820,7 +906,7 @@ static bool same_batch(const FitBatch &a, const FitBatch &b);
 // once and replayed, one launch instead of one per kernel.  Timing brackets
 // (a process-wide switch) are not captured.
 static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t st,
-                                 bool graph = false, int col_hi = -1) {
+                                 bool graph = false, int col_hi = -1, bool pinned = false) {
   FitBatch &f = g.fb;
   const int W = f.W;
   hipError_t e;
@@ -839,15 +925,17 @@ static bbp_status absorb_columns(bbp_ctx *c, Group &g, int col_lo, hipStream_t s
   } true_dims{f};
   f.hdims = g.dims.data();
   f.bounded = c->skip_pad;
-  e = hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
-                     hipMemcpyHostToDevice, st);
+  e = pinned ? upload_pinned(c, f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(), st)
+             : hipMemcpyAsync(f.dims, g.dims.data(), sizeof(FitDims) * g.dims.size(),
+                              hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return c->hip_fail(e, "upload dims");
   g.flags.assign((size_t)W * f.items, 0);
   for (int col = 0; col < W; ++col)
     for (int i = 0; i < f.items; ++i)
       g.flags[(size_t)col * f.items + i] = g.dims[(size_t)i * W + col].rnd;
-  e = hipMemcpyAsync(g.flagbuf.p, g.flags.data(), 4 * g.flags.size(),
-                     hipMemcpyHostToDevice, st);
+  e = pinned ? upload_pinned(c, g.flagbuf.p, g.flags.data(), 4 * g.flags.size(), st)
+             : hipMemcpyAsync(g.flagbuf.p, g.flags.data(), 4 * g.flags.size(),
+                              hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return c->hip_fail(e, "upload flags");
   bool warm = true;
   for (int col = col_lo; col < W; ++col) warm = warm && !any_rnd[col];
@@ -1282,14 +1370,26 @@ static const double *region_site(const bbp_ctx *c, const RegionSpec &r, int y,
   return c->site(r.bi * c->bx + x, r.bj * c->by + y);
 }
 
+// The regions' contractions are planned, and their device memory taken,
+// before any of them is enqueued; then the boundary stacks of every shape
+// run on lanes of their own, each line batch follows on the lane of its
+// stacks (its matrix-unit steps and contractions behind it), and the host
+// synchronises once at the end.  A shape's column absorptions are a chain of
+// dependent launches whose length does not depend on its item count, so
+// shapes side by side (the blocks' stacks beside the two-block unions')
+// shorten the whole; every transfer in between goes through pinned staging,
+// so enqueueing never waits on the device.
 static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   ++c->obs_call;
   CacheTrim trim{c};  // declared first: runs after every batch has been returned
   hipStream_t st = c->stream;
   hipError_t e = hipMemsetAsync(c->errflag.p, 0, 4, st);
   if (e != hipSuccess) return c->hip_fail(e, "memset");
+  c->pin.reset();
+  size_t nev = 0;  // dependency events this call has used
   const int Kenv = c->chi_env, P = c->P, d = c->d, d2 = d * d;
   const size_t asite = (size_t)d * P * P;
+  const int nl = std::max(1, c->lanes);
   // ---- 1. boundary stacks, batched by rotated shape -----------------------
   std::vector<StackItem> stacks;
   std::vector<std::array<int, 4>> stack_of(regs.size(), {-1, -1, -1, -1});
@@ -1365,25 +1465,62 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   std::map<std::pair<int, int>, std::vector<int>> sgroups;
   for (size_t i = 0; i < stacks.size(); ++i)
     if (!reused[i]) sgroups[{stacks[i].Wc, stacks[i].Hc}].push_back((int)i);
-  // every shape split over the lanes: each lane then runs a share of every
-  // shape, and the lanes' kernels overlap at different steps of their fits
-  // (one lane's QR, which holds few CUs, beside another's visit)
   std::vector<std::vector<int>> batches;
   std::vector<int> shape_items;  // items of the shape each batch belongs to
-  for (auto &kv : sgroups)
-    if (reuse)  // kept stacks are updated in place, one per batch
+  std::vector<int> batch_lane;
+  if (reuse) {  // kept stacks are updated in place, one per batch
+    for (auto &kv : sgroups)
       for (int id : kv.second) {
         batches.push_back({id});
         shape_items.push_back(1);
+        batch_lane.push_back((int)(batch_lane.size() % nl));
       }
-    else
-      for (auto &part : split_batch(kv.second, c->lanes, kLaneMinItems)) {
+  } else {
+    // One lane per shape; lanes left over split the shapes with the longest
+    // chains (one part's QRs then run beside another part's visits).  The
+    // parts, longest chains first, go to the lane with the least work so
+    // far.  A chain's length is its absorbed columns times its fit steps.
+    struct Shape {
+      const std::vector<int> *ids;
+      double cost;
+      int parts;
+    };
+    std::vector<Shape> shapes;
+    for (auto &kv : sgroups)
+      shapes.push_back(Shape{&kv.second,
+                             (double)std::max(1, kv.first.first - 1) * (kv.first.second + 1), 1});
+    for (int extra = nl - (int)shapes.size(); extra > 0; --extra) {
+      int best = -1;
+      for (size_t i = 0; i < shapes.size(); ++i)
+        if ((int)shapes[i].ids->size() >= (shapes[i].parts + 1) * kLaneMinItems &&
+            (best < 0 ||
+             shapes[i].cost / shapes[i].parts > shapes[best].cost / shapes[best].parts))
+          best = (int)i;
+      if (best < 0) break;
+      ++shapes[best].parts;
+    }
+    std::vector<double> cost;
+    for (const Shape &sh : shapes)
+      for (auto &part : split_batch(*sh.ids, sh.parts, kLaneMinItems)) {
         batches.push_back(part);
-        shape_items.push_back((int)kv.second.size());
+        shape_items.push_back((int)sh.ids->size());
+        cost.push_back(sh.cost);
       }
+    std::vector<int> order(batches.size());
+    for (size_t b = 0; b < order.size(); ++b) order[b] = (int)b;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(nl, 0.0);
+    batch_lane.assign(batches.size(), 0);
+    for (int b : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      batch_lane[b] = l;
+      load[l] += cost[b];
+    }
+  }
   std::vector<std::unique_ptr<Group>> sg;
   BatchReturn sg_return{c, &sg};
-  std::vector<std::vector<double>> nus;
+  std::vector<double *> sg_host;  // pinned rotated tensors of every batch
   // allocate and stage every batch first: allocation waits on the context
   // stream, which must not yet hold absorption work
   for (size_t bi = 0; bi < batches.size(); ++bi) {
@@ -1402,8 +1539,9 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     if (bs != BBP_OK) return bs;
     FitBatch &f = g.fb;
     f.tile_items = shape_items[bi];
-    // rotated tensors, gather tables and bond caps
-    g.host.assign((size_t)f.items * f.H * f.W * asite, 0.0);
+    // rotated tensors (every site written), gather tables and bond caps
+    double *hst = (double *)c->pin.get((size_t)f.items * f.H * f.W * asite * 8);
+    if (!hst) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
     g.gs.assign(f.items, GatherSrc{});
     for (int i = 0; i < f.items; ++i) {
       const StackItem &it = stacks[ids[i]];
@@ -1413,7 +1551,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
           int y, x;
           canon_to_region(it.orient, R.H, R.W, yc, xc, &y, &x);
           rotate_site(c, region_site(c, R, y, x), it.orient,
-                      g.host.data() + (((size_t)i * f.H + yc) * f.W + xc) * asite);
+                      hst + (((size_t)i * f.H + yc) * f.W + xc) * asite);
         }
       char side[3];
       int rv[3];
@@ -1431,94 +1569,19 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     }
     g.ids = ids;
     sg.push_back(std::move(gp));
+    sg_host.push_back(hst);
   }
   // kept stacks whose columns from redo_hi down changed: those columns are
   // re-absorbed in place (their batch holds the earlier columns' results)
   std::vector<int> redo;
   for (size_t sidx = 0; sidx < stacks.size(); ++sidx)
     if (reused[sidx] && redo_hi[sidx] >= 0) redo.push_back((int)sidx);
-  {  // uploads, gather and absorption; batch b on lane b % nl
-    const int nl = std::max(1, std::min(c->lanes, (int)(sg.size() + redo.size())));
-    LaneFork lanes(c);
-    if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
-    for (size_t r = 0; r < redo.size(); ++r) {
-      const int sidx = redo[r];
-      Group &g = *where[sidx].g;
-      const hipStream_t sb = lane_stream(c, (int)((sg.size() + r) % nl));
-      e = hipMemcpyAsync(g.fb.acan, rot[sidx].data(), rot[sidx].size() * 8,
-                         hipMemcpyHostToDevice, sb);
-      if (e != hipSuccess) return c->hip_fail(e, "region setup");
-      bbp_status bs = absorb_columns(c, g, need_lo[sidx], sb, false, redo_hi[sidx]);
-      if (bs != BBP_OK) return bs;
-    }
-    for (size_t b = 0; b < sg.size(); ++b) {
-      Group &g = *sg[b];
-      FitBatch &f = g.fb;
-      const hipStream_t sb = lane_stream(c, (int)(b % nl));
-      e = hipMemcpyAsync(f.acan, g.host.data(), g.host.size() * 8, hipMemcpyHostToDevice, sb);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(g.gather.p, g.gs.data(), sizeof(GatherSrc) * f.items,
-                           hipMemcpyHostToDevice, sb);
-      if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, sb);
-      if (e != hipSuccess) return c->hip_fail(e, "region setup");
-      if (f.W > 1) {
-        // with kept stacks only the columns the lines need now: later calls
-        // extend a kept stack in place
-        bbp_status bs = absorb_columns(c, g, reuse ? std::max(1, need_lo[g.ids[0]]) : 1, sb);
-        if (bs != BBP_OK) return bs;
-      }
-    }
-    if ((e = lanes.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
-  }
-  for (auto &gp : sg) {  // column scales of every batch
-    const FitBatch &f = gp->fb;
-    nus.emplace_back((size_t)f.items * f.W, 1.0);
-    if (f.W > 1) {
-      e = hipMemcpyAsync(nus.back().data(), f.nu, nus.back().size() * 8,
-                         hipMemcpyDeviceToHost, st);
-      if (e != hipSuccess) return c->hip_fail(e, "region stacks");
-    }
-  }
-  for (int sidx : redo) {  // the kept entry: its new scales and tensors
-    const RegionSpec &R = regs[stacks[sidx].region];
-    bbp_ctx::KeptStack &k =
-        c->kept_stacks.at(std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient));
-    e = hipMemcpyAsync(k.nu.data(), k.g->fb.nu, k.nu.size() * 8, hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return c->hip_fail(e, "region stacks");
-    k.cols = rot[sidx];
-    const StackItem &it = stacks[sidx];
-    for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed now
-      for (int xc = 0; xc < need_lo[sidx]; ++xc)
-        std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
-  }
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return c->hip_fail(e, "region stacks");
-  int32_t errv = 0;
-  e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return c->hip_fail(e, "error flag");
-  if (errv) return c->fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
-  for (size_t b = 0; b < sg.size(); ++b)  // column scales of the computed stacks
-    for (size_t i = 0; i < sg[b]->ids.size(); ++i)
-      where[sg[b]->ids[i]].nu = nus[b].data() + i * sg[b]->fb.W;
-  if (reuse) {  // keep the computed stacks (and their batches) for later calls
-    for (size_t sidx = 0; sidx < stacks.size(); ++sidx) {
-      if (reused[sidx]) continue;
-      const RegionSpec &R = regs[stacks[sidx].region];
-      const StackRef &w = where[sidx];
-      bbp_ctx::KeptStack &k =
-          c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient)];
-      k = bbp_ctx::KeptStack{w.g, w.item, rot[sidx],
-                             std::vector<double>(w.nu, w.nu + w.g->fb.W)};
-      const StackItem &it = stacks[sidx];
-      for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed
-        for (int xc = 0; xc < need_lo[sidx]; ++xc)
-          std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
-      where[sidx].nu = k.nu.data();
-    }
-    for (auto &gp : sg) c->kept_groups.push_back(std::move(gp));
-    sg.clear();
-    gc_kept(c);
-  }
+  // the lane each stack is computed on (-1: kept and unchanged)
+  std::vector<int> stack_lane(stacks.size(), -1);
+  for (size_t b = 0; b < sg.size(); ++b)
+    for (int id : sg[b]->ids) stack_lane[id] = batch_lane[b];
+  for (size_t r = 0; r < redo.size(); ++r)
+    stack_lane[redo[r]] = (int)((sg.size() + r) % nl);
 
   // boundary after absorbing canonical columns W-1..col+1 (col = W-1: none)
   auto boundary = [&](int sidx, int col, size_t j) -> const double * {
@@ -1534,25 +1597,21 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     return t;
   };
 
-  // ---- 2. lines, batched by length ---------------------------------------
+  // ---- 2. lines, batched by length (planned here, enqueued below) ---------
   std::vector<LineItem> lines;
   for (size_t r = 0; r < regs.size(); ++r) {
     const RegionSpec &R = regs[r];
     if (R.row)
       for (int k = 0; k < R.H; ++k) {
         if (!R.wants_line(true, k)) continue;
-        LineItem L{(int)r, true, k, stack_of[r][dir_index('D')],
-                   stack_of[r][dir_index('U')], R.H - 1 - k, k, 0.0};
-        L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
-        lines.push_back(L);
+        lines.push_back(LineItem{(int)r, true, k, stack_of[r][dir_index('D')],
+                                 stack_of[r][dir_index('U')], R.H - 1 - k, k, 0.0});
       }
     if (R.col)
       for (int k = 0; k < R.W; ++k) {
         if (!R.wants_line(false, k)) continue;
-        LineItem L{(int)r, false, k, stack_of[r][dir_index('L')],
-                   stack_of[r][dir_index('R')], k, R.W - 1 - k, 0.0};
-        L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
-        lines.push_back(L);
+        lines.push_back(LineItem{(int)r, false, k, stack_of[r][dir_index('L')],
+                                 stack_of[r][dir_index('R')], k, R.W - 1 - k, 0.0});
       }
   }
   std::map<int, std::vector<int>> lgroups;
@@ -1560,114 +1619,104 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     const int Hc = stacks[lines[i].xs].Hc;
     lgroups[Hc].push_back((int)i);
   }
-  // results per line
-  std::vector<double> lz(lines.size(), 0.0);
-  // unit results: (line, j, u) -> LR step value maps keyed in host tables
-  std::map<std::tuple<int, int, int>, double> site_rho;        // (line,j,u)
-  std::map<std::tuple<int, int, int, int>, double> bond_rho;   // (line,j,u,v)
+  // buffers the enqueued work uses, alive until the final synchronisation
+  std::deque<DevBuf> keep;
+  std::vector<std::unique_ptr<Group>> unit_groups;
+  std::vector<DevBuf> outs;
+  struct OutReturn {  // unit outputs back to the context's cache
+    bbp_ctx *c;
+    std::vector<DevBuf> &o;
+    ~OutReturn() {
+      for (DevBuf &b : o)
+        if (b.p) c->unit_out_cache.emplace_back(c->obs_call, std::move(b));
+    }
+  } out_return{c, outs};
   std::vector<std::unique_ptr<Group>> lgs;
   BatchReturn lg_return{c, &lgs};
-  std::vector<std::vector<double>> line_sites;  // host staging, alive until the sync
+  struct Tag {
+    int kind, line, j, u, v;
+  };
+  struct LinePlan {
+    const std::vector<int> *lids = nullptr;
+    int Hc = 0, lane = 0, rlane = 0;
+    Group *lg = nullptr;
+    std::vector<CopyJob> jobs;
+    DevBuf *djobs = nullptr;
+    double *fresh = nullptr;  // reuse: the lines' current tensors (pinned)
+    std::vector<UnitItem> units[2];
+    int CH = 0;
+    Group *ug = nullptr;
+    DevBuf *kets = nullptr, *bras = nullptr, *tabs = nullptr, *ujobs = nullptr;
+    double *outp[2] = {nullptr, nullptr};
+    std::vector<const double *> pa, pb;
+    std::vector<Tag> tags;
+    DevBuf *da = nullptr, *db = nullptr, *dout = nullptr;
+    double *vals = nullptr;  // pinned
+  };
+  std::vector<LinePlan> plans;
+  plans.reserve(lgroups.size());
   for (auto &kv : lgroups) {
+    plans.emplace_back();
+    LinePlan &pl = plans.back();
     const int Hc = kv.first;
     const std::vector<int> &lids = kv.second;
+    pl.lids = &lids;
+    pl.Hc = Hc;
     lgs.push_back(take_batch(c, 1, Hc, (int)lids.size()));
     Group &lg = *lgs.back();
+    pl.lg = &lg;
     std::vector<uint64_t> slots(lids.size(), 0);
     bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots);
     if (bs != BBP_OK) return bs;
     FitBatch &f = lg.fb;
     const int N = f.N;
-    std::vector<CopyJob> jobs;
-    std::vector<double> &fresh = line_sites.emplace_back();  // reuse: current tensors
-    if (reuse) fresh.assign(lids.size() * (size_t)Hc * asite, 0.0);
+    pl.lane = std::max(0, stack_lane[lines[lids[0]].xs]);
+    // the left and right environment chains are independent: the right one
+    // takes a lane of its own (with a T3 scratch of its own) when this is
+    // the only line batch and the visit is fused (T3 is then the only
+    // buffer the two would share; the unfused contractions also stage T1
+    // and T2); with several line batches each keeps to its own lane
+    pl.rlane = (lgroups.size() == 1 && nl >= 2 && visit_fused_fits(f)) ? (pl.lane + 1) % nl
+                                                                       : pl.lane;
+    if (pl.rlane != pl.lane &&
+        lg.t3r.alloc((size_t)f.items * f.K * f.P * f.P * f.K * 8) != hipSuccess)
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    if (reuse) {
+      pl.fresh = (double *)c->pin.get(lids.size() * (size_t)Hc * asite * 8);
+      if (!pl.fresh) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
+    }
     for (size_t li = 0; li < lids.size(); ++li) {
       const LineItem &L = lines[lids[li]];
       const Group &gx = *where[L.xs].g;
       const int ix = where[L.xs].item;
       for (int j = 0; j < N; ++j) {
-        jobs.push_back(CopyJob{boundary(L.xs, L.cx, j),
-                               f.xin + (li * N + j) * f.S, (int64_t)f.S, 0, 0});
+        pl.jobs.push_back(CopyJob{boundary(L.xs, L.cx, j), f.xin + (li * N + j) * f.S,
+                                  (int64_t)f.S, 0, 0});
         const bool endsite = (j == 0 || j == N - 1);
-        jobs.push_back(CopyJob{boundary(L.ys, L.cy, N - 1 - j),
-                               f.store + (li * N + j) * f.S, (int64_t)f.S,
-                               endsite ? 2 : 1, 0});
+        pl.jobs.push_back(CopyJob{boundary(L.ys, L.cy, N - 1 - j),
+                                  f.store + (li * N + j) * f.S, (int64_t)f.S,
+                                  endsite ? 2 : 1, 0});
       }
       for (int j = 0; j < Hc; ++j)
         if (reuse)  // a kept stack's tensors may be older than the line's
-          std::memcpy(fresh.data() + (li * Hc + j) * asite,
+          std::memcpy(pl.fresh + (li * Hc + j) * asite,
                       rot[L.xs].data() + ((size_t)j * gx.fb.W + L.cx) * asite, asite * 8);
         else
-          jobs.push_back(CopyJob{
+          pl.jobs.push_back(CopyJob{
               gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
               f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
-      jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
-                             f.mt + li * f.S, (int64_t)f.S, 0, 0});
-      jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
-                             f.mb + li * f.S, (int64_t)f.S, 0, 0});
+      pl.jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                                f.mt + li * f.S, (int64_t)f.S, 0, 0});
+      pl.jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                                f.mb + li * f.S, (int64_t)f.S, 0, 0});
     }
-    DevBuf djobs;
-    if (djobs.alloc(sizeof(CopyJob) * jobs.size()) != hipSuccess)
+    keep.emplace_back();
+    pl.djobs = &keep.back();
+    if (pl.djobs->alloc(sizeof(CopyJob) * pl.jobs.size()) != hipSuccess)
       return c->fail(BBP_ENOMEM, "device allocation failed");
-    e = copy_sync(c, djobs.p, jobs.data(), sizeof(CopyJob) * jobs.size(),
-                  hipMemcpyHostToDevice);
-    if (e == hipSuccess && reuse)
-      e = hipMemcpyAsync(f.acan, fresh.data(), fresh.size() * 8, hipMemcpyHostToDevice, st);
-    for (size_t o = 0; e == hipSuccess && o < jobs.size(); o += 60000)
-      e = launch_copy_jobs((const CopyJob *)djobs.p + o,
-                           (int)std::min<size_t>(60000, jobs.size() - o), Kenv,
-                           P, st);
-    if (e != hipSuccess) return c->hip_fail(e, "line setup");
-    const size_t sN = (size_t)N * f.S;
-    auto Xs = [&](int j) { return Ptr{f.xin + (size_t)j * f.S, sN}; };
-    auto Ys = [&](int j) { return Ptr{f.store + (size_t)j * f.S, sN}; };
-    auto Le = [&](int j) { return Ptr{f.lenv + (size_t)j * f.S, sN}; };
-    auto Re = [&](int j) { return Ptr{f.renv + (size_t)j * f.S, sN}; };
-    Ptr MT{f.mt, f.S}, MB{f.mb, f.S};
-    if ((e = launch_set_unit(f, Le(0), st)) != hipSuccess ||
-        (e = launch_set_unit(f, Re(N - 1), st)) != hipSuccess)
-      return c->hip_fail(e, "set_unit");
-    {
-      // the left and right environment chains are independent: with more
-      // than one lane the right one runs on lane 1 with a T3 scratch of its
-      // own, where the visit is fused (T3 is then the only buffer the two
-      // would share; the unfused contractions also stage T1 and T2)
-      const int nl2 = visit_fused_fits(f) ? std::min(c->lanes, 2) : 1;
-      FitBatch fr = f;
-      if (nl2 > 1) {
-        if (lg.t3r.alloc((size_t)f.items * f.K * f.P * f.P * f.K * 8) != hipSuccess)
-          return c->fail(BBP_ENOMEM, "device allocation failed");
-        fr.t3 = lg.t3r.d();
-      }
-      LaneFork chains(c);
-      if ((e = chains.fork(nl2)) != hipSuccess) return c->hip_fail(e, "fork lanes");
-      const hipStream_t sr = lane_stream(c, nl2 - 1);
-      for (int j = 0; j < N - 1; ++j) {
-        if (j == 0) {
-          e = launch_end_chain(f, 0, false, MT, Xs(0), st);
-          if (e == hipSuccess) e = launch_end_env(f, 0, false, Ys(0), Le(1), st);
-        } else {
-          e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), st);
-          if (e == hipSuccess) e = launch_inner_env(f, 0, j, false, Ys(j), Le(j + 1), st);
-        }
-        if (e != hipSuccess) return c->hip_fail(e, "line left environments");
-      }
-      for (int j = N - 1; j >= 1; --j) {
-        if (j == N - 1) {
-          e = launch_end_chain(fr, 0, true, MB, Xs(N - 1), sr);
-          if (e == hipSuccess) e = launch_end_env(fr, 0, true, Ys(N - 1), Re(N - 2), sr);
-        } else {
-          e = launch_inner_chain(fr, 0, j, true, Xs(j), Re(j), sr);
-          if (e == hipSuccess) e = launch_inner_env(fr, 0, j, true, Ys(j), Re(j - 1), sr);
-        }
-        if (e != hipSuccess) return c->hip_fail(e, "line right environments");
-      }
-      if ((e = chains.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
-    }
     // ---- 3. matrix-unit steps ------------------------------------------
     // needed (line, j, direction): sites and the first site of a bond take
     // a left-to-right step; the second site of a bond a right-to-left step.
-    std::vector<UnitItem> units[2];
     for (size_t li = 0; li < lids.size(); ++li) {
       const LineItem &L = lines[lids[li]];
       const RegionSpec &R = regs[L.region];
@@ -1696,150 +1745,322 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         }
       }
       for (int j : lr)
-        for (int u = 0; u < d2; ++u) units[0].push_back(UnitItem{(int)li, j, u});
+        for (int u = 0; u < d2; ++u) pl.units[0].push_back(UnitItem{(int)li, j, u});
       for (int j : rl)
-        for (int u = 0; u < d2; ++u) units[1].push_back(UnitItem{(int)li, j, u});
+        for (int u = 0; u < d2; ++u) pl.units[1].push_back(UnitItem{(int)li, j, u});
     }
     // units per chunk: 256, fewer where a unit's contraction scratch (T1,
     // T2, T3: up to (2 + d) K^2 P^2 doubles) would pass 16 GiB per chunk
     const size_t unit_scratch = 8ull * (2 + d) * Kenv * Kenv * (size_t)P * P;
-    const int CH = (int)std::max<size_t>(8, std::min<size_t>(256, (16ull << 30) / unit_scratch));
-    std::vector<double *> out_ptr[2];
-    DevBuf outbuf[2];
-    struct OutReturn {  // unit outputs back to the context's cache
-      bbp_ctx *c;
-      DevBuf *b;
-      ~OutReturn() {
-        for (int i = 0; i < 2; ++i)
-          if (b[i].p) c->unit_out_cache.emplace_back(c->obs_call, std::move(b[i]));
-      }
-    } out_return{c, outbuf};
+    pl.CH = (int)std::max<size_t>(8, std::min<size_t>(256, (16ull << 30) / unit_scratch));
     // chunk buffers, allocated once for the largest chunk and reused (stream
-    // order keeps a chunk's uploads behind the previous chunk's kernels); the
-    // host staging of every chunk lives until the stream is synchronised
-    const size_t chmax = std::min<size_t>(CH, std::max(units[0].size(), units[1].size()));
-    Group ug;
-    ug.W = 1;
-    ug.H = 1;
-    DevBuf kets, bras, tabs, ujobs;
-    std::vector<std::vector<CopyJob>> uj_keep;
-    std::vector<std::vector<double *>> tab_keep;
+    // order keeps a chunk's uploads behind the previous chunk's kernels)
+    const size_t chmax =
+        std::min<size_t>(pl.CH, std::max(pl.units[0].size(), pl.units[1].size()));
+    std::vector<double *> out_ptr[2];
     if (chmax > 0) {
-      bbp_status bs2 = alloc_batch(c, ug, (int)chmax, Kenv, std::vector<uint64_t>(chmax, 0),
-                                   NEED_SCRATCH);
+      unit_groups.emplace_back(new Group);
+      pl.ug = unit_groups.back().get();
+      pl.ug->W = 1;
+      pl.ug->H = 1;
+      bbp_status bs2 = alloc_batch(c, *pl.ug, (int)chmax, Kenv,
+                                   std::vector<uint64_t>(chmax, 0), NEED_SCRATCH);
       if (bs2 != BBP_OK) return bs2;
-      if (kets.alloc(chmax * asite * 8) != hipSuccess ||
-          bras.alloc(chmax * asite * 8) != hipSuccess ||
-          tabs.alloc(chmax * 3 * sizeof(double *)) != hipSuccess ||
-          ujobs.alloc(sizeof(CopyJob) * 2 * chmax) != hipSuccess)
-        return c->fail(BBP_ENOMEM, "device allocation failed");
+      DevBuf *bufs[4];
+      const size_t sizes[4] = {chmax * asite * 8, chmax * asite * 8,
+                               chmax * 3 * sizeof(double *), sizeof(CopyJob) * 2 * chmax};
+      for (int k = 0; k < 4; ++k) {
+        keep.emplace_back();
+        bufs[k] = &keep.back();
+        if (bufs[k]->alloc(sizes[k]) != hipSuccess)
+          return c->fail(BBP_ENOMEM, "device allocation failed");
+      }
+      pl.kets = bufs[0];
+      pl.bras = bufs[1];
+      pl.tabs = bufs[2];
+      pl.ujobs = bufs[3];
     }
     for (int dir = 0; dir < 2; ++dir) {
-      const std::vector<UnitItem> &U = units[dir];
+      const std::vector<UnitItem> &U = pl.units[dir];
       if (U.empty()) continue;
-      outbuf[dir] = take_unit_out(c, U.size() * f.S * 8);
-      if (outbuf[dir].alloc(U.size() * f.S * 8) != hipSuccess)
+      outs.push_back(take_unit_out(c, U.size() * f.S * 8));
+      if (outs.back().alloc(U.size() * f.S * 8) != hipSuccess)
         return c->fail(BBP_ENOMEM, "device allocation failed");
+      pl.outp[dir] = outs.back().d();
       out_ptr[dir].resize(U.size());
-      for (size_t i = 0; i < U.size(); ++i)
-        out_ptr[dir][i] = outbuf[dir].d() + i * f.S;
-      for (size_t o = 0; o < U.size(); o += CH) {
-        const int n = (int)std::min<size_t>(CH, U.size() - o);
-        FitBatch &fu = ug.fb;
+      for (size_t i = 0; i < U.size(); ++i) out_ptr[dir][i] = pl.outp[dir] + i * f.S;
+    }
+    // ---- 4. contractions: line values, site and bond density matrices -----
+    for (size_t li = 0; li < lids.size(); ++li) {
+      pl.pa.push_back(f.lenv + (li * N + 1) * f.S);
+      pl.pb.push_back(f.renv + (li * N + 0) * f.S);
+      pl.tags.push_back(Tag{0, (int)li, 0, 0, 0});
+    }
+    std::map<std::tuple<int, int, int>, int> lr_index, rl_index;
+    for (size_t i = 0; i < pl.units[0].size(); ++i)
+      lr_index[{pl.units[0][i].line, pl.units[0][i].j, pl.units[0][i].u}] = (int)i;
+    for (size_t i = 0; i < pl.units[1].size(); ++i)
+      rl_index[{pl.units[1][i].line, pl.units[1][i].j, pl.units[1][i].u}] = (int)i;
+    for (auto &kv2 : lr_index) {
+      const int li = std::get<0>(kv2.first), j = std::get<1>(kv2.first),
+                u = std::get<2>(kv2.first);
+      // site: <L^u_{j+1}, R_j>
+      pl.pa.push_back(out_ptr[0][kv2.second]);
+      pl.pb.push_back(f.renv + ((size_t)li * N + j) * f.S);
+      pl.tags.push_back(Tag{1, li, j, u, 0});
+      // bond (j, j+1): <L^u_{j+1}, R^v_j> with R^v_j the step at site j+1
+      for (int v = 0; v < d2; ++v) {
+        auto it = rl_index.find({li, j + 1, v});
+        if (it == rl_index.end()) continue;
+        pl.pa.push_back(out_ptr[0][kv2.second]);
+        pl.pb.push_back(out_ptr[1][it->second]);
+        pl.tags.push_back(Tag{2, li, j, u, v});
+      }
+    }
+    DevBuf *bufs[3];
+    for (int k = 0; k < 3; ++k) {
+      keep.emplace_back();
+      bufs[k] = &keep.back();
+      if (bufs[k]->alloc(pl.pa.size() * 8) != hipSuccess)
+        return c->fail(BBP_ENOMEM, "device allocation failed");
+    }
+    pl.da = bufs[0];
+    pl.db = bufs[1];
+    pl.dout = bufs[2];
+    pl.vals = (double *)c->pin.get(pl.pa.size() * 8);
+    if (!pl.vals) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
+  }
+
+  // ---- enqueue: stacks, then each line batch behind its stacks ------------
+  LaneFork lanes(c);
+  if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+  // every exit waits for the enqueued work before any buffer it uses goes
+  struct Drain {
+    LaneFork &l;
+    hipStream_t s;
+    ~Drain() {
+      (void)l.join();
+      (void)hipStreamSynchronize(s);
+    }
+  } drain{lanes, st};
+  for (size_t r = 0; r < redo.size(); ++r) {
+    const int sidx = redo[r];
+    Group &g = *where[sidx].g;
+    const hipStream_t sb = lane_stream(c, stack_lane[sidx]);
+    e = upload_pinned(c, g.fb.acan, rot[sidx].data(), rot[sidx].size() * 8, sb);
+    if (e != hipSuccess) return c->hip_fail(e, "region setup");
+    bbp_status bs = absorb_columns(c, g, need_lo[sidx], sb, false, redo_hi[sidx], true);
+    if (bs != BBP_OK) return bs;
+  }
+  std::vector<double *> nu_h(sg.size(), nullptr), redo_nu(redo.size(), nullptr);
+  for (size_t b = 0; b < sg.size(); ++b) {
+    Group &g = *sg[b];
+    FitBatch &f = g.fb;
+    const hipStream_t sb = lane_stream(c, batch_lane[b]);
+    e = hipMemcpyAsync(f.acan, sg_host[b], (size_t)f.items * f.H * f.W * asite * 8,
+                       hipMemcpyHostToDevice, sb);
+    if (e == hipSuccess) e = upload_pinned(c, g.gather.p, g.gs.data(),
+                                           sizeof(GatherSrc) * f.items, sb);
+    if (e == hipSuccess) e = launch_gather(f, (const GatherSrc *)g.gather.p, sb);
+    if (e != hipSuccess) return c->hip_fail(e, "region setup");
+    nu_h[b] = (double *)c->pin.get((size_t)f.items * f.W * 8);
+    if (!nu_h[b]) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
+    if (f.W > 1) {
+      // with kept stacks only the columns the lines need now: later calls
+      // extend a kept stack in place
+      bbp_status bs = absorb_columns(c, g, reuse ? std::max(1, need_lo[g.ids[0]]) : 1, sb,
+                                     false, -1, true);
+      if (bs != BBP_OK) return bs;
+      e = hipMemcpyAsync(nu_h[b], f.nu, (size_t)f.items * f.W * 8, hipMemcpyDeviceToHost, sb);
+      if (e != hipSuccess) return c->hip_fail(e, "region stacks");
+    } else {
+      std::fill_n(nu_h[b], (size_t)f.items * f.W, 1.0);
+    }
+  }
+  for (size_t r = 0; r < redo.size(); ++r) {  // the kept entry's new column scales
+    const FitBatch &f = where[redo[r]].g->fb;
+    redo_nu[r] = (double *)c->pin.get((size_t)f.items * f.W * 8);
+    if (!redo_nu[r]) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
+    e = hipMemcpyAsync(redo_nu[r], f.nu, (size_t)f.items * f.W * 8, hipMemcpyDeviceToHost,
+                       lane_stream(c, stack_lane[redo[r]]));
+    if (e != hipSuccess) return c->hip_fail(e, "region stacks");
+  }
+  for (size_t b = 0; b < sg.size(); ++b)  // column scales of the computed stacks
+    for (size_t i = 0; i < sg[b]->ids.size(); ++i)
+      where[sg[b]->ids[i]].nu = nu_h[b] + i * sg[b]->fb.W;
+  if (reuse) {
+    // keep the computed stacks (and their batches) for later calls: their
+    // column scales are read now
+    if ((e = lanes.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return c->hip_fail(e, "region stacks");
+    for (size_t r = 0; r < redo.size(); ++r) {
+      const int sidx = redo[r];
+      const RegionSpec &R = regs[stacks[sidx].region];
+      bbp_ctx::KeptStack &k =
+          c->kept_stacks.at(std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient));
+      const FitBatch &f = k.g->fb;
+      std::copy(redo_nu[r] + (size_t)k.item * f.W, redo_nu[r] + (size_t)(k.item + 1) * f.W,
+                k.nu.begin());
+      k.cols = rot[sidx];
+      const StackItem &it = stacks[sidx];
+      for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed now
+        for (int xc = 0; xc < need_lo[sidx]; ++xc)
+          std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
+    }
+    for (size_t sidx = 0; sidx < stacks.size(); ++sidx) {
+      if (reused[sidx]) continue;
+      const RegionSpec &R = regs[stacks[sidx].region];
+      const StackRef &w = where[sidx];
+      bbp_ctx::KeptStack &k =
+          c->kept_stacks[std::make_tuple(R.kind, R.bi, R.bj, stacks[sidx].orient)];
+      k = bbp_ctx::KeptStack{w.g, w.item, rot[sidx],
+                             std::vector<double>(w.nu, w.nu + w.g->fb.W)};
+      const StackItem &it = stacks[sidx];
+      for (int yc = 0; yc < it.Hc; ++yc)  // columns below need_lo: not absorbed
+        for (int xc = 0; xc < need_lo[sidx]; ++xc)
+          std::fill_n(k.cols.data() + ((size_t)yc * it.Wc + xc) * asite, asite, std::nan(""));
+      where[sidx].nu = k.nu.data();
+    }
+    for (auto &gp : sg) c->kept_groups.push_back(std::move(gp));
+    sg.clear();
+    gc_kept(c);
+    if ((e = lanes.fork(nl)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+  }
+
+  for (LinePlan &pl : plans) {
+    const std::vector<int> &lids = *pl.lids;
+    const int Hc = pl.Hc;
+    Group &lg = *pl.lg;
+    FitBatch &f = lg.fb;
+    const int N = f.N;
+    const hipStream_t sl = lane_stream(c, pl.lane);
+    // its boundary stacks on other lanes come first
+    std::set<int> deps;
+    for (int li : lids)
+      for (int sidx : {lines[li].xs, lines[li].ys})
+        if (stack_lane[sidx] >= 0 && stack_lane[sidx] != pl.lane) deps.insert(stack_lane[sidx]);
+    for (int l : deps)
+      if ((e = lane_after(c, sl, lane_stream(c, l), nev)) != hipSuccess)
+        return c->hip_fail(e, "line dependencies");
+    e = upload_pinned(c, pl.djobs->p, pl.jobs.data(), sizeof(CopyJob) * pl.jobs.size(), sl);
+    if (e == hipSuccess && reuse)
+      e = hipMemcpyAsync(f.acan, pl.fresh, lids.size() * (size_t)Hc * asite * 8,
+                         hipMemcpyHostToDevice, sl);
+    for (size_t o = 0; e == hipSuccess && o < pl.jobs.size(); o += 60000)
+      e = launch_copy_jobs((const CopyJob *)pl.djobs->p + o,
+                           (int)std::min<size_t>(60000, pl.jobs.size() - o), Kenv, P, sl);
+    if (e != hipSuccess) return c->hip_fail(e, "line setup");
+    const size_t sN = (size_t)N * f.S;
+    auto Xs = [&](int j) { return Ptr{f.xin + (size_t)j * f.S, sN}; };
+    auto Ys = [&](int j) { return Ptr{f.store + (size_t)j * f.S, sN}; };
+    auto Le = [&](int j) { return Ptr{f.lenv + (size_t)j * f.S, sN}; };
+    auto Re = [&](int j) { return Ptr{f.renv + (size_t)j * f.S, sN}; };
+    Ptr MT{f.mt, f.S}, MB{f.mb, f.S};
+    if ((e = launch_set_unit(f, Le(0), sl)) != hipSuccess ||
+        (e = launch_set_unit(f, Re(N - 1), sl)) != hipSuccess)
+      return c->hip_fail(e, "set_unit");
+    {
+      FitBatch fr = f;
+      const hipStream_t sr = lane_stream(c, pl.rlane);
+      if (sr != sl) {
+        fr.t3 = lg.t3r.d();
+        if ((e = lane_after(c, sr, sl, nev)) != hipSuccess) return c->hip_fail(e, "fork lanes");
+      }
+      for (int j = 0; j < N - 1; ++j) {
+        if (j == 0) {
+          e = launch_end_chain(f, 0, false, MT, Xs(0), sl);
+          if (e == hipSuccess) e = launch_end_env(f, 0, false, Ys(0), Le(1), sl);
+        } else {
+          e = launch_inner_chain(f, 0, j, false, Xs(j), Le(j), sl);
+          if (e == hipSuccess) e = launch_inner_env(f, 0, j, false, Ys(j), Le(j + 1), sl);
+        }
+        if (e != hipSuccess) return c->hip_fail(e, "line left environments");
+      }
+      for (int j = N - 1; j >= 1; --j) {
+        if (j == N - 1) {
+          e = launch_end_chain(fr, 0, true, MB, Xs(N - 1), sr);
+          if (e == hipSuccess) e = launch_end_env(fr, 0, true, Ys(N - 1), Re(N - 2), sr);
+        } else {
+          e = launch_inner_chain(fr, 0, j, true, Xs(j), Re(j), sr);
+          if (e == hipSuccess) e = launch_inner_env(fr, 0, j, true, Ys(j), Re(j - 1), sr);
+        }
+        if (e != hipSuccess) return c->hip_fail(e, "line right environments");
+      }
+      if (sr != sl && (e = lane_after(c, sl, sr, nev)) != hipSuccess)
+        return c->hip_fail(e, "join lanes");
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      const std::vector<UnitItem> &U = pl.units[dir];
+      if (U.empty()) continue;
+      for (size_t o = 0; o < U.size(); o += pl.CH) {
+        const int n = (int)std::min<size_t>(pl.CH, U.size() - o);
+        FitBatch &fu = pl.ug->fb;
         fu.items = n;
-        e = hipMemsetAsync(kets.p, 0, (size_t)n * asite * 8, st);
-        uj_keep.emplace_back();
-        tab_keep.emplace_back(3 * (size_t)n);
-        std::vector<CopyJob> &uj = uj_keep.back();
-        std::vector<double *> &tab = tab_keep.back();
+        e = hipMemsetAsync(pl.kets->p, 0, (size_t)n * asite * 8, sl);
+        CopyJob *uj = (CopyJob *)c->pin.get(sizeof(CopyJob) * 2 * n);
+        double **tab = (double **)c->pin.get(sizeof(double *) * 3 * n);
+        if (!uj || !tab) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
         const size_t slice = asite / d;
         for (int i = 0; i < n; ++i) {
           const UnitItem &ui = U[o + i];
           const double *A = f.acan + ((size_t)ui.line * Hc + (ui.j - 1)) * asite;
           const int sp = ui.u / d, s0 = ui.u % d;
           // bra: A; ket: only physical index s' present, equal to A[s]
-          uj.push_back(CopyJob{A, bras.d() + (size_t)i * asite, (int64_t)asite, 0, 0});
-          uj.push_back(CopyJob{A + s0 * slice, kets.d() + (size_t)i * asite + sp * slice,
-                               (int64_t)slice, 0, 0});
+          uj[2 * i] = CopyJob{A, pl.bras->d() + (size_t)i * asite, (int64_t)asite, 0, 0};
+          uj[2 * i + 1] = CopyJob{A + s0 * slice, pl.kets->d() + (size_t)i * asite + sp * slice,
+                                  (int64_t)slice, 0, 0};
           tab[i] = f.xin + ((size_t)ui.line * N + ui.j) * f.S;
           tab[n + i] = (dir == 0 ? f.lenv : f.renv) + ((size_t)ui.line * N + ui.j) * f.S;
           tab[2 * n + i] = f.store + ((size_t)ui.line * N + ui.j) * f.S;
         }
         if (e == hipSuccess)
-          e = hipMemcpyAsync(ujobs.p, uj.data(), sizeof(CopyJob) * uj.size(),
-                             hipMemcpyHostToDevice, st);
+          e = hipMemcpyAsync(pl.ujobs->p, uj, sizeof(CopyJob) * 2 * n, hipMemcpyHostToDevice,
+                             sl);
         if (e == hipSuccess)
-          e = hipMemcpyAsync(tabs.p, tab.data(), tab.size() * sizeof(double *),
-                             hipMemcpyHostToDevice, st);
+          e = hipMemcpyAsync(pl.tabs->p, tab, sizeof(double *) * 3 * n, hipMemcpyHostToDevice,
+                             sl);
         if (e == hipSuccess)
-          e = launch_copy_jobs((const CopyJob *)ujobs.p, (int)uj.size(), Kenv, P, st);
+          e = launch_copy_jobs((const CopyJob *)pl.ujobs->p, 2 * n, Kenv, P, sl);
         if (e != hipSuccess) return c->hip_fail(e, "unit setup");
-        fu.acan = kets.d();
-        fu.abra = bras.d();
-        double *const *tp = (double *const *)tabs.p;
+        fu.acan = pl.kets->d();
+        fu.abra = pl.bras->d();
+        double *const *tp = (double *const *)pl.tabs->p;
         Ptr X{nullptr, 0, tp}, F{nullptr, 0, tp + n}, Y{nullptr, 0, tp + 2 * n};
-        e = launch_inner_chain(fu, 0, 1, dir == 1, X, F, st);
+        e = launch_inner_chain(fu, 0, 1, dir == 1, X, F, sl);
         if (e == hipSuccess)
-          e = launch_inner_env(fu, 0, 1, dir == 1, Y, Ptr{outbuf[dir].d() + o * f.S, f.S},
-                               st);
+          e = launch_inner_env(fu, 0, 1, dir == 1, Y, Ptr{pl.outp[dir] + o * f.S, f.S}, sl);
         if (e != hipSuccess) return c->hip_fail(e, "unit steps");
       }
     }
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return c->hip_fail(e, "unit steps");
-    // ---- 4. contractions: line values, site and bond density matrices -----
-    std::vector<const double *> pa, pb;
-    struct Tag {
-      int kind, line, j, u, v;
-    };
-    std::vector<Tag> tags;
-    for (size_t li = 0; li < lids.size(); ++li) {
-      pa.push_back(f.lenv + (li * N + 1) * f.S);
-      pb.push_back(f.renv + (li * N + 0) * f.S);
-      tags.push_back(Tag{0, (int)li, 0, 0, 0});
-    }
-    std::map<std::tuple<int, int, int>, int> lr_index, rl_index;
-    for (size_t i = 0; i < units[0].size(); ++i)
-      lr_index[{units[0][i].line, units[0][i].j, units[0][i].u}] = (int)i;
-    for (size_t i = 0; i < units[1].size(); ++i)
-      rl_index[{units[1][i].line, units[1][i].j, units[1][i].u}] = (int)i;
-    for (auto &kv2 : lr_index) {
-      const int li = std::get<0>(kv2.first), j = std::get<1>(kv2.first),
-                u = std::get<2>(kv2.first);
-      // site: <L^u_{j+1}, R_j>
-      pa.push_back(out_ptr[0][kv2.second]);
-      pb.push_back(f.renv + ((size_t)li * N + j) * f.S);
-      tags.push_back(Tag{1, li, j, u, 0});
-      // bond (j, j+1): <L^u_{j+1}, R^v_j> with R^v_j the step at site j+1
-      for (int v = 0; v < d2; ++v) {
-        auto it = rl_index.find({li, j + 1, v});
-        if (it == rl_index.end()) continue;
-        pa.push_back(out_ptr[0][kv2.second]);
-        pb.push_back(out_ptr[1][it->second]);
-        tags.push_back(Tag{2, li, j, u, v});
-      }
-    }
-    DevBuf da, db, dout;
-    if (da.alloc(pa.size() * 8) != hipSuccess || db.alloc(pb.size() * 8) != hipSuccess ||
-        dout.alloc(pa.size() * 8) != hipSuccess)
-      return c->fail(BBP_ENOMEM, "device allocation failed");
-    std::vector<double> vals(pa.size());
-    e = copy_sync(c, da.p, pa.data(), pa.size() * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = copy_sync(c, db.p, pb.data(), pb.size() * 8, hipMemcpyHostToDevice);
+    e = upload_pinned(c, pl.da->p, pl.pa.data(), pl.pa.size() * 8, sl);
+    if (e == hipSuccess) e = upload_pinned(c, pl.db->p, pl.pb.data(), pl.pb.size() * 8, sl);
     if (e == hipSuccess)
-      e = launch_dots((int)pa.size(), (const double *const *)da.p,
-                      (const double *const *)db.p, f.S, dout.d(), st);
+      e = launch_dots((int)pl.pa.size(), (const double *const *)pl.da->p,
+                      (const double *const *)pl.db->p, f.S, pl.dout->d(), sl);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(vals.data(), dout.p, vals.size() * 8, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+      e = hipMemcpyAsync(pl.vals, pl.dout->p, pl.pa.size() * 8, hipMemcpyDeviceToHost, sl);
     if (e != hipSuccess) return c->hip_fail(e, "line contractions");
-    for (size_t t = 0; t < tags.size(); ++t) {
-      const Tag &tg = tags[t];
-      const int line = lids[tg.line];
-      if (tg.kind == 0) lz[line] = vals[t];
-      else if (tg.kind == 1) site_rho[{line, tg.j, tg.u}] = vals[t];
-      else bond_rho[{line, tg.j, tg.u, tg.v}] = vals[t];
-    }
   }
+  if ((e = lanes.join()) != hipSuccess) return c->hip_fail(e, "join lanes");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return c->hip_fail(e, "region contractions");
+  int32_t errv = 0;
+  e = copy_sync(c, &errv, c->errflag.p, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return c->hip_fail(e, "error flag");
+  if (errv) return c->fail(BBP_ENUMERIC, "zero or non-finite boundary norm");
+  for (LineItem &L : lines) L.ls = logscale(L.xs, L.cx) + logscale(L.ys, L.cy);
+  // results per line
+  std::vector<double> lz(lines.size(), 0.0);
+  // unit results: (line, j, u) -> LR step value maps keyed in host tables
+  std::map<std::tuple<int, int, int>, double> site_rho;        // (line,j,u)
+  std::map<std::tuple<int, int, int, int>, double> bond_rho;   // (line,j,u,v)
+  for (const LinePlan &pl : plans)
+    for (size_t t = 0; t < pl.tags.size(); ++t) {
+      const Tag &tg = pl.tags[t];
+      const int line = (*pl.lids)[tg.line];
+      if (tg.kind == 0) lz[line] = pl.vals[t];
+      else if (tg.kind == 1) site_rho[{line, tg.j, tg.u}] = pl.vals[t];
+      else bond_rho[{line, tg.j, tg.u, tg.v}] = pl.vals[t];
+    }
   // ---- 5. results per region ----------------------------------------------
   const double nan = std::nan("");
   for (size_t r = 0; r < regs.size(); ++r) {
@@ -2161,30 +2382,58 @@ static bbp_status rdm_bonds_only(bbp_ctx *c, int n, const int32_t *x0, const int
   return BBP_OK;
 }
 
+// Queries of n sites (bond false) or bonds, checked, appended to qs.
+static bool null_args(int n, const int32_t *x0, const int32_t *y0, const int32_t *x1,
+                      const int32_t *y1, bool bond, const double *op, const double *out) {
+  return n < 0 || (n > 0 && (!x0 || !y0 || !op || !out || (bond && (!x1 || !y1))));
+}
+static bbp_status expect_queries(bbp_ctx *c, int n, const int32_t *x0, const int32_t *y0,
+                                 const int32_t *x1, const int32_t *y1, bool bond,
+                                 const double *op, std::vector<Query> &qs) {
+  const int m = bond ? c->d * c->d : c->d;
+  for (int i = 0; n > 0 && i < m * m; ++i)
+    if (!std::isfinite(op[i])) return c->fail(BBP_EINVAL, "non-finite operator");
+  for (int i = 0; i < n; ++i) {
+    Query q;
+    bbp_status s = make_query(c, x0[i], y0[i], bond ? x1[i] : 0, bond ? y1[i] : 0, bond, q);
+    if (s != BBP_OK) return s;
+    qs.push_back(q);
+  }
+  return BBP_OK;
+}
+
+// ns sites with op_site, then nb bonds with op_bond, from one contraction of
+// every region they need.
+static bbp_status expect_terms(bbp_ctx *c, int ns, const int32_t *xs, const int32_t *ys,
+                               const double *op_site, int nb, const int32_t *x0,
+                               const int32_t *y0, const int32_t *x1, const int32_t *y1,
+                               const double *op_bond, double *out_sites, double *out_bonds) {
+  if (!c) return BBP_EINVAL;
+  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
+  if (null_args(ns, xs, ys, nullptr, nullptr, false, op_site, out_sites) ||
+      null_args(nb, x0, y0, x1, y1, true, op_bond, out_bonds))
+    return c->fail(BBP_EINVAL, "null argument");
+  if (c->chi_env < c->chi)
+    return c->fail(BBP_EINVAL, "chi_env must be at least chi");
+  std::vector<Query> qs;
+  bbp_status s = expect_queries(c, ns, xs, ys, nullptr, nullptr, false, op_site, qs);
+  if (s == BBP_OK) s = expect_queries(c, nb, x0, y0, x1, y1, true, op_bond, qs);
+  if (s == BBP_OK) s = ensure_regions(c, qs);
+  if (s != BBP_OK) return s;
+  for (int i = 0; i < ns + nb; ++i)
+    if ((s = answer(c, qs[i], i < ns ? op_site : op_bond,
+                    i < ns ? &out_sites[i] : &out_bonds[i - ns])) != BBP_OK)
+      return s;
+  return BBP_OK;
+}
+
 static bbp_status expect_many(bbp_ctx *c, int n, const int32_t *x0,
                               const int32_t *y0, const int32_t *x1,
                               const int32_t *y1, bool bond, const double *op,
                               double *out) {
-  if (!c) return BBP_EINVAL;
-  if (!c->tensors_set) return c->fail(BBP_ESTATE, "bbp_set_tensors first");
-  if (n < 0 || (n > 0 && (!x0 || !y0 || !op || !out || (bond && (!x1 || !y1)))))
-    return c->fail(BBP_EINVAL, "null argument");
-  if (c->chi_env < c->chi)
-    return c->fail(BBP_EINVAL, "chi_env must be at least chi");
-  const int m = bond ? c->d * c->d : c->d;
-  for (int i = 0; i < m * m; ++i)
-    if (!std::isfinite(op[i])) return c->fail(BBP_EINVAL, "non-finite operator");
-  std::vector<Query> qs(n);
-  for (int i = 0; i < n; ++i) {
-    bbp_status s = make_query(c, x0[i], y0[i], bond ? x1[i] : 0, bond ? y1[i] : 0,
-                              bond, qs[i]);
-    if (s != BBP_OK) return s;
-  }
-  bbp_status s = ensure_regions(c, qs);
-  if (s != BBP_OK) return s;
-  for (int i = 0; i < n; ++i)
-    if ((s = answer(c, qs[i], op, &out[i])) != BBP_OK) return s;
-  return BBP_OK;
+  return bond ? expect_terms(c, 0, nullptr, nullptr, nullptr, n, x0, y0, x1, y1, op, nullptr, out)
+              : expect_terms(c, n, x0, y0, op, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             out, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -2620,6 +2869,15 @@ bbp_status bbp_expect_bonds(bbp_ctx *c, int32_t n, const int32_t *x0,
   return expect_many(c, n, x0, y0, x1, y1, true, op, out);
 }
 
+bbp_status bbp_expect_terms(bbp_ctx *c, int32_t ns, const int32_t *xs, const int32_t *ys,
+                            const double *op_site, int32_t nb, const int32_t *x0,
+                            const int32_t *y0, const int32_t *x1, const int32_t *y1,
+                            const double *op_bond, double *out_sites, double *out_bonds) {
+  if (!c) return BBP_EINVAL;
+  AcctScope acct_scope(&c->mem);
+  return expect_terms(c, ns, xs, ys, op_site, nb, x0, y0, x1, y1, op_bond, out_sites,
+                      out_bonds);
+}
 bbp_status bbp_rdm_sites(bbp_ctx *c, int32_t n, const int32_t *xs, const int32_t *ys,
                          double *rho) {
   return rdm_many(c, n, xs, ys, nullptr, nullptr, false, rho);
@@ -2793,6 +3051,7 @@ void bbp_destroy(bbp_ctx *c) {
     (void)hipStreamDestroy(s);
   }
   for (hipEvent_t ev : c->lane_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : c->dep_ev) (void)hipEventDestroy(ev);
   if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
 }
@@ -3156,6 +3415,7 @@ bbp_status ctx_set_engine(bbp_ctx *c) {
   if (!c) return BBP_EINVAL;
   if (c->tensors_set) return c->fail(BBP_ESTATE, "engine mode must be set before the tensors");
   c->engine = true;
+  c->pin.pageable = true;
   return BBP_OK;
 }
 

@@ -87,6 +87,9 @@ def test_options_and_state_checks():
     with pytest.raises(bbp.BBPError) as e:
         g.expect_site(0, 0, np.eye(2))
     assert e.value.status == 4
+    with pytest.raises(bbp.BBPError) as e:
+        g.expect_terms([0], [0], np.eye(2), [(0, 0, 1, 0)], np.eye(4))
+    assert e.value.status == 4
 
 
 def test_allocator_validation():

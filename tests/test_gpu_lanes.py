@@ -62,3 +62,39 @@ def test_message_split_bitwise_equal(split):
     res = np.array([ctx.sweep(1) for _ in range(3)])
     assert np.array_equal(res, one[0])
     assert np.array_equal(ctx.get_messages_flat(), one[4])
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 3])
+def test_expect_terms_bitwise_equal(lanes):
+    # 8x8 lattice, 2x2 blocks, D=3: the sites' block regions and the bonds'
+    # two-block unions contracted in one call (their stacks side by side on
+    # the lanes) give bitwise the values of the two separate calls
+    from paper_2301_05844_amd import bbp
+    Lx = Ly = 8
+    A = peps_finite(Lx, Ly, 3, seed=7)
+    xs = np.array([x for y in range(Ly) for x in range(Lx)], dtype=np.int32)
+    ys = np.array([y for y in range(Ly) for x in range(Lx)], dtype=np.int32)
+    bonds = [(x, y, x + 1, y) for y in range(Ly) for x in range(Lx - 1)]
+    bonds += [(x, y, x, y + 1) for y in range(Ly - 1) for x in range(Lx)]
+    sep = bbp.BlockBP(Lx=Lx, Ly=Ly, bx=2, by=2, D=3, chi=9, lanes=1)
+    sep.set_tensors(A)
+    sep.sweep(3)
+    sz = sep.expect_sites(xs, ys, op_sz())
+    ss = sep.expect_bonds(bonds, op_heis())
+    tog = bbp.BlockBP(Lx=Lx, Ly=Ly, bx=2, by=2, D=3, chi=9, lanes=lanes)
+    tog.set_tensors(A)
+    tog.sweep(3)
+    for rep in range(2):   # the second call: cached batches and buffers
+        if rep:
+            tog.set_tensors(A)
+            tog.sweep(3)
+        sz2, ss2 = tog.expect_terms(xs, ys, op_sz(), bonds, op_heis())
+        print(f"lanes {lanes} call {rep}: max |sz| {np.abs(sz2).max():.3f}", flush=True)
+        assert np.array_equal(sz, sz2)
+        assert np.array_equal(ss, ss2)
+    assert np.array_equal(np.array(sep.log_norm()), np.array(tog.log_norm()))
+    # one kind only, and nothing at all
+    s3, b3 = tog.expect_terms(xs[:5], ys[:5], op_sz(), [], op_heis())
+    assert np.array_equal(s3, sz[:5]) and b3.size == 0
+    s4, b4 = tog.expect_terms([], [], op_sz(), bonds[:7], op_heis())
+    assert s4.size == 0 and np.array_equal(b4, ss[:7])
