@@ -1672,12 +1672,19 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     const int N = f.N;
     pl.lane = std::max(0, stack_lane[lines[lids[0]].xs]);
     // the left and right environment chains are independent: the right one
-    // takes a lane of its own (with a T3 scratch of its own) when this is
-    // the only line batch and the visit is fused (T3 is then the only
-    // buffer the two would share; the unfused contractions also stage T1
-    // and T2); with several line batches each keeps to its own lane
-    pl.rlane = (lgroups.size() == 1 && nl >= 2 && visit_fused_fits(f)) ? (pl.lane + 1) % nl
-                                                                       : pl.lane;
+    // takes a lane of its own (with a T3 scratch of its own) where the visit
+    // is fused (T3 is then the only buffer the two would share; the unfused
+    // contractions also stage T1 and T2): another lane of its stacks, which
+    // the batch waits for anyway, else, for the only line batch, the next
+    // lane; otherwise both keep to the batch's lane
+    pl.rlane = pl.lane;
+    if (nl >= 2 && visit_fused_fits(f)) {
+      for (int li : lids)
+        for (int sidx : {lines[li].xs, lines[li].ys})
+          if (pl.rlane == pl.lane && stack_lane[sidx] >= 0 && stack_lane[sidx] != pl.lane)
+            pl.rlane = stack_lane[sidx];
+      if (pl.rlane == pl.lane && lgroups.size() == 1) pl.rlane = (pl.lane + 1) % nl;
+    }
     if (pl.rlane != pl.lane &&
         lg.t3r.alloc((size_t)f.items * f.K * f.P * f.P * f.K * 8) != hipSuccess)
       return c->fail(BBP_ENOMEM, "device allocation failed");
