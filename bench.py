@@ -342,7 +342,7 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
-def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
+def mixed_precision(ctx, cfg, A, sites, bonds, ref, sweeps, steps, fp64_ms):
     """The precision pattern on the same workload, two protocols: FP32 sweeps
     until the residual stops falling (or drops below the tolerance), then
     FP64 sweeps to the tolerance; and BF16, then FP32, then FP64 the same
@@ -421,6 +421,34 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
                     err_sz_vs_converged=err(sz, szt), err_ss_vs_converged=err(ss, sst))
 
     protocols = {"fp32>fp64": protocol((32, 64)), "bf16>fp32>fp64": protocol((16, 32, 64))}
+    # the plain per-message FP64 form: every directed message updated as a
+    # batch of its own, one after another on one stream (message_split 0,
+    # lanes 1), the same sweeps and observables; its results are the
+    # batched FP64 solve's bits
+    pm = None
+    if fp64_ms < 1000.0:
+        from paper_2301_05844_amd import bbp
+        g = bbp.BlockBP(Lx=cfg["Lx"], Ly=cfg["Ly"], bx=cfg["bx"], by=cfg["by"], D=cfg["D"],
+                        chi=cfg["chi"], message_split=0, lanes=1)
+        n64 = sweeps
+        g.set_tensors(A)
+        g.sweep(n64)   # warm-up: the per-message graphs are captured here
+        sync()
+        t0 = time.perf_counter()
+        g.set_tensors(A)
+        res_pm = g.sweep(n64)
+        sz_pm, ss_pm = g.expect_terms(sites[:, 0], sites[:, 1], op_sz(), bonds, op_heis())
+        g.log_norm()
+        sync()
+        ms_pm = (time.perf_counter() - t0) * 1e3
+        g.close()
+        log(f"per-message FP64: {ms_pm:.0f} ms per solve")
+        pm = dict(ms_per_solve=ms_pm, sweeps=n64, residual=res_pm,
+                  equals_batched_fp64=bool(np.array_equal(sz_pm, ref[1]) and
+                                           np.array_equal(ss_pm, ref[2])),
+                  batched_fp64_speedup=ms_pm / fp64_ms)
+        for pr in protocols.values():
+            pr["speedup_vs_per_message_fp64"] = ms_pm / pr["ms_per_solve"]
     per = {}
     names = {16: "bf16", 32: "fp32", 64: "fp64"}
     peaks = {16: PEAK_BF16_TFLOPS, 32: PEAK_FP32_TFLOPS, 64: PEAK_FP64_TFLOPS}
@@ -435,7 +463,7 @@ def mixed_precision(ctx, A, sites, bonds, ref, steps, fp64_ms):
         tf = fl / (ms * 1e-3) / 1e12
         per[names[prec]] = dict(ms_per_sweep=ms, fit_tflops=tf, frac_of_peak=tf / peaks[prec])
     ctx.set_option("precision", 64)
-    return dict(protocols=protocols, per_precision=per,
+    return dict(protocols=protocols, per_precision=per, per_message_fp64=pm,
                 peaks_tflops=dict(fp64=PEAK_FP64_TFLOPS, fp32=PEAK_FP32_TFLOPS,
                                   bf16=PEAK_BF16_TFLOPS),
                 reference=f"FP64, {nt} sweeps to residual {rt:.1e}",
@@ -825,8 +853,8 @@ def main():
     )
     # the precision pattern (BF16 / FP32 contractions in the fused visits)
     if not args.no_mixed and "tol" in cfg and not cfg["infinite"]:
-        line["mixed_precision"] = mixed_precision(ctx, A, sites, bonds, out, args.steps,
-                                                  line["ms_per_step"])
+        line["mixed_precision"] = mixed_precision(ctx, cfg, A, sites, bonds, out, sweeps,
+                                                  args.steps, line["ms_per_step"])
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(cfg, A)

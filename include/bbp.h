@@ -125,10 +125,12 @@ bbp_status bbp_create(bbp_ctx **out, int32_t infinite, int32_t Lx, int32_t Ly,
  *              the same as shifting an open lattice embedded in a periodic
  *              one with dimension-1 bonds at its edges; sites keep their
  *              lattice coordinates in every call.
- *   "message_split" 1..4 (default 2; before bbp_set_tensors): the messages
+ *   "message_split" 0..4 (default 2; before bbp_set_tensors): the messages
  *              of one shape are updated as this many batches (of at least 8
  *              messages each), one per lane, so that one batch's QRs overlap
- *              another's visits.  Results do not depend on it.
+ *              another's visits; 0 updates every message as a batch of its
+ *              own (the plain per-message form, for comparison).  Results
+ *              do not depend on it.
  *   "lanes"    1..4 (default 3; before bbp_set_tensors): independent batches
  *              run on this many streams (the context stream and lanes-1
  *              streams the context creates) and overlap on the GPU: the

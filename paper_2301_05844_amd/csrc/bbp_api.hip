@@ -2529,8 +2529,8 @@ bbp_status bbp_set_option(bbp_ctx *c, const char *key, double v) {
     (k == "shift_x" ? c->sx : c->sy) = (int)v;
     partition(c);
   } else if (k == "message_split") {
-    if (v < 1 || v > 4 || v != std::floor(v))
-      return c->fail(BBP_EINVAL, "message_split must be an integer in [1,4]");
+    if (v < 0 || v > 4 || v != std::floor(v))
+      return c->fail(BBP_EINVAL, "message_split must be an integer in [0,4]");
     c->msg_split = (int)v;
   } else if (k == "skip_padding") {
     if (v != 0 && v != 1) return c->fail(BBP_EINVAL, "skip_padding must be 0 or 1");
@@ -2661,8 +2661,10 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
   // least kLaneMinItems messages, one per lane in turn: one part's QR and
   // environment updates, which hold few CUs, then overlap the other part's
   // visits (16x16 D=4 chi=32: 8 sweeps 107 -> 102 ms with two parts; three
-  // parts gain nothing more); the groups of an earlier call are kept (with
-  // their device buffers) when the partition is the same
+  // parts gain nothing more); message_split 0: one group per message (the
+  // kernels stay those of the whole shape, so results are the same bits);
+  // the groups of an earlier call are kept (with their device buffers) when
+  // the partition is the same
   std::vector<std::unique_ptr<Group>> groups;
   std::vector<int> shape_items;  // items of the shape each group belongs to
   if (c->engine) {  // the shared batches copy each message's rotated block from here
@@ -2692,7 +2694,9 @@ bbp_status bbp_set_tensors(bbp_ctx *c, const double *A, size_t n) {
     for (size_t i = 0; i < c->msgs.size(); ++i)
       by_shape[message_shape(c, c->msgs[i])].push_back((int)i);
     for (auto &kv : by_shape)
-      for (auto &part : split_batch(kv.second, c->msg_split, kLaneMinItems)) {
+      for (auto &part : c->msg_split == 0
+                            ? split_batch(kv.second, (int)kv.second.size(), 1)
+                            : split_batch(kv.second, c->msg_split, kLaneMinItems)) {
         groups.emplace_back(new Group);
         groups.back()->W = kv.first.first;
         groups.back()->H = kv.first.second;

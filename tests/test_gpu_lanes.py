@@ -49,10 +49,10 @@ def test_lanes_option_validation():
             bbp.BlockBP(Lx=4, Ly=4, bx=2, by=2, D=2, chi=4, lanes=bad)
 
 
-@pytest.mark.parametrize("split", [2, 3])
+@pytest.mark.parametrize("split", [0, 2, 3])
 def test_message_split_bitwise_equal(split):
     # 8x8 lattice with 2x2 blocks, D=3: the 48 messages of one shape split
-    # into `split` batches on their own lanes
+    # into `split` batches on their own lanes (0: one batch per message)
     from paper_2301_05844_amd import bbp
     A = peps_finite(8, 8, 3, seed=6)
     one = _run(3, A, 8, 8, 2, 2, 3, 9, 3)
