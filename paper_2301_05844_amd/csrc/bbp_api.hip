@@ -314,6 +314,7 @@ struct bbp_ctx {
   // last two calls' entries are kept)
   std::vector<std::unique_ptr<Group>> batch_cache;
   std::vector<std::pair<int, DevBuf>> unit_out_cache;
+  std::vector<std::unique_ptr<Group>> unit_groups;  // matrix-unit step batches
   // Boundary stacks kept from earlier bond-only region contractions (the
   // blockBP update's environment context, stack_reuse on): each with the
   // rotated tensors of every column it absorbed, reused by a later call
@@ -658,6 +659,10 @@ struct CacheTrim {
     u.erase(std::remove_if(u.begin(), u.end(),
                            [&](const std::pair<int, DevBuf> &e) { return e.first < keep; }),
             u.end());
+    auto &ug = c->unit_groups;
+    ug.erase(std::remove_if(ug.begin(), ug.end(),
+                            [&](const std::unique_ptr<Group> &g) { return g->cache_gen < keep; }),
+             ug.end());
   }
 };
 
@@ -667,6 +672,7 @@ static void evict_caches(void *ctx) {
   bbp_ctx *c = static_cast<bbp_ctx *>(ctx);
   c->batch_cache.clear();
   c->unit_out_cache.clear();
+  c->unit_groups.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -1620,17 +1626,33 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     lgroups[Hc].push_back((int)i);
   }
   // buffers the enqueued work uses, alive until the final synchronisation
+  // and then kept by the context for the next call
   std::deque<DevBuf> keep;
   std::vector<std::unique_ptr<Group>> unit_groups;
   std::vector<DevBuf> outs;
-  struct OutReturn {  // unit outputs back to the context's cache
+  struct OutReturn {  // device buffers and unit batches back to the context's caches
     bbp_ctx *c;
     std::vector<DevBuf> &o;
+    std::deque<DevBuf> &k;
+    std::vector<std::unique_ptr<Group>> &u;
     ~OutReturn() {
       for (DevBuf &b : o)
         if (b.p) c->unit_out_cache.emplace_back(c->obs_call, std::move(b));
+      for (DevBuf &b : k)
+        if (b.p) c->unit_out_cache.emplace_back(c->obs_call, std::move(b));
+      for (auto &g : u)
+        if (g) {
+          g->cache_gen = c->obs_call;
+          c->unit_groups.push_back(std::move(g));
+        }
     }
-  } out_return{c, outs};
+  } out_return{c, outs, keep, unit_groups};
+  // a device buffer of `bytes` kept until the end of the call (from the
+  // context's cache when one of that size is there)
+  auto keep_buf = [&](size_t bytes) -> DevBuf * {
+    keep.push_back(take_unit_out(c, bytes));
+    return keep.back().alloc(bytes) == hipSuccess ? &keep.back() : nullptr;
+  };
   std::vector<std::unique_ptr<Group>> lgs;
   BatchReturn lg_return{c, &lgs};
   struct Tag {
@@ -1717,9 +1739,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       pl.jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
                                 f.mb + li * f.S, (int64_t)f.S, 0, 0});
     }
-    keep.emplace_back();
-    pl.djobs = &keep.back();
-    if (pl.djobs->alloc(sizeof(CopyJob) * pl.jobs.size()) != hipSuccess)
+    if (!(pl.djobs = keep_buf(sizeof(CopyJob) * pl.jobs.size())))
       return c->fail(BBP_ENOMEM, "device allocation failed");
     // ---- 3. matrix-unit steps ------------------------------------------
     // needed (line, j, direction): sites and the first site of a bond take
@@ -1766,7 +1786,15 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
         std::min<size_t>(pl.CH, std::max(pl.units[0].size(), pl.units[1].size()));
     std::vector<double *> out_ptr[2];
     if (chmax > 0) {
-      unit_groups.emplace_back(new Group);
+      std::unique_ptr<Group> ugp;
+      for (auto it = c->unit_groups.begin(); it != c->unit_groups.end(); ++it)
+        if ((*it)->fb.items == (int)chmax && (*it)->fb.K == Kenv) {
+          ugp = std::move(*it);
+          c->unit_groups.erase(it);
+          break;
+        }
+      if (!ugp) ugp.reset(new Group);
+      unit_groups.push_back(std::move(ugp));
       pl.ug = unit_groups.back().get();
       pl.ug->W = 1;
       pl.ug->H = 1;
@@ -1776,12 +1804,9 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       DevBuf *bufs[4];
       const size_t sizes[4] = {chmax * asite * 8, chmax * asite * 8,
                                chmax * 3 * sizeof(double *), sizeof(CopyJob) * 2 * chmax};
-      for (int k = 0; k < 4; ++k) {
-        keep.emplace_back();
-        bufs[k] = &keep.back();
-        if (bufs[k]->alloc(sizes[k]) != hipSuccess)
+      for (int k = 0; k < 4; ++k)
+        if (!(bufs[k] = keep_buf(sizes[k])))
           return c->fail(BBP_ENOMEM, "device allocation failed");
-      }
       pl.kets = bufs[0];
       pl.bras = bufs[1];
       pl.tabs = bufs[2];
@@ -1825,12 +1850,9 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       }
     }
     DevBuf *bufs[3];
-    for (int k = 0; k < 3; ++k) {
-      keep.emplace_back();
-      bufs[k] = &keep.back();
-      if (bufs[k]->alloc(pl.pa.size() * 8) != hipSuccess)
+    for (int k = 0; k < 3; ++k)
+      if (!(bufs[k] = keep_buf(pl.pa.size() * 8)))
         return c->fail(BBP_ENOMEM, "device allocation failed");
-    }
     pl.da = bufs[0];
     pl.db = bufs[1];
     pl.dout = bufs[2];
