@@ -2269,7 +2269,7 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
   __shared__ double wred[NW][256];
   __shared__ double Ws[256], Zs[256];
   __shared__ double Tm[CT][16][16];
-  __shared__ double wp[2][NW][16], wq[2][NW][16];
+  __shared__ double wp[2][NW][16], wq[2][16];
   __shared__ double tau_s[16 * CT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane >> 4, lc = lane & 15;
@@ -2380,38 +2380,35 @@ __global__ __launch_bounds__(NW * 64) void k_qrm(QrArgs q) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) cv[t * 4 + s] = a[t][b][s];
       row_bcast<RT * 4>(xb, cv, kc);
-      double pdot = 0.0, qk = 0.0;  // x^T a_c, and a_kc where this lane holds row k
+      // x^T a_c over this wave's rows, and the row-k entries a_kc, which the
+      // lanes holding row k store on their own
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int row = rowof(0, s);
         if (row <= k) xb[s] = 0.0;
-        if (row == k) qk = a[0][b][s];
+        if (row == k) wq[pb][lc] = a[0][b][s];
       }
       double pp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int s = 0; s < 4; ++s) pp[s] = fma(xb[t * 4 + s], a[t][b][s], pp[s]);
-      pdot = sum_rows4((pp[0] + pp[1]) + (pp[2] + pp[3]));
-      qk = sum_rows4(qk);
-      if (lr == 0) {
-        wp[pb][wave][lc] = pdot;
-        wq[pb][wave][lc] = qk;
-      }
+      const double pdot = sum_rows4((pp[0] + pp[1]) + (pp[2] + pp[3]));
+      if (lr == 0) wp[pb][wave][lc] = pdot;
       __syncthreads();
-      double pc = 0.0, qc = 0.0;
+      // x^T a_c over all rows (waves in a fixed order), for this lane's
+      // column and for column k; every lane reads the same words per
+      // column, so all hold the same bits
+      double pc = 0.0, sigma2 = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < NW; ww += 4) {
-        pc += wp[pb][ww + lr][lc];
-        qc += wq[pb][ww + lr][lc];
+      for (int ww = 0; ww < NW; ++ww) {
+        pc += wp[pb][ww][lc];
+        sigma2 += wp[pb][ww][kc];
       }
-      pc = sum_rows4(pc);
-      qc = sum_rows4(qc);
+      const double qc = wq[pb][lc];
+      // dlarfg on column k: sigma^2 = x^T x, alpha = a_kk
+      const double alpha = wq[pb][kc];
       pb ^= 1;
-      // dlarfg on column k: sigma^2 = x^T x, alpha = a_kk (lane kc of each row)
-      double sa[2] = {pc, qc}, sb[2];
-      row_bcast<2>(sb, sa, kc);
-      const double sigma2 = sb[0], alpha = sb[1];
       double tau = 0.0, scal = 0.0, beta = alpha;
       if (sigma2 > 0.0) {
         const double nrm = sqrt(alpha * alpha + sigma2);
