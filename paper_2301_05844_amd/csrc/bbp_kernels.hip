@@ -324,6 +324,104 @@ hipError_t run_gemm(const Op &op, int items, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Split-K form for a few output tiles per item and a long reduction (the
+// end-site local update: one 32 x 32 tile from K P = 512 terms at chi = 32,
+// which one workgroup per item walks in eight dependent chunks): NS
+// workgroups per tile each reduce one contiguous k range into a partial
+// tile of `part` ([item][NS][M][N]), and k_splitk_sum adds the NS partials
+// of every element in a fixed order (k range 0 first) and stores the sum
+// through the op.
+template <int BM, int BN, int BK, int NS, class Op>
+__global__ __launch_bounds__(kThreads) void k_gemm_part(Op op, double *part,
+                                                        size_t part_stride) {
+  const int it = blockIdx.z;
+  if (op.flag && !op.flag[it]) return;
+  constexpr int TMX = BM / 16, TNX = BN / 16, NT = TMX * TNX;
+  constexpr int TPW = (NT + 3) / 4;
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int ks = blockIdx.x % NS;
+  const int m0 = blockIdx.y * BM, n0 = (blockIdx.x / NS) * BN;
+  const int span = ((op.Kd + NS - 1) / NS + BK - 1) / BK * BK;
+  const int kb = ks * span, ke = min(op.Kd, kb + span);
+  v4d acc[TPW];
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    for (int i = tid; i < BM * BK; i += kThreads) {
+      const int kk = i % BK, mm = i / BK;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < op.M && k < ke) ? op.a(it, m, k) : 0.0;
+    }
+    for (int i = tid; i < BK * BN; i += kThreads) {
+      const int nn = i % BN, kk = i / BN;
+      const int n = n0 + nn, k = k0 + kk;
+      Bs[kk][nn] = (n < op.N && k < ke) ? op.b(it, k, n) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int t = wave + 4 * q;
+      if (t < NT) {
+        const int tm = (t / TNX) * 16, tn = (t % TNX) * 16;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              As[kk + lq][tm + lr], Bs[kk + lq][tn + lr], acc[q], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  double *pp = part + (size_t)it * part_stride + (size_t)ks * op.M * op.N;
+#pragma unroll
+  for (int q = 0; q < TPW; ++q) {
+    const int t = wave + 4 * q;
+    if (t < NT) {
+      const int tm = (t / TNX) * 16, tn = (t % TNX) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + tm + 4 * r + lq, n = n0 + tn + lr;
+        if (m < op.M && n < op.N) pp[(size_t)m * op.N + n] = acc[q][r];
+      }
+    }
+  }
+}
+
+template <int NS, class Op>
+__global__ __launch_bounds__(kThreads) void k_splitk_sum(Op op, const double *part,
+                                                         size_t part_stride) {
+  const int it = blockIdx.y;
+  if (op.flag && !op.flag[it]) return;
+  const size_t mn = (size_t)op.M * op.N;
+  const double *pp = part + (size_t)it * part_stride;
+  for (size_t i = blockIdx.x * (size_t)kThreads + threadIdx.x; i < mn;
+       i += (size_t)gridDim.x * kThreads) {
+    double v = pp[i];
+#pragma unroll
+    for (int ks = 1; ks < NS; ++ks) v += pp[(size_t)ks * mn + i];
+    op.st(it, (int)(i / op.N), (int)(i % op.N), v);
+  }
+}
+
+// Split-K GEMM of `items` items: part holds NS M N doubles per item (stride
+// part_stride).
+template <int BM, int BN, int BK, int NS, class Op>
+hipError_t run_gemm_splitk(const Op &op, int items, double *part, size_t part_stride,
+                           hipStream_t st) {
+  if (items <= 0 || op.M <= 0 || op.N <= 0) return hipSuccess;
+  if (part_stride < (size_t)NS * op.M * op.N) return hipErrorInvalidValue;
+  dim3 grid(NS * ((op.N + BN - 1) / BN), (op.M + BM - 1) / BM, items);
+  hipLaunchKernelGGL((k_gemm_part<BM, BN, BK, NS, Op>), grid, dim3(kThreads), 0, st, op,
+                     part, part_stride);
+  const int blocks = (int)std::min<size_t>(8, ((size_t)op.M * op.N + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((k_splitk_sum<NS, Op>), dim3(blocks, items), dim3(kThreads), 0, st, op,
+                     (const double *)part, part_stride);
+  return hipGetLastError();
+}
+
 // Site tensor A'[s][u][l][d][r] of the rotated block, flat index.
 __device__ __forceinline__ size_t aidx(int D, int s, int u, int l, int dd,
                                        int r) {
@@ -3231,7 +3329,11 @@ hipError_t launch_end_local(const FitBatch &f, int c, bool rl, Ptr G, Ptr Ye,
   const Count tc = count_end(f, c, rl, 2);
   Span sp(KC_END, st, tc.flops, tc.bytes, it * 2 * K * K * P * K,
           it * 8 * (2 * K * P * K + K * K));
-  return run_gemm<32, 32, 64>(e2, f.items, st);  // one 32x32 tile, K P long
+  // one 32x32 tile, K P long: split over eight (P >= 8) workgroups per tile
+  // through the item's tmp slot (K P K doubles >= 8 K^2), which nothing
+  // else holds at this point of a column
+  if (f.P >= 8 && f.tmp) return run_gemm_splitk<32, 32, 64, 8>(e2, f.items, f.tmp, f.S, st);
+  return run_gemm<32, 32, 64>(e2, f.items, st);
 }
 
 hipError_t launch_end_env(const FitBatch &f, int c, bool rl, Ptr Ye, Ptr envOut,
