@@ -1667,6 +1667,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     double *fresh = nullptr;  // reuse: the lines' current tensors (pinned)
     std::vector<UnitItem> units[2];
     int CH = 0;
+    size_t chmax = 0;
     Group *ug = nullptr;
     DevBuf *kets = nullptr, *bras = nullptr, *tabs = nullptr, *ujobs = nullptr;
     double *outp[2] = {nullptr, nullptr};
@@ -1691,7 +1692,6 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots);
     if (bs != BBP_OK) return bs;
     FitBatch &f = lg.fb;
-    const int N = f.N;
     pl.lane = std::max(0, stack_lane[lines[lids[0]].xs]);
     // the left and right environment chains are independent: the right one
     // takes a lane of its own (with a T3 scratch of its own) where the visit
@@ -1709,37 +1709,6 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     }
     if (pl.rlane != pl.lane &&
         lg.t3r.alloc((size_t)f.items * f.K * f.P * f.P * f.K * 8) != hipSuccess)
-      return c->fail(BBP_ENOMEM, "device allocation failed");
-    if (reuse) {
-      pl.fresh = (double *)c->pin.get(lids.size() * (size_t)Hc * asite * 8);
-      if (!pl.fresh) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
-    }
-    for (size_t li = 0; li < lids.size(); ++li) {
-      const LineItem &L = lines[lids[li]];
-      const Group &gx = *where[L.xs].g;
-      const int ix = where[L.xs].item;
-      for (int j = 0; j < N; ++j) {
-        pl.jobs.push_back(CopyJob{boundary(L.xs, L.cx, j), f.xin + (li * N + j) * f.S,
-                                  (int64_t)f.S, 0, 0});
-        const bool endsite = (j == 0 || j == N - 1);
-        pl.jobs.push_back(CopyJob{boundary(L.ys, L.cy, N - 1 - j),
-                                  f.store + (li * N + j) * f.S, (int64_t)f.S,
-                                  endsite ? 2 : 1, 0});
-      }
-      for (int j = 0; j < Hc; ++j)
-        if (reuse)  // a kept stack's tensors may be older than the line's
-          std::memcpy(pl.fresh + (li * Hc + j) * asite,
-                      rot[L.xs].data() + ((size_t)j * gx.fb.W + L.cx) * asite, asite * 8);
-        else
-          pl.jobs.push_back(CopyJob{
-              gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
-              f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
-      pl.jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
-                                f.mt + li * f.S, (int64_t)f.S, 0, 0});
-      pl.jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
-                                f.mb + li * f.S, (int64_t)f.S, 0, 0});
-    }
-    if (!(pl.djobs = keep_buf(sizeof(CopyJob) * pl.jobs.size())))
       return c->fail(BBP_ENOMEM, "device allocation failed");
     // ---- 3. matrix-unit steps ------------------------------------------
     // needed (line, j, direction): sites and the first site of a bond take
@@ -1784,7 +1753,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     // order keeps a chunk's uploads behind the previous chunk's kernels)
     const size_t chmax =
         std::min<size_t>(pl.CH, std::max(pl.units[0].size(), pl.units[1].size()));
-    std::vector<double *> out_ptr[2];
+    pl.chmax = chmax;
     if (chmax > 0) {
       std::unique_ptr<Group> ugp;
       for (auto it = c->unit_groups.begin(); it != c->unit_groups.end(); ++it)
@@ -1801,9 +1770,52 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       bbp_status bs2 = alloc_batch(c, *pl.ug, (int)chmax, Kenv,
                                    std::vector<uint64_t>(chmax, 0), NEED_SCRATCH);
       if (bs2 != BBP_OK) return bs2;
+    }
+  }
+
+  // The host tables of a line batch (copy jobs, matrix-unit buffers, the
+  // contraction pointers), built while the GPU works on the stacks.
+  auto plan_tables = [&](LinePlan &pl) -> bbp_status {
+    const std::vector<int> &lids = *pl.lids;
+    const int Hc = pl.Hc;
+    FitBatch &f = pl.lg->fb;
+    const int N = f.N;
+    if (reuse) {
+      pl.fresh = (double *)c->pin.get(lids.size() * (size_t)Hc * asite * 8);
+      if (!pl.fresh) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
+    }
+    for (size_t li = 0; li < lids.size(); ++li) {
+      const LineItem &L = lines[lids[li]];
+      const Group &gx = *where[L.xs].g;
+      const int ix = where[L.xs].item;
+      for (int j = 0; j < N; ++j) {
+        pl.jobs.push_back(CopyJob{boundary(L.xs, L.cx, j), f.xin + (li * N + j) * f.S,
+                                  (int64_t)f.S, 0, 0});
+        const bool endsite = (j == 0 || j == N - 1);
+        pl.jobs.push_back(CopyJob{boundary(L.ys, L.cy, N - 1 - j),
+                                  f.store + (li * N + j) * f.S, (int64_t)f.S,
+                                  endsite ? 2 : 1, 0});
+      }
+      for (int j = 0; j < Hc; ++j)
+        if (reuse)  // a kept stack's tensors may be older than the line's
+          std::memcpy(pl.fresh + (li * Hc + j) * asite,
+                      rot[L.xs].data() + ((size_t)j * gx.fb.W + L.cx) * asite, asite * 8);
+        else
+          pl.jobs.push_back(CopyJob{
+              gx.fb.acan + (((size_t)ix * gx.fb.H + j) * gx.fb.W + L.cx) * asite,
+              f.acan + (li * Hc + j) * asite, (int64_t)asite, 0, 0});
+      pl.jobs.push_back(CopyJob{gx.fb.mt + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                                f.mt + li * f.S, (int64_t)f.S, 0, 0});
+      pl.jobs.push_back(CopyJob{gx.fb.mb + ((size_t)ix * gx.fb.W + L.cx) * gx.fb.S,
+                                f.mb + li * f.S, (int64_t)f.S, 0, 0});
+    }
+    if (!(pl.djobs = keep_buf(sizeof(CopyJob) * pl.jobs.size())))
+      return c->fail(BBP_ENOMEM, "device allocation failed");
+    std::vector<double *> out_ptr[2];
+    if (pl.chmax > 0) {
       DevBuf *bufs[4];
-      const size_t sizes[4] = {chmax * asite * 8, chmax * asite * 8,
-                               chmax * 3 * sizeof(double *), sizeof(CopyJob) * 2 * chmax};
+      const size_t sizes[4] = {pl.chmax * asite * 8, pl.chmax * asite * 8,
+                               pl.chmax * 3 * sizeof(double *), sizeof(CopyJob) * 2 * pl.chmax};
       for (int k = 0; k < 4; ++k)
         if (!(bufs[k] = keep_buf(sizes[k])))
           return c->fail(BBP_ENOMEM, "device allocation failed");
@@ -1858,7 +1870,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     pl.dout = bufs[2];
     pl.vals = (double *)c->pin.get(pl.pa.size() * 8);
     if (!pl.vals) return c->fail(BBP_ENOMEM, "pinned host allocation failed");
-  }
+      return BBP_OK;
+  };
 
   // ---- enqueue: stacks, then each line batch behind its stacks ------------
   LaneFork lanes(c);
@@ -1957,6 +1970,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
   }
 
   for (LinePlan &pl : plans) {
+    bbp_status tb = plan_tables(pl);
+    if (tb != BBP_OK) return tb;
     const std::vector<int> &lids = *pl.lids;
     const int Hc = pl.Hc;
     Group &lg = *pl.lg;
