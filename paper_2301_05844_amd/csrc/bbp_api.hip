@@ -699,9 +699,12 @@ enum : unsigned {
   NEED_SCRATCH = 2u,  // t3, and t1/t2 when the generic chain or QR needs them
 };
 
+// With `pinned`, the slot table goes up through the context's pinned pool
+// and the call returns without waiting for the device (the clears and the
+// upload are queued on the context stream).
 static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
                               const std::vector<uint64_t> &slots,
-                              unsigned need = NEED_FIT | NEED_SCRATCH) {
+                              unsigned need = NEED_FIT | NEED_SCRATCH, bool pinned = false) {
   FitBatch &f = g.fb;
   f.items = items;
   f.tile_items = items;
@@ -775,7 +778,8 @@ static bbp_status alloc_batch(bbp_ctx *c, Group &g, int items, int bond_cap,
   f.err = (int32_t *)c->errflag.p;
   g.dims.assign(it * f.W, FitDims{});
   g.have.assign(it * f.W, 0);
-  e = copy_sync(c, f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
+  e = pinned ? upload_pinned(c, f.slot, slots.data(), 8 * it, c->stream)
+             : copy_sync(c, f.slot, slots.data(), 8 * it, hipMemcpyHostToDevice);
   if (e != hipSuccess) return c->hip_fail(e, "upload slots");
   return BBP_OK;
 }
@@ -1541,7 +1545,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       slots[i] = region_slot(R.kind, R.bi, R.bj, it.orient);
       where[ids[i]] = StackRef{gp.get(), (int)i, nullptr};
     }
-    bbp_status bs = alloc_batch(c, g, (int)ids.size(), Kenv, slots);
+    bbp_status bs = alloc_batch(c, g, (int)ids.size(), Kenv, slots, NEED_FIT | NEED_SCRATCH,
+                                true);
     if (bs != BBP_OK) return bs;
     FitBatch &f = g.fb;
     f.tile_items = shape_items[bi];
@@ -1689,7 +1694,8 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
     Group &lg = *lgs.back();
     pl.lg = &lg;
     std::vector<uint64_t> slots(lids.size(), 0);
-    bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots);
+    bbp_status bs = alloc_batch(c, lg, (int)lids.size(), Kenv, slots, NEED_FIT | NEED_SCRATCH,
+                                true);
     if (bs != BBP_OK) return bs;
     FitBatch &f = lg.fb;
     pl.lane = std::max(0, stack_lane[lines[lids[0]].xs]);
@@ -1768,7 +1774,7 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       pl.ug->W = 1;
       pl.ug->H = 1;
       bbp_status bs2 = alloc_batch(c, *pl.ug, (int)chmax, Kenv,
-                                   std::vector<uint64_t>(chmax, 0), NEED_SCRATCH);
+                                   std::vector<uint64_t>(chmax, 0), NEED_SCRATCH, true);
       if (bs2 != BBP_OK) return bs2;
     }
   }
