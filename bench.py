@@ -794,6 +794,10 @@ def main():
     phase_kernels = {}
     if not args.no_kernel_pass:
         log("event-timed pass")
+        # the first context's buffers are released first: at D=6 one
+        # context's observables hold over 100 GB of the 288
+        ctx.close()
+        ctx = None
         ctx1 = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
                            lanes=1)
         ctx1.set_option("timing", 1)
@@ -853,6 +857,9 @@ def main():
     )
     # the precision pattern (BF16 / FP32 contractions in the fused visits)
     if not args.no_mixed and "tol" in cfg and not cfg["infinite"]:
+        if ctx is None:
+            ctx = bbp.BlockBP(bx=cfg["bx"], by=cfg["by"], D=cfg["D"], chi=cfg["chi"], **geo,
+                              **opts)
         line["mixed_precision"] = mixed_precision(ctx, cfg, A, sites, bonds, out, sweeps,
                                                   args.steps, line["ms_per_step"])
     if not args.no_cpu_baseline:

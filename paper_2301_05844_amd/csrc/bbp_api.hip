@@ -1751,10 +1751,12 @@ static bbp_status compute_regions(bbp_ctx *c, std::vector<RegionSpec> &regs) {
       for (int j : rl)
         for (int u = 0; u < d2; ++u) pl.units[1].push_back(UnitItem{(int)li, j, u});
     }
-    // units per chunk: 256, fewer where a unit's contraction scratch (T1,
-    // T2, T3: up to (2 + d) K^2 P^2 doubles) would pass 16 GiB per chunk
+    // units per chunk: 256, fewer where the units' contraction scratch (T1,
+    // T2, T3: up to (2 + d) K^2 P^2 doubles a unit) of the line batches,
+    // which run side by side, would pass 16 GiB together
     const size_t unit_scratch = 8ull * (2 + d) * Kenv * Kenv * (size_t)P * P;
-    pl.CH = (int)std::max<size_t>(8, std::min<size_t>(256, (16ull << 30) / unit_scratch));
+    pl.CH = (int)std::max<size_t>(
+        8, std::min<size_t>(256, (16ull << 30) / lgroups.size() / unit_scratch));
     // chunk buffers, allocated once for the largest chunk and reused (stream
     // order keeps a chunk's uploads behind the previous chunk's kernels)
     const size_t chmax =
