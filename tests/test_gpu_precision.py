@@ -205,12 +205,15 @@ def test_bf16_fp32_fp64_stages_against_the_oracle():
     from oracle.blockbp import BlockBP as OracleBP
     A = peps_finite(8, 8, 4, seed=1)
     g = bbp.BlockBP(**CFG)
-    g.set_option("timing", 1)
-    g.set_option("precision", 16)
-    g.set_tensors(A)
-    log = []
-    st = _stages(g, 8, [(16, 1e-7), (32, 1e-7), (64, 1e-10)], log, extra=EXTRA)
-    ks = {k["name"]: k for k in g.kernel_stats()}
+    g.set_option("timing", 1)   # process-wide: switched off again below
+    try:
+        g.set_option("precision", 16)
+        g.set_tensors(A)
+        log = []
+        st = _stages(g, 8, [(16, 1e-7), (32, 1e-7), (64, 1e-10)], log, extra=EXTRA)
+        ks = {k["name"]: k for k in g.kernel_stats()}
+    finally:
+        g.set_option("timing", 0)
     ref = OracleBP(A, Lx=8, Ly=8, bx=4, by=4, D=4, chi=16)
     for _ in range(40):
         if ref.sweep() < 1e-10:
