@@ -28,5 +28,6 @@ from .gen import (  # noqa: F401
     op_sy_real,
     op_szsz,
     op_heis,
+    dense_matrices,
     CONFIGS,
 )

@@ -208,3 +208,33 @@ def peps_transpose(A, Lx, Ly):
         for x in range(Lx):
             B[x * Ly + y] = A[y * Lx + x].transpose(0, 2, 1, 4, 3)
     return B, Ly, Lx
+
+
+def dense_matrices(batch, m, n, seed=0, kind="gauss", rank=None, cond=1e3):
+    """A seeded batch of real m x n matrices, shape (batch, m, n).
+
+    ``gauss``: i.i.d. N(0, 1) entries.  ``graded``: Q1 diag(s) Q2^T with
+    random orthogonal factors (QR of Gaussian matrices) and s falling
+    geometrically from 1 to 1/cond, so the singular values are known and
+    well separated.  ``lowrank``: a product of m x rank and rank x n Gaussian
+    matrices.  ``equal``: the first n orthonormal columns of a random
+    orthogonal matrix (every singular value 1).  ``zero``: all zeros."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((batch, m, n))
+    for b in range(batch):
+        if kind == "gauss":
+            out[b] = rng.standard_normal((m, n))
+        elif kind == "graded":
+            q1, _ = np.linalg.qr(rng.standard_normal((m, n)))
+            q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+            s = cond ** (-np.arange(n) / max(n - 1, 1))
+            out[b] = (q1 * s) @ q2.T
+        elif kind == "lowrank":
+            r = rank if rank is not None else max(1, n // 3)
+            out[b] = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+        elif kind == "equal":
+            q, _ = np.linalg.qr(rng.standard_normal((m, n)))
+            out[b] = q
+        elif kind != "zero":
+            raise ValueError(kind)
+    return out

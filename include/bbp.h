@@ -270,6 +270,40 @@ bbp_status bbp_trace_distance(int32_t m, const double *rho, const double *sigma,
                               double *out);
 
 /*
+ * Truncated SVD of a batch of real m x n matrices (m >= n) on the GPU, FP64:
+ * A_b = U_b diag(S_b) V_b^T by one-sided (Hestenes) Jacobi rotations, of
+ * which the k largest singular triplets are kept -- the compression step of
+ * the standard alternative to the zip-up fit (App. A: multiply the MPO into
+ * the MPS, then compress it bond by bond).  No context.
+ *  - A: device, batch x m x n doubles, row-major, item b at A + b m n; read
+ *    only.  U: device, batch x m x k row-major; S: device, batch x k, in
+ *    descending order; V: device, batch x n x k row-major.  err2 (or null):
+ *    device, batch doubles, the discarded weight sum_{i >= k} S_i^2.
+ *    sweeps (or null): device, batch int32, the Jacobi sweeps taken,
+ *    negative if max_sweeps ended the iteration before a sweep rotated
+ *    nothing.  The caller owns every buffer; nothing is allocated.
+ *  - Each U column and its V column are signed so that the largest-magnitude
+ *    entry of the U column (the first of equal ones) is positive; the U
+ *    column of a zero singular value is zero.  Equal singular values keep
+ *    the order of the columns they came from.
+ *  - A pair of columns is rotated while |a_p . a_q| > tol |a_p| |a_q|; tol 0
+ *    takes sqrt(m) times the FP64 epsilon.  At most max_sweeps sweeps.
+ *  - The work is enqueued on hip_stream (null: the null stream) and the
+ *    call returns without waiting.  Each item's result is the same, bit for
+ *    bit, whatever else the batch holds.  Non-finite input gives non-finite
+ *    output, not an error.
+ *  - Errors: BBP_EINVAL for batch < 0, n outside [1, 64], m < n, k outside
+ *    [1, n], m n + n n > BBP_SVD_MAX_WORDS, max_sweeps outside [1, 100],
+ *    tol outside [0, 1), or a null A, U, S or V with batch > 0;
+ *    BBP_EDEVICE if the launch fails.
+ */
+#define BBP_SVD_MAX_WORDS 19968
+bbp_status bbp_svd_jacobi(int32_t batch, int32_t m, int32_t n, int32_t k,
+                          const double *A, double *U, double *S, double *V,
+                          double *err2, int32_t *sweeps, int32_t max_sweeps,
+                          double tol, void *hip_stream);
+
+/*
  * log|<psi|psi>| estimated by the block Bethe formula
  * sum_blocks log|Z_A| - sum_edges log|Z_AB| (Z_A: block A with its four
  * incoming unit-norm messages; Z_AB = <m_{A->B}, m_{B->A}>).  Exact when

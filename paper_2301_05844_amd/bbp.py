@@ -34,7 +34,7 @@ EXPORTS = (
     "bbp_server_poll", "bbp_server_cancel", "bbp_server_stats",
     "bbp_server_sweeps", "bbp_server_error", "bbp_server_destroy",
     "bbp_update_workspace", "bbp_update_message", "bbp_update_message_noalloc",
-    "bbp_update_last_error", "bbp_ite_step", "bbp_ite_fit",
+    "bbp_update_last_error", "bbp_ite_step", "bbp_ite_fit", "bbp_svd_jacobi",
 )
 
 OUT_SZ, OUT_SS, OUT_LOGNORM = 1, 2, 4
@@ -97,6 +97,7 @@ def _load():
         "bbp_rdm_sites": [P, c_int, ip, ip, dp],
         "bbp_rdm_bonds": [P, c_int, ip, ip, ip, ip, dp],
         "bbp_trace_distance": [c_int, dp, dp, dp],
+        "bbp_svd_jacobi": [c_int, c_int, c_int, c_int, P, P, P, P, P, P, c_int, c_double, P],
         "bbp_ite_step": [P, dp, c_int, dp],
         "bbp_ite_fit": [c_int, c_int, c_int, c_int, dp, dp, dp, c_int, dp, dp, dp],
         "bbp_log_norm": [P, dp, ip],
@@ -486,6 +487,36 @@ def trace_distance(rho, sigma):
     if st != 0:
         raise BBPError(st, "bbp_trace_distance rejected its arguments")
     return out.value
+
+
+SVD_MAX_WORDS = 19968   # BBP_SVD_MAX_WORDS
+
+
+def svd_jacobi(A, k=None, *, max_sweeps=60, tol=0.0, stream=None):
+    """bbp_svd_jacobi: truncated SVD of each m x n matrix of the float64
+    device tensor ``A`` (batch, m, n), m >= n.  Returns device tensors
+    ``(U (batch, m, k), S (batch, k), V (batch, n, k), err2 (batch,),
+    sweeps (batch,))``; ``k`` defaults to n.  Enqueued on ``stream``
+    (default: torch's current stream)."""
+    if A.dtype != torch.float64 or not A.is_cuda or A.dim() != 3 or not A.is_contiguous():
+        raise ValueError("A must be a contiguous float64 device tensor (batch, m, n)")
+    b, m, n = A.shape
+    k = n if k is None else int(k)
+    dev = A.device
+    U = torch.empty((b, m, k), dtype=torch.float64, device=dev)
+    S = torch.empty((b, k), dtype=torch.float64, device=dev)
+    V = torch.empty((b, n, k), dtype=torch.float64, device=dev)
+    e2 = torch.empty((b,), dtype=torch.float64, device=dev)
+    sw = torch.empty((b,), dtype=torch.int32, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    handle = getattr(stream, "cuda_stream", stream)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = _lib.bbp_svd_jacobi(b, m, n, k, ptr(A), ptr(U), ptr(S), ptr(V), ptr(e2), ptr(sw),
+                             int(max_sweeps), float(tol), ctypes.c_void_p(handle))
+    if st != 0:
+        raise BBPError(st, "bbp_svd_jacobi rejected its arguments or the launch failed")
+    return U, S, V, e2, sw
 
 
 def ite_fit(N, theta, gate, D, n_als=4):

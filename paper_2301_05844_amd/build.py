@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbp.so")
-SOURCES = ["bbp_kernels.hip", "bbp_api.hip", "bbp_server.hip", "bbp_ite.hip"]
+SOURCES = ["bbp_kernels.hip", "bbp_api.hip", "bbp_server.hip", "bbp_ite.hip", "bbp_svd.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

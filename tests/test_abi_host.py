@@ -241,3 +241,36 @@ def test_init_and_hbm_budget_option_validation():
             c.set_option(key, bad)
     c.set_option("init", 1)
     c.set_option("hbm_budget", 1 << 30)
+
+
+def test_svd_jacobi_rejects_bad_arguments_before_the_device():
+    """bbp_svd_jacobi checks its sizes and pointers before any HIP call."""
+    bbp = _bbp()
+    lib = bbp.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every case fails first
+    bad = [
+        (-1, 8, 4, 4, 60, 0.0),            # batch < 0
+        (1, 8, 0, 1, 60, 0.0),             # n = 0
+        (1, 80, 65, 65, 60, 0.0),          # n above 64
+        (1, 3, 4, 4, 60, 0.0),             # m < n
+        (1, 8, 4, 0, 60, 0.0),             # k = 0
+        (1, 8, 4, 5, 60, 0.0),             # k > n
+        (1, 8, 4, 4, 0, 0.0),              # max_sweeps = 0
+        (1, 8, 4, 4, 101, 0.0),            # max_sweeps above 100
+        (1, 8, 4, 4, 60, 1.0),             # tol >= 1
+        (1, 8, 4, 4, 60, -1e-3),           # tol < 0
+        (1, 8, 4, 4, 60, float("nan")),    # tol NaN
+        (1, 400, 60, 60, 60, 0.0),         # m n + n n above BBP_SVD_MAX_WORDS
+    ]
+    for b, m, n, k, sw, tol in bad:
+        st = lib.bbp_svd_jacobi(b, m, n, k, fake, fake, fake, fake, None, None, sw, tol, None)
+        assert st == 1, (b, m, n, k, sw, tol)
+    # null operands with work to do
+    assert lib.bbp_svd_jacobi(1, 8, 4, 4, None, fake, fake, fake, None, None, 60, 0.0,
+                              None) == 1
+    assert lib.bbp_svd_jacobi(1, 8, 4, 4, fake, fake, None, fake, None, None, 60, 0.0,
+                              None) == 1
+    # an empty batch is a no-op that needs no pointers
+    assert lib.bbp_svd_jacobi(0, 8, 4, 4, None, None, None, None, None, None, 60, 0.0,
+                              None) == 0
+    assert bbp.SVD_MAX_WORDS == 19968
