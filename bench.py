@@ -651,6 +651,81 @@ def ite_bench(args):
     print(json.dumps(line), flush=True)
 
 
+SVD_BATCH, SVD_M, SVD_N = 48, 512, 32
+
+
+def svd_bench(args):
+    """bbp_svd_jacobi on one batch of 48 message-panel shaped matrices (512 x
+    32, the (chi D^2) x chi panels of the 16x16 D=4 chi=32 workload's message
+    batch), all 32 singular triplets kept: K timed calls after W warm-up
+    calls, HIP events on the stream the kernel runs on, the FP64 vector-ALU
+    roofline on the rotations' arithmetic, and the oracle (LAPACK SVD) on
+    the same matrices on the host."""
+    import torch
+    from paper_2301_05844_amd import bbp
+    from bbp_inputs import dense_matrices
+    A = dense_matrices(SVD_BATCH, SVD_M, SVD_N, seed=args.seed)
+    t = torch.from_numpy(A).cuda()
+    for _ in range(args.warmup):
+        bbp.svd_jacobi(t)
+    sync()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(args.steps):
+        U, S, V, e2, sw = bbp.svd_jacobi(t)
+    e1.record(st)
+    sync()
+    total = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    sweeps = sw.cpu().numpy()
+    if np.any(sweeps <= 0):
+        raise SystemExit("bbp_svd_jacobi: an item did not converge")
+    # every pair of every sweep: three length-m dot products (6 m flops); the
+    # rotation of two columns of A and of V (6 m + 6 n) for every pair of
+    # every sweep but the last, which rotates nothing (an upper bound: pairs
+    # already orthogonal are skipped); the final column norms (2 m n)
+    m, n = SVD_M, SVD_N
+    P = n * (n - 1) / 2
+    flops = float(np.sum(sweeps) * P * 6 * m + np.sum(sweeps - 1) * P * (6 * m + 6 * n)
+                  + SVD_BATCH * 2 * m * n)
+    achieved = flops / (ev_ms * 1e-3) / 1e12
+    S_gpu = S.cpu().numpy()
+    from oracle.svd import truncated_svd
+    c0 = time.perf_counter()
+    err = 0.0
+    for b in range(SVD_BATCH):
+        _, So, _, _ = truncated_svd(A[b])
+        err = max(err, float(np.abs(S_gpu[b] - So).max() / So[0]))
+    cpu_s = time.perf_counter() - c0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    line = dict(
+        metric="matrices/s (batched truncated SVD by one-sided Jacobi, FP64)",
+        value=SVD_BATCH * args.steps / total, unit="matrices/s",
+        n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=total / args.steps * 1e3,
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"svd_{SVD_BATCH}x{m}x{n}", batch=SVD_BATCH, m=m, n=n, k=n),
+        sweeps=dict(mean=float(np.mean(sweeps)), max=int(np.max(sweeps))),
+        max_rel_err_singular_values_vs_oracle=err,
+        roofline=dict(bound="alu", achieved=achieved, peak=78.6, unit="TFLOP/s",
+                      frac=achieved / 78.6, traffic=None, kernel="k_svd_jacobi",
+                      avg_us=ev_ms * 1e3, flops_per_launch=flops,
+                      counted_on="pair sums of every sweep each item took, rotations of "
+                                 "every pair of every sweep but the last (an upper bound)"),
+        cpu_baseline=dict(value=SVD_BATCH / cpu_s, unit="matrices/s", cores=threads,
+                          kind="oracle", sample=f"the same {SVD_BATCH} matrices, LAPACK "
+                          "SVD (numpy.linalg.svd) one by one", **host_cpu()),
+    )
+    print(json.dumps(line), flush=True)
+
+
 def ite_cpu_baseline(w, A, G, gates):
     """The oracle's blockBP update on the host, on a bounded sample: block BP
     converged to 1e-6 (at most 10 sweeps) from the start, then gates of the
@@ -721,6 +796,8 @@ def main():
     ap.add_argument("--ite", choices=sorted(ITE_WORKLOADS), default=None,
                     help="ITE steps of the blockBP update on this workload instead of the "
                          "default solve")
+    ap.add_argument("--svd", action="store_true",
+                    help="the batched truncated SVD (bbp_svd_jacobi) on 48 512x32 panels")
     ap.add_argument("--lanes", type=int, default=None,
                     help="streams the message and boundary-stack batches spread over "
                          "(library default when absent)")
@@ -738,6 +815,9 @@ def main():
         return
     if args.ite:
         ite_bench(args)
+        return
+    if args.svd:
+        svd_bench(args)
         return
 
     from paper_2301_05844_amd import bbp

@@ -13,7 +13,7 @@
 // j contiguous, so a pair's dot products are lane-strided reads), V beside
 // it.  A sweep is n' - 1 rounds of the round-robin (circle) pairing of the
 // n' = n rounded up to even columns: the n'/2 pairs of a round share no
-// column, so the 8 waves rotate them side by side, a wave per pair, with
+// column, so the 16 waves rotate them side by side, a wave per pair, with
 // one barrier per round.  Each pair's three sums (|a_p|^2, |a_q|^2,
 // a_p . a_q) are accumulated per lane in row order and reduced by a fixed
 // butterfly, so every result is reproducible bit for bit and independent of
@@ -29,7 +29,7 @@
 namespace bbp {
 namespace {
 
-constexpr int kSvdWaves = 8, kSvdThreads = 64 * kSvdWaves;
+constexpr int kSvdWaves = 16, kSvdThreads = 64 * kSvdWaves;
 constexpr int kSvdMaxN = 64;
 
 struct SvdArgs {
@@ -90,6 +90,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(SvdArgs g) {
         if (q >= n) continue;  // the padding column of an odd n
         double *ap = a + (size_t)p * m, *aq = a + (size_t)q * m;
         double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll 8
         for (int i = lane; i < m; i += 64) {
           const double x = ap[i], y = aq[i];
           al = fma(x, x, al);
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(SvdArgs g) {
         const double ze = (be - al) / (2.0 * ga);
         const double t = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll 8
         for (int i = lane; i < m; i += 64) {
           const double x = ap[i], y = aq[i];
           ap[i] = c * x - s * y;
