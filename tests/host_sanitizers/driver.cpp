@@ -138,6 +138,26 @@ int main() {
   CHECK(bbp_server_submit(srv, &bad, T.data(), T.size(), nullptr, &ticket) == BBP_EINVAL);
   CHECK(bbp_server_submit(srv, &rq, T.data(), T.size() - 1, nullptr, &ticket) == BBP_EINVAL);
   bbp_server_destroy(srv);
+
+  // batched truncated SVD: every size and pointer check happens before the
+  // device is touched
+  double *fake = T.data();
+  CHECK(bbp_svd_jacobi(-1, 8, 4, 4, fake, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 3, 4, 4, fake, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 8, 65, 4, fake, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 8, 4, 5, fake, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 400, 60, 60, fake, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 8, 4, 4, fake, fake, fake, fake, nullptr, nullptr, 60, NAN,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(1, 8, 4, 4, nullptr, fake, fake, fake, nullptr, nullptr, 60, 0.0,
+                       nullptr) == BBP_EINVAL);
+  CHECK(bbp_svd_jacobi(0, 8, 4, 4, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 60,
+                       0.0, nullptr) == BBP_OK);
   std::printf("host paths clean\n");
   return 0;
 }

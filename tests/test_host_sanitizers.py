@@ -20,7 +20,7 @@ CLANG = os.path.join(ROCM, "llvm", "bin", "clang++")
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-sanitize=function", "-Xarch_host", "-fno-omit-frame-pointer"]
 # sources with device code are compiled whole; the others for the host only
-FULL = ("bbp_kernels.hip", "bbp_api.hip")
+FULL = ("bbp_kernels.hip", "bbp_api.hip", "bbp_svd.hip")
 HOST_ONLY = ("bbp_server.hip", "bbp_ite.hip")
 
 
