@@ -123,6 +123,19 @@ def solve(ctx, cfg, A, sweeps, sites, bonds, times=None, phase_ms=None):
     return res, sz, ss, ln
 
 
+def class_rates(s):
+    """One kernel class's launches and time with its counted rate against
+    both rooflines: TFLOP/s against the FP64 peak and the algorithmic bytes
+    (operands read and results written once, on the true extents) in GB/s
+    against HBM; the small-panel classes (QR, end sites) are latency- and
+    HBM-bound, so the GB/s figure is theirs to read."""
+    ms = max(s["ms"], 1e-9)
+    tf = s["flops"] / ms / 1e9
+    gbs = s["bytes"] / ms / 1e6
+    return dict(launches=s["launches"], ms=s["ms"], tflops=tf, frac_fp64=tf / PEAK_FP64_TFLOPS,
+                gbs=gbs, frac_hbm=gbs / PEAK_HBM_GBS)
+
+
 def roofline(stats, workload=WORKLOAD):
     """Roofline of the fit visit (the contraction class with the most time:
     the fused visit, or the unfused T1/ket/bra/local chain where the fused
@@ -643,9 +656,7 @@ def ite_bench(args):
             roofline(stats, None), measured_in="one further ITE step with every launch "
             "bracketed by HIP events (sweeps and the environment contractions)"),
         kernels=None if stats is None else {
-            s["name"]: dict(launches=s["launches"], ms=s["ms"],
-                            tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
-            for s in stats},
+            s["name"]: class_rates(s) for s in stats},
         cpu_baseline=None if args.no_cpu_baseline else ite_cpu_baseline(w, A0, G, gates),
     )
     print(json.dumps(line), flush=True)
@@ -927,9 +938,7 @@ def main():
             "solves on a one-stream context (lanes 1), every launch bracketed by HIP events",
             pass_ms_per_step=timed_total / args.steps * 1e3),
         kernels=None if stats is None else {
-            s["name"]: dict(launches=s["launches"], ms=s["ms"],
-                            tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
-            for s in stats},
+            s["name"]: class_rates(s) for s in stats},
         kernel_ms_per_solve_by_phase=None if stats is None else {
             ph: {n: v / args.steps for n, v in d.items() if v > 0}
             for ph, d in phase_kernels.items() if not ph.startswith("_")},
