@@ -133,3 +133,19 @@ def test_sweep_limit_is_reported():
     t = torch.from_numpy(A).cuda()
     _, _, _, _, sw = bbp.svd_jacobi(t, max_sweeps=1)
     assert np.all(sw.cpu().numpy() == -1)
+
+
+def test_non_finite_input_stays_in_its_item():
+    """A matrix holding NaN or Inf gives non-finite or zero output without an
+    error, and the other items of its batch keep their bits."""
+    A = dense_matrices(4, 40, 8, seed=17)
+    ref = _run(A[1:2], 4)
+    bad = A.copy()
+    bad[0, 3, 2] = np.nan
+    bad[2, 0, 0] = np.inf
+    U, S, V, e2, sw = _run(bad, 4)
+    assert np.array_equal(U[1], ref[0][0]) and np.array_equal(S[1], ref[1][0])
+    assert np.array_equal(V[1], ref[2][0])
+    # the NaN column's value sorts last, so it shows in the discarded weight;
+    # the infinite column's value comes first
+    assert np.isnan(e2[0]) and S[2][0] == np.inf
