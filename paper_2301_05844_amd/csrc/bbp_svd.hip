@@ -15,9 +15,10 @@
 // n' = n rounded up to even columns: the n'/2 pairs of a round share no
 // column, so the 16 waves rotate them side by side, a wave per pair, with
 // one barrier per round.  Each pair's three sums (|a_p|^2, |a_q|^2,
-// a_p . a_q) are accumulated per lane in row order and reduced by a fixed
-// butterfly, so every result is reproducible bit for bit and independent of
-// the other items of the batch.
+// a_p . a_q) are accumulated per lane in row order and reduced across the
+// wave in a fixed order (DPP moves within rows of 16 lanes, then the four row
+// sums), so every result is reproducible bit for bit and independent of the
+// other items of the batch.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -40,10 +41,30 @@ struct SvdArgs {
   double tol;
 };
 
-__device__ __forceinline__ double butterfly_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// v of lane (lane within its row of 16, permuted by the DPP control CTRL).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the 64 lanes, the same bits in every lane: within each row of 16
+// lanes by DPP moves (partner 1 apart, 2 apart, the other half of 8, the
+// other half of 16; each step adds a lane's value to its partner's, so the
+// partners hold equal sums), then the four row sums in a fixed order.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);  // row_half_mirror
+  v += dpp_f64<0x140>(v);  // row_mirror
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // Columns of round r (0 <= r < np - 1) of the circle pairing of np (even)
@@ -97,9 +118,9 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(SvdArgs g) {
           be = fma(y, y, be);
           ga = fma(x, y, ga);
         }
-        al = butterfly_sum(al);
-        be = butterfly_sum(be);
-        ga = butterfly_sum(ga);
+        al = wave_total(al);
+        be = wave_total(be);
+        ga = wave_total(ga);
         // rotate unless the pair is already orthogonal to the tolerance
         if (!(fabs(ga) > g.tol * (sqrt(al) * sqrt(be)))) continue;
         const double ze = (be - al) / (2.0 * ga);
@@ -138,7 +159,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_svd_jacobi(SvdArgs g) {
       ss = fma(x, x, ss);
       if (fabs(x) > big) big = fabs(x), at = i;
     }
-    ss = butterfly_sum(ss);
+    ss = wave_total(ss);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const double ob = __shfl_xor(big, o, 64);
