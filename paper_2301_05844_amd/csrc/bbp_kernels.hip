@@ -165,11 +165,13 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
   return (__attribute__((address_space(1))) T *)p;
 }
 
-// Loads through a buffer descriptor: the base lives in SGPRs and each lane
-// supplies a 32-bit byte offset, so a loop keeps one 32-bit offset per element
-// instead of a 64-bit address.  Descriptor word 3 selects the 32-bit data
-// format, which untyped buffer loads on this GPU family require.  Callers
-// keep every offset inside the `bytes` they declare.
+// Loads and stores through a buffer descriptor: the base lives in SGPRs and
+// each lane supplies a 32-bit byte offset, so a loop keeps one 32-bit offset
+// per element instead of a 64-bit address.  Descriptor word 3 selects the
+// 32-bit data format, which untyped buffer accesses on this GPU family
+// require.  The hardware checks every offset against the `bytes` declared: a
+// load at or beyond it returns zero and a store there is dropped; the visit
+// loads the elements outside its tile that way (offset `bytes`).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double *p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, (int)bytes, 0x00020000);
 }
@@ -178,6 +180,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float *p, unsig
 }
 __device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+template <class T>
+__device__ __forceinline__ void buf_st_t(__amdgpu_buffer_rsrc_t r, unsigned byte_off, T v);
+template <>
+__device__ __forceinline__ void buf_st_t<double>(__amdgpu_buffer_rsrc_t r, unsigned o, double v) {
+  typedef unsigned int v2u __attribute__((__vector_size__(8)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, o, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_st_t<float>(__amdgpu_buffer_rsrc_t r, unsigned o, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, o, 0, 0);
 }
 template <class T> __device__ __forceinline__ T buf_ld_t(__amdgpu_buffer_rsrc_t r, unsigned byte_off);
 template <> __device__ __forceinline__ double buf_ld_t<double>(__amdgpu_buffer_rsrc_t r, unsigned o) {
@@ -1667,6 +1680,8 @@ void k_visit4p(VisitArgs v) {
     const double *ak = v.aket + (size_t)it * v.aket_stride;
   const double *ab = v.abra + (size_t)it * v.abra_stride;
   T *T3g = reinterpret_cast<T *>(v.t3) + (size_t)it * v.t3_stride;
+  const __amdgpu_buffer_rsrc_t t3rs =
+      __builtin_amdgcn_make_buffer_rsrc(T3g, 0, (int)((unsigned)K * P * K * P * sizeof(T)), 0x00020000);
   const bool rl = v.rl != 0;
   const int ty = wave / TX, tx = wave % TX, pp = wave;  // this wave's pair
   T *Tp = T13s + pp * P2;
@@ -1712,26 +1727,23 @@ void k_visit4p(VisitArgs v) {
     wb = (i / TX) & 15;
     yb = i / (TX * 16);
   };
-  // raw loads of the pending step and which of them are real elements (the
-  // rest become zero when stored): nothing waits on the loads before the
-  // refill at the next step.  X and G of one item are K P K doubles each; an
-  // element outside the tile loads offset 0.  Without the local update there
-  // is no G (null): nothing is loaded from it.
+  // raw loads of the pending step: nothing waits on them before the refill at
+  // the next step.  X and G of one item are K P K doubles each; an element
+  // outside the tile loads at offset K P K doubles, past the descriptor's
+  // range, and reads zero.  Without the local update there is no G (null):
+  // nothing is loaded from it.
   double xr[LD], gr[LD];
-  unsigned xm = 0, gm = 0;
   const unsigned xgbytes = (unsigned)K * P * K * sizeof(double);
   const __amdgpu_buffer_rsrc_t xrs = buf_rsrc(v.X.at(it), xgbytes);
   const __amdgpu_buffer_rsrc_t grs = buf_rsrc(v.do_local ? v.G.at(it) : v.X.at(it), xgbytes);
   auto fetch = [&](int x0) {
-    xm = gm = 0;
 #pragma unroll
     for (int u = 0; u < LD; ++u) {
       int txx, a, xf;
       xdec(u, txx, a, xf);
       const bool xv = tid + u * NT < NX && xf < nxf && x0 + txx < nxb;
       const unsigned off = rl ? ((x0 + txx) * P + a) * K + xf : (xf * P + a) * K + x0 + txx;
-      xr[u] = buf_ld(xrs, xv ? off * 8u : 0u);
-      xm |= (unsigned)xv << u;
+      xr[u] = buf_ld(xrs, xv ? off * 8u : xgbytes);
     }
     if (v.do_local) {
 #pragma unroll
@@ -1739,8 +1751,7 @@ void k_visit4p(VisitArgs v) {
         int gtx, wb, yb;
         gdec(u, gtx, wb, yb);
         const bool gv = tid + u * NT < NX && yb < nyb && x0 + gtx < nxb;
-        gr[u] = buf_ld(grs, gv ? ((yb * P + wb) * K + x0 + gtx) * 8u : 0u);
-        gm |= (unsigned)gv << u;
+        gr[u] = buf_ld(grs, gv ? ((yb * P + wb) * K + x0 + gtx) * 8u : xgbytes);
       }
     }
   };
@@ -1754,9 +1765,9 @@ void k_visit4p(VisitArgs v) {
       int txx, a, xf, gtx, wb, yb;
       xdec(u, txx, a, xf);
       gdec(u, gtx, wb, yb);
-      if (xf < K4) Xs[txx * XT + xf * 16 + (a ^ v4p_x_sw(xf))] = (T)(((xm >> u) & 1) ? xr[u] : 0.0);
+      if (xf < K4) Xs[txx * XT + xf * 16 + (a ^ v4p_x_sw(xf))] = (T)xr[u];
       const int grow = gtx * 16 + wb;
-      if (yb < KY) Gs[grow * GS + (yb ^ v4p_g_sw(grow))] = (T)(((gm >> u) & 1) ? gr[u] : 0.0);
+      if (yb < KY) Gs[grow * GS + (yb ^ v4p_g_sw(grow))] = (T)(v.do_local ? gr[u] : 0.0);
     }
     __syncthreads();
     if (x0 + TX < nxb) fetch(x0 + TX);
@@ -1825,14 +1836,17 @@ void k_visit4p(VisitArgs v) {
       }
     }
     wave_lds_order();
-    // T3 of the pair to HBM as T3[yf][l][xb][wb] (16 lanes per 128-byte row)
+    // T3 of the pair to HBM as T3[yf][l][xb][wb] (16 lanes per 128-byte row),
+    // through the item's descriptor (32-bit offsets)
     {
       const int yf = y0 + ty, xb = x0 + tx;
       if (yf < nyf && xb < nxb) {
+        const unsigned o0 = (unsigned)(yf * P * K + xb) * P;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int idx = u * 64 + lane, wb = idx & 15, l = idx >> 4;
-          T3g[(((size_t)yf * P + l) * K + xb) * P + wb] = Tp[wb * 16 + (l ^ v4p_t3_sw(wb))];
+          buf_st_t<T>(t3rs, (o0 + (unsigned)(l * K * P + wb)) * (unsigned)sizeof(T),
+                      Tp[wb * 16 + (l ^ v4p_t3_sw(wb))]);
         }
       }
     }
