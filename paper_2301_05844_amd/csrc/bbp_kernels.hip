@@ -171,7 +171,8 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
 // 32-bit data format, which untyped buffer accesses on this GPU family
 // require.  The hardware checks every offset against the `bytes` declared: a
 // load at or beyond it returns zero and a store there is dropped; the visit
-// loads the elements outside its tile that way (offset `bytes`).
+// and the environment update load the elements outside their operands that
+// way (offset `bytes`).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double *p, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(p), 0, (int)bytes, 0x00020000);
 }
@@ -674,16 +675,16 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
     return;
   }
   // Y (K P K doubles) and this item's T3 (K P x K P) through buffer
-  // descriptors; an element outside the operand loads offset 0 and is
-  // replaced by zero
+  // descriptors; an element outside the operand (or past the true extents)
+  // loads at the descriptor's end, where the range check returns zero
   const T *T3 = reinterpret_cast<const T *>(e.t3) + (size_t)it * e.t3s;
-  const __amdgpu_buffer_rsrc_t yrs = buf_rsrc(e.Y.at(it), (unsigned)(K * P * K) * 8u);
-  const __amdgpu_buffer_rsrc_t trs = buf_rsrc(T3, (unsigned)(Kd * N) * (unsigned)sizeof(T));
+  const unsigned ybytes = (unsigned)(K * P * K) * 8u;
+  const unsigned tbytes = (unsigned)(Kd * N) * (unsigned)sizeof(T);
+  const __amdgpu_buffer_rsrc_t yrs = buf_rsrc(e.Y.at(it), ybytes);
+  const __amdgpu_buffer_rsrc_t trs = buf_rsrc(T3, tbytes);
   const bool rl = e.rl != 0;
-  // Y elements of the next chunk: raw loads and a validity mask, applied
-  // when staged in LDS
+  // Y elements of the next chunk (raw loads, staged in LDS by put)
   double an[NA];
-  unsigned am = 0;
   // RL layout: (yf, l) of k = k0 + kk for each staged element, packed as
   // yf * 256 + l and carried from chunk to chunk (no division in the loop)
   int yfl[NA];
@@ -694,35 +695,30 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   }
   const int dyfl = (CH / P) * 256 + CH % P;
   auto fetch_a = [&](int k0) {  // chunks in order 0, CH, 2 CH, ...
-    am = 0;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int i = tid + u * NT, kk = i / MW, m = i % MW, k = k0 + kk;
       const bool ok = m < K && k < Kd;
       const unsigned off = rl ? (m * P + (yfl[u] & 255)) * K + (yfl[u] >> 8) : k * K + m;
-      an[u] = buf_ld(yrs, ok ? off * 8u : 0u);
-      am |= (unsigned)ok << u;
+      an[u] = buf_ld(yrs, ok ? off * 8u : ybytes);
       yfl[u] += dyfl;
       if ((yfl[u] & 255) >= P) yfl[u] += 256 - P;
     }
   };
-  // T3 rows of chunk k0 for this wave's k part: raw loads and a validity
-  // mask, applied when used (two chunks are in flight)
-  auto fetch_b = [&](int k0, T (&b)[8], unsigned &bm) {
-    bm = 0;
+  // T3 rows of chunk k0 for this wave's k part (two chunks are in flight)
+  auto fetch_b = [&](int k0, T (&b)[8]) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = k0 + h * 32 + 4 * i + lq;
       const bool ok = n < Nt && k < Kd;
-      b[i] = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : 0u);
-      bm |= (unsigned)ok << i;
+      b[i] = buf_ld_t<T>(trs, ok ? (unsigned)(k * N + n) * (unsigned)sizeof(T) : tbytes);
     }
   };
   auto put = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int i = tid + u * NT;
-      As[buf][i / MW][i % MW] = (T)(((am >> u) & 1) ? an[u] : 0.0);
+      As[buf][i / MW][i % MW] = (T)an[u];
     }
   };
   // two accumulation chains per row tile, one where MT tiles already give
@@ -736,22 +732,21 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
   // T3 rows are fetched DB chunks ahead (two while the registers allow)
   constexpr int DB = MT <= 3 ? 2 : 1;
   T b0[8], b1[8];
-  unsigned m0 = 0, m1 = 0;
   fetch_a(0);
-  fetch_b(0, b0, m0);
-  if (DB == 2 && CH < Kd) fetch_b(CH, b1, m1);
+  fetch_b(0, b0);
+  if (DB == 2 && CH < Kd) fetch_b(CH, b1);
   put(0);
   __syncthreads();
   int buf = 0;
   // one chunk: multiply with the staged Y and the given T3 rows, then
   // refill those rows DB chunks ahead and stage the next Y chunk
-  auto step = [&](int k0, T (&b)[8], unsigned &bm) {
+  auto step = [&](int k0, T (&b)[8]) {
     if (k0 + CH < Kd) fetch_a(k0 + CH);
     if constexpr (B16) {  // copy out, refill, then two BF16 steps per row tile
       float bc[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) bc[i] = ((bm >> i) & 1) ? (float)b[i] : 0.f;
-      if (k0 + DB * CH < Kd) fetch_b(k0 + DB * CH, b, bm);
+      for (int i = 0; i < 8; ++i) bc[i] = (float)b[i];
+      if (k0 + DB * CH < Kd) fetch_b(k0 + DB * CH, b);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         float a[8];
@@ -763,8 +758,8 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
     } else if constexpr (DB == 1) {  // copy out, then refill the same registers
       T bc[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) bc[i] = ((bm >> i) & 1) ? b[i] : (T)0;
-      if (k0 + CH < Kd) fetch_b(k0 + CH, b, bm);
+      for (int i = 0; i < 8; ++i) bc[i] = b[i];
+      if (k0 + CH < Kd) fetch_b(k0 + CH, b);
 #pragma unroll
       for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -774,21 +769,21 @@ __attribute__((amdgpu_waves_per_eu(EnvShape<MT>::kWaves))) void k_env(EnvArgs e)
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const T bc = ((bm >> i) & 1) ? b[i] : (T)0;
+        const T bc = b[i];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
           acc[mt][i % NC] =
               M::run(As[buf][h * 32 + 4 * i + lq][mt * 16 + lr], bc, acc[mt][i % NC]);
       }
-      if (k0 + 2 * CH < Kd) fetch_b(k0 + 2 * CH, b, bm);
+      if (k0 + 2 * CH < Kd) fetch_b(k0 + 2 * CH, b);
     }
     if (k0 + CH < Kd) put(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   };
   for (int k0 = 0; k0 < Kd; k0 += DB * CH) {
-    step(k0, b0, m0);
-    if (DB == 2 && k0 + CH < Kd) step(k0 + CH, b1, m1);
+    step(k0, b0);
+    if (DB == 2 && k0 + CH < Kd) step(k0 + CH, b1);
   }
   Acc c[MT];
 #pragma unroll
